@@ -1,0 +1,154 @@
+/*
+ * sgm.h -- C ABI of the MI355X (gfx950) semi-global matching library.
+ *
+ * The library computes the dense-stereo stage of the road-disparity
+ * pipeline of Fan et al., "Rethinking Road Surface 3D Reconstruction and
+ * Pothole Detection: From Perspective Transformation to Disparity Map
+ * Segmentation":
+ *   - per-pixel matching cost c(p,d) (Sec. II-B, eq. (7); the paper leaves
+ *     the cost open, the library uses an n x n census transform with the
+ *     Hamming distance);
+ *   - path aggregation along 4 or 8 image directions (Sec. II-B, eq. (8)),
+ *     in the normalised form
+ *       L_r(p,k) = C(p,k) + min(L_r(q,k), L_r(q,k-1)+P1, L_r(q,k+1)+P1,
+ *                               m_q+P2) - m_q,   q = p - r,
+ *                  m_q = min_i L_r(q,i);
+ *   - the summed cost S(p,k) = sum_r L_r(p,k) and the winner-take-all
+ *     disparity (eq. (9), read as the smallest k minimising S);
+ *   - parabola sub-pixel refinement (Sec. I names sub-pixel disparities,
+ *     the method is not given);
+ *   - the perspective-transformation window (Sec. II-A, eq. (6)) as a
+ *     per-row integer window start d_lo(v): window index k of row v means
+ *     disparity d_lo(v) + k, and outputs are returned in disparities of
+ *     the original pair (eq. (10)).
+ *
+ * Conventions common to every call
+ *   - Images are uint8 grayscale, row-major, H rows of W pixels, with a
+ *     row pitch in bytes (pitch >= W).  The left image is the reference.
+ *   - Volumes are row-major [H][W][w] with the window index k fastest:
+ *     element (u, v, k) is at ((v * W + u) * w + k).
+ *   - Path indices r = 0..7 are the directions (du, dv) = (+1,0), (-1,0),
+ *     (0,+1), (0,-1), (+1,+1), (-1,+1), (+1,-1), (-1,-1); the predecessor
+ *     of pixel p on path r is p - r.  4-path runs use r = 0..3.
+ *   - Every pointer marked "device" is device memory owned by the caller;
+ *     the library never allocates, frees or synchronises on the compute
+ *     calls.  Work is enqueued asynchronously on `stream` (a hipStream_t;
+ *     NULL is the null stream).  Outputs are valid once the stream has
+ *     reached the enqueued work.
+ *   - Argument checks happen before anything is enqueued; a failing call
+ *     enqueues nothing.  A failed launch returns SGM_ERR_HIP.  Device faults
+ *     surface at the caller's next synchronisation.  sgm_last_error()
+ *     returns a thread-local description of the last failure.
+ *   - A plan is immutable after sgm_plan() and may be used from several
+ *     threads and streams at once, each with its own workspace.
+ */
+#ifndef SGM_H
+#define SGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SGM_OK = 0,
+    SGM_ERR_INVALID = -1,     /* null pointer, size or parameter out of range */
+    SGM_ERR_UNSUPPORTED = -2, /* well-formed request the library does not handle */
+    SGM_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+    SGM_ERR_WORKSPACE = -4    /* the workspace passed is smaller than required */
+} sgm_status;
+
+/* Parameters of one matching problem (Sec. II-B, eq. (7)-(8)). */
+typedef struct {
+    int32_t width, height; /* W, H >= 1, W * H * ndisp < 2^31            */
+    int32_t census;        /* census window side n: 3, 5 or 7 (Cmax = n*n-1) */
+    int32_t ndisp;         /* window width w, 1..256                       */
+    int32_t npaths;        /* 4 or 8                                       */
+    int32_t p1, p2;        /* 0 <= P1 <= P2 and Cmax + 2*P2 < 16383        */
+    uint32_t flags;        /* reserved, must be 0                          */
+} sgm_params;
+
+typedef struct sgm_plan_s *sgm_plan_t;
+
+/* Validate `params` and build a plan (host only, touches no device).
+ * On success *out owns host memory released by sgm_plan_free(). */
+sgm_status sgm_plan(const sgm_params *params, sgm_plan_t *out);
+void sgm_plan_free(sgm_plan_t plan);
+
+/* Bytes of device workspace that sgm_cost, sgm_aggregate,
+ * sgm_aggregate_wta and sgm_match need (one figure covers all of them).
+ * The workspace must be 256-byte aligned; its contents need not persist
+ * between calls. */
+sgm_status sgm_workspace_size(sgm_plan_t plan, size_t *bytes);
+
+/* Census codes of one image: codes[v * W + u] (device, uint64), bit b set
+ * iff the b-th neighbour of the n x n window (row by row, centre skipped,
+ * coordinates clamped to the image) is strictly darker than the centre. */
+sgm_status sgm_census(sgm_plan_t plan, const uint8_t *image, int32_t pitch,
+                      uint64_t *codes, void *stream);
+
+/* Matching cost volume (device, uint8 [H][W][w]):
+ *   C(u,v,k) = popcount(cL(u,v) XOR cR(u - d_lo[v] - k, v)),
+ *   or Cmax where u - d_lo[v] - k < 0  (Sec. II-B with eq. (6)).
+ * d_lo: device int32 [H] window starts, each >= 0, or NULL for all 0. */
+sgm_status sgm_cost(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
+                    int32_t pitch, const int32_t *d_lo, uint8_t *cost,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
+/* Summed aggregated cost (device, uint16 [H][W][w]): S = sum_r L_r over the
+ * plan's npaths directions (eq. (8), eq. (9)). */
+sgm_status sgm_aggregate(sgm_plan_t plan, const uint8_t *cost, uint16_t *sum,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* One direction's aggregated cost L_r (device, uint16 [H][W][w]), for
+ * testing and inspection; path in 0..7 (see the direction table above). */
+sgm_status sgm_aggregate_path(sgm_plan_t plan, const uint8_t *cost, int32_t path,
+                              uint16_t *L, void *stream);
+
+/* Winner-take-all and sub-pixel step on a summed cost volume (eq. (9),
+ * eq. (10)).  k* is the smallest k minimising S(p,k); disp_int[v*W+u] =
+ * d_lo[v] + k* (device uint16 [H][W]).  If disp_sub is not NULL it receives
+ * (float)(d_lo[v] + k*) + delta (device float [H][W]), where for
+ * 0 < k* < w-1, delta = (S(k*-1) - S(k*+1)) / (2 (S(k*-1) - 2 S(k*) +
+ * S(k*+1))) computed as one IEEE fp32 division of exact integers, and
+ * delta = 0 otherwise.  d_lo may be NULL (all 0). */
+sgm_status sgm_wta(sgm_plan_t plan, const uint16_t *sum, const int32_t *d_lo,
+                   uint16_t *disp_int, float *disp_sub, void *stream);
+
+/* sgm_aggregate followed by sgm_wta without materialising S: identical
+ * outputs, less memory traffic. */
+sgm_status sgm_aggregate_wta(sgm_plan_t plan, const uint8_t *cost,
+                             const int32_t *d_lo, uint16_t *disp_int,
+                             float *disp_sub, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
+/* The whole path on one pair: census, cost, aggregation, selection and
+ * sub-pixel step.  Identical outputs to sgm_cost + sgm_aggregate_wta; the
+ * cost volume lives in the workspace. */
+sgm_status sgm_match(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
+                     int32_t pitch, const int32_t *d_lo, uint16_t *disp_int,
+                     float *disp_sub, void *workspace, size_t workspace_bytes,
+                     void *stream);
+
+/* Per-row window starts from the road model of eq. (3),
+ *   f(u,v) = a0 + a1 (cos(phi) (v - cy) - sin(phi) (u - cx)),
+ * with (cx, cy) = ((W-1)/2, (H-1)/2) the centre of the roll rotation.
+ * Host only; d_lo_host is a host int32 [H] array.
+ *   mode 0: window of width w centred on the road disparity at the row
+ *           centre: d_lo = max(0, floor(f(cx, v) + 1/2) - floor(w/2)).
+ *   mode 1: the shift of eq. (6): d_lo = max(0, floor(min over
+ *           x = 0..W-1 of f(x, v) - delta)). */
+sgm_status sgm_window_from_road(double a0, double a1, double phi, int32_t width,
+                                int32_t height, int32_t w, int32_t mode,
+                                double delta, int32_t *d_lo_host);
+
+const char *sgm_status_str(sgm_status status);
+const char *sgm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGM_H */

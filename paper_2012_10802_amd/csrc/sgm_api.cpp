@@ -1,0 +1,273 @@
+// C-ABI layer of the SGM library: plans, argument validation, workspace
+// layout and the calls declared in include/sgm.h.  Every check happens on
+// the host before anything is enqueued; kernels live in sgm_kernels.hip.
+
+#include "../../include/sgm.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "sgm_internal.h"
+
+struct sgm_plan_s {
+    sgm_params params;
+    sgm::Problem pb;
+    sgm::KernelConfig kc;
+    int paths[8];
+    size_t n_pix, n_vol;      // W*H, W*H*w
+    size_t off_codes_l, off_codes_r, off_cost, off_paths, ws_bytes;
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+sgm_status fail(sgm_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+sgm_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(SGM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int choose_vpl(int w)
+{
+    if (w <= 32) return 2;
+    if (w <= 64) return 4;
+    if (w <= 128) return 8;
+    if (w <= 192) return 12;
+    return 16;
+}
+
+bool is_aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+sgm_status check_plan(sgm_plan_t plan)
+{
+    if (!plan) return fail(SGM_ERR_INVALID, "plan is NULL");
+    return SGM_OK;
+}
+
+sgm_status check_ws(const sgm_plan_s *p, void *ws, size_t bytes)
+{
+    if (!ws) return fail(SGM_ERR_INVALID, "workspace is NULL");
+    if (!is_aligned(ws, 256)) return fail(SGM_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (bytes < p->ws_bytes)
+        return fail(SGM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", bytes,
+                    p->ws_bytes);
+    return SGM_OK;
+}
+
+// Effective kernel configuration for given buffer pointers: vector access of
+// a lane's values needs w % vpl == 0 and buffers aligned to a lane's bytes.
+sgm::KernelConfig config_for(const sgm_plan_s *p, const void *a, const void *b)
+{
+    sgm::KernelConfig kc = p->kc;
+    // widest access: a lane's values as uint16 (2*vpl bytes), issued as
+    // power-of-two sized pieces
+    const size_t bytes = (size_t)kc.vpl * 2;
+    const size_t need = bytes & (~bytes + 1);
+    if (kc.aligned && ((a && !is_aligned(a, need)) || (b && !is_aligned(b, need)))) kc.aligned = false;
+    return kc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sgm_status_str(sgm_status s)
+{
+    switch (s) {
+    case SGM_OK: return "SGM_OK";
+    case SGM_ERR_INVALID: return "SGM_ERR_INVALID";
+    case SGM_ERR_UNSUPPORTED: return "SGM_ERR_UNSUPPORTED";
+    case SGM_ERR_HIP: return "SGM_ERR_HIP";
+    case SGM_ERR_WORKSPACE: return "SGM_ERR_WORKSPACE";
+    }
+    return "unknown sgm_status";
+}
+
+const char *sgm_last_error(void) { return g_err; }
+
+sgm_status sgm_plan(const sgm_params *pr, sgm_plan_t *out)
+{
+    if (!pr || !out) return fail(SGM_ERR_INVALID, "params and out must not be NULL");
+    *out = nullptr;
+    const sgm_params &q = *pr;
+    if (q.width < 1 || q.height < 1) return fail(SGM_ERR_INVALID, "width and height must be >= 1");
+    if (q.census != 3 && q.census != 5 && q.census != 7)
+        return fail(SGM_ERR_UNSUPPORTED, "census window %d not in {3, 5, 7}", q.census);
+    if (q.ndisp < 1 || q.ndisp > 256) return fail(SGM_ERR_INVALID, "ndisp %d not in [1, 256]", q.ndisp);
+    if (q.npaths != 4 && q.npaths != 8) return fail(SGM_ERR_UNSUPPORTED, "npaths %d not in {4, 8}", q.npaths);
+    if (q.p1 < 0 || q.p2 < q.p1) return fail(SGM_ERR_INVALID, "need 0 <= P1 <= P2 (got %d, %d)", q.p1, q.p2);
+    const int cmax = q.census * q.census - 1;
+    if (cmax + 2 * q.p2 >= 0x3FFF)
+        return fail(SGM_ERR_INVALID, "need Cmax + 2*P2 < 16383 (Cmax %d, P2 %d)", cmax, q.p2);
+    if ((long long)q.npaths * (cmax + q.p2) > 0xFFFF)
+        return fail(SGM_ERR_INVALID, "summed cost would exceed 16 bits");
+    if ((long long)q.width * q.height * q.ndisp >= (1ll << 31))
+        return fail(SGM_ERR_UNSUPPORTED, "W*H*ndisp must be < 2^31");
+    if (q.flags != 0) return fail(SGM_ERR_INVALID, "flags must be 0");
+
+    sgm_plan_s *p = new (std::nothrow) sgm_plan_s();
+    if (!p) return fail(SGM_ERR_INVALID, "out of host memory");
+    p->params = q;
+    p->pb = {q.width, q.height, q.ndisp, q.census, q.npaths, q.p1, q.p2, cmax};
+    p->kc.vpl = choose_vpl(q.ndisp);
+    p->kc.aligned = (q.ndisp % p->kc.vpl) == 0;
+    p->kc.l8 = cmax + q.p2 <= 255;
+    p->kc.agg_block = 256;
+    for (int i = 0; i < 8; ++i) p->paths[i] = i;
+    p->n_pix = (size_t)q.width * q.height;
+    p->n_vol = p->n_pix * (size_t)q.ndisp;
+    const size_t esz = p->kc.l8 ? 1 : 2;
+    const size_t vstride = align256(p->n_vol * esz);
+    size_t off = 0;
+    p->off_codes_l = off;
+    off += align256(p->n_pix * 8);
+    p->off_codes_r = off;
+    off += align256(p->n_pix * 8);
+    p->off_cost = off;
+    off += align256(p->n_vol);
+    p->off_paths = off;
+    off += vstride * (size_t)q.npaths;
+    p->ws_bytes = off;
+    *out = p;
+    return SGM_OK;
+}
+
+void sgm_plan_free(sgm_plan_t plan) { delete plan; }
+
+sgm_status sgm_workspace_size(sgm_plan_t plan, size_t *bytes)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!bytes) return fail(SGM_ERR_INVALID, "bytes is NULL");
+    *bytes = plan->ws_bytes;
+    return SGM_OK;
+}
+
+sgm_status sgm_census(sgm_plan_t plan, const uint8_t *image, int32_t pitch, uint64_t *codes, void *stream)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!image || !codes) return fail(SGM_ERR_INVALID, "image and codes must not be NULL");
+    if (pitch < plan->pb.W) return fail(SGM_ERR_INVALID, "pitch %d < width %d", pitch, plan->pb.W);
+    hipError_t e = sgm::launch_census(plan->pb, image, pitch, codes, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "census launch");
+}
+
+sgm_status sgm_cost(sgm_plan_t plan, const uint8_t *left, const uint8_t *right, int32_t pitch, const int32_t *d_lo,
+                    uint8_t *cost, void *ws, size_t ws_bytes, void *stream)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!left || !right || !cost) return fail(SGM_ERR_INVALID, "left, right and cost must not be NULL");
+    if (pitch < plan->pb.W) return fail(SGM_ERR_INVALID, "pitch %d < width %d", pitch, plan->pb.W);
+    if (sgm_status s = check_ws(plan, ws, ws_bytes)) return s;
+    uint8_t *base = static_cast<uint8_t *>(ws);
+    uint64_t *cl = reinterpret_cast<uint64_t *>(base + plan->off_codes_l);
+    uint64_t *cr = reinterpret_cast<uint64_t *>(base + plan->off_codes_r);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = sgm::launch_census(plan->pb, left, pitch, cl, st);
+    if (e == hipSuccess) e = sgm::launch_census(plan->pb, right, pitch, cr, st);
+    if (e == hipSuccess) e = sgm::launch_cost(plan->pb, config_for(plan, cost, nullptr), cl, cr, d_lo, cost, st);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "cost launch");
+}
+
+sgm_status sgm_aggregate(sgm_plan_t plan, const uint8_t *cost, uint16_t *sum, void *ws, size_t ws_bytes,
+                         void *stream)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!cost || !sum) return fail(SGM_ERR_INVALID, "cost and sum must not be NULL");
+    if (sgm_status s = check_ws(plan, ws, ws_bytes)) return s;
+    void *vols = static_cast<uint8_t *>(ws) + plan->off_paths;
+    hipStream_t st = (hipStream_t)stream;
+    const sgm::KernelConfig kc = config_for(plan, cost, nullptr);
+    hipError_t e = sgm::launch_aggregate(plan->pb, kc, cost, plan->paths, plan->pb.npaths, kc.l8, vols, st);
+    if (e == hipSuccess) e = sgm::launch_sum(plan->pb, kc, vols, plan->pb.npaths, kc.l8, sum, st);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "aggregate launch");
+}
+
+sgm_status sgm_aggregate_path(sgm_plan_t plan, const uint8_t *cost, int32_t path, uint16_t *L, void *stream)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!cost || !L) return fail(SGM_ERR_INVALID, "cost and L must not be NULL");
+    if (path < 0 || path > 7) return fail(SGM_ERR_INVALID, "path %d not in [0, 7]", path);
+    const sgm::KernelConfig kc = config_for(plan, cost, L);
+    const int paths[1] = {path};
+    hipError_t e = sgm::launch_aggregate(plan->pb, kc, cost, paths, 1, false, L, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "aggregate_path launch");
+}
+
+sgm_status sgm_wta(sgm_plan_t plan, const uint16_t *sum, const int32_t *d_lo, uint16_t *disp_int, float *disp_sub,
+                   void *stream)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!sum || !disp_int) return fail(SGM_ERR_INVALID, "sum and disp_int must not be NULL");
+    const sgm::KernelConfig kc = config_for(plan, sum, nullptr);
+    hipError_t e = sgm::launch_wta_sum(plan->pb, kc, sum, d_lo, disp_int, disp_sub, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "wta launch");
+}
+
+sgm_status sgm_aggregate_wta(sgm_plan_t plan, const uint8_t *cost, const int32_t *d_lo, uint16_t *disp_int,
+                             float *disp_sub, void *ws, size_t ws_bytes, void *stream)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!cost || !disp_int) return fail(SGM_ERR_INVALID, "cost and disp_int must not be NULL");
+    if (sgm_status s = check_ws(plan, ws, ws_bytes)) return s;
+    void *vols = static_cast<uint8_t *>(ws) + plan->off_paths;
+    hipStream_t st = (hipStream_t)stream;
+    const sgm::KernelConfig kc = config_for(plan, cost, nullptr);
+    hipError_t e = sgm::launch_aggregate(plan->pb, kc, cost, plan->paths, plan->pb.npaths, kc.l8, vols, st);
+    if (e == hipSuccess)
+        e = sgm::launch_wta_paths(plan->pb, kc, vols, plan->pb.npaths, kc.l8, d_lo, disp_int, disp_sub, st);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "aggregate_wta launch");
+}
+
+sgm_status sgm_match(sgm_plan_t plan, const uint8_t *left, const uint8_t *right, int32_t pitch, const int32_t *d_lo,
+                     uint16_t *disp_int, float *disp_sub, void *ws, size_t ws_bytes, void *stream)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!disp_int) return fail(SGM_ERR_INVALID, "disp_int must not be NULL");
+    if (sgm_status s = check_ws(plan, ws, ws_bytes)) return s;
+    uint8_t *cost = static_cast<uint8_t *>(ws) + plan->off_cost;
+    if (sgm_status s = sgm_cost(plan, left, right, pitch, d_lo, cost, ws, ws_bytes, stream)) return s;
+    return sgm_aggregate_wta(plan, cost, d_lo, disp_int, disp_sub, ws, ws_bytes, stream);
+}
+
+sgm_status sgm_window_from_road(double a0, double a1, double phi, int32_t W, int32_t H, int32_t w, int32_t mode,
+                                double delta, int32_t *d_lo)
+{
+    if (!d_lo) return fail(SGM_ERR_INVALID, "d_lo_host is NULL");
+    if (W < 1 || H < 1 || w < 1) return fail(SGM_ERR_INVALID, "sizes must be >= 1");
+    if (mode != 0 && mode != 1) return fail(SGM_ERR_INVALID, "mode %d not in {0, 1}", mode);
+    if (!isfinite(a0) || !isfinite(a1) || !isfinite(phi) || !isfinite(delta))
+        return fail(SGM_ERR_INVALID, "road parameters must be finite");
+    const double cx = (W - 1) * 0.5, cy = (H - 1) * 0.5;
+    const double c = cos(phi), s = sin(phi);
+    // the road disparity is linear in x along a row, so its minimum over
+    // x = 0..W-1 sits at x = 0 or x = W-1
+    const double xmin = s > 0.0 ? (double)(W - 1) : 0.0;
+    for (int v = 0; v < H; ++v) {
+        double lo;
+        if (mode == 0) {
+            lo = floor(a0 + a1 * c * (v - cy) + 0.5) - (double)(w / 2);
+        } else {
+            lo = floor(a0 + a1 * (c * (v - cy) - s * (xmin - cx)) - delta);
+        }
+        if (lo > 32767.0) return fail(SGM_ERR_INVALID, "window start out of range on row %d", v);
+        d_lo[v] = lo > 0.0 ? (int32_t)lo : 0;
+    }
+    return SGM_OK;
+}
+
+}  // extern "C"

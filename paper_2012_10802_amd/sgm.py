@@ -1,0 +1,264 @@
+"""Python binding of libsgm (the C ABI in include/sgm.h).
+
+Argument marshalling only: every function here checks tensor shapes and
+dtypes, passes device pointers and the current HIP stream to the library,
+and raises on a non-zero status.  All computation happens in the HIP
+kernels of libsgm.so; there is no fallback of any kind, and importing this
+module fails if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgm.so")
+
+SGM_OK = 0
+STATUS = {0: "SGM_OK", -1: "SGM_ERR_INVALID", -2: "SGM_ERR_UNSUPPORTED", -3: "SGM_ERR_HIP",
+          -4: "SGM_ERR_WORKSPACE"}
+
+# path index -> direction r = (du, dv); predecessor of p is p - r
+PATH_DIRECTIONS = [(+1, 0), (-1, 0), (0, +1), (0, -1), (+1, +1), (-1, +1), (+1, -1), (-1, -1)]
+
+
+class SgmError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__("%s: %s (%s)" % (what, STATUS.get(status, status), detail))
+        self.status = status
+
+
+class sgm_params(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("census", ctypes.c_int32), ("ndisp", ctypes.c_int32),
+                ("npaths", ctypes.c_int32), ("p1", ctypes.c_int32),
+                ("p2", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+def _load_library():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsgm.so is not built; run `python -m paper_2012_10802_amd.build` "
+                          "(expected at %s)" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, S = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    D = ctypes.c_double
+    sig = {
+        "sgm_plan": [ctypes.POINTER(sgm_params), ctypes.POINTER(P)],
+        "sgm_plan_free": [P],
+        "sgm_workspace_size": [P, ctypes.POINTER(S)],
+        "sgm_census": [P, P, I, P, P],
+        "sgm_cost": [P, P, P, I, P, P, P, S, P],
+        "sgm_aggregate": [P, P, P, P, S, P],
+        "sgm_aggregate_path": [P, P, I, P, P],
+        "sgm_wta": [P, P, P, P, P, P],
+        "sgm_aggregate_wta": [P, P, P, P, P, P, S, P],
+        "sgm_match": [P, P, P, I, P, P, P, P, S, P],
+        "sgm_window_from_road": [D, D, D, I, I, I, I, D, P],
+        "sgm_status_str": [I],
+        "sgm_last_error": [],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.sgm_plan_free.restype = None
+    lib.sgm_status_str.restype = ctypes.c_char_p
+    lib.sgm_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load_library()
+
+
+def library():
+    """The loaded ctypes library (for tests of the exported symbols)."""
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != SGM_OK:
+        raise SgmError(status, what, _lib.sgm_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _need(t, dtype, shape, name, device=True):
+    if t is None:
+        raise ValueError("%s is required" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if device and not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return t
+
+
+# ---------------------------------------------------------------------------
+# the C calls, one for one
+
+
+def sgm_plan(width, height, census, ndisp, npaths, p1, p2, flags=0):
+    prm = sgm_params(width, height, census, ndisp, npaths, p1, p2, flags)
+    h = ctypes.c_void_p()
+    _check(_lib.sgm_plan(ctypes.byref(prm), ctypes.byref(h)), "sgm_plan")
+    return h
+
+
+def sgm_plan_free(plan):
+    _lib.sgm_plan_free(plan)
+
+
+def sgm_workspace_size(plan) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.sgm_workspace_size(plan, ctypes.byref(n)), "sgm_workspace_size")
+    return int(n.value)
+
+
+def sgm_window_from_road(a0, a1, phi, width, height, w, mode=0, delta=0.0):
+    """Host helper: per-row window starts (int32 CPU tensor [H])."""
+    out = torch.empty(height, dtype=torch.int32)
+    _check(_lib.sgm_window_from_road(float(a0), float(a1), float(phi), int(width), int(height),
+                                     int(w), int(mode), float(delta), _ptr(out)),
+           "sgm_window_from_road")
+    return out
+
+
+class Matcher:
+    """A plan plus its device workspace, with one method per C call.
+
+    Inputs and outputs are torch tensors on the current HIP device; every
+    call enqueues work on the current stream (or `stream`) and returns
+    without synchronising.
+    """
+
+    def __init__(self, width, height, census=7, ndisp=128, npaths=8, p1=10, p2=120,
+                 device=None):
+        self.W, self.H, self.n, self.w = int(width), int(height), int(census), int(ndisp)
+        self.npaths, self.p1, self.p2 = int(npaths), int(p1), int(p2)
+        self.plan = sgm_plan(self.W, self.H, self.n, self.w, self.npaths, self.p1, self.p2)
+        self.device = torch.device(device or "cuda")
+        self.ws_bytes = sgm_workspace_size(self.plan)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        plan = getattr(self, "plan", None)
+        if plan is not None and _lib is not None:
+            _lib.sgm_plan_free(plan)
+            self.plan = None
+
+    # shapes
+    @property
+    def image_shape(self):
+        return (self.H, self.W)
+
+    @property
+    def volume_shape(self):
+        return (self.H, self.W, self.w)
+
+    def _img(self, t, name):
+        _need(t, torch.uint8, None, name)
+        if t.dim() != 2 or t.shape[0] != self.H or t.shape[1] < self.W:
+            raise ValueError("%s must be uint8 [H, >=W]" % name)
+        return t
+
+    def _dlo(self, d_lo):
+        if d_lo is None:
+            return None
+        return _need(d_lo, torch.int32, (self.H,), "d_lo")
+
+    def new_volume(self, dtype=torch.uint8):
+        return torch.empty(self.volume_shape, dtype=dtype, device=self.device)
+
+    def census(self, image, codes=None, stream=None):
+        self._img(image, "image")
+        if codes is None:
+            codes = torch.empty((self.H, self.W), dtype=torch.int64, device=self.device)
+        _need(codes, torch.int64, (self.H, self.W), "codes")
+        _check(_lib.sgm_census(self.plan, _ptr(image), image.shape[1], _ptr(codes),
+                               _stream(stream)), "sgm_census")
+        return codes
+
+    def cost(self, left, right, d_lo=None, cost=None, stream=None):
+        self._img(left, "left")
+        self._img(right, "right")
+        if left.shape != right.shape:
+            raise ValueError("left and right must share a pitch")
+        if cost is None:
+            cost = self.new_volume(torch.uint8)
+        _need(cost, torch.uint8, self.volume_shape, "cost")
+        _check(_lib.sgm_cost(self.plan, _ptr(left), _ptr(right), left.shape[1],
+                             _ptr(self._dlo(d_lo)), _ptr(cost), _ptr(self.workspace),
+                             self.ws_bytes, _stream(stream)), "sgm_cost")
+        return cost
+
+    def aggregate(self, cost, out=None, stream=None):
+        _need(cost, torch.uint8, self.volume_shape, "cost")
+        if out is None:
+            out = self.new_volume(torch.int16)
+        _need(out, torch.int16, self.volume_shape, "sum")
+        _check(_lib.sgm_aggregate(self.plan, _ptr(cost), _ptr(out), _ptr(self.workspace),
+                                  self.ws_bytes, _stream(stream)), "sgm_aggregate")
+        return out
+
+    def aggregate_path(self, cost, path, out=None, stream=None):
+        _need(cost, torch.uint8, self.volume_shape, "cost")
+        if out is None:
+            out = self.new_volume(torch.int16)
+        _need(out, torch.int16, self.volume_shape, "L")
+        _check(_lib.sgm_aggregate_path(self.plan, _ptr(cost), int(path), _ptr(out),
+                                       _stream(stream)), "sgm_aggregate_path")
+        return out
+
+    def _outs(self, disp_int, disp_sub, want_sub):
+        if disp_int is None:
+            disp_int = torch.empty(self.image_shape, dtype=torch.int16, device=self.device)
+        _need(disp_int, torch.int16, self.image_shape, "disp_int")
+        if disp_sub is None and want_sub:
+            disp_sub = torch.empty(self.image_shape, dtype=torch.float32, device=self.device)
+        if disp_sub is not None:
+            _need(disp_sub, torch.float32, self.image_shape, "disp_sub")
+        return disp_int, disp_sub
+
+    def wta(self, sum_volume, d_lo=None, disp_int=None, disp_sub=None, subpixel=True, stream=None):
+        _need(sum_volume, torch.int16, self.volume_shape, "sum")
+        disp_int, disp_sub = self._outs(disp_int, disp_sub, subpixel)
+        _check(_lib.sgm_wta(self.plan, _ptr(sum_volume), _ptr(self._dlo(d_lo)), _ptr(disp_int),
+                            _ptr(disp_sub), _stream(stream)), "sgm_wta")
+        return disp_int, disp_sub
+
+    def aggregate_wta(self, cost, d_lo=None, disp_int=None, disp_sub=None, subpixel=True,
+                      stream=None):
+        _need(cost, torch.uint8, self.volume_shape, "cost")
+        disp_int, disp_sub = self._outs(disp_int, disp_sub, subpixel)
+        _check(_lib.sgm_aggregate_wta(self.plan, _ptr(cost), _ptr(self._dlo(d_lo)),
+                                      _ptr(disp_int), _ptr(disp_sub), _ptr(self.workspace),
+                                      self.ws_bytes, _stream(stream)), "sgm_aggregate_wta")
+        return disp_int, disp_sub
+
+    def match(self, left, right, d_lo=None, disp_int=None, disp_sub=None, subpixel=True,
+              stream=None):
+        self._img(left, "left")
+        self._img(right, "right")
+        disp_int, disp_sub = self._outs(disp_int, disp_sub, subpixel)
+        _check(_lib.sgm_match(self.plan, _ptr(left), _ptr(right), left.shape[1],
+                              _ptr(self._dlo(d_lo)), _ptr(disp_int), _ptr(disp_sub),
+                              _ptr(self.workspace), self.ws_bytes, _stream(stream)), "sgm_match")
+        return disp_int, disp_sub
+
+
+def u16(t: torch.Tensor) -> torch.Tensor:
+    """Reinterpret an int16 tensor holding uint16 values as int32 values."""
+    return t.to(torch.int32) & 0xFFFF

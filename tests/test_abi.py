@@ -1,0 +1,110 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+that include/sgm.h declares, and rejects bad arguments before enqueueing
+anything (none of these calls needs a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgm_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def sgm():
+    from paper_2012_10802_amd import sgm as mod
+    return mod
+
+
+def test_every_declared_symbol_is_exported(sgm):
+    names = _declared("sgm.h")
+    assert "sgm_plan" in names and "sgm_match" in names
+    lib = ctypes.CDLL(sgm.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _params(**kw):
+    from paper_2012_10802_amd.sgm import sgm_params
+    d = dict(width=64, height=32, census=7, ndisp=64, npaths=8, p1=10, p2=120, flags=0)
+    d.update(kw)
+    return sgm_params(**d)
+
+
+def _plan_status(sgm, **kw):
+    h = ctypes.c_void_p()
+    st = sgm.library().sgm_plan(ctypes.byref(_params(**kw)), ctypes.byref(h))
+    if st == 0:
+        sgm.library().sgm_plan_free(h)
+    return st
+
+
+@pytest.mark.parametrize("kw,want", [
+    ({}, 0),
+    ({"width": 0}, -1),
+    ({"height": -3}, -1),
+    ({"census": 9}, -2),
+    ({"census": 4}, -2),
+    ({"ndisp": 0}, -1),
+    ({"ndisp": 257}, -1),
+    ({"npaths": 6}, -2),
+    ({"p1": 11, "p2": 10}, -1),
+    ({"p1": -1}, -1),
+    ({"p2": 8200}, -1),
+    ({"flags": 1}, -1),
+    ({"width": 40000, "height": 40000, "ndisp": 8}, -2),
+    ({"census": 3, "ndisp": 256, "npaths": 4, "p2": 4000}, 0),
+])
+def test_plan_validation(sgm, kw, want):
+    assert _plan_status(sgm, **kw) == want
+
+
+def test_error_strings(sgm):
+    lib = sgm.library()
+    assert lib.sgm_status_str(-4) == b"SGM_ERR_WORKSPACE"
+    assert _plan_status(sgm, npaths=5) == -2
+    assert b"npaths" in lib.sgm_last_error()
+
+
+def test_workspace_size_and_checks(sgm):
+    lib = sgm.library()
+    plan = sgm.sgm_plan(1280, 720, 7, 128, 8, 10, 120)
+    try:
+        n = sgm.sgm_workspace_size(plan)
+        # census codes + cost + 8 uint8 per-path volumes
+        assert n >= 2 * 1280 * 720 * 8 + 9 * 1280 * 720 * 128
+        dummy = ctypes.c_void_p(256)
+        # null inputs and a short workspace are refused before any launch
+        assert lib.sgm_cost(plan, None, dummy, 1280, None, dummy, dummy, n, None) == -1
+        assert lib.sgm_cost(plan, dummy, dummy, 1000, None, dummy, dummy, n, None) == -1
+        assert lib.sgm_aggregate(plan, dummy, dummy, dummy, n - 1, None) == -4
+        assert lib.sgm_aggregate(plan, dummy, dummy, ctypes.c_void_p(258), n, None) == -1
+        assert lib.sgm_aggregate_path(plan, dummy, 8, dummy, None) == -1
+        assert lib.sgm_wta(plan, None, None, dummy, None, None) == -1
+        assert lib.sgm_match(plan, dummy, dummy, 1280, None, None, None, dummy, n, None) == -1
+        assert lib.sgm_aggregate(None, dummy, dummy, dummy, n, None) == -1
+    finally:
+        sgm.sgm_plan_free(plan)
+
+
+def test_window_helper_host(sgm):
+    import math
+    import oracle
+    d = sgm.sgm_window_from_road(20.0, 0.1, 0.0, 640, 480, 24, 0).numpy()
+    cy = 239.5
+    assert list(d) == [max(0, math.floor(20.0 + 0.1 * (v - cy) + 0.5) - 12) for v in range(480)]
+    for args in [(7.8, 0.0996, 0.05, 1280, 720, 24, 1, 3.0), (2.6, 0.09, -0.03, 640, 480, 32, 1, 0.5),
+                 (44.0, 0.15, 0.02, 1920, 1080, 16, 0, 0.0)]:
+        np.testing.assert_array_equal(sgm.sgm_window_from_road(*args).numpy(),
+                                      oracle.window_from_road(*args))
+    lib = sgm.library()
+    assert lib.sgm_window_from_road(1.0, 1.0, 0.0, 10, 10, 4, 2, 0.0, None) == -1
+    with pytest.raises(sgm.SgmError):
+        sgm.sgm_window_from_road(float("nan"), 1.0, 0.0, 10, 10, 4, 0)
