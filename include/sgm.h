@@ -124,6 +124,24 @@ sgm_status sgm_aggregate_wta(sgm_plan_t plan, const uint8_t *cost,
                              float *disp_sub, void *workspace,
                              size_t workspace_bytes, void *stream);
 
+/* Layout of the per-direction aggregated costs that sgm_aggregate_paths
+ * writes: npaths volumes [H][W][w] of elem_bytes each (1 when Cmax + P2 <=
+ * 255, else 2), volume r starting volume_stride bytes after volume r-1
+ * (a multiple of 256); total_bytes covers all of them. */
+sgm_status sgm_path_volumes(sgm_plan_t plan, int32_t *elem_bytes, size_t *volume_stride,
+                            size_t *total_bytes);
+
+/* The aggregation step alone (eq. (8)): every direction's L_r in one
+ * launch, written to `paths` (device, 256-byte aligned, layout from
+ * sgm_path_volumes; volume r holds direction r). */
+sgm_status sgm_aggregate_paths(sgm_plan_t plan, const uint8_t *cost, void *paths,
+                               size_t paths_bytes, void *stream);
+
+/* Selection on per-direction volumes (eq. (9), eq. (10)): S is summed on
+ * the fly and never stored; outputs as for sgm_wta. */
+sgm_status sgm_wta_paths(sgm_plan_t plan, const void *paths, const int32_t *d_lo,
+                         uint16_t *disp_int, float *disp_sub, void *stream);
+
 /* The whole path on one pair: census, cost, aggregation, selection and
  * sub-pixel step.  Identical outputs to sgm_cost + sgm_aggregate_wta; the
  * cost volume lives in the workspace. */

@@ -233,6 +233,45 @@ sgm_status sgm_aggregate_wta(sgm_plan_t plan, const uint8_t *cost, const int32_t
     return e == hipSuccess ? SGM_OK : hip_fail(e, "aggregate_wta launch");
 }
 
+sgm_status sgm_path_volumes(sgm_plan_t plan, int32_t *elem_bytes, size_t *volume_stride, size_t *total_bytes)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    const size_t esz = plan->kc.l8 ? 1 : 2;
+    const size_t vs = align256(plan->n_vol * esz);
+    if (elem_bytes) *elem_bytes = (int32_t)esz;
+    if (volume_stride) *volume_stride = vs;
+    if (total_bytes) *total_bytes = vs * (size_t)plan->pb.npaths;
+    return SGM_OK;
+}
+
+sgm_status sgm_aggregate_paths(sgm_plan_t plan, const uint8_t *cost, void *paths, size_t paths_bytes, void *stream)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!cost || !paths) return fail(SGM_ERR_INVALID, "cost and paths must not be NULL");
+    if (!is_aligned(paths, 256)) return fail(SGM_ERR_INVALID, "paths must be 256-byte aligned");
+    size_t total = 0;
+    sgm_path_volumes(plan, nullptr, nullptr, &total);
+    if (paths_bytes < total)
+        return fail(SGM_ERR_WORKSPACE, "paths buffer of %zu bytes is smaller than the %zu required", paths_bytes,
+                    total);
+    const sgm::KernelConfig kc = config_for(plan, cost, nullptr);
+    hipError_t e =
+        sgm::launch_aggregate(plan->pb, kc, cost, plan->paths, plan->pb.npaths, kc.l8, paths, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "aggregate_paths launch");
+}
+
+sgm_status sgm_wta_paths(sgm_plan_t plan, const void *paths, const int32_t *d_lo, uint16_t *disp_int,
+                         float *disp_sub, void *stream)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!paths || !disp_int) return fail(SGM_ERR_INVALID, "paths and disp_int must not be NULL");
+    if (!is_aligned(paths, 256)) return fail(SGM_ERR_INVALID, "paths must be 256-byte aligned");
+    const sgm::KernelConfig kc = config_for(plan, nullptr, nullptr);
+    hipError_t e = sgm::launch_wta_paths(plan->pb, kc, paths, plan->pb.npaths, kc.l8, d_lo, disp_int, disp_sub,
+                                         (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "wta_paths launch");
+}
+
 sgm_status sgm_match(sgm_plan_t plan, const uint8_t *left, const uint8_t *right, int32_t pitch, const int32_t *d_lo,
                      uint16_t *disp_int, float *disp_sub, void *ws, size_t ws_bytes, void *stream)
 {

@@ -55,6 +55,9 @@ def _load_library():
         "sgm_wta": [P, P, P, P, P, P],
         "sgm_aggregate_wta": [P, P, P, P, P, P, S, P],
         "sgm_match": [P, P, P, I, P, P, P, P, S, P],
+        "sgm_path_volumes": [P, ctypes.POINTER(I), ctypes.POINTER(S), ctypes.POINTER(S)],
+        "sgm_aggregate_paths": [P, P, P, S, P],
+        "sgm_wta_paths": [P, P, P, P, P, P],
         "sgm_window_from_road": [D, D, D, I, I, I, I, D, P],
         "sgm_status_str": [I],
         "sgm_last_error": [],
@@ -246,6 +249,41 @@ class Matcher:
         _check(_lib.sgm_aggregate_wta(self.plan, _ptr(cost), _ptr(self._dlo(d_lo)),
                                       _ptr(disp_int), _ptr(disp_sub), _ptr(self.workspace),
                                       self.ws_bytes, _stream(stream)), "sgm_aggregate_wta")
+        return disp_int, disp_sub
+
+    def path_volumes(self):
+        """(elem_bytes, volume_stride, total_bytes) of sgm_aggregate_paths' output."""
+        e, vs, tot = ctypes.c_int32(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.sgm_path_volumes(self.plan, ctypes.byref(e), ctypes.byref(vs), ctypes.byref(tot)),
+               "sgm_path_volumes")
+        return int(e.value), int(vs.value), int(tot.value)
+
+    def new_paths(self):
+        return torch.empty(self.path_volumes()[2], dtype=torch.uint8, device=self.device)
+
+    def aggregate_paths(self, cost, paths=None, stream=None):
+        _need(cost, torch.uint8, self.volume_shape, "cost")
+        if paths is None:
+            paths = self.new_paths()
+        _need(paths, torch.uint8, None, "paths")
+        _check(_lib.sgm_aggregate_paths(self.plan, _ptr(cost), _ptr(paths), paths.numel(),
+                                        _stream(stream)), "sgm_aggregate_paths")
+        return paths
+
+    def path_volume(self, paths, r):
+        """View of direction r's volume inside an sgm_aggregate_paths buffer."""
+        e, vs, _ = self.path_volumes()
+        n = self.H * self.W * self.w
+        v = paths[r * vs: r * vs + n * e]
+        return (v if e == 1 else v.view(torch.int16)).view(self.volume_shape)
+
+    def wta_paths(self, paths, d_lo=None, disp_int=None, disp_sub=None, subpixel=True, stream=None):
+        _need(paths, torch.uint8, None, "paths")
+        if paths.numel() < self.path_volumes()[2]:
+            raise ValueError("paths buffer too small")
+        disp_int, disp_sub = self._outs(disp_int, disp_sub, subpixel)
+        _check(_lib.sgm_wta_paths(self.plan, _ptr(paths), _ptr(self._dlo(d_lo)), _ptr(disp_int),
+                                  _ptr(disp_sub), _stream(stream)), "sgm_wta_paths")
         return disp_int, disp_sub
 
     def match(self, left, right, d_lo=None, disp_int=None, disp_sub=None, subpixel=True,

@@ -167,13 +167,16 @@ def _full_parity(lib, name, seed, d_lo=None):
     cost = m.cost(_dev(p.left), _dev(p.right), d_lo=dl)
     dint, dsub = m.aggregate_wta(cost, d_lo=dl)
     mi, ms = m.match(_dev(p.left), _dev(p.right), d_lo=dl)
+    # the split calls bench.py times
+    paths = m.aggregate_paths(cost)
+    bi, bs = m.wta_paths(paths, d_lo=dl)
     torch.cuda.synchronize()
     n, w = c["census"], c["ndisp"]
     want_c = oracle.cost(oracle.census(p.left, n), oracle.census(p.right, n), n, w, d_lo)
     np.testing.assert_array_equal(cost.cpu().numpy(), want_c)
     want_S = oracle.sum_paths(want_c, c["npaths"], c["p1"], c["p2"])
     wi, ws = oracle.wta(want_S, d_lo)
-    for a, b in ((dint, dsub), (mi, ms)):
+    for a, b in ((dint, dsub), (mi, ms), (bi, bs)):
         np.testing.assert_array_equal(_np_u16(a), wi)
         assert np.abs(b.cpu().numpy() - ws).max() <= SUB_TOL
         np.testing.assert_array_equal(b.cpu().numpy(), ws)
@@ -224,3 +227,29 @@ def test_repeatable_bitwise(lib):
     for a, b in outs[1:]:
         np.testing.assert_array_equal(a, outs[0][0])
         np.testing.assert_array_equal(b, outs[0][1])
+
+
+@pytest.mark.parametrize("shape", [(133, 41, 7, 128, 8), (70, 23, 7, 24, 8), (61, 27, 7, 48, 8)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_split_aggregate_paths_and_selection(lib, shape):
+    """sgm_aggregate_paths (all directions, one launch) + sgm_wta_paths."""
+    import torch
+    W, H, n, w, R = shape
+    p2 = 120 if w != 48 else 220  # 48: Cmax + P2 > 255 -> uint16 volumes
+    L, Rimg = _rand_pair(W, H, 17 + w)
+    d_lo = np.random.default_rng(w).integers(0, 4, size=H).astype(np.int32)
+    m = lib.Matcher(W, H, census=n, ndisp=w, npaths=R, p1=10, p2=p2)
+    cost = m.cost(_dev(L), _dev(Rimg), d_lo=_dev(d_lo))
+    paths = m.aggregate_paths(cost)
+    dint, dsub = m.wta_paths(paths, d_lo=_dev(d_lo))
+    torch.cuda.synchronize()
+    c = cost.cpu().numpy()
+    esz = m.path_volumes()[0]
+    assert esz == (1 if 48 + p2 <= 255 else 2)
+    for r in range(R):
+        got = m.path_volume(paths, r).cpu().numpy()
+        got = got.view(np.uint16) if esz == 2 else got
+        np.testing.assert_array_equal(got, oracle.path(c, r, 10, p2), err_msg="path %d" % r)
+    wi, ws = oracle.wta(oracle.sum_paths(c, R, 10, p2), d_lo)
+    np.testing.assert_array_equal(_np_u16(dint), wi)
+    np.testing.assert_array_equal(dsub.cpu().numpy(), ws)
