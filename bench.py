@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--workload", default="road1280", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=2001)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="after timing, run one device-to-device copy of this many MiB "
+                         "(reference kernel for scaling memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the SGM path shards by independent stereo pairs and "
@@ -134,6 +137,14 @@ def main():
 
     evals = W * H * w
     value = evals / (ms_per_step * 1e-3) / 1e6
+
+    if args.copy_calibration_mb:
+        src = torch.ones(args.copy_calibration_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # dominant kernel: the one-launch aggregation of all directions
     elem_bytes, _, _ = m.path_volumes()

@@ -66,7 +66,8 @@ typedef struct {
     int32_t census;        /* census window side n: 3, 5 or 7 (Cmax = n*n-1) */
     int32_t ndisp;         /* window width w, 1..256                       */
     int32_t npaths;        /* 4 or 8                                       */
-    int32_t p1, p2;        /* 0 <= P1 <= P2 and Cmax + 2*P2 < 16383        */
+    int32_t p1, p2;        /* 0 <= P1 <= P2, 2*Cmax + 3*P2 < 16383 and
+                              npaths * (Cmax + P2) <= 65535                 */
     uint32_t flags;        /* reserved, must be 0                          */
 } sgm_params;
 

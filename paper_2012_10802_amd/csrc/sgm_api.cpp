@@ -112,8 +112,10 @@ sgm_status sgm_plan(const sgm_params *pr, sgm_plan_t *out)
     if (q.npaths != 4 && q.npaths != 8) return fail(SGM_ERR_UNSUPPORTED, "npaths %d not in {4, 8}", q.npaths);
     if (q.p1 < 0 || q.p2 < q.p1) return fail(SGM_ERR_INVALID, "need 0 <= P1 <= P2 (got %d, %d)", q.p1, q.p2);
     const int cmax = q.census * q.census - 1;
-    if (cmax + 2 * q.p2 >= 0x3FFF)
-        return fail(SGM_ERR_INVALID, "need Cmax + 2*P2 < 16383 (Cmax %d, P2 %d)", cmax, q.p2);
+    // window indices beyond w carry the cost 0x3FFF; they never win a
+    // minimum while 2*Cmax + 3*P2 < 0x3FFF
+    if (2 * cmax + 3 * q.p2 >= 0x3FFF)
+        return fail(SGM_ERR_INVALID, "need 2*Cmax + 3*P2 < 16383 (Cmax %d, P2 %d)", cmax, q.p2);
     if ((long long)q.npaths * (cmax + q.p2) > 0xFFFF)
         return fail(SGM_ERR_INVALID, "summed cost would exceed 16 bits");
     if ((long long)q.width * q.height * q.ndisp >= (1ll << 31))

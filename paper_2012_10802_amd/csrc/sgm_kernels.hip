@@ -14,11 +14,10 @@
 //   * loads its VPL cost bytes (prefetched PF steps ahead into registers),
 //   * forms the k-1 / k+1 neighbour pairs with v_alignbit inside the lane
 //     and one row_shr / row_shl DPP move across lanes,
-//   * evaluates min(L'(k), min(L'(k-1), L'(k+1)) + P1, P2) + C with packed
-//     u16 min/add (L' is the previous pixel's L minus its minimum, so the
-//     "m_q + P2" term of eq. (8) becomes the constant P2),
-//   * reduces the minimum over the window with four DPP steps and
-//     subtracts it for the next step.
+//   * reduces the predecessor's minimum m_q over the window with four DPP
+//     steps (independent of, and overlapped with, the neighbour terms),
+//   * evaluates C + min(L(k), min(L(k-1), L(k+1)) + P1, m_q + P2) - m_q with
+//     packed u16 min/add/sub.
 // Window indices k >= w (when 16*VPL > w) carry the cost 0x3FFF; their
 // aggregated values then never win a minimum because Cmax + 2 P2 < 0x3FFF.
 //
@@ -110,6 +109,7 @@ struct Raw {
     uint32_t d[NW];
 };
 
+// (used for the per-direction volumes, which are read once: non-temporal)
 template <int VPL, bool ALIGNED>
 __device__ __forceinline__ void load_u8(Raw<VPL> &r, const uint8_t *p, int nvalid)
 {
@@ -119,20 +119,21 @@ __device__ __forceinline__ void load_u8(Raw<VPL> &r, const uint8_t *p, int nvali
         } else if constexpr (VPL == 4) {
             r.d[0] = *reinterpret_cast<const uint32_t *>(p);
         } else if constexpr (VPL == 8) {
-            const uint2 t = *reinterpret_cast<const uint2 *>(p);
-            r.d[0] = t.x;
-            r.d[1] = t.y;
+            const unsigned long long t = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p));
+            r.d[0] = (uint32_t)t;
+            r.d[1] = (uint32_t)(t >> 32);
         } else if constexpr (VPL == 12) {
             const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
-            r.d[0] = q[0];
-            r.d[1] = q[1];
-            r.d[2] = q[2];
+            r.d[0] = __builtin_nontemporal_load(q);
+            r.d[1] = __builtin_nontemporal_load(q + 1);
+            r.d[2] = __builtin_nontemporal_load(q + 2);
         } else {
-            const uint4 t = *reinterpret_cast<const uint4 *>(p);
-            r.d[0] = t.x;
-            r.d[1] = t.y;
-            r.d[2] = t.z;
-            r.d[3] = t.w;
+            const unsigned long long *q = reinterpret_cast<const unsigned long long *>(p);
+            const unsigned long long t0 = __builtin_nontemporal_load(q), t1 = __builtin_nontemporal_load(q + 1);
+            r.d[0] = (uint32_t)t0;
+            r.d[1] = (uint32_t)(t0 >> 32);
+            r.d[2] = (uint32_t)t1;
+            r.d[3] = (uint32_t)(t1 >> 32);
         }
     } else {
 #pragma unroll
@@ -282,43 +283,65 @@ __global__ __launch_bounds__(256) void k_census(const uint8_t *__restrict__ img,
 
 // ---------------------------------------------------------------------------
 // matching cost: C(u,v,k) = popcount(cL(u,v) ^ cR(u - d_lo(v) - k, v))
+//
+// A workgroup covers kCostTile pixels of one row.  The left codes of the
+// tile and the right codes of every column the tile's windows reach are
+// staged in LDS.  Each thread then produces CH consecutive window values of
+// one pixel per item; neighbouring lanes take neighbouring pixels, so the
+// LDS reads of a wave are conflict-free (8-byte stride), and a pixel's
+// window is written in CH-byte pieces.
 
-template <int VPL, bool ALIGNED>
+constexpr int kCostTile = 64;
+
+template <int CH>
 __global__ __launch_bounds__(256) void k_cost(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr,
                                               const int32_t *__restrict__ d_lo, int W, int H, int w, int cmax,
                                               uint8_t *__restrict__ cost)
 {
-    __shared__ uint64_t s_cr[16 + 256];
+    __shared__ uint64_t s_cl[kCostTile];
+    __shared__ uint64_t s_cr[kCostTile + 256];
     const int v = blockIdx.y;
-    const int u0 = blockIdx.x * 16;
+    const int u0 = blockIdx.x * kCostTile;
     const int lo = d_lo ? d_lo[v] : 0;
     const int first = u0 - lo - (w - 1);  // right column held in s_cr[0]
-    for (int t = threadIdx.x; t < 15 + w; t += blockDim.x) {
+    const uint64_t *crow = cr + (size_t)v * W;
+    for (int t = threadIdx.x; t < kCostTile - 1 + w; t += blockDim.x) {
         const int col = first + t;
-        s_cr[t] = (col >= 0 && col < W) ? cr[(size_t)v * W + col] : 0ull;
+        s_cr[t] = (col >= 0 && col < W) ? crow[col] : 0ull;
     }
+    for (int t = threadIdx.x; t < kCostTile; t += blockDim.x)
+        s_cl[t] = (u0 + t < W) ? cl[(size_t)v * W + u0 + t] : 0ull;
     __syncthreads();
-    const int lane = threadIdx.x & 15;
-    const int u = u0 + (threadIdx.x >> 4);
-    const int kbase = lane * VPL;
-    if (u >= W || kbase >= w) return;
-    const int nvalid = min(VPL, w - kbase);
-    const uint64_t a = cl[(size_t)v * W + u];
-    uint32_t pairs[VPL / 2];
+    const int npix = min(kCostTile, W - u0);
+    const int nch = (w + CH - 1) / CH;
+    uint8_t *out = cost + ((size_t)v * W + u0) * w;
+    for (int it = threadIdx.x; it < npix * nch; it += blockDim.x) {
+        const int ch = it / npix, px = it - ch * npix;
+        const int k0 = CH * ch;
+        const uint64_t a = s_cl[px];
+        // right column of window index k: u0 + px - lo - k = first + (px + w - 1 - k)
+        const int base = px + w - 1 - k0;
+        const int col0 = u0 + px - lo - k0;
+        uint32_t word[CH / 4];
 #pragma unroll
-    for (int j = 0; j < VPL / 2; ++j) {
-        uint32_t pr = 0;
+        for (int q = 0; q < CH / 4; ++q) {
+            uint32_t wd = 0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int k = kbase + 2 * j + h;
-            const int col = u - lo - k;
-            uint32_t c = (uint32_t)cmax;
-            if (col >= 0 && k < w) c = (uint32_t)__popcll(a ^ s_cr[col - first]);
-            pr |= c << (16 * h);
+            for (int h = 0; h < 4; ++h) {
+                const int kk = 4 * q + h;
+                uint32_t c = (uint32_t)cmax;
+                if (col0 - kk >= 0 && k0 + kk < w) c = (uint32_t)__popcll(a ^ s_cr[base - kk]);
+                wd |= c << (8 * h);
+            }
+            word[q] = wd;
         }
-        pairs[j] = pr;
+        uint8_t *dst = out + (size_t)px * w + k0;
+        if constexpr (CH == 16) {
+            *reinterpret_cast<uint4 *>(dst) = make_uint4(word[0], word[1], word[2], word[3]);
+        } else {
+            for (int h = 0; h < CH && k0 + h < w; ++h) dst[h] = (uint8_t)(word[h / 4] >> (8 * (h % 4)));
+        }
     }
-    store_u8_pairs<VPL, ALIGNED>(cost + ((size_t)v * W + u) * w + kbase, pairs, nvalid);
 }
 
 // ---------------------------------------------------------------------------
@@ -384,6 +407,9 @@ __device__ __forceinline__ Line line_geom(int idx, int du, int dv, int W, int H)
 // are discarded), so scanlines outside the image need no branches.
 constexpr uint32_t kOff = 0x80000000u;  // an offset outside every buffer
 constexpr int kRsrcWord3 = 0x00020000;
+// cache policy of the per-direction volume stores: non-temporal, so the
+// streamed volumes do not evict the cost volume that every direction reads
+constexpr int kStreamPolicy = 2;
 
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 typedef unsigned int v3u __attribute__((ext_vector_type(3)));
@@ -486,91 +512,191 @@ __device__ __forceinline__ void buf_store_pairs(const uint32_t (&v)[VPL / 2], __
     }
 }
 
+// Inside the aggregation a lane keeps its VPL window values as NP = VPL/2
+// packed pairs in a strided order: pair j holds (k0 + j, k0 + j + NP).  The
+// k-1 neighbours of pair j are then pair j-1 and the k+1 neighbours pair
+// j+1, so only the two end pairs need a shuffle (one alignbit each, fed by
+// a DPP move from the neighbouring lane).
+template <int VPL>
+__device__ __forceinline__ uint32_t unpack_strided(const Raw<VPL> &r, int j)
+{
+    constexpr int NP = VPL / 2;
+    const int blo = j, bhi = j + NP;
+    const uint32_t sel = (uint32_t)(blo % 4) | (0x0Cu << 8) | ((uint32_t)(4 + bhi % 4) << 16) | (0x0Cu << 24);
+    return __builtin_amdgcn_perm(r.d[bhi / 4], r.d[blo / 4], sel);
+}
+
+// strided pairs -> the lane's VPL bytes in window order, packed in dwords
+template <int VPL>
+__device__ __forceinline__ void pack_strided(const uint32_t (&p)[VPL / 2], uint32_t (&d)[(VPL + 3) / 4])
+{
+    constexpr int NP = VPL / 2;
+    if constexpr (NP == 1) {
+        d[0] = __builtin_amdgcn_perm(p[0], p[0], 0x0C0C0200u);
+    } else if constexpr (NP == 2) {
+        d[0] = __builtin_amdgcn_perm(p[1], p[0], 0x06020400u);
+    } else {
+        // t[q] = (p[2q].lo, p[2q+1].lo, p[2q].hi, p[2q+1].hi)
+        uint32_t t[NP / 2];
+#pragma unroll
+        for (int q = 0; q < NP / 2; ++q) t[q] = __builtin_amdgcn_perm(p[2 * q + 1], p[2 * q], 0x06020400u);
+        // byte b of the lane: b < NP -> low byte of pair b, else high of b-NP
+        // = byte (b%2) + 2*(b >= NP) of t[(b % NP) / 2]
+#pragma unroll
+        for (int q = 0; q < (VPL + 3) / 4; ++q) {
+            const int b0 = 4 * q, b2 = 4 * q + 2;
+            const int ta = (b0 % NP) / 2, tb = (b2 % NP) / 2;
+            const uint32_t sa = (uint32_t)((b0 >= NP) ? 2 : 0), sb = (uint32_t)((b2 >= NP) ? 2 : 0);
+            // bytes b0, b0+1 come from t[ta], bytes b2, b2+1 from t[tb]
+            const uint32_t sel = (sa) | ((sa + 1) << 8) | ((4 + sb) << 16) | ((5 + sb) << 24);
+            d[q] = __builtin_amdgcn_perm(t[tb], t[ta], sel);
+        }
+    }
+}
+
+// stores of one lane's aggregated values (strided pairs) at element offset
+// `off` of the output volume (kOff: dropped by the range check)
+template <int VPL, bool ALIGNED, bool L8>
+__device__ __forceinline__ void store_strided(const uint32_t (&v)[VPL / 2], __amdgpu_buffer_rsrc_t rs, uint32_t off,
+                                              int nvalid)
+{
+    constexpr int NP = VPL / 2;
+    if constexpr (ALIGNED && L8) {
+        uint32_t d[(VPL + 3) / 4];
+        pack_strided<VPL>(v, d);
+        if constexpr (VPL == 2) {
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)d[0], rs, off, 0, kStreamPolicy);
+        } else if constexpr (VPL == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(d[0], rs, off, 0, kStreamPolicy);
+        } else if constexpr (VPL == 8) {
+            const v2u t = {d[0], d[1]};
+            __builtin_amdgcn_raw_buffer_store_b64(t, rs, off, 0, kStreamPolicy);
+        } else if constexpr (VPL == 12) {
+            const v3u t = {d[0], d[1], d[2]};
+            __builtin_amdgcn_raw_buffer_store_b96(t, rs, off, 0, kStreamPolicy);
+        } else {
+            const v4u t = {d[0], d[1], d[2], d[3]};
+            __builtin_amdgcn_raw_buffer_store_b128(t, rs, off, 0, kStreamPolicy);
+        }
+    } else {
+        // value i of the lane: pair i % NP, half i / NP
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) {
+            const uint32_t val = (i < NP) ? (v[i] & 0xFFFFu) : (v[i - NP] >> 16);
+            const bool ok = i < nvalid && off != kOff;
+            if (L8)
+                __builtin_amdgcn_raw_buffer_store_b8((unsigned char)val, rs, ok ? off + i : kOff, 0, kStreamPolicy);
+            else
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)val, rs, ok ? 2 * (off + i) : kOff, 0,
+                                                      kStreamPolicy);
+        }
+    }
+}
+
 // vector memory instructions issued per aggregation step (loads, stores)
 template <int VPL, bool ALIGNED, bool L8>
 struct VmemPerStep {
     static constexpr int loads = ALIGNED ? 1 : VPL;
-    static constexpr int stores = !ALIGNED ? VPL : (L8 ? 1 : (VPL / 2 <= 2 ? 1 : VPL / 4));
+    static constexpr int stores = (ALIGNED && L8) ? 1 : VPL;
     static constexpr int total = loads + stores;
 };
 
-// s_waitcnt immediate that waits until at most n vector memory operations
-// are outstanding (gfx9 encoding; expcnt and lgkmcnt left at their maxima)
+// s_waitcnt immediate: wait until at most n vector memory operations are
+// outstanding (gfx9 encoding; expcnt and lgkmcnt left at their maxima)
 constexpr int vmcnt_imm(int n)
 {
-    return (n > 63 ? 63 : n) < 0 ? 0x0F70 : (((n > 63 ? 63 : n) & 0xF) | (0x7 << 4) | (0xF << 8) | (((n > 63 ? 63 : n) >> 4) << 14));
+    return ((n > 63 ? 63 : n) & 0xF) | (0x7 << 4) | (0xF << 8) | (((n > 63 ? 63 : n) >> 4) << 14);
 }
 
-template <int VPL, bool ALIGNED, bool PAD, bool L8, int PF>
-__global__ __launch_bounds__(256) void k_aggregate(AggParams a)
+enum { kHorizontal = 0, kVertical = 1, kDiagonal = 2 };
+
+// One workgroup's scanlines of one direction.  KIND selects the bookkeeping:
+// horizontal and vertical scanlines cover the whole image edge to edge, so
+// every lane is active at every step (tail lines past the last scanline
+// repeat the last one, writing identical values to identical addresses);
+// diagonal scanlines enter and leave the image at different steps, and
+// only their loads and stores are masked.  Before a scanline enters the
+// image its loads return 0, which keeps L' at 0, so the first in-image
+// step computes L = C without any reset.
+template <int VPL, bool ALIGNED, bool PAD, bool L8, int PF, int KIND>
+__device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsrc_t rc, __amdgpu_buffer_rsrc_t ro,
+                                         int du, int dv, int g)
 {
     constexpr int NP = VPL / 2;
+    constexpr int UNROLL = 2 * PF;  // steps per loop iteration
     const int lane = threadIdx.x & 15;
     const int lw = threadIdx.x >> 4;
-    int slot = 0;
-    while (slot + 1 < a.np && (int)blockIdx.x >= a.gstart[slot + 1]) ++slot;
-    const int r = a.paths[slot] & 0xFF;
-    const int vol = a.paths[slot] >> 8;
-    const int g = (int)blockIdx.x - a.gstart[slot];
-    const int du = dir_du(r), dv = dir_dv(r);
     const int W = a.W, H = a.H, w = a.w;
+    const int lpw = a.lines_per_wg;
 
-    // step range of the whole workgroup (uniform) and of this scanline
-    int I0 = 1 << 30, I1 = 0;
-    for (int l = 0; l < a.lines_per_wg; ++l) {
-        const Line t = line_geom(g * a.lines_per_wg + l, du, dv, W, H);
-        if (t.i1 > t.i0) {
-            I0 = min(I0, t.i0);
-            I1 = max(I1, t.i1);
+    int I0 = 0, I1;
+    int idx = g * lpw + lw;
+    if constexpr (KIND == kHorizontal) {
+        idx = min(idx, H - 1);
+        I1 = W;
+    } else if constexpr (KIND == kVertical) {
+        idx = min(idx, W - 1);
+        I1 = H;
+    } else {
+        I0 = 1 << 30;
+        I1 = 0;
+        for (int l = 0; l < lpw; ++l) {
+            const Line t = line_geom(g * lpw + l, du, dv, W, H);
+            if (t.i1 > t.i0) {
+                I0 = min(I0, t.i0);
+                I1 = max(I1, t.i1);
+            }
         }
+        if (I1 <= I0) return;
     }
-    if (I1 <= I0) return;
-    const Line ln = line_geom(g * a.lines_per_wg + lw, du, dv, W, H);
+    const Line ln = line_geom(idx, du, dv, W, H);
     const int kbase = lane * VPL;
     const int nvalid = min(max(w - kbase, 0), VPL);
-    const int nlen = nvalid > 0 ? ln.i1 - ln.i0 : 0;  // steps this lane loads and stores
+    const bool has = nvalid > 0;
     // element offset of this lane's values at step i: off0 + i * stride
-    // (wrapping 32-bit arithmetic; exact whenever the pixel is in the image)
-    const uint32_t off0 = (uint32_t)((ln.vb * W + ln.ub) * w + kbase);
-    const uint32_t stride = (uint32_t)((ln.sv * W + ln.su) * w);
-    const uint32_t nbytes = (uint32_t)W * (uint32_t)H * (uint32_t)w;
-    const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost, nbytes);
-    const __amdgpu_buffer_rsrc_t ro =
-        L8 ? make_rsrc(static_cast<const uint8_t *>(a.out) + (size_t)vol * a.vstride, nbytes)
-           : make_rsrc(static_cast<const uint16_t *>(a.out) + (size_t)vol * a.vstride, nbytes * 2u);
+    // (wrapping 32-bit arithmetic; exact whenever the pixel is in the image);
+    // lanes past the window never touch memory (offset stays kOff)
+    const uint32_t stride = has ? (uint32_t)((ln.sv * W + ln.su) * w) : 0u;
+    const uint32_t off0 = has ? (uint32_t)((ln.vb * W + ln.ub) * w + kbase) : kOff;
+    const uint32_t li0 = (uint32_t)ln.i0, llen = (uint32_t)(ln.i1 - ln.i0);
+    auto offset = [&](int i) -> uint32_t {
+        const uint32_t o = off0 + (uint32_t)i * stride;
+        if constexpr (KIND == kDiagonal)
+            return ((uint32_t)i - li0 < llen) ? o : kOff;
+        else
+            return o;
+    };
 
     uint32_t padp[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         padp[j] = 0;
         if (PAD) {
-            if (2 * j >= nvalid) padp[j] |= kPad;
-            if (2 * j + 1 >= nvalid) padp[j] |= kPad << 16;
+            if (j >= nvalid) padp[j] |= kPad;
+            if (j + NP >= nvalid) padp[j] |= kPad << 16;
         }
     }
 
     Raw<VPL> ring[PF];
 #pragma unroll
-    for (int s = 0; s < PF; ++s) {
-        const int i = I0 + s;
-        const uint32_t o = (uint32_t)(i - ln.i0) < (uint32_t)nlen ? off0 + (uint32_t)i * stride : kOff;
-        buf_load_u8<VPL, ALIGNED>(ring[s], rc, o, nvalid);
-    }
+    for (int s = 0; s < PF; ++s)
+        buf_load_u8<VPL, ALIGNED>(ring[s], rc, (I0 + s < I1) ? offset(I0 + s) : kOff, nvalid);
 
-    uint32_t Lp[NP];
+    // Lq: the predecessor's L (as stored), mnq: its running pair minimum.
+    // A scanline starts from Lq = 0 (then L = C + min(0, P1, P2) - 0 = C).
+    uint32_t Lq[NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) Lp[j] = 0;
+    for (int j = 0; j < NP; ++j) Lq[j] = 0;
+    uint32_t mnq = 0;
 
-    // the step count is padded to a multiple of PF; padded steps are
-    // inactive in every lane
-    const int nblk = (I1 - I0 + PF - 1) / PF;
+    // the step count is padded to a multiple of UNROLL; padded steps load
+    // nothing and store nothing
+    const int nblk = (I1 - I0 + UNROLL - 1) / UNROLL;
     for (int blk = 0; blk < nblk; ++blk) {
 #pragma unroll
-        for (int s = 0; s < PF; ++s) {
-            const int i = I0 + blk * PF + s;
-            const bool act = (uint32_t)(i - ln.i0) < (uint32_t)(ln.i1 - ln.i0);
-            const bool io = (uint32_t)(i - ln.i0) < (uint32_t)nlen;
-            // ring[s] was loaded PF steps ago; everything issued since then
+        for (int s = 0; s < UNROLL; ++s) {
+            const int i = I0 + blk * UNROLL + s;
+            // ring[s % PF] was loaded PF steps ago; everything issued since
             // may stay in flight.  The scheduling fence keeps later steps'
             // reads of the ring below this wait.
             __builtin_amdgcn_sched_barrier(0);
@@ -578,33 +704,68 @@ __global__ __launch_bounds__(256) void k_aggregate(AggParams a)
                                                  (PF - 1) * VmemPerStep<VPL, ALIGNED, L8>::total));
             uint32_t c2[NP];
 #pragma unroll
-            for (int j = 0; j < NP; ++j) c2[j] = unpack_pair(ring[s], j) | padp[j];
+            for (int j = 0; j < NP; ++j) c2[j] = unpack_strided(ring[s % PF], j) | padp[j];
             {
                 const int ip = i + PF;
-                const uint32_t o =
-                    (uint32_t)(ip - ln.i0) < (uint32_t)nlen ? off0 + (uint32_t)ip * stride : kOff;
-                buf_load_u8<VPL, ALIGNED>(ring[s], rc, o, nvalid);
+                const uint32_t o = (ip < I1) ? offset(ip) : kOff;
+                buf_load_u8<VPL, ALIGNED>(ring[s % PF], rc, o, nvalid);
             }
-            // neighbours across the lane edges (outside the window: 0x3FFF)
-            const uint32_t le = dpp<kRowShr1>(kInf2, Lp[NP - 1]);
-            const uint32_t re = dpp<kRowShl1>(kInf2, Lp[0]);
+            // m_q = min_k L(q,k): lane-local pair minimum (computed at the end
+            // of the previous step) reduced over the 16 lanes.  This chain is
+            // independent of the neighbour terms below, which overlap it.
+            const uint32_t m = row_min16(min(mnq & 0xFFFFu, mnq >> 16));
+            const uint32_t mm = m | (m << 16);
+            const uint32_t mp2 = pk_add(mm, a.p2x2);
+            // end neighbours across the lane edges (outside the window: 0x3FFF)
+            const uint32_t e = dpp<kRowShr1>(kInf2, Lq[NP - 1]);
+            const uint32_t f = dpp<kRowShl1>(kInf2, Lq[0]);
             uint32_t Ln[NP];
             uint32_t mn = 0xFFFFFFFFu;
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
-                const uint32_t lft = __builtin_amdgcn_alignbit(Lp[j], j ? Lp[j - 1] : le, 16);
-                const uint32_t rgt = __builtin_amdgcn_alignbit(j + 1 < NP ? Lp[j + 1] : re, Lp[j], 16);
+                const uint32_t lft = j ? Lq[j - 1] : __builtin_amdgcn_alignbit(Lq[NP - 1], e, 16);
+                const uint32_t rgt = j + 1 < NP ? Lq[j + 1] : __builtin_amdgcn_alignbit(f, Lq[0], 16);
+                // L(p,k) = C(p,k) + min(L(q,k), L(q,k+-1) + P1, m_q + P2) - m_q
                 uint32_t t = pk_add(pk_min(lft, rgt), a.p1x2);
-                t = pk_min(pk_min(t, Lp[j]), a.p2x2);
-                Ln[j] = pk_add(t, c2[j]);
+                t = pk_min(pk_min(t, Lq[j]), mp2);
+                Ln[j] = pk_sub(pk_add(t, c2[j]), mm);
                 mn = pk_min(mn, Ln[j]);
             }
-            const uint32_t m = row_min16(min(mn & 0xFFFFu, mn >> 16));
-            const uint32_t mm = m | (m << 16);
-            buf_store_pairs<VPL, ALIGNED, L8>(Ln, ro, io ? off0 + (uint32_t)i * stride : kOff, nvalid);
+            store_strided<VPL, ALIGNED, L8>(Ln, ro, (i < I1) ? offset(i) : kOff, nvalid);
 #pragma unroll
-            for (int j = 0; j < NP; ++j) Lp[j] = act ? pk_sub(Ln[j], mm) : 0u;
+            for (int j = 0; j < NP; ++j) Lq[j] = Ln[j];
+            mnq = mn;
         }
+    }
+}
+
+template <int VPL, bool ALIGNED, bool PAD, bool L8, int PF>
+__global__ __launch_bounds__(256) void k_aggregate(AggParams a)
+{
+    int slot = 0;
+    while (slot + 1 < a.np && (int)blockIdx.x >= a.gstart[slot + 1]) ++slot;
+    // workgroup-uniform by construction; say so, so that the buffer
+    // descriptors built from them stay in scalar registers
+    slot = __builtin_amdgcn_readfirstlane(slot);
+    const int r = a.paths[slot] & 0xFF;
+    const int vol = __builtin_amdgcn_readfirstlane(a.paths[slot] >> 8);
+    const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x - a.gstart[slot]);
+    const int du = __builtin_amdgcn_readfirstlane(dir_du(r)), dv = __builtin_amdgcn_readfirstlane(dir_dv(r));
+    // buffer descriptors (scalar registers): the cost volume and this
+    // direction's output volume
+    const uint32_t nbytes = (uint32_t)a.W * (uint32_t)a.H * (uint32_t)a.w;
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost, nbytes);
+    const __amdgpu_buffer_rsrc_t ro =
+        L8 ? make_rsrc(static_cast<const uint8_t *>(a.out) + (size_t)vol * a.vstride, nbytes)
+           : make_rsrc(static_cast<const uint16_t *>(a.out) + (size_t)vol * a.vstride, nbytes * 2u);
+    if (dv == 0) {
+        // the longest dependency chains: issue them first on a shared SIMD
+        __builtin_amdgcn_s_setprio(2);
+        agg_scan<VPL, ALIGNED, PAD, L8, PF, kHorizontal>(a, rc, ro, du, dv, g);
+    } else if (du == 0) {
+        agg_scan<VPL, ALIGNED, PAD, L8, PF, kVertical>(a, rc, ro, du, dv, g);
+    } else {
+        agg_scan<VPL, ALIGNED, PAD, L8, PF, kDiagonal>(a, rc, ro, du, dv, g);
     }
 }
 
@@ -714,6 +875,59 @@ __global__ __launch_bounds__(256) void k_wta_sum(const uint16_t *__restrict__ su
     select_and_write<VPL>(S, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
 }
 
+// Selection on uint8 per-direction volumes: the byte sums are formed SWAR
+// style, even and odd bytes of each dword accumulating in the two u16
+// halves of separate registers (sums <= npaths * (Cmax + P2) <= 65535, so
+// halves never carry).  ev[q] then holds S at window indices (4q, 4q+2) and
+// od[q] at (4q+1, 4q+3) of the lane's range.
+template <int VPL>
+__device__ __forceinline__ void select_swar(const uint32_t (&ev)[Raw<VPL>::NW], const uint32_t (&od)[Raw<VPL>::NW],
+                                            int kbase, int w, int lane, int lo, long long pix, uint16_t *dint,
+                                            float *dsub)
+{
+    constexpr int NW = Raw<VPL>::NW;
+    uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int k = kbase + 4 * q + h;
+            const uint32_t sv = ((h & 1) ? od[q] : ev[q]) >> (16 * (h >> 1)) & 0xFFFFu;
+            if (4 * q + h < VPL && k < w) best = min(best, (sv << 8) | (uint32_t)k);
+        }
+    }
+    best = row_min16(best);
+    const int ks = (int)(best & 0xFFu);
+    const int s0 = (int)(best >> 8);
+    uint32_t sm = 0, sp = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int k = kbase + 4 * q + h;
+            const uint32_t sv = ((h & 1) ? od[q] : ev[q]) >> (16 * (h >> 1)) & 0xFFFFu;
+            if (4 * q + h < VPL) {
+                if (k == ks - 1) sm = sv;
+                if (k == ks + 1) sp = sv;
+            }
+        }
+    }
+    sm = row_max16(sm);
+    sp = row_max16(sp);
+    if (lane == 0) {
+        dint[pix] = (uint16_t)(lo + ks);
+        if (dsub) {
+            float delta = 0.0f;
+            if (ks > 0 && ks < w - 1) {
+                const int num = (int)sm - (int)sp;
+                const int den = 2 * ((int)sm - 2 * s0 + (int)sp);
+                delta = __fdiv_rn((float)num, (float)den);
+            }
+            dsub[pix] = __fadd_rn((float)(lo + ks), delta);
+        }
+    }
+}
+
 template <int VPL, bool ALIGNED, bool L8>
 __global__ __launch_bounds__(256) void k_wta_paths(const void *__restrict__ vols, long long vstride, int np,
                                                    const int32_t *__restrict__ d_lo, int W, int H, int w,
@@ -725,28 +939,59 @@ __global__ __launch_bounds__(256) void k_wta_paths(const void *__restrict__ vols
     if (pix >= (long long)W * H) return;
     const int kbase = lane * VPL;
     const int nvalid = min(max(w - kbase, 0), VPL);
-    uint32_t S[NP];
+    const int v = (int)(pix / W);
+    if constexpr (L8 && VPL % 4 == 0) {
+        constexpr int NW = Raw<VPL>::NW;
+        uint32_t ev[NW], od[NW];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) S[j] = 0;
-    if (nvalid > 0) {
-        for (int r = 0; r < np; ++r) {
-            if (L8) {
-                Raw<VPL> raw;
-                load_u8<VPL, ALIGNED>(raw, static_cast<const uint8_t *>(vols) + r * vstride + pix * w + kbase,
-                                      nvalid);
+        for (int q = 0; q < NW; ++q) ev[q] = od[q] = 0;
+        if (nvalid > 0) {
+            const uint8_t *base = static_cast<const uint8_t *>(vols) + pix * w + kbase;
+            int r = 0;
+            for (; r + 1 < np; r += 2) {
+                Raw<VPL> x, y;
+                load_u8<VPL, ALIGNED>(x, base + r * vstride, nvalid);
+                load_u8<VPL, ALIGNED>(y, base + (r + 1) * vstride, nvalid);
 #pragma unroll
-                for (int j = 0; j < NP; ++j) S[j] = pk_add(S[j], unpack_pair(raw, j));
-            } else {
-                uint32_t t[NP];
-                load_u16_pairs<VPL, ALIGNED>(t, static_cast<const uint16_t *>(vols) + r * vstride + pix * w + kbase,
-                                             nvalid);
+                for (int q = 0; q < NW; ++q) {
+                    ev[q] += (x.d[q] & 0x00FF00FFu) + (y.d[q] & 0x00FF00FFu);
+                    od[q] += ((x.d[q] >> 8) & 0x00FF00FFu) + ((y.d[q] >> 8) & 0x00FF00FFu);
+                }
+            }
+            if (r < np) {
+                Raw<VPL> x;
+                load_u8<VPL, ALIGNED>(x, base + r * vstride, nvalid);
 #pragma unroll
-                for (int j = 0; j < NP; ++j) S[j] = pk_add(S[j], t[j]);
+                for (int q = 0; q < NW; ++q) {
+                    ev[q] += x.d[q] & 0x00FF00FFu;
+                    od[q] += (x.d[q] >> 8) & 0x00FF00FFu;
+                }
             }
         }
+        select_swar<VPL>(ev, od, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
+    } else {
+        uint32_t S[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) S[j] = 0;
+        if (nvalid > 0) {
+            for (int r = 0; r < np; ++r) {
+                if (L8) {
+                    Raw<VPL> raw;
+                    load_u8<VPL, ALIGNED>(raw, static_cast<const uint8_t *>(vols) + r * vstride + pix * w + kbase,
+                                          nvalid);
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) S[j] = pk_add(S[j], unpack_pair(raw, j));
+                } else {
+                    uint32_t t[NP];
+                    load_u16_pairs<VPL, ALIGNED>(
+                        t, static_cast<const uint16_t *>(vols) + r * vstride + pix * w + kbase, nvalid);
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) S[j] = pk_add(S[j], t[j]);
+                }
+            }
+        }
+        select_and_write<VPL>(S, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
     }
-    const int v = (int)(pix / W);
-    select_and_write<VPL>(S, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
 }
 
 // ---------------------------------------------------------------------------
@@ -782,21 +1027,6 @@ struct AggLaunch {
             if (l8) hipLaunchKernelGGL((k_aggregate<VPL, true, false, true, kPrefetch>), grid, block, 0, s, p);
             else hipLaunchKernelGGL((k_aggregate<VPL, true, false, false, kPrefetch>), grid, block, 0, s, p);
         }
-        return hipGetLastError();
-    }
-};
-
-template <int VPL>
-struct CostLaunch {
-    static hipError_t run(const KernelConfig &kc, const Problem &pb, const uint64_t *cl, const uint64_t *cr,
-                          const int32_t *d_lo, uint8_t *cost, hipStream_t s)
-    {
-        dim3 grid((pb.W + 15) / 16, pb.H), block(256);
-        if (kc.aligned)
-            hipLaunchKernelGGL((k_cost<VPL, true>), grid, block, 0, s, cl, cr, d_lo, pb.W, pb.H, pb.w, pb.cmax, cost);
-        else
-            hipLaunchKernelGGL((k_cost<VPL, false>), grid, block, 0, s, cl, cr, d_lo, pb.W, pb.H, pb.w, pb.cmax,
-                               cost);
         return hipGetLastError();
     }
 };
@@ -867,7 +1097,14 @@ hipError_t launch_census(const Problem &pb, const uint8_t *img, int pitch, uint6
 hipError_t launch_cost(const Problem &pb, const KernelConfig &kc, const uint64_t *cl, const uint64_t *cr,
                        const int32_t *d_lo, uint8_t *cost, hipStream_t s)
 {
-    return by_vpl<CostLaunch>(kc.vpl, kc, pb, cl, cr, d_lo, cost, s);
+    (void)kc;
+    dim3 grid((pb.W + kCostTile - 1) / kCostTile, pb.H), block(256);
+    // 16-byte stores need w % 16 == 0 and a 16-byte aligned volume
+    if ((pb.w % 16) == 0 && (reinterpret_cast<uintptr_t>(cost) % 16) == 0)
+        hipLaunchKernelGGL(k_cost<16>, grid, block, 0, s, cl, cr, d_lo, pb.W, pb.H, pb.w, pb.cmax, cost);
+    else
+        hipLaunchKernelGGL(k_cost<4>, grid, block, 0, s, cl, cr, d_lo, pb.W, pb.H, pb.w, pb.cmax, cost);
+    return hipGetLastError();
 }
 
 hipError_t launch_aggregate(const Problem &pb, const KernelConfig &kc, const uint8_t *cost, const int *paths, int np,

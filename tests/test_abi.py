@@ -58,9 +58,13 @@ def _plan_status(sgm, **kw):
     ({"p1": 11, "p2": 10}, -1),
     ({"p1": -1}, -1),
     ({"p2": 8200}, -1),
+    ({"p2": 5430}, -1),
+    ({"p1": 5, "p2": 5397}, 0),
     ({"flags": 1}, -1),
     ({"width": 40000, "height": 40000, "ndisp": 8}, -2),
     ({"census": 3, "ndisp": 256, "npaths": 4, "p2": 4000}, 0),
+    ({"census": 7, "npaths": 8, "p2": 5429}, -1),
+    ({"census": 7, "npaths": 8, "p2": 5428}, 0),
 ])
 def test_plan_validation(sgm, kw, want):
     assert _plan_status(sgm, **kw) == want
