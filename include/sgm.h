@@ -151,6 +151,75 @@ sgm_status sgm_match(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
                      float *disp_sub, void *workspace, size_t workspace_bytes,
                      void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many pairs, of several sizes, matched together.
+ *
+ * A batch fixes the pairs (sizes and device buffers) at plan time.  A run
+ * enqueues five launches for the whole batch: a queue reset, census and
+ * cost of every pair, ONE persistent aggregation launch in which waves pull
+ * scanline groups of every pair and direction from a shared queue (in the
+ * order the tuning selects), and the selection of every pair.  Results are
+ * identical to sgm_match on each pair.  Scratch (census codes, cost
+ * volumes, per-direction volumes, descriptor tables, the queue counter)
+ * lives in the caller's workspace.  One run at a time per workspace.
+ */
+typedef struct {
+    int32_t width, height; /* W, H of this pair                               */
+    int32_t ndisp;         /* window width w; must be a multiple of the lane
+                              width (2, 4, 8, 12, 16 values for w up to 32,
+                              64, 128, 192, 256)                           */
+    int32_t pitch;         /* bytes between image rows, >= width             */
+    const uint8_t *left, *right; /* device images [H][pitch]                 */
+    const int32_t *d_lo;   /* device [H] window starts, or NULL for all 0    */
+    uint16_t *disp_int;    /* device [H][W] output                           */
+    float *disp_sub;       /* device [H][W] output, or NULL                  */
+} sgm_pair;
+
+typedef struct {
+    int32_t census, npaths, p1, p2; /* shared by every pair, as in sgm_params */
+    uint32_t flags;                 /* reserved, must be 0                    */
+} sgm_batch_params;
+
+/* Launch choices of the persistent aggregation (picked by sgm_batch_autotune
+ * or set by hand; neither changes results). */
+typedef struct {
+    int32_t waves_per_cu; /* resident aggregation waves per compute unit, 1..32 */
+    int32_t order;        /* queue order of scanline groups: 0 longest first,
+                             1 pair by pair, 2 direction by direction       */
+} sgm_tuning;
+
+typedef struct sgm_batch_s *sgm_batch_t;
+
+/* Validate and lay out a batch (host; allocates pinned host memory for the
+ * descriptor tables).  The pairs' buffers must stay valid while the batch
+ * is used. */
+sgm_status sgm_batch_plan(const sgm_batch_params *params, const sgm_pair *pairs,
+                          int32_t npairs, sgm_batch_t *out);
+void sgm_batch_free(sgm_batch_t batch);
+sgm_status sgm_batch_workspace_size(sgm_batch_t batch, size_t *bytes);
+sgm_status sgm_batch_set_tuning(sgm_batch_t batch, const sgm_tuning *tuning);
+sgm_status sgm_batch_get_tuning(sgm_batch_t batch, sgm_tuning *tuning);
+
+/* Enqueue one run of the whole batch on `stream`. */
+sgm_status sgm_batch_run(sgm_batch_t batch, void *workspace, size_t workspace_bytes,
+                         void *stream);
+
+/* Record one run into a HIP graph owned by the batch (stream capture on
+ * `stream`, which must not be the null stream), and replay it.  Changing
+ * the tuning drops the graph. */
+sgm_status sgm_batch_capture(sgm_batch_t batch, void *workspace, size_t workspace_bytes,
+                             void *stream);
+sgm_status sgm_batch_launch(sgm_batch_t batch, void *stream);
+
+/* Pick the tuning: reuse the entry for this batch shape from the text file
+ * `cache_path` (may be NULL) if it holds one, else time every candidate on
+ * the device (synchronising `stream`), keep the fastest and append it to
+ * the file.  A missing or unreadable cache falls back to timing; if timing
+ * fails the default tuning stays.  *chosen (may be NULL) receives the
+ * result. */
+sgm_status sgm_batch_autotune(sgm_batch_t batch, void *workspace, size_t workspace_bytes,
+                              void *stream, const char *cache_path, sgm_tuning *chosen);
+
 /* Per-row window starts from the road model of eq. (3),
  *   f(u,v) = a0 + a1 (cos(phi) (v - cy) - sin(phi) (u - cx)),
  * with (cx, cy) = ((W-1)/2, (H-1)/2) the centre of the roll rotation.

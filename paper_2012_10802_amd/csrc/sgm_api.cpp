@@ -24,13 +24,11 @@ struct sgm_plan_s {
 
 namespace {
 
-thread_local char g_err[512] = "";
-
 sgm_status fail(sgm_status st, const char *fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    vsnprintf(sgm::error_buffer(), sgm::kErrorBufferSize, fmt, ap);
     va_end(ap);
     return st;
 }
@@ -84,6 +82,14 @@ sgm::KernelConfig config_for(const sgm_plan_s *p, const void *a, const void *b)
 
 }  // namespace
 
+namespace sgm {
+char *error_buffer()
+{
+    static thread_local char buf[kErrorBufferSize] = "";
+    return buf;
+}
+}  // namespace sgm
+
 extern "C" {
 
 const char *sgm_status_str(sgm_status s)
@@ -98,7 +104,7 @@ const char *sgm_status_str(sgm_status s)
     return "unknown sgm_status";
 }
 
-const char *sgm_last_error(void) { return g_err; }
+const char *sgm_last_error(void) { return sgm::error_buffer(); }
 
 sgm_status sgm_plan(const sgm_params *pr, sgm_plan_t *out)
 {

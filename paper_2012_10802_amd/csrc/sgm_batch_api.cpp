@@ -1,0 +1,485 @@
+// C-ABI layer of batches: validation, workspace layout, the per-pair
+// descriptor table and the aggregation queue, runs, graph capture and the
+// autotuner.  Kernels live in sgm_batch.hip.
+
+#include "../../include/sgm.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sgm_internal.h"
+
+namespace {
+
+sgm_status bfail(sgm_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(sgm::error_buffer(), sgm::kErrorBufferSize, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int lane_width(int w)
+{
+    if (w <= 32) return 2;
+    if (w <= 64) return 4;
+    if (w <= 128) return 8;
+    if (w <= 192) return 12;
+    return 16;
+}
+
+// Step range of scanline group g (4 lines) of direction r; same geometry as
+// the kernels (horizontal: rows, vertical: columns, diagonal: sheared index).
+int group_length(int r, int g, int W, int H)
+{
+    static const int DU[8] = {1, -1, 0, 0, 1, -1, 1, -1};
+    static const int DV[8] = {0, 0, 1, -1, 1, 1, -1, -1};
+    const int du = DU[r], dv = DV[r];
+    if (dv == 0) return W;
+    if (du == 0) return H;
+    int i0 = 1 << 30, i1 = 0;
+    for (int l = 0; l < 4; ++l) {
+        const int idx = 4 * g + l;
+        if (idx >= W + H - 1) break;
+        const int ell = du > 0 ? idx - (H - 1) : idx;
+        int a, b;
+        if (du > 0) {
+            a = std::max(0, -ell);
+            b = std::min(H, W - ell);
+        } else {
+            a = std::max(0, ell - (W - 1));
+            b = std::min(H, ell + 1);
+        }
+        if (b > a) {
+            i0 = std::min(i0, a);
+            i1 = std::max(i1, b);
+        }
+    }
+    return i1 > i0 ? i1 - i0 : 0;
+}
+
+int groups_of(int r, int W, int H)
+{
+    if (r <= 1) return (H + 3) / 4;
+    if (r <= 3) return (W + 3) / 4;
+    return (W + H - 1 + 3) / 4;
+}
+
+struct Item {
+    uint32_t w0, g;
+    int len, pair, kind;
+};
+
+}  // namespace
+
+struct sgm_batch_s {
+    sgm_batch_params prm;
+    std::vector<sgm_pair> pairs;
+    int cmax = 0;
+    bool l8 = true;
+    sgm_tuning tuning{8, 0};
+    size_t off_pairs = 0, off_items = 0, off_counter = 0, ws_bytes = 0;
+    std::vector<sgm::PairDev> dev;  // offsets, host copy
+    sgm::BatchGrids grids{0, 0, 0};
+    std::vector<Item> items;
+    sgm::PairDev *pin_pairs = nullptr;  // pinned host copies uploaded by every run
+    uint32_t *pin_items = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int num_cu = 0;
+    ~sgm_batch_s()
+    {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        if (pin_pairs) hipHostFree(pin_pairs);
+        if (pin_items) hipHostFree(pin_items);
+    }
+};
+
+namespace {
+
+void drop_graph(sgm_batch_s *b)
+{
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Queue order of the aggregation items for the current tuning.
+void order_items(sgm_batch_s *b)
+{
+    std::vector<Item> &it = b->items;
+    switch (b->tuning.order) {
+    case 1:  // pair by pair, horizontal then diagonal then vertical inside a pair
+        std::stable_sort(it.begin(), it.end(), [](const Item &x, const Item &y) {
+            return x.pair != y.pair ? x.pair < y.pair : x.kind < y.kind;
+        });
+        break;
+    case 2:  // direction kind by kind over all pairs
+        std::stable_sort(it.begin(), it.end(), [](const Item &x, const Item &y) {
+            return x.kind != y.kind ? x.kind < y.kind : x.pair < y.pair;
+        });
+        break;
+    default:  // longest scanline group first
+        std::stable_sort(it.begin(), it.end(), [](const Item &x, const Item &y) { return x.len > y.len; });
+        break;
+    }
+    for (size_t i = 0; i < it.size(); ++i) {
+        b->pin_items[2 * i] = it[i].w0;
+        b->pin_items[2 * i + 1] = it[i].g;
+    }
+}
+
+sgm_status check_batch_ws(const sgm_batch_s *b, void *ws, size_t bytes)
+{
+    if (!ws) return bfail(SGM_ERR_INVALID, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return bfail(SGM_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (bytes < b->ws_bytes)
+        return bfail(SGM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", bytes,
+                     b->ws_bytes);
+    return SGM_OK;
+}
+
+int agg_waves(sgm_batch_s *b)
+{
+    if (b->num_cu <= 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        b->num_cu = n;
+    }
+    const long long want = (long long)b->num_cu * b->tuning.waves_per_cu;
+    return (int)std::max(1ll, std::min(want, (long long)b->items.size()));
+}
+
+sgm_status enqueue_run(sgm_batch_s *b, void *ws, hipStream_t st)
+{
+    uint8_t *base = static_cast<uint8_t *>(ws);
+    const size_t np = b->pairs.size();
+    hipError_t e = hipMemcpyAsync(base + b->off_pairs, b->pin_pairs, np * sizeof(sgm::PairDev),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + b->off_items, b->pin_items, b->items.size() * 2 * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return bfail(SGM_ERR_HIP, "descriptor upload: %s", hipGetErrorString(e));
+    sgm::BatchDev d;
+    d.ws = base;
+    d.pairs = reinterpret_cast<const sgm::PairDev *>(base + b->off_pairs);
+    d.items = reinterpret_cast<const uint32_t *>(base + b->off_items);
+    d.counter = reinterpret_cast<uint32_t *>(base + b->off_counter);
+    d.npairs = (int)np;
+    d.nitems = (int)b->items.size();
+    d.p1x2 = (uint32_t)b->prm.p1 * 0x10001u;
+    d.p2x2 = (uint32_t)b->prm.p2 * 0x10001u;
+    d.cmax = b->cmax;
+    d.npaths = b->prm.npaths;
+    e = sgm::launch_batch(d, b->grids, b->prm.census, b->l8, agg_waves(b), st);
+    return e == hipSuccess ? SGM_OK : bfail(SGM_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
+}
+
+std::string tuning_key(const sgm_batch_s *b)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    for (char &c : arch)
+        if (c == ' ' || c == ':') c = '_';
+    std::vector<std::string> shapes;
+    for (const sgm_pair &p : b->pairs)
+        shapes.push_back(std::to_string(p.width) + "x" + std::to_string(p.height) + "x" + std::to_string(p.ndisp));
+    std::sort(shapes.begin(), shapes.end());
+    std::string key = arch + "|n" + std::to_string(b->prm.census) + "|R" + std::to_string(b->prm.npaths) + "|P" +
+                      std::to_string(b->prm.p1) + "," + std::to_string(b->prm.p2) + "|";
+    for (size_t i = 0; i < shapes.size();) {
+        size_t j = i;
+        while (j < shapes.size() && shapes[j] == shapes[i]) ++j;
+        key += shapes[i] + "*" + std::to_string(j - i) + ";";
+        i = j;
+    }
+    return key;
+}
+
+bool valid_tuning(const sgm_tuning &t) { return t.waves_per_cu >= 1 && t.waves_per_cu <= 32 && t.order >= 0 && t.order <= 2; }
+
+bool read_cache(const char *path, const std::string &key, sgm_tuning *out)
+{
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[4096];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        char k[3500];
+        int wv = 0, ord = 0;
+        double ms = 0;
+        if (sscanf(line, "%3499s %d %d %lf", k, &wv, &ord, &ms) == 4 && key == k) {
+            sgm_tuning t{wv, ord};
+            if (valid_tuning(t)) {
+                *out = t;
+                found = true;
+            }
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+}  // namespace
+
+extern "C" {
+
+sgm_status sgm_batch_plan(const sgm_batch_params *prm, const sgm_pair *pairs, int32_t npairs, sgm_batch_t *out)
+{
+    if (!prm || !pairs || !out) return bfail(SGM_ERR_INVALID, "params, pairs and out must not be NULL");
+    *out = nullptr;
+    if (npairs < 1 || npairs > (1 << 23)) return bfail(SGM_ERR_INVALID, "npairs %d out of range", npairs);
+    const sgm_batch_params &q = *prm;
+    if (q.census != 3 && q.census != 5 && q.census != 7)
+        return bfail(SGM_ERR_UNSUPPORTED, "census window %d not in {3, 5, 7}", q.census);
+    if (q.npaths != 4 && q.npaths != 8) return bfail(SGM_ERR_UNSUPPORTED, "npaths %d not in {4, 8}", q.npaths);
+    if (q.p1 < 0 || q.p2 < q.p1) return bfail(SGM_ERR_INVALID, "need 0 <= P1 <= P2");
+    const int cmax = q.census * q.census - 1;
+    if (2 * cmax + 3 * q.p2 >= 0x3FFF) return bfail(SGM_ERR_INVALID, "need 2*Cmax + 3*P2 < 16383");
+    if ((long long)q.npaths * (cmax + q.p2) > 0xFFFF) return bfail(SGM_ERR_INVALID, "summed cost exceeds 16 bits");
+    if (q.flags != 0) return bfail(SGM_ERR_INVALID, "flags must be 0");
+    for (int i = 0; i < npairs; ++i) {
+        const sgm_pair &p = pairs[i];
+        if (p.width < 1 || p.height < 1 || p.pitch < p.width)
+            return bfail(SGM_ERR_INVALID, "pair %d: bad size or pitch", i);
+        if (p.ndisp < 1 || p.ndisp > 256) return bfail(SGM_ERR_INVALID, "pair %d: ndisp not in [1, 256]", i);
+        if (p.ndisp % lane_width(p.ndisp))
+            return bfail(SGM_ERR_UNSUPPORTED, "pair %d: ndisp %d is not a multiple of its lane width %d", i,
+                         p.ndisp, lane_width(p.ndisp));
+        if ((long long)p.width * p.height * p.ndisp >= (1ll << 31))
+            return bfail(SGM_ERR_UNSUPPORTED, "pair %d: W*H*ndisp must be < 2^31", i);
+        if (!p.left || !p.right || !p.disp_int) return bfail(SGM_ERR_INVALID, "pair %d: NULL buffer", i);
+    }
+    sgm_batch_s *b = new (std::nothrow) sgm_batch_s();
+    if (!b) return bfail(SGM_ERR_INVALID, "out of host memory");
+    b->prm = q;
+    b->pairs.assign(pairs, pairs + npairs);
+    b->cmax = cmax;
+    b->l8 = cmax + q.p2 <= 255;
+    const size_t esz = b->l8 ? 1 : 2;
+
+    // workspace: descriptor table, queue, counter, then each pair's scratch
+    size_t off = 0;
+    b->off_pairs = off;
+    off += align256((size_t)npairs * sizeof(sgm::PairDev));
+    size_t nitems = 0;
+    for (int i = 0; i < npairs; ++i)
+        for (int r = 0; r < q.npaths; ++r) nitems += groups_of(r, pairs[i].width, pairs[i].height);
+    if (nitems >= (1u << 31)) {
+        delete b;
+        return bfail(SGM_ERR_UNSUPPORTED, "too many scanline groups");
+    }
+    b->off_items = off;
+    off += align256(nitems * 2 * sizeof(uint32_t));
+    b->off_counter = off;
+    off += 256;
+    b->dev.resize(npairs);
+    int census_blk = 0, cost_blk = 0, wta_blk = 0;
+    for (int i = 0; i < npairs; ++i) {
+        const sgm_pair &p = pairs[i];
+        sgm::PairDev &d = b->dev[i];
+        memset(&d, 0, sizeof d);
+        const size_t npix = (size_t)p.width * p.height, nvol = npix * (size_t)p.ndisp;
+        d.left = p.left;
+        d.right = p.right;
+        d.d_lo = p.d_lo;
+        d.dint = p.disp_int;
+        d.dsub = p.disp_sub;
+        d.off_codes_l = (long long)off;
+        off += align256(npix * 8);
+        d.off_codes_r = (long long)off;
+        off += align256(npix * 8);
+        d.off_cost = (long long)off;
+        off += align256(nvol);
+        d.off_vols = (long long)off;
+        const size_t vs = align256(nvol * esz);
+        off += vs * (size_t)q.npaths;
+        d.vstride = (long long)(vs / esz);
+        d.W = p.width;
+        d.H = p.height;
+        d.w = p.ndisp;
+        d.pitch = p.pitch;
+        d.vpl = lane_width(p.ndisp);
+        d.pad = p.ndisp < 16 * d.vpl ? 1 : 0;
+        d.census_tx = (p.width + 63) / 64;
+        d.census_ty = (p.height + 3) / 4;
+        d.cost_tx = (p.width + 63) / 64;
+        d.census_start = census_blk;
+        census_blk += 2 * d.census_tx * d.census_ty;
+        d.cost_start = cost_blk;
+        cost_blk += d.cost_tx * p.height;
+        d.wta_start = wta_blk;
+        wta_blk += (int)((npix + 15) / 16);
+    }
+    b->ws_bytes = off;
+    b->grids = {census_blk, cost_blk, wta_blk};
+    b->items.reserve(nitems);
+    for (int i = 0; i < npairs; ++i)
+        for (int r = 0; r < q.npaths; ++r) {
+            const int kind = r <= 1 ? 0 : (r >= 4 ? 1 : 2);  // horizontal, diagonal, vertical
+            for (int g = 0, n = groups_of(r, pairs[i].width, pairs[i].height); g < n; ++g)
+                b->items.push_back(Item{(uint32_t)(i << 8 | r), (uint32_t)g,
+                                        group_length(r, g, pairs[i].width, pairs[i].height), i, kind});
+        }
+    if (hipHostMalloc(reinterpret_cast<void **>(&b->pin_pairs), npairs * sizeof(sgm::PairDev)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&b->pin_items), std::max<size_t>(1, nitems) * 2 * sizeof(uint32_t)) !=
+            hipSuccess) {
+        delete b;
+        return bfail(SGM_ERR_HIP, "pinned host allocation failed");
+    }
+    memcpy(b->pin_pairs, b->dev.data(), npairs * sizeof(sgm::PairDev));
+    order_items(b);
+    *out = b;
+    return SGM_OK;
+}
+
+void sgm_batch_free(sgm_batch_t b) { delete b; }
+
+sgm_status sgm_batch_workspace_size(sgm_batch_t b, size_t *bytes)
+{
+    if (!b || !bytes) return bfail(SGM_ERR_INVALID, "batch and bytes must not be NULL");
+    *bytes = b->ws_bytes;
+    return SGM_OK;
+}
+
+sgm_status sgm_batch_set_tuning(sgm_batch_t b, const sgm_tuning *t)
+{
+    if (!b || !t) return bfail(SGM_ERR_INVALID, "batch and tuning must not be NULL");
+    if (!valid_tuning(*t)) return bfail(SGM_ERR_INVALID, "tuning out of range");
+    if (t->order != b->tuning.order || t->waves_per_cu != b->tuning.waves_per_cu) {
+        drop_graph(b);
+        const bool reorder = t->order != b->tuning.order;
+        b->tuning = *t;
+        if (reorder) order_items(b);
+    }
+    return SGM_OK;
+}
+
+sgm_status sgm_batch_get_tuning(sgm_batch_t b, sgm_tuning *t)
+{
+    if (!b || !t) return bfail(SGM_ERR_INVALID, "batch and tuning must not be NULL");
+    *t = b->tuning;
+    return SGM_OK;
+}
+
+sgm_status sgm_batch_run(sgm_batch_t b, void *ws, size_t bytes, void *stream)
+{
+    if (!b) return bfail(SGM_ERR_INVALID, "batch is NULL");
+    if (sgm_status s = check_batch_ws(b, ws, bytes)) return s;
+    return enqueue_run(b, ws, (hipStream_t)stream);
+}
+
+sgm_status sgm_batch_capture(sgm_batch_t b, void *ws, size_t bytes, void *stream)
+{
+    if (!b) return bfail(SGM_ERR_INVALID, "batch is NULL");
+    if (!stream) return bfail(SGM_ERR_INVALID, "capture needs a stream other than the null stream");
+    if (sgm_status s = check_batch_ws(b, ws, bytes)) return s;
+    drop_graph(b);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(SGM_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
+    sgm_status rs = enqueue_run(b, ws, st);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (rs != SGM_OK) {
+        if (g) hipGraphDestroy(g);
+        return rs;
+    }
+    if (e != hipSuccess) return bfail(SGM_ERR_HIP, "end capture: %s", hipGetErrorString(e));
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return bfail(SGM_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    b->graph = g;
+    b->exec = x;
+    return SGM_OK;
+}
+
+sgm_status sgm_batch_launch(sgm_batch_t b, void *stream)
+{
+    if (!b) return bfail(SGM_ERR_INVALID, "batch is NULL");
+    if (!b->exec) return bfail(SGM_ERR_INVALID, "no captured graph (call sgm_batch_capture first)");
+    hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : bfail(SGM_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+}
+
+sgm_status sgm_batch_autotune(sgm_batch_t b, void *ws, size_t bytes, void *stream, const char *cache_path,
+                              sgm_tuning *chosen)
+{
+    if (!b) return bfail(SGM_ERR_INVALID, "batch is NULL");
+    if (sgm_status s = check_batch_ws(b, ws, bytes)) return s;
+    const std::string key = tuning_key(b);
+    sgm_tuning t;
+    if (read_cache(cache_path, key, &t)) {
+        sgm_status s = sgm_batch_set_tuning(b, &t);
+        if (chosen) *chosen = b->tuning;
+        return s;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        if (chosen) *chosen = b->tuning;
+        return bfail(SGM_ERR_HIP, "event creation failed; default tuning kept");
+    }
+    const sgm_tuning start = b->tuning;
+    sgm_tuning best = start;
+    float best_ms = 1e30f;
+    const int waves[] = {4, 8, 12, 16, 24};
+    bool ok = true;
+    for (int order = 0; order <= 2 && ok; ++order)
+        for (int wv : waves) {
+            sgm_tuning c{wv, order};
+            sgm_batch_set_tuning(b, &c);
+            float ms = 1e30f;
+            for (int rep = 0; rep < 3 && ok; ++rep) {
+                ok = hipEventRecord(e0, st) == hipSuccess && enqueue_run(b, ws, st) == SGM_OK &&
+                     hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+                float t_ms = 0;
+                if (ok && rep > 0 && hipEventElapsedTime(&t_ms, e0, e1) == hipSuccess) ms = std::min(ms, t_ms);
+            }
+            if (!ok) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (!ok) {
+        sgm_batch_set_tuning(b, &start);
+        if (chosen) *chosen = b->tuning;
+        return bfail(SGM_ERR_HIP, "autotune run failed; previous tuning kept");
+    }
+    sgm_batch_set_tuning(b, &best);
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s %d %d %.4f\n", key.c_str(), best.waves_per_cu, best.order, best_ms);
+            fclose(f);
+        }
+    }
+    if (chosen) *chosen = b->tuning;
+    return SGM_OK;
+}
+
+}  // extern "C"

@@ -8,6 +8,10 @@
 
 namespace sgm {
 
+// thread-local text of the last failure (sgm_last_error)
+constexpr int kErrorBufferSize = 512;
+char *error_buffer();
+
 // Launch configuration chosen at plan time.
 struct KernelConfig {
     int vpl;        // disparities per lane; 16 lanes carry one scanline
@@ -39,5 +43,41 @@ hipError_t launch_wta_sum(const Problem &pb, const KernelConfig &kc, const uint1
 hipError_t launch_wta_paths(const Problem &pb, const KernelConfig &kc, const void *vols, int np,
                             bool l8, const int32_t *d_lo, uint16_t *dint, float *dsub,
                             hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// batches
+
+// Device descriptor of one pair.  Caller buffers are absolute pointers;
+// scratch buffers are byte offsets into the run's workspace, so one table
+// serves every workspace (and a captured graph keeps working).
+struct PairDev {
+    const uint8_t *left, *right;
+    const int32_t *d_lo;
+    uint16_t *dint;
+    float *dsub;
+    long long off_codes_l, off_codes_r, off_cost, off_vols;
+    long long vstride;  // elements between per-direction volumes
+    int32_t W, H, w, pitch, vpl, pad;
+    int32_t census_start, cost_start, wta_start;  // first block of the pair in each batched grid
+    int32_t census_tx, census_ty, cost_tx;
+};
+
+struct BatchDev {
+    uint8_t *ws;             // workspace base
+    const PairDev *pairs;    // in the workspace
+    const uint32_t *items;   // in the workspace: (pair << 8 | direction, group) per item
+    uint32_t *counter;       // in the workspace
+    int npairs, nitems;
+    uint32_t p1x2, p2x2;
+    int cmax, npaths;
+};
+
+// Workgroups of each batched grid (the last pair's start + its count).
+struct BatchGrids {
+    int census, cost, wta;
+};
+
+hipError_t launch_batch(const BatchDev &b, const BatchGrids &g, int census_n, bool l8, int agg_waves,
+                        hipStream_t s);
 
 }  // namespace sgm

@@ -31,712 +31,27 @@
 
 #include "sgm_internal.h"
 
+#include "sgm_device.h"
+#include "sgm_internal.h"
+
 namespace sgm {
 namespace {
 
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-constexpr uint32_t kInf2 = 0x3FFF3FFFu;  // pair of "outside the window" values
-constexpr uint32_t kPad = 0x3FFFu;
-
-__device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b)
-{
-    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
-                                                                  __builtin_bit_cast(u16x2, b)));
-}
-__device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b)
-{
-    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + __builtin_bit_cast(u16x2, b));
-}
-__device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b)
-{
-    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
-}
-
-// DPP move: lanes whose source lies outside their 16-lane row keep `old`.
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t src)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, 0xF, 0xF, false);
-}
-constexpr int kQuadSwap1 = 0xB1;  // quad_perm [1,0,3,2]
-constexpr int kQuadSwap2 = 0x4E;  // quad_perm [2,3,0,1]
-constexpr int kRowShl1 = 0x101;   // lane i reads lane i+1
-constexpr int kRowShr1 = 0x111;   // lane i reads lane i-1
-constexpr int kRowRor4 = 0x124;
-constexpr int kRowRor8 = 0x128;
-
-// minimum / maximum over the 16 lanes of a DPP row, broadcast to all of them
-// (quad permutations and row rotations never leave the row)
-template <int CTRL>
-__device__ __forceinline__ uint32_t rot(uint32_t src)
-{
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)src, CTRL, 0xF, 0xF, true);
-}
-__device__ __forceinline__ uint32_t row_min16(uint32_t x)
-{
-    x = min(x, rot<kQuadSwap1>(x));
-    x = min(x, rot<kQuadSwap2>(x));
-    x = min(x, rot<kRowRor4>(x));
-    x = min(x, rot<kRowRor8>(x));
-    return x;
-}
-__device__ __forceinline__ uint32_t row_max16(uint32_t x)
-{
-    x = max(x, rot<kQuadSwap1>(x));
-    x = max(x, rot<kQuadSwap2>(x));
-    x = max(x, rot<kRowRor4>(x));
-    x = max(x, rot<kRowRor8>(x));
-    return x;
-}
-
-// direction table: path r -> r = (du, dv); predecessor of p is p - r
-__device__ __forceinline__ int dir_du(int r)
-{
-    return (r == 0 || r == 4 || r == 6) ? 1 : ((r == 1 || r == 5 || r == 7) ? -1 : 0);
-}
-__device__ __forceinline__ int dir_dv(int r)
-{
-    return (r == 2 || r == 4 || r == 5) ? 1 : ((r == 3 || r == 6 || r == 7) ? -1 : 0);
-}
-
-// ---------------------------------------------------------------------------
-// lane value I/O: VPL bytes (or u16) per lane
-
-template <int VPL>
-struct Raw {
-    static constexpr int NW = (VPL + 3) / 4;
-    uint32_t d[NW];
-};
-
-// (used for the per-direction volumes, which are read once: non-temporal)
-template <int VPL, bool ALIGNED>
-__device__ __forceinline__ void load_u8(Raw<VPL> &r, const uint8_t *p, int nvalid)
-{
-    if constexpr (ALIGNED) {
-        if constexpr (VPL == 2) {
-            r.d[0] = *reinterpret_cast<const uint16_t *>(p);
-        } else if constexpr (VPL == 4) {
-            r.d[0] = *reinterpret_cast<const uint32_t *>(p);
-        } else if constexpr (VPL == 8) {
-            const unsigned long long t = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p));
-            r.d[0] = (uint32_t)t;
-            r.d[1] = (uint32_t)(t >> 32);
-        } else if constexpr (VPL == 12) {
-            const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
-            r.d[0] = __builtin_nontemporal_load(q);
-            r.d[1] = __builtin_nontemporal_load(q + 1);
-            r.d[2] = __builtin_nontemporal_load(q + 2);
-        } else {
-            const unsigned long long *q = reinterpret_cast<const unsigned long long *>(p);
-            const unsigned long long t0 = __builtin_nontemporal_load(q), t1 = __builtin_nontemporal_load(q + 1);
-            r.d[0] = (uint32_t)t0;
-            r.d[1] = (uint32_t)(t0 >> 32);
-            r.d[2] = (uint32_t)t1;
-            r.d[3] = (uint32_t)(t1 >> 32);
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < Raw<VPL>::NW; ++i) r.d[i] = 0;
-#pragma unroll
-        for (int i = 0; i < VPL; ++i)
-            if (i < nvalid) r.d[i / 4] |= (uint32_t)p[i] << (8 * (i % 4));
-    }
-}
-
-template <int VPL>
-__device__ __forceinline__ void zero(Raw<VPL> &r)
-{
-#pragma unroll
-    for (int i = 0; i < Raw<VPL>::NW; ++i) r.d[i] = 0;
-}
-
-// bytes (2j, 2j+1) of the raw lane values -> packed u16 pair j
-template <int VPL>
-__device__ __forceinline__ uint32_t unpack_pair(const Raw<VPL> &r, int j)
-{
-    const uint32_t x = r.d[j / 2];
-    return (j & 1) ? __builtin_amdgcn_perm(x, x, 0x0C030C02u) : __builtin_amdgcn_perm(x, x, 0x0C010C00u);
-}
-
-// low bytes of packed pairs a (values 0,1) and b (values 2,3) -> one dword
-__device__ __forceinline__ uint32_t pack_bytes(uint32_t a, uint32_t b)
-{
-    return __builtin_amdgcn_perm(b, a, 0x06040200u);
-}
-
-template <int VPL, bool ALIGNED>
-__device__ __forceinline__ void store_u8_pairs(uint8_t *p, const uint32_t (&v)[VPL / 2], int nvalid)
-{
-    constexpr int NP = VPL / 2;
-    if constexpr (ALIGNED) {
-        if constexpr (VPL == 2) {
-            *reinterpret_cast<uint16_t *>(p) = (uint16_t)__builtin_amdgcn_perm(v[0], v[0], 0x0C0C0200u);
-        } else if constexpr (VPL == 4) {
-            *reinterpret_cast<uint32_t *>(p) = pack_bytes(v[0], v[1]);
-        } else if constexpr (VPL == 8) {
-            *reinterpret_cast<uint2 *>(p) = make_uint2(pack_bytes(v[0], v[1]), pack_bytes(v[2], v[3]));
-        } else if constexpr (VPL == 12) {
-            uint32_t *q = reinterpret_cast<uint32_t *>(p);
-            q[0] = pack_bytes(v[0], v[1]);
-            q[1] = pack_bytes(v[2], v[3]);
-            q[2] = pack_bytes(v[4], v[5]);
-        } else {
-            *reinterpret_cast<uint4 *>(p) = make_uint4(pack_bytes(v[0], v[1]), pack_bytes(v[2], v[3]),
-                                                       pack_bytes(v[4], v[5]), pack_bytes(v[6], v[7]));
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            if (2 * j < nvalid) p[2 * j] = (uint8_t)(v[j] & 0xFF);
-            if (2 * j + 1 < nvalid) p[2 * j + 1] = (uint8_t)((v[j] >> 16) & 0xFF);
-        }
-    }
-}
-
-template <int VPL, bool ALIGNED>
-__device__ __forceinline__ void store_u16_pairs(uint16_t *p, const uint32_t (&v)[VPL / 2], int nvalid)
-{
-    constexpr int NP = VPL / 2;
-    if constexpr (ALIGNED) {
-        uint32_t *q = reinterpret_cast<uint32_t *>(p);
-#pragma unroll
-        for (int j = 0; j < NP; ++j) q[j] = v[j];
-    } else {
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            if (2 * j < nvalid) p[2 * j] = (uint16_t)(v[j] & 0xFFFF);
-            if (2 * j + 1 < nvalid) p[2 * j + 1] = (uint16_t)(v[j] >> 16);
-        }
-    }
-}
-
-template <int VPL, bool ALIGNED>
-__device__ __forceinline__ void load_u16_pairs(uint32_t (&v)[VPL / 2], const uint16_t *p, int nvalid)
-{
-    constexpr int NP = VPL / 2;
-    if constexpr (ALIGNED) {
-        const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
-        if constexpr (NP % 4 == 0) {
-#pragma unroll
-            for (int j = 0; j < NP; j += 4) {
-                const uint4 t = reinterpret_cast<const uint4 *>(q)[j / 4];
-                v[j] = t.x;
-                v[j + 1] = t.y;
-                v[j + 2] = t.z;
-                v[j + 3] = t.w;
-            }
-        } else if constexpr (NP % 2 == 0) {
-#pragma unroll
-            for (int j = 0; j < NP; j += 2) {
-                const uint2 t = reinterpret_cast<const uint2 *>(q)[j / 2];
-                v[j] = t.x;
-                v[j + 1] = t.y;
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < NP; ++j) v[j] = q[j];
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            const uint32_t lo = (2 * j < nvalid) ? p[2 * j] : 0u;
-            const uint32_t hi = (2 * j + 1 < nvalid) ? p[2 * j + 1] : 0u;
-            v[j] = lo | (hi << 16);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// census transform
+using namespace dev;
 
 template <int N>
 __global__ __launch_bounds__(256) void k_census(const uint8_t *__restrict__ img, int pitch, int W, int H,
                                                 uint64_t *__restrict__ out)
 {
-    constexpr int R = N / 2, TW = 64, TH = 4, LW = TW + 2 * R, LH = TH + 2 * R;
-    __shared__ uint8_t tile[LH][LW];
-    const int u0 = blockIdx.x * TW, v0 = blockIdx.y * TH;
-    for (int t = threadIdx.x; t < LH * LW; t += blockDim.x) {
-        const int ty = t / LW, tx = t % LW;
-        const int v = min(max(v0 + ty - R, 0), H - 1);
-        const int u = min(max(u0 + tx - R, 0), W - 1);
-        tile[ty][tx] = img[(size_t)v * pitch + u];
-    }
-    __syncthreads();
-    const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
-    const int u = u0 + tx, v = v0 + ty;
-    if (u >= W || v >= H) return;
-    const int c = tile[ty + R][tx + R];
-    uint64_t bits = 0;
-    int b = 0;
-#pragma unroll
-    for (int dy = -R; dy <= R; ++dy)
-#pragma unroll
-        for (int dx = -R; dx <= R; ++dx) {
-            if (dx == 0 && dy == 0) continue;
-            bits |= (uint64_t)(tile[ty + R + dy][tx + R + dx] < c) << b;
-            ++b;
-        }
-    out[(size_t)v * W + u] = bits;
+    census_tile<N>(img, pitch, W, H, out, blockIdx.x, blockIdx.y);
 }
-
-// ---------------------------------------------------------------------------
-// matching cost: C(u,v,k) = popcount(cL(u,v) ^ cR(u - d_lo(v) - k, v))
-//
-// A workgroup covers kCostTile pixels of one row.  The left codes of the
-// tile and the right codes of every column the tile's windows reach are
-// staged in LDS.  Each thread then produces CH consecutive window values of
-// one pixel per item; neighbouring lanes take neighbouring pixels, so the
-// LDS reads of a wave are conflict-free (8-byte stride), and a pixel's
-// window is written in CH-byte pieces.
-
-constexpr int kCostTile = 64;
 
 template <int CH>
 __global__ __launch_bounds__(256) void k_cost(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr,
                                               const int32_t *__restrict__ d_lo, int W, int H, int w, int cmax,
                                               uint8_t *__restrict__ cost)
 {
-    __shared__ uint64_t s_cl[kCostTile];
-    __shared__ uint64_t s_cr[kCostTile + 256];
-    const int v = blockIdx.y;
-    const int u0 = blockIdx.x * kCostTile;
-    const int lo = d_lo ? d_lo[v] : 0;
-    const int first = u0 - lo - (w - 1);  // right column held in s_cr[0]
-    const uint64_t *crow = cr + (size_t)v * W;
-    for (int t = threadIdx.x; t < kCostTile - 1 + w; t += blockDim.x) {
-        const int col = first + t;
-        s_cr[t] = (col >= 0 && col < W) ? crow[col] : 0ull;
-    }
-    for (int t = threadIdx.x; t < kCostTile; t += blockDim.x)
-        s_cl[t] = (u0 + t < W) ? cl[(size_t)v * W + u0 + t] : 0ull;
-    __syncthreads();
-    const int npix = min(kCostTile, W - u0);
-    const int nch = (w + CH - 1) / CH;
-    uint8_t *out = cost + ((size_t)v * W + u0) * w;
-    for (int it = threadIdx.x; it < npix * nch; it += blockDim.x) {
-        const int ch = it / npix, px = it - ch * npix;
-        const int k0 = CH * ch;
-        const uint64_t a = s_cl[px];
-        // right column of window index k: u0 + px - lo - k = first + (px + w - 1 - k)
-        const int base = px + w - 1 - k0;
-        const int col0 = u0 + px - lo - k0;
-        uint32_t word[CH / 4];
-#pragma unroll
-        for (int q = 0; q < CH / 4; ++q) {
-            uint32_t wd = 0;
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int kk = 4 * q + h;
-                uint32_t c = (uint32_t)cmax;
-                if (col0 - kk >= 0 && k0 + kk < w) c = (uint32_t)__popcll(a ^ s_cr[base - kk]);
-                wd |= c << (8 * h);
-            }
-            word[q] = wd;
-        }
-        uint8_t *dst = out + (size_t)px * w + k0;
-        if constexpr (CH == 16) {
-            *reinterpret_cast<uint4 *>(dst) = make_uint4(word[0], word[1], word[2], word[3]);
-        } else {
-            for (int h = 0; h < CH && k0 + h < w; ++h) dst[h] = (uint8_t)(word[h / 4] >> (8 * (h % 4)));
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// path aggregation, eq. (8)
-
-struct AggParams {
-    const uint8_t *cost;
-    void *out;
-    long long vstride;  // elements between consecutive output volumes
-    int W, H, w;
-    uint32_t p1x2, p2x2;  // P1, P2 replicated in both u16 halves
-    int np;
-    int lines_per_wg;
-    int paths[8];   // per dispatch slot: direction | output volume << 8
-    int gstart[9];  // first workgroup of each slot, ascending
-};
-
-// Scanline `idx` of direction (du, dv): pixel at step i is
-// (ub + su*i, vb + sv*i) for i in [i0, i1); empty when idx is past the end.
-struct Line {
-    int ub, vb, su, sv, i0, i1;
-};
-
-__device__ __forceinline__ Line line_geom(int idx, int du, int dv, int W, int H)
-{
-    Line L;
-    if (dv == 0) {  // horizontal: one scanline per row
-        L.vb = idx;
-        L.sv = 0;
-        L.su = du;
-        L.ub = du > 0 ? 0 : W - 1;
-        L.i0 = 0;
-        L.i1 = idx < H ? W : 0;
-        return L;
-    }
-    L.vb = dv > 0 ? 0 : H - 1;
-    L.sv = dv;
-    L.su = du;
-    if (du == 0) {  // vertical: one scanline per column
-        L.ub = idx;
-        L.i0 = 0;
-        L.i1 = idx < W ? H : 0;
-        return L;
-    }
-    // diagonal: u = ell + du * i, indexed so that neighbouring idx are
-    // neighbouring pixels of one row at every step
-    const int nl = W + H - 1;
-    const int ell = du > 0 ? idx - (H - 1) : idx;
-    L.ub = ell;
-    if (du > 0) {
-        L.i0 = max(0, -ell);
-        L.i1 = min(H, W - ell);
-    } else {
-        L.i0 = max(0, ell - (W - 1));
-        L.i1 = min(H, ell + 1);
-    }
-    if (idx >= nl || L.i1 < L.i0) L.i1 = L.i0;
-    return L;
-}
-
-// Buffer I/O for the aggregation loop.  Offsets at or beyond the end of a
-// buffer are dropped by the hardware range check (loads return 0, stores
-// are discarded), so scanlines outside the image need no branches.
-constexpr uint32_t kOff = 0x80000000u;  // an offset outside every buffer
-constexpr int kRsrcWord3 = 0x00020000;
-// cache policy of the per-direction volume stores: non-temporal, so the
-// streamed volumes do not evict the cost volume that every direction reads
-constexpr int kStreamPolicy = 2;
-
-typedef unsigned int v2u __attribute__((ext_vector_type(2)));
-typedef unsigned int v3u __attribute__((ext_vector_type(3)));
-typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kRsrcWord3);
-}
-
-// VPL cost bytes of one lane at byte offset `off` (kOff: none)
-template <int VPL, bool ALIGNED>
-__device__ __forceinline__ void buf_load_u8(Raw<VPL> &r, __amdgpu_buffer_rsrc_t rs, uint32_t off, int nvalid)
-{
-    if constexpr (ALIGNED) {
-        if constexpr (VPL == 2) {
-            r.d[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
-        } else if constexpr (VPL == 4) {
-            r.d[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
-        } else if constexpr (VPL == 8) {
-            const v2u t = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
-            r.d[0] = t.x;
-            r.d[1] = t.y;
-        } else if constexpr (VPL == 12) {
-            const v3u t = __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0);
-            r.d[0] = t.x;
-            r.d[1] = t.y;
-            r.d[2] = t.z;
-        } else {
-            const v4u t = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-            r.d[0] = t.x;
-            r.d[1] = t.y;
-            r.d[2] = t.z;
-            r.d[3] = t.w;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < Raw<VPL>::NW; ++i) r.d[i] = 0;
-#pragma unroll
-        for (int i = 0; i < VPL; ++i) {
-            const uint32_t o = (i < nvalid && off != kOff) ? off + i : kOff;
-            r.d[i / 4] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, o, 0, 0) << (8 * (i % 4));
-        }
-    }
-}
-
-// packed u16 pairs of one lane -> uint8 (L8) or uint16 values at element
-// offset `off` of the buffer (kOff: none)
-template <int VPL, bool ALIGNED, bool L8>
-__device__ __forceinline__ void buf_store_pairs(const uint32_t (&v)[VPL / 2], __amdgpu_buffer_rsrc_t rs, uint32_t off,
-                                                int nvalid)
-{
-    constexpr int NP = VPL / 2;
-    if constexpr (ALIGNED && L8) {
-        if constexpr (VPL == 2) {
-            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)__builtin_amdgcn_perm(v[0], v[0], 0x0C0C0200u), rs,
-                                                  off, 0, 0);
-        } else if constexpr (VPL == 4) {
-            __builtin_amdgcn_raw_buffer_store_b32(pack_bytes(v[0], v[1]), rs, off, 0, 0);
-        } else if constexpr (VPL == 8) {
-            const v2u t = {pack_bytes(v[0], v[1]), pack_bytes(v[2], v[3])};
-            __builtin_amdgcn_raw_buffer_store_b64(t, rs, off, 0, 0);
-        } else if constexpr (VPL == 12) {
-            const v3u t = {pack_bytes(v[0], v[1]), pack_bytes(v[2], v[3]), pack_bytes(v[4], v[5])};
-            __builtin_amdgcn_raw_buffer_store_b96(t, rs, off, 0, 0);
-        } else {
-            const v4u t = {pack_bytes(v[0], v[1]), pack_bytes(v[2], v[3]), pack_bytes(v[4], v[5]),
-                           pack_bytes(v[6], v[7])};
-            __builtin_amdgcn_raw_buffer_store_b128(t, rs, off, 0, 0);
-        }
-    } else if constexpr (ALIGNED) {
-        const uint32_t bo = off == kOff ? kOff : off * 2;
-        if constexpr (NP == 1) {
-            __builtin_amdgcn_raw_buffer_store_b32(v[0], rs, bo, 0, 0);
-        } else if constexpr (NP == 2) {
-            const v2u t = {v[0], v[1]};
-            __builtin_amdgcn_raw_buffer_store_b64(t, rs, bo, 0, 0);
-        } else {
-#pragma unroll
-            for (int j = 0; j < NP; j += 2) {
-                const v2u t = {v[j], v[j + 1]};
-                __builtin_amdgcn_raw_buffer_store_b64(t, rs, bo == kOff ? kOff : bo + 4 * j, 0, 0);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int i = 2 * j + h;
-                const uint32_t val = h ? (v[j] >> 16) : (v[j] & 0xFFFFu);
-                const bool ok = i < nvalid && off != kOff;
-                if (L8)
-                    __builtin_amdgcn_raw_buffer_store_b8((unsigned char)val, rs, ok ? off + i : kOff, 0, 0);
-                else
-                    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)val, rs, ok ? 2 * (off + i) : kOff, 0,
-                                                          0);
-            }
-        }
-    }
-}
-
-// Inside the aggregation a lane keeps its VPL window values as NP = VPL/2
-// packed pairs in a strided order: pair j holds (k0 + j, k0 + j + NP).  The
-// k-1 neighbours of pair j are then pair j-1 and the k+1 neighbours pair
-// j+1, so only the two end pairs need a shuffle (one alignbit each, fed by
-// a DPP move from the neighbouring lane).
-template <int VPL>
-__device__ __forceinline__ uint32_t unpack_strided(const Raw<VPL> &r, int j)
-{
-    constexpr int NP = VPL / 2;
-    const int blo = j, bhi = j + NP;
-    const uint32_t sel = (uint32_t)(blo % 4) | (0x0Cu << 8) | ((uint32_t)(4 + bhi % 4) << 16) | (0x0Cu << 24);
-    return __builtin_amdgcn_perm(r.d[bhi / 4], r.d[blo / 4], sel);
-}
-
-// strided pairs -> the lane's VPL bytes in window order, packed in dwords
-template <int VPL>
-__device__ __forceinline__ void pack_strided(const uint32_t (&p)[VPL / 2], uint32_t (&d)[(VPL + 3) / 4])
-{
-    constexpr int NP = VPL / 2;
-    if constexpr (NP == 1) {
-        d[0] = __builtin_amdgcn_perm(p[0], p[0], 0x0C0C0200u);
-    } else if constexpr (NP == 2) {
-        d[0] = __builtin_amdgcn_perm(p[1], p[0], 0x06020400u);
-    } else {
-        // t[q] = (p[2q].lo, p[2q+1].lo, p[2q].hi, p[2q+1].hi)
-        uint32_t t[NP / 2];
-#pragma unroll
-        for (int q = 0; q < NP / 2; ++q) t[q] = __builtin_amdgcn_perm(p[2 * q + 1], p[2 * q], 0x06020400u);
-        // byte b of the lane: b < NP -> low byte of pair b, else high of b-NP
-        // = byte (b%2) + 2*(b >= NP) of t[(b % NP) / 2]
-#pragma unroll
-        for (int q = 0; q < (VPL + 3) / 4; ++q) {
-            const int b0 = 4 * q, b2 = 4 * q + 2;
-            const int ta = (b0 % NP) / 2, tb = (b2 % NP) / 2;
-            const uint32_t sa = (uint32_t)((b0 >= NP) ? 2 : 0), sb = (uint32_t)((b2 >= NP) ? 2 : 0);
-            // bytes b0, b0+1 come from t[ta], bytes b2, b2+1 from t[tb]
-            const uint32_t sel = (sa) | ((sa + 1) << 8) | ((4 + sb) << 16) | ((5 + sb) << 24);
-            d[q] = __builtin_amdgcn_perm(t[tb], t[ta], sel);
-        }
-    }
-}
-
-// stores of one lane's aggregated values (strided pairs) at element offset
-// `off` of the output volume (kOff: dropped by the range check)
-template <int VPL, bool ALIGNED, bool L8>
-__device__ __forceinline__ void store_strided(const uint32_t (&v)[VPL / 2], __amdgpu_buffer_rsrc_t rs, uint32_t off,
-                                              int nvalid)
-{
-    constexpr int NP = VPL / 2;
-    if constexpr (ALIGNED && L8) {
-        uint32_t d[(VPL + 3) / 4];
-        pack_strided<VPL>(v, d);
-        if constexpr (VPL == 2) {
-            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)d[0], rs, off, 0, kStreamPolicy);
-        } else if constexpr (VPL == 4) {
-            __builtin_amdgcn_raw_buffer_store_b32(d[0], rs, off, 0, kStreamPolicy);
-        } else if constexpr (VPL == 8) {
-            const v2u t = {d[0], d[1]};
-            __builtin_amdgcn_raw_buffer_store_b64(t, rs, off, 0, kStreamPolicy);
-        } else if constexpr (VPL == 12) {
-            const v3u t = {d[0], d[1], d[2]};
-            __builtin_amdgcn_raw_buffer_store_b96(t, rs, off, 0, kStreamPolicy);
-        } else {
-            const v4u t = {d[0], d[1], d[2], d[3]};
-            __builtin_amdgcn_raw_buffer_store_b128(t, rs, off, 0, kStreamPolicy);
-        }
-    } else {
-        // value i of the lane: pair i % NP, half i / NP
-#pragma unroll
-        for (int i = 0; i < VPL; ++i) {
-            const uint32_t val = (i < NP) ? (v[i] & 0xFFFFu) : (v[i - NP] >> 16);
-            const bool ok = i < nvalid && off != kOff;
-            if (L8)
-                __builtin_amdgcn_raw_buffer_store_b8((unsigned char)val, rs, ok ? off + i : kOff, 0, kStreamPolicy);
-            else
-                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)val, rs, ok ? 2 * (off + i) : kOff, 0,
-                                                      kStreamPolicy);
-        }
-    }
-}
-
-// vector memory instructions issued per aggregation step (loads, stores)
-template <int VPL, bool ALIGNED, bool L8>
-struct VmemPerStep {
-    static constexpr int loads = ALIGNED ? 1 : VPL;
-    static constexpr int stores = (ALIGNED && L8) ? 1 : VPL;
-    static constexpr int total = loads + stores;
-};
-
-// s_waitcnt immediate: wait until at most n vector memory operations are
-// outstanding (gfx9 encoding; expcnt and lgkmcnt left at their maxima)
-constexpr int vmcnt_imm(int n)
-{
-    return ((n > 63 ? 63 : n) & 0xF) | (0x7 << 4) | (0xF << 8) | (((n > 63 ? 63 : n) >> 4) << 14);
-}
-
-enum { kHorizontal = 0, kVertical = 1, kDiagonal = 2 };
-
-// One workgroup's scanlines of one direction.  KIND selects the bookkeeping:
-// horizontal and vertical scanlines cover the whole image edge to edge, so
-// every lane is active at every step (tail lines past the last scanline
-// repeat the last one, writing identical values to identical addresses);
-// diagonal scanlines enter and leave the image at different steps, and
-// only their loads and stores are masked.  Before a scanline enters the
-// image its loads return 0, which keeps L' at 0, so the first in-image
-// step computes L = C without any reset.
-template <int VPL, bool ALIGNED, bool PAD, bool L8, int PF, int KIND>
-__device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsrc_t rc, __amdgpu_buffer_rsrc_t ro,
-                                         int du, int dv, int g)
-{
-    constexpr int NP = VPL / 2;
-    constexpr int UNROLL = 2 * PF;  // steps per loop iteration
-    const int lane = threadIdx.x & 15;
-    const int lw = threadIdx.x >> 4;
-    const int W = a.W, H = a.H, w = a.w;
-    const int lpw = a.lines_per_wg;
-
-    int I0 = 0, I1;
-    int idx = g * lpw + lw;
-    if constexpr (KIND == kHorizontal) {
-        idx = min(idx, H - 1);
-        I1 = W;
-    } else if constexpr (KIND == kVertical) {
-        idx = min(idx, W - 1);
-        I1 = H;
-    } else {
-        I0 = 1 << 30;
-        I1 = 0;
-        for (int l = 0; l < lpw; ++l) {
-            const Line t = line_geom(g * lpw + l, du, dv, W, H);
-            if (t.i1 > t.i0) {
-                I0 = min(I0, t.i0);
-                I1 = max(I1, t.i1);
-            }
-        }
-        if (I1 <= I0) return;
-    }
-    const Line ln = line_geom(idx, du, dv, W, H);
-    const int kbase = lane * VPL;
-    const int nvalid = min(max(w - kbase, 0), VPL);
-    const bool has = nvalid > 0;
-    // element offset of this lane's values at step i: off0 + i * stride
-    // (wrapping 32-bit arithmetic; exact whenever the pixel is in the image);
-    // lanes past the window never touch memory (offset stays kOff)
-    const uint32_t stride = has ? (uint32_t)((ln.sv * W + ln.su) * w) : 0u;
-    const uint32_t off0 = has ? (uint32_t)((ln.vb * W + ln.ub) * w + kbase) : kOff;
-    const uint32_t li0 = (uint32_t)ln.i0, llen = (uint32_t)(ln.i1 - ln.i0);
-    auto offset = [&](int i) -> uint32_t {
-        const uint32_t o = off0 + (uint32_t)i * stride;
-        if constexpr (KIND == kDiagonal)
-            return ((uint32_t)i - li0 < llen) ? o : kOff;
-        else
-            return o;
-    };
-
-    uint32_t padp[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        padp[j] = 0;
-        if (PAD) {
-            if (j >= nvalid) padp[j] |= kPad;
-            if (j + NP >= nvalid) padp[j] |= kPad << 16;
-        }
-    }
-
-    Raw<VPL> ring[PF];
-#pragma unroll
-    for (int s = 0; s < PF; ++s)
-        buf_load_u8<VPL, ALIGNED>(ring[s], rc, (I0 + s < I1) ? offset(I0 + s) : kOff, nvalid);
-
-    // Lq: the predecessor's L (as stored), mnq: its running pair minimum.
-    // A scanline starts from Lq = 0 (then L = C + min(0, P1, P2) - 0 = C).
-    uint32_t Lq[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) Lq[j] = 0;
-    uint32_t mnq = 0;
-
-    // the step count is padded to a multiple of UNROLL; padded steps load
-    // nothing and store nothing
-    const int nblk = (I1 - I0 + UNROLL - 1) / UNROLL;
-    for (int blk = 0; blk < nblk; ++blk) {
-#pragma unroll
-        for (int s = 0; s < UNROLL; ++s) {
-            const int i = I0 + blk * UNROLL + s;
-            // ring[s % PF] was loaded PF steps ago; everything issued since
-            // may stay in flight.  The scheduling fence keeps later steps'
-            // reads of the ring below this wait.
-            __builtin_amdgcn_sched_barrier(0);
-            __builtin_amdgcn_s_waitcnt(vmcnt_imm(VmemPerStep<VPL, ALIGNED, L8>::stores +
-                                                 (PF - 1) * VmemPerStep<VPL, ALIGNED, L8>::total));
-            uint32_t c2[NP];
-#pragma unroll
-            for (int j = 0; j < NP; ++j) c2[j] = unpack_strided(ring[s % PF], j) | padp[j];
-            {
-                const int ip = i + PF;
-                const uint32_t o = (ip < I1) ? offset(ip) : kOff;
-                buf_load_u8<VPL, ALIGNED>(ring[s % PF], rc, o, nvalid);
-            }
-            // m_q = min_k L(q,k): lane-local pair minimum (computed at the end
-            // of the previous step) reduced over the 16 lanes.  This chain is
-            // independent of the neighbour terms below, which overlap it.
-            const uint32_t m = row_min16(min(mnq & 0xFFFFu, mnq >> 16));
-            const uint32_t mm = m | (m << 16);
-            const uint32_t mp2 = pk_add(mm, a.p2x2);
-            // end neighbours across the lane edges (outside the window: 0x3FFF)
-            const uint32_t e = dpp<kRowShr1>(kInf2, Lq[NP - 1]);
-            const uint32_t f = dpp<kRowShl1>(kInf2, Lq[0]);
-            uint32_t Ln[NP];
-            uint32_t mn = 0xFFFFFFFFu;
-#pragma unroll
-            for (int j = 0; j < NP; ++j) {
-                const uint32_t lft = j ? Lq[j - 1] : __builtin_amdgcn_alignbit(Lq[NP - 1], e, 16);
-                const uint32_t rgt = j + 1 < NP ? Lq[j + 1] : __builtin_amdgcn_alignbit(f, Lq[0], 16);
-                // L(p,k) = C(p,k) + min(L(q,k), L(q,k+-1) + P1, m_q + P2) - m_q
-                uint32_t t = pk_add(pk_min(lft, rgt), a.p1x2);
-                t = pk_min(pk_min(t, Lq[j]), mp2);
-                Ln[j] = pk_sub(pk_add(t, c2[j]), mm);
-                mn = pk_min(mn, Ln[j]);
-            }
-            store_strided<VPL, ALIGNED, L8>(Ln, ro, (i < I1) ? offset(i) : kOff, nvalid);
-#pragma unroll
-            for (int j = 0; j < NP; ++j) Lq[j] = Ln[j];
-            mnq = mn;
-        }
-    }
+    cost_tile<CH>(cl, cr, d_lo, W, H, w, cmax, cost, blockIdx.x, blockIdx.y);
 }
 
 template <int VPL, bool ALIGNED, bool PAD, bool L8, int PF>
@@ -747,26 +62,10 @@ __global__ __launch_bounds__(256) void k_aggregate(AggParams a)
     // workgroup-uniform by construction; say so, so that the buffer
     // descriptors built from them stay in scalar registers
     slot = __builtin_amdgcn_readfirstlane(slot);
-    const int r = a.paths[slot] & 0xFF;
+    const int r = __builtin_amdgcn_readfirstlane(a.paths[slot] & 0xFF);
     const int vol = __builtin_amdgcn_readfirstlane(a.paths[slot] >> 8);
     const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x - a.gstart[slot]);
-    const int du = __builtin_amdgcn_readfirstlane(dir_du(r)), dv = __builtin_amdgcn_readfirstlane(dir_dv(r));
-    // buffer descriptors (scalar registers): the cost volume and this
-    // direction's output volume
-    const uint32_t nbytes = (uint32_t)a.W * (uint32_t)a.H * (uint32_t)a.w;
-    const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost, nbytes);
-    const __amdgpu_buffer_rsrc_t ro =
-        L8 ? make_rsrc(static_cast<const uint8_t *>(a.out) + (size_t)vol * a.vstride, nbytes)
-           : make_rsrc(static_cast<const uint16_t *>(a.out) + (size_t)vol * a.vstride, nbytes * 2u);
-    if (dv == 0) {
-        // the longest dependency chains: issue them first on a shared SIMD
-        __builtin_amdgcn_s_setprio(2);
-        agg_scan<VPL, ALIGNED, PAD, L8, PF, kHorizontal>(a, rc, ro, du, dv, g);
-    } else if (du == 0) {
-        agg_scan<VPL, ALIGNED, PAD, L8, PF, kVertical>(a, rc, ro, du, dv, g);
-    } else {
-        agg_scan<VPL, ALIGNED, PAD, L8, PF, kDiagonal>(a, rc, ro, du, dv, g);
-    }
+    agg_item<VPL, ALIGNED, PAD, L8, PF>(a, r, vol, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -810,51 +109,6 @@ __global__ __launch_bounds__(256) void k_sum(const void *__restrict__ vols, long
     }
 }
 
-// ---------------------------------------------------------------------------
-// winner-take-all, sub-pixel parabola, eq. (10) offset
-
-template <int VPL>
-__device__ __forceinline__ void select_and_write(const uint32_t (&S)[VPL / 2], int kbase, int w, int lane,
-                                                 int lo, long long pix, uint16_t *dint, float *dsub)
-{
-    constexpr int NP = VPL / 2;
-    uint32_t best = 0xFFFFFFFFu;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const int k = kbase + 2 * j;
-        const uint32_t s0 = S[j] & 0xFFFFu, s1 = S[j] >> 16;
-        if (k < w) best = min(best, (s0 << 8) | (uint32_t)k);
-        if (k + 1 < w) best = min(best, (s1 << 8) | (uint32_t)(k + 1));
-    }
-    best = row_min16(best);
-    const int ks = (int)(best & 0xFFu);
-    const int s0 = (int)(best >> 8);
-    uint32_t sm = 0, sp = 0;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const int k = kbase + 2 * j;
-        const uint32_t a = S[j] & 0xFFFFu, b = S[j] >> 16;
-        if (k == ks - 1) sm = a;
-        if (k + 1 == ks - 1) sm = b;
-        if (k == ks + 1) sp = a;
-        if (k + 1 == ks + 1) sp = b;
-    }
-    sm = row_max16(sm);
-    sp = row_max16(sp);
-    if (lane == 0) {
-        dint[pix] = (uint16_t)(lo + ks);
-        if (dsub) {
-            float delta = 0.0f;
-            if (ks > 0 && ks < w - 1) {
-                const int num = (int)sm - (int)sp;
-                const int den = 2 * ((int)sm - 2 * s0 + (int)sp);
-                delta = __fdiv_rn((float)num, (float)den);
-            }
-            dsub[pix] = __fadd_rn((float)(lo + ks), delta);
-        }
-    }
-}
-
 template <int VPL, bool ALIGNED>
 __global__ __launch_bounds__(256) void k_wta_sum(const uint16_t *__restrict__ sum, const int32_t *__restrict__ d_lo,
                                                  int W, int H, int w, uint16_t *__restrict__ dint,
@@ -875,123 +129,12 @@ __global__ __launch_bounds__(256) void k_wta_sum(const uint16_t *__restrict__ su
     select_and_write<VPL>(S, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
 }
 
-// Selection on uint8 per-direction volumes: the byte sums are formed SWAR
-// style, even and odd bytes of each dword accumulating in the two u16
-// halves of separate registers (sums <= npaths * (Cmax + P2) <= 65535, so
-// halves never carry).  ev[q] then holds S at window indices (4q, 4q+2) and
-// od[q] at (4q+1, 4q+3) of the lane's range.
-template <int VPL>
-__device__ __forceinline__ void select_swar(const uint32_t (&ev)[Raw<VPL>::NW], const uint32_t (&od)[Raw<VPL>::NW],
-                                            int kbase, int w, int lane, int lo, long long pix, uint16_t *dint,
-                                            float *dsub)
-{
-    constexpr int NW = Raw<VPL>::NW;
-    uint32_t best = 0xFFFFFFFFu;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) {
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            const int k = kbase + 4 * q + h;
-            const uint32_t sv = ((h & 1) ? od[q] : ev[q]) >> (16 * (h >> 1)) & 0xFFFFu;
-            if (4 * q + h < VPL && k < w) best = min(best, (sv << 8) | (uint32_t)k);
-        }
-    }
-    best = row_min16(best);
-    const int ks = (int)(best & 0xFFu);
-    const int s0 = (int)(best >> 8);
-    uint32_t sm = 0, sp = 0;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) {
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            const int k = kbase + 4 * q + h;
-            const uint32_t sv = ((h & 1) ? od[q] : ev[q]) >> (16 * (h >> 1)) & 0xFFFFu;
-            if (4 * q + h < VPL) {
-                if (k == ks - 1) sm = sv;
-                if (k == ks + 1) sp = sv;
-            }
-        }
-    }
-    sm = row_max16(sm);
-    sp = row_max16(sp);
-    if (lane == 0) {
-        dint[pix] = (uint16_t)(lo + ks);
-        if (dsub) {
-            float delta = 0.0f;
-            if (ks > 0 && ks < w - 1) {
-                const int num = (int)sm - (int)sp;
-                const int den = 2 * ((int)sm - 2 * s0 + (int)sp);
-                delta = __fdiv_rn((float)num, (float)den);
-            }
-            dsub[pix] = __fadd_rn((float)(lo + ks), delta);
-        }
-    }
-}
-
 template <int VPL, bool ALIGNED, bool L8>
 __global__ __launch_bounds__(256) void k_wta_paths(const void *__restrict__ vols, long long vstride, int np,
                                                    const int32_t *__restrict__ d_lo, int W, int H, int w,
                                                    uint16_t *__restrict__ dint, float *__restrict__ dsub)
 {
-    constexpr int NP = VPL / 2;
-    const int lane = threadIdx.x & 15;
-    const long long pix = (long long)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
-    if (pix >= (long long)W * H) return;
-    const int kbase = lane * VPL;
-    const int nvalid = min(max(w - kbase, 0), VPL);
-    const int v = (int)(pix / W);
-    if constexpr (L8 && VPL % 4 == 0) {
-        constexpr int NW = Raw<VPL>::NW;
-        uint32_t ev[NW], od[NW];
-#pragma unroll
-        for (int q = 0; q < NW; ++q) ev[q] = od[q] = 0;
-        if (nvalid > 0) {
-            const uint8_t *base = static_cast<const uint8_t *>(vols) + pix * w + kbase;
-            int r = 0;
-            for (; r + 1 < np; r += 2) {
-                Raw<VPL> x, y;
-                load_u8<VPL, ALIGNED>(x, base + r * vstride, nvalid);
-                load_u8<VPL, ALIGNED>(y, base + (r + 1) * vstride, nvalid);
-#pragma unroll
-                for (int q = 0; q < NW; ++q) {
-                    ev[q] += (x.d[q] & 0x00FF00FFu) + (y.d[q] & 0x00FF00FFu);
-                    od[q] += ((x.d[q] >> 8) & 0x00FF00FFu) + ((y.d[q] >> 8) & 0x00FF00FFu);
-                }
-            }
-            if (r < np) {
-                Raw<VPL> x;
-                load_u8<VPL, ALIGNED>(x, base + r * vstride, nvalid);
-#pragma unroll
-                for (int q = 0; q < NW; ++q) {
-                    ev[q] += x.d[q] & 0x00FF00FFu;
-                    od[q] += (x.d[q] >> 8) & 0x00FF00FFu;
-                }
-            }
-        }
-        select_swar<VPL>(ev, od, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
-    } else {
-        uint32_t S[NP];
-#pragma unroll
-        for (int j = 0; j < NP; ++j) S[j] = 0;
-        if (nvalid > 0) {
-            for (int r = 0; r < np; ++r) {
-                if (L8) {
-                    Raw<VPL> raw;
-                    load_u8<VPL, ALIGNED>(raw, static_cast<const uint8_t *>(vols) + r * vstride + pix * w + kbase,
-                                          nvalid);
-#pragma unroll
-                    for (int j = 0; j < NP; ++j) S[j] = pk_add(S[j], unpack_pair(raw, j));
-                } else {
-                    uint32_t t[NP];
-                    load_u16_pairs<VPL, ALIGNED>(
-                        t, static_cast<const uint16_t *>(vols) + r * vstride + pix * w + kbase, nvalid);
-#pragma unroll
-                    for (int j = 0; j < NP; ++j) S[j] = pk_add(S[j], t[j]);
-                }
-            }
-        }
-        select_and_write<VPL>(S, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
-    }
+    wta_paths_group<VPL, ALIGNED, L8>(vols, vstride, np, d_lo, W, H, w, dint, dsub, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

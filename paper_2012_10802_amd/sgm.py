@@ -37,6 +37,23 @@ class sgm_params(ctypes.Structure):
                 ("p2", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
+class sgm_pair(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("ndisp", ctypes.c_int32), ("pitch", ctypes.c_int32),
+                ("left", ctypes.c_void_p), ("right", ctypes.c_void_p),
+                ("d_lo", ctypes.c_void_p), ("disp_int", ctypes.c_void_p),
+                ("disp_sub", ctypes.c_void_p)]
+
+
+class sgm_batch_params(ctypes.Structure):
+    _fields_ = [("census", ctypes.c_int32), ("npaths", ctypes.c_int32),
+                ("p1", ctypes.c_int32), ("p2", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class sgm_tuning(ctypes.Structure):
+    _fields_ = [("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+
 def _load_library():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libsgm.so is not built; run `python -m paper_2012_10802_amd.build` "
@@ -59,6 +76,16 @@ def _load_library():
         "sgm_aggregate_paths": [P, P, P, S, P],
         "sgm_wta_paths": [P, P, P, P, P, P],
         "sgm_window_from_road": [D, D, D, I, I, I, I, D, P],
+        "sgm_batch_plan": [ctypes.POINTER(sgm_batch_params), ctypes.POINTER(sgm_pair), I,
+                           ctypes.POINTER(P)],
+        "sgm_batch_free": [P],
+        "sgm_batch_workspace_size": [P, ctypes.POINTER(S)],
+        "sgm_batch_set_tuning": [P, ctypes.POINTER(sgm_tuning)],
+        "sgm_batch_get_tuning": [P, ctypes.POINTER(sgm_tuning)],
+        "sgm_batch_run": [P, P, S, P],
+        "sgm_batch_capture": [P, P, S, P],
+        "sgm_batch_launch": [P, P],
+        "sgm_batch_autotune": [P, P, S, P, ctypes.c_char_p, ctypes.POINTER(sgm_tuning)],
         "sgm_status_str": [I],
         "sgm_last_error": [],
     }
@@ -67,6 +94,7 @@ def _load_library():
         f.argtypes = args
         f.restype = ctypes.c_int
     lib.sgm_plan_free.restype = None
+    lib.sgm_batch_free.restype = None
     lib.sgm_status_str.restype = ctypes.c_char_p
     lib.sgm_last_error.restype = ctypes.c_char_p
     return lib
@@ -295,6 +323,88 @@ class Matcher:
                               _ptr(self._dlo(d_lo)), _ptr(disp_int), _ptr(disp_sub),
                               _ptr(self.workspace), self.ws_bytes, _stream(stream)), "sgm_match")
         return disp_int, disp_sub
+
+
+class Batch:
+    """Many pairs (of several sizes) matched together by the batch calls.
+
+    `pairs` is a list of dicts with `left`, `right` (uint8 device tensors
+    [H, pitch]), `ndisp` and optionally `width` (default: the tensor width),
+    `d_lo` (int32 [H] device tensor) and `subpixel` (default True).  The
+    outputs are allocated here (`disp_int[i]`, `disp_sub[i]`) and written by
+    every run.  Census, paths and penalties are shared by the batch.
+    """
+
+    def __init__(self, pairs, census=7, npaths=8, p1=10, p2=120, device=None):
+        self.device = torch.device(device or "cuda")
+        self._keep = []
+        self.disp_int, self.disp_sub = [], []
+        arr = (sgm_pair * len(pairs))()
+        for i, pr in enumerate(pairs):
+            left, right = pr["left"], pr["right"]
+            _need(left, torch.uint8, None, "left")
+            _need(right, torch.uint8, None, "right")
+            if left.shape != right.shape or left.dim() != 2:
+                raise ValueError("pair %d: left and right must be uint8 [H, pitch] of one shape" % i)
+            H, pitch = left.shape
+            W = int(pr.get("width", pitch))
+            d_lo = pr.get("d_lo")
+            if d_lo is not None:
+                _need(d_lo, torch.int32, (H,), "d_lo")
+            di = torch.empty((H, W), dtype=torch.int16, device=self.device)
+            ds = (torch.empty((H, W), dtype=torch.float32, device=self.device)
+                  if pr.get("subpixel", True) else None)
+            self.disp_int.append(di)
+            self.disp_sub.append(ds)
+            self._keep += [left, right, d_lo]
+            arr[i] = sgm_pair(W, H, int(pr["ndisp"]), pitch, left.data_ptr(), right.data_ptr(),
+                              None if d_lo is None else d_lo.data_ptr(), di.data_ptr(),
+                              None if ds is None else ds.data_ptr())
+        prm = sgm_batch_params(census, npaths, p1, p2, 0)
+        h = ctypes.c_void_p()
+        _check(_lib.sgm_batch_plan(ctypes.byref(prm), arr, len(pairs), ctypes.byref(h)),
+               "sgm_batch_plan")
+        self.handle = h
+        n = ctypes.c_size_t()
+        _check(_lib.sgm_batch_workspace_size(self.handle, ctypes.byref(n)), "sgm_batch_workspace_size")
+        self.ws_bytes = int(n.value)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.sgm_batch_free(h)
+            self.handle = None
+
+    @property
+    def tuning(self):
+        t = sgm_tuning()
+        _check(_lib.sgm_batch_get_tuning(self.handle, ctypes.byref(t)), "sgm_batch_get_tuning")
+        return int(t.waves_per_cu), int(t.order)
+
+    @tuning.setter
+    def tuning(self, value):
+        t = sgm_tuning(int(value[0]), int(value[1]))
+        _check(_lib.sgm_batch_set_tuning(self.handle, ctypes.byref(t)), "sgm_batch_set_tuning")
+
+    def run(self, stream=None):
+        _check(_lib.sgm_batch_run(self.handle, _ptr(self.workspace), self.ws_bytes, _stream(stream)),
+               "sgm_batch_run")
+
+    def capture(self, stream):
+        """Record one run into a graph on `stream` (a non-default torch stream)."""
+        _check(_lib.sgm_batch_capture(self.handle, _ptr(self.workspace), self.ws_bytes,
+                                      _stream(stream)), "sgm_batch_capture")
+
+    def launch(self, stream=None):
+        _check(_lib.sgm_batch_launch(self.handle, _stream(stream)), "sgm_batch_launch")
+
+    def autotune(self, cache_path=None, stream=None):
+        t = sgm_tuning()
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(_lib.sgm_batch_autotune(self.handle, _ptr(self.workspace), self.ws_bytes,
+                                       _stream(stream), path, ctypes.byref(t)), "sgm_batch_autotune")
+        return int(t.waves_per_cu), int(t.order)
 
 
 def u16(t: torch.Tensor) -> torch.Tensor:

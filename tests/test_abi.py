@@ -112,3 +112,29 @@ def test_window_helper_host(sgm):
     assert lib.sgm_window_from_road(1.0, 1.0, 0.0, 10, 10, 4, 2, 0.0, None) == -1
     with pytest.raises(sgm.SgmError):
         sgm.sgm_window_from_road(float("nan"), 1.0, 0.0, 10, 10, 4, 0)
+
+
+def test_batch_plan_validation(sgm):
+    lib = sgm.library()
+    prm = sgm.sgm_batch_params(7, 8, 10, 120, 0)
+
+    def status(*pairs, prm=prm):
+        arr = (sgm.sgm_pair * len(pairs))(*pairs)
+        h = ctypes.c_void_p()
+        st = lib.sgm_batch_plan(ctypes.byref(prm), arr, len(pairs), ctypes.byref(h))
+        if st == 0:
+            lib.sgm_batch_free(h)
+        return st
+
+    ok = sgm.sgm_pair(64, 32, 64, 64, 256, 256, None, 256, None)
+    assert status(sgm.sgm_pair(64, 32, 100, 64, 256, 256, None, 256, None)) == -2  # 100 % 8
+    assert status(sgm.sgm_pair(64, 32, 64, 60, 256, 256, None, 256, None)) == -1  # pitch
+    assert status(sgm.sgm_pair(64, 32, 64, 64, None, 256, None, 256, None)) == -1  # NULL
+    assert status(ok, sgm.sgm_pair(0, 32, 64, 64, 256, 256, None, 256, None)) == -1
+    assert status(ok, prm=sgm.sgm_batch_params(9, 8, 10, 120, 0)) == -2
+    assert status(ok, prm=sgm.sgm_batch_params(7, 8, 130, 120, 0)) == -1
+    h = ctypes.c_void_p()
+    arr = (sgm.sgm_pair * 1)(ok)
+    assert lib.sgm_batch_plan(ctypes.byref(prm), arr, 0, ctypes.byref(h)) == -1
+    assert lib.sgm_batch_run(None, None, 0, None) == -1
+    assert lib.sgm_batch_launch(None, None) == -1
