@@ -35,13 +35,25 @@ METRIC = "SGM Mdisp-evals/s at 1280x720x128; learned-window vs plain at same bad
 WORKLOADS = {
     "road1280": "1280x720 uint8 road pair, census 7x7, 8 paths, P1=10, P2=120, disparities 0-127",
     "road320": "320x240 uint8 road pair, census 5x5, 4 paths, P1=10, P2=120, disparities 0-31",
+    "road_batch64": "64 uint8 road pairs in one batch: 24 x 640x480 (disparities 0-63), "
+                    "24 x 1280x720 (0-127), 16 x 1920x1080 (0-191); census 7x7, 8 paths, "
+                    "P1=10, P2=120; roll U(0,4) deg",
+}
+
+# pairs of each batched workload: (generator config, count)
+BATCHES = {
+    "road_batch64": [("road640", 24), ("road1280", 24), ("road1920", 16)],
+    "road1280": [("road1280", 1)],
 }
 
 
 def kernel_source_digest() -> str:
+    """Digest of the device code (kernels and the shared device header)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2012_10802_amd", "csrc", "sgm_kernels.hip"), "rb") as f:
-        h.update(f.read())
+    csrc = os.path.join(ROOT, "paper_2012_10802_amd", "csrc")
+    for name in ("sgm_device.h", "sgm_kernels.hip", "sgm_batch.hip"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -71,12 +83,81 @@ def eval_mask(p, w, r):
     return m
 
 
+def run_batch(args):
+    """Batch mode: the whole batch as one captured graph per step."""
+    import numpy as np
+    import torch
+
+    from paper_2012_10802_amd import sgm, synth
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    pairs, evals, renders = [], 0, {}
+    for name, count in BATCHES[args.workload]:
+        c = synth.CONFIGS[name]
+        for j in range(count):
+            k = (name, j % args.unique)
+            if k not in renders:
+                seed = args.seed + 97 * j
+                p = synth.make_pair(synth.scene_for_config(name, seed), seed)
+                renders[k] = (torch.from_numpy(p.left).to(dev), torch.from_numpy(p.right).to(dev))
+            L, R = renders[k]
+            pairs.append({"left": L, "right": R, "ndisp": c["ndisp"]})
+            evals += c["width"] * c["height"] * c["ndisp"]
+    c0 = synth.CONFIGS[BATCHES[args.workload][0][0]]
+    b = sgm.Batch(pairs, census=c0["census"], npaths=c0["npaths"], p1=c0["p1"], p2=c0["p2"], device=dev)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        tuning = b.autotune(args.tune_cache)
+        b.capture(stream)
+        for _ in range(args.warmup):
+            b.launch(stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            b.launch(stream)
+        e1.record(stream)
+        stream.synchronize()
+        t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    out = {
+        "metric": METRIC,
+        "value": round(evals / (ms * 1e-3) / 1e6, 1),
+        "unit": "Mdisp-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "ms_per_step_events": round(e0.elapsed_time(e1) / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "mode": "batch (one persistent aggregation launch, graph replay)",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "pairs": len(pairs), "evals_per_step": evals, "unique_renders": len(renders)},
+        "tuning": {"waves_per_cu": tuning[0], "order": ["longest-first", "pair-major",
+                                                        "direction-major"][tuning[1]]},
+        "kernel_source_sha256": kernel_source_digest(),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="road1280", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="single", choices=["single", "batch"],
+                    help="single: the split single-pair calls; batch: the batch calls as a graph")
+    ap.add_argument("--unique", type=int, default=2,
+                    help="batch mode: distinct rendered pairs per size (inputs are shared)")
+    ap.add_argument("--tune-cache", default=None, help="batch mode: autotuner cache file")
     ap.add_argument("--seed", type=int, default=2001)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -88,6 +169,8 @@ def main():
               "this build runs and reports a single MI355X (got --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batch" or args.workload == "road_batch64":
+        return run_batch(args)
 
     import numpy as np
     import torch

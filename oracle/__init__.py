@@ -53,6 +53,10 @@ def _load():
         lib.oracle_sgm.argtypes = [P, P, I, I, I, I, I, I, I, I, P, P, P]
         lib.oracle_window_from_road.argtypes = [D, D, D, I, I, I, I, D, P]
         lib.oracle_num_threads.argtypes = []
+        lib.oracle_cost_win.argtypes = [P, P, I, I, I, I, P, P]
+        lib.oracle_path_win.argtypes = [P, P, I, I, I, I, I, I, I, P]
+        lib.oracle_sgm_win.argtypes = [P, P, I, I, I, I, I, I, I, I, P, P, P]
+        lib.oracle_downsample4.argtypes = [P, I, I, I, P]
         _lib = lib
     return _lib
 
@@ -161,4 +165,56 @@ def window_from_road(a0, a1, phi, W, H, w, mode=0, delta=0.0) -> np.ndarray:
     out = np.empty((H,), np.int32)
     _check(_load().oracle_window_from_road(float(a0), float(a1), float(phi), W, H, w,
                                            int(mode), float(delta), _p(out)), "window")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# per-pixel windows in absolute disparity
+
+
+def _lo_map(lo, H, W):
+    lo = np.ascontiguousarray(lo, dtype=np.int32)
+    if lo.shape != (H, W):
+        raise ValueError("lo must be int32 [H, W]")
+    return lo
+
+
+def cost_win(cl, cr, n, w, lo):
+    cl = np.ascontiguousarray(cl, dtype=np.uint64)
+    cr = np.ascontiguousarray(cr, dtype=np.uint64)
+    H, W = cl.shape
+    lo = _lo_map(lo, H, W)
+    out = np.empty((H, W, w), np.uint8)
+    _check(_load().oracle_cost_win(_p(cl), _p(cr), W, H, n, w, _p(lo), _p(out)), "cost_win")
+    return out
+
+
+def path_win(c, lo, r, p1, p2):
+    c = np.ascontiguousarray(c, dtype=np.uint8)
+    H, W, w = c.shape
+    lo = _lo_map(lo, H, W)
+    du, dv = PATHS[r]
+    out = np.empty((H, W, w), np.uint16)
+    _check(_load().oracle_path_win(_p(c), _p(lo), W, H, w, du, dv, p1, p2, _p(out)), "path_win")
+    return out
+
+
+def sgm_win(left, right, n, w, npaths, p1, p2, lo):
+    """Per-pixel-window SGM: (Dint uint16, Dsub float32) with D = lo + k*."""
+    left = np.ascontiguousarray(left, dtype=np.uint8)
+    right = np.ascontiguousarray(right, dtype=np.uint8)
+    H, W = left.shape
+    lo = _lo_map(lo, H, W)
+    dint = np.empty((H, W), np.uint16)
+    dsub = np.empty((H, W), np.float32)
+    _check(_load().oracle_sgm_win(_p(left), _p(right), W, H, W, n, w, npaths, p1, p2, _p(lo),
+                                  _p(dint), _p(dsub)), "sgm_win")
+    return dint, dsub
+
+
+def downsample4(img):
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    out = np.empty((H // 4, W // 4), np.uint8)
+    _check(_load().oracle_downsample4(_p(img), W, H, W, _p(out)), "downsample4")
     return out

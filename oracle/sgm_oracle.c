@@ -296,6 +296,139 @@ int oracle_window_from_road(double a0, double a1, double phi, int W, int H,
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* per-pixel windows in absolute disparity (learned-window form)        */
+/*
+ * Every pixel p has its own window of w disparities [lo(p), lo(p) + w).
+ * The cost is taken over that window; the aggregation of eq. (8) is
+ * written in absolute disparity, a predecessor's values outside its own
+ * window counting as infinite (so those neighbour terms drop out and the
+ * m_q + P2 term keeps the result finite).  L is stored by window index
+ * j = d - lo(p).  lo is int32 [H][W], every entry >= 0.
+ */
+
+#define ORACLE_INF ((int64_t)1 << 40)
+
+int oracle_cost_win(const uint64_t *cl, const uint64_t *cr, int W, int H, int n, int w,
+                    const int32_t *lo, uint8_t *cost)
+{
+    if (!cl || !cr || !lo || !cost || W < 1 || H < 1 || w < 1 || w > 256) return -1;
+    int cmax = n * n - 1;
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            int l = lo[(size_t)v * W + u];
+            if (l < 0) return -1;
+            for (int j = 0; j < w; ++j) {
+                int ur = u - l - j;
+                cost[((size_t)v * W + u) * w + j] =
+                    (uint8_t)(ur >= 0 ? popcount64(cl[(size_t)v * W + u] ^ cr[(size_t)v * W + ur]) : cmax);
+            }
+        }
+    return 0;
+}
+
+int oracle_path_win(const uint8_t *cost, const int32_t *lo, int W, int H, int w, int du, int dv,
+                    int p1, int p2, uint16_t *L)
+{
+    if (!cost || !lo || !L || W < 1 || H < 1 || w < 1 || p1 < 0 || p2 < p1) return -1;
+    if (du < -1 || du > 1 || dv < -1 || dv > 1 || (du == 0 && dv == 0)) return -1;
+    for (int i = 0; i < H; ++i) {
+        int v = dv >= 0 ? i : H - 1 - i;
+        for (int jx = 0; jx < W; ++jx) {
+            int u = du >= 0 ? jx : W - 1 - jx;
+            const uint8_t *c = cost + ((size_t)v * W + u) * w;
+            uint16_t *out = L + ((size_t)v * W + u) * w;
+            int qu = u - du, qv = v - dv;
+            if (qu < 0 || qu >= W || qv < 0 || qv >= H) {
+                for (int k = 0; k < w; ++k) out[k] = c[k];
+                continue;
+            }
+            const uint16_t *prev = L + ((size_t)qv * W + qu) * w;
+            int lp = lo[(size_t)v * W + u], lq = lo[(size_t)qv * W + qu];
+            int64_t m = prev[0];
+            for (int k = 1; k < w; ++k) if (prev[k] < m) m = prev[k];
+            for (int k = 0; k < w; ++k) {
+                int d = lp + k;  /* absolute disparity */
+                int64_t at[3];   /* L(q, d - 1), L(q, d), L(q, d + 1) */
+                for (int e = -1; e <= 1; ++e) {
+                    int jq = d + e - lq;
+                    at[e + 1] = (jq >= 0 && jq < w) ? (int64_t)prev[jq] : ORACLE_INF;
+                }
+                int64_t best = at[1];
+                if (at[0] + p1 < best) best = at[0] + p1;
+                if (at[2] + p1 < best) best = at[2] + p1;
+                if (m + p2 < best) best = m + p2;
+                out[k] = (uint16_t)(c[k] + best - m);
+            }
+        }
+    }
+    return 0;
+}
+
+int oracle_sgm_win(const uint8_t *left, const uint8_t *right, int W, int H, int pitch, int n, int w,
+                   int npaths, int p1, int p2, const int32_t *lo, uint16_t *dint, float *dsub)
+{
+    if (!lo || (npaths != 4 && npaths != 8)) return -1;
+    size_t np = (size_t)W * H, nv = np * (size_t)w;
+    uint64_t *cl = (uint64_t *)malloc(np * sizeof(uint64_t));
+    uint64_t *cr = (uint64_t *)malloc(np * sizeof(uint64_t));
+    uint8_t *c = (uint8_t *)malloc(nv);
+    uint32_t *S = (uint32_t *)calloc(nv, sizeof(uint32_t));
+    uint16_t *Lr = (uint16_t *)malloc(nv * sizeof(uint16_t) * (size_t)npaths);
+    int rc = -2;
+    if (cl && cr && c && S && Lr) {
+        rc = oracle_census(left, W, H, pitch, n, cl);
+        if (!rc) rc = oracle_census(right, W, H, pitch, n, cr);
+        if (!rc) rc = oracle_cost_win(cl, cr, W, H, n, w, lo, c);
+        if (!rc) {
+            int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+            for (int r = 0; r < npaths; ++r)
+                err |= oracle_path_win(c, lo, W, H, w, PATH_DU[r], PATH_DV[r], p1, p2, Lr + nv * r) ? 1 : 0;
+            rc = err ? -1 : 0;
+        }
+        if (!rc) {
+            for (int r = 0; r < npaths; ++r)
+                for (size_t i = 0; i < nv; ++i) S[i] += Lr[nv * r + i];
+            /* selection on window indices, output lo(p) + k (+ parabola) */
+            for (size_t pix = 0; pix < np; ++pix) {
+                const uint32_t *s = S + pix * w;
+                int best = 0;
+                for (int k = 1; k < w; ++k) if (s[k] < s[best]) best = k;
+                int l = lo[pix];
+                dint[pix] = (uint16_t)(l + best);
+                if (dsub) {
+                    float delta = 0.0f;
+                    if (best > 0 && best < w - 1) {
+                        int sm = (int)s[best - 1], s0 = (int)s[best], sp = (int)s[best + 1];
+                        delta = (float)(sm - sp) / (float)(2 * (sm - 2 * s0 + sp));
+                    }
+                    dsub[pix] = (float)(l + best) + delta;
+                }
+            }
+        }
+    }
+    free(cl); free(cr); free(c); free(S); free(Lr);
+    return rc;
+}
+
+/* 4 x 4 box reduction of an 8-bit image: each output pixel is the rounded
+ * mean (sum + 8) / 16 of its block; blocks past the border are dropped
+ * (output size floor(W/4) x floor(H/4)). */
+int oracle_downsample4(const uint8_t *img, int W, int H, int pitch, uint8_t *out)
+{
+    if (!img || !out || W < 4 || H < 4 || pitch < W) return -1;
+    int Wc = W / 4, Hc = H / 4;
+    for (int y = 0; y < Hc; ++y)
+        for (int x = 0; x < Wc; ++x) {
+            int sum = 0;
+            for (int dy = 0; dy < 4; ++dy)
+                for (int dx = 0; dx < 4; ++dx) sum += img[(size_t)(4 * y + dy) * pitch + 4 * x + dx];
+            out[(size_t)y * Wc + x] = (uint8_t)((sum + 8) / 16);
+        }
+    return 0;
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

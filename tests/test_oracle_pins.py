@@ -371,3 +371,85 @@ def test_generator_ground_truth_is_the_road_model():
     assert float(np.sum((d - T @ a) ** 2)) < 1e-12
     # potholes are deeper: lower disparity than the plane
     assert (p.gt[p.pothole] < f[p.pothole]).all()
+
+
+# ---------------------------------------------------------------------------
+# per-pixel windows in absolute disparity (learned-window form)
+
+
+def _brute_energy_win(c, lo, pix, d_end, p1, p2):
+    """min over absolute-disparity sequences, d_i in the window of pixel i,
+    ending at d_end, of sum C + sum penalties."""
+    w = c.shape[2]
+    choices = [range(lo[v, u], lo[v, u] + w) for (u, v) in pix[:-1]]
+    best = None
+    for seq in itertools.product(*choices):
+        seq = seq + (d_end,)
+        e = sum(int(c[v, u, d - lo[v, u]]) for (u, v), d in zip(pix, seq))
+        e += sum(_pen(seq[i - 1], seq[i], p1, p2) for i in range(1, len(seq)))
+        best = e if best is None or e < best else best
+    return best
+
+
+@pytest.mark.parametrize("r", range(8))
+def test_window_path_equals_bruteforce(r):
+    rng = np.random.default_rng(300 + r)
+    H, W, w = 3, 4, 3
+    c = rng.integers(0, 25, size=(H, W, w), dtype=np.uint8)
+    lo = rng.integers(0, 4, size=(H, W)).astype(np.int32)
+    p1, p2 = 3, 7
+    du, dv = oracle.PATHS[r]
+    L = oracle.path_win(c, lo, r, p1, p2)
+    for v in range(H):
+        for u in range(W):
+            pix = _path_pixels(u, v, du, dv, W, H)
+            ub = [_brute_energy_win(c, lo, pix, lo[v, u] + j, p1, p2) for j in range(w)]
+            if len(pix) == 1:
+                assert list(L[v, u]) == list(c[v, u])
+            else:
+                qu, qv = pix[-2]
+                mq = min(_brute_energy_win(c, lo, pix[:-1], lo[qv, qu] + j, p1, p2) for j in range(w))
+                assert list(L[v, u]) == [x - mq for x in ub]
+
+
+def test_window_constant_start_is_row_window_sgm(road320):
+    p, _ = road320
+    for c0 in (0, 5):
+        lo = np.full(p.left.shape, c0, np.int32)
+        a = oracle.sgm_win(p.left, p.right, 5, 16, 8, 10, 120, lo)
+        b = oracle.sgm(p.left, p.right, 5, 16, 8, 10, 120, np.full(240, c0, np.int32))
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_window_cost_is_slice_of_full_cost():
+    p = synth.make_pair(synth.RoadScene(96, 40, focal=120.0, roll_deg=1.0), 8)
+    cl, cr = oracle.census(p.left, 7), oracle.census(p.right, 7)
+    full = oracle.cost(cl, cr, 7, 40)
+    lo = np.random.default_rng(1).integers(0, 25, size=(40, 96)).astype(np.int32)
+    win = oracle.cost_win(cl, cr, 7, 16, lo)
+    for v in range(40):
+        for u in range(96):
+            np.testing.assert_array_equal(win[v, u], full[v, u, lo[v, u]:lo[v, u] + 16])
+
+
+def test_window_exact_recovery_with_random_windows():
+    """Absolute-disparity smoothness: a plane at integer d0 is recovered
+    through per-pixel windows that contain d0 at random positions."""
+    W, H, d0 = 160, 48, 21
+    L, R = _shifted_pair(W, H, [d0] * H, 24)
+    lo = (d0 - np.random.default_rng(2).integers(0, 16, size=(H, W))).astype(np.int32)
+    dint, dsub = oracle.sgm_win(L, R, 7, 16, 8, 10, 120, lo)
+    band = dint[:, d0 + 3 + 16: W - 3 - 16]
+    assert (band == d0).all()
+
+
+def test_downsample4_closed_forms():
+    img = np.arange(16, dtype=np.uint8).reshape(4, 4)
+    assert oracle.downsample4(img)[0, 0] == (120 + 8) // 16
+    assert (oracle.downsample4(np.full((13, 9), 200, np.uint8)) == 200).all()
+    assert oracle.downsample4(np.full((13, 9), 200, np.uint8)).shape == (3, 2)
+    rng = np.random.default_rng(4)
+    big = rng.integers(0, 256, size=(8, 12), dtype=np.uint8)
+    want = (big.reshape(2, 4, 3, 4).astype(int).sum(axis=(1, 3)) + 8) // 16
+    np.testing.assert_array_equal(oracle.downsample4(big), want)
