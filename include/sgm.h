@@ -152,6 +152,41 @@ sgm_status sgm_match(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
                      void *stream);
 
 /* ------------------------------------------------------------------------
+ * Per-pixel search windows in absolute disparity (the learned-window form).
+ *
+ * Pixel p searches the w disparities [lo(p), lo(p) + w), w = the plan's
+ * ndisp, which must be <= 16; lo is a device int32 [H][W] map with
+ * 0 <= lo(p) <= 256 - w (values outside give unspecified but memory-safe
+ * results).  Volumes are [H][W][w] by window index j = d - lo(p).
+ *   cost:        C(u,v,j) = popcount(cL(u,v) XOR cR(u - lo(u,v) - j, v)),
+ *                Cmax where that column is < 0 (Sec. II-B).
+ *   aggregation: eq. (8) in absolute disparity: with q = p - r,
+ *                L(p,j) = C(p,j) + min(Lq(d), Lq(d-1)+P1, Lq(d+1)+P1,
+ *                m_q+P2) - m_q at d = lo(p) + j, where Lq(d) is q's value at
+ *                window index d - lo(q) and counts as infinite outside q's
+ *                window, and m_q is the minimum over q's window.
+ *   selection:   as sgm_wta on window indices; outputs lo(p) + k* (+ the
+ *                parabola offset).
+ * The workspace and path-volume layout are those of the plan.
+ */
+sgm_status sgm_cost_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
+                        int32_t pitch, const int32_t *lo, uint8_t *cost /* 16-byte aligned */,
+                        void *workspace, size_t workspace_bytes, void *stream);
+sgm_status sgm_aggregate_win_paths(sgm_plan_t plan, const uint8_t *cost, const int32_t *lo,
+                                   void *paths, size_t paths_bytes, void *stream);
+sgm_status sgm_wta_win_paths(sgm_plan_t plan, const void *paths, const int32_t *lo,
+                             uint16_t *disp_int, float *disp_sub, void *stream);
+sgm_status sgm_match_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
+                         int32_t pitch, const int32_t *lo, uint16_t *disp_int, float *disp_sub,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* 4 x 4 box reduction of an 8-bit image (the coarse level of the
+ * learned-window form): out is floor(H/4) x floor(W/4), row-major, each
+ * value (sum of its 16 pixels + 8) / 16.  Device buffers; needs W, H >= 4. */
+sgm_status sgm_downsample4(const uint8_t *image, int32_t width, int32_t height, int32_t pitch,
+                           uint8_t *out, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batches: many pairs, of several sizes, matched together.
  *
  * A batch fixes the pairs (sizes and device buffers) at plan time.  A run

@@ -291,6 +291,93 @@ sgm_status sgm_match(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
     return sgm_aggregate_wta(plan, cost, d_lo, disp_int, disp_sub, ws, ws_bytes, stream);
 }
 
+// ---------------------------------------------------------------------------
+// per-pixel windows
+
+namespace {
+
+sgm_status check_win_plan(sgm_plan_t plan)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (plan->pb.w > 16) return fail(SGM_ERR_UNSUPPORTED, "per-pixel windows need ndisp <= 16 (got %d)", plan->pb.w);
+    return SGM_OK;
+}
+
+}  // namespace
+
+sgm_status sgm_downsample4(const uint8_t *img, int32_t width, int32_t height, int32_t pitch, uint8_t *out,
+                           void *stream)
+{
+    if (!img || !out) return fail(SGM_ERR_INVALID, "img and out must not be NULL");
+    if (width < 4 || height < 4 || pitch < width) return fail(SGM_ERR_INVALID, "need width, height >= 4, pitch >= width");
+    hipError_t e = sgm::launch_downsample4(img, width, height, pitch, out, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "downsample launch");
+}
+
+sgm_status sgm_cost_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *right, int32_t pitch, const int32_t *lo,
+                        uint8_t *cost, void *ws, size_t ws_bytes, void *stream)
+{
+    if (sgm_status s = check_win_plan(plan)) return s;
+    if (!left || !right || !lo || !cost) return fail(SGM_ERR_INVALID, "left, right, lo and cost must not be NULL");
+    if (pitch < plan->pb.W) return fail(SGM_ERR_INVALID, "pitch %d < width %d", pitch, plan->pb.W);
+    if (!is_aligned(cost, 16)) return fail(SGM_ERR_INVALID, "cost must be 16-byte aligned");
+    if (sgm_status s = check_ws(plan, ws, ws_bytes)) return s;
+    uint8_t *base = static_cast<uint8_t *>(ws);
+    uint64_t *cl = reinterpret_cast<uint64_t *>(base + plan->off_codes_l);
+    uint64_t *cr = reinterpret_cast<uint64_t *>(base + plan->off_codes_r);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = sgm::launch_census(plan->pb, left, pitch, cl, st);
+    if (e == hipSuccess) e = sgm::launch_census(plan->pb, right, pitch, cr, st);
+    if (e == hipSuccess) e = sgm::launch_cost_win(plan->pb, cl, cr, lo, cost, st);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "cost_win launch");
+}
+
+sgm_status sgm_aggregate_win_paths(sgm_plan_t plan, const uint8_t *cost, const int32_t *lo, void *paths,
+                                   size_t paths_bytes, void *stream)
+{
+    if (sgm_status s = check_win_plan(plan)) return s;
+    if (!cost || !lo || !paths) return fail(SGM_ERR_INVALID, "cost, lo and paths must not be NULL");
+    if (!is_aligned(paths, 256)) return fail(SGM_ERR_INVALID, "paths must be 256-byte aligned");
+    size_t total = 0, vs = 0;
+    sgm_path_volumes(plan, nullptr, &vs, &total);
+    if (paths_bytes < total)
+        return fail(SGM_ERR_WORKSPACE, "paths buffer of %zu bytes is smaller than the %zu required", paths_bytes,
+                    total);
+    const long long vstride = (long long)(vs / (plan->kc.l8 ? 1 : 2));
+    hipError_t e = sgm::launch_aggregate_win(plan->pb, cost, lo, plan->paths, plan->pb.npaths, plan->kc.l8, paths,
+                                             vstride, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "aggregate_win launch");
+}
+
+sgm_status sgm_wta_win_paths(sgm_plan_t plan, const void *paths, const int32_t *lo, uint16_t *disp_int,
+                             float *disp_sub, void *stream)
+{
+    if (sgm_status s = check_win_plan(plan)) return s;
+    if (!paths || !lo || !disp_int) return fail(SGM_ERR_INVALID, "paths, lo and disp_int must not be NULL");
+    if (!is_aligned(paths, 256)) return fail(SGM_ERR_INVALID, "paths must be 256-byte aligned");
+    size_t vs = 0;
+    sgm_path_volumes(plan, nullptr, &vs, nullptr);
+    const long long vstride = (long long)(vs / (plan->kc.l8 ? 1 : 2));
+    hipError_t e = sgm::launch_wta_win(plan->pb, paths, vstride, plan->pb.npaths, plan->kc.l8, lo, disp_int,
+                                       disp_sub, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "wta_win launch");
+}
+
+sgm_status sgm_match_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *right, int32_t pitch, const int32_t *lo,
+                         uint16_t *disp_int, float *disp_sub, void *ws, size_t ws_bytes, void *stream)
+{
+    if (sgm_status s = check_win_plan(plan)) return s;
+    if (sgm_status s = check_ws(plan, ws, ws_bytes)) return s;
+    uint8_t *base = static_cast<uint8_t *>(ws);
+    if (sgm_status s = sgm_cost_win(plan, left, right, pitch, lo, base + plan->off_cost, ws, ws_bytes, stream))
+        return s;
+    size_t total = 0;
+    sgm_path_volumes(plan, nullptr, nullptr, &total);
+    if (sgm_status s = sgm_aggregate_win_paths(plan, base + plan->off_cost, lo, base + plan->off_paths, total, stream))
+        return s;
+    return sgm_wta_win_paths(plan, base + plan->off_paths, lo, disp_int, disp_sub, stream);
+}
+
 sgm_status sgm_window_from_road(double a0, double a1, double phi, int32_t W, int32_t H, int32_t w, int32_t mode,
                                 double delta, int32_t *d_lo)
 {

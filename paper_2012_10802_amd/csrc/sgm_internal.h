@@ -45,6 +45,17 @@ hipError_t launch_wta_paths(const Problem &pb, const KernelConfig &kc, const voi
                             hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// per-pixel windows (w <= 16)
+
+hipError_t launch_downsample4(const uint8_t *img, int W, int H, int pitch, uint8_t *out, hipStream_t s);
+hipError_t launch_cost_win(const Problem &pb, const uint64_t *cl, const uint64_t *cr, const int32_t *lo,
+                           uint8_t *cost, hipStream_t s);
+hipError_t launch_aggregate_win(const Problem &pb, const uint8_t *cost, const int32_t *lo, const int *paths, int np,
+                                bool l8, void *out, long long vstride, hipStream_t s);
+hipError_t launch_wta_win(const Problem &pb, const void *vols, long long vstride, int np, bool l8, const int32_t *lo,
+                          uint16_t *dint, float *dsub, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // batches
 
 // Device descriptor of one pair.  Caller buffers are absolute pointers;

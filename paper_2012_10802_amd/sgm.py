@@ -76,6 +76,11 @@ def _load_library():
         "sgm_aggregate_paths": [P, P, P, S, P],
         "sgm_wta_paths": [P, P, P, P, P, P],
         "sgm_window_from_road": [D, D, D, I, I, I, I, D, P],
+        "sgm_downsample4": [P, I, I, I, P, P],
+        "sgm_cost_win": [P, P, P, I, P, P, P, S, P],
+        "sgm_aggregate_win_paths": [P, P, P, P, S, P],
+        "sgm_wta_win_paths": [P, P, P, P, P, P],
+        "sgm_match_win": [P, P, P, I, P, P, P, P, S, P],
         "sgm_batch_plan": [ctypes.POINTER(sgm_batch_params), ctypes.POINTER(sgm_pair), I,
                            ctypes.POINTER(P)],
         "sgm_batch_free": [P],
@@ -164,6 +169,17 @@ def sgm_window_from_road(a0, a1, phi, width, height, w, mode=0, delta=0.0):
     _check(_lib.sgm_window_from_road(float(a0), float(a1), float(phi), int(width), int(height),
                                      int(w), int(mode), float(delta), _ptr(out)),
            "sgm_window_from_road")
+    return out
+
+
+def sgm_downsample4(image, out=None, stream=None):
+    """4 x 4 box reduction of a uint8 device image [H, pitch] (width = pitch)."""
+    _need(image, torch.uint8, None, "image")
+    H, W = image.shape
+    if out is None:
+        out = torch.empty((H // 4, W // 4), dtype=torch.uint8, device=image.device)
+    _need(out, torch.uint8, (H // 4, W // 4), "out")
+    _check(_lib.sgm_downsample4(_ptr(image), W, H, W, _ptr(out), _stream(stream)), "sgm_downsample4")
     return out
 
 
@@ -312,6 +328,45 @@ class Matcher:
         disp_int, disp_sub = self._outs(disp_int, disp_sub, subpixel)
         _check(_lib.sgm_wta_paths(self.plan, _ptr(paths), _ptr(self._dlo(d_lo)), _ptr(disp_int),
                                   _ptr(disp_sub), _stream(stream)), "sgm_wta_paths")
+        return disp_int, disp_sub
+
+    # per-pixel windows (ndisp <= 16): lo is int32 [H, W] on the device
+
+    def _lo(self, lo):
+        return _need(lo, torch.int32, (self.H, self.W), "lo")
+
+    def cost_win(self, left, right, lo, cost=None, stream=None):
+        self._img(left, "left")
+        self._img(right, "right")
+        if cost is None:
+            cost = self.new_volume(torch.uint8)
+        _need(cost, torch.uint8, self.volume_shape, "cost")
+        _check(_lib.sgm_cost_win(self.plan, _ptr(left), _ptr(right), left.shape[1], _ptr(self._lo(lo)),
+                                 _ptr(cost), _ptr(self.workspace), self.ws_bytes, _stream(stream)),
+               "sgm_cost_win")
+        return cost
+
+    def aggregate_win_paths(self, cost, lo, paths=None, stream=None):
+        _need(cost, torch.uint8, self.volume_shape, "cost")
+        if paths is None:
+            paths = self.new_paths()
+        _check(_lib.sgm_aggregate_win_paths(self.plan, _ptr(cost), _ptr(self._lo(lo)), _ptr(paths),
+                                            paths.numel(), _stream(stream)), "sgm_aggregate_win_paths")
+        return paths
+
+    def wta_win_paths(self, paths, lo, disp_int=None, disp_sub=None, subpixel=True, stream=None):
+        disp_int, disp_sub = self._outs(disp_int, disp_sub, subpixel)
+        _check(_lib.sgm_wta_win_paths(self.plan, _ptr(paths), _ptr(self._lo(lo)), _ptr(disp_int),
+                                      _ptr(disp_sub), _stream(stream)), "sgm_wta_win_paths")
+        return disp_int, disp_sub
+
+    def match_win(self, left, right, lo, disp_int=None, disp_sub=None, subpixel=True, stream=None):
+        self._img(left, "left")
+        self._img(right, "right")
+        disp_int, disp_sub = self._outs(disp_int, disp_sub, subpixel)
+        _check(_lib.sgm_match_win(self.plan, _ptr(left), _ptr(right), left.shape[1], _ptr(self._lo(lo)),
+                                  _ptr(disp_int), _ptr(disp_sub), _ptr(self.workspace), self.ws_bytes,
+                                  _stream(stream)), "sgm_match_win")
         return disp_int, disp_sub
 
     def match(self, left, right, d_lo=None, disp_int=None, disp_sub=None, subpixel=True,

@@ -1,0 +1,89 @@
+"""Per-pixel-window SGM (absolute disparity) and the 4x4 downsample
+against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_10802_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+N, R, P1, P2 = 7, 8, 10, 120
+
+
+@pytest.fixture(scope="module")
+def sgm():
+    import torch
+    from paper_2012_10802_amd import sgm as mod
+    assert torch.cuda.is_available()
+    return mod
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _lo_maps(H, W, D, w, seed):
+    rng = np.random.default_rng(seed)
+    smooth = np.clip((np.arange(W)[None, :] * 0.05 + np.arange(H)[:, None] * 0.3 + 2).astype(np.int32),
+                     0, D - w)
+    jumpy = smooth.copy()
+    jumpy[rng.random((H, W)) < 0.1] = rng.integers(0, D - w + 1)  # large jumps, no overlap
+    noisy = np.clip(smooth + rng.integers(-3, 4, size=(H, W)), 0, D - w).astype(np.int32)
+    return {"smooth": smooth, "jumpy": jumpy, "noisy": noisy,
+            "uniform": rng.integers(0, D - w + 1, size=(H, W)).astype(np.int32)}
+
+
+@pytest.mark.parametrize("shape", [(67, 29, 16), (130, 41, 16), (45, 17, 12), (33, 70, 5)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_window_cost_paths_and_selection(sgm, shape):
+    import torch
+    W, H, w = shape
+    rng = np.random.default_rng(W)
+    L = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+    Rm = np.clip(np.roll(L, -6, axis=1).astype(int) + rng.integers(-2, 3, size=(H, W)), 0, 255).astype(np.uint8)
+    m = sgm.Matcher(W, H, census=N, ndisp=w, npaths=R, p1=P1, p2=P2)
+    cl, cr = oracle.census(L, N), oracle.census(Rm, N)
+    for name, lo in _lo_maps(H, W, 48, w, W + H).items():
+        lod = _dev(lo)
+        cost = m.cost_win(_dev(L), _dev(Rm), lod)
+        paths = m.aggregate_win_paths(cost, lod)
+        di, ds = m.wta_win_paths(paths, lod)
+        mi, ms = m.match_win(_dev(L), _dev(Rm), lod)
+        torch.cuda.synchronize()
+        want_c = oracle.cost_win(cl, cr, N, w, lo)
+        np.testing.assert_array_equal(cost.cpu().numpy(), want_c, err_msg=name)
+        for r in range(R):
+            np.testing.assert_array_equal(m.path_volume(paths, r).cpu().numpy(),
+                                          oracle.path_win(want_c, lo, r, P1, P2), err_msg="%s path %d" % (name, r))
+        wi, ws = oracle.sgm_win(L, Rm, N, w, R, P1, P2, lo)
+        for a, b in ((di, ds), (mi, ms)):
+            np.testing.assert_array_equal(a.cpu().numpy().view(np.uint16), wi, err_msg=name)
+            np.testing.assert_array_equal(b.cpu().numpy(), ws, err_msg=name)
+
+
+def test_window_road1920_full_frame(sgm):
+    """1920x1080 road pair, 16-wide windows centred on the true disparity
+    (with noise): every output equals the oracle's."""
+    import torch
+    p = synth.make_pair(synth.scene_for_config("road1920", 5000), 5000)
+    H, W = p.left.shape
+    rng = np.random.default_rng(3)
+    lo = np.clip(np.rint(p.gt).astype(np.int32) - 8 + rng.integers(-2, 3, size=(H, W)), 0, 192 - 16)
+    lo = lo.astype(np.int32)
+    m = sgm.Matcher(W, H, census=N, ndisp=16, npaths=R, p1=P1, p2=P2)
+    di, ds = m.match_win(_dev(p.left), _dev(p.right), _dev(lo))
+    torch.cuda.synchronize()
+    wi, ws = oracle.sgm_win(p.left, p.right, N, 16, R, P1, P2, lo)
+    np.testing.assert_array_equal(di.cpu().numpy().view(np.uint16), wi)
+    np.testing.assert_array_equal(ds.cpu().numpy(), ws)
+
+
+def test_downsample4(sgm):
+    import torch
+    for H, W in [(1080, 1920), (37, 61), (4, 4)]:
+        img = np.random.default_rng(H).integers(0, 256, size=(H, W), dtype=np.uint8)
+        out = sgm.sgm_downsample4(_dev(img))
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), oracle.downsample4(img))
