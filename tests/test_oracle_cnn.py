@@ -1,0 +1,79 @@
+"""Pins of the CNN oracle: convolution against scipy's correlation,
+gradients against finite differences, Adam's first step in closed form,
+bfloat16 rounding on known values."""
+import numpy as np
+import pytest
+from scipy.signal import correlate
+
+from oracle import cnn
+
+
+def test_bf16_rounding_known_values():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9, -2.5, 0.0], np.float32)
+    got = cnn.bf16(vals)
+    # 1+2^-8 is a tie between 1 and 1+2^-7: even mantissa wins (1.0)
+    want = [1.0, 1.0, 1.0 + 2 ** -6, 1.0, -2.5, 0.0]
+    assert list(got) == want
+
+
+def test_conv_matches_scipy_correlate():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(2, 7, 9, cnn.CH))
+    W = rng.normal(size=(9, cnn.CH, cnn.CH))
+    b = rng.normal(size=cnn.CH)
+    out = cnn.conv3x3(x, W, b)
+    K = W.reshape(3, 3, cnn.CH, cnn.CH)  # [dy][dx][co][ci]
+    for n in range(2):
+        for co in range(cnn.CH):
+            ref = np.full((7, 9), b[co])
+            for ci in range(cnn.CH):
+                ref += correlate(x[n, :, :, ci], K[:, :, co, ci], mode="same", method="direct")
+            np.testing.assert_allclose(out[n, :, :, co], ref, rtol=1e-10, atol=1e-10)
+
+
+def _loss(params, x0, coarse, label):
+    _, out = cnn.forward(params, x0, rounding=False)
+    return cnn.loss_and_grad(out, coarse, label)[0]
+
+
+def test_backward_matches_finite_differences():
+    rng = np.random.default_rng(1)
+    H, W = 5, 6
+    params = rng.normal(scale=0.3, size=cnn.NPARAMS)
+    x0 = rng.normal(size=(1, H, W, cnn.CH))
+    coarse = rng.uniform(0, 4, size=(1, H, W))
+    label = coarse + rng.normal(scale=1.5, size=(1, H, W))
+    acts, out = cnn.forward(params, x0, rounding=False)
+    _, dout = cnn.loss_and_grad(out, coarse, label)
+    g = cnn.backward(params, x0, acts, dout, rounding=False)
+    idx = rng.choice(cnn.NPARAMS, size=40, replace=False)
+    idx = np.concatenate([idx, [3 * cnn.PER_LAYER - 1, cnn.NPARAMS - 1]])  # biases too
+    h = 1e-6
+    for i in idx:
+        pp, pm = params.copy(), params.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (_loss(pp, x0, coarse, label) - _loss(pm, x0, coarse, label)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 + 1e-4 * abs(fd), (i, fd, g[i])
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    p, m, v = cnn.adam(np.zeros(4), np.zeros(4), np.zeros(4), g, 1, lr=0.01, eps=1e-12)
+    np.testing.assert_allclose(p[:3], -0.01 * np.sign(g[:3]), rtol=1e-6)
+    assert p[3] == 0.0
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_window_map_fallback_and_clamps():
+    coarse = np.array([[2.0, 10.25], [0.1, 47.9]], np.float32)
+    out = np.zeros((1, 2, 2, cnn.CH), np.float32)
+    out[0, :, :, 0] = [[1.0, -0.5], [0.0, 3.0]]
+    out[0, :, :, 1] = [[5.0, -5.0], [5.0, 5.0]]
+    lo, nfb = cnn.window_map(coarse, out, 8, 8, 192, 16, 0.0)
+    assert nfb == 4 * 4  # one coarse pixel of four falls back, 16 full pixels
+    assert lo[0, 0] == 4 * 3 - 8           # confident: 4 * (2 + 1) = 12 -> 4
+    assert lo[0, 4] == 41 - 8              # fallback: 4 * 10.25 = 41
+    assert lo[4, 0] == 0                   # clamped below
+    assert lo[4, 4] == 192 - 16            # 4 * 50.9 -> clamped above
