@@ -187,6 +187,64 @@ sgm_status sgm_downsample4(const uint8_t *image, int32_t width, int32_t height, 
                            uint8_t *out, void *stream);
 
 /* ------------------------------------------------------------------------
+ * The search-window network (learned-window form) and its training.
+ *
+ * Four 3x3 convolutions with 16 channels, zero padding, ReLU after the
+ * first three; bfloat16 weights and activations, float32 accumulation on
+ * the matrix cores.  It runs on the quarter-resolution level: input channel
+ * 0 = coarse disparity / 16, channel 1 = coarse left intensity / 255 - 1/2,
+ * channels 2..15 zero; output channel 0 = window-centre offset (coarse
+ * pixels), channel 1 = confidence logit.  The window centre of a full-
+ * resolution pixel is 4 * (coarse + offset) where the logit reaches the
+ * threshold, and 4 * coarse (the full-range SGM estimate) elsewhere.
+ *
+ * Buffers (all device, caller-owned; n images of W x H at a time):
+ *   params  float32 [sgm_cnn_num_params()]: per layer W[tap][co][ci], b[co],
+ *           tap = (dy + 1) * 3 + (dx + 1)
+ *   wf, wb  bfloat16 [4][9][16][16]: weights as [tap][co][ci] and
+ *           [tap][ci][co] (written by sgm_cnn_pack_weights / sgm_cnn_adam)
+ *   x0      bfloat16 NHWC [n][H][W][16] network input
+ *   acts    bfloat16 [3][n][H][W][16] hidden activations (forward output,
+ *           backward input)
+ *   out     float32 NHWC [n][H][W][16] network output
+ *   dy      bfloat16 NHWC [n][H][W][16] loss gradient w.r.t. out
+ * Activations and dy must be 16-byte aligned.  Weight gradients are reduced
+ * in a fixed order, so training is bitwise reproducible.
+ */
+int32_t sgm_cnn_num_params(void);
+size_t sgm_cnn_scratch_bytes(int32_t width, int32_t height, int32_t nimg);
+sgm_status sgm_cnn_pack_weights(const float *params, uint16_t *wf, uint16_t *wb, void *stream);
+sgm_status sgm_cnn_prepare_input(const float *coarse_disp, const uint8_t *coarse_left, int32_t width,
+                                 int32_t height, int32_t nimg, uint16_t *x0, void *stream);
+sgm_status sgm_cnn_forward(const uint16_t *wf, const float *params, const uint16_t *x0, int32_t width,
+                           int32_t height, int32_t nimg, uint16_t *acts, float *out, void *stream);
+/* Loss = mean over pixels of Huber(offset - (label - coarse)) + logistic
+ * loss of the logit against [|offset - (label - coarse)| < 1]; writes dy
+ * and adds the two loss terms to loss_sum[0..1] (may be NULL). */
+sgm_status sgm_cnn_loss(const float *out, const float *coarse_disp, const float *label, int32_t width,
+                        int32_t height, int32_t nimg, uint16_t *dy, float *loss_sum, void *stream);
+/* Parameter gradient (float32 [num_params]) of the loss given dy. */
+sgm_status sgm_cnn_backward(const uint16_t *wb, const uint16_t *x0, const uint16_t *acts,
+                            const uint16_t *dy, int32_t width, int32_t height, int32_t nimg,
+                            float *grad, void *scratch, size_t scratch_bytes, void *stream);
+/* One bias-corrected Adam step (step >= 1) on params with moments m, v;
+ * refreshes wf and wb. */
+sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
+                        float beta1, float beta2, float eps, uint16_t *wf, uint16_t *wb, void *stream);
+/* Per-pixel window starts lo (int32 [H][W]) of width w for a full-range
+ * search of ndisp disparities: lo = clamp(floor(centre + 1/2) - w/2, 0,
+ * ndisp - w), full pixel (x, y) reading coarse pixel (min(x/4, Wc-1),
+ * min(y/4, Hc-1)).  nfallback (may be NULL) counts pixels that fell back. */
+sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_t coarse_width,
+                          int32_t coarse_height, int32_t width, int32_t height, int32_t ndisp,
+                          int32_t w, float conf_logit_threshold, int32_t *lo, uint32_t *nfallback,
+                          void *stream);
+/* Training target at the coarse level: mean of each 4 x 4 block of a full-
+ * resolution disparity map, divided by 4 (coarse pixels). */
+sgm_status sgm_label_downsample4(const float *label, int32_t width, int32_t height, float *coarse,
+                                 void *stream);
+
+/* ------------------------------------------------------------------------
  * Batches: many pairs, of several sizes, matched together.
  *
  * A batch fixes the pairs (sizes and device buffers) at plan time.  A run

@@ -1,0 +1,449 @@
+// The search-window network of the learned-window form: four 3x3
+// convolutions, 16 channels, zero padding, ReLU after the first three,
+// bfloat16 weights and activations with float32 accumulation on the matrix
+// cores (v_mfma_f32_16x16x16bf16_1k), plus its hand-written training
+// kernels (loss, input and weight gradients, Adam) and the window map that
+// turns its output into per-pixel search windows.
+//
+// Implicit GEMM: a wave owns 16 consecutive pixels of one row (the M
+// dimension) and all 16 output channels (N); the reduction runs over the 9
+// taps x 16 input channels as 9 MFMA steps of K = 16.  Activations are
+// NHWC [n][H][W][16] bfloat16, so a lane's 4 input channels of one pixel
+// are one 8-byte load.
+//
+// Operand layout of v_mfma_f32_16x16x16bf16_1k used here (lane l, g = l/16):
+//   A[i][k]: i = l % 16, k = 4g .. 4g+3      (4 bf16 in one 64-bit register)
+//   B[k][j]: j = l % 16, k = 4g .. 4g+3
+//   D[i][j]: j = l % 16, i = 4g + r for accumulator element r = 0..3.
+//
+// Weight-gradient sums run over pixels; each wave writes its partial sums
+// and a second kernel adds the partials in wave order, so the gradient is
+// bitwise reproducible.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include "../../include/sgm.h"
+#include "sgm_internal.h"
+
+namespace sgm {
+namespace {
+
+constexpr int CH = 16;
+constexpr int LAYERS = 4;
+constexpr int PER_LAYER = 9 * CH * CH + CH;
+constexpr int NPARAMS = LAYERS * PER_LAYER;
+constexpr int kWgradWaves = 1024;
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16, round to nearest even
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ v4s load4(const uint16_t *p)
+{
+    const uint2 t = *reinterpret_cast<const uint2 *>(p);
+    v4s r;
+    r[0] = (short)(t.x & 0xFFFF);
+    r[1] = (short)(t.x >> 16);
+    r[2] = (short)(t.y & 0xFFFF);
+    r[3] = (short)(t.y >> 16);
+    return r;
+}
+
+// strip s of 16 pixels: image n, row y, first column x0
+struct Strip {
+    int n, y, x0;
+};
+__device__ __forceinline__ Strip strip_of(int s, int W, int H)
+{
+    const int sx = (W + 15) / 16;
+    Strip t;
+    t.x0 = (s % sx) * 16;
+    const int r = s / sx;
+    t.y = r % H;
+    t.n = r / H;
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// convolution forward (and input gradient): D[pixel][co] over 9 taps
+
+// MODE 0: hidden layer forward  (out = bf16(relu(conv + b)))
+// MODE 1: last layer forward    (out32 = conv + b, float)
+// MODE 2: input gradient        (dx = conv^T(dy); out = bf16(dx * [mask > 0]))
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ x, const uint16_t *__restrict__ wt,
+                                              const float *__restrict__ bias, const uint16_t *__restrict__ mask,
+                                              int W, int H, int nstrips, uint16_t *__restrict__ out,
+                                              float *__restrict__ out32)
+{
+    const int lane = threadIdx.x & 63;
+    const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (s >= nstrips) return;
+    const Strip st = strip_of(s, W, H);
+    const int i = lane & 15, g = lane >> 4;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        int dy = t / 3 - 1, dx = t % 3 - 1;
+        if (MODE == 2) {  // transpose: the gradient flows back from p - offset
+            dy = -dy;
+            dx = -dx;
+        }
+        const int yy = st.y + dy, xx = st.x0 + i + dx;
+        v4s a = {0, 0, 0, 0};
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+            a = load4(x + (((size_t)st.n * H + yy) * W + xx) * CH + 4 * g);
+        const v4s b = load4(wt + (size_t)t * CH * CH + (size_t)i * CH + 4 * g);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int xo = st.x0 + 4 * g + r;
+        if (xo >= W) continue;
+        const size_t o = (((size_t)st.n * H + st.y) * W + xo) * CH + i;
+        if (MODE == 0) {
+            out[o] = f2bf(fmaxf(acc[r] + bias[i], 0.0f));
+        } else if (MODE == 1) {
+            out32[o] = acc[r] + bias[i];
+        } else {
+            out[o] = f2bf(bf2f(mask[o]) > 0.0f ? acc[r] : 0.0f);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: per tap D[co][ci] = sum_p dy[p][co] x[p + offset][ci]
+
+__global__ __launch_bounds__(64) void k_wgrad(const uint16_t *__restrict__ x, const uint16_t *__restrict__ dy, int W,
+                                              int H, int nstrips, float *__restrict__ partial)
+{
+    const int lane = threadIdx.x;
+    const int wave = blockIdx.x;
+    const int i = lane & 15, g = lane >> 4;
+    v4f acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = (v4f){0.f, 0.f, 0.f, 0.f};
+    float dbias = 0.0f;
+    for (int s = wave; s < nstrips; s += gridDim.x) {
+        const Strip st = strip_of(s, W, H);
+        // A[co][k]: dy of pixels x0 + 4g .. 4g+3, channel co = i
+        v4s a;
+        const size_t rowb = ((size_t)st.n * H + st.y) * W;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int xk = st.x0 + 4 * g + e;
+            const uint16_t v = xk < W ? dy[(rowb + xk) * CH + i] : (uint16_t)0;
+            a[e] = (short)v;
+            dbias += bf2f(v);
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ddy = t / 3 - 1, ddx = t % 3 - 1;
+            const int yy = st.y + ddy;
+            v4s b;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int xk = st.x0 + 4 * g + e, xx = xk + ddx;
+                uint16_t v = 0;
+                if (xk < W && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    v = x[(((size_t)st.n * H + yy) * W + xx) * CH + i];
+                b[e] = (short)v;
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+    }
+    // partial layout per wave: [tap][co][ci] then bias partials [group][co]
+    float *p = partial + (size_t)wave * (9 * CH * CH + 4 * CH);
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p[(size_t)t * CH * CH + (4 * g + r) * CH + i] = acc[t][r];
+    p[9 * CH * CH + g * CH + i] = dbias;
+}
+
+// sum of the per-wave partials, in wave order
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ partial, int nwaves,
+                                                      float *__restrict__ grad)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= PER_LAYER) return;
+    const int stride = 9 * CH * CH + 4 * CH;
+    float sum = 0.0f;
+    if (k < 9 * CH * CH) {
+        for (int wv = 0; wv < nwaves; ++wv) sum += partial[(size_t)wv * stride + k];
+    } else {
+        const int co = k - 9 * CH * CH;
+        for (int wv = 0; wv < nwaves; ++wv)
+            for (int g = 0; g < 4; ++g) sum += partial[(size_t)wv * stride + 9 * CH * CH + g * CH + co];
+    }
+    grad[k] = sum;
+}
+
+// ---------------------------------------------------------------------------
+// input, loss, optimiser, window map
+
+__global__ void k_prepare_input(const float *__restrict__ coarse, const uint8_t *__restrict__ left, int npix,
+                                uint16_t *__restrict__ x0)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    uint16_t v[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) v[c] = 0;
+    v[0] = f2bf(__fdiv_rn(coarse[p], 16.0f));
+    v[1] = f2bf(__fsub_rn(__fdiv_rn((float)left[p], 255.0f), 0.5f));
+    uint4 *o = reinterpret_cast<uint4 *>(x0 + (size_t)p * CH);
+    o[0] = make_uint4(v[0] | (uint32_t)v[1] << 16, 0u, 0u, 0u);
+    o[1] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__global__ void k_loss(const float *__restrict__ out, const float *__restrict__ coarse, const float *__restrict__ label,
+                       int npix, uint16_t *__restrict__ dy, float *__restrict__ loss_sum)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const float invn = 1.0f / (float)npix;
+    const float off = out[(size_t)p * CH], logit = out[(size_t)p * CH + 1];
+    const float e = off - (label[p] - coarse[p]);
+    const float ae = fabsf(e);
+    const float c = ae < 1.0f ? 1.0f : 0.0f;
+    const float huber = ae <= 1.0f ? 0.5f * e * e : ae - 0.5f;
+    const float bce = fmaxf(logit, 0.0f) - c * logit + log1pf(expf(-fabsf(logit)));
+    uint16_t g[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) g[k] = 0;
+    g[0] = f2bf(fminf(fmaxf(e, -1.0f), 1.0f) * invn);
+    g[1] = f2bf((1.0f / (1.0f + expf(-logit)) - c) * invn);
+    uint4 *o = reinterpret_cast<uint4 *>(dy + (size_t)p * CH);
+    o[0] = make_uint4(g[0] | (uint32_t)g[1] << 16, 0u, 0u, 0u);
+    o[1] = make_uint4(0u, 0u, 0u, 0u);
+    if (loss_sum) {
+        atomicAdd(loss_sum, huber * invn);
+        atomicAdd(loss_sum + 1, bce * invn);
+    }
+}
+
+// Adam on the float32 master parameters; also refreshes the bfloat16
+// weights in the forward ([tap][co][ci]) and transposed ([tap][ci][co])
+// layouts.
+__global__ void k_adam(float *__restrict__ params, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ grad, float lr, float b1, float b2, float eps, float c1, float c2,
+                       int update, uint16_t *__restrict__ wf, uint16_t *__restrict__ wb)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= NPARAMS) return;
+    float p = params[k];
+    if (update) {
+        const float gk = grad[k];
+        const float mk = b1 * m[k] + (1.0f - b1) * gk;
+        const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+        m[k] = mk;
+        v[k] = vk;
+        p = p - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+        params[k] = p;
+    }
+    const int l = k / PER_LAYER, r = k % PER_LAYER;
+    if (r < 9 * CH * CH) {
+        const int t = r / (CH * CH), co = (r / CH) % CH, ci = r % CH;
+        const size_t base = (size_t)l * 9 * CH * CH + (size_t)t * CH * CH;
+        wf[base + co * CH + ci] = f2bf(p);
+        wb[base + ci * CH + co] = f2bf(p);
+    }
+}
+
+__global__ void k_window_map(const float *__restrict__ coarse, const float *__restrict__ out, int Wc, int Hc, int W,
+                             int H, int D, int w, float thr, int32_t *__restrict__ lo, uint32_t *__restrict__ nfallback)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= W) return;
+    const int cx = min(x / 4, Wc - 1), cy = min(y / 4, Hc - 1);
+    const size_t cp = (size_t)cy * Wc + cx;
+    const float cd = coarse[cp];
+    const float logit = out[cp * CH + 1];
+    const bool conf = logit >= thr;
+    const float centre = 4.0f * (conf ? __fadd_rn(cd, out[cp * CH]) : cd);
+    int l = (int)floorf(__fadd_rn(centre, 0.5f)) - w / 2;
+    l = min(max(l, 0), D - w);
+    lo[(size_t)y * W + x] = l;
+    if (nfallback && !conf) atomicAdd(nfallback, 1u);
+}
+
+__global__ void k_label_downsample4(const float *__restrict__ full, int W, int H, float *__restrict__ coarse)
+{
+    const int Wc = W / 4, Hc = H / 4;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= Wc || y >= Hc) return;
+    float s = 0.0f;
+    for (int dy = 0; dy < 4; ++dy)
+        for (int dx = 0; dx < 4; ++dx) s += full[(size_t)(4 * y + dy) * W + 4 * x + dx];
+    coarse[(size_t)y * Wc + x] = s * (1.0f / 64.0f);  // mean of the block, in coarse pixels
+}
+
+sgm_status cfail(sgm_status st, const char *msg)
+{
+    snprintf(error_buffer(), kErrorBufferSize, "%s", msg);
+    return st;
+}
+
+sgm_status launched(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return SGM_OK;
+    snprintf(error_buffer(), kErrorBufferSize, "%s: %s", what, hipGetErrorString(e));
+    return SGM_ERR_HIP;
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+}  // namespace
+}  // namespace sgm
+
+using namespace sgm;
+
+extern "C" {
+
+int32_t sgm_cnn_num_params(void) { return NPARAMS; }
+
+size_t sgm_cnn_scratch_bytes(int32_t width, int32_t height, int32_t nimg)
+{
+    if (width < 1 || height < 1 || nimg < 1) return 0;
+    const size_t act = (size_t)nimg * height * width * CH * 2;
+    return 2 * ((act + 255) & ~(size_t)255) + (size_t)kWgradWaves * (9 * CH * CH + 4 * CH) * 4;
+}
+
+sgm_status sgm_cnn_pack_weights(const float *params, uint16_t *wf, uint16_t *wb, void *stream)
+{
+    if (!params || !wf || !wb) return cfail(SGM_ERR_INVALID, "params, wf and wb must not be NULL");
+    hipLaunchKernelGGL(k_adam, dim3((NPARAMS + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       const_cast<float *>(params), nullptr, nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f, 0, wf,
+                       wb);
+    return launched("pack weights");
+}
+
+sgm_status sgm_cnn_prepare_input(const float *coarse_disp, const uint8_t *coarse_left, int32_t width, int32_t height,
+                                 int32_t nimg, uint16_t *x0, void *stream)
+{
+    if (!coarse_disp || !coarse_left || !x0) return cfail(SGM_ERR_INVALID, "NULL buffer");
+    if (width < 1 || height < 1 || nimg < 1) return cfail(SGM_ERR_INVALID, "bad size");
+    if (!aligned(x0, 16)) return cfail(SGM_ERR_INVALID, "x0 must be 16-byte aligned");
+    const int npix = width * height * nimg;
+    hipLaunchKernelGGL(k_prepare_input, dim3((npix + 255) / 256), dim3(256), 0, (hipStream_t)stream, coarse_disp,
+                       coarse_left, npix, x0);
+    return launched("prepare input");
+}
+
+sgm_status sgm_cnn_forward(const uint16_t *wf, const float *params, const uint16_t *x0, int32_t width, int32_t height,
+                           int32_t nimg, uint16_t *acts, float *out, void *stream)
+{
+    if (!wf || !params || !x0 || !acts || !out) return cfail(SGM_ERR_INVALID, "NULL buffer");
+    if (width < 1 || height < 1 || nimg < 1) return cfail(SGM_ERR_INVALID, "bad size");
+    if (!aligned(x0, 8) || !aligned(acts, 8) || !aligned(wf, 8)) return cfail(SGM_ERR_INVALID, "misaligned buffer");
+    const size_t act = (size_t)nimg * height * width * CH;
+    const int nstrips = nimg * height * ((width + 15) / 16);
+    dim3 grid((nstrips + 3) / 4), block(256);
+    hipStream_t s = (hipStream_t)stream;
+    const uint16_t *in = x0;
+    for (int l = 0; l < LAYERS; ++l) {
+        const uint16_t *wl = wf + (size_t)l * 9 * CH * CH;
+        const float *bl = params + (size_t)l * PER_LAYER + 9 * CH * CH;
+        if (l < LAYERS - 1) {
+            uint16_t *o = acts + (size_t)l * act;
+            hipLaunchKernelGGL(k_conv<0>, grid, block, 0, s, in, wl, bl, nullptr, width, height, nstrips, o, nullptr);
+            in = o;
+        } else {
+            hipLaunchKernelGGL(k_conv<1>, grid, block, 0, s, in, wl, bl, nullptr, width, height, nstrips, nullptr,
+                               out);
+        }
+    }
+    return launched("cnn forward");
+}
+
+sgm_status sgm_cnn_loss(const float *out, const float *coarse_disp, const float *label, int32_t width, int32_t height,
+                        int32_t nimg, uint16_t *dy, float *loss_sum, void *stream)
+{
+    if (!out || !coarse_disp || !label || !dy) return cfail(SGM_ERR_INVALID, "NULL buffer");
+    if (width < 1 || height < 1 || nimg < 1) return cfail(SGM_ERR_INVALID, "bad size");
+    if (!aligned(dy, 16)) return cfail(SGM_ERR_INVALID, "dy must be 16-byte aligned");
+    const int npix = width * height * nimg;
+    hipLaunchKernelGGL(k_loss, dim3((npix + 255) / 256), dim3(256), 0, (hipStream_t)stream, out, coarse_disp, label,
+                       npix, dy, loss_sum);
+    return launched("cnn loss");
+}
+
+sgm_status sgm_cnn_backward(const uint16_t *wb, const uint16_t *x0, const uint16_t *acts, const uint16_t *dy_out,
+                            int32_t width, int32_t height, int32_t nimg, float *grad, void *scratch,
+                            size_t scratch_bytes, void *stream)
+{
+    if (!wb || !x0 || !acts || !dy_out || !grad || !scratch) return cfail(SGM_ERR_INVALID, "NULL buffer");
+    if (width < 1 || height < 1 || nimg < 1) return cfail(SGM_ERR_INVALID, "bad size");
+    if (scratch_bytes < sgm_cnn_scratch_bytes(width, height, nimg))
+        return cfail(SGM_ERR_WORKSPACE, "scratch smaller than sgm_cnn_scratch_bytes");
+    if (!aligned(scratch, 256)) return cfail(SGM_ERR_INVALID, "scratch must be 256-byte aligned");
+    const size_t act = (size_t)nimg * height * width * CH;
+    const size_t act_bytes = (act * 2 + 255) & ~(size_t)255;
+    uint16_t *dyA = static_cast<uint16_t *>(scratch);
+    uint16_t *dyB = reinterpret_cast<uint16_t *>(static_cast<uint8_t *>(scratch) + act_bytes);
+    float *partial = reinterpret_cast<float *>(static_cast<uint8_t *>(scratch) + 2 * act_bytes);
+    const int nstrips = nimg * height * ((width + 15) / 16);
+    const int nw = nstrips < kWgradWaves ? nstrips : kWgradWaves;
+    hipStream_t s = (hipStream_t)stream;
+    const uint16_t *dy = dy_out;
+    for (int l = LAYERS - 1; l >= 0; --l) {
+        const uint16_t *xin = l == 0 ? x0 : acts + (size_t)(l - 1) * act;
+        hipLaunchKernelGGL(k_wgrad, dim3(nw), dim3(64), 0, s, xin, dy, width, height, nstrips, partial);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((PER_LAYER + 255) / 256), dim3(256), 0, s, partial, nw,
+                           grad + (size_t)l * PER_LAYER);
+        if (l > 0) {
+            uint16_t *dnext = (l % 2) ? dyA : dyB;
+            hipLaunchKernelGGL(k_conv<2>, dim3((nstrips + 3) / 4), dim3(256), 0, s, dy, wb + (size_t)l * 9 * CH * CH,
+                               nullptr, xin, width, height, nstrips, dnext, nullptr);
+            dy = dnext;
+        }
+    }
+    return launched("cnn backward");
+}
+
+sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr, float beta1,
+                        float beta2, float eps, uint16_t *wf, uint16_t *wb, void *stream)
+{
+    if (!params || !m || !v || !grad || !wf || !wb) return cfail(SGM_ERR_INVALID, "NULL buffer");
+    if (step < 1) return cfail(SGM_ERR_INVALID, "step must be >= 1");
+    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((NPARAMS + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, m, v, grad,
+                       lr, beta1, beta2, eps, c1, c2, 1, wf, wb);
+    return launched("cnn adam");
+}
+
+sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_t coarse_width, int32_t coarse_height,
+                          int32_t width, int32_t height, int32_t ndisp, int32_t w, float conf_logit_threshold,
+                          int32_t *lo, uint32_t *nfallback, void *stream)
+{
+    if (!coarse_disp || !cnn_out || !lo) return cfail(SGM_ERR_INVALID, "NULL buffer");
+    if (coarse_width < 1 || coarse_height < 1 || width < 1 || height < 1 || w < 1 || w > ndisp || ndisp > 256)
+        return cfail(SGM_ERR_INVALID, "bad size");
+    dim3 grid((width + 255) / 256, height), block(256);
+    hipLaunchKernelGGL(k_window_map, grid, block, 0, (hipStream_t)stream, coarse_disp, cnn_out, coarse_width,
+                       coarse_height, width, height, ndisp, w, conf_logit_threshold, lo, nfallback);
+    return launched("window map");
+}
+
+sgm_status sgm_label_downsample4(const float *label, int32_t width, int32_t height, float *coarse, void *stream)
+{
+    if (!label || !coarse) return cfail(SGM_ERR_INVALID, "NULL buffer");
+    if (width < 4 || height < 4) return cfail(SGM_ERR_INVALID, "need width, height >= 4");
+    dim3 grid((width / 4 + 255) / 256, height / 4), block(256);
+    hipLaunchKernelGGL(k_label_downsample4, grid, block, 0, (hipStream_t)stream, label, width, height, coarse);
+    return launched("label downsample");
+}
+
+}  // extern "C"

@@ -81,6 +81,15 @@ def _load_library():
         "sgm_aggregate_win_paths": [P, P, P, P, S, P],
         "sgm_wta_win_paths": [P, P, P, P, P, P],
         "sgm_match_win": [P, P, P, I, P, P, P, P, S, P],
+        "sgm_cnn_pack_weights": [P, P, P, P],
+        "sgm_cnn_prepare_input": [P, P, I, I, I, P, P],
+        "sgm_cnn_forward": [P, P, P, I, I, I, P, P, P],
+        "sgm_cnn_loss": [P, P, P, I, I, I, P, P, P],
+        "sgm_cnn_backward": [P, P, P, P, I, I, I, P, P, S, P],
+        "sgm_cnn_adam": [P, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                         ctypes.c_float, P, P, P],
+        "sgm_window_map": [P, P, I, I, I, I, I, I, ctypes.c_float, P, P, P],
+        "sgm_label_downsample4": [P, I, I, P, P],
         "sgm_batch_plan": [ctypes.POINTER(sgm_batch_params), ctypes.POINTER(sgm_pair), I,
                            ctypes.POINTER(P)],
         "sgm_batch_free": [P],
@@ -99,6 +108,10 @@ def _load_library():
         f.argtypes = args
         f.restype = ctypes.c_int
     lib.sgm_plan_free.restype = None
+    lib.sgm_cnn_num_params.argtypes = []
+    lib.sgm_cnn_num_params.restype = ctypes.c_int32
+    lib.sgm_cnn_scratch_bytes.argtypes = [I, I, I]
+    lib.sgm_cnn_scratch_bytes.restype = ctypes.c_size_t
     lib.sgm_batch_free.restype = None
     lib.sgm_status_str.restype = ctypes.c_char_p
     lib.sgm_last_error.restype = ctypes.c_char_p

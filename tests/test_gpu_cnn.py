@@ -1,0 +1,311 @@
+"""Search-window network kernels (forward, loss, backward, Adam, window map)
+against the numpy oracle, plus the learned-window pipeline step by step.
+
+Floating-point bar: the GPU rounds the same operands to bfloat16 as the
+oracle and accumulates in float32, so a float32 result may differ from the
+oracle's float64 sum by the accumulation error, bounded here by
+K * 2^-22 * (the same sum over absolute values) for K = 144 products per
+output; a bfloat16 result may in addition sit one bfloat16 step (2^-7
+relative) away where the exact value lies near a rounding boundary.  Weight
+gradients are sums over every pixel: bounded relative to their absolute
+sums (2e-3, far below the O(1) error of any wrong index).  Integer results
+(window starts, fallback counts, disparities) are exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cnn as ocnn
+from paper_2012_10802_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CH = 16
+
+
+@pytest.fixture(scope="module")
+def lw():
+    import torch
+    from paper_2012_10802_amd import learned_window as mod
+    assert torch.cuda.is_available()
+    return mod
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _bf16_bits_to_f(t):
+    a = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return a.view(np.float32).astype(np.float64)
+
+
+def _params(seed):
+    from paper_2012_10802_amd import learned_window as mod
+    rng = np.random.default_rng(seed)
+    p = mod.init_params(seed).astype(np.float64)
+    per = ocnn.PER_LAYER
+    for l in range(4):  # non-zero biases, last layer at full scale
+        p[l * per + 9 * CH * CH: (l + 1) * per] = rng.normal(0, 0.1, CH)
+    p[3 * per: 3 * per + 9 * CH * CH] *= 10
+    return p.astype(np.float32)
+
+
+def _input(n, H, W, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((n, H, W, CH))
+    x[..., 0] = rng.uniform(0, 4, (n, H, W))
+    x[..., 1] = rng.uniform(-0.5, 0.5, (n, H, W))
+    return ocnn.bf16(x)
+
+
+def _to_bf16_dev(x):
+    u = np.ascontiguousarray(np.asarray(x, np.float32)).view(np.uint32) >> 16
+    return _dev(u.astype(np.uint16).view(np.int16))
+
+
+def _ulp_bf16(x):
+    ax = np.maximum(np.abs(x), 1e-30)
+    return 2.0 ** (np.floor(np.log2(ax)) - 7)
+
+
+def _abs_conv(x, W, b):
+    return ocnn.conv3x3(np.abs(x), np.abs(W), np.abs(b))
+
+
+SHAPES = [(1, 5, 16), (2, 13, 37), (1, 9, 70)]  # several strips, ragged tails
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_forward_layerwise(lw, shape):
+    """Each layer, fed the GPU's own previous activation, against the oracle."""
+    import torch
+    n, H, W = shape
+    params = _params(n * 100 + W)
+    x0 = _input(n, H, W, W)
+    net = lw.WindowNet(params)
+    acts, out = net.buffers(W, H, n)
+    net.forward(_to_bf16_dev(x0), acts, out, W, H, n)
+    torch.cuda.synchronize()
+    Ws, bs = ocnn.unpack(params)
+    x = x0
+    for l in range(4):
+        want = ocnn.conv3x3(x, ocnn.bf16(Ws[l]), bs[l])
+        mag = _abs_conv(x, ocnn.bf16(Ws[l]), bs[l])
+        tol = 144 * 2.0 ** -21 * mag + 1e-30
+        if l < 3:
+            got = _bf16_bits_to_f(acts[l])
+            r = np.maximum(want, 0)
+            err = np.abs(got - r)
+            assert np.all(err <= tol + _ulp_bf16(r) * (r > 0)), "layer %d max err %g" % (l, err.max())
+            assert np.mean(got == ocnn.bf16(r)) > 0.99
+            x = got
+        else:
+            got = out.cpu().numpy().astype(np.float64)
+            err = np.abs(got - want)
+            assert np.all(err <= tol), "output max err %g" % err.max()
+
+
+def test_forward_end_to_end_matches_oracle(lw):
+    import torch
+    n, H, W = 2, 11, 45
+    params = _params(7)
+    x0 = _input(n, H, W, 3)
+    net = lw.WindowNet(params)
+    acts, out = net.buffers(W, H, n)
+    net.forward(_to_bf16_dev(x0), acts, out, W, H, n)
+    torch.cuda.synchronize()
+    _, want = ocnn.forward(params, x0)
+    got = out.cpu().numpy()
+    scale = np.abs(want).max()
+    assert np.abs(got - want).max() <= 0.02 * scale
+
+
+def test_prepare_input_and_label_downsample(lw):
+    import torch
+    rng = np.random.default_rng(5)
+    Hc, Wc = 9, 23
+    cd = rng.uniform(0, 48, (Hc, Wc)).astype(np.float32)
+    cl = rng.integers(0, 256, (Hc, Wc), dtype=np.uint8)
+    x0 = lw.prepare_input(_dev(cd), _dev(cl), Wc, Hc, 1)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_bf16_bits_to_f(x0), ocnn.bf16(ocnn.prepare_input(cd, cl)))
+    full = rng.uniform(0, 190, (4 * Hc + 2, 4 * Wc + 3)).astype(np.float32)
+    got = lw.label_downsample4(_dev(full)).cpu().numpy()
+    blocks = full[:4 * Hc, :4 * Wc].reshape(Hc, 4, Wc, 4).astype(np.float64)
+    want = blocks.mean(axis=(1, 3)) / 4.0  # mean disparity in coarse pixels
+    np.testing.assert_allclose(got, want, rtol=1e-6, atol=1e-5)
+
+
+def test_loss_gradient(lw):
+    import torch
+    from paper_2012_10802_amd import sgm as S
+    rng = np.random.default_rng(9)
+    n, H, W = 1, 10, 33
+    out = rng.normal(0, 2, (n, H, W, CH)).astype(np.float32)
+    # multiples of 1/64: label - coarse is exact in float32 on both sides
+    coarse = (rng.integers(0, 40 * 64, (H, W)) / 64.0).astype(np.float32)
+    label = (coarse + rng.integers(-96, 97, (H, W)) / 64.0).astype(np.float32)
+    dy = torch.empty((n, H, W, CH), dtype=torch.int16, device="cuda")
+    loss = torch.zeros(2, dtype=torch.float32, device="cuda")
+    S._check(S.library().sgm_cnn_loss(lw._c(_dev(out)), lw._c(_dev(coarse)), lw._c(_dev(label)), W, H, n,
+                                      lw._c(dy), lw._c(loss), S._stream()), "sgm_cnn_loss")
+    torch.cuda.synchronize()
+    want_loss, g = ocnn.loss_and_grad(out, coarse[None], label[None])
+    got = _bf16_bits_to_f(dy)
+    wb = ocnn.bf16(g)
+    assert np.all(np.abs(got - wb) <= _ulp_bf16(g) + 1e-30)
+    assert np.all(got[..., 2:] == 0)
+    np.testing.assert_allclose(float(loss.sum()), want_loss, rtol=1e-4)
+
+
+@pytest.mark.parametrize("shape", [(1, 6, 20), (2, 13, 37)], ids=lambda s: "x".join(map(str, s)))
+def test_backward_gradients(lw, shape):
+    """Parameter gradient for a given output gradient, with the GPU's own
+    forward activations, against the oracle; and bitwise reproducible."""
+    import torch
+    n, H, W = shape
+    params = _params(W + 1)
+    x0 = _input(n, H, W, W + 2)
+    rng = np.random.default_rng(W + 3)
+    dout = np.zeros((n, H, W, CH))
+    dout[..., :2] = rng.normal(0, 1e-3, (n, H, W, 2))
+    dout = ocnn.bf16(dout)
+    net = lw.WindowNet(params)
+    bufs = net.train_buffers(W, H, n)
+    acts, out, _, scratch, _ = bufs
+    x0d = _to_bf16_dev(x0)
+    net.forward(x0d, acts, out, W, H, n)
+    S = lw.S
+    grads = []
+    for _ in range(2):
+        S._check(S.library().sgm_cnn_backward(lw._c(net.wb), lw._c(x0d), lw._c(acts), lw._c(_to_bf16_dev(dout)),
+                                              W, H, n, lw._c(net.grad), lw._c(scratch), scratch.numel(),
+                                              S._stream()), "sgm_cnn_backward")
+        torch.cuda.synchronize()
+        grads.append(net.grad.cpu().numpy().copy())
+    np.testing.assert_array_equal(grads[0], grads[1])
+    gacts = [_bf16_bits_to_f(acts[l]) for l in range(3)]
+    want = ocnn.backward(params, x0, gacts, dout)
+    mag = ocnn.backward(np.abs(params), np.abs(x0), gacts, np.abs(dout))
+    err = np.abs(grads[0] - want)
+    assert np.all(err <= 2e-3 * mag + 1e-30), "max rel err %g" % (err / np.maximum(mag, 1e-30)).max()
+    # the unused input channels of layer 0 get exactly zero gradient
+    W0 = grads[0][:9 * CH * CH].reshape(9, CH, CH)
+    assert np.all(W0[:, :, 2:] == 0)
+
+
+def test_adam_and_weight_packing(lw):
+    import torch
+    rng = np.random.default_rng(21)
+    params = _params(3)
+    net = lw.WindowNet(params)
+    m = rng.normal(0, 1e-3, params.shape).astype(np.float32)
+    v = rng.uniform(0, 1e-6, params.shape).astype(np.float32)
+    g = rng.normal(0, 1e-3, params.shape).astype(np.float32)
+    net.m.copy_(_dev(m))
+    net.v.copy_(_dev(v))
+    net.grad.copy_(_dev(g))
+    S = lw.S
+    step, lr = 7, 1e-3
+    S._check(S.library().sgm_cnn_adam(lw._c(net.params), lw._c(net.m), lw._c(net.v), lw._c(net.grad), step, lr,
+                                      0.9, 0.999, 1e-8, lw._c(net.wf), lw._c(net.wb), S._stream()), "adam")
+    torch.cuda.synchronize()
+    wp, wm, wv = ocnn.adam(params.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                           g.astype(np.float64), step, lr)
+    np.testing.assert_allclose(net.m.cpu().numpy(), wm, rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(net.v.cpu().numpy(), wv, rtol=1e-6, atol=1e-15)
+    np.testing.assert_allclose(net.params.cpu().numpy(), wp, rtol=1e-6, atol=lr * 1e-4)
+    # bfloat16 weight layouts: forward [tap][co][ci], transposed [tap][ci][co]
+    p = net.params.cpu().numpy()
+    Ws, _ = ocnn.unpack(p)
+    wf = _bf16_bits_to_f(net.wf).reshape(4, 9, CH, CH)
+    wb = _bf16_bits_to_f(net.wb).reshape(4, 9, CH, CH)
+    for l in range(4):
+        np.testing.assert_array_equal(wf[l], ocnn.bf16(Ws[l]))
+        np.testing.assert_array_equal(wb[l], ocnn.bf16(Ws[l]).transpose(0, 2, 1))
+
+
+def test_window_map_exact(lw):
+    import torch
+    rng = np.random.default_rng(4)
+    Hc, Wc, D, w = 17, 29, 192, 16
+    H, W = 4 * Hc + 3, 4 * Wc + 1  # ragged: last coarse row/column is reused
+    cd = rng.uniform(0, 48, (Hc, Wc)).astype(np.float32)
+    cd[0, :4] = [0.0, 47.9, 1.9, 2.125]  # clamps at both ends, a .5 tie
+    out = rng.normal(0, 1.5, (1, Hc, Wc, CH)).astype(np.float32)
+    for thr in (-1e30, 0.0, 0.7, 1e30):
+        nfb = torch.zeros(1, dtype=torch.int32, device="cuda")
+        lo = lw.window_map(_dev(cd), _dev(out), W, H, D, w, thr, nfallback=nfb)
+        torch.cuda.synchronize()
+        want, want_n = ocnn.window_map(cd, out, W, H, D, w, thr)
+        np.testing.assert_array_equal(lo.cpu().numpy(), want)
+        assert int(nfb.item()) == want_n
+
+
+def test_training_resume_is_bitwise(lw, tmp_path):
+    """N steps straight == N/2 steps, checkpoint, reload, N/2 steps; and
+    the loss goes down on a fixed batch."""
+    import torch
+    n, H, W = 2, 12, 40
+    rng = np.random.default_rng(8)
+    coarse = rng.uniform(2, 40, (n, H, W)).astype(np.float32)
+    label = (coarse + np.clip(rng.normal(0, 0.8, (n, H, W)), -3, 3)).astype(np.float32)
+    left = rng.integers(0, 256, (n, H, W), dtype=np.uint8)
+    x0 = torch.empty((n, H, W, CH), dtype=torch.int16, device="cuda")
+    for i in range(n):
+        lw.prepare_input(_dev(coarse[i]), _dev(left[i]), W, H, 1, x0[i])
+    cdev, ldev = _dev(coarse), _dev(label)
+
+    def run(net, steps):
+        bufs = net.train_buffers(W, H, n)
+        losses = []
+        for _ in range(steps):
+            loss = net.train_step(x0, cdev, ldev, W, H, n, 3e-3, bufs)
+            losses.append(float(loss.sum()))
+        return losses
+
+    a = lw.WindowNet(seed=1)
+    la = run(a, 20)
+    b = lw.WindowNet(seed=1)
+    run(b, 10)
+    ck = str(tmp_path / "ck.npz")
+    b.save(ck)
+    c = lw.WindowNet.load(ck)
+    assert c.step == 10
+    run(c, 10)
+    torch.cuda.synchronize()
+    for name in ("params", "m", "v", "wf", "wb"):
+        np.testing.assert_array_equal(getattr(a, name).cpu().numpy(), getattr(c, name).cpu().numpy(), err_msg=name)
+    assert la[-1] < la[0]
+
+
+def test_learned_window_pipeline_stepwise(lw):
+    """Every stage of the learned-window matcher checked against the oracle
+    on the inputs that stage consumed."""
+    import torch
+    pair = synth.make_pair(synth.scene_for_config("road320", 2), 2)
+    H, W = pair.left.shape
+    D, w = 64, 16
+    net = lw.WindowNet(_params(11))
+    m = lw.LearnedWindowMatcher(W, H, ndisp=D, window=w, census=7, npaths=8, p1=10, p2=120, net=net,
+                                threshold=0.0)
+    dint, dsub, lo, nfb = m.match(_dev(pair.left), _dev(pair.right))
+    torch.cuda.synchronize()
+    Lc, Rc = oracle.downsample4(pair.left), oracle.downsample4(pair.right)
+    np.testing.assert_array_equal(m.cl.cpu().numpy(), Lc)
+    ci, cs = oracle.sgm(Lc, Rc, 7, D // 4, 8, 10, 120)
+    np.testing.assert_array_equal(m.cdi.cpu().numpy().astype(np.uint16), ci)
+    gcs = m.cds.cpu().numpy()
+    assert np.abs(gcs - cs).max() <= 1e-4
+    x0 = ocnn.prepare_input(gcs, Lc)
+    np.testing.assert_array_equal(_bf16_bits_to_f(m.x0)[0], ocnn.bf16(x0)[0])
+    _, want_out = ocnn.forward(net.params.cpu().numpy(), x0)
+    assert np.abs(m.out.cpu().numpy() - want_out).max() <= 0.02 * np.abs(want_out).max() + 1e-6
+    want_lo, want_n = ocnn.window_map(gcs, m.out.cpu().numpy(), W, H, D, w, 0.0)
+    np.testing.assert_array_equal(lo.cpu().numpy(), want_lo)
+    assert int(nfb.item()) == want_n
+    wi, ws = oracle.sgm_win(pair.left, pair.right, 7, w, 8, 10, 120, want_lo)
+    np.testing.assert_array_equal(dint.cpu().numpy().astype(np.uint16), wi)
+    assert np.abs(dsub.cpu().numpy() - ws).max() <= 1e-4
