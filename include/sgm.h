@@ -193,10 +193,18 @@ sgm_status sgm_downsample4(const uint8_t *image, int32_t width, int32_t height, 
  * first three; bfloat16 weights and activations, float32 accumulation on
  * the matrix cores.  It runs on the quarter-resolution level: input channel
  * 0 = coarse disparity / 16, channel 1 = coarse left intensity / 255 - 1/2,
- * channels 2..15 zero; output channel 0 = window-centre offset (coarse
- * pixels), channel 1 = confidence logit.  The window centre of a full-
- * resolution pixel is 4 * (coarse + offset) where the logit reaches the
- * threshold, and 4 * coarse (the full-range SGM estimate) elsewhere.
+ * channel 2 = min(column - coarse disparity, 16) / 16 (distance of the
+ * coarse match from the left border), channels 3..15 zero; output channel
+ * 0 = window-centre offset (coarse pixels), channel 1 = confidence logit.
+ * Where the confidence sigmoid(logit) exceeds the threshold tau the window
+ * of a full-resolution pixel is centred on 4 * (coarse + offset); elsewhere
+ * the pixel falls back to full-range SGM (its window, still needed by the
+ * windowed aggregation of its neighbours, is centred on 4 * coarse).
+ *
+ * The network has no counterpart in the paper, whose windows come from the
+ * road model of Sec. II-A (eq. (3), (6)); it predicts the same quantity
+ * (a search window per pixel instead of per row) from the quarter-scale
+ * full-range SGM result.
  *
  * Buffers (all device, caller-owned; n images of W x H at a time):
  *   params  float32 [sgm_cnn_num_params()]: per layer W[tap][co][ci], b[co],
@@ -234,11 +242,23 @@ sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, in
 /* Per-pixel window starts lo (int32 [H][W]) of width w for a full-range
  * search of ndisp disparities: lo = clamp(floor(centre + 1/2) - w/2, 0,
  * ndisp - w), full pixel (x, y) reading coarse pixel (min(x/4, Wc-1),
- * min(y/4, Hc-1)).  nfallback (may be NULL) counts pixels that fell back. */
+ * min(y/4, Hc-1)).  A pixel is confident when logit > log(tau / (1 - tau))
+ * (tau <= 0: every pixel, tau >= 1: none).  Optional outputs (NULL to
+ * skip): fallback_mask uint8 [H][W] (1 = falls back), row_fallback uint32
+ * [H] fallback pixels per row, nfallback uint32 total; the counters are
+ * cleared by this call.  coarse_disp and cnn_out are [Hc][Wc] and
+ * [Hc][Wc][16] float32. */
 sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_t coarse_width,
                           int32_t coarse_height, int32_t width, int32_t height, int32_t ndisp,
-                          int32_t w, float conf_logit_threshold, int32_t *lo, uint32_t *nfallback,
-                          void *stream);
+                          int32_t w, float conf_threshold, int32_t *lo, uint8_t *fallback_mask,
+                          uint32_t *row_fallback, uint32_t *nfallback, void *stream);
+/* The full-range fallback: full-range SGM of rows y0 .. y0+rows-1 (band_int
+ * int16 / band_sub float32, [rows][width], band_sub may be NULL) replaces
+ * the windowed result in disp_int / disp_sub ([height][width]) on the
+ * pixels that fallback_mask marks.  Other pixels are left as they are. */
+sgm_status sgm_fallback_merge(const uint8_t *fallback_mask, const int16_t *band_int,
+                              const float *band_sub, int32_t width, int32_t height, int32_t y0,
+                              int32_t rows, int16_t *disp_int, float *disp_sub, void *stream);
 /* Training target at the coarse level: mean of each 4 x 4 block of a full-
  * resolution disparity map, divided by 4 (coarse pixels). */
 sgm_status sgm_label_downsample4(const float *label, int32_t width, int32_t height, float *coarse,

@@ -129,25 +129,77 @@ def adam(params, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 def prepare_input(coarse_disp, coarse_left):
     """Network input: channel 0 = coarse disparity / 16, channel 1 =
-    intensity / 255 - 1/2, channels 2..15 zero."""
+    intensity / 255 - 1/2, channel 2 = min(column - coarse disparity, 16) / 16
+    (how far the coarse match lies from the left image border, saturated),
+    channels 3..15 zero.  Float32 arithmetic, as the input is built."""
     H, W = coarse_disp.shape
+    cd = np.asarray(coarse_disp, np.float32)
+    col = np.broadcast_to(np.arange(W, dtype=np.float32)[None, :], (H, W))
     x = np.zeros((1, H, W, CH))
-    x[0, :, :, 0] = np.asarray(coarse_disp, np.float32) / np.float32(16.0)
+    x[0, :, :, 0] = cd / np.float32(16.0)
     x[0, :, :, 1] = np.asarray(coarse_left, np.float32) / np.float32(255.0) - np.float32(0.5)
+    x[0, :, :, 2] = np.minimum(col - cd, np.float32(16.0)) / np.float32(16.0)
     return x
 
 
-def window_map(coarse_disp, out, W, H, D, w, thr_logit):
-    """Per-pixel window start: centre = 4 * (coarse + offset) where the
-    confidence logit reaches thr_logit, else 4 * coarse (the full-range
-    estimate); lo = clamp(floor(centre + 1/2) - w/2, 0, D - w)."""
+def confidence_threshold(tau):
+    """Logit threshold of the confidence probability tau: a pixel is
+    confident when sigmoid(logit) > tau, i.e. logit > log(tau / (1 - tau));
+    tau <= 0 accepts every logit, tau >= 1 none."""
+    if tau <= 0.0:
+        return np.float32(-np.inf)
+    if tau >= 1.0:
+        return np.float32(np.inf)
+    return np.float32(np.log(tau / (1.0 - tau)))
+
+
+def window_map(coarse_disp, out, W, H, D, w, tau):
+    """Per-pixel window start and fallback mask.  Each full-resolution pixel
+    takes its coarse pixel (x // 4, y // 4, clamped to the coarse grid).
+    Confident pixels centre the window on 4 * (coarse + offset), the others
+    on 4 * coarse and are marked for the full-range fallback;
+    lo = clamp(floor(centre + 1/2) - w/2, 0, D - w).
+    Returns (lo int32 [H, W], number of fallback pixels, mask uint8 [H, W])."""
     Hc, Wc = coarse_disp.shape
     ys = np.minimum(np.arange(H) // 4, Hc - 1)
     xs = np.minimum(np.arange(W) // 4, Wc - 1)
     cd = np.asarray(coarse_disp, np.float32)[ys][:, xs]
     off = np.asarray(out[0, :, :, 0], np.float32)[ys][:, xs]
     lg = np.asarray(out[0, :, :, 1], np.float32)[ys][:, xs]
-    centre_c = np.where(lg >= np.float32(thr_logit), cd + off, cd).astype(np.float32)
+    conf = lg > confidence_threshold(tau)
+    centre_c = np.where(conf, cd + off, cd).astype(np.float32)
     centre = np.float32(4.0) * centre_c
     lo = np.floor(centre + np.float32(0.5)).astype(np.int64) - w // 2
-    return np.clip(lo, 0, D - w).astype(np.int32), int((lg < np.float32(thr_logit)).sum())
+    mask = (~conf).astype(np.uint8)
+    return np.clip(lo, 0, D - w).astype(np.int32), int(mask.sum()), mask
+
+
+def fallback_bands(mask, margin, full_fraction):
+    """Row bands for the full-range fallback: every row holding a fallback
+    pixel, widened by `margin` rows on both sides, overlapping or touching
+    bands joined; when the bands cover more than `full_fraction` of the rows
+    the whole frame is one band.  Returns a list of (y0, y1)."""
+    H = mask.shape[0]
+    rows = [y for y in range(H) if mask[y].any()]
+    bands = []
+    for y in rows:
+        a, b = max(0, y - margin), min(H, y + margin + 1)
+        if bands and a <= bands[-1][1]:
+            bands[-1] = (bands[-1][0], max(bands[-1][1], b))
+        else:
+            bands.append((a, b))
+    if sum(b - a for a, b in bands) > full_fraction * H:
+        return [(0, H)]
+    return bands
+
+
+def merge_fallback(win_int, win_sub, mask, bands, band_results):
+    """Final disparities: the windowed result, replaced on fallback pixels by
+    the full-range result of the band that holds their row."""
+    dint = np.array(win_int, copy=True)
+    dsub = np.array(win_sub, copy=True)
+    for (y0, y1), (bi, bs) in zip(bands, band_results):
+        m = mask[y0:y1].astype(bool)
+        dint[y0:y1][m] = bi[m]
+        dsub[y0:y1][m] = bs[m]
+    return dint, dsub

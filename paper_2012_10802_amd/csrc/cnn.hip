@@ -192,18 +192,19 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ 
 // ---------------------------------------------------------------------------
 // input, loss, optimiser, window map
 
-__global__ void k_prepare_input(const float *__restrict__ coarse, const uint8_t *__restrict__ left, int npix,
+__global__ void k_prepare_input(const float *__restrict__ coarse, const uint8_t *__restrict__ left, int W, int npix,
                                 uint16_t *__restrict__ x0)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
-    uint16_t v[CH];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) v[c] = 0;
-    v[0] = f2bf(__fdiv_rn(coarse[p], 16.0f));
-    v[1] = f2bf(__fsub_rn(__fdiv_rn((float)left[p], 255.0f), 0.5f));
+    const float cd = coarse[p];
+    const float col = (float)(p % W);
+    const uint16_t c0 = f2bf(__fdiv_rn(cd, 16.0f));
+    const uint16_t c1 = f2bf(__fsub_rn(__fdiv_rn((float)left[p], 255.0f), 0.5f));
+    // distance of the coarse match from the left border, saturated at 16
+    const uint16_t c2 = f2bf(__fdiv_rn(fminf(__fsub_rn(col, cd), 16.0f), 16.0f));
     uint4 *o = reinterpret_cast<uint4 *>(x0 + (size_t)p * CH);
-    o[0] = make_uint4(v[0] | (uint32_t)v[1] << 16, 0u, 0u, 0u);
+    o[0] = make_uint4(c0 | (uint32_t)c1 << 16, c2, 0u, 0u);
     o[1] = make_uint4(0u, 0u, 0u, 0u);
 }
 
@@ -261,21 +262,51 @@ __global__ void k_adam(float *__restrict__ params, float *__restrict__ m, float 
     }
 }
 
-__global__ void k_window_map(const float *__restrict__ coarse, const float *__restrict__ out, int Wc, int Hc, int W,
-                             int H, int D, int w, float thr, int32_t *__restrict__ lo, uint32_t *__restrict__ nfallback)
+__global__ void k_zero_u32(uint32_t *__restrict__ a, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0u;
+}
+
+// One row of full-resolution pixels per grid row; block of 256 along x.
+// Fallback counts are reduced per wave (ballot) before one atomic add.
+__global__ __launch_bounds__(256) void k_window_map(const float *__restrict__ coarse, const float *__restrict__ out,
+                                                    int Wc, int Hc, int W, int H, int D, int w, float thr,
+                                                    int32_t *__restrict__ lo, uint8_t *__restrict__ mask,
+                                                    uint32_t *__restrict__ row_count, uint32_t *__restrict__ nfallback)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-    if (x >= W) return;
-    const int cx = min(x / 4, Wc - 1), cy = min(y / 4, Hc - 1);
-    const size_t cp = (size_t)cy * Wc + cx;
-    const float cd = coarse[cp];
-    const float logit = out[cp * CH + 1];
-    const bool conf = logit >= thr;
-    const float centre = 4.0f * (conf ? __fadd_rn(cd, out[cp * CH]) : cd);
-    int l = (int)floorf(__fadd_rn(centre, 0.5f)) - w / 2;
-    l = min(max(l, 0), D - w);
-    lo[(size_t)y * W + x] = l;
-    if (nfallback && !conf) atomicAdd(nfallback, 1u);
+    bool fb = false;
+    if (x < W) {
+        const int cx = min(x / 4, Wc - 1), cy = min(y / 4, Hc - 1);
+        const size_t cp = (size_t)cy * Wc + cx;
+        const float cd = coarse[cp];
+        const bool conf = out[cp * CH + 1] > thr;
+        const float centre = 4.0f * (conf ? __fadd_rn(cd, out[cp * CH]) : cd);
+        int l = (int)floorf(__fadd_rn(centre, 0.5f)) - w / 2;
+        l = min(max(l, 0), D - w);
+        lo[(size_t)y * W + x] = l;
+        if (mask) mask[(size_t)y * W + x] = conf ? 0 : 1;
+        fb = !conf;
+    }
+    const uint32_t cnt = (uint32_t)__popcll(__ballot(fb));
+    if ((threadIdx.x & 63) == 0 && cnt) {
+        if (row_count) atomicAdd(row_count + y, cnt);
+        if (nfallback) atomicAdd(nfallback, cnt);
+    }
+}
+
+// Fallback pixels of rows y0 .. y0+rows-1 take the band's full-range result.
+__global__ void k_merge_fallback(const uint8_t *__restrict__ mask, const int16_t *__restrict__ band_int,
+                                 const float *__restrict__ band_sub, int W, int y0, int rows, int16_t *__restrict__ dint,
+                                 float *__restrict__ dsub)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (x >= W || r >= rows) return;
+    const size_t o = (size_t)(y0 + r) * W + x, b = (size_t)r * W + x;
+    if (!mask[o]) return;
+    dint[o] = band_int[b];
+    if (dsub && band_sub) dsub[o] = band_sub[b];
 }
 
 __global__ void k_label_downsample4(const float *__restrict__ full, int W, int H, float *__restrict__ coarse)
@@ -338,7 +369,7 @@ sgm_status sgm_cnn_prepare_input(const float *coarse_disp, const uint8_t *coarse
     if (!aligned(x0, 16)) return cfail(SGM_ERR_INVALID, "x0 must be 16-byte aligned");
     const int npix = width * height * nimg;
     hipLaunchKernelGGL(k_prepare_input, dim3((npix + 255) / 256), dim3(256), 0, (hipStream_t)stream, coarse_disp,
-                       coarse_left, npix, x0);
+                       coarse_left, width, npix, x0);
     return launched("prepare input");
 }
 
@@ -418,23 +449,53 @@ sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, in
 {
     if (!params || !m || !v || !grad || !wf || !wb) return cfail(SGM_ERR_INVALID, "NULL buffer");
     if (step < 1) return cfail(SGM_ERR_INVALID, "step must be >= 1");
-    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    // bias corrections in double: 1 - beta2^t is small early on and would
+    // lose most of its digits in float
+    const float c1 = (float)(1.0 - pow((double)beta1, (double)step));
+    const float c2 = (float)(1.0 - pow((double)beta2, (double)step));
     hipLaunchKernelGGL(k_adam, dim3((NPARAMS + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, m, v, grad,
                        lr, beta1, beta2, eps, c1, c2, 1, wf, wb);
     return launched("cnn adam");
 }
 
 sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_t coarse_width, int32_t coarse_height,
-                          int32_t width, int32_t height, int32_t ndisp, int32_t w, float conf_logit_threshold,
-                          int32_t *lo, uint32_t *nfallback, void *stream)
+                          int32_t width, int32_t height, int32_t ndisp, int32_t w, float conf_threshold, int32_t *lo,
+                          uint8_t *fallback_mask, uint32_t *row_fallback, uint32_t *nfallback, void *stream)
 {
     if (!coarse_disp || !cnn_out || !lo) return cfail(SGM_ERR_INVALID, "NULL buffer");
     if (coarse_width < 1 || coarse_height < 1 || width < 1 || height < 1 || w < 1 || w > ndisp || ndisp > 256)
         return cfail(SGM_ERR_INVALID, "bad size");
+    if (conf_threshold != conf_threshold) return cfail(SGM_ERR_INVALID, "threshold is NaN");
+    // confident iff sigmoid(logit) > tau  <=>  logit > log(tau / (1 - tau))
+    float thr;
+    if (conf_threshold <= 0.0f)
+        thr = -INFINITY;
+    else if (conf_threshold >= 1.0f)
+        thr = INFINITY;
+    else
+        thr = (float)log((double)conf_threshold / (1.0 - (double)conf_threshold));
+    hipStream_t s = (hipStream_t)stream;
+    if (row_fallback)
+        hipLaunchKernelGGL(k_zero_u32, dim3((height + 255) / 256), dim3(256), 0, s, row_fallback, (int)height);
+    if (nfallback) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, nfallback, 1);
     dim3 grid((width + 255) / 256, height), block(256);
-    hipLaunchKernelGGL(k_window_map, grid, block, 0, (hipStream_t)stream, coarse_disp, cnn_out, coarse_width,
-                       coarse_height, width, height, ndisp, w, conf_logit_threshold, lo, nfallback);
+    hipLaunchKernelGGL(k_window_map, grid, block, 0, s, coarse_disp, cnn_out, coarse_width, coarse_height, width,
+                       height, ndisp, w, thr, lo, fallback_mask, row_fallback, nfallback);
     return launched("window map");
+}
+
+sgm_status sgm_fallback_merge(const uint8_t *fallback_mask, const int16_t *band_int, const float *band_sub,
+                              int32_t width, int32_t height, int32_t y0, int32_t rows, int16_t *disp_int,
+                              float *disp_sub, void *stream)
+{
+    if (!fallback_mask || !band_int || !disp_int) return cfail(SGM_ERR_INVALID, "NULL buffer");
+    if (width < 1 || height < 1 || y0 < 0 || rows < 0 || y0 + rows > height)
+        return cfail(SGM_ERR_INVALID, "band outside the frame");
+    if (rows == 0) return SGM_OK;
+    dim3 grid((width + 255) / 256, rows), block(256);
+    hipLaunchKernelGGL(k_merge_fallback, grid, block, 0, (hipStream_t)stream, fallback_mask, band_int, band_sub,
+                       width, y0, rows, disp_int, disp_sub);
+    return launched("fallback merge");
 }
 
 sgm_status sgm_label_downsample4(const float *label, int32_t width, int32_t height, float *coarse, void *stream)

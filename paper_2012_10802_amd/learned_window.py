@@ -1,21 +1,34 @@
 """Learned search windows (the learned-window form of the SGM path).
 
-Pipeline per pair, every step a HIP kernel behind the C ABI:
+Pipeline for a batch of pairs of one size, every step a HIP kernel behind
+the C ABI:
   1. 4 x 4 box reduction of both images (quarter resolution);
-  2. plain full-range SGM on the quarter-resolution pair (ndisp / 4
-     disparities): the coarse disparity;
-  3. the window network (four 3x3 convolutions, 16 channels, bfloat16 on the
-     matrix cores) on [coarse disparity, coarse left image]: a centre offset
-     and a confidence logit per coarse pixel;
+  2. plain full-range SGM of all quarter-resolution pairs (ndisp / 4
+     disparities) in one batched launch: the coarse disparity;
+  3. the window network (four 3x3 convolutions, 16 channels, bfloat16 on
+     the matrix cores) on [coarse disparity, coarse left image, distance of
+     the coarse match from the left border]: a centre offset and a
+     confidence logit per coarse pixel;
   4. the window map: per full-resolution pixel a 16-wide window centred on
-     4 * (coarse + offset) where the network is confident, on 4 * coarse
-     (the full-range estimate) where it is not;
-  5. SGM over the per-pixel windows at full resolution.
+     4 * (coarse + offset) where the network is confident; the other pixels
+     are marked for the fallback (their window, centred on 4 * coarse, still
+     feeds the windowed aggregation of their neighbours);
+  5. SGM over the per-pixel windows at full resolution;
+  6. the full-range fallback: plain SGM over all ndisp disparities on the
+     row bands that hold marked pixels (widened by a margin, joined when they
+     touch, the whole frame once they cover most of it), whose result
+     replaces the windowed one on the marked pixels.  With every pixel
+     marked the output is plain full-range SGM of the frame, exactly.
 
-Training: pairs from the road generator, labelled by full-range plain SGM at
-full resolution on the GPU; Adam on float32 master weights with the
-hand-written forward, loss, backward and optimiser kernels.  Checkpoints
-are plain arrays (numpy .npz, no pickles) with a JSON header.
+The network is the project's own addition: the paper's windows come from
+its road model (Sec. II-A, eq. (3) and (6)) one per row; here a window is
+predicted per pixel from the quarter-scale SGM result.
+
+Training (train_window.py): pairs from the road generator, labelled by
+full-range plain SGM at full resolution on the GPU; Adam on float32 master
+weights with the hand-written forward, loss, backward and optimiser
+kernels.  Checkpoints are plain arrays (numpy .npz, no pickles) with a JSON
+header.
 """
 from __future__ import annotations
 
@@ -43,16 +56,16 @@ def num_params() -> int:
 
 
 def init_params(seed=0):
-    """He-normal weights for the used input channels, zero biases; the last
-    layer starts small."""
+    """He-normal weights on the used input channels (three in the first
+    layer), zero biases; the last layer starts small."""
     rng = np.random.default_rng(seed)
     per = 9 * CH * CH + CH
     p = np.zeros(4 * per, np.float32)
     for l in range(4):
-        fan_in = 9 * (2 if l == 0 else CH)
+        fan_in = 9 * (3 if l == 0 else CH)
         Wl = rng.normal(0.0, np.sqrt(2.0 / fan_in), size=(9, CH, CH)).astype(np.float32)
         if l == 0:
-            Wl[:, :, 2:] = 0.0
+            Wl[:, :, 3:] = 0.0
         if l == 3:
             Wl *= 0.1
         p[l * per: l * per + 9 * CH * CH] = Wl.ravel()
@@ -74,8 +87,12 @@ class WindowNet:
         self.v = torch.zeros_like(self.params)
         self.grad = torch.zeros_like(self.params)
         self.step = 0
+        self.header = {}
         self.wf = torch.empty(4 * 9 * CH * CH, dtype=torch.int16, device=self.device)
         self.wb = torch.empty_like(self.wf)
+        self.pack()
+
+    def pack(self):
         S._check(_lib.sgm_cnn_pack_weights(_c(self.params), _c(self.wf), _c(self.wb), S._stream()),
                  "sgm_cnn_pack_weights")
 
@@ -89,6 +106,14 @@ class WindowNet:
         S._check(_lib.sgm_cnn_forward(_c(self.wf), _c(self.params), _c(x0), W, H, n, _c(acts), _c(out),
                                       S._stream(stream)), "sgm_cnn_forward")
         return out
+
+    def train_buffers(self, W, H, n):
+        acts, out = self.buffers(W, H, n)
+        dy = torch.empty((n, H, W, CH), dtype=torch.int16, device=self.device)
+        scratch = torch.empty(int(_lib.sgm_cnn_scratch_bytes(W, H, n)), dtype=torch.uint8,
+                              device=self.device)
+        loss = torch.zeros(2, dtype=torch.float32, device=self.device)
+        return acts, out, dy, scratch, loss
 
     def train_step(self, x0, coarse, label, W, H, n, lr, bufs, stream=None):
         """Forward, loss, backward, Adam.  Returns the device loss pair
@@ -106,26 +131,22 @@ class WindowNet:
                                    float(lr), 0.9, 0.999, 1e-8, _c(self.wf), _c(self.wb), st), "sgm_cnn_adam")
         return loss
 
-    def train_buffers(self, W, H, n):
-        acts, out = self.buffers(W, H, n)
-        dy = torch.empty((n, H, W, CH), dtype=torch.int16, device=self.device)
-        scratch = torch.empty(int(_lib.sgm_cnn_scratch_bytes(W, H, n)), dtype=torch.uint8,
-                              device=self.device)
-        loss = torch.zeros(2, dtype=torch.float32, device=self.device)
-        return acts, out, dy, scratch, loss
-
     # --- checkpoints: plain arrays + JSON header (no pickles)
     def save(self, path, extra=None):
         header = {"format": "window-cnn/1", "step": self.step, "num_params": num_params()}
         header.update(extra or {})
-        np.savez(path, params=self.params.cpu().numpy(), m=self.m.cpu().numpy(),
+        tmp = path + ".tmp.npz"
+        np.savez(tmp, params=self.params.cpu().numpy(), m=self.m.cpu().numpy(),
                  v=self.v.cpu().numpy(),
                  header=np.frombuffer(json.dumps(header).encode(), dtype=np.uint8))
+        os.replace(tmp, path)
 
     @classmethod
     def load(cls, path, device="cuda"):
         with np.load(path, allow_pickle=False) as z:
             header = json.loads(bytes(z["header"]).decode())
+            if header.get("format") != "window-cnn/1" or header.get("num_params") != num_params():
+                raise ValueError("%s is not a window-network checkpoint of this layout" % path)
             net = cls(params=z["params"], device=device)
             net.m.copy_(torch.from_numpy(z["m"]))
             net.v.copy_(torch.from_numpy(z["v"]))
@@ -151,52 +172,131 @@ def label_downsample4(label, out=None, stream=None):
     return out
 
 
-def window_map(coarse_disp, out, W, H, ndisp, w, threshold, lo=None, nfallback=None, stream=None):
+def window_map(coarse_disp, out, W, H, ndisp, w, tau, lo=None, mask=None, row_fallback=None,
+               nfallback=None, stream=None):
     Hc, Wc = coarse_disp.shape[-2:]
     if lo is None:
         lo = torch.empty((H, W), dtype=torch.int32, device=coarse_disp.device)
-    S._check(_lib.sgm_window_map(_c(coarse_disp), _c(out), Wc, Hc, W, H, ndisp, w, float(threshold),
-                                 _c(lo), _c(nfallback), S._stream(stream)), "sgm_window_map")
+    S._check(_lib.sgm_window_map(_c(coarse_disp), _c(out), Wc, Hc, W, H, ndisp, w, float(tau), _c(lo),
+                                 _c(mask), _c(row_fallback), _c(nfallback), S._stream(stream)),
+             "sgm_window_map")
     return lo
 
 
-class LearnedWindowMatcher:
-    """Coarse full-range SGM -> window network -> per-pixel-window SGM."""
+def fallback_merge(mask, band_int, band_sub, y0, rows, disp_int, disp_sub, stream=None):
+    H, W = disp_int.shape
+    S._check(_lib.sgm_fallback_merge(_c(mask), _c(band_int), _c(band_sub), W, H, int(y0), int(rows),
+                                     _c(disp_int), _c(disp_sub), S._stream(stream)), "sgm_fallback_merge")
 
-    def __init__(self, width, height, ndisp=192, window=16, census=7, npaths=8, p1=10, p2=120,
-                 net=None, threshold=0.0, device="cuda"):
+
+def fallback_bands(row_counts, margin=32, full_fraction=0.75):
+    """Row bands [(y0, y1)] for the full-range fallback from per-row counts
+    of fallback pixels: each such row widened by `margin` rows both ways,
+    overlapping or touching bands joined, and the whole frame as one band
+    when they would cover more than `full_fraction` of the rows."""
+    counts = np.asarray(row_counts)
+    H = counts.shape[0]
+    flagged = np.flatnonzero(counts > 0)
+    if flagged.size == 0:
+        return []
+    lo = np.maximum(flagged - margin, 0)
+    hi = np.minimum(flagged + margin + 1, H)
+    # a new band starts where the widened row does not reach the previous one
+    starts = np.ones(flagged.size, bool)
+    starts[1:] = lo[1:] > np.maximum.accumulate(hi)[:-1]
+    idx = np.flatnonzero(starts)
+    ends = np.r_[idx[1:], flagged.size]
+    bands = [(int(lo[a]), int(hi[a:b].max())) for a, b in zip(idx, ends)]
+    if sum(b - a for a, b in bands) > full_fraction * H:
+        return [(0, H)]
+    return bands
+
+
+class LearnedWindowMatcher:
+    """Coarse full-range SGM -> window network -> per-pixel-window SGM ->
+    full-range fallback, for batches of `batch` pairs of one size."""
+
+    def __init__(self, width, height, batch=1, ndisp=192, window=16, census=7, npaths=8, p1=10,
+                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.75, device="cuda"):
         if width % 4 or height % 4 or ndisp % 4:
             raise ValueError("width, height and ndisp must be multiples of 4")
-        self.W, self.H, self.D, self.w = width, height, ndisp, window
+        self.W, self.H, self.D, self.w, self.n = width, height, ndisp, window, batch
         self.Wc, self.Hc = width // 4, height // 4
-        self.threshold = threshold
-        self.device = torch.device(device)
+        self.census, self.npaths, self.p1, self.p2 = census, npaths, p1, p2
+        self.tau, self.margin, self.full_fraction = tau, margin, full_fraction
+        self.device = dev = torch.device(device)
         self.net = net if net is not None else WindowNet.load(DEFAULT_WEIGHTS, device=device)
-        self.coarse = S.Matcher(self.Wc, self.Hc, census=census, ndisp=ndisp // 4, npaths=npaths,
-                                p1=p1, p2=p2, device=device)
-        self.fine = S.Matcher(width, height, census=census, ndisp=window, npaths=npaths, p1=p1, p2=p2,
-                              device=device)
-        dev = self.device
-        self.cl = torch.empty((self.Hc, self.Wc), dtype=torch.uint8, device=dev)
+        n, Hc, Wc = batch, self.Hc, self.Wc
+        self.cl = torch.empty((n, Hc, Wc), dtype=torch.uint8, device=dev)
         self.cr = torch.empty_like(self.cl)
-        self.cdi = torch.empty((self.Hc, self.Wc), dtype=torch.int16, device=dev)
-        self.cds = torch.empty((self.Hc, self.Wc), dtype=torch.float32, device=dev)
-        self.x0 = torch.empty((1, self.Hc, self.Wc, CH), dtype=torch.int16, device=dev)
-        self.acts, self.out = self.net.buffers(self.Wc, self.Hc, 1)
-        self.lo = torch.empty((height, width), dtype=torch.int32, device=dev)
-        self.nfallback = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.dint = torch.empty((height, width), dtype=torch.int16, device=dev)
-        self.dsub = torch.empty((height, width), dtype=torch.float32, device=dev)
+        self.coarse = S.Batch([dict(left=self.cl[i], right=self.cr[i], ndisp=ndisp // 4) for i in range(n)],
+                              census=census, npaths=npaths, p1=p1, p2=p2, device=dev)
+        self.x0 = torch.empty((n, Hc, Wc, CH), dtype=torch.int16, device=dev)
+        self.acts, self.out = self.net.buffers(Wc, Hc, n)
+        self.fine = S.Matcher(width, height, census=census, ndisp=window, npaths=npaths, p1=p1, p2=p2,
+                              device=dev)
+        self.lo = torch.empty((n, height, width), dtype=torch.int32, device=dev)
+        self.mask = torch.empty((n, height, width), dtype=torch.uint8, device=dev)
+        self.rows = torch.zeros((n, height), dtype=torch.int32, device=dev)
+        self.nfallback = torch.zeros((n,), dtype=torch.int32, device=dev)
+        self.dint = torch.empty((n, height, width), dtype=torch.int16, device=dev)
+        self.dsub = torch.empty((n, height, width), dtype=torch.float32, device=dev)
+        # full-range fallback: one workspace sized for the whole frame, plans per band height
+        full = S.sgm_plan(width, height, census, ndisp, npaths, p1, p2)
+        try:
+            need = S.sgm_workspace_size(full)
+        finally:
+            S.sgm_plan_free(full)
+        self.full_ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.band_int = torch.empty((height, width), dtype=torch.int16, device=dev)
+        self.band_sub = torch.empty((height, width), dtype=torch.float32, device=dev)
+        self._full = {}
+        self.last_bands = []
+
+    def _full_matcher(self, rows):
+        m = self._full.get(rows)
+        if m is None:
+            m = S.Matcher(self.W, rows, census=self.census, ndisp=self.D, npaths=self.npaths, p1=self.p1,
+                          p2=self.p2, device=self.device, workspace=self.full_ws)
+            self._full[rows] = m
+        return m
+
+    def windows(self, left, right, stream=None):
+        """Steps 1-5 for left, right uint8 [n, H, W]; returns nothing, fills
+        lo, mask, rows, dint, dsub."""
+        n = self.n
+        if tuple(left.shape) != (n, self.H, self.W) or tuple(right.shape) != (n, self.H, self.W):
+            raise ValueError("left and right must be uint8 [%d, %d, %d]" % (n, self.H, self.W))
+        for i in range(n):
+            S.sgm_downsample4(left[i], self.cl[i], stream)
+            S.sgm_downsample4(right[i], self.cr[i], stream)
+        self.coarse.run(stream)
+        for i in range(n):
+            prepare_input(self.coarse.disp_sub[i], self.cl[i], self.Wc, self.Hc, 1, self.x0[i], stream)
+        self.net.forward(self.x0, self.acts, self.out, self.Wc, self.Hc, n, stream)
+        for i in range(n):
+            window_map(self.coarse.disp_sub[i], self.out[i], self.W, self.H, self.D, self.w, self.tau,
+                       self.lo[i], self.mask[i], self.rows[i], self.nfallback[i:i + 1], stream)
+            self.fine.match_win(left[i], right[i], self.lo[i], disp_int=self.dint[i], disp_sub=self.dsub[i],
+                                stream=stream)
+
+    def fallback(self, left, right, stream=None):
+        """Step 6 (synchronises once to read the per-row counts)."""
+        counts = self.rows.cpu().numpy()
+        self.last_bands = []
+        for i in range(self.n):
+            bands = fallback_bands(counts[i], self.margin, self.full_fraction)
+            self.last_bands.append(bands)
+            for y0, y1 in bands:
+                h = y1 - y0
+                m = self._full_matcher(h)
+                m.match(left[i][y0:y1], right[i][y0:y1], disp_int=self.band_int[:h], disp_sub=self.band_sub[:h],
+                        stream=stream)
+                fallback_merge(self.mask[i], self.band_int[:h], self.band_sub[:h], y0, h, self.dint[i],
+                               self.dsub[i], stream)
 
     def match(self, left, right, stream=None):
-        """Returns (disp_int, disp_sub, lo, nfallback) device tensors."""
-        S.sgm_downsample4(left, self.cl, stream)
-        S.sgm_downsample4(right, self.cr, stream)
-        self.coarse.match(self.cl, self.cr, disp_int=self.cdi, disp_sub=self.cds, stream=stream)
-        prepare_input(self.cds, self.cl, self.Wc, self.Hc, 1, self.x0, stream)
-        self.net.forward(self.x0, self.acts, self.out, self.Wc, self.Hc, 1, stream)
-        self.nfallback.zero_()
-        window_map(self.cds, self.out, self.W, self.H, self.D, self.w, self.threshold, self.lo,
-                   self.nfallback, stream)
-        self.fine.match_win(left, right, self.lo, disp_int=self.dint, disp_sub=self.dsub, stream=stream)
-        return self.dint, self.dsub, self.lo, self.nfallback
+        """Returns (disp_int int16 [n,H,W], disp_sub float32 [n,H,W]) device tensors."""
+        self.windows(left, right, stream)
+        self.fallback(left, right, stream)
+        return self.dint, self.dsub

@@ -88,7 +88,8 @@ def _load_library():
         "sgm_cnn_backward": [P, P, P, P, I, I, I, P, P, S, P],
         "sgm_cnn_adam": [P, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                          ctypes.c_float, P, P, P],
-        "sgm_window_map": [P, P, I, I, I, I, I, I, ctypes.c_float, P, P, P],
+        "sgm_window_map": [P, P, I, I, I, I, I, I, ctypes.c_float, P, P, P, P, P],
+        "sgm_fallback_merge": [P, P, P, I, I, I, I, P, P, P],
         "sgm_label_downsample4": [P, I, I, P, P],
         "sgm_batch_plan": [ctypes.POINTER(sgm_batch_params), ctypes.POINTER(sgm_pair), I,
                            ctypes.POINTER(P)],
@@ -205,13 +206,19 @@ class Matcher:
     """
 
     def __init__(self, width, height, census=7, ndisp=128, npaths=8, p1=10, p2=120,
-                 device=None):
+                 device=None, workspace=None):
         self.W, self.H, self.n, self.w = int(width), int(height), int(census), int(ndisp)
         self.npaths, self.p1, self.p2 = int(npaths), int(p1), int(p2)
         self.plan = sgm_plan(self.W, self.H, self.n, self.w, self.npaths, self.p1, self.p2)
         self.device = torch.device(device or "cuda")
-        self.ws_bytes = sgm_workspace_size(self.plan)
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        need = sgm_workspace_size(self.plan)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        _need(workspace, torch.uint8, None, "workspace")
+        if workspace.numel() < need:
+            raise ValueError("workspace holds %d bytes, the plan needs %d" % (workspace.numel(), need))
+        self.workspace = workspace  # may be shared by matchers that run one at a time
+        self.ws_bytes = workspace.numel()
 
     def __del__(self):
         plan = getattr(self, "plan", None)

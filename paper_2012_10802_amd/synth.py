@@ -38,7 +38,7 @@ import math
 
 import numpy as np
 
-__all__ = ["RoadScene", "make_pair", "scene_for_config", "PairSet",
+__all__ = ["RoadScene", "make_pair", "make_pair_torch", "scene_for_config", "PairSet",
            "CONFIGS", "road_model_disparity"]
 
 
@@ -214,6 +214,93 @@ def make_pair(scene: RoadScene, seed: int) -> PairSet:
     right = np.clip(np.rint(clean_r + nr), 0, 255).astype(np.uint8)
     return PairSet(left, right, gt, road, hole, scene.road_params,
                    (scene.cx, scene.cy), scene)
+
+
+# ---------------------------------------------------------------------------
+# the same scenes rendered with torch (on the GPU, for training data)
+
+
+def _noise_torch(o: _GradientNoise, x, y, gx, gy):
+    import torch
+    x = x + float(o.off[0])
+    y = y + float(o.off[1])
+    x0 = torch.floor(x)
+    y0 = torch.floor(y)
+    fx = x - x0
+    fy = y - y0
+    p = o.period
+    ix = x0.long() % p
+    iy = y0.long() % p
+    ix1 = (ix + 1) % p
+    iy1 = (iy + 1) % p
+
+    def dot(jx, jy, dx, dy):
+        k = jy * p + jx
+        return gx[k] * dx + gy[k] * dy
+
+    n00 = dot(ix, iy, fx, fy)
+    n10 = dot(ix1, iy, fx - 1.0, fy)
+    n01 = dot(ix, iy1, fx, fy - 1.0)
+    n11 = dot(ix1, iy1, fx - 1.0, fy - 1.0)
+    sx = _fade(fx)
+    sy = _fade(fy)
+    a = n00 + sx * (n10 - n00)
+    b = n01 + sx * (n11 - n01)
+    return a + sy * (b - a)
+
+
+def make_pair_torch(scene: RoadScene, seed: int, device="cuda", noise=True):
+    """The scene of make_pair(scene, seed) rendered with torch in float64 on
+    `device`: same lattices, potholes and formulas, so the clean images and
+    the ground truth agree with make_pair's; the sensor noise is drawn from
+    torch's generator (same distribution, other samples).  Returns
+    (left, right, gt, road) tensors: uint8, uint8, float32, bool."""
+    import torch
+    rng = np.random.default_rng(seed)
+    tex = _Texture(scene, rng)
+    holes = _potholes(scene, rng)
+    H, W = scene.height, scene.width
+    dev = torch.device(device)
+    f64 = torch.float64
+    vv = torch.arange(H, dtype=f64, device=dev)[:, None].expand(H, W)
+    uu = torch.arange(W, dtype=f64, device=dev)[None, :].expand(H, W)
+    lat = [(torch.from_numpy(o.gx.ravel()).to(dev), torch.from_numpy(o.gy.ravel()).to(dev))
+           for o in tex.octs]
+    a0, a1, phi = scene.road_params
+
+    def disparity(u, v):
+        d = a0 + a1 * (math.cos(phi) * (v - scene.cy) - math.sin(phi) * (u - scene.cx))
+        road = d >= 0.5
+        z = torch.zeros_like(d)
+        for cu, cv, ru, rv, depth in holes:
+            r2 = ((u - cu) / ru) ** 2 + ((v - cv) / rv) ** 2
+            z = torch.maximum(z, torch.where(r2 < 1.0, depth * (1.0 - r2), torch.zeros_like(r2)))
+        return torch.where(road, d * scene.cam_height / (scene.cam_height + z), torch.zeros_like(d)), road
+
+    def texture(x, y):
+        acc = torch.zeros_like(x)
+        amp, norm, wl = 1.0, 0.0, scene.base_wavelength
+        for o, (gx, gy) in zip(tex.octs, lat):
+            acc = acc + amp * _noise_torch(o, x / wl, y / wl, gx, gy)
+            norm += amp
+            amp *= scene.gain
+            wl = max(wl / 2.0, 1.0)
+        return torch.clamp(128.0 + scene.contrast * (acc / norm) / 0.2, 0.0, 255.0)
+
+    gt, road = disparity(uu, vv)
+    clean_l = texture(uu, vv)
+    u = uu.clone()
+    for _ in range(3):
+        u = uu + disparity(u, vv)[0]
+    clean_r = texture(u, vv)
+    if noise:
+        g = torch.Generator(device=dev)
+        g.manual_seed(int(seed))
+        clean_l = clean_l + scene.noise_sigma * torch.randn((H, W), generator=g, dtype=f64, device=dev)
+        clean_r = clean_r + scene.noise_sigma * torch.randn((H, W), generator=g, dtype=f64, device=dev)
+    left = torch.clamp(torch.round(clean_l), 0, 255).to(torch.uint8)
+    right = torch.clamp(torch.round(clean_r), 0, 255).to(torch.uint8)
+    return left, right, gt.to(torch.float32), road
 
 
 # ---------------------------------------------------------------------------

@@ -138,3 +138,18 @@ def test_batch_plan_validation(sgm):
     assert lib.sgm_batch_plan(ctypes.byref(prm), arr, 0, ctypes.byref(h)) == -1
     assert lib.sgm_batch_run(None, None, 0, None) == -1
     assert lib.sgm_batch_launch(None, None) == -1
+
+
+def test_fallback_bands_host_logic_matches_oracle():
+    """The product's band selection (host code, numpy) against the oracle's
+    plain loop, on random masks of several densities."""
+    from oracle import cnn as ocnn
+    from paper_2012_10802_amd import learned_window as lw
+    rng = np.random.default_rng(17)
+    for trial in range(200):
+        H = int(rng.integers(1, 120))
+        dens = [0.0, 0.002, 0.02, 0.1, 0.5][trial % 5]
+        mask = (rng.random((H, 9)) < dens).astype(np.uint8)
+        margin = int(rng.integers(0, 20))
+        frac = float(rng.choice([0.3, 0.75, 1.0]))
+        assert lw.fallback_bands(mask.sum(axis=1), margin, frac) == ocnn.fallback_bands(mask, margin, frac)

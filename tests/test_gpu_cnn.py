@@ -126,11 +126,12 @@ def test_prepare_input_and_label_downsample(lw):
     import torch
     rng = np.random.default_rng(5)
     Hc, Wc = 9, 23
-    cd = rng.uniform(0, 48, (Hc, Wc)).astype(np.float32)
-    cl = rng.integers(0, 256, (Hc, Wc), dtype=np.uint8)
-    x0 = lw.prepare_input(_dev(cd), _dev(cl), Wc, Hc, 1)
+    cd = rng.uniform(0, 30, (2, Hc, Wc)).astype(np.float32)
+    cl = rng.integers(0, 256, (2, Hc, Wc), dtype=np.uint8)
+    x0 = lw.prepare_input(_dev(cd), _dev(cl), Wc, Hc, 2)  # two images in one call
     torch.cuda.synchronize()
-    np.testing.assert_array_equal(_bf16_bits_to_f(x0), ocnn.bf16(ocnn.prepare_input(cd, cl)))
+    for i in range(2):
+        np.testing.assert_array_equal(_bf16_bits_to_f(x0)[i], ocnn.bf16(ocnn.prepare_input(cd[i], cl[i]))[0])
     full = rng.uniform(0, 190, (4 * Hc + 2, 4 * Wc + 3)).astype(np.float32)
     got = lw.label_downsample4(_dev(full)).cpu().numpy()
     blocks = full[:4 * Hc, :4 * Wc].reshape(Hc, 4, Wc, 4).astype(np.float64)
@@ -149,7 +150,8 @@ def test_loss_gradient(lw):
     label = (coarse + rng.integers(-96, 97, (H, W)) / 64.0).astype(np.float32)
     dy = torch.empty((n, H, W, CH), dtype=torch.int16, device="cuda")
     loss = torch.zeros(2, dtype=torch.float32, device="cuda")
-    S._check(S.library().sgm_cnn_loss(lw._c(_dev(out)), lw._c(_dev(coarse)), lw._c(_dev(label)), W, H, n,
+    outd, cd, ld = _dev(out), _dev(coarse), _dev(label)  # held until the call has run
+    S._check(S.library().sgm_cnn_loss(lw._c(outd), lw._c(cd), lw._c(ld), W, H, n,
                                       lw._c(dy), lw._c(loss), S._stream()), "sgm_cnn_loss")
     torch.cuda.synchronize()
     want_loss, g = ocnn.loss_and_grad(out, coarse[None], label[None])
@@ -175,12 +177,12 @@ def test_backward_gradients(lw, shape):
     net = lw.WindowNet(params)
     bufs = net.train_buffers(W, H, n)
     acts, out, _, scratch, _ = bufs
-    x0d = _to_bf16_dev(x0)
+    x0d, doutd = _to_bf16_dev(x0), _to_bf16_dev(dout)
     net.forward(x0d, acts, out, W, H, n)
     S = lw.S
     grads = []
     for _ in range(2):
-        S._check(S.library().sgm_cnn_backward(lw._c(net.wb), lw._c(x0d), lw._c(acts), lw._c(_to_bf16_dev(dout)),
+        S._check(S.library().sgm_cnn_backward(lw._c(net.wb), lw._c(x0d), lw._c(acts), lw._c(doutd),
                                               W, H, n, lw._c(net.grad), lw._c(scratch), scratch.numel(),
                                               S._stream()), "sgm_cnn_backward")
         torch.cuda.synchronize()
@@ -212,11 +214,22 @@ def test_adam_and_weight_packing(lw):
     S._check(S.library().sgm_cnn_adam(lw._c(net.params), lw._c(net.m), lw._c(net.v), lw._c(net.grad), step, lr,
                                       0.9, 0.999, 1e-8, lw._c(net.wf), lw._c(net.wb), S._stream()), "adam")
     torch.cuda.synchronize()
+    # the kernel receives the hyper-parameters as float32: the oracle takes
+    # the same values
+    f = lambda a: float(np.float32(a))  # noqa: E731
     wp, wm, wv = ocnn.adam(params.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
-                           g.astype(np.float64), step, lr)
-    np.testing.assert_allclose(net.m.cpu().numpy(), wm, rtol=1e-6, atol=1e-12)
-    np.testing.assert_allclose(net.v.cpu().numpy(), wv, rtol=1e-6, atol=1e-15)
-    np.testing.assert_allclose(net.params.cpu().numpy(), wp, rtol=1e-6, atol=lr * 1e-4)
+                           g.astype(np.float64), step, f(lr), f(0.9), f(0.999), f(1e-8))
+    # float32 rounding, bounded by the magnitudes of the terms that are added
+    # (the moments can cancel), then carried through the update
+    b1, b2, eps = f(0.9), f(0.999), f(1e-8)
+    tm = 2.0 ** -21 * (b1 * np.abs(m) + (1 - b1) * np.abs(g))
+    tv = 2.0 ** -21 * (b2 * v + (1 - b2) * g.astype(np.float64) ** 2)
+    c1, c2 = 1 - b1 ** step, 1 - b2 ** step
+    den = np.sqrt(wv / c2) + eps
+    tp = 2.0 ** -22 * np.abs(wp) + lr * (tm / c1 / den + 2.0 ** -19 * np.abs(wm / c1) / den)
+    assert np.all(np.abs(net.m.cpu().numpy() - wm) <= tm)
+    assert np.all(np.abs(net.v.cpu().numpy() - wv) <= tv)
+    assert np.all(np.abs(net.params.cpu().numpy() - wp) <= tp)
     # bfloat16 weight layouts: forward [tap][co][ci], transposed [tap][ci][co]
     p = net.params.cpu().numpy()
     Ws, _ = ocnn.unpack(p)
@@ -235,13 +248,42 @@ def test_window_map_exact(lw):
     cd = rng.uniform(0, 48, (Hc, Wc)).astype(np.float32)
     cd[0, :4] = [0.0, 47.9, 1.9, 2.125]  # clamps at both ends, a .5 tie
     out = rng.normal(0, 1.5, (1, Hc, Wc, CH)).astype(np.float32)
-    for thr in (-1e30, 0.0, 0.7, 1e30):
+    out[0, 1, :3, 1] = 0.0  # logit exactly at the tau = 1/2 threshold: not confident
+    for tau in (0.0, 0.5, 0.8, 1.0):
         nfb = torch.zeros(1, dtype=torch.int32, device="cuda")
-        lo = lw.window_map(_dev(cd), _dev(out), W, H, D, w, thr, nfallback=nfb)
+        rows = torch.full((H,), 7, dtype=torch.int32, device="cuda")  # cleared by the call
+        mask = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+        lo = lw.window_map(_dev(cd), _dev(out), W, H, D, w, tau, mask=mask, row_fallback=rows, nfallback=nfb)
         torch.cuda.synchronize()
-        want, want_n = ocnn.window_map(cd, out, W, H, D, w, thr)
-        np.testing.assert_array_equal(lo.cpu().numpy(), want)
+        want, want_n, want_mask = ocnn.window_map(cd, out, W, H, D, w, tau)
+        np.testing.assert_array_equal(lo.cpu().numpy(), want, err_msg=str(tau))
+        np.testing.assert_array_equal(mask.cpu().numpy(), want_mask, err_msg=str(tau))
+        np.testing.assert_array_equal(rows.cpu().numpy(), want_mask.sum(axis=1), err_msg=str(tau))
         assert int(nfb.item()) == want_n
+    assert want_n == H * W  # tau = 1: every pixel falls back
+
+
+def test_fallback_merge(lw):
+    import torch
+    rng = np.random.default_rng(12)
+    H, W = 37, 300
+    wi = rng.integers(0, 50, (H, W)).astype(np.int16)
+    ws = rng.uniform(0, 50, (H, W)).astype(np.float32)
+    mask = (rng.random((H, W)) < 0.4).astype(np.uint8)
+    bands = [(0, 9), (20, 37)]
+    res = [(rng.integers(100, 190, (b - a, W)).astype(np.int16),
+            rng.uniform(100, 190, (b - a, W)).astype(np.float32)) for a, b in bands]
+    di, ds = _dev(wi), _dev(ws)
+    md = _dev(mask)
+    keep = []
+    for (a, b), (bi, bs) in zip(bands, res):
+        bid, bsd = _dev(bi), _dev(bs)
+        keep += [bid, bsd]
+        lw.fallback_merge(md, bid, bsd, a, b - a, di, ds)
+    torch.cuda.synchronize()
+    want_i, want_s = ocnn.merge_fallback(wi, ws, mask, bands, res)
+    np.testing.assert_array_equal(di.cpu().numpy(), want_i)
+    np.testing.assert_array_equal(ds.cpu().numpy(), want_s)
 
 
 def test_training_resume_is_bitwise(lw, tmp_path):
@@ -281,31 +323,79 @@ def test_training_resume_is_bitwise(lw, tmp_path):
     assert la[-1] < la[0]
 
 
-def test_learned_window_pipeline_stepwise(lw):
-    """Every stage of the learned-window matcher checked against the oracle
-    on the inputs that stage consumed."""
+def _road_pairs(name, seeds):
+    ps = [synth.make_pair(synth.scene_for_config(name, sd), sd) for sd in seeds]
+    return ps, np.stack([p.left for p in ps]), np.stack([p.right for p in ps])
+
+
+@pytest.mark.parametrize("fallback", ["most", "few"])
+def test_learned_window_pipeline_stepwise(lw, fallback):
+    """Every stage of the learned-window matcher, for a batch of two pairs,
+    checked against the oracle on the inputs that stage consumed; the
+    fallback bands are the oracle's own, from its own mask.  'few' sets tau
+    just above the lowest logits, so that only a few rows fall back."""
     import torch
-    pair = synth.make_pair(synth.scene_for_config("road320", 2), 2)
-    H, W = pair.left.shape
+    ps, L, R = _road_pairs("road320", [2, 3])
+    n, H, W = L.shape
     D, w = 64, 16
     net = lw.WindowNet(_params(11))
-    m = lw.LearnedWindowMatcher(W, H, ndisp=D, window=w, census=7, npaths=8, p1=10, p2=120, net=net,
-                                threshold=0.0)
-    dint, dsub, lo, nfb = m.match(_dev(pair.left), _dev(pair.right))
+    m = lw.LearnedWindowMatcher(W, H, batch=n, ndisp=D, window=w, census=7, npaths=8, p1=10, p2=120, net=net,
+                                tau=0.5, margin=8, full_fraction=0.75)
+    Ld, Rd = _dev(L), _dev(R)
+    dint, dsub = m.match(Ld, Rd)
     torch.cuda.synchronize()
-    Lc, Rc = oracle.downsample4(pair.left), oracle.downsample4(pair.right)
-    np.testing.assert_array_equal(m.cl.cpu().numpy(), Lc)
-    ci, cs = oracle.sgm(Lc, Rc, 7, D // 4, 8, 10, 120)
-    np.testing.assert_array_equal(m.cdi.cpu().numpy().astype(np.uint16), ci)
-    gcs = m.cds.cpu().numpy()
-    assert np.abs(gcs - cs).max() <= 1e-4
-    x0 = ocnn.prepare_input(gcs, Lc)
-    np.testing.assert_array_equal(_bf16_bits_to_f(m.x0)[0], ocnn.bf16(x0)[0])
-    _, want_out = ocnn.forward(net.params.cpu().numpy(), x0)
-    assert np.abs(m.out.cpu().numpy() - want_out).max() <= 0.02 * np.abs(want_out).max() + 1e-6
-    want_lo, want_n = ocnn.window_map(gcs, m.out.cpu().numpy(), W, H, D, w, 0.0)
-    np.testing.assert_array_equal(lo.cpu().numpy(), want_lo)
-    assert int(nfb.item()) == want_n
-    wi, ws = oracle.sgm_win(pair.left, pair.right, 7, w, 8, 10, 120, want_lo)
-    np.testing.assert_array_equal(dint.cpu().numpy().astype(np.uint16), wi)
-    assert np.abs(dsub.cpu().numpy() - ws).max() <= 1e-4
+    if fallback == "few":
+        logits = np.sort(m.out[..., 1].cpu().numpy().ravel())
+        m.tau = float(1.0 / (1.0 + np.exp(-0.5 * (logits[3] + logits[4]))))
+        dint, dsub = m.match(Ld, Rd)
+        torch.cuda.synchronize()
+        assert 0 < int(m.nfallback.sum()) <= 4 * 16
+        assert any(b and b != [(0, H)] for b in m.last_bands)
+    tau = m.tau
+    nfb_total = 0
+    for i in range(n):
+        Lc, Rc = oracle.downsample4(L[i]), oracle.downsample4(R[i])
+        np.testing.assert_array_equal(m.cl[i].cpu().numpy(), Lc)
+        ci, cs = oracle.sgm(Lc, Rc, 7, D // 4, 8, 10, 120)
+        np.testing.assert_array_equal(m.coarse.disp_int[i].cpu().numpy().astype(np.uint16), ci)
+        gcs = m.coarse.disp_sub[i].cpu().numpy()
+        assert np.abs(gcs - cs).max() <= 1e-4
+        x0 = ocnn.prepare_input(gcs, Lc)
+        np.testing.assert_array_equal(_bf16_bits_to_f(m.x0[i]), ocnn.bf16(x0)[0])
+        _, want_out = ocnn.forward(net.params.cpu().numpy(), x0)
+        gout = m.out[i:i + 1].cpu().numpy()
+        assert np.abs(gout - want_out).max() <= 0.02 * np.abs(want_out).max() + 1e-6
+        want_lo, want_n, want_mask = ocnn.window_map(gcs, gout, W, H, D, w, tau)
+        np.testing.assert_array_equal(m.lo[i].cpu().numpy(), want_lo)
+        np.testing.assert_array_equal(m.mask[i].cpu().numpy(), want_mask)
+        nfb_total += want_n
+        wi, ws = oracle.sgm_win(L[i], R[i], 7, w, 8, 10, 120, want_lo)
+        bands = ocnn.fallback_bands(want_mask, 8, 0.75)
+        assert m.last_bands[i] == bands
+        res = [oracle.sgm(L[i][a:b], R[i][a:b], 7, D, 8, 10, 120) for a, b in bands]
+        fi, fs = ocnn.merge_fallback(wi, ws, want_mask, bands, res)
+        np.testing.assert_array_equal(dint[i].cpu().numpy().astype(np.uint16), fi)
+        assert np.abs(dsub[i].cpu().numpy() - fs).max() <= 1e-4
+    assert int(m.nfallback.sum()) == nfb_total
+
+
+def test_full_fallback_is_plain_sgm(lw):
+    """tau = 1: no pixel is confident, and the learned-window form returns
+    plain full-range SGM of each frame, exactly."""
+    import torch
+    from paper_2012_10802_amd import sgm as S
+    ps, L, R = _road_pairs("road320", [5, 6])
+    n, H, W = L.shape
+    D = 64
+    m = lw.LearnedWindowMatcher(W, H, batch=n, ndisp=D, window=16, net=lw.WindowNet(_params(2)), tau=1.0)
+    Ld, Rd = _dev(L), _dev(R)
+    dint, dsub = m.match(Ld, Rd)
+    plain = S.Matcher(W, H, census=7, ndisp=D, npaths=8, p1=10, p2=120)
+    for i in range(n):
+        pi, pf = plain.match(Ld[i], Rd[i])
+        torch.cuda.synchronize()
+        assert m.last_bands[i] == [(0, H)]
+        np.testing.assert_array_equal(dint[i].cpu().numpy(), pi.cpu().numpy())
+        np.testing.assert_array_equal(dsub[i].cpu().numpy(), pf.cpu().numpy())
+        wi, _ = oracle.sgm(L[i], R[i], 7, D, 8, 10, 120)
+        np.testing.assert_array_equal(dint[i].cpu().numpy().astype(np.uint16), wi)

@@ -71,9 +71,66 @@ def test_window_map_fallback_and_clamps():
     out = np.zeros((1, 2, 2, cnn.CH), np.float32)
     out[0, :, :, 0] = [[1.0, -0.5], [0.0, 3.0]]
     out[0, :, :, 1] = [[5.0, -5.0], [5.0, 5.0]]
-    lo, nfb = cnn.window_map(coarse, out, 8, 8, 192, 16, 0.0)
+    lo, nfb, mask = cnn.window_map(coarse, out, 8, 8, 192, 16, 0.5)
     assert nfb == 4 * 4  # one coarse pixel of four falls back, 16 full pixels
+    assert mask[:4, 4:].all() and mask.sum() == 16
     assert lo[0, 0] == 4 * 3 - 8           # confident: 4 * (2 + 1) = 12 -> 4
     assert lo[0, 4] == 41 - 8              # fallback: 4 * 10.25 = 41
     assert lo[4, 0] == 0                   # clamped below
     assert lo[4, 4] == 192 - 16            # 4 * 50.9 -> clamped above
+    # tau = 1 sends every pixel to the fallback, tau = 0 none
+    assert cnn.window_map(coarse, out, 8, 8, 192, 16, 1.0)[1] == 64
+    assert cnn.window_map(coarse, out, 8, 8, 192, 16, 0.0)[1] == 0
+
+
+def test_confidence_threshold_is_the_logit():
+    for tau in (0.1, 0.5, 0.73, 0.99):
+        t = float(cnn.confidence_threshold(tau))
+        assert abs(1.0 / (1.0 + np.exp(-t)) - tau) < 1e-6
+    assert cnn.confidence_threshold(0.5) == 0.0
+
+
+def test_prepare_input_border_channel():
+    cd = np.array([[0.0, 3.0, 1.5, 0.0]], np.float32)
+    left = np.array([[0, 255, 51, 128]], np.uint8)
+    x = cnn.prepare_input(cd, left)
+    np.testing.assert_allclose(x[0, 0, :, 2], [0.0, -2.0 / 16, 0.5 / 16, 3.0 / 16])
+    np.testing.assert_allclose(x[0, 0, :, 0], cd[0] / 16)
+    np.testing.assert_allclose(x[0, 0, :, 1], left[0] / 255.0 - 0.5, atol=1e-7)
+    assert not x[..., 3:].any()
+    far = cnn.prepare_input(np.zeros((1, 40), np.float32), np.zeros((1, 40), np.uint8))
+    assert far[0, 0, 39, 2] == 1.0  # saturates at 16 columns
+
+
+def test_fallback_bands():
+    H = 200
+    m = np.zeros((H, 5), np.uint8)
+    assert cnn.fallback_bands(m, 32, 0.75) == []
+    m[100, 2] = 1
+    assert cnn.fallback_bands(m, 32, 0.75) == [(68, 133)]
+    m[10, 0] = 1
+    m[150, 4] = 1  # touches the band of row 100 once widened
+    assert cnn.fallback_bands(m, 32, 0.8) == [(0, 43), (68, 183)]  # 158 rows
+    assert cnn.fallback_bands(m, 32, 0.75) == [(0, H)]
+    m[:] = 1
+    assert cnn.fallback_bands(m, 32, 0.75) == [(0, H)]
+    m[:] = 0
+    m[0, 0] = m[H - 1, 0] = 1
+    assert cnn.fallback_bands(m, 10, 0.75) == [(0, 11), (H - 11, H)]
+
+
+def test_merge_fallback_takes_band_results_on_masked_pixels():
+    rng = np.random.default_rng(3)
+    H, W = 12, 7
+    wi = rng.integers(0, 50, (H, W)).astype(np.uint16)
+    ws = wi.astype(np.float32) + 0.25
+    mask = (rng.random((H, W)) < 0.3).astype(np.uint8)
+    mask[:3] = 0
+    bands = [(2, 12)]
+    bi = rng.integers(100, 150, (10, W)).astype(np.uint16)
+    bs = bi.astype(np.float32) - 0.25
+    di, ds = cnn.merge_fallback(wi, ws, mask, bands, [(bi, bs)])
+    m = mask.astype(bool)
+    assert (di[m] >= 100).all() and (di[~m] < 50).all()
+    np.testing.assert_array_equal(di[2:][m[2:]], bi[m[2:]])
+    np.testing.assert_array_equal(ds[~m], ws[~m])

@@ -373,6 +373,22 @@ def test_generator_ground_truth_is_the_road_model():
     assert (p.gt[p.pothole] < f[p.pothole]).all()
 
 
+def test_torch_renderer_matches_generator():
+    """The torch renderer (used for training data) draws the same scene:
+    identical clean images, road mask and ground truth."""
+    import dataclasses
+    s = dataclasses.replace(synth.scene_for_config("road640", 4), noise_sigma=0.0)
+    p = synth.make_pair(s, 4)
+    left, right, gt, road = synth.make_pair_torch(s, 4, device="cpu", noise=False)
+    np.testing.assert_array_equal(left.numpy(), p.left)
+    np.testing.assert_array_equal(right.numpy(), p.right)
+    np.testing.assert_array_equal(road.numpy(), p.road)
+    assert np.abs(gt.numpy() - p.gt).max() < 1e-5
+    noisy_l, _, _, _ = synth.make_pair_torch(dataclasses.replace(s, noise_sigma=2.0), 4, device="cpu")
+    diff = noisy_l.numpy().astype(float) - p.left
+    assert 1.5 < diff.std() < 2.5
+
+
 # ---------------------------------------------------------------------------
 # per-pixel windows in absolute disparity (learned-window form)
 
