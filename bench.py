@@ -147,6 +147,111 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def learned_vs_plain(args, log=None):
+    """The learned-window form against plain full-range SGM on held-out
+    1920x1080 road pairs (disparities 0..191, census 7x7, 8 paths), batches
+    of 16: wall time per batch and the bad-pixel rate (> 1 px) against the
+    generator's ground truth over the evaluation mask."""
+    import numpy as np
+    import torch
+
+    from paper_2012_10802_amd import learned_window as LW
+    from paper_2012_10802_amd import sgm, synth
+
+    dev = torch.device("cuda:0")
+    c = synth.CONFIGS["road1920"]
+    W, H, D = c["width"], c["height"], c["ndisp"]
+    n_cen, R, p1, p2 = c["census"], c["npaths"], c["p1"], c["p2"]
+    B = 16
+    r = n_cen // 2
+    net = LW.WindowNet.load(args.weights, device=dev)
+    L = torch.empty((B, H, W), dtype=torch.uint8, device=dev)
+    Rt = torch.empty_like(L)
+    plain = sgm.Batch([dict(left=L[i], right=Rt[i], ndisp=D) for i in range(B)], census=n_cen, npaths=R,
+                      p1=p1, p2=p2, device=dev)
+    lw = LW.LearnedWindowMatcher(W, H, batch=B, ndisp=D, window=16, census=n_cen, npaths=R, p1=p1, p2=p2,
+                                 net=net, tau=args.tau, device=dev)
+    stream = torch.cuda.Stream()
+    uu = torch.arange(W, device=dev)[None, :]
+    tot = {"pix": 0, "bad_plain": 0, "bad_learned": 0, "miss": 0, "conf_pix": 0, "fallback": 0,
+           "rect_area": 0}
+    t_plain, t_learned = [], []
+    nb = max(1, args.eval_pairs // B)
+    with torch.cuda.stream(stream):
+        plain.capture(stream)
+        for b in range(nb):
+            gts, masks = [], []
+            for j in range(B):
+                sd = args.seed + 10_000_000 + b * B + j
+                l, rr, gt, road = synth.make_pair_torch(synth.scene_for_config("road1920", sd), sd, device=dev)
+                L[j].copy_(l)
+                Rt[j].copy_(rr)
+                m = road & (gt < D - 1) & ((uu - gt) >= r)
+                m[:r] = False
+                m[-r:] = False
+                m[:, :r] = False
+                m[:, -r:] = False
+                gts.append(gt)
+                masks.append(m)
+            stream.synchronize()
+            reps = []
+            for k in range(args.lw_reps + 1):
+                stream.synchronize()
+                t0 = time.perf_counter()
+                plain.launch(stream)
+                stream.synchronize()
+                if k:
+                    reps.append(time.perf_counter() - t0)
+            t_plain.append(float(np.median(reps)))
+            reps = []
+            for k in range(args.lw_reps + 1):
+                stream.synchronize()
+                t0 = time.perf_counter()
+                lw.match(L, Rt, stream)
+                stream.synchronize()
+                if k:
+                    reps.append(time.perf_counter() - t0)
+            t_learned.append(float(np.median(reps)))
+            for j in range(B):
+                m = masks[j]
+                e_p = (plain.disp_sub[j] - gts[j]).abs()
+                e_l = (lw.dsub[j] - gts[j]).abs()
+                tot["pix"] += int(m.sum())
+                tot["bad_plain"] += int(((e_p > 1.0) & m).sum())
+                tot["bad_learned"] += int(((e_l > 1.0) & m).sum())
+                conf = m & (lw.mask[j] == 0)
+                d = plain.disp_int[j].int()
+                lo = lw.lo[j]
+                tot["miss"] += int((conf & ((d < lo) | (d >= lo + 16))).sum())
+                tot["conf_pix"] += int(conf.sum())
+                tot["fallback"] += int(lw.nfallback[j])
+                tot["rect_area"] += sum((y1 - y0) * (x1 - x0) for y0, y1, x0, x1 in lw.last_rects[j])
+            if log:
+                log("learned-window batch %d/%d: plain %.2f ms, learned %.2f ms"
+                    % (b + 1, nb, t_plain[-1] * 1e3, t_learned[-1] * 1e3))
+    npairs = nb * B
+    bp = 100.0 * tot["bad_plain"] / tot["pix"]
+    bl = 100.0 * tot["bad_learned"] / tot["pix"]
+    return {
+        "workload": "%d held-out 1920x1080 road pairs in batches of %d, disparities 0-191, census 7x7, "
+                    "8 paths, P1=10, P2=120" % (npairs, B),
+        "ms_per_batch_plain": round(1e3 * float(np.mean(t_plain)), 3),
+        "ms_per_batch_learned": round(1e3 * float(np.mean(t_learned)), 3),
+        "speedup": round(float(np.mean(t_plain)) / float(np.mean(t_learned)), 3),
+        "bad_1px_pct_plain": round(bp, 4),
+        "bad_1px_pct_learned": round(bl, 4),
+        "bad_1px_delta_points": round(bl - bp, 4),
+        "fallback_pixel_pct": round(100.0 * tot["fallback"] / (npairs * W * H), 4),
+        "fallback_area_pct": round(100.0 * tot["rect_area"] / (npairs * W * H), 3),
+        "window_miss_pct_vs_full_range": round(100.0 * tot["miss"] / max(1, tot["conf_pix"]), 4),
+        "tau": args.tau,
+        "window": 16,
+        "pixels_scored": tot["pix"],
+        "timing": "host wall clock around each batch (learned includes its one host read of the "
+                  "fallback rows), median of %d after one warm-up, mean over batches" % args.lw_reps,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +265,13 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="batch mode: autotuner cache file")
     ap.add_argument("--seed", type=int, default=2001)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-window vs plain comparison")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2012_10802_amd", "window_cnn.npz"))
+    ap.add_argument("--tau", type=float, default=0.5, help="confidence threshold of the learned windows")
+    ap.add_argument("--eval-pairs", type=int, default=64)
+    ap.add_argument("--lw-reps", type=int, default=3)
+    ap.add_argument("--learned-only", action="store_true", help="print only the learned-window comparison")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(reference kernel for scaling memory counters)")
@@ -171,6 +283,12 @@ def main():
         sys.exit(2)
     if args.mode == "batch" or args.workload == "road_batch64":
         return run_batch(args)
+    if args.learned_only:
+        import torch
+        torch.cuda.set_device(0)
+        res = learned_vs_plain(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
+        print(json.dumps(res), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -265,6 +383,10 @@ def main():
                "sample": "one full %dx%dx%d frame through the C oracle (census, cost, %d paths, "
                          "selection), %.1f s wall" % (W, H, w, R, dt)}
 
+    learned = None
+    if not args.no_learned and os.path.exists(args.weights):
+        learned = learned_vs_plain(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
+
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -286,6 +408,7 @@ def main():
         "kernels_ms": {"cost": round(cost_ms, 4), "aggregate": round(agg_ms, 4),
                        "wta": round(wta_ms, 4)},
         "accuracy": accuracy,
+        "learned_window": learned,
         "cpu_baseline": cpu,
         "kernel_source_sha256": kernel_source_digest(),
     }

@@ -244,21 +244,24 @@ sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, in
  * ndisp - w), full pixel (x, y) reading coarse pixel (min(x/4, Wc-1),
  * min(y/4, Hc-1)).  A pixel is confident when logit > log(tau / (1 - tau))
  * (tau <= 0: every pixel, tau >= 1: none).  Optional outputs (NULL to
- * skip): fallback_mask uint8 [H][W] (1 = falls back), row_fallback uint32
- * [H] fallback pixels per row, nfallback uint32 total; the counters are
- * cleared by this call.  coarse_disp and cnn_out are [Hc][Wc] and
- * [Hc][Wc][16] float32. */
+ * skip): fallback_mask uint8 [H][W] (1 = falls back); row_stats int32
+ * [3][H]: per row the number of fallback pixels, the leftmost and the
+ * rightmost fallback column (W and -1 for a row without any); nfallback
+ * uint32, the total.  The statistics are cleared by this call.
+ * coarse_disp and cnn_out are [Hc][Wc] and [Hc][Wc][16] float32. */
 sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_t coarse_width,
                           int32_t coarse_height, int32_t width, int32_t height, int32_t ndisp,
                           int32_t w, float conf_threshold, int32_t *lo, uint8_t *fallback_mask,
-                          uint32_t *row_fallback, uint32_t *nfallback, void *stream);
-/* The full-range fallback: full-range SGM of rows y0 .. y0+rows-1 (band_int
- * int16 / band_sub float32, [rows][width], band_sub may be NULL) replaces
- * the windowed result in disp_int / disp_sub ([height][width]) on the
- * pixels that fallback_mask marks.  Other pixels are left as they are. */
+                          int32_t *row_stats, uint32_t *nfallback, void *stream);
+/* The full-range fallback: the full-range SGM result of the rectangle rows
+ * y0 .. y0+rows-1, columns x0 .. x0+cols-1 (band_int int16 / band_sub
+ * float32, [rows][cols], band_sub may be NULL) replaces the windowed result
+ * in disp_int / disp_sub ([height][width]) on the pixels of the rectangle
+ * that fallback_mask marks.  Other pixels are left as they are. */
 sgm_status sgm_fallback_merge(const uint8_t *fallback_mask, const int16_t *band_int,
                               const float *band_sub, int32_t width, int32_t height, int32_t y0,
-                              int32_t rows, int16_t *disp_int, float *disp_sub, void *stream);
+                              int32_t rows, int32_t x0, int32_t cols, int16_t *disp_int,
+                              float *disp_sub, void *stream);
 /* Training target at the coarse level: mean of each 4 x 4 block of a full-
  * resolution disparity map, divided by 4 (coarse pixels). */
 sgm_status sgm_label_downsample4(const float *label, int32_t width, int32_t height, float *coarse,

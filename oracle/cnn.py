@@ -174,32 +174,41 @@ def window_map(coarse_disp, out, W, H, D, w, tau):
     return np.clip(lo, 0, D - w).astype(np.int32), int(mask.sum()), mask
 
 
-def fallback_bands(mask, margin, full_fraction):
-    """Row bands for the full-range fallback: every row holding a fallback
-    pixel, widened by `margin` rows on both sides, overlapping or touching
-    bands joined; when the bands cover more than `full_fraction` of the rows
-    the whole frame is one band.  Returns a list of (y0, y1)."""
-    H = mask.shape[0]
+def fallback_rects(mask, margin, full_fraction, ndisp, r):
+    """Rectangles (y0, y1, x0, x1) for the full-range fallback.  Rows that
+    hold a fallback pixel, widened by `margin` rows both ways, form bands
+    (overlapping or touching ones joined).  A band spans the columns of its
+    fallback pixels, widened by margin + r on the right and by
+    margin + (ndisp - 1) + r on the left, so that every disparity of the
+    widened region finds its right-image pixel (and census neighbours)
+    inside the rectangle.  When the rectangles would cover more than
+    `full_fraction` of the frame, the whole frame is one rectangle."""
+    H, W = mask.shape
     rows = [y for y in range(H) if mask[y].any()]
-    bands = []
+    bands = []  # [y0, y1, xmin, xmax]
     for y in rows:
+        cols = [x for x in range(W) if mask[y, x]]
         a, b = max(0, y - margin), min(H, y + margin + 1)
         if bands and a <= bands[-1][1]:
-            bands[-1] = (bands[-1][0], max(bands[-1][1], b))
+            bands[-1][1] = max(bands[-1][1], b)
+            bands[-1][2] = min(bands[-1][2], cols[0])
+            bands[-1][3] = max(bands[-1][3], cols[-1])
         else:
-            bands.append((a, b))
-    if sum(b - a for a, b in bands) > full_fraction * H:
-        return [(0, H)]
-    return bands
+            bands.append([a, b, cols[0], cols[-1]])
+    rects = [(a, b, max(0, xl - margin - (ndisp - 1) - r), min(W, xr + margin + r + 1))
+             for a, b, xl, xr in bands]
+    if sum((b - a) * (x1 - x0) for a, b, x0, x1 in rects) > full_fraction * H * W:
+        return [(0, H, 0, W)]
+    return rects
 
 
-def merge_fallback(win_int, win_sub, mask, bands, band_results):
+def merge_fallback(win_int, win_sub, mask, rects, results):
     """Final disparities: the windowed result, replaced on fallback pixels by
-    the full-range result of the band that holds their row."""
+    the full-range result of the rectangle that holds them."""
     dint = np.array(win_int, copy=True)
     dsub = np.array(win_sub, copy=True)
-    for (y0, y1), (bi, bs) in zip(bands, band_results):
-        m = mask[y0:y1].astype(bool)
-        dint[y0:y1][m] = bi[m]
-        dsub[y0:y1][m] = bs[m]
+    for (y0, y1, x0, x1), (bi, bs) in zip(rects, results):
+        m = mask[y0:y1, x0:x1].astype(bool)
+        dint[y0:y1, x0:x1][m] = bi[m]
+        dsub[y0:y1, x0:x1][m] = bs[m]
     return dint, dsub

@@ -262,18 +262,24 @@ __global__ void k_adam(float *__restrict__ params, float *__restrict__ m, float 
     }
 }
 
-__global__ void k_zero_u32(uint32_t *__restrict__ a, int n)
+__global__ void k_clear_stats(int32_t *__restrict__ row_stats, int H, int W, uint32_t *__restrict__ nfallback)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = 0u;
+    if (row_stats && i < H) {
+        row_stats[i] = 0;          // fallback pixels in the row
+        row_stats[H + i] = W;      // leftmost fallback column
+        row_stats[2 * H + i] = -1; // rightmost fallback column
+    }
+    if (nfallback && i == 0) *nfallback = 0u;
 }
 
 // One row of full-resolution pixels per grid row; block of 256 along x.
-// Fallback counts are reduced per wave (ballot) before one atomic add.
+// Fallback counts and column extents are reduced per wave (the lanes of a
+// wave hold 64 consecutive columns) before one atomic per wave.
 __global__ __launch_bounds__(256) void k_window_map(const float *__restrict__ coarse, const float *__restrict__ out,
                                                     int Wc, int Hc, int W, int H, int D, int w, float thr,
                                                     int32_t *__restrict__ lo, uint8_t *__restrict__ mask,
-                                                    uint32_t *__restrict__ row_count, uint32_t *__restrict__ nfallback)
+                                                    int32_t *__restrict__ row_stats, uint32_t *__restrict__ nfallback)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     bool fb = false;
@@ -289,21 +295,27 @@ __global__ __launch_bounds__(256) void k_window_map(const float *__restrict__ co
         if (mask) mask[(size_t)y * W + x] = conf ? 0 : 1;
         fb = !conf;
     }
-    const uint32_t cnt = (uint32_t)__popcll(__ballot(fb));
-    if ((threadIdx.x & 63) == 0 && cnt) {
-        if (row_count) atomicAdd(row_count + y, cnt);
-        if (nfallback) atomicAdd(nfallback, cnt);
+    const unsigned long long bal = __ballot(fb);
+    if ((threadIdx.x & 63) == 0 && bal) {
+        const int xw = x;  // column of lane 0 of this wave
+        if (row_stats) {
+            atomicAdd(row_stats + y, (int)__popcll(bal));
+            atomicMin(row_stats + H + y, xw + (int)__ffsll((long long)bal) - 1);
+            atomicMax(row_stats + 2 * H + y, xw + 63 - (int)__clzll((long long)bal));
+        }
+        if (nfallback) atomicAdd(nfallback, (uint32_t)__popcll(bal));
     }
 }
 
-// Fallback pixels of rows y0 .. y0+rows-1 take the band's full-range result.
+// Fallback pixels of the rectangle (rows y0.., columns x0..) take the
+// rectangle's full-range result.
 __global__ void k_merge_fallback(const uint8_t *__restrict__ mask, const int16_t *__restrict__ band_int,
-                                 const float *__restrict__ band_sub, int W, int y0, int rows, int16_t *__restrict__ dint,
-                                 float *__restrict__ dsub)
+                                 const float *__restrict__ band_sub, int W, int y0, int rows, int x0, int cols,
+                                 int16_t *__restrict__ dint, float *__restrict__ dsub)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
-    if (x >= W || r >= rows) return;
-    const size_t o = (size_t)(y0 + r) * W + x, b = (size_t)r * W + x;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= cols || r >= rows) return;
+    const size_t o = (size_t)(y0 + r) * W + x0 + c, b = (size_t)r * cols + c;
     if (!mask[o]) return;
     dint[o] = band_int[b];
     if (dsub && band_sub) dsub[o] = band_sub[b];
@@ -460,7 +472,7 @@ sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, in
 
 sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_t coarse_width, int32_t coarse_height,
                           int32_t width, int32_t height, int32_t ndisp, int32_t w, float conf_threshold, int32_t *lo,
-                          uint8_t *fallback_mask, uint32_t *row_fallback, uint32_t *nfallback, void *stream)
+                          uint8_t *fallback_mask, int32_t *row_stats, uint32_t *nfallback, void *stream)
 {
     if (!coarse_disp || !cnn_out || !lo) return cfail(SGM_ERR_INVALID, "NULL buffer");
     if (coarse_width < 1 || coarse_height < 1 || width < 1 || height < 1 || w < 1 || w > ndisp || ndisp > 256)
@@ -475,26 +487,27 @@ sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_
     else
         thr = (float)log((double)conf_threshold / (1.0 - (double)conf_threshold));
     hipStream_t s = (hipStream_t)stream;
-    if (row_fallback)
-        hipLaunchKernelGGL(k_zero_u32, dim3((height + 255) / 256), dim3(256), 0, s, row_fallback, (int)height);
-    if (nfallback) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, nfallback, 1);
+    if (row_stats || nfallback)
+        hipLaunchKernelGGL(k_clear_stats, dim3((height + 255) / 256), dim3(256), 0, s, row_stats, (int)height,
+                           (int)width, nfallback);
     dim3 grid((width + 255) / 256, height), block(256);
     hipLaunchKernelGGL(k_window_map, grid, block, 0, s, coarse_disp, cnn_out, coarse_width, coarse_height, width,
-                       height, ndisp, w, thr, lo, fallback_mask, row_fallback, nfallback);
+                       height, ndisp, w, thr, lo, fallback_mask, row_stats, nfallback);
     return launched("window map");
 }
 
 sgm_status sgm_fallback_merge(const uint8_t *fallback_mask, const int16_t *band_int, const float *band_sub,
-                              int32_t width, int32_t height, int32_t y0, int32_t rows, int16_t *disp_int,
-                              float *disp_sub, void *stream)
+                              int32_t width, int32_t height, int32_t y0, int32_t rows, int32_t x0, int32_t cols,
+                              int16_t *disp_int, float *disp_sub, void *stream)
 {
     if (!fallback_mask || !band_int || !disp_int) return cfail(SGM_ERR_INVALID, "NULL buffer");
-    if (width < 1 || height < 1 || y0 < 0 || rows < 0 || y0 + rows > height)
-        return cfail(SGM_ERR_INVALID, "band outside the frame");
-    if (rows == 0) return SGM_OK;
-    dim3 grid((width + 255) / 256, rows), block(256);
+    if (width < 1 || height < 1 || y0 < 0 || rows < 0 || y0 + rows > height || x0 < 0 || cols < 0 ||
+        x0 + cols > width)
+        return cfail(SGM_ERR_INVALID, "rectangle outside the frame");
+    if (rows == 0 || cols == 0) return SGM_OK;
+    dim3 grid((cols + 255) / 256, rows), block(256);
     hipLaunchKernelGGL(k_merge_fallback, grid, block, 0, (hipStream_t)stream, fallback_mask, band_int, band_sub,
-                       width, y0, rows, disp_int, disp_sub);
+                       width, y0, rows, x0, cols, disp_int, disp_sub);
     return launched("fallback merge");
 }
 

@@ -14,11 +14,13 @@ the C ABI:
      are marked for the fallback (their window, centred on 4 * coarse, still
      feeds the windowed aggregation of their neighbours);
   5. SGM over the per-pixel windows at full resolution;
-  6. the full-range fallback: plain SGM over all ndisp disparities on the
-     row bands that hold marked pixels (widened by a margin, joined when they
-     touch, the whole frame once they cover most of it), whose result
-     replaces the windowed one on the marked pixels.  With every pixel
-     marked the output is plain full-range SGM of the frame, exactly.
+  6. the full-range fallback: plain SGM over all ndisp disparities on
+     rectangles around the marked pixels (their rows and columns widened by
+     a margin, and by ndisp - 1 more columns to the left so that every
+     disparity finds its right-image pixel; the whole frame once they cover
+     most of it), whose result replaces the windowed one on the marked
+     pixels.  With every pixel marked the output is plain full-range SGM of
+     the frame, exactly.
 
 The network is the project's own addition: the paper's windows come from
 its road model (Sec. II-A, eq. (3) and (6)) one per row; here a window is
@@ -172,44 +174,57 @@ def label_downsample4(label, out=None, stream=None):
     return out
 
 
-def window_map(coarse_disp, out, W, H, ndisp, w, tau, lo=None, mask=None, row_fallback=None,
+def window_map(coarse_disp, out, W, H, ndisp, w, tau, lo=None, mask=None, row_stats=None,
                nfallback=None, stream=None):
     Hc, Wc = coarse_disp.shape[-2:]
     if lo is None:
         lo = torch.empty((H, W), dtype=torch.int32, device=coarse_disp.device)
     S._check(_lib.sgm_window_map(_c(coarse_disp), _c(out), Wc, Hc, W, H, ndisp, w, float(tau), _c(lo),
-                                 _c(mask), _c(row_fallback), _c(nfallback), S._stream(stream)),
+                                 _c(mask), _c(row_stats), _c(nfallback), S._stream(stream)),
              "sgm_window_map")
     return lo
 
 
-def fallback_merge(mask, band_int, band_sub, y0, rows, disp_int, disp_sub, stream=None):
+def fallback_merge(mask, band_int, band_sub, y0, x0, disp_int, disp_sub, stream=None):
     H, W = disp_int.shape
-    S._check(_lib.sgm_fallback_merge(_c(mask), _c(band_int), _c(band_sub), W, H, int(y0), int(rows),
-                                     _c(disp_int), _c(disp_sub), S._stream(stream)), "sgm_fallback_merge")
+    rows, cols = band_int.shape
+    S._check(_lib.sgm_fallback_merge(_c(mask), _c(band_int), _c(band_sub), W, H, int(y0), int(rows), int(x0),
+                                     int(cols), _c(disp_int), _c(disp_sub), S._stream(stream)),
+             "sgm_fallback_merge")
 
 
-def fallback_bands(row_counts, margin=32, full_fraction=0.75):
-    """Row bands [(y0, y1)] for the full-range fallback from per-row counts
-    of fallback pixels: each such row widened by `margin` rows both ways,
-    overlapping or touching bands joined, and the whole frame as one band
-    when they would cover more than `full_fraction` of the rows."""
-    counts = np.asarray(row_counts)
-    H = counts.shape[0]
-    flagged = np.flatnonzero(counts > 0)
+def fallback_rects(row_stats, W, ndisp, r, margin=32, full_fraction=0.5):
+    """Rectangles [(y0, y1, x0, x1)] for the full-range fallback from the
+    per-row statistics of the window map (int32 [3, H]: fallback count,
+    leftmost and rightmost fallback column).  Each row with fallback pixels
+    is widened by `margin` rows both ways; overlapping or touching rows form
+    one band, whose columns span its fallback pixels widened by margin + r
+    on the right and margin + ndisp - 1 + r on the left (every disparity of
+    the widened region then reads its right-image pixel, and the census
+    neighbours, inside the rectangle).  Past `full_fraction` of the frame's
+    area the whole frame is one rectangle."""
+    stats = np.asarray(row_stats)
+    count, xmin, xmax = stats[0], stats[1], stats[2]
+    H = count.shape[0]
+    flagged = np.flatnonzero(count > 0)
     if flagged.size == 0:
         return []
     lo = np.maximum(flagged - margin, 0)
     hi = np.minimum(flagged + margin + 1, H)
-    # a new band starts where the widened row does not reach the previous one
+    # a new band starts where the widened row does not reach the previous ones
     starts = np.ones(flagged.size, bool)
     starts[1:] = lo[1:] > np.maximum.accumulate(hi)[:-1]
     idx = np.flatnonzero(starts)
     ends = np.r_[idx[1:], flagged.size]
-    bands = [(int(lo[a]), int(hi[a:b].max())) for a, b in zip(idx, ends)]
-    if sum(b - a for a, b in bands) > full_fraction * H:
-        return [(0, H)]
-    return bands
+    rects = []
+    for a, b in zip(idx, ends):
+        rows = flagged[a:b]
+        xl, xr = int(xmin[rows].min()), int(xmax[rows].max())
+        rects.append((int(lo[a]), int(hi[a:b].max()), max(0, xl - margin - (ndisp - 1) - r),
+                      min(W, xr + margin + r + 1)))
+    if sum((y1 - y0) * (x1 - x0) for y0, y1, x0, x1 in rects) > full_fraction * H * W:
+        return [(0, H, 0, W)]
+    return rects
 
 
 class LearnedWindowMatcher:
@@ -217,7 +232,7 @@ class LearnedWindowMatcher:
     full-range fallback, for batches of `batch` pairs of one size."""
 
     def __init__(self, width, height, batch=1, ndisp=192, window=16, census=7, npaths=8, p1=10,
-                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.75, device="cuda"):
+                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, device="cuda"):
         if width % 4 or height % 4 or ndisp % 4:
             raise ValueError("width, height and ndisp must be multiples of 4")
         self.W, self.H, self.D, self.w, self.n = width, height, ndisp, window, batch
@@ -237,33 +252,36 @@ class LearnedWindowMatcher:
                               device=dev)
         self.lo = torch.empty((n, height, width), dtype=torch.int32, device=dev)
         self.mask = torch.empty((n, height, width), dtype=torch.uint8, device=dev)
-        self.rows = torch.zeros((n, height), dtype=torch.int32, device=dev)
+        self.stats = torch.zeros((n, 3, height), dtype=torch.int32, device=dev)
         self.nfallback = torch.zeros((n,), dtype=torch.int32, device=dev)
         self.dint = torch.empty((n, height, width), dtype=torch.int16, device=dev)
         self.dsub = torch.empty((n, height, width), dtype=torch.float32, device=dev)
-        # full-range fallback: one workspace sized for the whole frame, plans per band height
+        # full-range fallback: one workspace sized for the whole frame, plans per rectangle size
         full = S.sgm_plan(width, height, census, ndisp, npaths, p1, p2)
         try:
             need = S.sgm_workspace_size(full)
         finally:
             S.sgm_plan_free(full)
         self.full_ws = torch.empty(need, dtype=torch.uint8, device=dev)
-        self.band_int = torch.empty((height, width), dtype=torch.int16, device=dev)
-        self.band_sub = torch.empty((height, width), dtype=torch.float32, device=dev)
+        self.band_int = torch.empty(height * width, dtype=torch.int16, device=dev)
+        self.band_sub = torch.empty(height * width, dtype=torch.float32, device=dev)
         self._full = {}
-        self.last_bands = []
+        self.last_rects = []
 
-    def _full_matcher(self, rows):
-        m = self._full.get(rows)
+    def _full_matcher(self, rows, cols):
+        key = (rows, cols)
+        m = self._full.pop(key, None)
         if m is None:
-            m = S.Matcher(self.W, rows, census=self.census, ndisp=self.D, npaths=self.npaths, p1=self.p1,
+            m = S.Matcher(cols, rows, census=self.census, ndisp=self.D, npaths=self.npaths, p1=self.p1,
                           p2=self.p2, device=self.device, workspace=self.full_ws)
-            self._full[rows] = m
+            while len(self._full) >= 256:  # plans are host objects; keep the most recent
+                self._full.pop(next(iter(self._full)))
+        self._full[key] = m
         return m
 
     def windows(self, left, right, stream=None):
-        """Steps 1-5 for left, right uint8 [n, H, W]; returns nothing, fills
-        lo, mask, rows, dint, dsub."""
+        """Steps 1-5 for left, right uint8 [n, H, W]: fills lo, mask, stats,
+        nfallback, dint and dsub."""
         n = self.n
         if tuple(left.shape) != (n, self.H, self.W) or tuple(right.shape) != (n, self.H, self.W):
             raise ValueError("left and right must be uint8 [%d, %d, %d]" % (n, self.H, self.W))
@@ -276,24 +294,24 @@ class LearnedWindowMatcher:
         self.net.forward(self.x0, self.acts, self.out, self.Wc, self.Hc, n, stream)
         for i in range(n):
             window_map(self.coarse.disp_sub[i], self.out[i], self.W, self.H, self.D, self.w, self.tau,
-                       self.lo[i], self.mask[i], self.rows[i], self.nfallback[i:i + 1], stream)
+                       self.lo[i], self.mask[i], self.stats[i], self.nfallback[i:i + 1], stream)
             self.fine.match_win(left[i], right[i], self.lo[i], disp_int=self.dint[i], disp_sub=self.dsub[i],
                                 stream=stream)
 
     def fallback(self, left, right, stream=None):
-        """Step 6 (synchronises once to read the per-row counts)."""
-        counts = self.rows.cpu().numpy()
-        self.last_bands = []
+        """Step 6 (synchronises once to read the per-row statistics)."""
+        stats = self.stats.cpu().numpy()
+        self.last_rects = []
         for i in range(self.n):
-            bands = fallback_bands(counts[i], self.margin, self.full_fraction)
-            self.last_bands.append(bands)
-            for y0, y1 in bands:
-                h = y1 - y0
-                m = self._full_matcher(h)
-                m.match(left[i][y0:y1], right[i][y0:y1], disp_int=self.band_int[:h], disp_sub=self.band_sub[:h],
-                        stream=stream)
-                fallback_merge(self.mask[i], self.band_int[:h], self.band_sub[:h], y0, h, self.dint[i],
-                               self.dsub[i], stream)
+            rects = fallback_rects(stats[i], self.W, self.D, self.census // 2, self.margin, self.full_fraction)
+            self.last_rects.append(rects)
+            for y0, y1, x0, x1 in rects:
+                h, w = y1 - y0, x1 - x0
+                bi = self.band_int[:h * w].view(h, w)
+                bs = self.band_sub[:h * w].view(h, w)
+                self._full_matcher(h, w).match_at(left[i], right[i], y0, x0, disp_int=bi, disp_sub=bs,
+                                                  stream=stream)
+                fallback_merge(self.mask[i], bi, bs, y0, x0, self.dint[i], self.dsub[i], stream)
 
     def match(self, left, right, stream=None):
         """Returns (disp_int int16 [n,H,W], disp_sub float32 [n,H,W]) device tensors."""

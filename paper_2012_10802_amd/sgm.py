@@ -89,7 +89,7 @@ def _load_library():
         "sgm_cnn_adam": [P, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                          ctypes.c_float, P, P, P],
         "sgm_window_map": [P, P, I, I, I, I, I, I, ctypes.c_float, P, P, P, P, P],
-        "sgm_fallback_merge": [P, P, P, I, I, I, I, P, P, P],
+        "sgm_fallback_merge": [P, P, P, I, I, I, I, I, I, P, P, P],
         "sgm_label_downsample4": [P, I, I, P, P],
         "sgm_batch_plan": [ctypes.POINTER(sgm_batch_params), ctypes.POINTER(sgm_pair), I,
                            ctypes.POINTER(P)],
@@ -387,6 +387,24 @@ class Matcher:
         _check(_lib.sgm_match_win(self.plan, _ptr(left), _ptr(right), left.shape[1], _ptr(self._lo(lo)),
                                   _ptr(disp_int), _ptr(disp_sub), _ptr(self.workspace), self.ws_bytes,
                                   _stream(stream)), "sgm_match_win")
+        return disp_int, disp_sub
+
+    def match_at(self, left, right, y0, x0, disp_int=None, disp_sub=None, subpixel=True, stream=None):
+        """Plain SGM of the H x W rectangle at row y0, column x0 of larger
+        frames left, right (uint8 [Hf, pitch]); outputs are [H, W]."""
+        _need(left, torch.uint8, None, "left")
+        _need(right, torch.uint8, None, "right")
+        if left.shape != right.shape or left.dim() != 2:
+            raise ValueError("left and right must be uint8 frames of one shape")
+        Hf, pitch = left.shape
+        y0, x0 = int(y0), int(x0)
+        if y0 < 0 or x0 < 0 or y0 + self.H > Hf or x0 + self.W > pitch:
+            raise ValueError("rectangle outside the frame")
+        disp_int, disp_sub = self._outs(disp_int, disp_sub, subpixel)
+        off = y0 * pitch + x0
+        _check(_lib.sgm_match(self.plan, ctypes.c_void_p(left.data_ptr() + off),
+                              ctypes.c_void_p(right.data_ptr() + off), pitch, None, _ptr(disp_int),
+                              _ptr(disp_sub), _ptr(self.workspace), self.ws_bytes, _stream(stream)), "sgm_match")
         return disp_int, disp_sub
 
     def match(self, left, right, d_lo=None, disp_int=None, disp_sub=None, subpixel=True,

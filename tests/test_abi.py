@@ -140,16 +140,23 @@ def test_batch_plan_validation(sgm):
     assert lib.sgm_batch_launch(None, None) == -1
 
 
-def test_fallback_bands_host_logic_matches_oracle():
-    """The product's band selection (host code, numpy) against the oracle's
-    plain loop, on random masks of several densities."""
+def test_fallback_rects_host_logic_matches_oracle():
+    """The product's rectangle selection (host code, numpy, from per-row
+    statistics) against the oracle's plain loops over the mask."""
     from oracle import cnn as ocnn
     from paper_2012_10802_amd import learned_window as lw
     rng = np.random.default_rng(17)
-    for trial in range(200):
-        H = int(rng.integers(1, 120))
-        dens = [0.0, 0.002, 0.02, 0.1, 0.5][trial % 5]
-        mask = (rng.random((H, 9)) < dens).astype(np.uint8)
-        margin = int(rng.integers(0, 20))
-        frac = float(rng.choice([0.3, 0.75, 1.0]))
-        assert lw.fallback_bands(mask.sum(axis=1), margin, frac) == ocnn.fallback_bands(mask, margin, frac)
+    for trial in range(300):
+        H, W = int(rng.integers(1, 90)), int(rng.integers(1, 400))
+        dens = [0.0, 0.0005, 0.005, 0.05, 0.5][trial % 5]
+        mask = (rng.random((H, W)) < dens).astype(np.uint8)
+        if trial % 7 == 0:
+            mask[:, :int(rng.integers(0, W + 1))] = 0  # fallback only on the right
+        stats = np.zeros((3, H), np.int64)
+        stats[0] = mask.sum(axis=1)
+        cols = np.arange(W)
+        stats[1] = np.where(mask > 0, cols, W).min(axis=1)
+        stats[2] = np.where(mask > 0, cols, -1).max(axis=1)
+        margin, D = int(rng.integers(0, 20)), int(rng.choice([16, 64, 192]))
+        frac = float(rng.choice([0.2, 0.5, 1.0]))
+        assert lw.fallback_rects(stats, W, D, 3, margin, frac) == ocnn.fallback_rects(mask, margin, frac, D, 3)

@@ -251,14 +251,18 @@ def test_window_map_exact(lw):
     out[0, 1, :3, 1] = 0.0  # logit exactly at the tau = 1/2 threshold: not confident
     for tau in (0.0, 0.5, 0.8, 1.0):
         nfb = torch.zeros(1, dtype=torch.int32, device="cuda")
-        rows = torch.full((H,), 7, dtype=torch.int32, device="cuda")  # cleared by the call
+        stats = torch.full((3, H), 7, dtype=torch.int32, device="cuda")  # cleared by the call
         mask = torch.empty((H, W), dtype=torch.uint8, device="cuda")
-        lo = lw.window_map(_dev(cd), _dev(out), W, H, D, w, tau, mask=mask, row_fallback=rows, nfallback=nfb)
+        lo = lw.window_map(_dev(cd), _dev(out), W, H, D, w, tau, mask=mask, row_stats=stats, nfallback=nfb)
         torch.cuda.synchronize()
         want, want_n, want_mask = ocnn.window_map(cd, out, W, H, D, w, tau)
         np.testing.assert_array_equal(lo.cpu().numpy(), want, err_msg=str(tau))
         np.testing.assert_array_equal(mask.cpu().numpy(), want_mask, err_msg=str(tau))
-        np.testing.assert_array_equal(rows.cpu().numpy(), want_mask.sum(axis=1), err_msg=str(tau))
+        st = stats.cpu().numpy()
+        cols = np.arange(W)
+        np.testing.assert_array_equal(st[0], want_mask.sum(axis=1), err_msg=str(tau))
+        np.testing.assert_array_equal(st[1], np.where(want_mask > 0, cols, W).min(axis=1), err_msg=str(tau))
+        np.testing.assert_array_equal(st[2], np.where(want_mask > 0, cols, -1).max(axis=1), err_msg=str(tau))
         assert int(nfb.item()) == want_n
     assert want_n == H * W  # tau = 1: every pixel falls back
 
@@ -270,18 +274,18 @@ def test_fallback_merge(lw):
     wi = rng.integers(0, 50, (H, W)).astype(np.int16)
     ws = rng.uniform(0, 50, (H, W)).astype(np.float32)
     mask = (rng.random((H, W)) < 0.4).astype(np.uint8)
-    bands = [(0, 9), (20, 37)]
-    res = [(rng.integers(100, 190, (b - a, W)).astype(np.int16),
-            rng.uniform(100, 190, (b - a, W)).astype(np.float32)) for a, b in bands]
+    rects = [(0, 9, 0, 300), (20, 37, 41, 250), (9, 20, 299, 300)]
+    res = [(rng.integers(100, 190, (b - a, x1 - x0)).astype(np.int16),
+            rng.uniform(100, 190, (b - a, x1 - x0)).astype(np.float32)) for a, b, x0, x1 in rects]
     di, ds = _dev(wi), _dev(ws)
     md = _dev(mask)
     keep = []
-    for (a, b), (bi, bs) in zip(bands, res):
+    for (a, b, x0, x1), (bi, bs) in zip(rects, res):
         bid, bsd = _dev(bi), _dev(bs)
         keep += [bid, bsd]
-        lw.fallback_merge(md, bid, bsd, a, b - a, di, ds)
+        lw.fallback_merge(md, bid, bsd, a, x0, di, ds)
     torch.cuda.synchronize()
-    want_i, want_s = ocnn.merge_fallback(wi, ws, mask, bands, res)
+    want_i, want_s = ocnn.merge_fallback(wi, ws, mask, rects, res)
     np.testing.assert_array_equal(di.cpu().numpy(), want_i)
     np.testing.assert_array_equal(ds.cpu().numpy(), want_s)
 
@@ -350,7 +354,7 @@ def test_learned_window_pipeline_stepwise(lw, fallback):
         dint, dsub = m.match(Ld, Rd)
         torch.cuda.synchronize()
         assert 0 < int(m.nfallback.sum()) <= 4 * 16
-        assert any(b and b != [(0, H)] for b in m.last_bands)
+        assert any(rc and rc != [(0, H, 0, W)] for rc in m.last_rects)
     tau = m.tau
     nfb_total = 0
     for i in range(n):
@@ -370,10 +374,10 @@ def test_learned_window_pipeline_stepwise(lw, fallback):
         np.testing.assert_array_equal(m.mask[i].cpu().numpy(), want_mask)
         nfb_total += want_n
         wi, ws = oracle.sgm_win(L[i], R[i], 7, w, 8, 10, 120, want_lo)
-        bands = ocnn.fallback_bands(want_mask, 8, 0.75)
-        assert m.last_bands[i] == bands
-        res = [oracle.sgm(L[i][a:b], R[i][a:b], 7, D, 8, 10, 120) for a, b in bands]
-        fi, fs = ocnn.merge_fallback(wi, ws, want_mask, bands, res)
+        rects = ocnn.fallback_rects(want_mask, 8, 0.75, D, 3)
+        assert m.last_rects[i] == rects
+        res = [oracle.sgm(L[i][a:b, x0:x1], R[i][a:b, x0:x1], 7, D, 8, 10, 120) for a, b, x0, x1 in rects]
+        fi, fs = ocnn.merge_fallback(wi, ws, want_mask, rects, res)
         np.testing.assert_array_equal(dint[i].cpu().numpy().astype(np.uint16), fi)
         assert np.abs(dsub[i].cpu().numpy() - fs).max() <= 1e-4
     assert int(m.nfallback.sum()) == nfb_total
@@ -394,7 +398,7 @@ def test_full_fallback_is_plain_sgm(lw):
     for i in range(n):
         pi, pf = plain.match(Ld[i], Rd[i])
         torch.cuda.synchronize()
-        assert m.last_bands[i] == [(0, H)]
+        assert m.last_rects[i] == [(0, H, 0, W)]
         np.testing.assert_array_equal(dint[i].cpu().numpy(), pi.cpu().numpy())
         np.testing.assert_array_equal(dsub[i].cpu().numpy(), pf.cpu().numpy())
         wi, _ = oracle.sgm(L[i], R[i], 7, D, 8, 10, 120)

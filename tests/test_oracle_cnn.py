@@ -102,35 +102,39 @@ def test_prepare_input_border_channel():
     assert far[0, 0, 39, 2] == 1.0  # saturates at 16 columns
 
 
-def test_fallback_bands():
-    H = 200
-    m = np.zeros((H, 5), np.uint8)
-    assert cnn.fallback_bands(m, 32, 0.75) == []
-    m[100, 2] = 1
-    assert cnn.fallback_bands(m, 32, 0.75) == [(68, 133)]
-    m[10, 0] = 1
-    m[150, 4] = 1  # touches the band of row 100 once widened
-    assert cnn.fallback_bands(m, 32, 0.8) == [(0, 43), (68, 183)]  # 158 rows
-    assert cnn.fallback_bands(m, 32, 0.75) == [(0, H)]
+def test_fallback_rects():
+    H, W, D, r = 200, 600, 64, 3
+    m = np.zeros((H, W), np.uint8)
+    assert cnn.fallback_rects(m, 32, 0.75, D, r) == []
+    m[100, 300] = 1
+    # rows 68..132, columns 300 - 32 - 63 - 3 .. 300 + 32 + 3
+    assert cnn.fallback_rects(m, 32, 0.75, D, r) == [(68, 133, 202, 336)]
+    m[10, 5] = 1
+    m[150, 320] = 1  # touches the band of row 100 once widened
+    assert cnn.fallback_rects(m, 32, 0.75, D, r) == [(0, 43, 0, 41), (68, 183, 202, 356)]
+    # area 43 * 41 + 115 * 154 = 19473 > 0.15 * H * W = 18000
+    assert cnn.fallback_rects(m, 32, 0.15, D, r) == [(0, H, 0, W)]
     m[:] = 1
-    assert cnn.fallback_bands(m, 32, 0.75) == [(0, H)]
+    assert cnn.fallback_rects(m, 32, 1.0, D, r) == [(0, H, 0, W)]
     m[:] = 0
-    m[0, 0] = m[H - 1, 0] = 1
-    assert cnn.fallback_bands(m, 10, 0.75) == [(0, 11), (H - 11, H)]
+    m[0, W - 1] = m[H - 1, 0] = 1
+    assert cnn.fallback_rects(m, 10, 0.75, D, r) == [(0, 11, W - 1 - 10 - 63 - 3, W), (H - 11, H, 0, 14)]
 
 
-def test_merge_fallback_takes_band_results_on_masked_pixels():
+def test_merge_fallback_takes_rect_results_on_masked_pixels():
     rng = np.random.default_rng(3)
     H, W = 12, 7
     wi = rng.integers(0, 50, (H, W)).astype(np.uint16)
     ws = wi.astype(np.float32) + 0.25
     mask = (rng.random((H, W)) < 0.3).astype(np.uint8)
     mask[:3] = 0
-    bands = [(2, 12)]
-    bi = rng.integers(100, 150, (10, W)).astype(np.uint16)
+    mask[:, 5:] = 0
+    mask[:, 0] = 0
+    rects = [(2, 12, 1, 5)]
+    bi = rng.integers(100, 150, (10, 4)).astype(np.uint16)
     bs = bi.astype(np.float32) - 0.25
-    di, ds = cnn.merge_fallback(wi, ws, mask, bands, [(bi, bs)])
+    di, ds = cnn.merge_fallback(wi, ws, mask, rects, [(bi, bs)])
     m = mask.astype(bool)
     assert (di[m] >= 100).all() and (di[~m] < 50).all()
-    np.testing.assert_array_equal(di[2:][m[2:]], bi[m[2:]])
+    np.testing.assert_array_equal(di[2:, 1:5][m[2:, 1:5]], bi[m[2:, 1:5]])
     np.testing.assert_array_equal(ds[~m], ws[~m])
