@@ -347,9 +347,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # dominant kernel: the one-launch aggregation of all directions
+    # dominant kernel: the one-launch aggregation of all directions.  Its
+    # compulsory traffic under this schedule: every direction streams the
+    # cost volume once (1 B/eval) and writes its own volume (e B/eval).
     elem_bytes, _, _ = m.path_volumes()
-    agg_bytes = evals * (1 + R * elem_bytes)  # read C once, write R volumes
+    agg_bytes_per_eval = R * (1 + elem_bytes)
+    agg_bytes = evals * agg_bytes_per_eval
     agg_gbs = agg_bytes / (agg_ms * 1e-3) / 1e9
     # packed-u16 ops of the recurrence per eval and direction: neighbour min,
     # +P1, min with L(k), min with P2, +C, running min, -m
@@ -357,11 +360,16 @@ def main():
     agg_tops = agg_ops / (agg_ms * 1e-3) / 1e12
     traffic = counter_traffic(args.workload)
     hbm = {"bound": "hbm", "achieved": round(agg_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(agg_gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+           "frac": round(agg_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "bytes_per_eval": agg_bytes_per_eval, "bytes_per_launch": agg_bytes}
     alu = {"bound": "alu", "achieved": round(agg_tops, 2), "peak": round(VALU_PEAK_TOPS_U16, 2),
            "unit": "TOP/s (u16)", "frac": round(agg_tops / VALU_PEAK_TOPS_U16, 4), "traffic": traffic}
     roofline = hbm if hbm["frac"] >= alu["frac"] else alu
     roofline["kernel"] = "k_aggregate"
+    # the whole step: cost written once, read once per direction, R volumes
+    # written and read back by the selection
+    step_bytes_per_eval = 1 + R * (1 + 2 * elem_bytes)
+    step_gbs = evals * step_bytes_per_eval / (ms_per_step * 1e-3) / 1e9
 
     # accuracy against the generator's ground truth (bad-pixel rate, eq. (18))
     torch.cuda.synchronize()
@@ -405,6 +413,8 @@ def main():
                    "p1": p1, "p2": p2, "evals_per_step": evals},
         "roofline": roofline,
         "roofline_other_bound": alu if roofline is hbm else hbm,
+        "step_hbm": {"bytes_per_eval": step_bytes_per_eval, "achieved": round(step_gbs, 1), "unit": "GB/s",
+                     "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "kernels_ms": {"cost": round(cost_ms, 4), "aggregate": round(agg_ms, 4),
                        "wta": round(wta_ms, 4)},
         "accuracy": accuracy,
