@@ -180,6 +180,25 @@ sgm_status sgm_match_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *ri
                          int32_t pitch, const int32_t *lo, uint16_t *disp_int, float *disp_sub,
                          void *workspace, size_t workspace_bytes, void *stream);
 
+/* Per-pixel-window SGM of nimg pairs of one size (the plan's) together:
+ * census and cost of every pair, the aggregation of every pair and
+ * direction in ONE launch (one scanline per lane, 16 window values in
+ * registers), and the selection of every pair.  Results equal sgm_match_win
+ * on each pair.  Needs ndisp = 16 and Cmax + P2 <= 255 (uint8 volumes),
+ * else SGM_ERR_UNSUPPORTED.
+ *   left, right   device uint8; pair i at + i * image_stride bytes, rows of
+ *                 `pitch` bytes (image_stride >= pitch * H)
+ *   lo            device int32 [nimg][H][W] window starts
+ *   disp_int      device uint16 [nimg][H][W]; disp_sub float32 [nimg][H][W]
+ *                 or NULL
+ *   workspace     device, 256-byte aligned, sgm_workspace_size_win_batch()
+ *                 bytes (pair i uses the i-th sgm_workspace_size() slice). */
+sgm_status sgm_workspace_size_win_batch(sgm_plan_t plan, int32_t nimg, size_t *bytes);
+sgm_status sgm_match_win_batch(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
+                               int32_t pitch, int64_t image_stride, const int32_t *lo,
+                               int32_t nimg, uint16_t *disp_int, float *disp_sub, void *workspace,
+                               size_t workspace_bytes, void *stream);
+
 /* 4 x 4 box reduction of an 8-bit image (the coarse level of the
  * learned-window form): out is floor(H/4) x floor(W/4), row-major, each
  * value (sum of its 16 pixels + 8) / 16.  Device buffers; needs W, H >= 4. */

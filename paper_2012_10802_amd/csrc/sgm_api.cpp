@@ -378,6 +378,54 @@ sgm_status sgm_match_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *ri
     return sgm_wta_win_paths(plan, base + plan->off_paths, lo, disp_int, disp_sub, stream);
 }
 
+sgm_status sgm_workspace_size_win_batch(sgm_plan_t plan, int32_t nimg, size_t *bytes)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!bytes) return fail(SGM_ERR_INVALID, "bytes is NULL");
+    if (nimg < 1) return fail(SGM_ERR_INVALID, "nimg must be >= 1 (got %d)", nimg);
+    *bytes = plan->ws_bytes * (size_t)nimg;
+    return SGM_OK;
+}
+
+sgm_status sgm_match_win_batch(sgm_plan_t plan, const uint8_t *left, const uint8_t *right, int32_t pitch,
+                               int64_t image_stride, const int32_t *lo, int32_t nimg, uint16_t *disp_int,
+                               float *disp_sub, void *ws, size_t ws_bytes, void *stream)
+{
+    if (sgm_status s = check_win_plan(plan)) return s;
+    if (plan->pb.w != 16 || !plan->kc.l8)
+        return fail(SGM_ERR_UNSUPPORTED, "batched windows need ndisp = 16 and Cmax + P2 <= 255");
+    if (!left || !right || !lo || !disp_int || !ws)
+        return fail(SGM_ERR_INVALID, "left, right, lo, disp_int and workspace must not be NULL");
+    if (nimg < 1) return fail(SGM_ERR_INVALID, "nimg must be >= 1 (got %d)", nimg);
+    if (pitch < plan->pb.W) return fail(SGM_ERR_INVALID, "pitch %d < width %d", pitch, plan->pb.W);
+    if (image_stride < (int64_t)pitch * plan->pb.H)
+        return fail(SGM_ERR_INVALID, "image_stride %lld < pitch * height", (long long)image_stride);
+    if (!is_aligned(ws, 256)) return fail(SGM_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (ws_bytes / (size_t)nimg < plan->ws_bytes)
+        return fail(SGM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+                    plan->ws_bytes * (size_t)nimg);
+    uint8_t *base = static_cast<uint8_t *>(ws);
+    size_t vs = 0;
+    sgm_path_volumes(plan, nullptr, &vs, nullptr);
+    sgm::WinPairs b{};
+    b.left = left;
+    b.right = right;
+    b.pitch = pitch;
+    b.img_pair = (long long)image_stride;
+    b.lo = lo;
+    b.npairs = nimg;
+    b.ws_pair = plan->ws_bytes;
+    b.codes_l = reinterpret_cast<uint64_t *>(base + plan->off_codes_l);
+    b.codes_r = reinterpret_cast<uint64_t *>(base + plan->off_codes_r);
+    b.cost = base + plan->off_cost;
+    b.paths = base + plan->off_paths;
+    b.vstride = (long long)vs;
+    b.dint = disp_int;
+    b.dsub = disp_sub;
+    hipError_t e = sgm::launch_match_win_pairs(plan->pb, b, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "match_win_batch launch");
+}
+
 sgm_status sgm_window_from_road(double a0, double a1, double phi, int32_t W, int32_t H, int32_t w, int32_t mode,
                                 double delta, int32_t *d_lo)
 {

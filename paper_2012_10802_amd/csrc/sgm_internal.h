@@ -55,6 +55,25 @@ hipError_t launch_aggregate_win(const Problem &pb, const uint8_t *cost, const in
 hipError_t launch_wta_win(const Problem &pb, const void *vols, long long vstride, int np, bool l8, const int32_t *lo,
                           uint16_t *dint, float *dsub, hipStream_t s);
 
+// npairs pairs of one size, w = 16 and uint8 volumes: census, cost,
+// aggregation (one launch, one scanline per lane) and selection.  Pair i's
+// scratch (codes, cost, volumes) sits at i * ws_pair bytes from the first
+// pair's pointers below.
+struct WinPairs {
+    const uint8_t *left, *right;
+    int pitch;
+    long long img_pair;  // bytes between the images of consecutive pairs
+    const int32_t *lo;   // [npairs][H][W]
+    int npairs;
+    size_t ws_pair;
+    uint64_t *codes_l, *codes_r;
+    uint8_t *cost, *paths;
+    long long vstride;   // bytes between direction volumes
+    uint16_t *dint;      // [npairs][H][W]
+    float *dsub;         // [npairs][H][W] or NULL
+};
+hipError_t launch_match_win_pairs(const Problem &pb, const WinPairs &b, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // batches
 

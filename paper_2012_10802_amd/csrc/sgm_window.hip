@@ -48,9 +48,15 @@ constexpr int kWinReach = 256;  // right columns reachable left of the tile
 
 __global__ __launch_bounds__(64) void k_cost_win(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr,
                                                  const int32_t *__restrict__ lo, int W, int H, int w, int cmax,
-                                                 uint8_t *__restrict__ cost)
+                                                 uint8_t *__restrict__ cost, long long codes_pair,
+                                                 long long pix_pair, long long cost_pair)
 {
     __shared__ uint64_t s_cr[kWinTile + kWinReach];
+    // pair blockIdx.z of a batch (strides 0 for one pair)
+    cl += blockIdx.z * codes_pair;
+    cr += blockIdx.z * codes_pair;
+    lo += blockIdx.z * pix_pair;
+    cost += blockIdx.z * cost_pair;
     const int v = blockIdx.y, u0 = blockIdx.x * kWinTile;
     const int first = u0 - kWinReach;  // right column held in s_cr[0]
     for (int t = threadIdx.x; t < kWinTile + kWinReach; t += blockDim.x) {
@@ -96,6 +102,7 @@ struct WinParams {
 };
 
 constexpr int kNoLo = -0x40000000;  // "no predecessor window yet"
+constexpr int kWinPrefetch = 8;     // steps of cost prefetched by agg_scan_win
 constexpr uint32_t kInf1 = 0x3FFFu;
 
 __device__ __forceinline__ uint32_t lane_pick(uint32_t v, int src_lane)
@@ -234,10 +241,16 @@ __global__ __launch_bounds__(256) void k_aggregate_win(WinParams a)
 template <bool L8>
 __global__ __launch_bounds__(256) void k_wta_win(const void *__restrict__ vols, long long vstride, int np,
                                                  const int32_t *__restrict__ lo, int W, int H, int w,
-                                                 uint16_t *__restrict__ dint, float *__restrict__ dsub)
+                                                 uint16_t *__restrict__ dint, float *__restrict__ dsub,
+                                                 long long vol_pair, long long pix_pair)
 {
     const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= (long long)W * H) return;
+    // pair blockIdx.y of a batch (strides 0 for one pair); vol_pair in elements
+    vols = static_cast<const uint8_t *>(vols) + blockIdx.y * vol_pair * (L8 ? 1 : 2);
+    lo += blockIdx.y * pix_pair;
+    dint += blockIdx.y * pix_pair;
+    if (dsub) dsub += blockIdx.y * pix_pair;
     uint32_t S[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) S[j] = 0;
@@ -293,7 +306,239 @@ __global__ __launch_bounds__(256) void k_wta_win(const void *__restrict__ vols, 
     }
 }
 
-constexpr int kWinPrefetch = 8;
+// ---------------------------------------------------------------------------
+// census of every image of a batch: grid z = image (left images, then right)
+
+template <int N>
+__global__ __launch_bounds__(256) void k_census_pairs(const uint8_t *__restrict__ left, const uint8_t *__restrict__ right,
+                                                      int pitch, long long img_pair, int W, int H, int npairs,
+                                                      uint64_t *__restrict__ codes_l, uint64_t *__restrict__ codes_r,
+                                                      long long ws_pair_words)
+{
+    const int z = blockIdx.z;
+    const int pr = z < npairs ? z : z - npairs;
+    const uint8_t *img = (z < npairs ? left : right) + pr * img_pair;
+    uint64_t *out = (z < npairs ? codes_l : codes_r) + pr * ws_pair_words;
+    census_tile<N>(img, pitch, W, H, out, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------------------
+// windowed aggregation for w = 16, one scanline per lane
+//
+// Each lane carries the 16 values of its scanline as 8 packed u16 pairs, so
+// a step needs no cross-lane traffic: k +- 1 neighbours are funnel shifts
+// of adjacent registers.  When lo(p) = lo(q) on every lane of the wave (the
+// common case: windows are constant over 4 x 4 blocks) the predecessor is
+// used as it is; otherwise each lane re-indexes its own values through a
+// private LDS row padded with the sentinel.  Waves of a batch's pairs share
+// one launch (grid y = pair), which is what keeps the chip busy: one
+// 1920x1080 pair has only 18 000 scanlines.
+
+constexpr int kW16Lines = 256;       // scanlines (lanes) per workgroup
+constexpr int kW16Row = 27;          // dwords of LDS per lane: 18 + 16 + 20 u16
+constexpr int kW16Pad = 18;          // u16 index of value 0 in the lane's row
+
+struct Win16Params {
+    const uint8_t *cost;
+    const int32_t *lo;
+    uint8_t *out;
+    long long cost_pair, lo_pair, out_pair, vstride;  // bytes, elements, bytes, bytes
+    int W, H;
+    uint32_t p1, p2;
+    int np;
+    int paths[8];   // per slot: direction | output volume << 8
+    int gstart[9];  // first workgroup (grid x) of each slot
+};
+
+__device__ __forceinline__ uint32_t bytes_lo(uint32_t c) { return __builtin_amdgcn_perm(0u, c, 0x0C010C00u); }
+__device__ __forceinline__ uint32_t bytes_hi(uint32_t c) { return __builtin_amdgcn_perm(0u, c, 0x0C030C02u); }
+// low bytes of two u16 pairs (values <= 255) -> 4 bytes
+__device__ __forceinline__ uint32_t pack4(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x06040200u); }
+__device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) { return __builtin_amdgcn_alignbit(hi, lo, 16); }
+
+__device__ __forceinline__ int wave_min(int x)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) x = min(x, __shfl_xor(x, o, 64));
+    return x;
+}
+__device__ __forceinline__ int wave_max(int x)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) x = max(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+template <int PF, int KIND>
+__device__ __forceinline__ void win16_scan(const Win16Params &a, __amdgpu_buffer_rsrc_t rc,
+                                           __amdgpu_buffer_rsrc_t rl, __amdgpu_buffer_rsrc_t ro, int du, int dv,
+                                           int g, uint32_t *row)
+{
+    const int W = a.W, H = a.H;
+    const int idx = g * kW16Lines + (int)threadIdx.x;
+    const Line ln = line_geom(KIND == kHorizontal ? (idx < H ? idx : H) : idx, du, dv, W, H);
+    // wave-uniform step range
+    int I0, I1;
+    if constexpr (KIND == kDiagonal) {
+        const bool any = ln.i1 > ln.i0;
+        I0 = __builtin_amdgcn_readfirstlane(wave_min(any ? ln.i0 : 1 << 30));
+        I1 = __builtin_amdgcn_readfirstlane(wave_max(any ? ln.i1 : 0));
+        if (I1 <= I0) return;
+    } else {
+        I0 = 0;
+        I1 = KIND == kHorizontal ? W : H;
+    }
+    const uint32_t pstep = (uint32_t)(ln.sv * W + ln.su);
+    const uint32_t pix0 = (uint32_t)(ln.vb * W + ln.ub);
+    const uint32_t li0 = (uint32_t)ln.i0, llen = (uint32_t)(ln.i1 - ln.i0);
+    auto inside = [&](int i) -> bool { return (uint32_t)i - li0 < llen; };
+
+    v4u ring_c[PF];
+    uint32_t ring_l[PF];
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+        const int i = I0 + s;
+        const uint32_t px = pix0 + (uint32_t)i * pstep;
+        const bool in = inside(i);
+        ring_c[s] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rc, in ? px * 16u : kOff, 0, 0));
+        ring_l[s] = __builtin_amdgcn_raw_buffer_load_b32(rl, in ? px * 4u : kOff, 0, 0);
+    }
+    const uint32_t P1 = a.p1 | (a.p1 << 16);
+    uint32_t L[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) L[k] = 0u;
+    uint32_t m = 0u;  // min of L
+    int loq = kNoLo;
+
+    // one step: consume ring slot S (loaded PF steps ago), refill it for
+    // step i + PF, aggregate, store
+    auto step = [&](const int i, const int S) __attribute__((always_inline)) {
+        const bool act = inside(i);
+        // later loads and the stores since may stay in flight (2 loads + 1
+        // store per step)
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(1 + (PF - 1) * 3));
+        const v4u c4 = ring_c[S];
+        const int lop = (int)ring_l[S];
+        {
+            const int ip = i + PF;
+            const uint32_t px = pix0 + (uint32_t)ip * pstep;
+            const bool in = inside(ip);
+            ring_c[S] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rc, in ? px * 16u : kOff, 0, 0));
+            ring_l[S] = __builtin_amdgcn_raw_buffer_load_b32(rl, in ? px * 4u : kOff, 0, 0);
+        }
+        // predecessor values at window indices j - 1, j, j + 1 of p's window:
+        // V[j] = L[j + sh - 1] for j = 0..17 (sentinel outside q's window),
+        // held as 9 packed pairs; Pm = V[0..15], P0 = V[1..16], Pp = V[2..17]
+        const int sh = (act && loq != kNoLo) ? lop - loq : 0;
+        auto Ld = [&](int q) -> uint32_t { return (q >= 0 && q < 8) ? L[q] : kInf2; };
+        uint32_t V[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) V[q] = funnel16(Ld(q), Ld(q - 1));  // sh = 0
+        if (__ballot(sh != 0) != 0) {
+            if (__ballot(sh < -1 || sh > 1) != 0) {
+                // any shift: through the lane's LDS row
+#pragma unroll
+                for (int k = 0; k < 8; ++k) row[kW16Pad / 2 + k] = L[k];
+                const int e = min(max(sh - 1, -kW16Pad), 16);
+                const int b = e & 1;
+                const int base = (kW16Pad + e - b) >> 1;  // dword of V[0] (or of V[-1] when e is odd)
+                uint32_t D[10];
+#pragma unroll
+                for (int q = 0; q < 10; ++q) D[q] = row[base + q];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) V[q] = b ? funnel16(D[q + 1], D[q]) : D[q];
+            } else {
+                // shifts of one: whole registers move
+#pragma unroll
+                for (int q = 0; q < 9; ++q) V[q] = sh == 1 ? Ld(q) : (sh == -1 ? Ld(q - 1) : V[q]);
+            }
+        }
+        uint32_t Pm[8], P0[8], Pp[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            Pm[k] = V[k];
+            P0[k] = funnel16(V[k + 1], V[k]);
+            Pp[k] = V[k + 1];
+        }
+        const uint32_t m2 = m | (m << 16);
+        const uint32_t mp2 = pk_add(m2, a.p2 | (a.p2 << 16));
+        const uint32_t cw[4] = {c4.x, c4.y, c4.z, c4.w};
+        uint32_t Ln[8];
+        uint32_t mn = 0xFFFFFFFFu;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            uint32_t t = pk_add(pk_min(Pm[k], Pp[k]), P1);
+            t = pk_min(pk_min(t, P0[k]), mp2);
+            const uint32_t c = (k & 1) ? bytes_hi(cw[k >> 1]) : bytes_lo(cw[k >> 1]);
+            Ln[k] = pk_sub(pk_add(c, t), m2);
+            mn = pk_min(mn, Ln[k]);
+        }
+        const v4u o4 = {pack4(Ln[0], Ln[1]), pack4(Ln[2], Ln[3]), pack4(Ln[4], Ln[5]), pack4(Ln[6], Ln[7])};
+        const uint32_t o = act ? (pix0 + (uint32_t)i * pstep) * 16u : kOff;
+        __builtin_amdgcn_raw_buffer_store_b128(o4, ro, o, 0, kStreamPolicy);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) L[k] = Ln[k];
+        m = min(mn & 0xFFFFu, mn >> 16);
+        loq = act ? lop : kNoLo;
+    };
+
+    // The first turn of the ring runs outside the loop: at the loop head
+    // every slot was then refilled by a step, exactly as on the back edge,
+    // so the loads in flight there need no deeper wait than inside the loop.
+#pragma unroll
+    for (int S = 0; S < PF; ++S) step(I0 + S, S);
+    // two turns of the ring per iteration keep each slot in its registers
+    constexpr int UNROLL = 2 * PF;
+    const int nblk = (I1 - I0 - PF + UNROLL - 1) / UNROLL;
+    for (int blk = 0; blk < nblk; ++blk) {
+#pragma unroll
+        for (int S = 0; S < UNROLL; ++S) step(I0 + PF + blk * UNROLL + S, S % PF);
+    }
+}
+
+// Horizontal directions keep the 16-lanes-per-scanline form of
+// agg_scan_win (4 rows per wave): with one scanline per lane, the 64 lanes
+// of a wave would sit in 64 different rows and every access would touch 64
+// cache lines.  Vertical and diagonal scanlines are neighbouring pixels of
+// one row at every step, so one scanline per lane stays contiguous.
+template <int PF>
+__global__ __launch_bounds__(256, 4) void k_aggregate_win16(Win16Params a)
+{
+    __shared__ uint32_t rows[kW16Lines * kW16Row];
+    uint32_t *row = rows + threadIdx.x * kW16Row;
+    int slot = 0;
+    while (slot + 1 < a.np && (int)blockIdx.x >= a.gstart[slot + 1]) ++slot;
+    slot = __builtin_amdgcn_readfirstlane(slot);
+    const int r = __builtin_amdgcn_readfirstlane(a.paths[slot] & 0xFF);
+    const int vol = __builtin_amdgcn_readfirstlane(a.paths[slot] >> 8);
+    const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x - a.gstart[slot]);
+    const int du = __builtin_amdgcn_readfirstlane(dir_du(r)), dv = __builtin_amdgcn_readfirstlane(dir_dv(r));
+    const int pr = blockIdx.y;
+    const uint32_t npix = (uint32_t)a.W * (uint32_t)a.H;
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost + pr * a.cost_pair, npix * 16u);
+    const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.lo + pr * a.lo_pair, npix * 4u);
+    const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out + pr * a.out_pair + (size_t)vol * a.vstride, npix * 16u);
+    if (dv == 0) {
+        WinParams h{};
+        h.W = a.W;
+        h.H = a.H;
+        h.w = 16;
+        h.p1 = a.p1;
+        h.p2 = a.p2;
+        __builtin_amdgcn_s_setprio(2);  // the longest scanlines
+        agg_scan_win<true, kWinPrefetch, kHorizontal>(h, rc, rl, ro, du, dv, g);
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < kW16Row; ++q) row[q] = kInf2;  // sentinel padding; values are written per use
+    if (du == 0)
+        win16_scan<PF, kVertical>(a, rc, rl, ro, du, dv, g, row);
+    else
+        win16_scan<PF, kDiagonal>(a, rc, rl, ro, du, dv, g, row);
+}
+
+constexpr int kWin16Prefetch = 6;  // steps of cost prefetched by k_aggregate_win16 (4 waves per SIMD)
 
 }  // namespace
 
@@ -308,7 +553,7 @@ hipError_t launch_cost_win(const Problem &pb, const uint64_t *cl, const uint64_t
                            uint8_t *cost, hipStream_t s)
 {
     dim3 grid((pb.W + kWinTile - 1) / kWinTile, pb.H), block(kWinTile);
-    hipLaunchKernelGGL(k_cost_win, grid, block, 0, s, cl, cr, lo, pb.W, pb.H, pb.w, pb.cmax, cost);
+    hipLaunchKernelGGL(k_cost_win, grid, block, 0, s, cl, cr, lo, pb.W, pb.H, pb.w, pb.cmax, cost, 0ll, 0ll, 0ll);
     return hipGetLastError();
 }
 
@@ -350,8 +595,81 @@ hipError_t launch_wta_win(const Problem &pb, const void *vols, long long vstride
 {
     const long long npix = (long long)pb.W * pb.H;
     dim3 grid((unsigned)((npix + 255) / 256)), block(256);
-    if (l8) hipLaunchKernelGGL(k_wta_win<true>, grid, block, 0, s, vols, vstride, np, lo, pb.W, pb.H, pb.w, dint, dsub);
-    else hipLaunchKernelGGL(k_wta_win<false>, grid, block, 0, s, vols, vstride, np, lo, pb.W, pb.H, pb.w, dint, dsub);
+    if (l8)
+        hipLaunchKernelGGL(k_wta_win<true>, grid, block, 0, s, vols, vstride, np, lo, pb.W, pb.H, pb.w, dint, dsub, 0ll,
+                           0ll);
+    else
+        hipLaunchKernelGGL(k_wta_win<false>, grid, block, 0, s, vols, vstride, np, lo, pb.W, pb.H, pb.w, dint, dsub,
+                           0ll, 0ll);
+    return hipGetLastError();
+}
+
+hipError_t launch_match_win_pairs(const Problem &pb, const WinPairs &b, hipStream_t s)
+{
+    const long long npix = (long long)pb.W * pb.H;
+    const long long ws_words = (long long)(b.ws_pair / 8);
+    // census of every left and right image
+    {
+        dim3 grid((pb.W + 63) / 64, (pb.H + 3) / 4, 2 * b.npairs), block(256);
+        switch (pb.n) {
+        case 3:
+            hipLaunchKernelGGL(k_census_pairs<3>, grid, block, 0, s, b.left, b.right, b.pitch, b.img_pair, pb.W, pb.H,
+                               b.npairs, b.codes_l, b.codes_r, ws_words);
+            break;
+        case 5:
+            hipLaunchKernelGGL(k_census_pairs<5>, grid, block, 0, s, b.left, b.right, b.pitch, b.img_pair, pb.W, pb.H,
+                               b.npairs, b.codes_l, b.codes_r, ws_words);
+            break;
+        case 7:
+            hipLaunchKernelGGL(k_census_pairs<7>, grid, block, 0, s, b.left, b.right, b.pitch, b.img_pair, pb.W, pb.H,
+                               b.npairs, b.codes_l, b.codes_r, ws_words);
+            break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    // windowed cost of every pair
+    {
+        dim3 grid((pb.W + kWinTile - 1) / kWinTile, pb.H, b.npairs), block(kWinTile);
+        hipLaunchKernelGGL(k_cost_win, grid, block, 0, s, b.codes_l, b.codes_r, b.lo, pb.W, pb.H, pb.w, pb.cmax, b.cost,
+                           ws_words, npix, (long long)b.ws_pair);
+    }
+    // aggregation of every pair and direction in one launch
+    {
+        Win16Params p{};
+        p.cost = b.cost;
+        p.lo = b.lo;
+        p.out = b.paths;
+        p.cost_pair = (long long)b.ws_pair;
+        p.lo_pair = npix;
+        p.out_pair = (long long)b.ws_pair;
+        p.vstride = b.vstride;
+        p.W = pb.W;
+        p.H = pb.H;
+        p.p1 = (uint32_t)pb.p1;
+        p.p2 = (uint32_t)pb.p2;
+        p.np = pb.npaths;
+        int acc = 0, no = 0;
+        // horizontal groups first (the longest scanlines), then diagonal, then vertical
+        for (const int kind : {0, 2, 1})
+            for (int r = 0; r < pb.npaths; ++r) {
+                const int k = (r <= 1) ? 0 : (r >= 4 ? 2 : 1);
+                if (k != kind) continue;
+                const int nl = (r <= 1) ? pb.H : (r <= 3 ? pb.W : pb.W + pb.H - 1);
+                const int lpg = (r <= 1) ? 16 : kW16Lines;  // scanlines per workgroup
+                p.paths[no] = r | (r << 8);
+                p.gstart[no] = acc;
+                acc += (nl + lpg - 1) / lpg;
+                ++no;
+            }
+        p.gstart[pb.npaths] = acc;
+        hipLaunchKernelGGL(k_aggregate_win16<kWin16Prefetch>, dim3(acc, b.npairs), dim3(kW16Lines), 0, s, p);
+    }
+    // selection of every pair
+    {
+        dim3 grid((unsigned)((npix + 255) / 256), b.npairs), block(256);
+        hipLaunchKernelGGL(k_wta_win<true>, grid, block, 0, s, b.paths, b.vstride, pb.npaths, b.lo, pb.W, pb.H, pb.w,
+                           b.dint, b.dsub, (long long)b.ws_pair, npix);
+    }
     return hipGetLastError();
 }
 

@@ -13,7 +13,8 @@ the C ABI:
      4 * (coarse + offset) where the network is confident; the other pixels
      are marked for the fallback (their window, centred on 4 * coarse, still
      feeds the windowed aggregation of their neighbours);
-  5. SGM over the per-pixel windows at full resolution;
+  5. SGM over the per-pixel windows at full resolution, every pair of the
+     batch in one set of launches;
   6. the full-range fallback: plain SGM over all ndisp disparities on
      rectangles around the marked pixels (their rows and columns widened by
      a margin, and by ndisp - 1 more columns to the left so that every
@@ -248,8 +249,14 @@ class LearnedWindowMatcher:
                               census=census, npaths=npaths, p1=p1, p2=p2, device=dev)
         self.x0 = torch.empty((n, Hc, Wc, CH), dtype=torch.int16, device=dev)
         self.acts, self.out = self.net.buffers(Wc, Hc, n)
+        fine_plan = S.sgm_plan(width, height, census, window, npaths, p1, p2)
+        try:
+            fine_ws = int(S.sgm_workspace_size(fine_plan)) * n
+        finally:
+            S.sgm_plan_free(fine_plan)
+        self.fine_ws = torch.empty(fine_ws, dtype=torch.uint8, device=dev)  # every pair's slice
         self.fine = S.Matcher(width, height, census=census, ndisp=window, npaths=npaths, p1=p1, p2=p2,
-                              device=dev)
+                              device=dev, workspace=self.fine_ws)
         self.lo = torch.empty((n, height, width), dtype=torch.int32, device=dev)
         self.mask = torch.empty((n, height, width), dtype=torch.uint8, device=dev)
         self.stats = torch.zeros((n, 3, height), dtype=torch.int32, device=dev)
@@ -295,8 +302,13 @@ class LearnedWindowMatcher:
         for i in range(n):
             window_map(self.coarse.disp_sub[i], self.out[i], self.W, self.H, self.D, self.w, self.tau,
                        self.lo[i], self.mask[i], self.stats[i], self.nfallback[i:i + 1], stream)
-            self.fine.match_win(left[i], right[i], self.lo[i], disp_int=self.dint[i], disp_sub=self.dsub[i],
-                                stream=stream)
+        if self.w == 16:
+            self.fine.match_win_batch(left, right, self.lo, disp_int=self.dint, disp_sub=self.dsub,
+                                      workspace=self.fine_ws, stream=stream)
+        else:
+            for i in range(n):
+                self.fine.match_win(left[i], right[i], self.lo[i], disp_int=self.dint[i], disp_sub=self.dsub[i],
+                                    stream=stream)
 
     def fallback(self, left, right, stream=None):
         """Step 6 (synchronises once to read the per-row statistics)."""

@@ -81,6 +81,8 @@ def _load_library():
         "sgm_aggregate_win_paths": [P, P, P, P, S, P],
         "sgm_wta_win_paths": [P, P, P, P, P, P],
         "sgm_match_win": [P, P, P, I, P, P, P, P, S, P],
+        "sgm_workspace_size_win_batch": [ctypes.c_void_p, I, ctypes.POINTER(ctypes.c_size_t)],
+        "sgm_match_win_batch": [ctypes.c_void_p, P, P, I, ctypes.c_int64, P, I, P, P, P, S, P],
         "sgm_cnn_pack_weights": [P, P, P, P],
         "sgm_cnn_prepare_input": [P, P, I, I, I, P, P],
         "sgm_cnn_forward": [P, P, P, I, I, I, P, P, P],
@@ -387,6 +389,38 @@ class Matcher:
         _check(_lib.sgm_match_win(self.plan, _ptr(left), _ptr(right), left.shape[1], _ptr(self._lo(lo)),
                                   _ptr(disp_int), _ptr(disp_sub), _ptr(self.workspace), self.ws_bytes,
                                   _stream(stream)), "sgm_match_win")
+        return disp_int, disp_sub
+
+    def win_batch_workspace(self, n):
+        b = ctypes.c_size_t()
+        _check(_lib.sgm_workspace_size_win_batch(self.plan, int(n), ctypes.byref(b)), "sgm_workspace_size_win_batch")
+        return torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
+
+    def match_win_batch(self, left, right, lo, disp_int=None, disp_sub=None, subpixel=True, workspace=None,
+                        stream=None):
+        """Per-pixel-window SGM of n pairs at once: left, right uint8
+        [n, H, pitch]; lo int32 [n, H, W]; outputs [n, H, W].  `workspace`
+        from win_batch_workspace(n) (allocated here if omitted)."""
+        _need(left, torch.uint8, None, "left")
+        _need(right, torch.uint8, None, "right")
+        if left.dim() != 3 or left.shape != right.shape or left.shape[1] != self.H or left.shape[2] < self.W:
+            raise ValueError("left and right must be uint8 [n, H, >=W] of one shape")
+        n = left.shape[0]
+        _need(lo, torch.int32, (n, self.H, self.W), "lo")
+        if disp_int is None:
+            disp_int = torch.empty((n, self.H, self.W), dtype=torch.int16, device=self.device)
+        _need(disp_int, torch.int16, (n, self.H, self.W), "disp_int")
+        if disp_sub is None and subpixel:
+            disp_sub = torch.empty((n, self.H, self.W), dtype=torch.float32, device=self.device)
+        if disp_sub is not None:
+            _need(disp_sub, torch.float32, (n, self.H, self.W), "disp_sub")
+        if workspace is None:
+            workspace = self.win_batch_workspace(n)
+        _need(workspace, torch.uint8, None, "workspace")
+        pitch = left.shape[2]
+        _check(_lib.sgm_match_win_batch(self.plan, _ptr(left), _ptr(right), pitch, self.H * pitch, _ptr(lo), n,
+                                        _ptr(disp_int), _ptr(disp_sub), _ptr(workspace), workspace.numel(),
+                                        _stream(stream)), "sgm_match_win_batch")
         return disp_int, disp_sub
 
     def match_at(self, left, right, y0, x0, disp_int=None, disp_sub=None, subpixel=True, stream=None):

@@ -160,3 +160,21 @@ def test_fallback_rects_host_logic_matches_oracle():
         margin, D = int(rng.integers(0, 20)), int(rng.choice([16, 64, 192]))
         frac = float(rng.choice([0.2, 0.5, 1.0]))
         assert lw.fallback_rects(stats, W, D, 3, margin, frac) == ocnn.fallback_rects(mask, margin, frac, D, 3)
+
+
+def test_window_batch_needs_width_16():
+    """sgm_match_win_batch refuses plans other than 16 disparities before it
+    touches any buffer (SGM_ERR_UNSUPPORTED)."""
+    import ctypes
+    from paper_2012_10802_amd import sgm
+    lib = sgm.library()
+    plan = sgm.sgm_plan(64, 32, 7, 12, 8, 10, 120)
+    try:
+        rc = lib.sgm_match_win_batch(plan, None, None, 64, 64 * 32, None, 2, None, None, None, 0, None)
+        assert rc == -2
+        b = ctypes.c_size_t()
+        assert lib.sgm_workspace_size_win_batch(plan, 3, ctypes.byref(b)) == 0
+        assert b.value == 3 * sgm.sgm_workspace_size(plan)
+        assert lib.sgm_workspace_size_win_batch(plan, 0, ctypes.byref(b)) == -1
+    finally:
+        sgm.sgm_plan_free(plan)

@@ -87,3 +87,38 @@ def test_downsample4(sgm):
         out = sgm.sgm_downsample4(_dev(img))
         torch.cuda.synchronize()
         np.testing.assert_array_equal(out.cpu().numpy(), oracle.downsample4(img))
+
+
+@pytest.mark.parametrize("shape", [(300, 70), (67, 29), (17, 300)], ids=lambda s: "x".join(map(str, s)))
+def test_window_batch_matches_oracle_and_single_pair(sgm, shape):
+    """Batched windowed SGM (w = 16, one aggregation launch for every pair
+    and direction, one scanline per lane) against the oracle, pair by pair,
+    and against the single-pair path; several scanline groups per direction
+    and ragged tails, lo maps with no jumps, small jumps and large ones."""
+    import torch
+    W, H = shape
+    w, D = 16, 64
+    rng = np.random.default_rng(W * H)
+    maps = _lo_maps(H, W, D, w, W + 7)
+    names = sorted(maps)
+    n = len(names)
+    L = rng.integers(0, 256, size=(n, H, W), dtype=np.uint8)
+    Rm = np.empty_like(L)
+    for i in range(n):
+        Rm[i] = np.clip(np.roll(L[i], -(5 + i), axis=1).astype(int) + rng.integers(-2, 3, size=(H, W)),
+                        0, 255).astype(np.uint8)
+    lo = np.stack([maps[k] for k in names]).astype(np.int32)
+    m = sgm.Matcher(W, H, census=N, ndisp=w, npaths=R, p1=P1, p2=P2)
+    Ld, Rd, lod = _dev(L), _dev(Rm), _dev(lo)
+    di, ds = m.match_win_batch(Ld, Rd, lod)
+    di2, ds2 = m.match_win_batch(Ld, Rd, lod)  # a second run over the same workspace size
+    torch.cuda.synchronize()
+    for i, name in enumerate(names):
+        wi, ws = oracle.sgm_win(L[i], Rm[i], N, w, R, P1, P2, lo[i])
+        np.testing.assert_array_equal(di[i].cpu().numpy().astype(np.uint16), wi, err_msg=name)
+        assert np.abs(ds[i].cpu().numpy() - ws).max() <= 1e-4, name
+        si, ss = m.match_win(Ld[i], Rd[i], lod[i])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(di[i].cpu().numpy(), si.cpu().numpy(), err_msg=name)
+        np.testing.assert_array_equal(ds[i].cpu().numpy(), ss.cpu().numpy(), err_msg=name)
+    np.testing.assert_array_equal(di.cpu().numpy(), di2.cpu().numpy())
