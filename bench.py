@@ -35,6 +35,8 @@ METRIC = "SGM Mdisp-evals/s at 1280x720x128; learned-window vs plain at same bad
 WORKLOADS = {
     "road1280": "1280x720 uint8 road pair, census 7x7, 8 paths, P1=10, P2=120, disparities 0-127",
     "road320": "320x240 uint8 road pair, census 5x5, 4 paths, P1=10, P2=120, disparities 0-31",
+    "road1280_pt": "1280x720 uint8 road pair, census 7x7, 8 paths, P1=10, P2=120, per-row windows of 24 "
+                   "disparities centred on the road model (perspective-transformed form)",
     "road_batch64": "64 uint8 road pairs in one batch: 24 x 640x480 (disparities 0-63), "
                     "24 x 1280x720 (0-127), 16 x 1920x1080 (0-191); census 7x7, 8 paths, "
                     "P1=10, P2=120; roll U(0,4) deg",
@@ -71,13 +73,14 @@ def counter_traffic(workload: str):
     return float(val.group(1))
 
 
-def eval_mask(p, w, r):
+def eval_mask(p, w, r, d_lo=None):
     """Pixels scored for accuracy: road, ground truth inside the window and
     away from the image border (census half-window r)."""
     import numpy as np
     H, W = p.gt.shape
     uu = np.arange(W)[None, :]
-    m = p.road & (p.gt < w - 1) & (uu - p.gt >= r)
+    lo = np.zeros((H, 1)) if d_lo is None else np.asarray(d_lo, np.float64)[:, None]
+    m = p.road & (p.gt >= lo) & (p.gt < lo + w - 1) & (uu - p.gt >= r)
     m[:r] = m[-r:] = False
     m[:, :r] = m[:, -r:] = False
     return m
@@ -304,6 +307,10 @@ def main():
     m = sgm.Matcher(W, H, census=n, ndisp=w, npaths=R, p1=p1, p2=p2, device=dev)
     left = torch.from_numpy(pair.left).to(dev)
     right = torch.from_numpy(pair.right).to(dev)
+    d_lo = None
+    if args.workload == "road1280_pt":  # per-row windows from the scene's road model, eq. (3), (6)
+        a0, a1, phi = pair.road_params
+        d_lo = sgm.sgm_window_from_road(a0, a1, phi, W, H, w, mode=0).to(dev)
     cost = m.new_volume(torch.uint8)
     paths = m.new_paths()
     dint = torch.empty((H, W), dtype=torch.int16, device=dev)
@@ -312,13 +319,13 @@ def main():
     def step(ev=None):
         if ev:
             ev[0].record()
-        m.cost(left, right, cost=cost)
+        m.cost(left, right, d_lo=d_lo, cost=cost)
         if ev:
             ev[1].record()
         m.aggregate_paths(cost, paths)
         if ev:
             ev[2].record()
-        m.wta_paths(paths, disp_int=dint, disp_sub=dsub)
+        m.wta_paths(paths, d_lo=d_lo, disp_int=dint, disp_sub=dsub)
         if ev:
             ev[3].record()
 
@@ -374,7 +381,7 @@ def main():
     # accuracy against the generator's ground truth (bad-pixel rate, eq. (18))
     torch.cuda.synchronize()
     ds = dsub.cpu().numpy()
-    mask = eval_mask(pair, w, n // 2)
+    mask = eval_mask(pair, w, n // 2, None if d_lo is None else d_lo.cpu().numpy())
     err = np.abs(ds - pair.gt)[mask]
     accuracy = {"bad_1px_pct": round(float((err > 1.0).mean() * 100), 4),
                 "rmse_px": round(float(np.sqrt((err ** 2).mean())), 4),
@@ -384,7 +391,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         t = time.perf_counter()
-        oracle.sgm(pair.left, pair.right, n, w, R, p1, p2)
+        oracle.sgm(pair.left, pair.right, n, w, R, p1, p2, None if d_lo is None else d_lo.cpu().numpy())
         dt = time.perf_counter() - t
         cpu = {"value": round(evals / dt / 1e6, 3), "unit": "Mdisp-evals/s",
                "cores": min(R, oracle.num_threads()), "kind": "oracle",
@@ -411,6 +418,9 @@ def main():
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "width": W, "height": H, "ndisp": w, "census": n, "npaths": R,
                    "p1": p1, "p2": p2, "evals_per_step": evals},
+        "full_range_equivalent": None if d_lo is None else {
+            "ndisp": 128, "value": round(W * H * 128 / (ms_per_step * 1e-3) / 1e6, 1),
+            "unit": "Mdisp-evals/s (pixels x 128 disparities per second)"},
         "roofline": roofline,
         "roofline_other_bound": alu if roofline is hbm else hbm,
         "step_hbm": {"bytes_per_eval": step_bytes_per_eval, "achieved": round(step_gbs, 1), "unit": "GB/s",
