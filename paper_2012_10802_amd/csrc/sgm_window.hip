@@ -13,6 +13,8 @@
 // ds_bpermute per neighbour offset (-1, 0, +1), which also covers the
 // window edges.
 
+#include <mutex>
+
 #include "sgm_device.h"
 #include "sgm_internal.h"
 
@@ -369,6 +371,66 @@ __device__ __forceinline__ int wave_max(int x)
     return x;
 }
 
+// One step of eq. (8) on per-pixel windows for one lane (one scanline):
+// L, m hold the predecessor's 16 values (packed u16 pairs) and their
+// minimum and are replaced by the new ones; c4 holds the 16 cost bytes; sh
+// = lo(p) - lo(q) (0 where q has no window).  Returns the new values as
+// bytes.  Every lane of the wave must call it (wave-uniform branches).
+__device__ __forceinline__ v4u win16_update(uint32_t (&L)[8], uint32_t &m, const v4u c4, const int sh,
+                                            const uint32_t P1, const uint32_t P2, uint32_t *row)
+{
+    // predecessor values at window indices j - 1, j, j + 1 of p's window:
+    // V[j] = L[j + sh - 1] for j = 0..17 (sentinel outside q's window),
+    // held as 9 packed pairs; Pm = V[0..15], P0 = V[1..16], Pp = V[2..17]
+    auto Ld = [&](int q) -> uint32_t { return (q >= 0 && q < 8) ? L[q] : kInf2; };
+    uint32_t V[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) V[q] = funnel16(Ld(q), Ld(q - 1));  // sh = 0
+    if (__ballot(sh != 0) != 0) {
+        if (__ballot(sh < -1 || sh > 1) != 0) {
+            // any shift: through the lane's LDS row
+#pragma unroll
+            for (int k = 0; k < 8; ++k) row[kW16Pad / 2 + k] = L[k];
+            const int e = min(max(sh - 1, -kW16Pad), 16);
+            const int b = e & 1;
+            const int base = (kW16Pad + e - b) >> 1;  // dword of V[0] (or of V[-1] when e is odd)
+            uint32_t D[10];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) D[q] = row[base + q];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) V[q] = b ? funnel16(D[q + 1], D[q]) : D[q];
+        } else {
+            // shifts of one: whole registers move
+#pragma unroll
+            for (int q = 0; q < 9; ++q) V[q] = sh == 1 ? Ld(q) : (sh == -1 ? Ld(q - 1) : V[q]);
+        }
+    }
+    uint32_t Pm[8], P0[8], Pp[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        Pm[k] = V[k];
+        P0[k] = funnel16(V[k + 1], V[k]);
+        Pp[k] = V[k + 1];
+    }
+    const uint32_t m2 = m | (m << 16);
+    const uint32_t mp2 = pk_add(m2, P2);
+    const uint32_t cw[4] = {c4.x, c4.y, c4.z, c4.w};
+    uint32_t Ln[8];
+    uint32_t mn = 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        uint32_t t = pk_add(pk_min(Pm[k], Pp[k]), P1);
+        t = pk_min(pk_min(t, P0[k]), mp2);
+        const uint32_t c = (k & 1) ? bytes_hi(cw[k >> 1]) : bytes_lo(cw[k >> 1]);
+        Ln[k] = pk_sub(pk_add(c, t), m2);
+        mn = pk_min(mn, Ln[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) L[k] = Ln[k];
+    m = min(mn & 0xFFFFu, mn >> 16);
+    return (v4u){pack4(Ln[0], Ln[1]), pack4(Ln[2], Ln[3]), pack4(Ln[4], Ln[5]), pack4(Ln[6], Ln[7])};
+}
+
 template <int PF, int KIND>
 __device__ __forceinline__ void win16_scan(const Win16Params &a, __amdgpu_buffer_rsrc_t rc,
                                            __amdgpu_buffer_rsrc_t rl, __amdgpu_buffer_rsrc_t ro, int du, int dv,
@@ -403,7 +465,7 @@ __device__ __forceinline__ void win16_scan(const Win16Params &a, __amdgpu_buffer
         ring_c[s] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rc, in ? px * 16u : kOff, 0, 0));
         ring_l[s] = __builtin_amdgcn_raw_buffer_load_b32(rl, in ? px * 4u : kOff, 0, 0);
     }
-    const uint32_t P1 = a.p1 | (a.p1 << 16);
+    const uint32_t P1 = a.p1 | (a.p1 << 16), P2 = a.p2 | (a.p2 << 16);
     uint32_t L[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) L[k] = 0u;
@@ -427,59 +489,10 @@ __device__ __forceinline__ void win16_scan(const Win16Params &a, __amdgpu_buffer
             ring_c[S] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rc, in ? px * 16u : kOff, 0, 0));
             ring_l[S] = __builtin_amdgcn_raw_buffer_load_b32(rl, in ? px * 4u : kOff, 0, 0);
         }
-        // predecessor values at window indices j - 1, j, j + 1 of p's window:
-        // V[j] = L[j + sh - 1] for j = 0..17 (sentinel outside q's window),
-        // held as 9 packed pairs; Pm = V[0..15], P0 = V[1..16], Pp = V[2..17]
         const int sh = (act && loq != kNoLo) ? lop - loq : 0;
-        auto Ld = [&](int q) -> uint32_t { return (q >= 0 && q < 8) ? L[q] : kInf2; };
-        uint32_t V[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) V[q] = funnel16(Ld(q), Ld(q - 1));  // sh = 0
-        if (__ballot(sh != 0) != 0) {
-            if (__ballot(sh < -1 || sh > 1) != 0) {
-                // any shift: through the lane's LDS row
-#pragma unroll
-                for (int k = 0; k < 8; ++k) row[kW16Pad / 2 + k] = L[k];
-                const int e = min(max(sh - 1, -kW16Pad), 16);
-                const int b = e & 1;
-                const int base = (kW16Pad + e - b) >> 1;  // dword of V[0] (or of V[-1] when e is odd)
-                uint32_t D[10];
-#pragma unroll
-                for (int q = 0; q < 10; ++q) D[q] = row[base + q];
-#pragma unroll
-                for (int q = 0; q < 9; ++q) V[q] = b ? funnel16(D[q + 1], D[q]) : D[q];
-            } else {
-                // shifts of one: whole registers move
-#pragma unroll
-                for (int q = 0; q < 9; ++q) V[q] = sh == 1 ? Ld(q) : (sh == -1 ? Ld(q - 1) : V[q]);
-            }
-        }
-        uint32_t Pm[8], P0[8], Pp[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            Pm[k] = V[k];
-            P0[k] = funnel16(V[k + 1], V[k]);
-            Pp[k] = V[k + 1];
-        }
-        const uint32_t m2 = m | (m << 16);
-        const uint32_t mp2 = pk_add(m2, a.p2 | (a.p2 << 16));
-        const uint32_t cw[4] = {c4.x, c4.y, c4.z, c4.w};
-        uint32_t Ln[8];
-        uint32_t mn = 0xFFFFFFFFu;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            uint32_t t = pk_add(pk_min(Pm[k], Pp[k]), P1);
-            t = pk_min(pk_min(t, P0[k]), mp2);
-            const uint32_t c = (k & 1) ? bytes_hi(cw[k >> 1]) : bytes_lo(cw[k >> 1]);
-            Ln[k] = pk_sub(pk_add(c, t), m2);
-            mn = pk_min(mn, Ln[k]);
-        }
-        const v4u o4 = {pack4(Ln[0], Ln[1]), pack4(Ln[2], Ln[3]), pack4(Ln[4], Ln[5]), pack4(Ln[6], Ln[7])};
+        const v4u o4 = win16_update(L, m, c4, sh, P1, P2, row);
         const uint32_t o = act ? (pix0 + (uint32_t)i * pstep) * 16u : kOff;
         __builtin_amdgcn_raw_buffer_store_b128(o4, ro, o, 0, kStreamPolicy);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) L[k] = Ln[k];
-        m = min(mn & 0xFFFFu, mn >> 16);
         loq = act ? lop : kNoLo;
     };
 
@@ -497,11 +510,136 @@ __device__ __forceinline__ void win16_scan(const Win16Params &a, __amdgpu_buffer
     }
 }
 
-// Horizontal directions keep the 16-lanes-per-scanline form of
-// agg_scan_win (4 rows per wave): with one scanline per lane, the 64 lanes
-// of a wave would sit in 64 different rows and every access would touch 64
-// cache lines.  Vertical and diagonal scanlines are neighbouring pixels of
-// one row at every step, so one scanline per lane stays contiguous.
+// Horizontal scanlines, one per lane, staged through LDS.  The 64 lanes of
+// a wave hold 64 rows, so a direct access per step would touch 64 cache
+// lines.  Instead the wave moves tiles of 8 pixels x 64 rows: the cost tile
+// (8 KB) and the window starts (2 KB) are fetched with 8 rows x 128 bytes
+// per load instruction into a register ring two tiles ahead, written to LDS,
+// read back one pixel per lane and step, and the results go out the same
+// way.  The cost and output tiles are XOR-swizzled (unit (r, p) at
+// r * 8 + (p ^ (r & 7))) so that both the row-wise copies and the per-lane
+// reads are free of bank conflicts; the window-start tile has rows of 9
+// dwords.  One wave per workgroup: LDS is private to the wave and needs no
+// barrier.
+
+constexpr int kHT = 8;      // pixels per tile
+constexpr int kHRing = 2;   // tiles in flight ahead of the one processed
+
+__global__ __launch_bounds__(64) void k_aggregate_win16_h(Win16Params a)
+{
+    __shared__ v4u s_c[64 * kHT];
+    __shared__ v4u s_o[64 * kHT];
+    __shared__ uint32_t s_l[64 * (kHT + 1)];
+    __shared__ uint32_t rows[64 * kW16Row];
+    // few, long scanlines sharing SIMDs with the vertical and diagonal
+    // waves: let them issue first
+    __builtin_amdgcn_s_setprio(3);
+    const int lane = threadIdx.x;
+    uint32_t *row = rows + lane * kW16Row;
+#pragma unroll
+    for (int q = 0; q < kW16Row; ++q) row[q] = kInf2;
+    int slot = 0;
+    while (slot + 1 < a.np && (int)blockIdx.x >= a.gstart[slot + 1]) ++slot;
+    slot = __builtin_amdgcn_readfirstlane(slot);
+    const int r = __builtin_amdgcn_readfirstlane(a.paths[slot] & 0xFF);
+    const int vol = __builtin_amdgcn_readfirstlane(a.paths[slot] >> 8);
+    const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x - a.gstart[slot]);
+    const int du = __builtin_amdgcn_readfirstlane(dir_du(r));
+    const int pr = blockIdx.y;
+    const int W = a.W, H = a.H;
+    const uint32_t npix = (uint32_t)W * (uint32_t)H;
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost + pr * a.cost_pair, npix * 16u);
+    const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.lo + pr * a.lo_pair, npix * 4u);
+    const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out + pr * a.out_pair + (size_t)vol * a.vstride, npix * 16u);
+    const int R0 = g * 64;            // first row of this wave
+    const int K = (W + kHT - 1) / kHT;  // tiles per row
+    // row-wise copy mapping: copy q (0..7) moves rows 8q .. 8q+7, lane l at
+    // row 8q + l/8, pixel unit (l % 8) ^ (row & 7); its LDS unit is 64q + l
+    const int crow = lane >> 3, cu = lane & 7;
+    // (unsigned compares and bitwise & keep these branch-free)
+    auto cost_off = [&](int k, int q) -> uint32_t {
+        const int rr = 8 * q + crow, x = kHT * k + (cu ^ (rr & 7)), y = R0 + rr;
+        const bool in = ((uint32_t)y < (uint32_t)H) & ((uint32_t)x < (uint32_t)W);
+        return in ? ((uint32_t)y * (uint32_t)W + (uint32_t)x) * 16u : kOff;
+    };
+    auto lo_off = [&](int k, int q) -> uint32_t {
+        const int rr = 8 * q + crow, x = kHT * k + cu, y = R0 + rr;
+        const bool in = ((uint32_t)y < (uint32_t)H) & ((uint32_t)x < (uint32_t)W);
+        return in ? ((uint32_t)y * (uint32_t)W + (uint32_t)x) * 4u : kOff;
+    };
+    v4u ring_c[kHRing][8];
+    uint32_t ring_l[kHRing][8];
+    auto fetch = [&](int t, int slot_) __attribute__((always_inline)) {
+        // tile number t of the scan (t >= K loads nothing)
+        // (t >= K gives k outside 0..K-1, so every offset is kOff)
+        const int k = du > 0 ? t : K - 1 - t;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            ring_c[slot_][q] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rc, cost_off(k, q), 0, 0));
+            ring_l[slot_][q] = __builtin_amdgcn_raw_buffer_load_b32(rl, lo_off(k, q), 0, 0);
+        }
+    };
+#pragma unroll
+    for (int t = 0; t < kHRing; ++t) fetch(t, t);
+
+    const uint32_t P1 = a.p1 | (a.p1 << 16), P2 = a.p2 | (a.p2 << 16);
+    uint32_t L[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) L[k] = 0u;
+    uint32_t m = 0u;
+    int loq = kNoLo;
+    const int y = R0 + lane;
+    // 16 loads and 8 stores per tile; the tile's loads were issued two tiles
+    // ago, followed by the previous tiles' stores and the next tile's loads
+    constexpr int kAfter = 8 + 16 + 8;
+    auto tile = [&](const int t, const int sl) __attribute__((always_inline)) {
+        const int k = du > 0 ? t : K - 1 - t;
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(kAfter));
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            s_c[64 * q + lane] = ring_c[sl][q];
+            s_l[(8 * q + crow) * (kHT + 1) + cu] = ring_l[sl][q];
+        }
+        // this lane's 8 pixels of the tile, read before the dependent chain
+        v4u c4s[kHT];
+        int lops[kHT];
+#pragma unroll
+        for (int s = 0; s < kHT; ++s) {
+            const int pp = du > 0 ? s : kHT - 1 - s;
+            c4s[s] = s_c[lane * 8 + (pp ^ (lane & 7))];
+            lops[s] = (int)s_l[lane * (kHT + 1) + pp];
+        }
+        fetch(t + kHRing, sl);
+#pragma unroll
+        for (int s = 0; s < kHT; ++s) {
+            const int pp = du > 0 ? s : kHT - 1 - s;
+            const int x = kHT * k + pp;
+            const bool act = t < K && x < W && y < H;
+            const v4u c4 = c4s[s];
+            const int lop = lops[s];
+            const int sh = (act && loq != kNoLo) ? lop - loq : 0;
+            const v4u o4 = win16_update(L, m, c4, sh, P1, P2, row);
+            s_o[lane * 8 + (pp ^ (lane & 7))] = o4;
+            loq = act ? lop : kNoLo;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            __builtin_amdgcn_raw_buffer_store_b128(s_o[64 * q + lane], ro, cost_off(k, q), 0, kStreamPolicy);
+    };
+    // the first turn of the ring outside the loop, so that the loop head
+    // sees the same loads in flight from both sides
+#pragma unroll
+    for (int sl = 0; sl < kHRing; ++sl) tile(sl, sl);
+    for (int tb = kHRing; tb < K; tb += kHRing) {
+#pragma unroll
+        for (int sl = 0; sl < kHRing; ++sl) tile(tb + sl, sl);
+    }
+}
+
+// Vertical and diagonal scanlines: neighbouring lanes are neighbouring
+// pixels of one row at every step, so one scanline per lane keeps every
+// access contiguous.
 template <int PF>
 __global__ __launch_bounds__(256, 4) void k_aggregate_win16(Win16Params a)
 {
@@ -519,17 +657,6 @@ __global__ __launch_bounds__(256, 4) void k_aggregate_win16(Win16Params a)
     const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost + pr * a.cost_pair, npix * 16u);
     const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.lo + pr * a.lo_pair, npix * 4u);
     const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out + pr * a.out_pair + (size_t)vol * a.vstride, npix * 16u);
-    if (dv == 0) {
-        WinParams h{};
-        h.W = a.W;
-        h.H = a.H;
-        h.w = 16;
-        h.p1 = a.p1;
-        h.p2 = a.p2;
-        __builtin_amdgcn_s_setprio(2);  // the longest scanlines
-        agg_scan_win<true, kWinPrefetch, kHorizontal>(h, rc, rl, ro, du, dv, g);
-        return;
-    }
 #pragma unroll
     for (int q = 0; q < kW16Row; ++q) row[q] = kInf2;  // sentinel padding; values are written per use
     if (du == 0)
@@ -604,6 +731,32 @@ hipError_t launch_wta_win(const Problem &pb, const void *vols, long long vstride
     return hipGetLastError();
 }
 
+// A second stream per device for the horizontal aggregation, which has
+// too few scanlines (one wave per 64 rows) to fill the chip on its own and
+// runs beside the vertical and diagonal one.  Created on first use; the
+// fork / join (event record + stream wait) is serialised across host threads.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool ok = false, tried = false;
+};
+static std::mutex g_side_mutex;
+static SideStream g_side[64];
+
+static SideStream *side_stream()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    SideStream &ss = g_side[dev];
+    if (!ss.tried) {
+        ss.tried = true;
+        ss.ok = hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) == hipSuccess &&
+                hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess &&
+                hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) == hipSuccess;
+    }
+    return ss.ok ? &ss : nullptr;
+}
+
 hipError_t launch_match_win_pairs(const Problem &pb, const WinPairs &b, hipStream_t s)
 {
     const long long npix = (long long)pb.W * pb.H;
@@ -648,21 +801,45 @@ hipError_t launch_match_win_pairs(const Problem &pb, const WinPairs &b, hipStrea
         p.p1 = (uint32_t)pb.p1;
         p.p2 = (uint32_t)pb.p2;
         p.np = pb.npaths;
+        // horizontal directions: one wave (64 rows) per workgroup, LDS-staged
+        Win16Params h = p;
         int acc = 0, no = 0;
-        // horizontal groups first (the longest scanlines), then diagonal, then vertical
-        for (const int kind : {0, 2, 1})
-            for (int r = 0; r < pb.npaths; ++r) {
-                const int k = (r <= 1) ? 0 : (r >= 4 ? 2 : 1);
+        for (int r = 0; r < 2 && r < pb.npaths; ++r) {
+            h.paths[no] = r | (r << 8);
+            h.gstart[no] = acc;
+            acc += (pb.H + 63) / 64;
+            ++no;
+        }
+        h.np = no;
+        h.gstart[no] = acc;
+        std::unique_lock<std::mutex> lock(g_side_mutex);
+        SideStream *ss = side_stream();
+        hipStream_t hs = s;
+        if (ss && hipEventRecord(ss->fork, s) == hipSuccess && hipStreamWaitEvent(ss->stream, ss->fork, 0) == hipSuccess)
+            hs = ss->stream;
+        if (no > 0) hipLaunchKernelGGL(k_aggregate_win16_h, dim3(acc, b.npairs), dim3(64), 0, hs, h);
+        // vertical and diagonal directions: diagonal groups first
+        acc = 0;
+        no = 0;
+        for (const int kind : {2, 1})
+            for (int r = 2; r < pb.npaths; ++r) {
+                const int k = r >= 4 ? 2 : 1;
                 if (k != kind) continue;
-                const int nl = (r <= 1) ? pb.H : (r <= 3 ? pb.W : pb.W + pb.H - 1);
-                const int lpg = (r <= 1) ? 16 : kW16Lines;  // scanlines per workgroup
+                const int nl = r <= 3 ? pb.W : pb.W + pb.H - 1;
                 p.paths[no] = r | (r << 8);
                 p.gstart[no] = acc;
-                acc += (nl + lpg - 1) / lpg;
+                acc += (nl + kW16Lines - 1) / kW16Lines;
                 ++no;
             }
-        p.gstart[pb.npaths] = acc;
-        hipLaunchKernelGGL(k_aggregate_win16<kWin16Prefetch>, dim3(acc, b.npairs), dim3(kW16Lines), 0, s, p);
+        p.np = no;
+        p.gstart[no] = acc;
+        if (no > 0)
+            hipLaunchKernelGGL(k_aggregate_win16<kWin16Prefetch>, dim3(acc, b.npairs), dim3(kW16Lines), 0, s, p);
+        if (hs != s) {
+            const hipError_t e1 = hipEventRecord(ss->join, hs);
+            const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s, ss->join, 0) : e1;
+            if (e2 != hipSuccess) return e2;
+        }
     }
     // selection of every pair
     {

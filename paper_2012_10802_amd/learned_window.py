@@ -233,7 +233,7 @@ class LearnedWindowMatcher:
     full-range fallback, for batches of `batch` pairs of one size."""
 
     def __init__(self, width, height, batch=1, ndisp=192, window=16, census=7, npaths=8, p1=10,
-                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, device="cuda"):
+                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, fallback_streams=4, device="cuda"):
         if width % 4 or height % 4 or ndisp % 4:
             raise ValueError("width, height and ndisp must be multiples of 4")
         self.W, self.H, self.D, self.w, self.n = width, height, ndisp, window, batch
@@ -269,21 +269,28 @@ class LearnedWindowMatcher:
             need = S.sgm_workspace_size(full)
         finally:
             S.sgm_plan_free(full)
-        self.full_ws = torch.empty(need, dtype=torch.uint8, device=dev)
-        self.band_int = torch.empty(height * width, dtype=torch.int16, device=dev)
-        self.band_sub = torch.empty(height * width, dtype=torch.float32, device=dev)
-        self._full = {}
+        # The rectangles are small (a few hundred scanlines each), so the
+        # pairs' fallbacks run on several streams at once; each stream owns
+        # a full-frame workspace and result buffers, and pair i always uses
+        # stream i % len(streams), so no two streams touch one pair.
+        nst = max(1, min(fallback_streams, n))
+        self.fb_streams = [torch.cuda.Stream(device=dev) for _ in range(nst)]
+        self.fb_ws = [torch.empty(need, dtype=torch.uint8, device=dev) for _ in range(nst)]
+        self.fb_int = [torch.empty(height * width, dtype=torch.int16, device=dev) for _ in range(nst)]
+        self.fb_sub = [torch.empty(height * width, dtype=torch.float32, device=dev) for _ in range(nst)]
+        self._full = [{} for _ in range(nst)]
         self.last_rects = []
 
-    def _full_matcher(self, rows, cols):
+    def _full_matcher(self, j, rows, cols):
+        cache = self._full[j]
         key = (rows, cols)
-        m = self._full.pop(key, None)
+        m = cache.pop(key, None)
         if m is None:
             m = S.Matcher(cols, rows, census=self.census, ndisp=self.D, npaths=self.npaths, p1=self.p1,
-                          p2=self.p2, device=self.device, workspace=self.full_ws)
-            while len(self._full) >= 256:  # plans are host objects; keep the most recent
-                self._full.pop(next(iter(self._full)))
-        self._full[key] = m
+                          p2=self.p2, device=self.device, workspace=self.fb_ws[j])
+            while len(cache) >= 256:  # plans are host objects; keep the most recent
+                cache.pop(next(iter(cache)))
+        cache[key] = m
         return m
 
     def windows(self, left, right, stream=None):
@@ -311,19 +318,29 @@ class LearnedWindowMatcher:
                                     stream=stream)
 
     def fallback(self, left, right, stream=None):
-        """Step 6 (synchronises once to read the per-row statistics)."""
+        """Step 6 (waits once for `stream` to read the per-row statistics)."""
+        main = stream if stream is not None else torch.cuda.current_stream(self.device)
+        main.synchronize()
         stats = self.stats.cpu().numpy()
         self.last_rects = []
+        used = set()
         for i in range(self.n):
             rects = fallback_rects(stats[i], self.W, self.D, self.census // 2, self.margin, self.full_fraction)
             self.last_rects.append(rects)
+            j = i % len(self.fb_streams)
+            st = self.fb_streams[j]
+            if rects and j not in used:
+                st.wait_stream(main)  # inputs, masks and windowed results are ready
+                used.add(j)
             for y0, y1, x0, x1 in rects:
                 h, w = y1 - y0, x1 - x0
-                bi = self.band_int[:h * w].view(h, w)
-                bs = self.band_sub[:h * w].view(h, w)
-                self._full_matcher(h, w).match_at(left[i], right[i], y0, x0, disp_int=bi, disp_sub=bs,
-                                                  stream=stream)
-                fallback_merge(self.mask[i], bi, bs, y0, x0, self.dint[i], self.dsub[i], stream)
+                bi = self.fb_int[j][:h * w].view(h, w)
+                bs = self.fb_sub[j][:h * w].view(h, w)
+                self._full_matcher(j, h, w).match_at(left[i], right[i], y0, x0, disp_int=bi, disp_sub=bs,
+                                                     stream=st)
+                fallback_merge(self.mask[i], bi, bs, y0, x0, self.dint[i], self.dsub[i], st)
+        for j in sorted(used):
+            main.wait_stream(self.fb_streams[j])
 
     def match(self, left, right, stream=None):
         """Returns (disp_int int16 [n,H,W], disp_sub float32 [n,H,W]) device tensors."""
