@@ -348,6 +348,16 @@ sgm_status launched(const char *what)
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// n images of W x H: sizes >= 1, and every element index (16 channels per
+// pixel) fits the kernels' 32-bit arithmetic
+sgm_status check_images(int32_t width, int32_t height, int32_t nimg)
+{
+    if (width < 1 || height < 1 || nimg < 1) return cfail(SGM_ERR_INVALID, "sizes must be >= 1");
+    if ((long long)width * height * nimg * CH >= (1ll << 31))
+        return cfail(SGM_ERR_UNSUPPORTED, "nimg * height * width * 16 must be < 2^31");
+    return SGM_OK;
+}
+
 }  // namespace
 }  // namespace sgm
 
@@ -377,7 +387,7 @@ sgm_status sgm_cnn_prepare_input(const float *coarse_disp, const uint8_t *coarse
                                  int32_t nimg, uint16_t *x0, void *stream)
 {
     if (!coarse_disp || !coarse_left || !x0) return cfail(SGM_ERR_INVALID, "NULL buffer");
-    if (width < 1 || height < 1 || nimg < 1) return cfail(SGM_ERR_INVALID, "bad size");
+    if (sgm_status st = check_images(width, height, nimg)) return st;
     if (!aligned(x0, 16)) return cfail(SGM_ERR_INVALID, "x0 must be 16-byte aligned");
     const int npix = width * height * nimg;
     hipLaunchKernelGGL(k_prepare_input, dim3((npix + 255) / 256), dim3(256), 0, (hipStream_t)stream, coarse_disp,
@@ -389,7 +399,7 @@ sgm_status sgm_cnn_forward(const uint16_t *wf, const float *params, const uint16
                            int32_t nimg, uint16_t *acts, float *out, void *stream)
 {
     if (!wf || !params || !x0 || !acts || !out) return cfail(SGM_ERR_INVALID, "NULL buffer");
-    if (width < 1 || height < 1 || nimg < 1) return cfail(SGM_ERR_INVALID, "bad size");
+    if (sgm_status st = check_images(width, height, nimg)) return st;
     if (!aligned(x0, 8) || !aligned(acts, 8) || !aligned(wf, 8)) return cfail(SGM_ERR_INVALID, "misaligned buffer");
     const size_t act = (size_t)nimg * height * width * CH;
     const int nstrips = nimg * height * ((width + 15) / 16);
@@ -415,7 +425,7 @@ sgm_status sgm_cnn_loss(const float *out, const float *coarse_disp, const float 
                         int32_t nimg, uint16_t *dy, float *loss_sum, void *stream)
 {
     if (!out || !coarse_disp || !label || !dy) return cfail(SGM_ERR_INVALID, "NULL buffer");
-    if (width < 1 || height < 1 || nimg < 1) return cfail(SGM_ERR_INVALID, "bad size");
+    if (sgm_status st = check_images(width, height, nimg)) return st;
     if (!aligned(dy, 16)) return cfail(SGM_ERR_INVALID, "dy must be 16-byte aligned");
     const int npix = width * height * nimg;
     hipLaunchKernelGGL(k_loss, dim3((npix + 255) / 256), dim3(256), 0, (hipStream_t)stream, out, coarse_disp, label,
@@ -428,7 +438,7 @@ sgm_status sgm_cnn_backward(const uint16_t *wb, const uint16_t *x0, const uint16
                             size_t scratch_bytes, void *stream)
 {
     if (!wb || !x0 || !acts || !dy_out || !grad || !scratch) return cfail(SGM_ERR_INVALID, "NULL buffer");
-    if (width < 1 || height < 1 || nimg < 1) return cfail(SGM_ERR_INVALID, "bad size");
+    if (sgm_status st = check_images(width, height, nimg)) return st;
     if (scratch_bytes < sgm_cnn_scratch_bytes(width, height, nimg))
         return cfail(SGM_ERR_WORKSPACE, "scratch smaller than sgm_cnn_scratch_bytes");
     if (!aligned(scratch, 256)) return cfail(SGM_ERR_INVALID, "scratch must be 256-byte aligned");
@@ -477,6 +487,9 @@ sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_
     if (!coarse_disp || !cnn_out || !lo) return cfail(SGM_ERR_INVALID, "NULL buffer");
     if (coarse_width < 1 || coarse_height < 1 || width < 1 || height < 1 || w < 1 || w > ndisp || ndisp > 256)
         return cfail(SGM_ERR_INVALID, "bad size");
+    if (height > 65535 || (long long)width * height >= (1ll << 31) ||
+        (long long)coarse_width * coarse_height * CH >= (1ll << 31))
+        return cfail(SGM_ERR_UNSUPPORTED, "image too large");
     if (conf_threshold != conf_threshold) return cfail(SGM_ERR_INVALID, "threshold is NaN");
     // confident iff sigmoid(logit) > tau  <=>  logit > log(tau / (1 - tau))
     float thr;
@@ -505,6 +518,7 @@ sgm_status sgm_fallback_merge(const uint8_t *fallback_mask, const int16_t *band_
         x0 + cols > width)
         return cfail(SGM_ERR_INVALID, "rectangle outside the frame");
     if (rows == 0 || cols == 0) return SGM_OK;
+    if (rows > 65535) return cfail(SGM_ERR_UNSUPPORTED, "more than 65535 rows");
     dim3 grid((cols + 255) / 256, rows), block(256);
     hipLaunchKernelGGL(k_merge_fallback, grid, block, 0, (hipStream_t)stream, fallback_mask, band_int, band_sub,
                        width, y0, rows, x0, cols, disp_int, disp_sub);
@@ -515,6 +529,8 @@ sgm_status sgm_label_downsample4(const float *label, int32_t width, int32_t heig
 {
     if (!label || !coarse) return cfail(SGM_ERR_INVALID, "NULL buffer");
     if (width < 4 || height < 4) return cfail(SGM_ERR_INVALID, "need width, height >= 4");
+    if (height / 4 > 65535 || (long long)width * height >= (1ll << 31))
+        return cfail(SGM_ERR_UNSUPPORTED, "image too large");
     dim3 grid((width / 4 + 255) / 256, height / 4), block(256);
     hipLaunchKernelGGL(k_label_downsample4, grid, block, 0, (hipStream_t)stream, label, width, height, coarse);
     return launched("label downsample");

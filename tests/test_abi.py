@@ -178,3 +178,29 @@ def test_window_batch_needs_width_16():
         assert lib.sgm_workspace_size_win_batch(plan, 0, ctypes.byref(b)) == -1
     finally:
         sgm.sgm_plan_free(plan)
+
+
+def test_cnn_and_window_calls_validate_before_launch():
+    """Size, threshold and rectangle checks of the network / window-map /
+    fallback calls return their status before anything is enqueued (dummy
+    non-NULL pointers are never touched)."""
+    import ctypes
+    from paper_2012_10802_amd import sgm
+    lib = sgm.library()
+    d = ctypes.c_void_p(256)  # never dereferenced: every call below fails validation
+    f = ctypes.c_float
+    # sizes
+    assert lib.sgm_cnn_forward(d, d, d, 0, 8, 1, d, d, None) == -1
+    assert lib.sgm_cnn_forward(d, d, d, 1 << 16, 1 << 12, 1, d, d, None) == -2
+    assert lib.sgm_cnn_prepare_input(d, d, 8, 8, 0, d, None) == -1
+    assert lib.sgm_cnn_loss(d, d, d, 8, -1, 1, d, None, None) == -1
+    assert lib.sgm_cnn_backward(d, d, d, d, 8, 8, 1, d, d, 0, None) == -4  # scratch too small
+    assert lib.sgm_cnn_adam(d, d, d, d, 0, f(1e-3), f(0.9), f(0.999), f(1e-8), d, d, None) == -1
+    # window map: NaN threshold, window wider than the range
+    assert lib.sgm_window_map(d, d, 4, 4, 16, 16, 192, 16, f(float("nan")), d, None, None, None, None) == -1
+    assert lib.sgm_window_map(d, d, 4, 4, 16, 16, 8, 16, f(0.5), d, None, None, None, None) == -1
+    # fallback merge: rectangle outside the frame, too many rows
+    assert lib.sgm_fallback_merge(d, d, None, 100, 50, 40, 20, 0, 10, d, None, None) == -1
+    assert lib.sgm_fallback_merge(d, d, None, 100, 50, 0, 10, 95, 10, d, None, None) == -1
+    assert lib.sgm_fallback_merge(d, d, None, 4, 70000, 0, 70000, 0, 4, d, None, None) == -2
+    assert lib.sgm_label_downsample4(d, 3, 8, d, None) == -1
