@@ -145,6 +145,10 @@ def run_batch(args):
                    "pairs": len(pairs), "evals_per_step": evals, "unique_renders": len(renders)},
         "tuning": {"waves_per_cu": tuning[0], "order": ["longest-first", "pair-major",
                                                         "direction-major"][tuning[1]]},
+        # whole step: cost written once and read by each of the 8 directions,
+        # 8 uint8 volumes written and read back by the selection
+        "step_hbm": {"bytes_per_eval": 25, "achieved": round(evals * 25 / (ms * 1e-3) / 1e9, 1), "unit": "GB/s",
+                     "frac": round(evals * 25 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernel_source_sha256": kernel_source_digest(),
     }
     print(json.dumps(out), flush=True)

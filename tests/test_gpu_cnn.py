@@ -403,3 +403,58 @@ def test_full_fallback_is_plain_sgm(lw):
         np.testing.assert_array_equal(dsub[i].cpu().numpy(), pf.cpu().numpy())
         wi, _ = oracle.sgm(L[i], R[i], 7, D, 8, 10, 120)
         np.testing.assert_array_equal(dint[i].cpu().numpy().astype(np.uint16), wi)
+
+
+def test_learned_window_full_size_batch16(lw):
+    """The configuration the benchmark times: a batch of 16 1920x1080 road
+    pairs (disparities 0..191, census 7x7, 8 paths) through the trained
+    network.  Two pairs are checked stage by stage against the oracle; every
+    pair's result equals the single-pair windowed path on the same windows,
+    with the fallback rectangles' plain full-range SGM merged in."""
+    import torch
+    from paper_2012_10802_amd import sgm as S
+    n, H, W, D, w = 16, 1080, 1920, 192, 16
+    Ls, Rs = [], []
+    for i in range(n):
+        sd = 777 + i
+        l, r, _, _ = synth.make_pair_torch(synth.scene_for_config("road1920", sd), sd, device="cuda")
+        Ls.append(l)
+        Rs.append(r)
+    Ld, Rd = torch.stack(Ls).contiguous(), torch.stack(Rs).contiguous()
+    m = lw.LearnedWindowMatcher(W, H, batch=n, ndisp=D, window=w)
+    dint, dsub = m.match(Ld, Rd)
+    torch.cuda.synchronize()
+    single = S.Matcher(W, H, census=7, ndisp=w, npaths=8, p1=10, p2=120)
+    for i in range(n):
+        si, ss = single.match_win(Ld[i], Rd[i], m.lo[i])
+        want_i, want_s = si.clone(), ss.clone()
+        for (y0, y1, x0, x1) in m.last_rects[i]:
+            full = S.Matcher(x1 - x0, y1 - y0, census=7, ndisp=D, npaths=8, p1=10, p2=120)
+            fi, fs = full.match_at(Ld[i], Rd[i], y0, x0)
+            msk = m.mask[i][y0:y1, x0:x1].bool()
+            want_i[y0:y1, x0:x1][msk] = fi[msk]
+            want_s[y0:y1, x0:x1][msk] = fs[msk]
+        torch.cuda.synchronize()
+        assert torch.equal(dint[i], want_i), i
+        assert torch.equal(dsub[i], want_s), i
+    params = m.net.params.cpu().numpy()
+    for i in (0, 9):
+        L, R = Ld[i].cpu().numpy(), Rd[i].cpu().numpy()
+        Lc, Rc = oracle.downsample4(L), oracle.downsample4(R)
+        ci, cs = oracle.sgm(Lc, Rc, 7, D // 4, 8, 10, 120)
+        np.testing.assert_array_equal(m.coarse.disp_int[i].cpu().numpy().astype(np.uint16), ci)
+        gcs = m.coarse.disp_sub[i].cpu().numpy()
+        assert np.abs(gcs - cs).max() <= 1e-4
+        x0 = ocnn.prepare_input(gcs, Lc)
+        _, want_out = ocnn.forward(params, x0)
+        gout = m.out[i:i + 1].cpu().numpy()
+        assert np.abs(gout - want_out).max() <= 0.02 * np.abs(want_out).max()
+        want_lo, _, want_mask = ocnn.window_map(gcs, gout, W, H, D, w, m.tau)
+        np.testing.assert_array_equal(m.lo[i].cpu().numpy(), want_lo)
+        rects = ocnn.fallback_rects(want_mask, m.margin, m.full_fraction, D, 3)
+        assert m.last_rects[i] == rects
+        wi, ws = oracle.sgm_win(L, R, 7, w, 8, 10, 120, want_lo)
+        res = [oracle.sgm(L[a:b, x0:x1], R[a:b, x0:x1], 7, D, 8, 10, 120) for a, b, x0, x1 in rects]
+        fi, fs = ocnn.merge_fallback(wi, ws, want_mask, rects, res)
+        np.testing.assert_array_equal(dint[i].cpu().numpy().astype(np.uint16), fi)
+        assert np.abs(dsub[i].cpu().numpy() - fs).max() <= 1e-4
