@@ -306,8 +306,17 @@ __device__ __forceinline__ void cost_tile(const uint64_t *__restrict__ cl, const
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
                 const int kk = 4 * q + h;
-                uint32_t c = (uint32_t)cmax;
-                if (col0 - kk >= 0 && k0 + kk < w) c = (uint32_t)__popcll(a ^ s_cr[base - kk]);
+                uint32_t c;
+                if constexpr (CH == 16) {
+                    // w % 16 == 0: every kk is inside the window and base - kk
+                    // inside s_cr, so the read is unconditional and only the
+                    // off-image columns are replaced (branch-free)
+                    const uint32_t pc = (uint32_t)__popcll(a ^ s_cr[base - kk]);
+                    c = col0 - kk >= 0 ? pc : (uint32_t)cmax;
+                } else {
+                    c = (uint32_t)cmax;
+                    if (col0 - kk >= 0 && k0 + kk < w) c = (uint32_t)__popcll(a ^ s_cr[base - kk]);
+                }
                 wd |= c << (8 * h);
             }
             word[q] = wd;
@@ -862,7 +871,20 @@ __device__ __forceinline__ void wta_paths_group(const void *__restrict__ vols, l
         uint32_t ev[NW], od[NW];
 #pragma unroll
         for (int q = 0; q < NW; ++q) ev[q] = od[q] = 0;
-        if (nvalid > 0) {
+        if (nvalid > 0 && np == 8) {
+            // all eight volumes in flight at once
+            const uint8_t *base = static_cast<const uint8_t *>(vols) + pix * w + kbase;
+            Raw<VPL> x[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) load_u8<VPL, ALIGNED>(x[r], base + r * vstride, nvalid);
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    ev[q] += x[r].d[q] & 0x00FF00FFu;
+                    od[q] += (x[r].d[q] >> 8) & 0x00FF00FFu;
+                }
+        } else if (nvalid > 0) {
             const uint8_t *base = static_cast<const uint8_t *>(vols) + pix * w + kbase;
             int r = 0;
             for (; r + 1 < np; r += 2) {
