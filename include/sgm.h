@@ -204,6 +204,11 @@ sgm_status sgm_match_win_batch(sgm_plan_t plan, const uint8_t *left, const uint8
  * value (sum of its 16 pixels + 8) / 16.  Device buffers; needs W, H >= 4. */
 sgm_status sgm_downsample4(const uint8_t *image, int32_t width, int32_t height, int32_t pitch,
                            uint8_t *out, void *stream);
+/* The same for nimg images image_stride bytes apart (>= pitch * height);
+ * out holds the nimg results packed, [nimg][H/4][W/4]. */
+sgm_status sgm_downsample4_batch(const uint8_t *images, int32_t width, int32_t height,
+                                 int32_t pitch, int64_t image_stride, int32_t nimg, uint8_t *out,
+                                 void *stream);
 
 /* ------------------------------------------------------------------------
  * The search-window network (learned-window form) and its training.
@@ -272,6 +277,15 @@ sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_
                           int32_t coarse_height, int32_t width, int32_t height, int32_t ndisp,
                           int32_t w, float conf_threshold, int32_t *lo, uint8_t *fallback_mask,
                           int32_t *row_stats, uint32_t *nfallback, void *stream);
+/* The same for nimg images at once: every buffer holds the images packed
+ * one after another (coarse_disp [nimg][Hc][Wc], cnn_out [nimg][Hc][Wc][16],
+ * lo and fallback_mask [nimg][H][W], row_stats [nimg][3][H], nfallback
+ * [nimg]). */
+sgm_status sgm_window_map_batch(const float *coarse_disp, const float *cnn_out,
+                                int32_t coarse_width, int32_t coarse_height, int32_t width,
+                                int32_t height, int32_t ndisp, int32_t w, float conf_threshold,
+                                int32_t nimg, int32_t *lo, uint8_t *fallback_mask, int32_t *row_stats,
+                                uint32_t *nfallback, void *stream);
 /* The full-range fallback: the full-range SGM result of the rectangle rows
  * y0 .. y0+rows-1, columns x0 .. x0+cols-1 (band_int int16 / band_sub
  * float32, [rows][cols], band_sub may be NULL) replaces the windowed result

@@ -80,6 +80,12 @@ __device__ __forceinline__ Strip strip_of(int s, int W, int H)
 // MODE 0: hidden layer forward  (out = bf16(relu(conv + b)))
 // MODE 1: last layer forward    (out32 = conv + b, float)
 // MODE 2: input gradient        (dx = conv^T(dy); out = bf16(dx * [mask > 0]))
+//
+// A wave takes kStripsPerWave consecutive strips: the 9 taps' weight
+// operands stay in registers, and each strip's 9 input loads are issued
+// before its 9 MFMAs.
+constexpr int kStripsPerWave = 8;
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ x, const uint16_t *__restrict__ wt,
                                               const float *__restrict__ bias, const uint16_t *__restrict__ mask,
@@ -87,36 +93,45 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ x, co
                                               float *__restrict__ out32)
 {
     const int lane = threadIdx.x & 63;
-    const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (s >= nstrips) return;
-    const Strip st = strip_of(s, W, H);
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int s_first = wave * kStripsPerWave;
+    if (s_first >= nstrips) return;
     const int i = lane & 15, g = lane >> 4;
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    v4s b[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        int dy = t / 3 - 1, dx = t % 3 - 1;
-        if (MODE == 2) {  // transpose: the gradient flows back from p - offset
-            dy = -dy;
-            dx = -dx;
+    for (int t = 0; t < 9; ++t) b[t] = load4(wt + (size_t)t * CH * CH + (size_t)i * CH + 4 * g);
+    const float bi = MODE == 2 ? 0.0f : bias[i];
+    const int s_end = min(s_first + kStripsPerWave, nstrips);
+    for (int s = s_first; s < s_end; ++s) {
+        const Strip st = strip_of(s, W, H);
+        v4s a[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            int dy = t / 3 - 1, dx = t % 3 - 1;
+            if (MODE == 2) {  // transpose: the gradient flows back from p - offset
+                dy = -dy;
+                dx = -dx;
+            }
+            const int yy = st.y + dy, xx = st.x0 + i + dx;
+            a[t] = (v4s){0, 0, 0, 0};
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                a[t] = load4(x + (((size_t)st.n * H + yy) * W + xx) * CH + 4 * g);
         }
-        const int yy = st.y + dy, xx = st.x0 + i + dx;
-        v4s a = {0, 0, 0, 0};
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-            a = load4(x + (((size_t)st.n * H + yy) * W + xx) * CH + 4 * g);
-        const v4s b = load4(wt + (size_t)t * CH * CH + (size_t)i * CH + 4 * g);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int xo = st.x0 + 4 * g + r;
-        if (xo >= W) continue;
-        const size_t o = (((size_t)st.n * H + st.y) * W + xo) * CH + i;
-        if (MODE == 0) {
-            out[o] = f2bf(fmaxf(acc[r] + bias[i], 0.0f));
-        } else if (MODE == 1) {
-            out32[o] = acc[r] + bias[i];
-        } else {
-            out[o] = f2bf(bf2f(mask[o]) > 0.0f ? acc[r] : 0.0f);
+        for (int t = 0; t < 9; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], b[t], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int xo = st.x0 + 4 * g + r;
+            if (xo >= W) continue;
+            const size_t o = (((size_t)st.n * H + st.y) * W + xo) * CH + i;
+            if (MODE == 0) {
+                out[o] = f2bf(fmaxf(acc[r] + bi, 0.0f));
+            } else if (MODE == 1) {
+                out32[o] = acc[r] + bi;
+            } else {
+                out[o] = f2bf(bf2f(mask[o]) > 0.0f ? acc[r] : 0.0f);
+            }
         }
     }
 }
@@ -265,6 +280,9 @@ __global__ void k_adam(float *__restrict__ params, float *__restrict__ m, float 
 __global__ void k_clear_stats(int32_t *__restrict__ row_stats, int H, int W, uint32_t *__restrict__ nfallback)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // image blockIdx.z of a stack
+    if (row_stats) row_stats += (size_t)blockIdx.z * 3 * H;
+    if (nfallback) nfallback += blockIdx.z;
     if (row_stats && i < H) {
         row_stats[i] = 0;          // fallback pixels in the row
         row_stats[H + i] = W;      // leftmost fallback column
@@ -282,6 +300,16 @@ __global__ __launch_bounds__(256) void k_window_map(const float *__restrict__ co
                                                     int32_t *__restrict__ row_stats, uint32_t *__restrict__ nfallback)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    // image blockIdx.z of a stack: every buffer is packed per image
+    {
+        const size_t z = blockIdx.z;
+        coarse += z * Wc * Hc;
+        out += z * Wc * Hc * CH;
+        lo += z * W * H;
+        if (mask) mask += z * W * H;
+        if (row_stats) row_stats += z * 3 * H;
+        if (nfallback) nfallback += z;
+    }
     bool fb = false;
     if (x < W) {
         const int cx = min(x / 4, Wc - 1), cy = min(y / 4, Hc - 1);
@@ -403,7 +431,8 @@ sgm_status sgm_cnn_forward(const uint16_t *wf, const float *params, const uint16
     if (!aligned(x0, 8) || !aligned(acts, 8) || !aligned(wf, 8)) return cfail(SGM_ERR_INVALID, "misaligned buffer");
     const size_t act = (size_t)nimg * height * width * CH;
     const int nstrips = nimg * height * ((width + 15) / 16);
-    dim3 grid((nstrips + 3) / 4), block(256);
+    const int nwaves = (nstrips + kStripsPerWave - 1) / kStripsPerWave;
+    dim3 grid((nwaves + 3) / 4), block(256);
     hipStream_t s = (hipStream_t)stream;
     const uint16_t *in = x0;
     for (int l = 0; l < LAYERS; ++l) {
@@ -458,7 +487,8 @@ sgm_status sgm_cnn_backward(const uint16_t *wb, const uint16_t *x0, const uint16
                            grad + (size_t)l * PER_LAYER);
         if (l > 0) {
             uint16_t *dnext = (l % 2) ? dyA : dyB;
-            hipLaunchKernelGGL(k_conv<2>, dim3((nstrips + 3) / 4), dim3(256), 0, s, dy, wb + (size_t)l * 9 * CH * CH,
+            const int nwaves = (nstrips + kStripsPerWave - 1) / kStripsPerWave;
+            hipLaunchKernelGGL(k_conv<2>, dim3((nwaves + 3) / 4), dim3(256), 0, s, dy, wb + (size_t)l * 9 * CH * CH,
                                nullptr, xin, width, height, nstrips, dnext, nullptr);
             dy = dnext;
         }
@@ -480,15 +510,17 @@ sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, in
     return launched("cnn adam");
 }
 
-sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_t coarse_width, int32_t coarse_height,
-                          int32_t width, int32_t height, int32_t ndisp, int32_t w, float conf_threshold, int32_t *lo,
-                          uint8_t *fallback_mask, int32_t *row_stats, uint32_t *nfallback, void *stream)
+static sgm_status window_map_n(const float *coarse_disp, const float *cnn_out, int32_t coarse_width,
+                               int32_t coarse_height, int32_t width, int32_t height, int32_t ndisp, int32_t w,
+                               float conf_threshold, int32_t nimg, int32_t *lo, uint8_t *fallback_mask,
+                               int32_t *row_stats, uint32_t *nfallback, void *stream)
 {
     if (!coarse_disp || !cnn_out || !lo) return cfail(SGM_ERR_INVALID, "NULL buffer");
     if (coarse_width < 1 || coarse_height < 1 || width < 1 || height < 1 || w < 1 || w > ndisp || ndisp > 256)
         return cfail(SGM_ERR_INVALID, "bad size");
-    if (height > 65535 || (long long)width * height >= (1ll << 31) ||
-        (long long)coarse_width * coarse_height * CH >= (1ll << 31))
+    if (nimg < 1 || nimg > 65535) return cfail(SGM_ERR_INVALID, "nimg must be in [1, 65535]");
+    if (height > 65535 || (long long)width * height * nimg >= (1ll << 31) ||
+        (long long)coarse_width * coarse_height * CH * nimg >= (1ll << 31))
         return cfail(SGM_ERR_UNSUPPORTED, "image too large");
     if (conf_threshold != conf_threshold) return cfail(SGM_ERR_INVALID, "threshold is NaN");
     // confident iff sigmoid(logit) > tau  <=>  logit > log(tau / (1 - tau))
@@ -501,12 +533,29 @@ sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_
         thr = (float)log((double)conf_threshold / (1.0 - (double)conf_threshold));
     hipStream_t s = (hipStream_t)stream;
     if (row_stats || nfallback)
-        hipLaunchKernelGGL(k_clear_stats, dim3((height + 255) / 256), dim3(256), 0, s, row_stats, (int)height,
-                           (int)width, nfallback);
-    dim3 grid((width + 255) / 256, height), block(256);
+        hipLaunchKernelGGL(k_clear_stats, dim3((height + 255) / 256, 1, nimg), dim3(256), 0, s, row_stats,
+                           (int)height, (int)width, nfallback);
+    dim3 grid((width + 255) / 256, height, nimg), block(256);
     hipLaunchKernelGGL(k_window_map, grid, block, 0, s, coarse_disp, cnn_out, coarse_width, coarse_height, width,
                        height, ndisp, w, thr, lo, fallback_mask, row_stats, nfallback);
     return launched("window map");
+}
+
+sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_t coarse_width, int32_t coarse_height,
+                          int32_t width, int32_t height, int32_t ndisp, int32_t w, float conf_threshold, int32_t *lo,
+                          uint8_t *fallback_mask, int32_t *row_stats, uint32_t *nfallback, void *stream)
+{
+    return window_map_n(coarse_disp, cnn_out, coarse_width, coarse_height, width, height, ndisp, w, conf_threshold, 1,
+                        lo, fallback_mask, row_stats, nfallback, stream);
+}
+
+sgm_status sgm_window_map_batch(const float *coarse_disp, const float *cnn_out, int32_t coarse_width,
+                                int32_t coarse_height, int32_t width, int32_t height, int32_t ndisp, int32_t w,
+                                float conf_threshold, int32_t nimg, int32_t *lo, uint8_t *fallback_mask,
+                                int32_t *row_stats, uint32_t *nfallback, void *stream)
+{
+    return window_map_n(coarse_disp, cnn_out, coarse_width, coarse_height, width, height, ndisp, w, conf_threshold,
+                        nimg, lo, fallback_mask, row_stats, nfallback, stream);
 }
 
 sgm_status sgm_fallback_merge(const uint8_t *fallback_mask, const int16_t *band_int, const float *band_sub,

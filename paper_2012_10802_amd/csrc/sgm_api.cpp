@@ -310,8 +310,20 @@ sgm_status sgm_downsample4(const uint8_t *img, int32_t width, int32_t height, in
 {
     if (!img || !out) return fail(SGM_ERR_INVALID, "img and out must not be NULL");
     if (width < 4 || height < 4 || pitch < width) return fail(SGM_ERR_INVALID, "need width, height >= 4, pitch >= width");
-    hipError_t e = sgm::launch_downsample4(img, width, height, pitch, out, (hipStream_t)stream);
+    hipError_t e = sgm::launch_downsample4(img, width, height, pitch, 0, 1, out, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "downsample launch");
+}
+
+sgm_status sgm_downsample4_batch(const uint8_t *images, int32_t width, int32_t height, int32_t pitch,
+                                 int64_t image_stride, int32_t nimg, uint8_t *out, void *stream)
+{
+    if (!images || !out) return fail(SGM_ERR_INVALID, "images and out must not be NULL");
+    if (width < 4 || height < 4 || pitch < width) return fail(SGM_ERR_INVALID, "need width, height >= 4, pitch >= width");
+    if (nimg < 1 || nimg > 65535) return fail(SGM_ERR_INVALID, "nimg must be in [1, 65535]");
+    if (image_stride < (int64_t)pitch * height) return fail(SGM_ERR_INVALID, "image_stride < pitch * height");
+    hipError_t e = sgm::launch_downsample4(images, width, height, pitch, (long long)image_stride, nimg, out,
+                                           (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "downsample4 launch");
 }
 
 sgm_status sgm_cost_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *right, int32_t pitch, const int32_t *lo,

@@ -47,7 +47,8 @@ hipError_t launch_wta_paths(const Problem &pb, const KernelConfig &kc, const voi
 // ---------------------------------------------------------------------------
 // per-pixel windows (w <= 16)
 
-hipError_t launch_downsample4(const uint8_t *img, int W, int H, int pitch, uint8_t *out, hipStream_t s);
+hipError_t launch_downsample4(const uint8_t *img, int W, int H, int pitch, long long img_stride, int nimg,
+                              uint8_t *out, hipStream_t s);
 hipError_t launch_cost_win(const Problem &pb, const uint64_t *cl, const uint64_t *cr, const int32_t *lo,
                            uint8_t *cost, hipStream_t s);
 hipError_t launch_aggregate_win(const Problem &pb, const uint8_t *cost, const int32_t *lo, const int *paths, int np,

@@ -27,9 +27,12 @@ using namespace dev;
 // 4 x 4 box reduction: out = (sum of the block + 8) / 16
 
 __global__ __launch_bounds__(256) void k_downsample4(const uint8_t *__restrict__ img, int W, int H, int pitch,
-                                                     uint8_t *__restrict__ out)
+                                                     uint8_t *__restrict__ out, long long img_stride)
 {
     const int Wc = W / 4, Hc = H / 4;
+    // image blockIdx.z of a stack (img_stride bytes apart; outputs packed)
+    img += blockIdx.z * img_stride;
+    out += (size_t)blockIdx.z * Wc * Hc;
     const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= Wc || y >= Hc) return;
     uint32_t sum = 0;
@@ -669,10 +672,11 @@ constexpr int kWin16Prefetch = 6;  // steps of cost prefetched by k_aggregate_wi
 
 }  // namespace
 
-hipError_t launch_downsample4(const uint8_t *img, int W, int H, int pitch, uint8_t *out, hipStream_t s)
+hipError_t launch_downsample4(const uint8_t *img, int W, int H, int pitch, long long img_stride, int nimg,
+                              uint8_t *out, hipStream_t s)
 {
-    dim3 grid((W / 4 + 63) / 64, (H / 4 + 3) / 4), block(256);
-    hipLaunchKernelGGL(k_downsample4, grid, block, 0, s, img, W, H, pitch, out);
+    dim3 grid((W / 4 + 63) / 64, (H / 4 + 3) / 4, nimg), block(256);
+    hipLaunchKernelGGL(k_downsample4, grid, block, 0, s, img, W, H, pitch, out, img_stride);
     return hipGetLastError();
 }
 

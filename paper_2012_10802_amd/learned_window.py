@@ -16,7 +16,8 @@ the C ABI:
   5. SGM over the per-pixel windows at full resolution, every pair of the
      batch in one set of launches;
   6. the full-range fallback: plain SGM over all ndisp disparities on
-     rectangles around the marked pixels (their rows and columns widened by
+     rectangles around the marked pixels (on a side stream that starts once
+     the window maps are known and runs beside step 5) (their rows and columns widened by
      a margin, and by ndisp - 1 more columns to the left so that every
      disparity finds its right-image pixel; the whole frame once they cover
      most of it), whose result replaces the windowed one on the marked
@@ -186,6 +187,15 @@ def window_map(coarse_disp, out, W, H, ndisp, w, tau, lo=None, mask=None, row_st
     return lo
 
 
+def window_map_batch(coarse_disp, out, W, H, ndisp, w, tau, lo, mask, row_stats, nfallback, stream=None):
+    """window_map for a stack of n images (every buffer packed per image)."""
+    n, Hc, Wc = coarse_disp.shape
+    S._check(_lib.sgm_window_map_batch(_c(coarse_disp), _c(out), Wc, Hc, W, H, ndisp, w, float(tau), n, _c(lo),
+                                       _c(mask), _c(row_stats), _c(nfallback), S._stream(stream)),
+             "sgm_window_map_batch")
+    return lo
+
+
 def fallback_merge(mask, band_int, band_sub, y0, x0, disp_int, disp_sub, stream=None):
     H, W = disp_int.shape
     rows, cols = band_int.shape
@@ -233,7 +243,7 @@ class LearnedWindowMatcher:
     full-range fallback, for batches of `batch` pairs of one size."""
 
     def __init__(self, width, height, batch=1, ndisp=192, window=16, census=7, npaths=8, p1=10,
-                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, fallback_streams=4, device="cuda"):
+                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, device="cuda"):
         if width % 4 or height % 4 or ndisp % 4:
             raise ValueError("width, height and ndisp must be multiples of 4")
         self.W, self.H, self.D, self.w, self.n = width, height, ndisp, window, batch
@@ -245,7 +255,10 @@ class LearnedWindowMatcher:
         n, Hc, Wc = batch, self.Hc, self.Wc
         self.cl = torch.empty((n, Hc, Wc), dtype=torch.uint8, device=dev)
         self.cr = torch.empty_like(self.cl)
-        self.coarse = S.Batch([dict(left=self.cl[i], right=self.cr[i], ndisp=ndisp // 4) for i in range(n)],
+        self.cdi = torch.empty((n, Hc, Wc), dtype=torch.int16, device=dev)
+        self.cds = torch.empty((n, Hc, Wc), dtype=torch.float32, device=dev)
+        self.coarse = S.Batch([dict(left=self.cl[i], right=self.cr[i], ndisp=ndisp // 4, disp_int=self.cdi[i],
+                                    disp_sub=self.cds[i]) for i in range(n)],
                               census=census, npaths=npaths, p1=p1, p2=p2, device=dev)
         self.x0 = torch.empty((n, Hc, Wc, CH), dtype=torch.int16, device=dev)
         self.acts, self.out = self.net.buffers(Wc, Hc, n)
@@ -260,87 +273,92 @@ class LearnedWindowMatcher:
         self.lo = torch.empty((n, height, width), dtype=torch.int32, device=dev)
         self.mask = torch.empty((n, height, width), dtype=torch.uint8, device=dev)
         self.stats = torch.zeros((n, 3, height), dtype=torch.int32, device=dev)
+        self.stats_host = torch.zeros((n, 3, height), dtype=torch.int32, pin_memory=True)
         self.nfallback = torch.zeros((n,), dtype=torch.int32, device=dev)
         self.dint = torch.empty((n, height, width), dtype=torch.int16, device=dev)
         self.dsub = torch.empty((n, height, width), dtype=torch.float32, device=dev)
-        # full-range fallback: one workspace sized for the whole frame, plans per rectangle size
+        # full-range fallback: plain SGM of each rectangle on a side stream,
+        # which starts as soon as the window maps are done and runs beside
+        # the windowed SGM; one full-frame workspace, plans per rectangle
+        # size (host objects), results in an arena merged on the main stream
         full = S.sgm_plan(width, height, census, ndisp, npaths, p1, p2)
         try:
             need = S.sgm_workspace_size(full)
         finally:
             S.sgm_plan_free(full)
-        # The rectangles are small (a few hundred scanlines each), so the
-        # pairs' fallbacks run on several streams at once; each stream owns
-        # a full-frame workspace and result buffers, and pair i always uses
-        # stream i % len(streams), so no two streams touch one pair.
-        nst = max(1, min(fallback_streams, n))
-        self.fb_streams = [torch.cuda.Stream(device=dev) for _ in range(nst)]
-        self.fb_ws = [torch.empty(need, dtype=torch.uint8, device=dev) for _ in range(nst)]
-        self.fb_int = [torch.empty(height * width, dtype=torch.int16, device=dev) for _ in range(nst)]
-        self.fb_sub = [torch.empty(height * width, dtype=torch.float32, device=dev) for _ in range(nst)]
-        self._full = [{} for _ in range(nst)]
+        self.fb_ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.fb_int = torch.empty(n * height * width, dtype=torch.int16, device=dev)
+        self.fb_sub = torch.empty(n * height * width, dtype=torch.float32, device=dev)
+        self.fb_stream = torch.cuda.Stream(device=dev)
+        self.ev_maps = torch.cuda.Event()
+        self.ev_fb = torch.cuda.Event()
+        self._full = {}
         self.last_rects = []
 
-    def _full_matcher(self, j, rows, cols):
-        cache = self._full[j]
+    def _full_matcher(self, rows, cols):
         key = (rows, cols)
-        m = cache.pop(key, None)
+        m = self._full.pop(key, None)
         if m is None:
             m = S.Matcher(cols, rows, census=self.census, ndisp=self.D, npaths=self.npaths, p1=self.p1,
-                          p2=self.p2, device=self.device, workspace=self.fb_ws[j])
-            while len(cache) >= 256:  # plans are host objects; keep the most recent
-                cache.pop(next(iter(cache)))
-        cache[key] = m
+                          p2=self.p2, device=self.device, workspace=self.fb_ws)
+            while len(self._full) >= 256:  # plans are host objects; keep the most recent
+                self._full.pop(next(iter(self._full)))
+        self._full[key] = m
         return m
 
     def windows(self, left, right, stream=None):
         """Steps 1-5 for left, right uint8 [n, H, W]: fills lo, mask, stats,
-        nfallback, dint and dsub."""
+        nfallback, dint and dsub (records ev_maps once the maps are done)."""
         n = self.n
         if tuple(left.shape) != (n, self.H, self.W) or tuple(right.shape) != (n, self.H, self.W):
             raise ValueError("left and right must be uint8 [%d, %d, %d]" % (n, self.H, self.W))
-        for i in range(n):
-            S.sgm_downsample4(left[i], self.cl[i], stream)
-            S.sgm_downsample4(right[i], self.cr[i], stream)
-        self.coarse.run(stream)
-        for i in range(n):
-            prepare_input(self.coarse.disp_sub[i], self.cl[i], self.Wc, self.Hc, 1, self.x0[i], stream)
-        self.net.forward(self.x0, self.acts, self.out, self.Wc, self.Hc, n, stream)
-        for i in range(n):
-            window_map(self.coarse.disp_sub[i], self.out[i], self.W, self.H, self.D, self.w, self.tau,
-                       self.lo[i], self.mask[i], self.stats[i], self.nfallback[i:i + 1], stream)
+        main = stream if stream is not None else torch.cuda.current_stream(self.device)
+        S.sgm_downsample4_batch(left, self.cl, main)
+        S.sgm_downsample4_batch(right, self.cr, main)
+        self.coarse.run(main)
+        prepare_input(self.cds, self.cl, self.Wc, self.Hc, n, self.x0, main)
+        self.net.forward(self.x0, self.acts, self.out, self.Wc, self.Hc, n, main)
+        window_map_batch(self.cds, self.out, self.W, self.H, self.D, self.w, self.tau, self.lo, self.mask,
+                         self.stats, self.nfallback, main)
+        self.ev_maps.record(main)
         if self.w == 16:
             self.fine.match_win_batch(left, right, self.lo, disp_int=self.dint, disp_sub=self.dsub,
-                                      workspace=self.fine_ws, stream=stream)
+                                      workspace=self.fine_ws, stream=main)
         else:
             for i in range(n):
                 self.fine.match_win(left[i], right[i], self.lo[i], disp_int=self.dint[i], disp_sub=self.dsub[i],
-                                    stream=stream)
+                                    stream=main)
 
     def fallback(self, left, right, stream=None):
-        """Step 6 (waits once for `stream` to read the per-row statistics)."""
+        """Step 6: waits on the host for the window maps only; the
+        rectangles' plain SGM runs on the side stream beside the windowed
+        SGM, and the merge follows both on the main stream."""
         main = stream if stream is not None else torch.cuda.current_stream(self.device)
-        main.synchronize()
-        stats = self.stats.cpu().numpy()
+        fb = self.fb_stream
+        fb.wait_event(self.ev_maps)
+        with torch.cuda.stream(fb):
+            self.stats_host.copy_(self.stats, non_blocking=True)
+        fb.synchronize()
+        stats = self.stats_host.numpy()
         self.last_rects = []
-        used = set()
+        merges = []
+        used = 0
         for i in range(self.n):
             rects = fallback_rects(stats[i], self.W, self.D, self.census // 2, self.margin, self.full_fraction)
             self.last_rects.append(rects)
-            j = i % len(self.fb_streams)
-            st = self.fb_streams[j]
-            if rects and j not in used:
-                st.wait_stream(main)  # inputs, masks and windowed results are ready
-                used.add(j)
             for y0, y1, x0, x1 in rects:
                 h, w = y1 - y0, x1 - x0
-                bi = self.fb_int[j][:h * w].view(h, w)
-                bs = self.fb_sub[j][:h * w].view(h, w)
-                self._full_matcher(j, h, w).match_at(left[i], right[i], y0, x0, disp_int=bi, disp_sub=bs,
-                                                     stream=st)
-                fallback_merge(self.mask[i], bi, bs, y0, x0, self.dint[i], self.dsub[i], st)
-        for j in sorted(used):
-            main.wait_stream(self.fb_streams[j])
+                bi = self.fb_int[used:used + h * w].view(h, w)
+                bs = self.fb_sub[used:used + h * w].view(h, w)
+                used += h * w
+                self._full_matcher(h, w).match_at(left[i], right[i], y0, x0, disp_int=bi, disp_sub=bs, stream=fb)
+                merges.append((i, y0, x0, bi, bs))
+        if not merges:
+            return
+        self.ev_fb.record(fb)
+        main.wait_event(self.ev_fb)
+        for i, y0, x0, bi, bs in merges:
+            fallback_merge(self.mask[i], bi, bs, y0, x0, self.dint[i], self.dsub[i], main)
 
     def match(self, left, right, stream=None):
         """Returns (disp_int int16 [n,H,W], disp_sub float32 [n,H,W]) device tensors."""

@@ -92,6 +92,8 @@ def _load_library():
                          ctypes.c_float, P, P, P],
         "sgm_window_map": [P, P, I, I, I, I, I, I, ctypes.c_float, P, P, P, P, P],
         "sgm_fallback_merge": [P, P, P, I, I, I, I, I, I, P, P, P],
+        "sgm_window_map_batch": [P, P, I, I, I, I, I, I, ctypes.c_float, I, P, P, P, P, P],
+        "sgm_downsample4_batch": [P, I, I, I, ctypes.c_int64, I, P, P],
         "sgm_label_downsample4": [P, I, I, P, P],
         "sgm_batch_plan": [ctypes.POINTER(sgm_batch_params), ctypes.POINTER(sgm_pair), I,
                            ctypes.POINTER(P)],
@@ -196,6 +198,20 @@ def sgm_downsample4(image, out=None, stream=None):
         out = torch.empty((H // 4, W // 4), dtype=torch.uint8, device=image.device)
     _need(out, torch.uint8, (H // 4, W // 4), "out")
     _check(_lib.sgm_downsample4(_ptr(image), W, H, W, _ptr(out), _stream(stream)), "sgm_downsample4")
+    return out
+
+
+def sgm_downsample4_batch(images, out=None, stream=None):
+    """4 x 4 box reduction of every image of a uint8 device stack [n, H, pitch]."""
+    _need(images, torch.uint8, None, "images")
+    if images.dim() != 3:
+        raise ValueError("images must be uint8 [n, H, pitch]")
+    n, H, W = images.shape
+    if out is None:
+        out = torch.empty((n, H // 4, W // 4), dtype=torch.uint8, device=images.device)
+    _need(out, torch.uint8, (n, H // 4, W // 4), "out")
+    _check(_lib.sgm_downsample4_batch(_ptr(images), W, H, W, H * W, n, _ptr(out), _stream(stream)),
+           "sgm_downsample4_batch")
     return out
 
 
@@ -457,9 +473,13 @@ class Batch:
 
     `pairs` is a list of dicts with `left`, `right` (uint8 device tensors
     [H, pitch]), `ndisp` and optionally `width` (default: the tensor width),
-    `d_lo` (int32 [H] device tensor) and `subpixel` (default True).  The
-    outputs are allocated here (`disp_int[i]`, `disp_sub[i]`) and written by
-    every run.  Census, paths and penalties are shared by the batch.
+    `d_lo` (int32 [H] device tensor) and `subpixel` (default True).  A pair
+    may also be a rectangle of its frames: `y0`, `x0`, `height`, `width`
+    (the images are then read at that offset with the frames' pitch).  The
+    outputs are allocated here (`disp_int[i]`, `disp_sub[i]`, [height,
+    width]) unless given as `disp_int` / `disp_sub` (contiguous int16 /
+    float32 device tensors of that shape), and written by every run.
+    Census, paths and penalties are shared by the batch.
     """
 
     def __init__(self, pairs, census=7, npaths=8, p1=10, p2=120, device=None):
@@ -473,18 +493,29 @@ class Batch:
             _need(right, torch.uint8, None, "right")
             if left.shape != right.shape or left.dim() != 2:
                 raise ValueError("pair %d: left and right must be uint8 [H, pitch] of one shape" % i)
-            H, pitch = left.shape
-            W = int(pr.get("width", pitch))
+            Hf, pitch = left.shape
+            y0, x0 = int(pr.get("y0", 0)), int(pr.get("x0", 0))
+            H = int(pr.get("height", Hf - y0))
+            W = int(pr.get("width", pitch - x0))
+            if y0 < 0 or x0 < 0 or H < 1 or W < 1 or y0 + H > Hf or x0 + W > pitch:
+                raise ValueError("pair %d: rectangle outside the frames" % i)
+            off = y0 * pitch + x0
             d_lo = pr.get("d_lo")
             if d_lo is not None:
                 _need(d_lo, torch.int32, (H,), "d_lo")
-            di = torch.empty((H, W), dtype=torch.int16, device=self.device)
-            ds = (torch.empty((H, W), dtype=torch.float32, device=self.device)
-                  if pr.get("subpixel", True) else None)
+            di = pr.get("disp_int")
+            if di is None:
+                di = torch.empty((H, W), dtype=torch.int16, device=self.device)
+            _need(di, torch.int16, (H, W), "disp_int")
+            ds = pr.get("disp_sub")
+            if ds is None and pr.get("subpixel", True):
+                ds = torch.empty((H, W), dtype=torch.float32, device=self.device)
+            if ds is not None:
+                _need(ds, torch.float32, (H, W), "disp_sub")
             self.disp_int.append(di)
             self.disp_sub.append(ds)
             self._keep += [left, right, d_lo]
-            arr[i] = sgm_pair(W, H, int(pr["ndisp"]), pitch, left.data_ptr(), right.data_ptr(),
+            arr[i] = sgm_pair(W, H, int(pr["ndisp"]), pitch, left.data_ptr() + off, right.data_ptr() + off,
                               None if d_lo is None else d_lo.data_ptr(), di.data_ptr(),
                               None if ds is None else ds.data_ptr())
         prm = sgm_batch_params(census, npaths, p1, p2, 0)
