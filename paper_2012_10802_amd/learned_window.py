@@ -243,7 +243,7 @@ class LearnedWindowMatcher:
     full-range fallback, for batches of `batch` pairs of one size."""
 
     def __init__(self, width, height, batch=1, ndisp=192, window=16, census=7, npaths=8, p1=10,
-                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, device="cuda"):
+                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, fallback_streams=4, device="cuda"):
         if width % 4 or height % 4 or ndisp % 4:
             raise ValueError("width, height and ndisp must be multiples of 4")
         self.W, self.H, self.D, self.w, self.n = width, height, ndisp, window, batch
@@ -286,24 +286,28 @@ class LearnedWindowMatcher:
             need = S.sgm_workspace_size(full)
         finally:
             S.sgm_plan_free(full)
-        self.fb_ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        # pair i's rectangles go to side stream i % len(streams), each stream
+        # with its own workspace, so the small launches also overlap each other
+        nst = max(1, min(fallback_streams, n))
+        self.fb_streams = [torch.cuda.Stream(device=dev) for _ in range(nst)]
+        self.fb_ws = [torch.empty(need, dtype=torch.uint8, device=dev) for _ in range(nst)]
         self.fb_int = torch.empty(n * height * width, dtype=torch.int16, device=dev)
         self.fb_sub = torch.empty(n * height * width, dtype=torch.float32, device=dev)
-        self.fb_stream = torch.cuda.Stream(device=dev)
         self.ev_maps = torch.cuda.Event()
-        self.ev_fb = torch.cuda.Event()
-        self._full = {}
+        self.ev_fb = [torch.cuda.Event() for _ in range(nst)]
+        self._full = [{} for _ in range(nst)]
         self.last_rects = []
 
-    def _full_matcher(self, rows, cols):
+    def _full_matcher(self, j, rows, cols):
+        cache = self._full[j]
         key = (rows, cols)
-        m = self._full.pop(key, None)
+        m = cache.pop(key, None)
         if m is None:
             m = S.Matcher(cols, rows, census=self.census, ndisp=self.D, npaths=self.npaths, p1=self.p1,
-                          p2=self.p2, device=self.device, workspace=self.fb_ws)
-            while len(self._full) >= 256:  # plans are host objects; keep the most recent
-                self._full.pop(next(iter(self._full)))
-        self._full[key] = m
+                          p2=self.p2, device=self.device, workspace=self.fb_ws[j])
+            while len(cache) >= 256:  # plans are host objects; keep the most recent
+                cache.pop(next(iter(cache)))
+        cache[key] = m
         return m
 
     def windows(self, left, right, stream=None):
@@ -334,11 +338,12 @@ class LearnedWindowMatcher:
         rectangles' plain SGM runs on the side stream beside the windowed
         SGM, and the merge follows both on the main stream."""
         main = stream if stream is not None else torch.cuda.current_stream(self.device)
-        fb = self.fb_stream
-        fb.wait_event(self.ev_maps)
-        with torch.cuda.stream(fb):
+        fb0 = self.fb_streams[0]
+        for st in self.fb_streams:
+            st.wait_event(self.ev_maps)
+        with torch.cuda.stream(fb0):
             self.stats_host.copy_(self.stats, non_blocking=True)
-        fb.synchronize()
+        fb0.synchronize()
         stats = self.stats_host.numpy()
         self.last_rects = []
         merges = []
@@ -346,17 +351,20 @@ class LearnedWindowMatcher:
         for i in range(self.n):
             rects = fallback_rects(stats[i], self.W, self.D, self.census // 2, self.margin, self.full_fraction)
             self.last_rects.append(rects)
+            j = i % len(self.fb_streams)
             for y0, y1, x0, x1 in rects:
                 h, w = y1 - y0, x1 - x0
                 bi = self.fb_int[used:used + h * w].view(h, w)
                 bs = self.fb_sub[used:used + h * w].view(h, w)
                 used += h * w
-                self._full_matcher(h, w).match_at(left[i], right[i], y0, x0, disp_int=bi, disp_sub=bs, stream=fb)
+                self._full_matcher(j, h, w).match_at(left[i], right[i], y0, x0, disp_int=bi, disp_sub=bs,
+                                                     stream=self.fb_streams[j])
                 merges.append((i, y0, x0, bi, bs))
         if not merges:
             return
-        self.ev_fb.record(fb)
-        main.wait_event(self.ev_fb)
+        for st, ev in zip(self.fb_streams, self.ev_fb):
+            ev.record(st)
+            main.wait_event(ev)
         for i, y0, x0, bi, bs in merges:
             fallback_merge(self.mask[i], bi, bs, y0, x0, self.dint[i], self.dsub[i], main)
 
