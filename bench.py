@@ -185,6 +185,9 @@ def learned_vs_plain(args, log=None):
     t_plain, t_learned = [], []
     nb = max(1, args.eval_pairs // B)
     with torch.cuda.stream(stream):
+        L.zero_()
+        Rt.zero_()
+        plain.autotune(stream=stream)  # both paths with tuned launch shapes
         plain.capture(stream)
         for b in range(nb):
             gts, masks = [], []

@@ -243,7 +243,8 @@ class LearnedWindowMatcher:
     full-range fallback, for batches of `batch` pairs of one size."""
 
     def __init__(self, width, height, batch=1, ndisp=192, window=16, census=7, npaths=8, p1=10,
-                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, fallback_streams=4, device="cuda"):
+                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, fallback_streams=4, autotune=True,
+                 device="cuda"):
         if width % 4 or height % 4 or ndisp % 4:
             raise ValueError("width, height and ndisp must be multiples of 4")
         self.W, self.H, self.D, self.w, self.n = width, height, ndisp, window, batch
@@ -260,6 +261,11 @@ class LearnedWindowMatcher:
         self.coarse = S.Batch([dict(left=self.cl[i], right=self.cr[i], ndisp=ndisp // 4, disp_int=self.cdi[i],
                                     disp_sub=self.cds[i]) for i in range(n)],
                               census=census, npaths=npaths, p1=p1, p2=p2, device=dev)
+        if autotune:
+            # launch shape of the quarter-scale batch (timed once on these buffers)
+            self.cl.zero_()
+            self.cr.zero_()
+            self.coarse.autotune()
         self.x0 = torch.empty((n, Hc, Wc, CH), dtype=torch.int16, device=dev)
         self.acts, self.out = self.net.buffers(Wc, Hc, n)
         fine_plan = S.sgm_plan(width, height, census, window, npaths, p1, p2)
