@@ -381,6 +381,13 @@ sgm_status sgm_window_from_road(double a0, double a1, double phi, int32_t width,
                                 int32_t height, int32_t w, int32_t mode,
                                 double delta, int32_t *d_lo_host);
 
+/* Failure-handling tests: arm a one-shot injected failure.  kind 1: the
+ * next call that would launch work returns SGM_ERR_HIP and enqueues
+ * nothing; kind 2: the next batch plan fails its pinned-memory allocation
+ * with SGM_ERR_HIP; 0 disarms.  The environment variable
+ * SGM_FAULT_INJECT=launch|alloc arms the same at the library's first call. */
+sgm_status sgm_debug_inject_fault(int32_t kind);
+
 const char *sgm_status_str(sgm_status status);
 const char *sgm_last_error(void);
 

@@ -405,6 +405,7 @@ size_t sgm_cnn_scratch_bytes(int32_t width, int32_t height, int32_t nimg)
 sgm_status sgm_cnn_pack_weights(const float *params, uint16_t *wf, uint16_t *wb, void *stream)
 {
     if (!params || !wf || !wb) return cfail(SGM_ERR_INVALID, "params, wf and wb must not be NULL");
+    if (fault_take(kFaultLaunch)) return cfail(SGM_ERR_HIP, "injected launch failure");
     hipLaunchKernelGGL(k_adam, dim3((NPARAMS + 255) / 256), dim3(256), 0, (hipStream_t)stream,
                        const_cast<float *>(params), nullptr, nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f, 0, wf,
                        wb);
@@ -418,6 +419,7 @@ sgm_status sgm_cnn_prepare_input(const float *coarse_disp, const uint8_t *coarse
     if (sgm_status st = check_images(width, height, nimg)) return st;
     if (!aligned(x0, 16)) return cfail(SGM_ERR_INVALID, "x0 must be 16-byte aligned");
     const int npix = width * height * nimg;
+    if (fault_take(kFaultLaunch)) return cfail(SGM_ERR_HIP, "injected launch failure");
     hipLaunchKernelGGL(k_prepare_input, dim3((npix + 255) / 256), dim3(256), 0, (hipStream_t)stream, coarse_disp,
                        coarse_left, width, npix, x0);
     return launched("prepare input");
@@ -435,6 +437,7 @@ sgm_status sgm_cnn_forward(const uint16_t *wf, const float *params, const uint16
     dim3 grid((nwaves + 3) / 4), block(256);
     hipStream_t s = (hipStream_t)stream;
     const uint16_t *in = x0;
+    if (fault_take(kFaultLaunch)) return cfail(SGM_ERR_HIP, "injected launch failure");
     for (int l = 0; l < LAYERS; ++l) {
         const uint16_t *wl = wf + (size_t)l * 9 * CH * CH;
         const float *bl = params + (size_t)l * PER_LAYER + 9 * CH * CH;
@@ -457,6 +460,7 @@ sgm_status sgm_cnn_loss(const float *out, const float *coarse_disp, const float 
     if (sgm_status st = check_images(width, height, nimg)) return st;
     if (!aligned(dy, 16)) return cfail(SGM_ERR_INVALID, "dy must be 16-byte aligned");
     const int npix = width * height * nimg;
+    if (fault_take(kFaultLaunch)) return cfail(SGM_ERR_HIP, "injected launch failure");
     hipLaunchKernelGGL(k_loss, dim3((npix + 255) / 256), dim3(256), 0, (hipStream_t)stream, out, coarse_disp, label,
                        npix, dy, loss_sum);
     return launched("cnn loss");
@@ -480,6 +484,7 @@ sgm_status sgm_cnn_backward(const uint16_t *wb, const uint16_t *x0, const uint16
     const int nw = nstrips < kWgradWaves ? nstrips : kWgradWaves;
     hipStream_t s = (hipStream_t)stream;
     const uint16_t *dy = dy_out;
+    if (fault_take(kFaultLaunch)) return cfail(SGM_ERR_HIP, "injected launch failure");
     for (int l = LAYERS - 1; l >= 0; --l) {
         const uint16_t *xin = l == 0 ? x0 : acts + (size_t)(l - 1) * act;
         hipLaunchKernelGGL(k_wgrad, dim3(nw), dim3(64), 0, s, xin, dy, width, height, nstrips, partial);
@@ -505,6 +510,7 @@ sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, in
     // lose most of its digits in float
     const float c1 = (float)(1.0 - pow((double)beta1, (double)step));
     const float c2 = (float)(1.0 - pow((double)beta2, (double)step));
+    if (fault_take(kFaultLaunch)) return cfail(SGM_ERR_HIP, "injected launch failure");
     hipLaunchKernelGGL(k_adam, dim3((NPARAMS + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, m, v, grad,
                        lr, beta1, beta2, eps, c1, c2, 1, wf, wb);
     return launched("cnn adam");
@@ -532,6 +538,7 @@ static sgm_status window_map_n(const float *coarse_disp, const float *cnn_out, i
     else
         thr = (float)log((double)conf_threshold / (1.0 - (double)conf_threshold));
     hipStream_t s = (hipStream_t)stream;
+    if (fault_take(kFaultLaunch)) return cfail(SGM_ERR_HIP, "injected launch failure");
     if (row_stats || nfallback)
         hipLaunchKernelGGL(k_clear_stats, dim3((height + 255) / 256, 1, nimg), dim3(256), 0, s, row_stats,
                            (int)height, (int)width, nfallback);
@@ -569,6 +576,7 @@ sgm_status sgm_fallback_merge(const uint8_t *fallback_mask, const int16_t *band_
     if (rows == 0 || cols == 0) return SGM_OK;
     if (rows > 65535) return cfail(SGM_ERR_UNSUPPORTED, "more than 65535 rows");
     dim3 grid((cols + 255) / 256, rows), block(256);
+    if (fault_take(kFaultLaunch)) return cfail(SGM_ERR_HIP, "injected launch failure");
     hipLaunchKernelGGL(k_merge_fallback, grid, block, 0, (hipStream_t)stream, fallback_mask, band_int, band_sub,
                        width, y0, rows, x0, cols, disp_int, disp_sub);
     return launched("fallback merge");
@@ -581,6 +589,7 @@ sgm_status sgm_label_downsample4(const float *label, int32_t width, int32_t heig
     if (height / 4 > 65535 || (long long)width * height >= (1ll << 31))
         return cfail(SGM_ERR_UNSUPPORTED, "image too large");
     dim3 grid((width / 4 + 255) / 256, height / 4), block(256);
+    if (fault_take(kFaultLaunch)) return cfail(SGM_ERR_HIP, "injected launch failure");
     hipLaunchKernelGGL(k_label_downsample4, grid, block, 0, (hipStream_t)stream, label, width, height, coarse);
     return launched("label downsample");
 }

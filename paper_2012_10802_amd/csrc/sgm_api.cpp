@@ -9,6 +9,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
+#include <cstdlib>
 #include <new>
 
 #include "sgm_internal.h"
@@ -37,6 +39,31 @@ sgm_status hip_fail(hipError_t e, const char *what)
 {
     return fail(SGM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+// One-shot fault injection (failure-handling tests): armed by
+// sgm_debug_inject_fault() or, at first use, by the environment variable
+// SGM_FAULT_INJECT=launch|alloc.  The next call that would launch (or
+// allocate pinned memory) returns SGM_ERR_HIP instead, enqueueing nothing.
+std::atomic<int> g_fault{-1};  // -1: environment not read yet
+
+}  // namespace
+namespace sgm {
+bool fault_take(int kind)
+{
+    int cur = g_fault.load();
+    if (cur < 0) {
+        const char *e = getenv("SGM_FAULT_INJECT");
+        const int k = !e ? 0 : (!strcmp(e, "launch") ? kFaultLaunch : (!strcmp(e, "alloc") ? kFaultAlloc : 0));
+        int expected = -1;
+        g_fault.compare_exchange_strong(expected, k);
+        cur = g_fault.load();
+    }
+    if (cur != kind) return false;
+    int expected = kind;
+    return g_fault.compare_exchange_strong(expected, 0);
+}
+}  // namespace sgm
+namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -170,6 +197,7 @@ sgm_status sgm_census(sgm_plan_t plan, const uint8_t *image, int32_t pitch, uint
     if (sgm_status s = check_plan(plan)) return s;
     if (!image || !codes) return fail(SGM_ERR_INVALID, "image and codes must not be NULL");
     if (pitch < plan->pb.W) return fail(SGM_ERR_INVALID, "pitch %d < width %d", pitch, plan->pb.W);
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_census(plan->pb, image, pitch, codes, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "census launch");
 }
@@ -185,6 +213,7 @@ sgm_status sgm_cost(sgm_plan_t plan, const uint8_t *left, const uint8_t *right, 
     uint64_t *cl = reinterpret_cast<uint64_t *>(base + plan->off_codes_l);
     uint64_t *cr = reinterpret_cast<uint64_t *>(base + plan->off_codes_r);
     hipStream_t st = (hipStream_t)stream;
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_census(plan->pb, left, pitch, cl, st);
     if (e == hipSuccess) e = sgm::launch_census(plan->pb, right, pitch, cr, st);
     if (e == hipSuccess) e = sgm::launch_cost(plan->pb, config_for(plan, cost, nullptr), cl, cr, d_lo, cost, st);
@@ -200,6 +229,7 @@ sgm_status sgm_aggregate(sgm_plan_t plan, const uint8_t *cost, uint16_t *sum, vo
     void *vols = static_cast<uint8_t *>(ws) + plan->off_paths;
     hipStream_t st = (hipStream_t)stream;
     const sgm::KernelConfig kc = config_for(plan, cost, nullptr);
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_aggregate(plan->pb, kc, cost, plan->paths, plan->pb.npaths, kc.l8, vols, st);
     if (e == hipSuccess) e = sgm::launch_sum(plan->pb, kc, vols, plan->pb.npaths, kc.l8, sum, st);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "aggregate launch");
@@ -212,6 +242,7 @@ sgm_status sgm_aggregate_path(sgm_plan_t plan, const uint8_t *cost, int32_t path
     if (path < 0 || path > 7) return fail(SGM_ERR_INVALID, "path %d not in [0, 7]", path);
     const sgm::KernelConfig kc = config_for(plan, cost, L);
     const int paths[1] = {path};
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_aggregate(plan->pb, kc, cost, paths, 1, false, L, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "aggregate_path launch");
 }
@@ -222,6 +253,7 @@ sgm_status sgm_wta(sgm_plan_t plan, const uint16_t *sum, const int32_t *d_lo, ui
     if (sgm_status s = check_plan(plan)) return s;
     if (!sum || !disp_int) return fail(SGM_ERR_INVALID, "sum and disp_int must not be NULL");
     const sgm::KernelConfig kc = config_for(plan, sum, nullptr);
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_wta_sum(plan->pb, kc, sum, d_lo, disp_int, disp_sub, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "wta launch");
 }
@@ -235,6 +267,7 @@ sgm_status sgm_aggregate_wta(sgm_plan_t plan, const uint8_t *cost, const int32_t
     void *vols = static_cast<uint8_t *>(ws) + plan->off_paths;
     hipStream_t st = (hipStream_t)stream;
     const sgm::KernelConfig kc = config_for(plan, cost, nullptr);
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_aggregate(plan->pb, kc, cost, plan->paths, plan->pb.npaths, kc.l8, vols, st);
     if (e == hipSuccess)
         e = sgm::launch_wta_paths(plan->pb, kc, vols, plan->pb.npaths, kc.l8, d_lo, disp_int, disp_sub, st);
@@ -275,6 +308,7 @@ sgm_status sgm_wta_paths(sgm_plan_t plan, const void *paths, const int32_t *d_lo
     if (!paths || !disp_int) return fail(SGM_ERR_INVALID, "paths and disp_int must not be NULL");
     if (!is_aligned(paths, 256)) return fail(SGM_ERR_INVALID, "paths must be 256-byte aligned");
     const sgm::KernelConfig kc = config_for(plan, nullptr, nullptr);
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_wta_paths(plan->pb, kc, paths, plan->pb.npaths, kc.l8, d_lo, disp_int, disp_sub,
                                          (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "wta_paths launch");
@@ -310,6 +344,7 @@ sgm_status sgm_downsample4(const uint8_t *img, int32_t width, int32_t height, in
 {
     if (!img || !out) return fail(SGM_ERR_INVALID, "img and out must not be NULL");
     if (width < 4 || height < 4 || pitch < width) return fail(SGM_ERR_INVALID, "need width, height >= 4, pitch >= width");
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_downsample4(img, width, height, pitch, 0, 1, out, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "downsample launch");
 }
@@ -321,6 +356,7 @@ sgm_status sgm_downsample4_batch(const uint8_t *images, int32_t width, int32_t h
     if (width < 4 || height < 4 || pitch < width) return fail(SGM_ERR_INVALID, "need width, height >= 4, pitch >= width");
     if (nimg < 1 || nimg > 65535) return fail(SGM_ERR_INVALID, "nimg must be in [1, 65535]");
     if (image_stride < (int64_t)pitch * height) return fail(SGM_ERR_INVALID, "image_stride < pitch * height");
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_downsample4(images, width, height, pitch, (long long)image_stride, nimg, out,
                                            (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "downsample4 launch");
@@ -338,6 +374,7 @@ sgm_status sgm_cost_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *rig
     uint64_t *cl = reinterpret_cast<uint64_t *>(base + plan->off_codes_l);
     uint64_t *cr = reinterpret_cast<uint64_t *>(base + plan->off_codes_r);
     hipStream_t st = (hipStream_t)stream;
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_census(plan->pb, left, pitch, cl, st);
     if (e == hipSuccess) e = sgm::launch_census(plan->pb, right, pitch, cr, st);
     if (e == hipSuccess) e = sgm::launch_cost_win(plan->pb, cl, cr, lo, cost, st);
@@ -356,6 +393,7 @@ sgm_status sgm_aggregate_win_paths(sgm_plan_t plan, const uint8_t *cost, const i
         return fail(SGM_ERR_WORKSPACE, "paths buffer of %zu bytes is smaller than the %zu required", paths_bytes,
                     total);
     const long long vstride = (long long)(vs / (plan->kc.l8 ? 1 : 2));
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_aggregate_win(plan->pb, cost, lo, plan->paths, plan->pb.npaths, plan->kc.l8, paths,
                                              vstride, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "aggregate_win launch");
@@ -370,6 +408,7 @@ sgm_status sgm_wta_win_paths(sgm_plan_t plan, const void *paths, const int32_t *
     size_t vs = 0;
     sgm_path_volumes(plan, nullptr, &vs, nullptr);
     const long long vstride = (long long)(vs / (plan->kc.l8 ? 1 : 2));
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_wta_win(plan->pb, paths, vstride, plan->pb.npaths, plan->kc.l8, lo, disp_int,
                                        disp_sub, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "wta_win launch");
@@ -434,8 +473,16 @@ sgm_status sgm_match_win_batch(sgm_plan_t plan, const uint8_t *left, const uint8
     b.vstride = (long long)vs;
     b.dint = disp_int;
     b.dsub = disp_sub;
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_match_win_pairs(plan->pb, b, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "match_win_batch launch");
+}
+
+sgm_status sgm_debug_inject_fault(int32_t kind)
+{
+    if (kind < 0 || kind > 2) return fail(SGM_ERR_INVALID, "fault kind %d not in {0, 1, 2}", kind);
+    g_fault.store(kind);
+    return SGM_OK;
 }
 
 sgm_status sgm_window_from_road(double a0, double a1, double phi, int32_t W, int32_t H, int32_t w, int32_t mode,

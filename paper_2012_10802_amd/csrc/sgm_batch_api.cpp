@@ -166,6 +166,7 @@ int agg_waves(sgm_batch_s *b)
 
 sgm_status enqueue_run(sgm_batch_s *b, void *ws, hipStream_t st)
 {
+    if (sgm::fault_take(sgm::kFaultLaunch)) return bfail(SGM_ERR_HIP, "injected launch failure");
     uint8_t *base = static_cast<uint8_t *>(ws);
     const size_t np = b->pairs.size();
     hipError_t e = hipMemcpyAsync(base + b->off_pairs, b->pin_pairs, np * sizeof(sgm::PairDev),
@@ -338,6 +339,10 @@ sgm_status sgm_batch_plan(const sgm_batch_params *prm, const sgm_pair *pairs, in
                 b->items.push_back(Item{(uint32_t)(i << 8 | r), (uint32_t)g,
                                         group_length(r, g, pairs[i].width, pairs[i].height), i, kind});
         }
+    if (sgm::fault_take(sgm::kFaultAlloc)) {
+        delete b;
+        return bfail(SGM_ERR_HIP, "injected allocation failure");
+    }
     if (hipHostMalloc(reinterpret_cast<void **>(&b->pin_pairs), npairs * sizeof(sgm::PairDev)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&b->pin_items), std::max<size_t>(1, nitems) * 2 * sizeof(uint32_t)) !=
             hipSuccess) {
@@ -418,6 +423,7 @@ sgm_status sgm_batch_launch(sgm_batch_t b, void *stream)
 {
     if (!b) return bfail(SGM_ERR_INVALID, "batch is NULL");
     if (!b->exec) return bfail(SGM_ERR_INVALID, "no captured graph (call sgm_batch_capture first)");
+    if (sgm::fault_take(sgm::kFaultLaunch)) return bfail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : bfail(SGM_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
 }

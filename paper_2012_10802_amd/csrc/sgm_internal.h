@@ -24,6 +24,11 @@ struct Problem {
     int W, H, w, n, npaths, p1, p2, cmax;
 };
 
+// One-shot injected failures (see sgm_debug_inject_fault): true once for
+// the armed kind, which is then disarmed.
+enum { kFaultLaunch = 1, kFaultAlloc = 2 };
+bool fault_take(int kind);
+
 // All launchers return hipSuccess or the launch error.
 hipError_t launch_census(const Problem &pb, const uint8_t *img, int pitch, uint64_t *codes,
                          hipStream_t s);

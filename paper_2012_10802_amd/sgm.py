@@ -81,6 +81,7 @@ def _load_library():
         "sgm_aggregate_win_paths": [P, P, P, P, S, P],
         "sgm_wta_win_paths": [P, P, P, P, P, P],
         "sgm_match_win": [P, P, P, I, P, P, P, P, S, P],
+        "sgm_debug_inject_fault": [I],
         "sgm_workspace_size_win_batch": [ctypes.c_void_p, I, ctypes.POINTER(ctypes.c_size_t)],
         "sgm_match_win_batch": [ctypes.c_void_p, P, P, I, ctypes.c_int64, P, I, P, P, P, S, P],
         "sgm_cnn_pack_weights": [P, P, P, P],

@@ -204,3 +204,31 @@ def test_cnn_and_window_calls_validate_before_launch():
     assert lib.sgm_fallback_merge(d, d, None, 100, 50, 0, 10, 95, 10, d, None, None) == -1
     assert lib.sgm_fallback_merge(d, d, None, 4, 70000, 0, 70000, 0, 4, d, None, None) == -2
     assert lib.sgm_label_downsample4(d, 3, 8, d, None) == -1
+
+
+def test_injected_faults_fail_before_anything_is_enqueued():
+    """The failure-handling hook: an armed launch fault makes the next
+    launching call return SGM_ERR_HIP with nothing enqueued (the dummy
+    buffers below are never touched), an armed allocation fault makes the
+    next batch plan fail; kinds outside 0..2 are rejected."""
+    import ctypes
+    from paper_2012_10802_amd import sgm
+    lib = sgm.library()
+    assert lib.sgm_debug_inject_fault(3) == -1
+    plan = sgm.sgm_plan(64, 32, 7, 16, 8, 10, 120)
+    try:
+        ws = sgm.sgm_workspace_size(plan)
+        d = ctypes.c_void_p(1 << 20)
+        assert lib.sgm_debug_inject_fault(1) == 0
+        rc = lib.sgm_cost(plan, d, d, 64, None, d, d, ws, None)
+        assert rc == -3 and b"injected" in lib.sgm_last_error()
+    finally:
+        sgm.sgm_plan_free(plan)
+    assert lib.sgm_debug_inject_fault(2) == 0
+    pairs = (sgm.sgm_pair * 1)()
+    pairs[0] = sgm.sgm_pair(64, 32, 16, 64, 1 << 20, 1 << 20, None, 1 << 20, None)
+    prm = sgm.sgm_batch_params(7, 8, 10, 120, 0)
+    h = ctypes.c_void_p()
+    rc = lib.sgm_batch_plan(ctypes.byref(prm), pairs, 1, ctypes.byref(h))
+    assert rc == -3 and b"injected" in lib.sgm_last_error()
+    assert lib.sgm_debug_inject_fault(0) == 0

@@ -253,3 +253,19 @@ def test_split_aggregate_paths_and_selection(lib, shape):
     wi, ws = oracle.wta(oracle.sum_paths(c, R, 10, p2), d_lo)
     np.testing.assert_array_equal(_np_u16(dint), wi)
     np.testing.assert_array_equal(dsub.cpu().numpy(), ws)
+
+
+def test_injected_launch_fault_then_recovery(lib):
+    """An armed launch fault fails exactly one call (nothing enqueued); the
+    next call runs normally and matches the oracle."""
+    import torch
+    L, R = _rand_pair(40, 12, 99)
+    m = lib.Matcher(40, 12, census=5, ndisp=16, npaths=4, p1=10, p2=120)
+    Ld, Rd = torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()
+    assert lib.library().sgm_debug_inject_fault(1) == 0
+    with pytest.raises(lib.SgmError):
+        m.match(Ld, Rd)
+    di, ds = m.match(Ld, Rd)
+    torch.cuda.synchronize()
+    wi, _ = oracle.sgm(L, R, 5, 16, 4, 10, 120)
+    np.testing.assert_array_equal(di.cpu().numpy().view(np.uint16), wi)
