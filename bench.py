@@ -86,6 +86,15 @@ def eval_mask(p, w, r, d_lo=None):
     return m
 
 
+def emit(record, args):
+    """Print the one JSON line (and append it to --jsonl when given)."""
+    line = json.dumps(record)
+    print(line, flush=True)
+    if getattr(args, "jsonl", None):
+        with open(args.jsonl, "a") as f:
+            f.write(line + "\n")
+
+
 def run_batch(args):
     """Batch mode: the whole batch as one captured graph per step."""
     import numpy as np
@@ -151,7 +160,7 @@ def run_batch(args):
                      "frac": round(evals * 25 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernel_source_sha256": kernel_source_digest(),
     }
-    print(json.dumps(out), flush=True)
+    emit(out, args)
 
 
 def learned_vs_plain(args, log=None):
@@ -282,6 +291,7 @@ def main():
     ap.add_argument("--eval-pairs", type=int, default=64)
     ap.add_argument("--lw-reps", type=int, default=3)
     ap.add_argument("--learned-only", action="store_true", help="print only the learned-window comparison")
+    ap.add_argument("--jsonl", default=None, help="also append the JSON record to this file")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(reference kernel for scaling memory counters)")
@@ -297,7 +307,7 @@ def main():
         import torch
         torch.cuda.set_device(0)
         res = learned_vs_plain(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
-        print(json.dumps(res), flush=True)
+        emit(res, args)
         return
 
     import numpy as np
@@ -439,7 +449,7 @@ def main():
         "cpu_baseline": cpu,
         "kernel_source_sha256": kernel_source_digest(),
     }
-    print(json.dumps(out), flush=True)
+    emit(out, args)
 
 
 if __name__ == "__main__":
