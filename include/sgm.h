@@ -369,6 +369,63 @@ sgm_status sgm_batch_launch(sgm_batch_t batch, void *stream);
 sgm_status sgm_batch_autotune(sgm_batch_t batch, void *workspace, size_t workspace_bytes,
                               void *stream, const char *cache_path, sgm_tuning *chosen);
 
+/* ------------------------------------------------------------------------
+ * Road model and disparity transformation (Sec. II-A, Sec. II-C).
+ *
+ * On the road the disparity of pixel (u, v) follows eq. (3),
+ *   f(u, v) = a0 + a1 (cos(phi) (v - cy) - sin(phi) (u - cx)),
+ * with the roll rotation about the image centre (cx, cy) = ((W-1)/2,
+ * (H-1)/2).  sgm_road_fit_batch fits (a0, a1, phi) to disparity maps as
+ * Sec. II-C does: for a fixed phi, eq. (11) gives the least-squares a and
+ * eq. (12) the residual E0min(phi); phi minimises E0min.  E0min is a ratio
+ * of two quadratic forms in (cos(phi), sin(phi)), so its minimum has a
+ * closed form: the least-squares plane d ~ c + g_u u + g_v v through the
+ * same pixels, read back as g_v = a1 cos(phi), g_u = -a1 sin(phi), with
+ * phi in (-pi/2, pi/2] (E0min has period pi).
+ *
+ * Buffers: disparity maps float32 [nimg][H][W] (dense), masks uint8
+ * [nimg][H][W] (dense), window starts int32 [nimg][H], fits
+ * sgm_road_fit [nimg]; all device, caller-owned.
+ */
+typedef struct {
+    double a0, a1, phi;  /* eq. (3); phi in radians, (-pi/2, pi/2] */
+    double g_u, g_v;     /* the same plane's slopes: -a1 sin(phi), a1 cos(phi) */
+    double e0min;        /* residual sum of squares at phi (eq. (12)) */
+    double count;        /* pixels that entered the fit */
+    int32_t status;      /* 0 fitted; 1 fewer than 3 pixels; 2 the pixels lie on
+                            one image line (det of the (u, v) covariance
+                            <= 1e-9 var(u) var(v)).  a0, a1, phi, g_u, g_v and
+                            e0min are NaN unless 0 */
+    int32_t reserved;
+} sgm_road_fit;
+
+/* Device scratch bytes of sgm_road_fit_batch for nimg maps of W x H. */
+sgm_status sgm_road_workspace_size(int32_t width, int32_t height, int32_t nimg, size_t *bytes);
+/* Fit of Sec. II-C to each of nimg disparity maps.  A pixel enters its
+ * map's fit when its mask entry is non-zero (mask NULL: every pixel), its
+ * disparity is finite and >= min_disp (pass -INFINITY for no bound; NaN is
+ * invalid).  Moments are accumulated in float64 in a fixed order, so the
+ * result is deterministic.  workspace: device, 256-byte aligned, at least
+ * sgm_road_workspace_size bytes.  The maps are read once (5 bytes per
+ * pixel with a mask, 4 without). */
+sgm_status sgm_road_fit_batch(const float *disp, const uint8_t *mask, int32_t width, int32_t height,
+                              int32_t nimg, float min_disp, sgm_road_fit *fit, void *workspace,
+                              size_t workspace_bytes, void *stream);
+/* Per-row window starts from device-resident fits (the device form of
+ * sgm_window_from_road below, with the plane's slopes in place of
+ * a1 cos(phi) and -a1 sin(phi)):
+ *   mode 0: d_lo = max(0, floor(f(cx, v) + 1/2) - floor(w/2));
+ *   mode 1: eq. (6), d_lo = max(0, floor(min over x = 0..W-1 of f(x, v) - delta)).
+ * Values are clamped to [0, 32767]; rows of a map whose fit failed get 0. */
+sgm_status sgm_road_window_batch(const sgm_road_fit *fit, int32_t width, int32_t height, int32_t nimg,
+                                 int32_t w, int32_t mode, double delta, int32_t *d_lo, void *stream);
+/* Disparity transformation of eq. (13): out = disp - f(u, v) + delta_dt per
+ * pixel, in float64 rounded once to float32; NaN on maps whose fit failed.
+ * out may equal disp (in place).  8 bytes of traffic per pixel. */
+sgm_status sgm_disparity_transform_batch(const float *disp, const sgm_road_fit *fit, int32_t width,
+                                         int32_t height, int32_t nimg, double delta_dt, float *out,
+                                         void *stream);
+
 /* Per-row window starts from the road model of eq. (3),
  *   f(u,v) = a0 + a1 (cos(phi) (v - cy) - sin(phi) (u - cx)),
  * with (cx, cy) = ((W-1)/2, (H-1)/2) the centre of the roll rotation.

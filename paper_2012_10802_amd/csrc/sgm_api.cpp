@@ -485,6 +485,70 @@ sgm_status sgm_debug_inject_fault(int32_t kind)
     return SGM_OK;
 }
 
+static sgm_status check_maps(int32_t W, int32_t H, int32_t nimg)
+{
+    if (W < 1 || H < 1 || nimg < 1) return fail(SGM_ERR_INVALID, "width, height and nimg must be >= 1");
+    if (nimg > 65535) return fail(SGM_ERR_UNSUPPORTED, "nimg %d > 65535", nimg);
+    if ((long long)W * H > (1LL << 30)) return fail(SGM_ERR_UNSUPPORTED, "W*H must be <= 2^30");
+    return SGM_OK;
+}
+
+sgm_status sgm_road_workspace_size(int32_t W, int32_t H, int32_t nimg, size_t *bytes)
+{
+    if (!bytes) return fail(SGM_ERR_INVALID, "bytes is NULL");
+    sgm_status st = check_maps(W, H, nimg);
+    if (st != SGM_OK) return st;
+    *bytes = sgm::road_workspace_bytes(W, H, nimg);
+    return SGM_OK;
+}
+
+sgm_status sgm_road_fit_batch(const float *disp, const uint8_t *mask, int32_t W, int32_t H, int32_t nimg,
+                              float min_disp, sgm_road_fit *fit, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!disp || !fit) return fail(SGM_ERR_INVALID, "disp and fit must not be NULL");
+    sgm_status st = check_maps(W, H, nimg);
+    if (st != SGM_OK) return st;
+    if (isnan(min_disp)) return fail(SGM_ERR_INVALID, "min_disp is NaN");
+    if (!ws) return fail(SGM_ERR_INVALID, "workspace is NULL");
+    if (!is_aligned(ws, 256)) return fail(SGM_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (!is_aligned(disp, 4) || !is_aligned(fit, 8)) return fail(SGM_ERR_INVALID, "disp or fit misaligned");
+    const size_t need = sgm::road_workspace_bytes(W, H, nimg);
+    if (ws_bytes < need)
+        return fail(SGM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
+    hipError_t e = sgm::launch_road_fit(disp, mask, W, H, nimg, min_disp, fit, ws, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "road fit launch");
+}
+
+sgm_status sgm_road_window_batch(const sgm_road_fit *fit, int32_t W, int32_t H, int32_t nimg, int32_t w,
+                                 int32_t mode, double delta, int32_t *d_lo, void *stream)
+{
+    if (!fit || !d_lo) return fail(SGM_ERR_INVALID, "fit and d_lo must not be NULL");
+    sgm_status st = check_maps(W, H, nimg);
+    if (st != SGM_OK) return st;
+    if (w < 1) return fail(SGM_ERR_INVALID, "w must be >= 1");
+    if (mode != 0 && mode != 1) return fail(SGM_ERR_INVALID, "mode %d not in {0, 1}", mode);
+    if (!isfinite(delta)) return fail(SGM_ERR_INVALID, "delta must be finite");
+    if (!is_aligned(fit, 8) || !is_aligned(d_lo, 4)) return fail(SGM_ERR_INVALID, "fit or d_lo misaligned");
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
+    hipError_t e = sgm::launch_road_window(fit, W, H, nimg, w, mode, delta, d_lo, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "road window launch");
+}
+
+sgm_status sgm_disparity_transform_batch(const float *disp, const sgm_road_fit *fit, int32_t W, int32_t H,
+                                         int32_t nimg, double delta_dt, float *out, void *stream)
+{
+    if (!disp || !fit || !out) return fail(SGM_ERR_INVALID, "disp, fit and out must not be NULL");
+    sgm_status st = check_maps(W, H, nimg);
+    if (st != SGM_OK) return st;
+    if (!isfinite(delta_dt)) return fail(SGM_ERR_INVALID, "delta_dt must be finite");
+    if (!is_aligned(disp, 4) || !is_aligned(out, 4) || !is_aligned(fit, 8))
+        return fail(SGM_ERR_INVALID, "disp, out or fit misaligned");
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
+    hipError_t e = sgm::launch_disp_transform(disp, fit, W, H, nimg, delta_dt, out, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "disparity transform launch");
+}
+
 sgm_status sgm_window_from_road(double a0, double a1, double phi, int32_t W, int32_t H, int32_t w, int32_t mode,
                                 double delta, int32_t *d_lo)
 {

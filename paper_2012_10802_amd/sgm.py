@@ -106,6 +106,10 @@ def _load_library():
         "sgm_batch_capture": [P, P, S, P],
         "sgm_batch_launch": [P, P],
         "sgm_batch_autotune": [P, P, S, P, ctypes.c_char_p, ctypes.POINTER(sgm_tuning)],
+        "sgm_road_workspace_size": [I, I, I, ctypes.POINTER(S)],
+        "sgm_road_fit_batch": [P, P, I, I, I, ctypes.c_float, P, P, S, P],
+        "sgm_road_window_batch": [P, I, I, I, I, I, D, P, P],
+        "sgm_disparity_transform_batch": [P, P, I, I, I, D, P, P],
         "sgm_status_str": [I],
         "sgm_last_error": [],
     }
@@ -213,6 +217,89 @@ def sgm_downsample4_batch(images, out=None, stream=None):
     _need(out, torch.uint8, (n, H // 4, W // 4), "out")
     _check(_lib.sgm_downsample4_batch(_ptr(images), W, H, W, H * W, n, _ptr(out), _stream(stream)),
            "sgm_downsample4_batch")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# road model (Sec. II-A eq. (3), Sec. II-C eq. (11)-(13))
+
+ROAD_FIT_WORDS = 8  # one sgm_road_fit = 8 float64 words (64 bytes)
+ROAD_FIELDS = ("a0", "a1", "phi", "g_u", "g_v", "e0min", "count")
+
+
+def road_workspace_size(width, height, nimg=1) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.sgm_road_workspace_size(int(width), int(height), int(nimg), ctypes.byref(n)),
+           "sgm_road_workspace_size")
+    return int(n.value)
+
+
+def _maps(t, dtype, name):
+    _need(t, dtype, None, name)
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3:
+        raise ValueError("%s must be [H, W] or [n, H, W]" % name)
+    return t
+
+
+def road_fit(disp, mask=None, min_disp=float("-inf"), fit=None, workspace=None, stream=None):
+    """Fit of the road model to float32 device disparity maps [H, W] or
+    [n, H, W] (mask: uint8 of the same shape, or None).  Returns the fits as
+    a float64 device tensor [n, 8] (sgm_road_fit records; see road_fit_dicts)."""
+    d = _maps(disp, torch.float32, "disp")
+    n, H, W = d.shape
+    if mask is not None:
+        mask = _maps(mask, torch.uint8, "mask")
+        if tuple(mask.shape) != (n, H, W):
+            raise ValueError("mask must have the shape of disp")
+    if fit is None:
+        fit = torch.empty((n, ROAD_FIT_WORDS), dtype=torch.float64, device=d.device)
+    _need(fit, torch.float64, (n, ROAD_FIT_WORDS), "fit")
+    need = road_workspace_size(W, H, n)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=d.device)
+    _need(workspace, torch.uint8, None, "workspace")
+    _check(_lib.sgm_road_fit_batch(_ptr(d), _ptr(mask), W, H, n, float(min_disp), _ptr(fit),
+                                   _ptr(workspace), workspace.numel(), _stream(stream)),
+           "sgm_road_fit_batch")
+    return fit
+
+
+def road_fit_dicts(fit):
+    """Host view of fits returned by road_fit (synchronises)."""
+    h = fit.detach().cpu()
+    st = h.view(torch.int32)[:, 14]
+    out = []
+    for i in range(h.shape[0]):
+        rec = {k: float(h[i, j]) for j, k in enumerate(ROAD_FIELDS)}
+        rec["status"] = int(st[i])
+        out.append(rec)
+    return out
+
+
+def road_window(fit, width, height, w, mode=0, delta=0.0, d_lo=None, stream=None):
+    """Per-row window starts int32 [n, H] from device fits."""
+    _need(fit, torch.float64, None, "fit")
+    n = fit.shape[0]
+    if d_lo is None:
+        d_lo = torch.empty((n, height), dtype=torch.int32, device=fit.device)
+    _need(d_lo, torch.int32, (n, height), "d_lo")
+    _check(_lib.sgm_road_window_batch(_ptr(fit), int(width), int(height), n, int(w), int(mode), float(delta),
+                                      _ptr(d_lo), _stream(stream)), "sgm_road_window_batch")
+    return d_lo
+
+
+def disparity_transform(disp, fit, delta_dt, out=None, stream=None):
+    """eq. (13) on float32 device maps [H, W] or [n, H, W]; out may be disp."""
+    d = _maps(disp, torch.float32, "disp")
+    n, H, W = d.shape
+    _need(fit, torch.float64, (n, ROAD_FIT_WORDS), "fit")
+    if out is None:
+        out = torch.empty_like(disp)
+    _need(out, torch.float32, tuple(disp.shape), "out")
+    _check(_lib.sgm_disparity_transform_batch(_ptr(d), _ptr(fit), W, H, n, float(delta_dt), _ptr(out),
+                                              _stream(stream)), "sgm_disparity_transform_batch")
     return out
 
 

@@ -232,3 +232,37 @@ def test_injected_faults_fail_before_anything_is_enqueued():
     rc = lib.sgm_batch_plan(ctypes.byref(prm), pairs, 1, ctypes.byref(h))
     assert rc == -3 and b"injected" in lib.sgm_last_error()
     assert lib.sgm_debug_inject_fault(0) == 0
+
+
+def test_road_calls_validate_before_launch():
+    """The road-model calls (fit, windows, transformation) check sizes,
+    bounds, alignment and workspace before anything is enqueued (dummy
+    non-NULL pointers are never touched); the fit record is 64 bytes."""
+    import ctypes
+    from paper_2012_10802_amd import sgm
+    lib = sgm.library()
+    d = ctypes.c_void_p(1 << 20)
+    f = ctypes.c_float
+    n = ctypes.c_size_t()
+    assert lib.sgm_road_workspace_size(1920, 1080, 16, ctypes.byref(n)) == 0 and n.value > 0
+    assert lib.sgm_road_workspace_size(0, 1080, 16, ctypes.byref(n)) == -1
+    assert lib.sgm_road_workspace_size(8, 8, 70000, ctypes.byref(n)) == -2
+    assert lib.sgm_road_workspace_size(1 << 16, 1 << 15, 1, ctypes.byref(n)) == -2
+    ws = sgm.road_workspace_size(64, 48, 2)
+    assert lib.sgm_road_fit_batch(None, None, 64, 48, 2, f(0.0), d, d, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(float("nan")), d, d, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), d, None, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), d, ctypes.c_void_p((1 << 20) + 16), ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), d, d, ws - 1, None) == -4
+    assert lib.sgm_road_fit_batch(ctypes.c_void_p((1 << 20) + 2), None, 64, 48, 2, f(0.0), d, d, ws, None) == -1
+    assert lib.sgm_road_window_batch(d, 64, 48, 2, 0, 0, 0.0, d, None) == -1
+    assert lib.sgm_road_window_batch(d, 64, 48, 2, 24, 2, 0.0, d, None) == -1
+    assert lib.sgm_road_window_batch(d, 64, 48, 2, 24, 1, float("inf"), d, None) == -1
+    assert lib.sgm_road_window_batch(None, 64, 48, 2, 24, 1, 0.0, d, None) == -1
+    assert lib.sgm_disparity_transform_batch(d, d, 64, 48, 2, float("nan"), d, None) == -1
+    assert lib.sgm_disparity_transform_batch(d, d, 64, -48, 2, 0.0, d, None) == -1
+    assert lib.sgm_disparity_transform_batch(d, d, 64, 48, 2, 0.0, None, None) == -1
+    # an armed launch fault fails the fit with nothing enqueued
+    assert lib.sgm_debug_inject_fault(1) == 0
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), d, d, ws, None) == -3
+    assert lib.sgm_debug_inject_fault(0) == 0
