@@ -135,6 +135,10 @@ def run_batch(args):
         stream.synchronize()
         t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
+    road = None
+    if not args.no_road:
+        road = road_model_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
+
     out = {
         "metric": METRIC,
         "value": round(evals / (ms * 1e-3) / 1e6, 1),
@@ -271,6 +275,112 @@ def learned_vs_plain(args, log=None):
     }
 
 
+def copy_calibration(args, dev):
+    """One device-to-device copy of --copy-calibration-mb MiB: the reference
+    kernel whose memory counters scale those of the measured kernels."""
+    import torch
+    if args.copy_calibration_mb:
+        src = torch.ones(args.copy_calibration_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+
+def road_model_leg(args, log=None):
+    """The road-model stages around the matcher on a batch of 16 full-range
+    1920x1080 SGM disparity maps of generated road pairs: the fit of
+    Sec. II-C (eq. (11), (12); road pixels from the generator's road mask),
+    per-row windows of eq. (6) from the device fits and the disparity
+    transformation of eq. (13).  Times each call with HIP events on the
+    stream it runs on and reports the HBM rate of the two streaming kernels
+    (fit: 4 B disparity + 1 B mask per pixel; transformation: 4 B in + 4 B
+    out per pixel) and the fit's error against the scenes' own (a0, a1,
+    phi)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2012_10802_amd import sgm, synth
+
+    dev = torch.device("cuda:0")
+    c = synth.CONFIGS["road1920"]
+    W, H, n = c["width"], c["height"], 16
+    L = torch.empty((n, H, W), dtype=torch.uint8, device=dev)
+    R = torch.empty_like(L)
+    mask = torch.empty((n, H, W), dtype=torch.uint8, device=dev)
+    truth = []
+    for i in range(n):
+        seed = 3_000_000 + i
+        sc = synth.scene_for_config("road1920", seed)
+        l, r, gt, road = synth.make_pair_torch(sc, seed, device=dev)
+        L[i].copy_(l)
+        R[i].copy_(r)
+        cols = torch.arange(W, device=dev)[None, :]
+        mask[i].copy_((road & (cols - gt >= 4)).to(torch.uint8))
+        truth.append(sc.road_params)
+    batch = sgm.Batch([dict(left=L[i], right=R[i], ndisp=c["ndisp"]) for i in range(n)], census=c["census"],
+                      npaths=c["npaths"], p1=c["p1"], p2=c["p2"], device=dev)
+    batch.run()
+    disp = torch.stack([batch.disp_sub[i] for i in range(n)]).contiguous()
+    del batch, L, R
+    fit = torch.empty((n, sgm.ROAD_FIT_WORDS), dtype=torch.float64, device=dev)
+    ws = torch.empty(sgm.road_workspace_size(W, H, n), dtype=torch.uint8, device=dev)
+    d_lo = torch.empty((n, H), dtype=torch.int32, device=dev)
+    d2 = torch.empty_like(disp)
+    torch.cuda.synchronize()
+
+    def once(ev=None):
+        if ev:
+            ev[0].record()
+        sgm.road_fit(disp, mask, 0.5, fit=fit, workspace=ws)
+        if ev:
+            ev[1].record()
+        sgm.road_window(fit, W, H, 24, mode=1, delta=2.0, d_lo=d_lo)
+        if ev:
+            ev[2].record()
+        sgm.disparity_transform(disp, fit, 10.0, out=d2)
+        if ev:
+            ev[3].record()
+
+    for _ in range(3):
+        once()
+    reps = 20
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+    torch.cuda.synchronize()
+    for e in events:
+        once(e)
+    torch.cuda.synchronize()
+    per = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(3)] for e in events])
+    fit_ms, win_ms, tr_ms = (float(x) for x in per.mean(axis=0))
+    copy_calibration(args, dev)
+    px = n * W * H
+    fit_gbs = px * 5 / (fit_ms * 1e-3) / 1e9
+    tr_gbs = px * 8 / (tr_ms * 1e-3) / 1e9
+    fits = sgm.road_fit_dicts(fit)
+    dphi = [abs(f["phi"] - t[2]) for f, t in zip(fits, truth)]
+    da1 = [abs(f["a1"] - t[1]) / t[1] for f, t in zip(fits, truth)]
+    da0 = [abs(f["a0"] - t[0]) for f, t in zip(fits, truth)]
+    if log:
+        log("road model: fit %.4f ms, windows %.4f ms, transformation %.4f ms per batch of %d"
+            % (fit_ms, win_ms, tr_ms, n))
+    return {
+        "maps": n, "width": W, "height": H,
+        "inputs": "full-range SGM disparity (0-191, census 7x7, 8 paths) of generated road pairs; "
+                  "mask = generator road pixels with u - gt >= 4",
+        "ms_per_batch": round(fit_ms + win_ms + tr_ms, 4),
+        "fit_ms": round(fit_ms, 4), "window_ms": round(win_ms, 4), "transform_ms": round(tr_ms, 4),
+        "fit_hbm": {"bytes_per_pixel": 5, "achieved": round(fit_gbs, 1), "unit": "GB/s",
+                    "frac": round(fit_gbs / HBM_PEAK_GBS, 4)},
+        "transform_hbm": {"bytes_per_pixel": 8, "achieved": round(tr_gbs, 1), "unit": "GB/s",
+                          "frac": round(tr_gbs / HBM_PEAK_GBS, 4)},
+        "fit_error": {"phi_max_deg": round(math.degrees(max(dphi)), 5),
+                      "a1_max_rel": round(max(da1), 6), "a0_max_px": round(max(da0), 4)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,6 +401,9 @@ def main():
     ap.add_argument("--eval-pairs", type=int, default=64)
     ap.add_argument("--lw-reps", type=int, default=3)
     ap.add_argument("--learned-only", action="store_true", help="print only the learned-window comparison")
+    ap.add_argument("--no-road", action="store_true", help="skip the road-model stages (fit, windows, "
+                    "disparity transformation)")
+    ap.add_argument("--road-only", action="store_true", help="print only the road-model stages")
     ap.add_argument("--jsonl", default=None, help="also append the JSON record to this file")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
@@ -303,6 +416,11 @@ def main():
         sys.exit(2)
     if args.mode == "batch" or args.workload == "road_batch64":
         return run_batch(args)
+    if args.road_only:
+        import torch
+        torch.cuda.set_device(0)
+        emit(road_model_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True)), args)
+        return
     if args.learned_only:
         import torch
         torch.cuda.set_device(0)
@@ -363,13 +481,7 @@ def main():
     evals = W * H * w
     value = evals / (ms_per_step * 1e-3) / 1e6
 
-    if args.copy_calibration_mb:
-        src = torch.ones(args.copy_calibration_mb << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_calibration(args, dev)
 
     # dominant kernel: the one-launch aggregation of all directions.  Its
     # compulsory traffic under this schedule: every direction streams the
@@ -419,6 +531,10 @@ def main():
     if not args.no_learned and os.path.exists(args.weights):
         learned = learned_vs_plain(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
 
+    road = None
+    if not args.no_road:
+        road = road_model_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
+
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -446,6 +562,7 @@ def main():
                        "wta": round(wta_ms, 4)},
         "accuracy": accuracy,
         "learned_window": learned,
+        "road_model": road,
         "cpu_baseline": cpu,
         "kernel_source_sha256": kernel_source_digest(),
     }

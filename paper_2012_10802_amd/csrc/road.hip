@@ -13,7 +13,8 @@
 //
 // Kernels:
 //   k_road_moments   one pass over the maps: per-block partial sums (float64,
-//                    fixed order), 4-5 bytes read per pixel, HBM-bound;
+//                    fixed order), 4-5 bytes read per pixel, HBM-bound
+//                    (k_road_moments_vec: float4 loads, two rows in flight);
 //   k_road_solve     one wave per map: ordered reduction of the partials and
 //                    the closed form;
 //   k_road_window    one thread per row: window starts from the fit;
@@ -30,7 +31,7 @@ namespace {
 
 constexpr int kMoments = 10;  // n, su, sv, suu, suv, svv, sd, sud, svd, sdd
 constexpr int kRoadThreads = 256;
-constexpr int kTargetBlocks = 4096;
+constexpr int kTargetBlocks = 4096;  // workgroups per launch (rows per workgroup follow)
 
 __device__ inline double wave_sum(double x)
 {
@@ -41,18 +42,116 @@ __device__ inline double wave_sum(double x)
 
 __device__ inline bool selected(float d, float min_disp)
 {
-    return d >= min_disp && fabsf(d) <= 3.402823466e38f;  // finite and above the bound (NaN fails)
+    return (d >= min_disp) & (fabsf(d) <= 3.402823466e38f);  // finite and above the bound (NaN fails)
 }
 
-// Rows [v0, v0 + rows) of one map per workgroup.  Each thread keeps the
-// sums that depend on u and d for the current row and folds them into its
-// totals with that row's v.  VEC: four consecutive pixels per load (W % 4 == 0
-// and 16-byte aligned maps).
-template <bool VEC>
+// Block-wide sum of the ten moments (fixed order), written as this
+// workgroup's partial.
+__device__ inline void store_partial(const double (&acc)[kMoments], double *__restrict__ part)
+{
+    __shared__ double red[kRoadThreads / 64][kMoments];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int i = 0; i < kMoments; ++i) {
+        const double s = wave_sum(acc[i]);
+        if (lane == 0) red[wave][i] = s;
+    }
+    __syncthreads();
+    if (t < kMoments) {
+        double s = 0.0;
+        for (int w = 0; w < kRoadThreads / 64; ++w) s += red[w][t];
+        part[t] = s;
+    }
+}
+
+// Folds one row's per-thread sums (u and d only) into the totals with the
+// row's v.
+__device__ inline void fold_row(double (&acc)[kMoments], double v, double rn, double ru, double ruu, double rd,
+                                double rud, double rdd)
+{
+    acc[0] += rn;
+    acc[1] += ru;
+    acc[2] += v * rn;
+    acc[3] += ruu;
+    acc[4] += v * ru;
+    acc[5] += v * v * rn;
+    acc[6] += rd;
+    acc[7] += rud;
+    acc[8] += v * rd;
+    acc[9] += rdd;
+}
+
+// Rows [v0, v0 + rows) of one map per workgroup, W % 4 == 0 and
+// W <= 1024 K: thread t owns the float4 groups t + 256 k (k < K) of every
+// row.  Two rows' loads (2 K float4 + 2 K mask words) are issued before any
+// is used, at clamped in-bounds addresses, and pixels outside the rows or
+// the row are dropped by the selection, so the body is straight-line code.
+// Per-row sums of the selected pixels' count, u and u^2 are exact int32
+// (at most 4 K pixels of u < 4096 per thread and row).
+template <int K>
+__global__ __launch_bounds__(kRoadThreads) void k_road_moments_vec(const float *__restrict__ disp,
+                                                                     const uint8_t *__restrict__ mask, int W,
+                                                                     int H, int rows, int nblk, float min_disp,
+                                                                     double *__restrict__ part)
+{
+    const int img = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
+    const size_t base = (size_t)img * W * H;
+    const int v0 = b * rows, v1 = min(H, v0 + rows);
+    double acc[kMoments];
+#pragma unroll
+    for (int i = 0; i < kMoments; ++i) acc[i] = 0.0;
+
+    for (int v = v0; v < v1; v += 2) {
+        float4 d4[2][K];
+        uint32_t m4[2][K];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int vr = min(v + r, v1 - 1);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int x = min(4 * (t + kRoadThreads * k), W - 4);
+                d4[r][k] = *reinterpret_cast<const float4 *>(disp + base + (size_t)vr * W + x);
+                m4[r][k] = mask ? *reinterpret_cast<const uint32_t *>(mask + base + (size_t)vr * W + x)
+                                : 0xFFFFFFFFu;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            if (v + r >= v1) break;
+            int rn = 0, ru = 0, ruu = 0;
+            double rd = 0.0, rud = 0.0, rdd = 0.0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int x = 4 * (t + kRoadThreads * k);
+                const bool in = x < W;
+                const float dv[4] = {d4[r][k].x, d4[r][k].y, d4[r][k].z, d4[r][k].w};
+                double se = 0.0, we = 0.0;  // sum d and sum e d over the four pixels x + e
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const bool sel = in & (((m4[r][k] >> (8 * e)) & 0xFFu) != 0) & selected(dv[e], min_disp);
+                    const double d = (double)(sel ? dv[e] : 0.0f);
+                    const int u = x + e;
+                    rn += sel ? 1 : 0;
+                    ru += sel ? u : 0;
+                    ruu += sel ? u * u : 0;
+                    se += d;
+                    if (e) we += (double)e * d;
+                    rdd += d * d;
+                }
+                rd += se;
+                rud += (double)x * se + we;
+            }
+            fold_row(acc, (double)(v + r), (double)rn, (double)ru, (double)ruu, rd, rud, rdd);
+        }
+    }
+    store_partial(acc, part + ((size_t)img * nblk + b) * kMoments);
+}
+
+// Any width, one pixel per load.
 __global__ __launch_bounds__(kRoadThreads) void k_road_moments(const float *__restrict__ disp,
-                                                                 const uint8_t *__restrict__ mask, int W,
-                                                                 int H, int rows, int nblk, float min_disp,
-                                                                 double *__restrict__ part)
+                                                               const uint8_t *__restrict__ mask, int W, int H,
+                                                               int rows, int nblk, float min_disp,
+                                                               double *__restrict__ part)
 {
     const int img = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
     const size_t base = (size_t)img * W * H;
@@ -65,56 +164,21 @@ __global__ __launch_bounds__(kRoadThreads) void k_road_moments(const float *__re
         const float *drow = disp + base + (size_t)v * W;
         const uint8_t *mrow = mask ? mask + base + (size_t)v * W : nullptr;
         double rn = 0.0, ru = 0.0, ruu = 0.0, rd = 0.0, rud = 0.0, rdd = 0.0;
-        auto take = [&](int u, float df, bool m) {
-            if (m && selected(df, min_disp)) {
-                const double d = (double)df, uu = (double)u;
+        for (int x = t; x < W; x += kRoadThreads) {
+            const float df = drow[x];
+            if ((!mrow || mrow[x] != 0) && selected(df, min_disp)) {
+                const double d = (double)df, u = (double)x;
                 rn += 1.0;
-                ru += uu;
-                ruu += uu * uu;
+                ru += u;
+                ruu += u * u;
                 rd += d;
-                rud += uu * d;
+                rud += u * d;
                 rdd += d * d;
             }
-        };
-        if (VEC) {
-            for (int x = 4 * t; x < W; x += 4 * kRoadThreads) {
-                const float4 d4 = *reinterpret_cast<const float4 *>(drow + x);
-                uint32_t m4 = 0xFFFFFFFFu;
-                if (mrow) m4 = *reinterpret_cast<const uint32_t *>(mrow + x);
-                take(x + 0, d4.x, (m4 & 0xFFu) != 0);
-                take(x + 1, d4.y, (m4 & 0xFF00u) != 0);
-                take(x + 2, d4.z, (m4 & 0xFF0000u) != 0);
-                take(x + 3, d4.w, (m4 & 0xFF000000u) != 0);
-            }
-        } else {
-            for (int x = t; x < W; x += kRoadThreads) take(x, drow[x], !mrow || mrow[x] != 0);
         }
-        const double vv = (double)v;
-        acc[0] += rn;
-        acc[1] += ru;
-        acc[2] += vv * rn;
-        acc[3] += ruu;
-        acc[4] += vv * ru;
-        acc[5] += vv * vv * rn;
-        acc[6] += rd;
-        acc[7] += rud;
-        acc[8] += vv * rd;
-        acc[9] += rdd;
+        fold_row(acc, (double)v, rn, ru, ruu, rd, rud, rdd);
     }
-
-    __shared__ double red[kRoadThreads / 64][kMoments];
-    const int lane = t & 63, wave = t >> 6;
-#pragma unroll
-    for (int i = 0; i < kMoments; ++i) {
-        const double s = wave_sum(acc[i]);
-        if (lane == 0) red[wave][i] = s;
-    }
-    __syncthreads();
-    if (t < kMoments) {
-        double s = 0.0;
-        for (int w = 0; w < kRoadThreads / 64; ++w) s += red[w][t];
-        part[((size_t)img * nblk + b) * kMoments + t] = s;
-    }
+    store_partial(acc, part + ((size_t)img * nblk + b) * kMoments);
 }
 
 // One wave per map: lane l sums partials l, l + 64, ... in order, then a
@@ -200,12 +264,63 @@ __global__ __launch_bounds__(256) void k_road_window(const sgm_road_fit *__restr
     d_lo[(size_t)img * H + v] = out;
 }
 
-// eq. (13) over rows [v0, v0 + rows) of one map per workgroup.
-template <bool VEC>
+// eq. (13) over rows [v0, v0 + rows) of one map per workgroup:
+// D2 = D1 - (a0 + g_v (v - cy) + g_u (u - cx)) + delta = D1 + (c(v) - g_u u).
+__device__ inline float transform_px(float d, double c, double gu, int u, bool ok)
+{
+    return ok ? (float)((double)d + (c - gu * (double)u)) : __builtin_nanf("");
+}
+
+// W % 4 == 0, W <= 1024 K: thread t owns float4 groups t + 256 k of every
+// row; two rows' loads are issued before the first store.
+template <int K>
+__global__ __launch_bounds__(kRoadThreads) void k_disp_transform_vec(const float *__restrict__ disp,
+                                                                       const sgm_road_fit *__restrict__ fit,
+                                                                       int W, int H, int rows, double delta,
+                                                                       float *__restrict__ out)
+{
+    const int img = blockIdx.y, t = threadIdx.x;
+    const int v0 = blockIdx.x * rows, v1 = min(H, v0 + rows);
+    const size_t base = (size_t)img * W * H;
+    const sgm_road_fit f = fit[img];
+    const bool ok = f.status == 0;
+    const double cx = 0.5 * (W - 1), cy = 0.5 * (H - 1);
+    for (int v = v0; v < v1; v += 2) {
+        float4 d4[2][K];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int vr = min(v + r, v1 - 1);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int x = min(4 * (t + kRoadThreads * k), W - 4);
+                d4[r][k] = *reinterpret_cast<const float4 *>(disp + base + (size_t)vr * W + x);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            if (v + r >= v1) break;
+            const double c = delta - f.a0 - f.g_v * ((double)(v + r) - cy) + f.g_u * cx;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int x = 4 * (t + kRoadThreads * k);
+                if (x < W) {
+                    float4 o;
+                    o.x = transform_px(d4[r][k].x, c, f.g_u, x + 0, ok);
+                    o.y = transform_px(d4[r][k].y, c, f.g_u, x + 1, ok);
+                    o.z = transform_px(d4[r][k].z, c, f.g_u, x + 2, ok);
+                    o.w = transform_px(d4[r][k].w, c, f.g_u, x + 3, ok);
+                    *reinterpret_cast<float4 *>(out + base + (size_t)(v + r) * W + x) = o;
+                }
+            }
+        }
+    }
+}
+
+// Any width, one pixel per access.
 __global__ __launch_bounds__(kRoadThreads) void k_disp_transform(const float *__restrict__ disp,
-                                                                   const sgm_road_fit *__restrict__ fit, int W,
-                                                                   int H, int rows, double delta,
-                                                                   float *__restrict__ out)
+                                                                 const sgm_road_fit *__restrict__ fit, int W,
+                                                                 int H, int rows, double delta,
+                                                                 float *__restrict__ out)
 {
     const int img = blockIdx.y, t = threadIdx.x;
     const int v0 = blockIdx.x * rows, v1 = min(H, v0 + rows);
@@ -214,31 +329,16 @@ __global__ __launch_bounds__(kRoadThreads) void k_disp_transform(const float *__
     const bool ok = f.status == 0;
     const double cx = 0.5 * (W - 1), cy = 0.5 * (H - 1);
     for (int v = v0; v < v1; ++v) {
-        // D2 = D1 - (a0 + g_v (v - cy) + g_u (u - cx)) + delta = D1 + (c0 - g_u u)
-        const double c0 = delta - f.a0 - f.g_v * ((double)v - cy) + f.g_u * cx;
-        const float *src = disp + base + (size_t)v * W;
-        float *dst = out + base + (size_t)v * W;
-        if (VEC) {
-            for (int x = 4 * t; x < W; x += 4 * kRoadThreads) {
-                const float4 d = *reinterpret_cast<const float4 *>(src + x);
-                float4 r;
-                r.x = ok ? (float)((double)d.x + (c0 - f.g_u * (double)(x + 0))) : __builtin_nanf("");
-                r.y = ok ? (float)((double)d.y + (c0 - f.g_u * (double)(x + 1))) : __builtin_nanf("");
-                r.z = ok ? (float)((double)d.z + (c0 - f.g_u * (double)(x + 2))) : __builtin_nanf("");
-                r.w = ok ? (float)((double)d.w + (c0 - f.g_u * (double)(x + 3))) : __builtin_nanf("");
-                *reinterpret_cast<float4 *>(dst + x) = r;
-            }
-        } else {
-            for (int x = t; x < W; x += kRoadThreads)
-                dst[x] = ok ? (float)((double)src[x] + (c0 - f.g_u * (double)x)) : __builtin_nanf("");
-        }
+        const double c = delta - f.a0 - f.g_v * ((double)v - cy) + f.g_u * cx;
+        for (int x = t; x < W; x += kRoadThreads)
+            out[base + (size_t)v * W + x] = transform_px(disp[base + (size_t)v * W + x], c, f.g_u, x, ok);
     }
 }
 
-// Rows per workgroup so that a launch has about kTargetBlocks workgroups.
-int road_rows(int H, int nimg)
+// Rows per workgroup so that a launch has about `target` workgroups.
+int road_rows(int H, int nimg, int target)
 {
-    const long long want = (kTargetBlocks + nimg - 1) / nimg;
+    const long long want = (target + nimg - 1) / nimg;
     const long long rows = (H + want - 1) / want;
     return (int)(rows < 1 ? 1 : rows);
 }
@@ -254,7 +354,7 @@ bool vec_ok(const void *a, const void *b, const void *c, int W)
 size_t road_workspace_bytes(int W, int H, int nimg)
 {
     (void)W;
-    const int rows = road_rows(H, nimg);
+    const int rows = road_rows(H, nimg, kTargetBlocks);
     const size_t nblk = (size_t)((H + rows - 1) / rows);
     return nblk * (size_t)nimg * kMoments * sizeof(double);
 }
@@ -262,14 +362,19 @@ size_t road_workspace_bytes(int W, int H, int nimg)
 hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H, int nimg, float min_disp,
                            sgm_road_fit *fit, void *ws, hipStream_t s)
 {
-    const int rows = road_rows(H, nimg);
+    const int rows = road_rows(H, nimg, kTargetBlocks);
     const int nblk = (H + rows - 1) / rows;
     double *part = static_cast<double *>(ws);
     const dim3 grid(nblk, nimg);
-    if (vec_ok(disp, mask, nullptr, W))
-        k_road_moments<true><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, part);
+    const bool vec = vec_ok(disp, mask, nullptr, W);
+    if (vec && W <= 1024)
+        k_road_moments_vec<1><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, part);
+    else if (vec && W <= 2048)
+        k_road_moments_vec<2><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, part);
+    else if (vec && W <= 4096)
+        k_road_moments_vec<4><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, part);
     else
-        k_road_moments<false><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, part);
+        k_road_moments<<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_road_solve<<<nimg, 64, 0, s>>>(part, nblk, W, H, fit);
@@ -287,12 +392,17 @@ hipError_t launch_road_window(const sgm_road_fit *fit, int W, int H, int nimg, i
 hipError_t launch_disp_transform(const float *disp, const sgm_road_fit *fit, int W, int H, int nimg,
                                  double delta, float *out, hipStream_t s)
 {
-    const int rows = road_rows(H, nimg);
+    const int rows = road_rows(H, nimg, kTargetBlocks);
     const dim3 grid((H + rows - 1) / rows, nimg);
-    if (vec_ok(disp, out, nullptr, W))
-        k_disp_transform<true><<<grid, kRoadThreads, 0, s>>>(disp, fit, W, H, rows, delta, out);
+    const bool vec = vec_ok(disp, out, nullptr, W);
+    if (vec && W <= 1024)
+        k_disp_transform_vec<1><<<grid, kRoadThreads, 0, s>>>(disp, fit, W, H, rows, delta, out);
+    else if (vec && W <= 2048)
+        k_disp_transform_vec<2><<<grid, kRoadThreads, 0, s>>>(disp, fit, W, H, rows, delta, out);
+    else if (vec && W <= 4096)
+        k_disp_transform_vec<4><<<grid, kRoadThreads, 0, s>>>(disp, fit, W, H, rows, delta, out);
     else
-        k_disp_transform<false><<<grid, kRoadThreads, 0, s>>>(disp, fit, W, H, rows, delta, out);
+        k_disp_transform<<<grid, kRoadThreads, 0, s>>>(disp, fit, W, H, rows, delta, out);
     return hipGetLastError();
 }
 

@@ -113,11 +113,14 @@ def test_fit_on_sgm_output_matches_oracle(lib, cfg, seed):
     assert abs(got["phi"] - phi) < 2e-3 and abs(got["a1"] - a1) < 2e-3
 
 
-@pytest.mark.parametrize("W,H", [(257, 131), (64, 1000), (1, 50), (50, 1), (4, 3), (1283, 37)])
+@pytest.mark.parametrize("W,H", [(257, 131), (64, 1000), (1, 50), (50, 1), (4, 3), (1283, 37),
+                                 (1024, 7), (1028, 6), (2600, 9), (4100, 5)])
 def test_fit_shapes_and_batches(lib, W, H):
-    """Ragged widths (scalar path), widths divisible by 4 (vector path),
-    single rows / columns (degenerate), several maps per launch with NaN,
-    infinite and below-floor pixels and masks."""
+    """Ragged widths (one pixel per access), widths divisible by 4 up to 1024,
+    2048 and 4096 (float4 paths with 1, 2, 4 groups per thread and row) and
+    beyond, odd and even row counts, single rows / columns (degenerate),
+    several maps per launch with NaN, infinite and below-floor pixels and
+    masks; the transformation on the same maps."""
     rng = np.random.default_rng(W * 1000 + H)
     n = 3
     Ds, Ms = [], []
@@ -132,9 +135,18 @@ def test_fit_shapes_and_batches(lib, W, H):
     fits = lib.road_fit_dicts(lib.road_fit(_dev(Ds), _dev(Ms), 19.0))
     for i in range(n):
         _close_fit(fits[i], oroad.fit_road(Ds[i], Ms[i], 19.0), Ds[i])
-    fits = lib.road_fit_dicts(lib.road_fit(_dev(Ds)))
+    fit = lib.road_fit(_dev(Ds))
+    fits = lib.road_fit_dicts(fit)
     for i in range(n):
         _close_fit(fits[i], oroad.fit_road(Ds[i]), Ds[i])
+    D2 = lib.disparity_transform(_dev(Ds), fit, 4.0).cpu().numpy()
+    for i in range(n):
+        f = fits[i]
+        if f["status"] == 0:
+            want = oroad.transform(Ds[i], f["a0"], f["a1"], f["phi"], 4.0)
+            np.testing.assert_allclose(D2[i], want, rtol=2.5e-7, atol=1e-9)
+        else:
+            assert np.isnan(D2[i]).all()
 
 
 def test_degenerate_selections(lib):
