@@ -135,9 +135,10 @@ def run_batch(args):
         stream.synchronize()
         t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
-    road = None
+    road = persp = None
     if not args.no_road:
         road = road_model_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
+        persp = perspective_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
 
     out = {
         "metric": METRIC,
@@ -381,6 +382,78 @@ def road_model_leg(args, log=None):
     }
 
 
+def perspective_leg(args, log=None):
+    """The perspective-transformed form from the images alone on 1280x720
+    road pairs (disparities 0-127, census 7x7, 8 paths): quarter-scale
+    full-range SGM, road fit on it (eq. (11), (12)), per-row windows of 24
+    (Sec. II-A), windowed SGM at full resolution, refit on D1 and eq. (13).
+    Wall time per frame (HIP events around the whole pipeline) against plain
+    full-range SGM on the same pairs, and the bad-pixel rate of both on the
+    same pixels (the full-range evaluation mask)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2012_10802_amd import sgm, synth
+    from paper_2012_10802_amd.road_pipeline import PerspectiveMatcher
+
+    dev = torch.device("cuda:0")
+    c = synth.CONFIGS["road1280"]
+    W, H, D, n = c["width"], c["height"], c["ndisp"], c["census"]
+    pm = PerspectiveMatcher(W, H, ndisp=D, w=24, census=n, npaths=c["npaths"], p1=c["p1"], p2=c["p2"],
+                            delta_dt=20.0, device=dev)
+    plain = sgm.Matcher(W, H, census=n, ndisp=D, npaths=c["npaths"], p1=c["p1"], p2=c["p2"], device=dev)
+    reps, npairs = 20, 4
+    t_pt, t_plain, bad_pt, bad_plain, miss, dphi, da0 = [], [], [], [], [], [], []
+    for i in range(npairs):
+        seed = args.seed + 100 + i
+        pair = synth.make_pair(synth.scene_for_config("road1280", seed), seed)
+        left = torch.from_numpy(pair.left).to(dev)
+        right = torch.from_numpy(pair.right).to(dev)
+        for fn, acc in ((lambda: pm.match(left, right), t_pt), (lambda: plain.match(left, right), t_plain)):
+            for _ in range(3):
+                fn()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(reps):
+                fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            acc.append(ev[0].elapsed_time(ev[1]) / reps)
+        _, ds_plain = plain.match(left, right)
+        torch.cuda.synchronize()
+        mask = eval_mask(pair, D, n // 2)
+        gt = pair.gt[mask]
+        bad_pt.append(float((np.abs(pm.disp_sub.cpu().numpy()[mask] - gt) > 1.0).mean()))
+        bad_plain.append(float((np.abs(ds_plain.cpu().numpy()[mask] - gt) > 1.0).mean()))
+        lo = pm.d_lo.cpu().numpy().astype(np.float64)[:, None]
+        inside = (pair.gt >= lo) & (pair.gt < lo + 24 - 1)
+        miss.append(float((~inside[mask]).mean()))
+        cf = sgm.road_fit_dicts(pm.coarse_fit)[0]
+        a0, a1, phi = pair.road_params
+        dphi.append(abs(cf["phi"] - phi))
+        da0.append(abs(4 * cf["a0"] - a0))
+    ms_pt, ms_plain = float(np.mean(t_pt)), float(np.mean(t_plain))
+    if log:
+        log("perspective form: %.4f ms vs plain %.4f ms per frame" % (ms_pt, ms_plain))
+    return {
+        "pairs": npairs, "width": W, "height": H, "ndisp": D, "window": 24,
+        "ms_per_frame": round(ms_pt, 4), "plain_ms_per_frame": round(ms_plain, 4),
+        "speedup": round(ms_plain / ms_pt, 3),
+        "full_range_equivalent": {"value": round(W * H * D / (ms_pt * 1e-3) / 1e6, 1),
+                                  "unit": "Mdisp-evals/s (pixels x 128 disparities per second)"},
+        "bad_1px_pct": round(100 * float(np.mean(bad_pt)), 4),
+        "plain_bad_1px_pct": round(100 * float(np.mean(bad_plain)), 4),
+        "window_miss_pct": round(100 * float(np.mean(miss)), 4),
+        "coarse_fit_error": {"phi_max_deg": round(math.degrees(max(dphi)), 4),
+                             "a0_max_px": round(max(da0), 4)},
+        "stages": "4x4 reduction, quarter-scale SGM (0-31), road fit, windows, windowed SGM (24), "
+                  "refit on D1, eq. (13)",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +477,8 @@ def main():
     ap.add_argument("--no-road", action="store_true", help="skip the road-model stages (fit, windows, "
                     "disparity transformation)")
     ap.add_argument("--road-only", action="store_true", help="print only the road-model stages")
+    ap.add_argument("--perspective-only", action="store_true",
+                    help="print only the perspective-transformed form estimated from the images")
     ap.add_argument("--jsonl", default=None, help="also append the JSON record to this file")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
@@ -420,6 +495,11 @@ def main():
         import torch
         torch.cuda.set_device(0)
         emit(road_model_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True)), args)
+        return
+    if args.perspective_only:
+        import torch
+        torch.cuda.set_device(0)
+        emit(perspective_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True)), args)
         return
     if args.learned_only:
         import torch
@@ -531,9 +611,10 @@ def main():
     if not args.no_learned and os.path.exists(args.weights):
         learned = learned_vs_plain(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
 
-    road = None
+    road = persp = None
     if not args.no_road:
         road = road_model_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
+        persp = perspective_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
 
     out = {
         "metric": METRIC,
@@ -563,6 +644,7 @@ def main():
         "accuracy": accuracy,
         "learned_window": learned,
         "road_model": road,
+        "perspective_from_images": persp,
         "cpu_baseline": cpu,
         "kernel_source_sha256": kernel_source_digest(),
     }

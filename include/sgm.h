@@ -401,24 +401,30 @@ typedef struct {
 
 /* Device scratch bytes of sgm_road_fit_batch for nimg maps of W x H. */
 sgm_status sgm_road_workspace_size(int32_t width, int32_t height, int32_t nimg, size_t *bytes);
-/* Fit of Sec. II-C to each of nimg disparity maps.  A pixel enters its
- * map's fit when its mask entry is non-zero (mask NULL: every pixel), its
- * disparity is finite and >= min_disp (pass -INFINITY for no bound; NaN is
+/* Fit of Sec. II-C to each of nimg disparity maps.  Pixel (u, v) (integer
+ * column and row) enters its map's fit when its mask entry is non-zero
+ * (mask NULL: every pixel), its disparity d is finite, d >= min_disp and
+ * u - d >= margin, i.e. its match lies inside the right image with that
+ * much room (compared in float64; pass -INFINITY for no bound; NaN is
  * invalid).  Moments are accumulated in float64 in a fixed order, so the
  * result is deterministic.  workspace: device, 256-byte aligned, at least
  * sgm_road_workspace_size bytes.  The maps are read once (5 bytes per
  * pixel with a mask, 4 without). */
 sgm_status sgm_road_fit_batch(const float *disp, const uint8_t *mask, int32_t width, int32_t height,
-                              int32_t nimg, float min_disp, sgm_road_fit *fit, void *workspace,
-                              size_t workspace_bytes, void *stream);
-/* Per-row window starts from device-resident fits (the device form of
- * sgm_window_from_road below, with the plane's slopes in place of
- * a1 cos(phi) and -a1 sin(phi)):
+                              int32_t nimg, float min_disp, double margin, sgm_road_fit *fit,
+                              void *workspace, size_t workspace_bytes, void *stream);
+/* Per-row window starts for W x H frames from device-resident fits (the
+ * device form of sgm_window_from_road below, with the plane's slopes in
+ * place of a1 cos(phi) and -a1 sin(phi)).  With scale s the fits are of
+ * maps at 1/s resolution (e.g. s = 4 for the 4x4 reduction): disparities
+ * and centred coordinates both scale by s, so f(u, v) = s a0 + g_u (u - cx)
+ * + g_v (v - cy) at full resolution; s = 1 for fits of W x H maps.
  *   mode 0: d_lo = max(0, floor(f(cx, v) + 1/2) - floor(w/2));
  *   mode 1: eq. (6), d_lo = max(0, floor(min over x = 0..W-1 of f(x, v) - delta)).
  * Values are clamped to [0, 32767]; rows of a map whose fit failed get 0. */
 sgm_status sgm_road_window_batch(const sgm_road_fit *fit, int32_t width, int32_t height, int32_t nimg,
-                                 int32_t w, int32_t mode, double delta, int32_t *d_lo, void *stream);
+                                 int32_t w, int32_t mode, double delta, double scale, int32_t *d_lo,
+                                 void *stream);
 /* Disparity transformation of eq. (13): out = disp - f(u, v) + delta_dt per
  * pixel, in float64 rounded once to float32; NaN on maps whose fit failed.
  * out may equal disp (in place).  8 bytes of traffic per pixel. */

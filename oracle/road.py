@@ -24,8 +24,10 @@ Disparity transformation (Sec. II-C, eq. (13)):
 D2(p) = D1(p) - f(a, p, phi) + delta_DT.
 
 Pixel selection (the paper fits "road disparities" without saying how they
-are chosen): a pixel is used when its mask entry is non-zero (no mask: all
-pixels), its disparity is finite and at least `min_disp`.
+are chosen): a pixel (column u, row v, integer indices) is used when its
+mask entry is non-zero (no mask: all pixels), its disparity d is finite and
+at least `min_disp`, and its match lies inside the right image with room to
+spare: u - d >= `margin` (computed in float64).
 
 Status: 0 fitted; 1 fewer than 3 pixels selected; 2 the selected pixels lie
 on one image line (the 2x2 covariance of (u, v) has
@@ -46,12 +48,13 @@ GOLDEN_TOL = 1e-11          # final bracket width of the golden-section search (
 COLLINEAR = 1e-9
 
 
-def select(disp, mask=None, min_disp=-math.inf):
+def select(disp, mask=None, min_disp=-math.inf, margin=-math.inf):
     """Centred coordinates (u, v) and disparities d (float64) of the pixels
     that enter the fit."""
     D = np.asarray(disp)
     H, W = D.shape
-    keep = np.isfinite(D) & (D >= min_disp)
+    cols = np.arange(W, dtype=np.float64)[None, :]
+    keep = np.isfinite(D) & (D >= min_disp) & (cols - D.astype(np.float64) >= margin)
     if mask is not None:
         keep &= np.asarray(mask) != 0
     vv, uu = np.nonzero(keep)
@@ -115,10 +118,10 @@ def minimise_phi(u, v, d):
     return _wrap(0.5 * (lo + hi))
 
 
-def fit_road(disp, mask=None, min_disp=-math.inf):
+def fit_road(disp, mask=None, min_disp=-math.inf, margin=-math.inf):
     """Fit of Sec. II-C to one disparity map [H][W]: dict with status, count,
     a0, a1, phi (radians) and e0min."""
-    u, v, d = select(disp, mask, min_disp)
+    u, v, d = select(disp, mask, min_disp, margin)
     k = d.size
     nan = float("nan")
     out = dict(status=0, count=k, a0=nan, a1=nan, phi=nan, e0min=nan)

@@ -40,9 +40,12 @@ __device__ inline double wave_sum(double x)
     return x;
 }
 
-__device__ inline bool selected(float d, float min_disp)
+// Selection of pixel (u, d): d finite, d >= min_disp and u - d >= margin,
+// in float64 (exact: u and d convert exactly, and so does their
+// difference); `lim` = u - margin.  NaN fails every comparison.
+__device__ inline bool selected(double d, double min_disp, double lim)
 {
-    return (d >= min_disp) & (fabsf(d) <= 3.402823466e38f);  // finite and above the bound (NaN fails)
+    return (d >= min_disp) & (d <= lim) & (fabs(d) <= 3.4028234663852886e38);
 }
 
 // Block-wide sum of the ten moments (fixed order), written as this
@@ -91,8 +94,8 @@ __device__ inline void fold_row(double (&acc)[kMoments], double v, double rn, do
 template <int K>
 __global__ __launch_bounds__(kRoadThreads) void k_road_moments_vec(const float *__restrict__ disp,
                                                                      const uint8_t *__restrict__ mask, int W,
-                                                                     int H, int rows, int nblk, float min_disp,
-                                                                     double *__restrict__ part)
+                                                                     int H, int rows, int nblk, double min_disp,
+                                                                     double margin, double *__restrict__ part)
 {
     const int img = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
     const size_t base = (size_t)img * W * H;
@@ -125,11 +128,14 @@ __global__ __launch_bounds__(kRoadThreads) void k_road_moments_vec(const float *
                 const int x = 4 * (t + kRoadThreads * k);
                 const bool in = x < W;
                 const float dv[4] = {d4[r][k].x, d4[r][k].y, d4[r][k].z, d4[r][k].w};
+                const double lim0 = (double)x - margin;
                 double se = 0.0, we = 0.0;  // sum d and sum e d over the four pixels x + e
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const bool sel = in & (((m4[r][k] >> (8 * e)) & 0xFFu) != 0) & selected(dv[e], min_disp);
-                    const double d = (double)(sel ? dv[e] : 0.0f);
+                    const double de = (double)dv[e];
+                    const bool sel = in & (((m4[r][k] >> (8 * e)) & 0xFFu) != 0) &
+                                     selected(de, min_disp, lim0 + (double)e);
+                    const double d = sel ? de : 0.0;
                     const int u = x + e;
                     rn += sel ? 1 : 0;
                     ru += sel ? u : 0;
@@ -150,7 +156,7 @@ __global__ __launch_bounds__(kRoadThreads) void k_road_moments_vec(const float *
 // Any width, one pixel per load.
 __global__ __launch_bounds__(kRoadThreads) void k_road_moments(const float *__restrict__ disp,
                                                                const uint8_t *__restrict__ mask, int W, int H,
-                                                               int rows, int nblk, float min_disp,
+                                                               int rows, int nblk, double min_disp, double margin,
                                                                double *__restrict__ part)
 {
     const int img = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
@@ -165,9 +171,8 @@ __global__ __launch_bounds__(kRoadThreads) void k_road_moments(const float *__re
         const uint8_t *mrow = mask ? mask + base + (size_t)v * W : nullptr;
         double rn = 0.0, ru = 0.0, ruu = 0.0, rd = 0.0, rud = 0.0, rdd = 0.0;
         for (int x = t; x < W; x += kRoadThreads) {
-            const float df = drow[x];
-            if ((!mrow || mrow[x] != 0) && selected(df, min_disp)) {
-                const double d = (double)df, u = (double)x;
+            const double d = (double)drow[x], u = (double)x;
+            if ((!mrow || mrow[x] != 0) && selected(d, min_disp, u - margin)) {
                 rn += 1.0;
                 ru += u;
                 ruu += u * u;
@@ -242,7 +247,8 @@ __global__ __launch_bounds__(64) void k_road_solve(const double *__restrict__ pa
 }
 
 __global__ __launch_bounds__(256) void k_road_window(const sgm_road_fit *__restrict__ fit, int W, int H, int w,
-                                                     int mode, double delta, int32_t *__restrict__ d_lo)
+                                                     int mode, double delta, double scale,
+                                                     int32_t *__restrict__ d_lo)
 {
     const int img = blockIdx.y, v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= H) return;
@@ -250,7 +256,9 @@ __global__ __launch_bounds__(256) void k_road_window(const sgm_road_fit *__restr
     int32_t out = 0;
     if (f.status == 0) {
         const double cx = 0.5 * (W - 1), cy = 0.5 * (H - 1);
-        const double row = f.a0 + f.g_v * ((double)v - cy);
+        // a fit of a map at 1/scale resolution: disparities and centred
+        // coordinates both scale, so a0 scales and the slopes stay
+        const double row = scale * f.a0 + f.g_v * ((double)v - cy);
         double lo;
         if (mode == 0) {
             lo = floor(row + 0.5) - (double)(w / 2);
@@ -360,7 +368,7 @@ size_t road_workspace_bytes(int W, int H, int nimg)
 }
 
 hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H, int nimg, float min_disp,
-                           sgm_road_fit *fit, void *ws, hipStream_t s)
+                           double margin, sgm_road_fit *fit, void *ws, hipStream_t s)
 {
     const int rows = road_rows(H, nimg, kTargetBlocks);
     const int nblk = (H + rows - 1) / rows;
@@ -368,13 +376,13 @@ hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H,
     const dim3 grid(nblk, nimg);
     const bool vec = vec_ok(disp, mask, nullptr, W);
     if (vec && W <= 1024)
-        k_road_moments_vec<1><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, part);
+        k_road_moments_vec<1><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, part);
     else if (vec && W <= 2048)
-        k_road_moments_vec<2><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, part);
+        k_road_moments_vec<2><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, part);
     else if (vec && W <= 4096)
-        k_road_moments_vec<4><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, part);
+        k_road_moments_vec<4><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, part);
     else
-        k_road_moments<<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, part);
+        k_road_moments<<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_road_solve<<<nimg, 64, 0, s>>>(part, nblk, W, H, fit);
@@ -382,10 +390,10 @@ hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H,
 }
 
 hipError_t launch_road_window(const sgm_road_fit *fit, int W, int H, int nimg, int w, int mode, double delta,
-                              int32_t *d_lo, hipStream_t s)
+                              double scale, int32_t *d_lo, hipStream_t s)
 {
     const dim3 grid((H + 255) / 256, nimg);
-    k_road_window<<<grid, 256, 0, s>>>(fit, W, H, w, mode, delta, d_lo);
+    k_road_window<<<grid, 256, 0, s>>>(fit, W, H, w, mode, delta, scale, d_lo);
     return hipGetLastError();
 }
 

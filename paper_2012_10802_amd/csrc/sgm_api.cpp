@@ -503,12 +503,13 @@ sgm_status sgm_road_workspace_size(int32_t W, int32_t H, int32_t nimg, size_t *b
 }
 
 sgm_status sgm_road_fit_batch(const float *disp, const uint8_t *mask, int32_t W, int32_t H, int32_t nimg,
-                              float min_disp, sgm_road_fit *fit, void *ws, size_t ws_bytes, void *stream)
+                              float min_disp, double margin, sgm_road_fit *fit, void *ws, size_t ws_bytes,
+                              void *stream)
 {
     if (!disp || !fit) return fail(SGM_ERR_INVALID, "disp and fit must not be NULL");
     sgm_status st = check_maps(W, H, nimg);
     if (st != SGM_OK) return st;
-    if (isnan(min_disp)) return fail(SGM_ERR_INVALID, "min_disp is NaN");
+    if (isnan(min_disp) || isnan(margin)) return fail(SGM_ERR_INVALID, "min_disp and margin must not be NaN");
     if (!ws) return fail(SGM_ERR_INVALID, "workspace is NULL");
     if (!is_aligned(ws, 256)) return fail(SGM_ERR_INVALID, "workspace must be 256-byte aligned");
     if (!is_aligned(disp, 4) || !is_aligned(fit, 8)) return fail(SGM_ERR_INVALID, "disp or fit misaligned");
@@ -516,12 +517,12 @@ sgm_status sgm_road_fit_batch(const float *disp, const uint8_t *mask, int32_t W,
     if (ws_bytes < need)
         return fail(SGM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
     if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
-    hipError_t e = sgm::launch_road_fit(disp, mask, W, H, nimg, min_disp, fit, ws, (hipStream_t)stream);
+    hipError_t e = sgm::launch_road_fit(disp, mask, W, H, nimg, min_disp, margin, fit, ws, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "road fit launch");
 }
 
 sgm_status sgm_road_window_batch(const sgm_road_fit *fit, int32_t W, int32_t H, int32_t nimg, int32_t w,
-                                 int32_t mode, double delta, int32_t *d_lo, void *stream)
+                                 int32_t mode, double delta, double scale, int32_t *d_lo, void *stream)
 {
     if (!fit || !d_lo) return fail(SGM_ERR_INVALID, "fit and d_lo must not be NULL");
     sgm_status st = check_maps(W, H, nimg);
@@ -529,9 +530,10 @@ sgm_status sgm_road_window_batch(const sgm_road_fit *fit, int32_t W, int32_t H, 
     if (w < 1) return fail(SGM_ERR_INVALID, "w must be >= 1");
     if (mode != 0 && mode != 1) return fail(SGM_ERR_INVALID, "mode %d not in {0, 1}", mode);
     if (!isfinite(delta)) return fail(SGM_ERR_INVALID, "delta must be finite");
+    if (!(scale > 0.0) || !isfinite(scale)) return fail(SGM_ERR_INVALID, "scale must be finite and > 0");
     if (!is_aligned(fit, 8) || !is_aligned(d_lo, 4)) return fail(SGM_ERR_INVALID, "fit or d_lo misaligned");
     if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
-    hipError_t e = sgm::launch_road_window(fit, W, H, nimg, w, mode, delta, d_lo, (hipStream_t)stream);
+    hipError_t e = sgm::launch_road_window(fit, W, H, nimg, w, mode, delta, scale, d_lo, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "road window launch");
 }
 

@@ -123,9 +123,9 @@ hipError_t launch_batch(const BatchDev &b, const BatchGrids &g, int census_n, bo
 
 size_t road_workspace_bytes(int W, int H, int nimg);
 hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H, int nimg, float min_disp,
-                           sgm_road_fit *fit, void *ws, hipStream_t s);
+                           double margin, sgm_road_fit *fit, void *ws, hipStream_t s);
 hipError_t launch_road_window(const sgm_road_fit *fit, int W, int H, int nimg, int w, int mode, double delta,
-                              int32_t *d_lo, hipStream_t s);
+                              double scale, int32_t *d_lo, hipStream_t s);
 hipError_t launch_disp_transform(const float *disp, const sgm_road_fit *fit, int W, int H, int nimg,
                                  double delta, float *out, hipStream_t s);
 

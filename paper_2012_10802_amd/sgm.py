@@ -107,8 +107,8 @@ def _load_library():
         "sgm_batch_launch": [P, P],
         "sgm_batch_autotune": [P, P, S, P, ctypes.c_char_p, ctypes.POINTER(sgm_tuning)],
         "sgm_road_workspace_size": [I, I, I, ctypes.POINTER(S)],
-        "sgm_road_fit_batch": [P, P, I, I, I, ctypes.c_float, P, P, S, P],
-        "sgm_road_window_batch": [P, I, I, I, I, I, D, P, P],
+        "sgm_road_fit_batch": [P, P, I, I, I, ctypes.c_float, D, P, P, S, P],
+        "sgm_road_window_batch": [P, I, I, I, I, I, D, D, P, P],
         "sgm_disparity_transform_batch": [P, P, I, I, I, D, P, P],
         "sgm_status_str": [I],
         "sgm_last_error": [],
@@ -243,10 +243,12 @@ def _maps(t, dtype, name):
     return t
 
 
-def road_fit(disp, mask=None, min_disp=float("-inf"), fit=None, workspace=None, stream=None):
+def road_fit(disp, mask=None, min_disp=float("-inf"), margin=float("-inf"), fit=None, workspace=None,
+             stream=None):
     """Fit of the road model to float32 device disparity maps [H, W] or
-    [n, H, W] (mask: uint8 of the same shape, or None).  Returns the fits as
-    a float64 device tensor [n, 8] (sgm_road_fit records; see road_fit_dicts)."""
+    [n, H, W] (mask: uint8 of the same shape, or None; pixels with
+    d < min_disp or column - d < margin are skipped).  Returns the fits as a
+    float64 device tensor [n, 8] (sgm_road_fit records; see road_fit_dicts)."""
     d = _maps(disp, torch.float32, "disp")
     n, H, W = d.shape
     if mask is not None:
@@ -260,7 +262,7 @@ def road_fit(disp, mask=None, min_disp=float("-inf"), fit=None, workspace=None, 
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=d.device)
     _need(workspace, torch.uint8, None, "workspace")
-    _check(_lib.sgm_road_fit_batch(_ptr(d), _ptr(mask), W, H, n, float(min_disp), _ptr(fit),
+    _check(_lib.sgm_road_fit_batch(_ptr(d), _ptr(mask), W, H, n, float(min_disp), float(margin), _ptr(fit),
                                    _ptr(workspace), workspace.numel(), _stream(stream)),
            "sgm_road_fit_batch")
     return fit
@@ -278,15 +280,16 @@ def road_fit_dicts(fit):
     return out
 
 
-def road_window(fit, width, height, w, mode=0, delta=0.0, d_lo=None, stream=None):
-    """Per-row window starts int32 [n, H] from device fits."""
+def road_window(fit, width, height, w, mode=0, delta=0.0, scale=1.0, d_lo=None, stream=None):
+    """Per-row window starts int32 [n, H] for W x H frames from device fits
+    (of maps at 1/scale resolution)."""
     _need(fit, torch.float64, None, "fit")
     n = fit.shape[0]
     if d_lo is None:
         d_lo = torch.empty((n, height), dtype=torch.int32, device=fit.device)
     _need(d_lo, torch.int32, (n, height), "d_lo")
     _check(_lib.sgm_road_window_batch(_ptr(fit), int(width), int(height), n, int(w), int(mode), float(delta),
-                                      _ptr(d_lo), _stream(stream)), "sgm_road_window_batch")
+                                      float(scale), _ptr(d_lo), _stream(stream)), "sgm_road_window_batch")
     return d_lo
 
 

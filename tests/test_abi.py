@@ -249,20 +249,26 @@ def test_road_calls_validate_before_launch():
     assert lib.sgm_road_workspace_size(8, 8, 70000, ctypes.byref(n)) == -2
     assert lib.sgm_road_workspace_size(1 << 16, 1 << 15, 1, ctypes.byref(n)) == -2
     ws = sgm.road_workspace_size(64, 48, 2)
-    assert lib.sgm_road_fit_batch(None, None, 64, 48, 2, f(0.0), d, d, ws, None) == -1
-    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(float("nan")), d, d, ws, None) == -1
-    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), d, None, ws, None) == -1
-    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), d, ctypes.c_void_p((1 << 20) + 16), ws, None) == -1
-    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), d, d, ws - 1, None) == -4
-    assert lib.sgm_road_fit_batch(ctypes.c_void_p((1 << 20) + 2), None, 64, 48, 2, f(0.0), d, d, ws, None) == -1
-    assert lib.sgm_road_window_batch(d, 64, 48, 2, 0, 0, 0.0, d, None) == -1
-    assert lib.sgm_road_window_batch(d, 64, 48, 2, 24, 2, 0.0, d, None) == -1
-    assert lib.sgm_road_window_batch(d, 64, 48, 2, 24, 1, float("inf"), d, None) == -1
-    assert lib.sgm_road_window_batch(None, 64, 48, 2, 24, 1, 0.0, d, None) == -1
+    ninf = float("-inf")
+    assert lib.sgm_road_fit_batch(None, None, 64, 48, 2, f(0.0), ninf, d, d, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(float("nan")), ninf, d, d, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), float("nan"), d, d, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, d, None, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, d, ctypes.c_void_p((1 << 20) + 16), ws,
+                                  None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, d, d, ws - 1, None) == -4
+    assert lib.sgm_road_fit_batch(ctypes.c_void_p((1 << 20) + 2), None, 64, 48, 2, f(0.0), ninf, d, d, ws,
+                                  None) == -1
+    assert lib.sgm_road_window_batch(d, 64, 48, 2, 0, 0, 0.0, 1.0, d, None) == -1
+    assert lib.sgm_road_window_batch(d, 64, 48, 2, 24, 2, 0.0, 1.0, d, None) == -1
+    assert lib.sgm_road_window_batch(d, 64, 48, 2, 24, 1, float("inf"), 1.0, d, None) == -1
+    assert lib.sgm_road_window_batch(d, 64, 48, 2, 24, 1, 0.0, 0.0, d, None) == -1
+    assert lib.sgm_road_window_batch(d, 64, 48, 2, 24, 1, 0.0, float("nan"), d, None) == -1
+    assert lib.sgm_road_window_batch(None, 64, 48, 2, 24, 1, 0.0, 1.0, d, None) == -1
     assert lib.sgm_disparity_transform_batch(d, d, 64, 48, 2, float("nan"), d, None) == -1
     assert lib.sgm_disparity_transform_batch(d, d, 64, -48, 2, 0.0, d, None) == -1
     assert lib.sgm_disparity_transform_batch(d, d, 64, 48, 2, 0.0, None, None) == -1
     # an armed launch fault fails the fit with nothing enqueued
     assert lib.sgm_debug_inject_fault(1) == 0
-    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), d, d, ws, None) == -3
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, d, d, ws, None) == -3
     assert lib.sgm_debug_inject_fault(0) == 0

@@ -59,8 +59,8 @@ def _close_fit(got, want, D):
     assert got["g_v"] == pytest.approx(got["a1"] * math.cos(got["phi"]), rel=1e-9, abs=1e-15)
 
 
-def _fit_one(lib, D, mask=None, min_disp=-math.inf):
-    fit = lib.road_fit(_dev(D), None if mask is None else _dev(mask.astype(np.uint8)), min_disp)
+def _fit_one(lib, D, mask=None, min_disp=-math.inf, margin=-math.inf):
+    fit = lib.road_fit(_dev(D), None if mask is None else _dev(mask.astype(np.uint8)), min_disp, margin)
     return lib.road_fit_dicts(fit)[0], fit
 
 
@@ -100,6 +100,11 @@ def test_fit_on_sgm_output_matches_oracle(lib, cfg, seed):
     _close_fit(got, oroad.fit_road(D, mask), D)
     got, _ = _fit_one(lib, D, None, 0.5)
     _close_fit(got, oroad.fit_road(D, None, 0.5), D)
+    # matches inside the right image only (the selection a pipeline without
+    # ground truth can make)
+    for margin in (4.0, 10.5):
+        got, _ = _fit_one(lib, D, None, 0.5, margin)
+        _close_fit(got, oroad.fit_road(D, None, 0.5, margin), D)
     # on the scored road pixels (matchable, away from the borders, no
     # potholes) the fit lands near the scene's own road line
     a0, a1, phi = ps.road_params
@@ -135,6 +140,10 @@ def test_fit_shapes_and_batches(lib, W, H):
     fits = lib.road_fit_dicts(lib.road_fit(_dev(Ds), _dev(Ms), 19.0))
     for i in range(n):
         _close_fit(fits[i], oroad.fit_road(Ds[i], Ms[i], 19.0), Ds[i])
+    margin = W / 3 - 20.25
+    fits = lib.road_fit_dicts(lib.road_fit(_dev(Ds), _dev(Ms), -math.inf, margin))
+    for i in range(n):
+        _close_fit(fits[i], oroad.fit_road(Ds[i], Ms[i], -math.inf, margin), Ds[i])
     fit = lib.road_fit(_dev(Ds))
     fits = lib.road_fit_dicts(fit)
     for i in range(n):
@@ -169,7 +178,7 @@ def test_degenerate_selections(lib):
         _close_fit(g, oroad.fit_road(D, M), D)
     assert [g["status"] for g in got] == [1, 1, 2, 2, 2]
     # failed fits: windows start at 0, the transformation gives NaN
-    lo = lib.road_window(fit, W, H, 24, 1, 2.0).cpu().numpy()
+    lo = lib.road_window(fit, W, H, 24, 1, 2.0, 1.0).cpu().numpy()
     assert not lo.any()
     D2 = lib.disparity_transform(_dev(Ds), fit, 3.0).cpu().numpy()
     assert np.isnan(D2).all()
@@ -198,13 +207,16 @@ def test_windows_from_fit_match_oracle(lib, mode, w, delta):
     Ds = np.stack(maps)
     fit = lib.road_fit(_dev(Ds), None, 0.5)
     lo = lib.road_window(fit, W, H, w, mode, delta).cpu().numpy()
+    # the same fits used for 4x larger frames: a0 scales by 4, the slopes stay
+    lo4 = lib.road_window(fit, 4 * W, 4 * H, w, mode, delta, scale=4.0).cpu().numpy()
     for i in range(len(maps)):
         f = oroad.fit_road(Ds[i], None, 0.5)
-        want = oracle.window_from_road(f["a0"], f["a1"], f["phi"], W, H, w, mode, delta)
-        arg = _floor_arg(f["a0"], f["a1"], f["phi"], W, H, w, mode, delta)
-        edge = np.abs(arg - np.rint(arg)) < 1e-6
-        np.testing.assert_array_equal(lo[i][~edge], want[~edge])
-        assert np.all(np.abs(lo[i][edge].astype(int) - want[edge]) <= 1)
+        for got, s in ((lo[i], 1), (lo4[i], 4)):
+            want = oracle.window_from_road(s * f["a0"], f["a1"], f["phi"], s * W, s * H, w, mode, delta)
+            arg = _floor_arg(s * f["a0"], f["a1"], f["phi"], s * W, s * H, w, mode, delta)
+            edge = np.abs(arg - np.rint(arg)) < 1e-6
+            np.testing.assert_array_equal(got[~edge], want[~edge])
+            assert np.all(np.abs(got[edge].astype(int) - want[edge]) <= 1)
 
 
 def test_transform_matches_oracle_and_in_place(lib):
@@ -255,3 +267,43 @@ def test_full_size_batch_of_16(lib):
     f = fits[9]
     want = oroad.transform(Dh[9], f["a0"], f["a1"], f["phi"], 10.0)
     np.testing.assert_allclose(D2[9].cpu().numpy(), want, rtol=2.5e-7, atol=1e-9)
+
+
+def test_perspective_pipeline_from_images_alone(lib):
+    """The self-contained perspective-transformed path on a 1280x720 road
+    pair: every stage equals the oracle on the previous stage's GPU output
+    (4x4 reduction and quarter-scale SGM bit-exact, coarse fit, windows at
+    scale 4, windowed SGM bit-exact, refit on D1, eq. (13)), and the coarse
+    fit finds the scene's own road line."""
+    import torch
+    from paper_2012_10802_amd.road_pipeline import PerspectiveMatcher
+    seed = 5
+    sc = synth.scene_for_config("road1280", seed)
+    ps = synth.make_pair(sc, seed)
+    pm = PerspectiveMatcher(1280, 720, ndisp=128, w=24, census=7, npaths=8, p1=10, p2=120, delta_dt=20.0)
+    dint, dsub, d2 = pm.match(_dev(ps.left), _dev(ps.right))
+    torch.cuda.synchronize()
+    lc, rc = oracle.downsample4(ps.left), oracle.downsample4(ps.right)
+    np.testing.assert_array_equal(pm.left_c.cpu().numpy(), lc)
+    np.testing.assert_array_equal(pm.right_c.cpu().numpy(), rc)
+    ci, cs = oracle.sgm(lc, rc, 7, 32, 8, 10, 120)
+    np.testing.assert_array_equal(pm.coarse_int.cpu().numpy().view(np.uint16), ci)
+    np.testing.assert_allclose(pm.coarse_sub.cpu().numpy(), cs, rtol=0, atol=1e-4)
+    cmap = pm.coarse_sub.cpu().numpy()
+    cf = lib.road_fit_dicts(pm.coarse_fit)[0]
+    _close_fit(cf, oroad.fit_road(cmap, None, 0.5, 4.0), cmap)
+    a0, a1, phi = ps.road_params
+    assert abs(cf["phi"] - phi) < math.radians(0.2) and abs(4 * cf["a0"] - a0) < 1.0
+    want = oracle.window_from_road(4 * cf["a0"], cf["a1"], cf["phi"], 1280, 720, 24, 0)
+    arg = _floor_arg(4 * cf["a0"], cf["a1"], cf["phi"], 1280, 720, 24, 0, 0.0)
+    edge = np.abs(arg - np.rint(arg)) < 1e-6
+    d_lo = pm.d_lo.cpu().numpy()
+    np.testing.assert_array_equal(d_lo[~edge], want[~edge])
+    oi, osub = oracle.sgm(ps.left, ps.right, 7, 24, 8, 10, 120, d_lo)
+    np.testing.assert_array_equal(dint.cpu().numpy().view(np.uint16), oi)
+    np.testing.assert_allclose(dsub.cpu().numpy(), osub, rtol=0, atol=1e-4)
+    D1 = dsub.cpu().numpy()
+    f = lib.road_fit_dicts(pm.fit)[0]
+    _close_fit(f, oroad.fit_road(D1, None, 2.0, 16.0), D1)
+    np.testing.assert_allclose(d2.cpu().numpy(), oroad.transform(D1, f["a0"], f["a1"], f["phi"], 20.0),
+                               rtol=2.5e-7, atol=1e-9)

@@ -138,6 +138,12 @@ def test_selection_and_degenerate_cases():
     Dn[:10] = np.nan
     assert road.fit_road(Dn)["count"] == D.size - 10 * D.shape[1]
     assert road.fit_road(D, min_disp=1e9)["status"] == 1
+    # margin: the match column u - d must stay >= margin
+    H, W = D.shape
+    for margin in (0.0, 30.5, 100.0):
+        want = int((np.arange(W)[None, :] - D.astype(np.float64) >= margin).sum())
+        assert road.fit_road(D, margin=margin)["count"] == want
+    assert road.fit_road(D, margin=1e9)["status"] == 1
     assert road.fit_road(D, np.zeros(D.shape, np.uint8))["status"] == 1
     two = np.zeros(D.shape, np.uint8)
     two[5, 5] = two[6, 7] = 1
