@@ -432,6 +432,56 @@ sgm_status sgm_disparity_transform_batch(const float *disp, const sgm_road_fit *
                                          int32_t height, int32_t nimg, double delta_dt, float *out,
                                          void *stream);
 
+/* ------------------------------------------------------------------------
+ * Pothole threshold and labelling (Sec. II-E, eq. (14), (15)) on
+ * transformed disparity maps D2 (eq. (13)), pixel by pixel (the paper's
+ * superpixel step is not part of the library).
+ *
+ * Each pixel p whose 3x3 neighbourhood lies inside the image, with p and
+ * its 8 neighbours selected (mask entry non-zero, or mask NULL) and finite,
+ * gives a vector g = [D2(p), sum of D2 over the 8 neighbours] (the sum in
+ * float64, neighbours in row-major order).  Candidate thresholds are
+ * t_r = lo + k b, b = (hi - lo) / nbins, k = 1 .. nbins - 1.  With the bin
+ * indices i = clamp(floor((g0 - lo) / b), 0, nbins - 1) and
+ * j = clamp(floor((g1 - 8 lo) / (8 b)), 0, nbins - 1) (float64), g is in
+ * region 1 (foreground) for k when max(i, j) < k and in region 2
+ * (background) when min(i, j) >= k: the split along the histogram's
+ * diagonal, with the two mixed regions left out.  E2(k) of eq. (15) is
+ * minimised over the k whose two regions are both non-empty (the smallest
+ * k on a tie), and t_s = t_r - delta_PD (eq. (14)).
+ *
+ * Buffers: maps float32 [nimg][H][W], masks uint8 [nimg][H][W], labels
+ * int32 [nimg][H][W], results sgm_pothole_threshold [nimg], E2 curves
+ * float64 [nimg][nbins + 1] (entries 0 and nbins NaN); all device.
+ */
+typedef struct {
+    double t_r, t_s;  /* eq. (14) */
+    double e2;        /* E2 at t_r (eq. (15)) */
+    double n1, n2;    /* vectors in regions 1 and 2 at t_r */
+    int32_t k;        /* t_r = lo + k b; 0 when status != 0 */
+    int32_t status;   /* 0 found; 1 no candidate has two non-empty regions
+                         (t_r, t_s, e2 NaN) */
+} sgm_pothole_threshold;
+
+/* Device scratch bytes of sgm_pothole_threshold_batch. */
+sgm_status sgm_pothole_workspace_size(int32_t nbins, int32_t nimg, size_t *bytes);
+/* Threshold search per map.  2 <= nbins <= 512; lo < hi, finite;
+ * delta_pd finite; e2_curve may be NULL.  workspace: device, 256-byte
+ * aligned, at least sgm_pothole_workspace_size bytes; it is cleared by the
+ * call itself.  E2 sums are float64 atomics, so their last bits may vary
+ * from run to run; counts are exact. */
+sgm_status sgm_pothole_threshold_batch(const float *d2, const uint8_t *mask, int32_t width, int32_t height,
+                                       int32_t nimg, double lo, double hi, int32_t nbins, double delta_pd,
+                                       sgm_pothole_threshold *result, double *e2_curve, void *workspace,
+                                       size_t workspace_bytes, void *stream);
+/* Pothole labels: pixels that are selected, finite and below t_s form
+ * 8-connected components; each is labelled 1 + the smallest row-major
+ * index (within its map) among its pixels, every other pixel 0.  Maps
+ * whose threshold has status != 0 get no pothole pixels. */
+sgm_status sgm_pothole_label_batch(const float *d2, const uint8_t *mask, int32_t width, int32_t height,
+                                   int32_t nimg, const sgm_pothole_threshold *result, int32_t *labels,
+                                   void *stream);
+
 /* Per-row window starts from the road model of eq. (3),
  *   f(u,v) = a0 + a1 (cos(phi) (v - cy) - sin(phi) (u - cx)),
  * with (cx, cy) = ((W-1)/2, (H-1)/2) the centre of the roll rotation.

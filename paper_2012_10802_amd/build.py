@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsgm.so")
 
-SOURCES = ["sgm_kernels.hip", "sgm_batch.hip", "sgm_window.hip", "cnn.hip", "road.hip", "sgm_api.cpp",
+SOURCES = ["sgm_kernels.hip", "sgm_batch.hip", "sgm_window.hip", "cnn.hip", "road.hip", "pothole.hip",
+           "sgm_api.cpp",
            "sgm_batch_api.cpp"]
 
 HIPCC_FLAGS = [

@@ -1,0 +1,326 @@
+// Pothole threshold and labelling on the transformed disparity map D2
+// (Sec. II-E, eq. (14), (15)), applied to D2 pixel by pixel (the paper
+// applies it to SLIC superpixels, which are not built here).
+//
+// Vectors g = [D2(p), sum of D2 over the 8-neighbourhood] of pixels whose
+// 3x3 neighbourhood is inside the image, selected and finite.  For a
+// threshold index k (t_r = lo + k b) a vector with bin indices (i, j) is in
+// region 1 when max(i, j) < k and in region 2 when min(i, j) >= k, so two
+// 1-D histograms of per-bin sums (count, g0, g1, |g|^2), one over max(i, j)
+// and one over min(i, j), give E2 of eq. (15) for every k by a prefix and a
+// suffix sum.
+//
+// Kernels:
+//   k_pd_clear    zero the histograms (a kernel, so a captured graph can
+//                 replay it);
+//   k_pd_hist     one thread per column of a strip of rows, a sliding 3x3
+//                 window (three loads per pixel), bins in float64; lanes
+//                 with the same bin are summed across the wave first (road
+//                 pixels crowd into few bins), then one LDS atomic per bin
+//                 and wave, one global atomic per bin and workgroup;
+//   k_pd_select   one workgroup per map: prefix / suffix sums, E2 per k,
+//                 the smallest k with minimal E2 among those with both
+//                 regions non-empty, t_s = t_r - delta_PD;
+//   k_pd_label_*  8-connected components of D2 < t_s by union-find with
+//                 atomicMin on parent links (parents always point to a
+//                 smaller index, so every find ends and the root of a
+//                 component is its smallest index): init, union with the
+//                 four preceding neighbours, flatten to the root, name.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "../../include/sgm.h"
+#include "sgm_internal.h"
+
+namespace sgm {
+namespace {
+
+constexpr int kPdThreads = 256;
+constexpr int kPdRows = 16;  // rows per histogram workgroup
+constexpr int kPdSums = 4;   // count, g0, g1, |g|^2
+
+__device__ inline double wave_sum_d(double x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+__device__ inline bool finite_f(float d) { return fabsf(d) <= 3.402823466e38f; }
+
+// Adds (1, g0, g1, sq) of every lane with key >= 0 to hist[key][.], one LDS
+// atomic per distinct key of the wave.  All lanes of the wave must call it.
+__device__ inline void wave_bin_add(double *hist, int key, double g0, double g1, double sq)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(key >= 0);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int k = __shfl(key, leader);
+        const bool mine = key == k;
+        const uint64_t same = __ballot(mine);
+        const double s0 = wave_sum_d(mine ? g0 : 0.0);
+        const double s1 = wave_sum_d(mine ? g1 : 0.0);
+        const double s2 = wave_sum_d(mine ? sq : 0.0);
+        if (lane == leader) {
+            atomicAdd(&hist[k * kPdSums + 0], (double)__popcll(same));
+            atomicAdd(&hist[k * kPdSums + 1], s0);
+            atomicAdd(&hist[k * kPdSums + 2], s1);
+            atomicAdd(&hist[k * kPdSums + 3], s2);
+        }
+        todo &= ~same;
+    }
+}
+
+__global__ void k_pd_clear(double *__restrict__ p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// Workgroup (bx, by, img): interior columns 1 + 256 bx + t, interior rows
+// [1 + kPdRows by, ...).  hist: [nimg][2][nbins][4] (max-index histogram,
+// then min-index histogram).
+__global__ __launch_bounds__(kPdThreads) void k_pd_hist(const float *__restrict__ d2,
+                                                        const uint8_t *__restrict__ mask, int W, int H,
+                                                        double lo, double b, int nbins,
+                                                        double *__restrict__ hist)
+{
+    extern __shared__ double sh[];  // [2][nbins][4]
+    const int img = blockIdx.z, t = threadIdx.x;
+    for (int i = t; i < 2 * nbins * kPdSums; i += kPdThreads) sh[i] = 0.0;
+    __syncthreads();
+
+    const size_t base = (size_t)img * W * H;
+    const int x = 1 + blockIdx.x * kPdThreads + t;
+    const bool col = x <= W - 2;
+    const int xc = col ? x : 1;  // loads of idle lanes stay in bounds (W, H >= 3 here)
+    const int v0 = 1 + blockIdx.y * kPdRows, v1 = min(H - 1, v0 + kPdRows);
+    float a[3][3];
+    bool s[3][3];
+    auto load_row = [&](int r, int v) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t at = base + (size_t)v * W + (xc - 1 + c);
+            a[r][c] = d2[at];
+            s[r][c] = (!mask || mask[at] != 0) && finite_f(a[r][c]);
+        }
+    };
+    load_row(0, v0 - 1);
+    load_row(1, v0);
+    const double b8 = 8.0 * b, lo8 = 8.0 * lo, top = (double)(nbins - 1);
+    for (int v = v0; v < v1; ++v) {
+        load_row(2, v + 1);
+        bool ok = col;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ok = ok && s[r][c];
+        int kmax = -1, kmin = -1;
+        double g0 = 0.0, g1 = 0.0, sq = 0.0;
+        if (ok) {
+            // neighbours in row-major order, summed left to right in float64
+            g1 = (double)a[0][0];
+            g1 += (double)a[0][1];
+            g1 += (double)a[0][2];
+            g1 += (double)a[1][0];
+            g1 += (double)a[1][2];
+            g1 += (double)a[2][0];
+            g1 += (double)a[2][1];
+            g1 += (double)a[2][2];
+            g0 = (double)a[1][1];
+            sq = g0 * g0 + g1 * g1;
+            const int i = (int)fmin(fmax(floor((g0 - lo) / b), 0.0), top);
+            const int j = (int)fmin(fmax(floor((g1 - lo8) / b8), 0.0), top);
+            kmax = max(i, j);
+            kmin = nbins + min(i, j);
+        }
+        wave_bin_add(sh, kmax, g0, g1, sq);
+        wave_bin_add(sh, kmin, g0, g1, sq);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a[0][c] = a[1][c];
+            s[0][c] = s[1][c];
+            a[1][c] = a[2][c];
+            s[1][c] = s[2][c];
+        }
+    }
+    __syncthreads();
+    double *gh = hist + (size_t)img * 2 * nbins * kPdSums;
+    for (int i = t; i < 2 * nbins; i += kPdThreads)
+        if (sh[i * kPdSums] != 0.0)
+            for (int q = 0; q < kPdSums; ++q) atomicAdd(&gh[i * kPdSums + q], sh[i * kPdSums + q]);
+}
+
+__device__ inline double region_e2(const double *r)
+{
+    return r[0] > 0.0 ? r[3] - (r[1] * r[1] + r[2] * r[2]) / r[0] : 0.0;
+}
+
+// One workgroup per map; thread 0 scans (nbins <= 512).  suffix: LDS
+// [nbins + 1][4] of the min-index histogram summed from the top.
+__global__ __launch_bounds__(64) void k_pd_select(const double *__restrict__ hist, int nbins, double lo, double b,
+                                                  double delta_pd, sgm_pothole_threshold *__restrict__ out,
+                                                  double *__restrict__ curve)
+{
+    extern __shared__ double suf[];
+    const int img = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    const double *h1 = hist + (size_t)img * 2 * nbins * kPdSums, *h2 = h1 + (size_t)nbins * kPdSums;
+    for (int q = 0; q < kPdSums; ++q) suf[nbins * kPdSums + q] = 0.0;
+    for (int k = nbins - 1; k >= 0; --k)
+        for (int q = 0; q < kPdSums; ++q) suf[k * kPdSums + q] = suf[(k + 1) * kPdSums + q] + h2[k * kPdSums + q];
+    const double nan = __builtin_nan("");
+    double pre[kPdSums] = {0.0, 0.0, 0.0, 0.0};
+    int best = 0;
+    double best_e = 0.0, bn1 = 0.0, bn2 = 0.0;
+    double *cv = curve ? curve + (size_t)img * (nbins + 1) : nullptr;
+    if (cv) cv[0] = cv[nbins] = nan;
+    for (int k = 1; k < nbins; ++k) {
+        for (int q = 0; q < kPdSums; ++q) pre[q] += h1[(k - 1) * kPdSums + q];
+        const double *r2 = suf + k * kPdSums;
+        const double e = region_e2(pre) + region_e2(r2);
+        if (cv) cv[k] = e;
+        if (pre[0] > 0.0 && r2[0] > 0.0 && (best == 0 || e < best_e)) {
+            best = k;
+            best_e = e;
+            bn1 = pre[0];
+            bn2 = r2[0];
+        }
+    }
+    sgm_pothole_threshold r;
+    r.k = best;
+    r.status = best ? 0 : 1;
+    r.t_r = best ? lo + best * b : nan;
+    r.t_s = best ? r.t_r - delta_pd : nan;
+    r.e2 = best ? best_e : nan;
+    r.n1 = bn1;
+    r.n2 = bn2;
+    out[img] = r;
+}
+
+__device__ inline int pd_find(const int32_t *lab, int x)
+{
+    int p = lab[x];
+    while (p != x) {
+        x = p;
+        p = lab[x];
+    }
+    return x;
+}
+
+__global__ void k_pd_label_init(const float *__restrict__ d2, const uint8_t *__restrict__ mask, int W, int H,
+                                const sgm_pothole_threshold *__restrict__ thr, int32_t *__restrict__ lab)
+{
+    const int img = blockIdx.y;
+    const int n = W * H;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const size_t at = (size_t)img * n + p;
+    const sgm_pothole_threshold r = thr[img];
+    const float d = d2[at];
+    const bool fg = r.status == 0 && (!mask || mask[at] != 0) && finite_f(d) && (double)d < r.t_s;
+    lab[at] = fg ? p : -1;
+}
+
+__global__ void k_pd_label_union(int W, int H, int32_t *__restrict__ lab_all)
+{
+    const int img = blockIdx.y;
+    const int n = W * H;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int32_t *lab = lab_all + (size_t)img * n;
+    if (lab[p] < 0) return;
+    const int y = p / W, x = p - y * W;
+    // the four neighbours that precede p in row-major order
+    const int dx[4] = {-1, -1, 0, 1}, dy[4] = {0, -1, -1, -1};
+    for (int e = 0; e < 4; ++e) {
+        const int xx = x + dx[e], yy = y + dy[e];
+        if (xx < 0 || xx >= W || yy < 0) continue;
+        const int q = yy * W + xx;
+        if (lab[q] < 0) continue;
+        int a = pd_find(lab, p), c = pd_find(lab, q);
+        // link the larger root under the smaller; a failed link (the root
+        // gained a parent meanwhile) retries from the new, smaller value
+        while (a != c) {
+            if (a < c) {
+                const int old = atomicMin(&lab[c], a);
+                if (old == c) break;
+                c = pd_find(lab, old);
+            } else {
+                const int old = atomicMin(&lab[a], c);
+                if (old == a) break;
+                a = pd_find(lab, old);
+            }
+        }
+    }
+}
+
+// Points every foreground pixel at its root.  Entries only ever move to
+// another ancestor of the same root, so concurrent finds stay on the chain.
+__global__ void k_pd_label_flatten(int W, int H, int32_t *__restrict__ lab_all)
+{
+    const int img = blockIdx.y;
+    const int n = W * H;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int32_t *lab = lab_all + (size_t)img * n;
+    if (lab[p] >= 0) lab[p] = pd_find(lab, p);
+}
+
+// Final names: root + 1 on the foreground, 0 (from -1) elsewhere.  A kernel
+// of its own: no find may run while the names change.
+__global__ void k_pd_label_name(size_t n, int32_t *__restrict__ lab)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        lab[i] += 1;
+}
+
+}  // namespace
+
+size_t pothole_workspace_bytes(int nbins, int nimg)
+{
+    return (size_t)nimg * 2 * nbins * kPdSums * sizeof(double);
+}
+
+hipError_t launch_pothole_threshold(const float *d2, const uint8_t *mask, int W, int H, int nimg, double lo,
+                                    double b, int nbins, double delta_pd, sgm_pothole_threshold *out,
+                                    double *curve, void *ws, hipStream_t s)
+{
+    double *hist = static_cast<double *>(ws);
+    const size_t n = (size_t)nimg * 2 * nbins * kPdSums;
+    k_pd_clear<<<(unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), 256, 0, s>>>(hist, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (W >= 3 && H >= 3) {
+        const dim3 grid((W - 2 + kPdThreads - 1) / kPdThreads, (H - 2 + kPdRows - 1) / kPdRows, nimg);
+        k_pd_hist<<<grid, kPdThreads, 2 * nbins * kPdSums * sizeof(double), s>>>(d2, mask, W, H, lo, b, nbins,
+                                                                                 hist);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_pd_select<<<nimg, 64, (nbins + 1) * kPdSums * sizeof(double), s>>>(hist, nbins, lo, b, delta_pd, out, curve);
+    return hipGetLastError();
+}
+
+hipError_t launch_pothole_label(const float *d2, const uint8_t *mask, int W, int H, int nimg,
+                                const sgm_pothole_threshold *thr, int32_t *labels, hipStream_t s)
+{
+    const int n = W * H;
+    const dim3 grid((n + 255) / 256, nimg);
+    k_pd_label_init<<<grid, 256, 0, s>>>(d2, mask, W, H, thr, labels);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_pd_label_union<<<grid, 256, 0, s>>>(W, H, labels);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_pd_label_flatten<<<grid, 256, 0, s>>>(W, H, labels);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t total = (size_t)n * nimg;
+    k_pd_label_name<<<(unsigned)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096), 256, 0, s>>>(total, labels);
+    return hipGetLastError();
+}
+
+}  // namespace sgm

@@ -551,6 +551,55 @@ sgm_status sgm_disparity_transform_batch(const float *disp, const sgm_road_fit *
     return e == hipSuccess ? SGM_OK : hip_fail(e, "disparity transform launch");
 }
 
+sgm_status sgm_pothole_workspace_size(int32_t nbins, int32_t nimg, size_t *bytes)
+{
+    if (!bytes) return fail(SGM_ERR_INVALID, "bytes is NULL");
+    if (nbins < 2 || nbins > 512) return fail(SGM_ERR_INVALID, "nbins %d not in [2, 512]", nbins);
+    if (nimg < 1 || nimg > 65535) return fail(SGM_ERR_INVALID, "nimg %d not in [1, 65535]", nimg);
+    *bytes = sgm::pothole_workspace_bytes(nbins, nimg);
+    return SGM_OK;
+}
+
+sgm_status sgm_pothole_threshold_batch(const float *d2, const uint8_t *mask, int32_t W, int32_t H, int32_t nimg,
+                                       double lo, double hi, int32_t nbins, double delta_pd,
+                                       sgm_pothole_threshold *result, double *e2_curve, void *ws, size_t ws_bytes,
+                                       void *stream)
+{
+    if (!d2 || !result) return fail(SGM_ERR_INVALID, "d2 and result must not be NULL");
+    sgm_status st = check_maps(W, H, nimg);
+    if (st != SGM_OK) return st;
+    if (nbins < 2 || nbins > 512) return fail(SGM_ERR_INVALID, "nbins %d not in [2, 512]", nbins);
+    if (!isfinite(lo) || !isfinite(hi) || !(lo < hi)) return fail(SGM_ERR_INVALID, "need finite lo < hi");
+    if (!isfinite(delta_pd)) return fail(SGM_ERR_INVALID, "delta_pd must be finite");
+    const double b = (hi - lo) / nbins;
+    if (!(b > 0.0) || !isfinite(8.0 * b) || !isfinite(8.0 * lo))
+        return fail(SGM_ERR_INVALID, "bin width out of range");
+    if (!ws) return fail(SGM_ERR_INVALID, "workspace is NULL");
+    if (!is_aligned(ws, 256)) return fail(SGM_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (!is_aligned(d2, 4) || !is_aligned(result, 8) || !is_aligned(e2_curve, 8))
+        return fail(SGM_ERR_INVALID, "d2, result or e2_curve misaligned");
+    const size_t need = sgm::pothole_workspace_bytes(nbins, nimg);
+    if (ws_bytes < need)
+        return fail(SGM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
+    hipError_t e = sgm::launch_pothole_threshold(d2, mask, W, H, nimg, lo, b, nbins, delta_pd, result, e2_curve, ws,
+                                                 (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "pothole threshold launch");
+}
+
+sgm_status sgm_pothole_label_batch(const float *d2, const uint8_t *mask, int32_t W, int32_t H, int32_t nimg,
+                                   const sgm_pothole_threshold *result, int32_t *labels, void *stream)
+{
+    if (!d2 || !result || !labels) return fail(SGM_ERR_INVALID, "d2, result and labels must not be NULL");
+    sgm_status st = check_maps(W, H, nimg);
+    if (st != SGM_OK) return st;
+    if (!is_aligned(d2, 4) || !is_aligned(result, 8) || !is_aligned(labels, 4))
+        return fail(SGM_ERR_INVALID, "d2, result or labels misaligned");
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
+    hipError_t e = sgm::launch_pothole_label(d2, mask, W, H, nimg, result, labels, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "pothole label launch");
+}
+
 sgm_status sgm_window_from_road(double a0, double a1, double phi, int32_t W, int32_t H, int32_t w, int32_t mode,
                                 double delta, int32_t *d_lo)
 {

@@ -129,4 +129,14 @@ hipError_t launch_road_window(const sgm_road_fit *fit, int W, int H, int nimg, i
 hipError_t launch_disp_transform(const float *disp, const sgm_road_fit *fit, int W, int H, int nimg,
                                  double delta, float *out, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// pothole threshold and labelling
+
+size_t pothole_workspace_bytes(int nbins, int nimg);
+hipError_t launch_pothole_threshold(const float *d2, const uint8_t *mask, int W, int H, int nimg, double lo,
+                                    double b, int nbins, double delta_pd, sgm_pothole_threshold *out,
+                                    double *curve, void *ws, hipStream_t s);
+hipError_t launch_pothole_label(const float *d2, const uint8_t *mask, int W, int H, int nimg,
+                                const sgm_pothole_threshold *thr, int32_t *labels, hipStream_t s);
+
 }  // namespace sgm

@@ -110,6 +110,9 @@ def _load_library():
         "sgm_road_fit_batch": [P, P, I, I, I, ctypes.c_float, D, P, P, S, P],
         "sgm_road_window_batch": [P, I, I, I, I, I, D, D, P, P],
         "sgm_disparity_transform_batch": [P, P, I, I, I, D, P, P],
+        "sgm_pothole_workspace_size": [I, I, ctypes.POINTER(S)],
+        "sgm_pothole_threshold_batch": [P, P, I, I, I, D, D, I, D, P, P, P, S, P],
+        "sgm_pothole_label_batch": [P, P, I, I, I, P, P, P],
         "sgm_status_str": [I],
         "sgm_last_error": [],
     }
@@ -304,6 +307,69 @@ def disparity_transform(disp, fit, delta_dt, out=None, stream=None):
     _check(_lib.sgm_disparity_transform_batch(_ptr(d), _ptr(fit), W, H, n, float(delta_dt), _ptr(out),
                                               _stream(stream)), "sgm_disparity_transform_batch")
     return out
+
+
+# ---------------------------------------------------------------------------
+# pothole threshold and labelling (Sec. II-E, eq. (14), (15))
+
+POTHOLE_WORDS = 6  # one sgm_pothole_threshold = 6 float64 words (48 bytes)
+
+
+def pothole_workspace_size(nbins, nimg=1) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.sgm_pothole_workspace_size(int(nbins), int(nimg), ctypes.byref(n)), "sgm_pothole_workspace_size")
+    return int(n.value)
+
+
+def pothole_threshold(d2, lo, hi, nbins, delta_pd, mask=None, result=None, curve=False, workspace=None,
+                      stream=None):
+    """Threshold search on float32 device maps [H, W] or [n, H, W].  Returns
+    (result float64 [n, 6] device tensor of sgm_pothole_threshold records,
+    E2 curves float64 [n, nbins + 1] or None)."""
+    d = _maps(d2, torch.float32, "d2")
+    n, H, W = d.shape
+    if mask is not None:
+        mask = _maps(mask, torch.uint8, "mask")
+        if tuple(mask.shape) != (n, H, W):
+            raise ValueError("mask must have the shape of d2")
+    if result is None:
+        result = torch.empty((n, POTHOLE_WORDS), dtype=torch.float64, device=d.device)
+    _need(result, torch.float64, (n, POTHOLE_WORDS), "result")
+    cv = torch.empty((n, int(nbins) + 1), dtype=torch.float64, device=d.device) if curve else None
+    if workspace is None:
+        workspace = torch.empty(pothole_workspace_size(nbins, n), dtype=torch.uint8, device=d.device)
+    _need(workspace, torch.uint8, None, "workspace")
+    _check(_lib.sgm_pothole_threshold_batch(_ptr(d), _ptr(mask), W, H, n, float(lo), float(hi), int(nbins),
+                                            float(delta_pd), _ptr(result), _ptr(cv), _ptr(workspace),
+                                            workspace.numel(), _stream(stream)), "sgm_pothole_threshold_batch")
+    return result, cv
+
+
+def pothole_threshold_dicts(result):
+    """Host view of pothole_threshold results (synchronises)."""
+    h = result.detach().cpu()
+    iv = h.view(torch.int32)
+    out = []
+    for i in range(h.shape[0]):
+        rec = {k: float(h[i, j]) for j, k in enumerate(("t_r", "t_s", "e2", "n1", "n2"))}
+        rec["k"], rec["status"] = int(iv[i, 10]), int(iv[i, 11])
+        out.append(rec)
+    return out
+
+
+def pothole_labels(d2, result, mask=None, labels=None, stream=None):
+    """8-connected pothole labels int32 [n, H, W] (1 + smallest index, 0 off)."""
+    d = _maps(d2, torch.float32, "d2")
+    n, H, W = d.shape
+    _need(result, torch.float64, (n, POTHOLE_WORDS), "result")
+    if mask is not None:
+        mask = _maps(mask, torch.uint8, "mask")
+    if labels is None:
+        labels = torch.empty((n, H, W), dtype=torch.int32, device=d.device)
+    _need(labels, torch.int32, (n, H, W), "labels")
+    _check(_lib.sgm_pothole_label_batch(_ptr(d), _ptr(mask), W, H, n, _ptr(result), _ptr(labels),
+                                        _stream(stream)), "sgm_pothole_label_batch")
+    return labels
 
 
 class Matcher:

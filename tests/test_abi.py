@@ -272,3 +272,34 @@ def test_road_calls_validate_before_launch():
     assert lib.sgm_debug_inject_fault(1) == 0
     assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, d, d, ws, None) == -3
     assert lib.sgm_debug_inject_fault(0) == 0
+
+
+def test_pothole_calls_validate_before_launch():
+    """Threshold / labelling calls check bins, range, alignment and
+    workspace before anything is enqueued (dummy pointers never touched)."""
+    import ctypes
+    from paper_2012_10802_amd import sgm
+    lib = sgm.library()
+    d = ctypes.c_void_p(1 << 20)
+    n = ctypes.c_size_t()
+    assert lib.sgm_pothole_workspace_size(128, 16, ctypes.byref(n)) == 0 and n.value == 16 * 2 * 128 * 4 * 8
+    assert lib.sgm_pothole_workspace_size(1, 16, ctypes.byref(n)) == -1
+    assert lib.sgm_pothole_workspace_size(513, 16, ctypes.byref(n)) == -1
+    ws = sgm.pothole_workspace_size(64, 2)
+    T = lib.sgm_pothole_threshold_batch
+    assert T(None, None, 64, 48, 2, 0.0, 16.0, 64, 2.36, d, None, d, ws, None) == -1
+    assert T(d, None, 64, 48, 2, 16.0, 16.0, 64, 2.36, d, None, d, ws, None) == -1
+    assert T(d, None, 64, 48, 2, 0.0, float("inf"), 64, 2.36, d, None, d, ws, None) == -1
+    assert T(d, None, 64, 48, 2, 0.0, 16.0, 1, 2.36, d, None, d, ws, None) == -1
+    assert T(d, None, 64, 48, 2, 0.0, 16.0, 64, float("nan"), d, None, d, ws, None) == -1
+    assert T(d, None, 64, 48, 2, 0.0, 16.0, 64, 2.36, d, None, d, ws - 8, None) == -4
+    assert T(d, None, 64, 48, 2, 0.0, 16.0, 64, 2.36, d, None, ctypes.c_void_p((1 << 20) + 64), ws, None) == -1
+    assert T(d, None, 64, 48, 2, 0.0, 16.0, 64, 2.36, d, ctypes.c_void_p((1 << 20) + 4), d, ws, None) == -1
+    assert T(d, None, 0, 48, 2, 0.0, 16.0, 64, 2.36, d, None, d, ws, None) == -1
+    L = lib.sgm_pothole_label_batch
+    assert L(d, None, 64, 48, 2, None, d, None) == -1
+    assert L(d, None, 64, 48, 2, d, ctypes.c_void_p((1 << 20) + 2), None) == -1
+    assert L(d, None, 64, 48, 70000, d, d, None) == -2
+    assert lib.sgm_debug_inject_fault(1) == 0
+    assert L(d, None, 64, 48, 2, d, d, None) == -3
+    assert lib.sgm_debug_inject_fault(0) == 0
