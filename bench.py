@@ -312,6 +312,7 @@ def road_model_leg(args, log=None):
     L = torch.empty((n, H, W), dtype=torch.uint8, device=dev)
     R = torch.empty_like(L)
     mask = torch.empty((n, H, W), dtype=torch.uint8, device=dev)
+    holes = torch.empty((n, H, W), dtype=torch.bool, device=dev)
     truth = []
     for i in range(n):
         seed = 3_000_000 + i
@@ -321,6 +322,10 @@ def road_model_leg(args, log=None):
         R[i].copy_(r)
         cols = torch.arange(W, device=dev)[None, :]
         mask[i].copy_((road & (cols - gt >= 4)).to(torch.uint8))
+        a0, a1, phi = sc.road_params
+        rows = torch.arange(H, device=dev, dtype=torch.float64)[:, None]
+        plane = a0 + a1 * (math.cos(phi) * (rows - sc.cy) - math.sin(phi) * (cols.double() - sc.cx))
+        holes[i].copy_(road & (gt.double() < plane - 1e-3))  # the generator's depressions
         truth.append(sc.road_params)
     batch = sgm.Batch([dict(left=L[i], right=R[i], ndisp=c["ndisp"]) for i in range(n)], census=c["census"],
                       npaths=c["npaths"], p1=c["p1"], p2=c["p2"], device=dev)
@@ -332,6 +337,11 @@ def road_model_leg(args, log=None):
     d_lo = torch.empty((n, H), dtype=torch.int32, device=dev)
     d2 = torch.empty_like(disp)
     torch.cuda.synchronize()
+
+    nbins, delta_pd = 128, 2.36
+    pd_res = torch.empty((n, sgm.POTHOLE_WORDS), dtype=torch.float64, device=dev)
+    pd_ws = torch.empty(sgm.pothole_workspace_size(nbins, n), dtype=torch.uint8, device=dev)
+    labels = torch.empty((n, H, W), dtype=torch.int32, device=dev)
 
     def once(ev=None):
         if ev:
@@ -345,17 +355,38 @@ def road_model_leg(args, log=None):
         sgm.disparity_transform(disp, fit, 10.0, out=d2)
         if ev:
             ev[3].record()
+        # eq. (14), (15) on D2 (road range 10 +- 8 px), then the components
+        sgm.pothole_threshold(d2, 2.0, 18.0, nbins, delta_pd, mask=mask, result=pd_res, workspace=pd_ws)
+        if ev:
+            ev[4].record()
+        sgm.pothole_labels(d2, pd_res, mask=mask, labels=labels)
+        if ev:
+            ev[5].record()
 
     for _ in range(3):
         once()
     reps = 20
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(reps)]
     torch.cuda.synchronize()
     for e in events:
         once(e)
     torch.cuda.synchronize()
-    per = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(3)] for e in events])
-    fit_ms, win_ms, tr_ms = (float(x) for x in per.mean(axis=0))
+    per = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(5)] for e in events])
+    fit_ms, win_ms, tr_ms, thr_ms, lab_ms = (float(x) for x in per.mean(axis=0))
+    pd_stat = sgm.pothole_threshold_dicts(pd_res)
+    detection = []
+    for dpd in (delta_pd, 1.0, 0.5):  # the paper's tolerance, then smaller ones for shallower potholes
+        res = pd_res.clone()
+        res[:, 1] = res[:, 0] - dpd  # t_s = t_r - delta_PD
+        lab = sgm.pothole_labels(d2, res, mask=mask)
+        found = lab > 0
+        tp = int((found & holes).sum())
+        prec = tp / max(1, int(found.sum()))
+        rec = tp / max(1, int(holes.sum()))
+        detection.append({"delta_pd": dpd, "pixel_precision": round(prec, 4), "pixel_recall": round(rec, 4),
+                          "pixel_f1": round(2 * prec * rec / max(1e-12, prec + rec), 4),
+                          "components_mean": round(float(np.mean(
+                              [torch.unique(lab[i][lab[i] > 0]).numel() for i in range(n)])), 1)})
     copy_calibration(args, dev)
     px = n * W * H
     fit_gbs = px * 5 / (fit_ms * 1e-3) / 1e9
@@ -365,8 +396,8 @@ def road_model_leg(args, log=None):
     da1 = [abs(f["a1"] - t[1]) / t[1] for f, t in zip(fits, truth)]
     da0 = [abs(f["a0"] - t[0]) for f, t in zip(fits, truth)]
     if log:
-        log("road model: fit %.4f ms, windows %.4f ms, transformation %.4f ms per batch of %d"
-            % (fit_ms, win_ms, tr_ms, n))
+        log("road model: fit %.4f ms, windows %.4f ms, transformation %.4f ms, pothole threshold %.4f ms, "
+            "labels %.4f ms per batch of %d" % (fit_ms, win_ms, tr_ms, thr_ms, lab_ms, n))
     return {
         "maps": n, "width": W, "height": H,
         "inputs": "full-range SGM disparity (0-191, census 7x7, 8 paths) of generated road pairs; "
@@ -379,6 +410,14 @@ def road_model_leg(args, log=None):
                           "frac": round(tr_gbs / HBM_PEAK_GBS, 4)},
         "fit_error": {"phi_max_deg": round(math.degrees(max(dphi)), 5),
                       "a1_max_rel": round(max(da1), 6), "a0_max_px": round(max(da0), 4)},
+        "pothole": {"threshold_ms": round(thr_ms, 4), "label_ms": round(lab_ms, 4),
+                    "threshold_hbm": {"bytes_per_pixel": 5,
+                                      "achieved": round(px * 5 / (thr_ms * 1e-3) / 1e9, 1), "unit": "GB/s"},
+                    "nbins": nbins, "delta_pd": delta_pd, "range": [2.0, 18.0],
+                    "t_r_mean": round(float(np.mean([r["t_r"] for r in pd_stat])), 4),
+                    "detection": detection,
+                    "note": "pixel-level thresholding of D2 (no superpixels); ground truth = the "
+                            "generator's depressions on road pixels"},
     }
 
 

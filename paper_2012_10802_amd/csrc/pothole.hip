@@ -14,10 +14,11 @@
 //   k_pd_clear    zero the histograms (a kernel, so a captured graph can
 //                 replay it);
 //   k_pd_hist     one thread per column of a strip of rows, a sliding 3x3
-//                 window (three loads per pixel), bins in float64; lanes
-//                 with the same bin are summed across the wave first (road
-//                 pixels crowd into few bins), then one LDS atomic per bin
-//                 and wave, one global atomic per bin and workgroup;
+//                 window (three loads per pixel, the next row in flight),
+//                 bins in float64, sums of a run of equal bins kept in
+//                 registers, float64 LDS atomics into several copies of the
+//                 histograms (road pixels crowd into few bins), one global
+//                 atomic per bin and workgroup;
 //   k_pd_select   one workgroup per map: prefix / suffix sums, E2 per k,
 //                 the smallest k with minimal E2 among those with both
 //                 regions non-empty, t_s = t_r - delta_PD;
@@ -37,41 +38,57 @@ namespace sgm {
 namespace {
 
 constexpr int kPdThreads = 256;
-constexpr int kPdRows = 16;  // rows per histogram workgroup
+constexpr int kPdRows = 32;  // rows per histogram workgroup
 constexpr int kPdSums = 4;   // count, g0, g1, |g|^2
-
-__device__ inline double wave_sum_d(double x)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
-    return x;
-}
+constexpr int kPdCopies = 4;              // most LDS histogram copies per workgroup
+constexpr size_t kPdLds = 65536;          // LDS bytes a workgroup may take
 
 __device__ inline bool finite_f(float d) { return fabsf(d) <= 3.402823466e38f; }
 
-// Adds (1, g0, g1, sq) of every lane with key >= 0 to hist[key][.], one LDS
-// atomic per distinct key of the wave.  All lanes of the wave must call it.
-__device__ inline void wave_bin_add(double *hist, int key, double g0, double g1, double sq)
+// floor(x / d) clamped to [0, top], with x / d the correctly rounded float64
+// quotient: the product with 1/d is within a few ulps of it, so its floor
+// is taken unless the product lies that close to an integer, where the
+// division itself decides.
+__device__ inline int bin_index(double x, double d, double inv_d, double top)
 {
-    const int lane = threadIdx.x & 63;
-    uint64_t todo = __ballot(key >= 0);
-    while (todo) {
-        const int leader = __ffsll((unsigned long long)todo) - 1;
-        const int k = __shfl(key, leader);
-        const bool mine = key == k;
-        const uint64_t same = __ballot(mine);
-        const double s0 = wave_sum_d(mine ? g0 : 0.0);
-        const double s1 = wave_sum_d(mine ? g1 : 0.0);
-        const double s2 = wave_sum_d(mine ? sq : 0.0);
-        if (lane == leader) {
-            atomicAdd(&hist[k * kPdSums + 0], (double)__popcll(same));
-            atomicAdd(&hist[k * kPdSums + 1], s0);
-            atomicAdd(&hist[k * kPdSums + 2], s1);
-            atomicAdd(&hist[k * kPdSums + 3], s2);
-        }
-        todo &= ~same;
-    }
+    const double q = x * inv_d;
+    const double f = floor(q);
+    const double e = 8.0 * 2.220446049250313e-16 * fmax(fabs(q), 1.0);
+    const double qq = (q - f < e || f + 1.0 - q < e) ? x / d : q;
+    return (int)fmin(fmax(floor(qq), 0.0), top);
 }
+
+// One pending (key, sums) entry per histogram and thread: consecutive
+// pixels of a column often share a bin, so their sums are added in
+// registers and reach LDS only when the key changes.
+struct BinCache {
+    int key = -1;
+    double c = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    __device__ void add(double *hist, int k, double g0, double g1, double sq)
+    {
+        if (k != key) {
+            flush(hist);
+            key = k;
+        }
+        if (k >= 0) {
+            c += 1.0;
+            s0 += g0;
+            s1 += g1;
+            s2 += sq;
+        }
+    }
+    __device__ void flush(double *hist)
+    {
+        if (key >= 0) {
+            atomicAdd(&hist[key * kPdSums + 0], c);
+            atomicAdd(&hist[key * kPdSums + 1], s0);
+            atomicAdd(&hist[key * kPdSums + 2], s1);
+            atomicAdd(&hist[key * kPdSums + 3], s2);
+        }
+        key = -1;
+        c = s0 = s1 = s2 = 0.0;
+    }
+};
 
 __global__ void k_pd_clear(double *__restrict__ p, size_t n)
 {
@@ -81,42 +98,51 @@ __global__ void k_pd_clear(double *__restrict__ p, size_t n)
 
 // Workgroup (bx, by, img): interior columns 1 + 256 bx + t, interior rows
 // [1 + kPdRows by, ...).  hist: [nimg][2][nbins][4] (max-index histogram,
-// then min-index histogram).
+// then min-index histogram).  The workgroup keeps `copies` LDS copies of
+// both histograms, lane l adding to copy l % copies: road pixels crowd into
+// few bins, and the copies cut the lanes that collide on one LDS address.
 __global__ __launch_bounds__(kPdThreads) void k_pd_hist(const float *__restrict__ d2,
                                                         const uint8_t *__restrict__ mask, int W, int H,
-                                                        double lo, double b, int nbins,
+                                                        double lo, double b, int nbins, int copies,
                                                         double *__restrict__ hist)
 {
-    extern __shared__ double sh[];  // [2][nbins][4]
+    extern __shared__ double sh[];  // [copies][2][nbins][4]
     const int img = blockIdx.z, t = threadIdx.x;
-    for (int i = t; i < 2 * nbins * kPdSums; i += kPdThreads) sh[i] = 0.0;
+    const int per = 2 * nbins * kPdSums;
+    for (int i = t; i < copies * per; i += kPdThreads) sh[i] = 0.0;
     __syncthreads();
+    double *mine = sh + (size_t)((t & 63) % copies) * per;
 
     const size_t base = (size_t)img * W * H;
     const int x = 1 + blockIdx.x * kPdThreads + t;
     const bool col = x <= W - 2;
     const int xc = col ? x : 1;  // loads of idle lanes stay in bounds (W, H >= 3 here)
     const int v0 = 1 + blockIdx.y * kPdRows, v1 = min(H - 1, v0 + kPdRows);
-    float a[3][3];
-    bool s[3][3];
+    float a[4][3];
+    uint8_t m[4][3];  // mask bytes (1 without a mask); used only once the row is binned
     auto load_row = [&](int r, int v) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const size_t at = base + (size_t)v * W + (xc - 1 + c);
             a[r][c] = d2[at];
-            s[r][c] = (!mask || mask[at] != 0) && finite_f(a[r][c]);
+            m[r][c] = mask ? mask[at] : (uint8_t)1;
         }
     };
+    // rows v - 1, v, v + 1 in a[0..2]; row v + 2 is loaded into a[3] while
+    // row v is binned
     load_row(0, v0 - 1);
     load_row(1, v0);
+    load_row(2, v0 + 1);
     const double b8 = 8.0 * b, lo8 = 8.0 * lo, top = (double)(nbins - 1);
+    const double inv_b = 1.0 / b, inv_b8 = 1.0 / b8;
+    BinCache cmax, cmin;
     for (int v = v0; v < v1; ++v) {
-        load_row(2, v + 1);
+        load_row(3, min(v + 2, H - 1));
         bool ok = col;
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ok = ok && s[r][c];
+            for (int c = 0; c < 3; ++c) ok = ok & (m[r][c] != 0) & finite_f(a[r][c]);
         int kmax = -1, kmin = -1;
         double g0 = 0.0, g1 = 0.0, sq = 0.0;
         if (ok) {
@@ -131,26 +157,34 @@ __global__ __launch_bounds__(kPdThreads) void k_pd_hist(const float *__restrict_
             g1 += (double)a[2][2];
             g0 = (double)a[1][1];
             sq = g0 * g0 + g1 * g1;
-            const int i = (int)fmin(fmax(floor((g0 - lo) / b), 0.0), top);
-            const int j = (int)fmin(fmax(floor((g1 - lo8) / b8), 0.0), top);
+            const int i = bin_index(g0 - lo, b, inv_b, top);
+            const int j = bin_index(g1 - lo8, b8, inv_b8, top);
             kmax = max(i, j);
             kmin = nbins + min(i, j);
         }
-        wave_bin_add(sh, kmax, g0, g1, sq);
-        wave_bin_add(sh, kmin, g0, g1, sq);
+        cmax.add(mine, kmax, g0, g1, sq);
+        cmin.add(mine, kmin, g0, g1, sq);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             a[0][c] = a[1][c];
-            s[0][c] = s[1][c];
+            m[0][c] = m[1][c];
             a[1][c] = a[2][c];
-            s[1][c] = s[2][c];
+            m[1][c] = m[2][c];
+            a[2][c] = a[3][c];
+            m[2][c] = m[3][c];
         }
     }
+    cmax.flush(mine);
+    cmin.flush(mine);
     __syncthreads();
-    double *gh = hist + (size_t)img * 2 * nbins * kPdSums;
-    for (int i = t; i < 2 * nbins; i += kPdThreads)
-        if (sh[i * kPdSums] != 0.0)
-            for (int q = 0; q < kPdSums; ++q) atomicAdd(&gh[i * kPdSums + q], sh[i * kPdSums + q]);
+    double *gh = hist + (size_t)img * per;
+    for (int i = t; i < 2 * nbins; i += kPdThreads) {
+        double tot[kPdSums] = {0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < copies; ++c)
+            for (int q = 0; q < kPdSums; ++q) tot[q] += sh[(size_t)c * per + i * kPdSums + q];
+        if (tot[0] != 0.0)
+            for (int q = 0; q < kPdSums; ++q) atomicAdd(&gh[i * kPdSums + q], tot[q]);
+    }
 }
 
 __device__ inline double region_e2(const double *r)
@@ -158,19 +192,29 @@ __device__ inline double region_e2(const double *r)
     return r[0] > 0.0 ? r[3] - (r[1] * r[1] + r[2] * r[2]) / r[0] : 0.0;
 }
 
-// One workgroup per map; thread 0 scans (nbins <= 512).  suffix: LDS
-// [nbins + 1][4] of the min-index histogram summed from the top.
+// One workgroup per map: the 64 threads copy both histograms to LDS, then
+// thread 0 scans (nbins <= 512).  LDS: h1 [nbins][4], suffix sums of h2
+// [nbins + 1][4].
 __global__ __launch_bounds__(64) void k_pd_select(const double *__restrict__ hist, int nbins, double lo, double b,
                                                   double delta_pd, sgm_pothole_threshold *__restrict__ out,
                                                   double *__restrict__ curve)
 {
-    extern __shared__ double suf[];
+    extern __shared__ double lds[];
     const int img = blockIdx.x;
+    const int per = nbins * kPdSums;
+    double *h1 = lds, *suf = lds + per;
+    const double *g = hist + (size_t)img * 2 * per;
+    for (int i = threadIdx.x; i < 2 * per; i += 64) lds[i] = g[i];  // h1, then h2 where suf starts
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    const double *h1 = hist + (size_t)img * 2 * nbins * kPdSums, *h2 = h1 + (size_t)nbins * kPdSums;
-    for (int q = 0; q < kPdSums; ++q) suf[nbins * kPdSums + q] = 0.0;
+    // suffix sums in place over h2: suf[k] = sum of h2[k .. nbins - 1], suf[nbins] = 0
+    double run[kPdSums] = {0.0, 0.0, 0.0, 0.0};
     for (int k = nbins - 1; k >= 0; --k)
-        for (int q = 0; q < kPdSums; ++q) suf[k * kPdSums + q] = suf[(k + 1) * kPdSums + q] + h2[k * kPdSums + q];
+        for (int q = 0; q < kPdSums; ++q) {
+            run[q] += suf[k * kPdSums + q];
+            suf[k * kPdSums + q] = run[q];
+        }
+    for (int q = 0; q < kPdSums; ++q) suf[per + q] = 0.0;
     const double nan = __builtin_nan("");
     double pre[kPdSums] = {0.0, 0.0, 0.0, 0.0};
     int best = 0;
@@ -295,12 +339,15 @@ hipError_t launch_pothole_threshold(const float *d2, const uint8_t *mask, int W,
     if (e != hipSuccess) return e;
     if (W >= 3 && H >= 3) {
         const dim3 grid((W - 2 + kPdThreads - 1) / kPdThreads, (H - 2 + kPdRows - 1) / kPdRows, nimg);
-        k_pd_hist<<<grid, kPdThreads, 2 * nbins * kPdSums * sizeof(double), s>>>(d2, mask, W, H, lo, b, nbins,
-                                                                                 hist);
+        const size_t one = 2 * (size_t)nbins * kPdSums * sizeof(double);
+        int copies = 1;
+        while (copies < kPdCopies && 2 * copies * one <= kPdLds) copies *= 2;
+        k_pd_hist<<<grid, kPdThreads, copies * one, s>>>(d2, mask, W, H, lo, b, nbins, copies, hist);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    k_pd_select<<<nimg, 64, (nbins + 1) * kPdSums * sizeof(double), s>>>(hist, nbins, lo, b, delta_pd, out, curve);
+    k_pd_select<<<nimg, 64, (2 * nbins + 1) * kPdSums * sizeof(double), s>>>(hist, nbins, lo, b, delta_pd, out,
+                                                                              curve);
     return hipGetLastError();
 }
 
