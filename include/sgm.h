@@ -482,6 +482,40 @@ sgm_status sgm_pothole_label_batch(const float *d2, const uint8_t *mask, int32_t
                                    int32_t nimg, const sgm_pothole_threshold *result, int32_t *labels,
                                    void *stream);
 
+/* ------------------------------------------------------------------------
+ * Superpixels on D2 (SLIC, Sec. II-D) and the superpixel-mean map D3
+ * (Sec. II-E).
+ *
+ * Grid step S: K = ceil(W/S) * ceil(H/S) centres; centre k = j * ceil(W/S)
+ * + i starts at (min(i S + S/2, W-1), min(j S + S/2, H-1)) (S/2 rounded
+ * down) and moves to the first position of its 3x3 neighbourhood
+ * (row-major) whose gradient G = (v(x+1,y) - v(x-1,y))^2 +
+ * (v(x,y+1) - v(x,y-1))^2 (float64, coordinates clamped; +inf unless the
+ * four pixels are used) is strictly below G at the start.  A pixel is used
+ * when its mask entry is non-zero (mask NULL: all), its value is finite
+ * and |v| < 2048; unused pixels get label -1 and D3 NaN.  Each of `iters`
+ * rounds assigns every used pixel of grid cell (i, j) to the nearest of
+ * the centres of cells (i+di, j+dj), |di|, |dj| <= 1, in index order, by
+ * d = (v - v_c)^2 + ((x - x_c)^2 + (y - y_c)^2) w, w = (m / S)^2, float64
+ * without fused multiply-add, first smallest wins; then every centre with
+ * pixels moves to their mean position and mean value, the value mean taken
+ * over v rounded to multiples of 2^-20 and summed exactly.  Labels are the
+ * last assignment's centre indices; D3(p) = value of p's centre after the
+ * last update (float32).  The result does not depend on the order of any
+ * sum, so it is the same on every run.
+ *
+ * Buffers: maps float32 [nimg][H][W], mask uint8 [nimg][H][W] or NULL,
+ * labels int32 [nimg][H][W], d3 float32 [nimg][H][W], centres float64
+ * [nimg][K][3] (x, y, v after the last update); all device.
+ */
+sgm_status sgm_slic_workspace_size(int32_t width, int32_t height, int32_t S, int32_t nimg, size_t *bytes);
+/* 2 <= S <= 256, ceil(H/S) <= 65535, m finite and >= 0, 1 <= iters <= 100.
+ * workspace: device, 256-byte aligned, at least sgm_slic_workspace_size
+ * bytes. */
+sgm_status sgm_slic_batch(const float *d2, const uint8_t *mask, int32_t width, int32_t height, int32_t nimg,
+                          int32_t S, double m, int32_t iters, int32_t *labels, float *d3, double *centres,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
 /* Per-row window starts from the road model of eq. (3),
  *   f(u,v) = a0 + a1 (cos(phi) (v - cy) - sin(phi) (u - cx)),
  * with (cx, cy) = ((W-1)/2, (H-1)/2) the centre of the roll rotation.

@@ -600,6 +600,45 @@ sgm_status sgm_pothole_label_batch(const float *d2, const uint8_t *mask, int32_t
     return e == hipSuccess ? SGM_OK : hip_fail(e, "pothole label launch");
 }
 
+static sgm_status check_slic(int32_t W, int32_t H, int32_t S, int32_t nimg)
+{
+    sgm_status st = check_maps(W, H, nimg);
+    if (st != SGM_OK) return st;
+    if (S < 2 || S > 256) return fail(SGM_ERR_INVALID, "S %d not in [2, 256]", S);
+    if ((H + S - 1) / S > 65535) return fail(SGM_ERR_UNSUPPORTED, "more than 65535 rows of grid cells");
+    return SGM_OK;
+}
+
+sgm_status sgm_slic_workspace_size(int32_t W, int32_t H, int32_t S, int32_t nimg, size_t *bytes)
+{
+    if (!bytes) return fail(SGM_ERR_INVALID, "bytes is NULL");
+    sgm_status st = check_slic(W, H, S, nimg);
+    if (st != SGM_OK) return st;
+    *bytes = sgm::slic_workspace_bytes(W, H, S, nimg);
+    return SGM_OK;
+}
+
+sgm_status sgm_slic_batch(const float *d2, const uint8_t *mask, int32_t W, int32_t H, int32_t nimg, int32_t S,
+                          double m, int32_t iters, int32_t *labels, float *d3, double *centres, void *ws,
+                          size_t ws_bytes, void *stream)
+{
+    if (!d2 || !labels || !d3 || !centres) return fail(SGM_ERR_INVALID, "d2, labels, d3 and centres must not be NULL");
+    sgm_status st = check_slic(W, H, S, nimg);
+    if (st != SGM_OK) return st;
+    if (!isfinite(m) || m < 0.0) return fail(SGM_ERR_INVALID, "m must be finite and >= 0");
+    if (iters < 1 || iters > 100) return fail(SGM_ERR_INVALID, "iters %d not in [1, 100]", iters);
+    if (!ws) return fail(SGM_ERR_INVALID, "workspace is NULL");
+    if (!is_aligned(ws, 256)) return fail(SGM_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (!is_aligned(d2, 4) || !is_aligned(labels, 4) || !is_aligned(d3, 4) || !is_aligned(centres, 8))
+        return fail(SGM_ERR_INVALID, "d2, labels, d3 or centres misaligned");
+    const size_t need = sgm::slic_workspace_bytes(W, H, S, nimg);
+    if (ws_bytes < need)
+        return fail(SGM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
+    hipError_t e = sgm::launch_slic(d2, mask, W, H, nimg, S, m, iters, labels, d3, centres, ws, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "slic launch");
+}
+
 sgm_status sgm_window_from_road(double a0, double a1, double phi, int32_t W, int32_t H, int32_t w, int32_t mode,
                                 double delta, int32_t *d_lo)
 {

@@ -133,6 +133,9 @@ hipError_t launch_disp_transform(const float *disp, const sgm_road_fit *fit, int
 // pothole threshold and labelling
 
 size_t pothole_workspace_bytes(int nbins, int nimg);
+size_t slic_workspace_bytes(int W, int H, int S, int nimg);
+hipError_t launch_slic(const float *d2, const uint8_t *mask, int W, int H, int nimg, int S, double m, int iters,
+                       int32_t *labels, float *d3, double *centres, void *ws, hipStream_t s);
 hipError_t launch_pothole_threshold(const float *d2, const uint8_t *mask, int W, int H, int nimg, double lo,
                                     double b, int nbins, double delta_pd, sgm_pothole_threshold *out,
                                     double *curve, void *ws, hipStream_t s);

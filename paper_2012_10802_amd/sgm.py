@@ -113,6 +113,8 @@ def _load_library():
         "sgm_pothole_workspace_size": [I, I, ctypes.POINTER(S)],
         "sgm_pothole_threshold_batch": [P, P, I, I, I, D, D, I, D, P, P, P, S, P],
         "sgm_pothole_label_batch": [P, P, I, I, I, P, P, P],
+        "sgm_slic_workspace_size": [I, I, I, I, ctypes.POINTER(S)],
+        "sgm_slic_batch": [P, P, I, I, I, I, D, I, P, P, P, P, S, P],
         "sgm_status_str": [I],
         "sgm_last_error": [],
     }
@@ -370,6 +372,49 @@ def pothole_labels(d2, result, mask=None, labels=None, stream=None):
     _check(_lib.sgm_pothole_label_batch(_ptr(d), _ptr(mask), W, H, n, _ptr(result), _ptr(labels),
                                         _stream(stream)), "sgm_pothole_label_batch")
     return labels
+
+
+# ---------------------------------------------------------------------------
+# superpixels (SLIC, Sec. II-D) and D3 (Sec. II-E)
+
+
+def slic_workspace_size(width, height, S, nimg=1) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.sgm_slic_workspace_size(int(width), int(height), int(S), int(nimg), ctypes.byref(n)),
+           "sgm_slic_workspace_size")
+    return int(n.value)
+
+
+def slic_num_centres(width, height, S) -> int:
+    return ((int(width) + S - 1) // S) * ((int(height) + S - 1) // S)
+
+
+def slic(d2, S, m, iters, mask=None, labels=None, d3=None, centres=None, workspace=None, stream=None):
+    """SLIC on float32 device maps [H, W] or [n, H, W].  Returns (labels
+    int32 [n, H, W], d3 float32 [n, H, W], centres float64 [n, K, 3])."""
+    d = _maps(d2, torch.float32, "d2")
+    n, H, W = d.shape
+    if mask is not None:
+        mask = _maps(mask, torch.uint8, "mask")
+        if tuple(mask.shape) != (n, H, W):
+            raise ValueError("mask must have the shape of d2")
+    K = slic_num_centres(W, H, S)
+    if labels is None:
+        labels = torch.empty((n, H, W), dtype=torch.int32, device=d.device)
+    if d3 is None:
+        d3 = torch.empty((n, H, W), dtype=torch.float32, device=d.device)
+    if centres is None:
+        centres = torch.empty((n, K, 3), dtype=torch.float64, device=d.device)
+    _need(labels, torch.int32, (n, H, W), "labels")
+    _need(d3, torch.float32, (n, H, W), "d3")
+    _need(centres, torch.float64, (n, K, 3), "centres")
+    if workspace is None:
+        workspace = torch.empty(slic_workspace_size(W, H, S, n), dtype=torch.uint8, device=d.device)
+    _need(workspace, torch.uint8, None, "workspace")
+    _check(_lib.sgm_slic_batch(_ptr(d), _ptr(mask), W, H, n, int(S), float(m), int(iters), _ptr(labels), _ptr(d3),
+                               _ptr(centres), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "sgm_slic_batch")
+    return labels, d3, centres
 
 
 class Matcher:
