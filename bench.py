@@ -342,6 +342,11 @@ def road_model_leg(args, log=None):
     pd_res = torch.empty((n, sgm.POTHOLE_WORDS), dtype=torch.float64, device=dev)
     pd_ws = torch.empty(sgm.pothole_workspace_size(nbins, n), dtype=torch.uint8, device=dev)
     labels = torch.empty((n, H, W), dtype=torch.int32, device=dev)
+    S_slic, m_slic, it_slic = 16, 4.0, 10
+    sp_labels = torch.empty((n, H, W), dtype=torch.int32, device=dev)
+    d3 = torch.empty((n, H, W), dtype=torch.float32, device=dev)
+    centres = torch.empty((n, sgm.slic_num_centres(W, H, S_slic), 3), dtype=torch.float64, device=dev)
+    sp_ws = torch.empty(sgm.slic_workspace_size(W, H, S_slic, n), dtype=torch.uint8, device=dev)
 
     def once(ev=None):
         if ev:
@@ -362,31 +367,38 @@ def road_model_leg(args, log=None):
         sgm.pothole_labels(d2, pd_res, mask=mask, labels=labels)
         if ev:
             ev[5].record()
+        # superpixels on D2 and the superpixel means D3 (SLIC, 10 rounds)
+        sgm.slic(d2, S_slic, m_slic, it_slic, mask=mask, labels=sp_labels, d3=d3, centres=centres,
+                 workspace=sp_ws)
+        if ev:
+            ev[6].record()
 
     for _ in range(3):
         once()
     reps = 20
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(reps)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(reps)]
     torch.cuda.synchronize()
     for e in events:
         once(e)
     torch.cuda.synchronize()
-    per = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(5)] for e in events])
-    fit_ms, win_ms, tr_ms, thr_ms, lab_ms = (float(x) for x in per.mean(axis=0))
+    per = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(6)] for e in events])
+    fit_ms, win_ms, tr_ms, thr_ms, lab_ms, slic_ms = (float(x) for x in per.mean(axis=0))
     pd_stat = sgm.pothole_threshold_dicts(pd_res)
     detection = []
     for dpd in (delta_pd, 1.0, 0.5):  # the paper's tolerance, then smaller ones for shallower potholes
         res = pd_res.clone()
         res[:, 1] = res[:, 0] - dpd  # t_s = t_r - delta_PD
-        lab = sgm.pothole_labels(d2, res, mask=mask)
-        found = lab > 0
-        tp = int((found & holes).sum())
-        prec = tp / max(1, int(found.sum()))
-        rec = tp / max(1, int(holes.sum()))
-        detection.append({"delta_pd": dpd, "pixel_precision": round(prec, 4), "pixel_recall": round(rec, 4),
-                          "pixel_f1": round(2 * prec * rec / max(1e-12, prec + rec), 4),
-                          "components_mean": round(float(np.mean(
-                              [torch.unique(lab[i][lab[i] > 0]).numel() for i in range(n)])), 1)})
+        for name, src in (("D2", d2), ("D3", d3)):  # pixel by pixel, then superpixel means
+            lab = sgm.pothole_labels(src, res, mask=mask)
+            found = lab > 0
+            tp = int((found & holes).sum())
+            prec = tp / max(1, int(found.sum()))
+            rec = tp / max(1, int(holes.sum()))
+            detection.append({"map": name, "delta_pd": dpd, "pixel_precision": round(prec, 4),
+                              "pixel_recall": round(rec, 4),
+                              "pixel_f1": round(2 * prec * rec / max(1e-12, prec + rec), 4),
+                              "components_mean": round(float(np.mean(
+                                  [torch.unique(lab[i][lab[i] > 0]).numel() for i in range(n)])), 1)})
     copy_calibration(args, dev)
     px = n * W * H
     fit_gbs = px * 5 / (fit_ms * 1e-3) / 1e9
@@ -397,7 +409,7 @@ def road_model_leg(args, log=None):
     da0 = [abs(f["a0"] - t[0]) for f, t in zip(fits, truth)]
     if log:
         log("road model: fit %.4f ms, windows %.4f ms, transformation %.4f ms, pothole threshold %.4f ms, "
-            "labels %.4f ms per batch of %d" % (fit_ms, win_ms, tr_ms, thr_ms, lab_ms, n))
+            "labels %.4f ms, SLIC %.4f ms per batch of %d" % (fit_ms, win_ms, tr_ms, thr_ms, lab_ms, slic_ms, n))
     return {
         "maps": n, "width": W, "height": H,
         "inputs": "full-range SGM disparity (0-191, census 7x7, 8 paths) of generated road pairs; "
@@ -411,13 +423,16 @@ def road_model_leg(args, log=None):
         "fit_error": {"phi_max_deg": round(math.degrees(max(dphi)), 5),
                       "a1_max_rel": round(max(da1), 6), "a0_max_px": round(max(da0), 4)},
         "pothole": {"threshold_ms": round(thr_ms, 4), "label_ms": round(lab_ms, 4),
+                    "slic_ms": round(slic_ms, 4),
+                    "slic": {"S": S_slic, "m": m_slic, "iters": it_slic,
+                             "superpixels_per_map": sgm.slic_num_centres(W, H, S_slic)},
                     "threshold_hbm": {"bytes_per_pixel": 5,
                                       "achieved": round(px * 5 / (thr_ms * 1e-3) / 1e9, 1), "unit": "GB/s"},
                     "nbins": nbins, "delta_pd": delta_pd, "range": [2.0, 18.0],
                     "t_r_mean": round(float(np.mean([r["t_r"] for r in pd_stat])), 4),
                     "detection": detection,
-                    "note": "pixel-level thresholding of D2 (no superpixels); ground truth = the "
-                            "generator's depressions on road pixels"},
+                    "note": "threshold t_r from D2 (eq. (14), (15)); potholes = D2 or D3 below t_s, "
+                            "8-connected; ground truth = the generator's depressions on road pixels"},
     }
 
 

@@ -15,8 +15,8 @@
 // Kernels:
 //   k_slic_init   one thread per centre: start position, gradient move,
 //                 value; clears the centre's accumulators;
-//   k_slic_cell   one wave per grid cell: the nine candidate centres in LDS,
-//                 each pixel of the cell assigned (float64, no fused
+//   k_slic_cell   one wave per grid cell, four adjacent cells per
+//                 workgroup: the nine candidate centres in LDS, each pixel of the cell assigned (float64, no fused
 //                 multiply-add, first smallest in index order), its label
 //                 written; sums for the cell's own centre in registers (most
 //                 pixels), for the other eight in LDS, then int64 global
@@ -97,87 +97,104 @@ __device__ inline long long wave_sum_ll(long long x)
     return x;
 }
 
-// One wave per grid cell (blockIdx.x, blockIdx.y) of map blockIdx.z.
-__global__ __launch_bounds__(64) void k_slic_cell(const float *__restrict__ d2, const uint8_t *__restrict__ mask,
-                                                  int W, int H, int S, int nx, int ny, double w,
-                                                  const double *__restrict__ centres,
-                                                  unsigned long long *__restrict__ acc,
-                                                  int32_t *__restrict__ labels)
+// Four adjacent grid cells (4 blockIdx.x + wave, blockIdx.y) of map
+// blockIdx.z per workgroup, one wave each: a row of the four cells is
+// contiguous in memory, so the workgroup's loads fill whole cache lines on
+// one CU.
+constexpr int kSlicCellsPerGroup = 4;
+
+__global__ __launch_bounds__(64 * kSlicCellsPerGroup) void k_slic_cell(
+    const float *__restrict__ d2, const uint8_t *__restrict__ mask, int W, int H, int S, int nx, int ny, double w,
+    const double *__restrict__ centres, unsigned long long *__restrict__ acc, int32_t *__restrict__ labels)
 {
 #pragma clang fp contract(off)
-    const int ci = blockIdx.x, cj = blockIdx.y, img = blockIdx.z, lane = threadIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ci = blockIdx.x * kSlicCellsPerGroup + wave, cj = blockIdx.y, img = blockIdx.z;
     const int K = nx * ny;
-    __shared__ double cand[9][3];
-    __shared__ int cidx[9];
-    __shared__ unsigned long long lacc[9][4];
+    // per wave: the nine candidate centres (LDS broadcast reads) and the
+    // sums for the eight neighbouring ones
+    __shared__ double cand[kSlicCellsPerGroup][9][3];
+    __shared__ int cidx[kSlicCellsPerGroup][9];
+    __shared__ unsigned long long lacc[kSlicCellsPerGroup][9][4];
     if (lane < 9) {
         const int i = ci + lane % 3 - 1, j = cj + lane / 3 - 1;
-        const bool in = i >= 0 && i < nx && j >= 0 && j < ny;
+        const bool in = ci < nx && i >= 0 && i < nx && j >= 0 && j < ny;
         const int k = in ? j * nx + i : -1;
-        cidx[lane] = k;
-        for (int q = 0; q < 3; ++q) cand[lane][q] = __builtin_nan("");
+        cidx[wave][lane] = k;
+        for (int q = 0; q < 3; ++q) cand[wave][lane][q] = 0.0;
         if (in)
-            for (int q = 0; q < 3; ++q) cand[lane][q] = centres[((size_t)img * K + k) * 3 + q];
+            for (int q = 0; q < 3; ++q) cand[wave][lane][q] = centres[((size_t)img * K + k) * 3 + q];
     }
-    if (lane < 36) lacc[lane / 4][lane % 4] = 0ull;
+    if (lane < 36) lacc[wave][lane / 4][lane % 4] = 0ull;
     __syncthreads();
-
-    const size_t off = (size_t)img * W * H;
-    const float *d = d2 + off;
-    const uint8_t *m = mask ? mask + off : nullptr;
-    int32_t *lab = labels + off;
-    long long own_n = 0, own_x = 0, own_y = 0, own_q = 0;
-    for (int p = lane; p < S * S; p += 64) {
-        const int x = ci * S + p % S, y = cj * S + p / S;
-        if (x >= W || y >= H) continue;
-        const size_t at = (size_t)y * W + x;
-        int best_s = -1;
-        if (px_used(d, m, at)) {
-            const double v = (double)d[at], xf = (double)x, yf = (double)y;
-            double best = __builtin_inf();
-            for (int s = 0; s < 9; ++s) {
-                if (cidx[s] < 0) continue;
-                const double dc = v - cand[s][2];
-                const double dx = xf - cand[s][0], dy = yf - cand[s][1];
-                const double ds2 = dx * dx + dy * dy;
-                const double dist = dc * dc + ds2 * w;
-                if (dist < best) {  // NaN (a centre without a value) never wins
-                    best = dist;
-                    best_s = s;
+    if (ci < nx) {  // a wave past the last column of cells has nothing to do
+        const size_t off = (size_t)img * W * H;
+        const float *d = d2 + off;
+        const uint8_t *m = mask ? mask + off : nullptr;
+        int32_t *lab = labels + off;
+        long long own_n = 0, own_x = 0, own_y = 0, own_q = 0;
+        // pixel p = lane + 64 t of the cell at (column c, row r), stepped
+        // without a division per pixel
+        int c = lane % S, r = lane / S;
+        const int dc_step = 64 % S, dr_step = 64 / S;
+        for (int p = lane; p < S * S; p += 64) {
+            const int x = ci * S + c, y = cj * S + r;
+            c += dc_step;
+            r += dr_step;
+            if (c >= S) {
+                c -= S;
+                r += 1;
+            }
+            if (x >= W || y >= H) continue;
+            const size_t at = (size_t)y * W + x;
+            int best_s = -1;
+            if (px_used(d, m, at)) {
+                const double v = (double)d[at], xf = (double)x, yf = (double)y;
+                double best = __builtin_inf();
+                for (int s = 0; s < 9; ++s) {
+                    if (cidx[wave][s] < 0) continue;
+                    const double dv = v - cand[wave][s][2];
+                    const double dx = xf - cand[wave][s][0], dy = yf - cand[wave][s][1];
+                    const double ds2 = dx * dx + dy * dy;
+                    const double dist = dv * dv + ds2 * w;
+                    if (dist < best) {  // NaN (a centre without a value) never wins
+                        best = dist;
+                        best_s = s;
+                    }
                 }
             }
+            lab[at] = best_s < 0 ? -1 : cidx[wave][best_s];
+            if (best_s < 0) continue;
+            const long long q = llrint((double)d[at] * kQScale);
+            if (best_s == 4) {
+                own_n += 1;
+                own_x += x;
+                own_y += y;
+                own_q += q;
+            } else {
+                atomicAdd(&lacc[wave][best_s][0], 1ull);
+                atomicAdd(&lacc[wave][best_s][1], (unsigned long long)x);
+                atomicAdd(&lacc[wave][best_s][2], (unsigned long long)y);
+                atomicAdd(&lacc[wave][best_s][3], (unsigned long long)q);
+            }
         }
-        lab[at] = best_s < 0 ? -1 : cidx[best_s];
-        if (best_s < 0) continue;
-        const long long q = llrint((double)d[at] * kQScale);
-        if (best_s == 4) {
-            own_n += 1;
-            own_x += x;
-            own_y += y;
-            own_q += q;
-        } else {
-            atomicAdd(&lacc[best_s][0], 1ull);
-            atomicAdd(&lacc[best_s][1], (unsigned long long)x);
-            atomicAdd(&lacc[best_s][2], (unsigned long long)y);
-            atomicAdd(&lacc[best_s][3], (unsigned long long)q);
+        own_n = wave_sum_ll(own_n);
+        own_x = wave_sum_ll(own_x);
+        own_y = wave_sum_ll(own_y);
+        own_q = wave_sum_ll(own_q);
+        if (lane == 0 && own_n > 0) {
+            unsigned long long *a = acc + ((size_t)img * K + cidx[wave][4]) * 4;
+            atomicAdd(&a[0], (unsigned long long)own_n);
+            atomicAdd(&a[1], (unsigned long long)own_x);
+            atomicAdd(&a[2], (unsigned long long)own_y);
+            atomicAdd(&a[3], (unsigned long long)own_q);
         }
     }
-    own_n = wave_sum_ll(own_n);
-    own_x = wave_sum_ll(own_x);
-    own_y = wave_sum_ll(own_y);
-    own_q = wave_sum_ll(own_q);
-    __syncthreads();
-    unsigned long long *a = acc + (size_t)img * K * 4;
-    if (lane == 0 && own_n > 0) {
-        const int k = cidx[4];
-        atomicAdd(&a[k * 4 + 0], (unsigned long long)own_n);
-        atomicAdd(&a[k * 4 + 1], (unsigned long long)own_x);
-        atomicAdd(&a[k * 4 + 2], (unsigned long long)own_y);
-        atomicAdd(&a[k * 4 + 3], (unsigned long long)own_q);
-    }
-    if (lane < 36) {
-        const int s = lane / 4, q = lane % 4;
-        if (s != 4 && lacc[s][0] != 0ull) atomicAdd(&a[cidx[s] * 4 + q], lacc[s][q]);
+    __syncthreads();  // the LDS sums of every wave are complete
+    if (ci < nx && lane < 36) {
+        const int sl = lane / 4, qq = lane % 4;
+        if (sl != 4 && lacc[wave][sl][0] != 0ull)  // only in-grid candidates ever win
+            atomicAdd(&acc[((size_t)img * K + cidx[wave][sl]) * 4 + qq], lacc[wave][sl][qq]);
     }
 }
 
@@ -227,8 +244,8 @@ hipError_t launch_slic(const float *d2, const uint8_t *mask, int W, int H, int n
     k_slic_init<<<cgrid, 64, 0, s>>>(d2, mask, W, H, S, nx, K, centres, acc);
     hipError_t e = hipGetLastError();
     for (int it = 0; it < iters && e == hipSuccess; ++it) {
-        k_slic_cell<<<dim3(nx, ny, nimg), 64, 0, s>>>(d2, mask, W, H, S, nx, ny, w, centres,
-                                                      reinterpret_cast<unsigned long long *>(acc), labels);
+        k_slic_cell<<<dim3((nx + kSlicCellsPerGroup - 1) / kSlicCellsPerGroup, ny, nimg), 64 * kSlicCellsPerGroup, 0,
+                      s>>>(d2, mask, W, H, S, nx, ny, w, centres, reinterpret_cast<unsigned long long *>(acc), labels);
         e = hipGetLastError();
         if (e != hipSuccess) break;
         k_slic_update<<<cgrid, 64, 0, s>>>(K, centres, acc);
