@@ -406,13 +406,19 @@ sgm_status sgm_road_workspace_size(int32_t width, int32_t height, int32_t nimg, 
  * (mask NULL: every pixel), its disparity d is finite, d >= min_disp and
  * u - d >= margin, i.e. its match lies inside the right image with that
  * much room (compared in float64; pass -INFINITY for no bound; NaN is
- * invalid).  Moments are accumulated in float64 in a fixed order, so the
+ * invalid), and, when `prior` is given (fits of the same maps, e.g. from a
+ * first call), |d - f_prior(u, v)| <= tol: the refit over the pixels that
+ * lie on the first fit's road, which drops the background and other
+ * outliers that bias a plain least-squares fit (tol >= 0, +INFINITY
+ * allowed; no pixel of a map whose prior failed is selected; prior may be
+ * the same array as fit).  Moments are accumulated in float64 in a fixed order, so the
  * result is deterministic.  workspace: device, 256-byte aligned, at least
  * sgm_road_workspace_size bytes.  The maps are read once (5 bytes per
  * pixel with a mask, 4 without). */
 sgm_status sgm_road_fit_batch(const float *disp, const uint8_t *mask, int32_t width, int32_t height,
-                              int32_t nimg, float min_disp, double margin, sgm_road_fit *fit,
-                              void *workspace, size_t workspace_bytes, void *stream);
+                              int32_t nimg, float min_disp, double margin, const sgm_road_fit *prior,
+                              double tol, sgm_road_fit *fit, void *workspace, size_t workspace_bytes,
+                              void *stream);
 /* Per-row window starts for W x H frames from device-resident fits (the
  * device form of sgm_window_from_road below, with the plane's slopes in
  * place of a1 cos(phi) and -a1 sin(phi)).  With scale s the fits are of
@@ -431,6 +437,15 @@ sgm_status sgm_road_window_batch(const sgm_road_fit *fit, int32_t width, int32_t
 sgm_status sgm_disparity_transform_batch(const float *disp, const sgm_road_fit *fit, int32_t width,
                                          int32_t height, int32_t nimg, double delta_dt, float *out,
                                          void *stream);
+/* Road region for maps without a hand-selected one (the paper selects its
+ * road regions by hand): mask = 1 where the fitted road disparity
+ * f(u, v) >= f_min (below the horizon line of the fit), u - f >= margin
+ * (the road's match lies inside the right image: left of that band no
+ * disparity can be measured) and the disparity is finite; 0 elsewhere and
+ * on maps whose fit failed.  float64, f from the fit's slopes.  mask:
+ * uint8 [nimg][H][W], device. */
+sgm_status sgm_road_mask_batch(const float *disp, const sgm_road_fit *fit, int32_t width, int32_t height,
+                               int32_t nimg, double f_min, double margin, uint8_t *mask, void *stream);
 
 /* ------------------------------------------------------------------------
  * Pothole threshold and labelling (Sec. II-E, eq. (14), (15)) on

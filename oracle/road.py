@@ -23,11 +23,20 @@ eq. (11) at the phi found.
 Disparity transformation (Sec. II-C, eq. (13)):
 D2(p) = D1(p) - f(a, p, phi) + delta_DT.
 
+Road region without ground truth (the paper selects it by hand): pixels
+whose road disparity f(a, p, phi) is at least f_min, i.e. below the horizon
+line of the fitted road, where the road's match lies inside the right image
+(u - f >= margin; left of that band no disparity can be measured), with a
+finite disparity.
+
 Pixel selection (the paper fits "road disparities" without saying how they
 are chosen): a pixel (column u, row v, integer indices) is used when its
 mask entry is non-zero (no mask: all pixels), its disparity d is finite and
 at least `min_disp`, and its match lies inside the right image with room to
-spare: u - d >= `margin` (computed in float64).
+spare: u - d >= `margin` (computed in float64).  A refit keeps only the
+pixels within `tol` of an earlier fit's road line, the "road disparities"
+of Sec. II-C being those on the road plane (the background and other
+outliers bias a plain least-squares fit).
 
 Status: 0 fitted; 1 fewer than 3 pixels selected; 2 the selected pixels lie
 on one image line (the 2x2 covariance of (u, v) has
@@ -48,13 +57,16 @@ GOLDEN_TOL = 1e-11          # final bracket width of the golden-section search (
 COLLINEAR = 1e-9
 
 
-def select(disp, mask=None, min_disp=-math.inf, margin=-math.inf):
+def select(disp, mask=None, min_disp=-math.inf, margin=-math.inf, prior=None, tol=math.inf):
     """Centred coordinates (u, v) and disparities d (float64) of the pixels
-    that enter the fit."""
+    that enter the fit; `prior` = (a0, a1, phi) of an earlier fit keeps only
+    the pixels within `tol` of its road line."""
     D = np.asarray(disp)
     H, W = D.shape
     cols = np.arange(W, dtype=np.float64)[None, :]
     keep = np.isfinite(D) & (D >= min_disp) & (cols - D.astype(np.float64) >= margin)
+    if prior is not None:
+        keep &= np.abs(D.astype(np.float64) - road_disparity(*prior, W, H)) <= tol
     if mask is not None:
         keep &= np.asarray(mask) != 0
     vv, uu = np.nonzero(keep)
@@ -118,10 +130,11 @@ def minimise_phi(u, v, d):
     return _wrap(0.5 * (lo + hi))
 
 
-def fit_road(disp, mask=None, min_disp=-math.inf, margin=-math.inf):
+def fit_road(disp, mask=None, min_disp=-math.inf, margin=-math.inf, prior=None, tol=math.inf):
     """Fit of Sec. II-C to one disparity map [H][W]: dict with status, count,
-    a0, a1, phi (radians) and e0min."""
-    u, v, d = select(disp, mask, min_disp, margin)
+    a0, a1, phi (radians) and e0min.  With `prior` ((a0, a1, phi), or None)
+    only pixels within `tol` of the prior road line enter (the refit)."""
+    u, v, d = select(disp, mask, min_disp, margin, prior, tol)
     k = d.size
     nan = float("nan")
     out = dict(status=0, count=k, a0=nan, a1=nan, phi=nan, e0min=nan)
@@ -151,3 +164,15 @@ def transform(disp, a0, a1, phi, delta_dt):
     D1 = np.asarray(disp, dtype=np.float64)
     H, W = D1.shape
     return (D1 - road_disparity(a0, a1, phi, W, H) + delta_dt).astype(np.float32)
+
+
+def road_mask(disp, a0, a1, phi, f_min, margin):
+    """Road region used without ground truth: pixels where the road line of
+    eq. (3) is at least f_min (below the horizon line) and its match lies at
+    least `margin` inside the right image (u - f >= margin), with a finite
+    disparity; uint8 [H][W]."""
+    D = np.asarray(disp, dtype=np.float32).astype(np.float64)
+    H, W = D.shape
+    f = road_disparity(a0, a1, phi, W, H)
+    cols = np.arange(W, dtype=np.float64)[None, :]
+    return ((f >= f_min) & (cols - f >= margin) & np.isfinite(D)).astype(np.uint8)

@@ -48,6 +48,29 @@ __device__ inline bool selected(double d, double min_disp, double lim)
     return (d >= min_disp) & (d <= lim) & (fabs(d) <= 3.4028234663852886e38);
 }
 
+// Optional prior fit of the same map: only pixels within `tol` of its road
+// line, |d - f(u, v)| <= tol, are selected (none if the prior failed).
+struct Prior {
+    bool use, none;
+    double gu, gv, base, tol, cy;
+    __device__ Prior(const sgm_road_fit *p, int img, int W, int H, double t)
+        : use(p != nullptr), none(false), gu(0.0), gv(0.0), base(0.0), tol(t), cy(0.5 * (H - 1))
+    {
+        if (use) {
+            const sgm_road_fit f = p[img];
+            none = f.status != 0;
+            gu = f.g_u;
+            gv = f.g_v;
+            base = f.a0 - f.g_u * 0.5 * (W - 1);  // f(u, v) = base + g_v (v - cy) + g_u u
+        }
+    }
+    __device__ double row(int v) const { return base + gv * ((double)v - cy); }
+    __device__ bool near(double d, double frow, int u) const
+    {
+        return !use || (!none && fabs(d - (frow + gu * (double)u)) <= tol);
+    }
+};
+
 // Block-wide sum of the ten moments (fixed order), written as this
 // workgroup's partial.
 __device__ inline void store_partial(const double (&acc)[kMoments], double *__restrict__ part)
@@ -95,11 +118,14 @@ template <int K>
 __global__ __launch_bounds__(kRoadThreads) void k_road_moments_vec(const float *__restrict__ disp,
                                                                      const uint8_t *__restrict__ mask, int W,
                                                                      int H, int rows, int nblk, double min_disp,
-                                                                     double margin, double *__restrict__ part)
+                                                                     double margin,
+                                                                     const sgm_road_fit *__restrict__ prior,
+                                                                     double tol, double *__restrict__ part)
 {
     const int img = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
     const size_t base = (size_t)img * W * H;
     const int v0 = b * rows, v1 = min(H, v0 + rows);
+    const Prior pr(prior, img, W, H, tol);
     double acc[kMoments];
 #pragma unroll
     for (int i = 0; i < kMoments; ++i) acc[i] = 0.0;
@@ -123,6 +149,7 @@ __global__ __launch_bounds__(kRoadThreads) void k_road_moments_vec(const float *
             if (v + r >= v1) break;
             int rn = 0, ru = 0, ruu = 0;
             double rd = 0.0, rud = 0.0, rdd = 0.0;
+            const double frow = pr.row(v + r);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int x = 4 * (t + kRoadThreads * k);
@@ -134,7 +161,7 @@ __global__ __launch_bounds__(kRoadThreads) void k_road_moments_vec(const float *
                 for (int e = 0; e < 4; ++e) {
                     const double de = (double)dv[e];
                     const bool sel = in & (((m4[r][k] >> (8 * e)) & 0xFFu) != 0) &
-                                     selected(de, min_disp, lim0 + (double)e);
+                                     selected(de, min_disp, lim0 + (double)e) & pr.near(de, frow, x + e);
                     const double d = sel ? de : 0.0;
                     const int u = x + e;
                     rn += sel ? 1 : 0;
@@ -157,11 +184,13 @@ __global__ __launch_bounds__(kRoadThreads) void k_road_moments_vec(const float *
 __global__ __launch_bounds__(kRoadThreads) void k_road_moments(const float *__restrict__ disp,
                                                                const uint8_t *__restrict__ mask, int W, int H,
                                                                int rows, int nblk, double min_disp, double margin,
+                                                               const sgm_road_fit *__restrict__ prior, double tol,
                                                                double *__restrict__ part)
 {
     const int img = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
     const size_t base = (size_t)img * W * H;
     const int v0 = b * rows, v1 = min(H, v0 + rows);
+    const Prior pr(prior, img, W, H, tol);
     double acc[kMoments];
 #pragma unroll
     for (int i = 0; i < kMoments; ++i) acc[i] = 0.0;
@@ -170,9 +199,10 @@ __global__ __launch_bounds__(kRoadThreads) void k_road_moments(const float *__re
         const float *drow = disp + base + (size_t)v * W;
         const uint8_t *mrow = mask ? mask + base + (size_t)v * W : nullptr;
         double rn = 0.0, ru = 0.0, ruu = 0.0, rd = 0.0, rud = 0.0, rdd = 0.0;
+        const double frow = pr.row(v);
         for (int x = t; x < W; x += kRoadThreads) {
             const double d = (double)drow[x], u = (double)x;
-            if ((!mrow || mrow[x] != 0) && selected(d, min_disp, u - margin)) {
+            if ((!mrow || mrow[x] != 0) && selected(d, min_disp, u - margin) && pr.near(d, frow, x)) {
                 rn += 1.0;
                 ru += u;
                 ruu += u * u;
@@ -343,6 +373,26 @@ __global__ __launch_bounds__(kRoadThreads) void k_disp_transform(const float *__
     }
 }
 
+// Road region: f(u, v) >= f_min (below the horizon line of the fit),
+// u - f >= margin (the road's match inside the right image) and the
+// disparity finite (float64); 0 for a failed fit.
+__global__ __launch_bounds__(256) void k_road_mask(const float *__restrict__ disp,
+                                                   const sgm_road_fit *__restrict__ fit, int W, int H,
+                                                   double f_min, double margin, uint8_t *__restrict__ mask)
+{
+    const int img = blockIdx.y;
+    const int n = W * H;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const size_t at = (size_t)img * n + p;
+    const sgm_road_fit f = fit[img];
+    const int v = p / W, u = p - v * W;
+    const double d = (double)disp[at];
+    const double road = f.a0 + f.g_v * ((double)v - 0.5 * (H - 1)) + f.g_u * ((double)u - 0.5 * (W - 1));
+    const bool in = f.status == 0 && road >= f_min && (double)u - road >= margin && fabs(d) <= 3.4028234663852886e38;
+    mask[at] = in ? 1 : 0;
+}
+
 // Rows per workgroup so that a launch has about `target` workgroups.
 int road_rows(int H, int nimg, int target)
 {
@@ -359,6 +409,14 @@ bool vec_ok(const void *a, const void *b, const void *c, int W)
 
 }  // namespace
 
+hipError_t launch_road_mask(const float *disp, const sgm_road_fit *fit, int W, int H, int nimg, double f_min,
+                            double margin, uint8_t *mask, hipStream_t s)
+{
+    const int n = W * H;
+    k_road_mask<<<dim3((n + 255) / 256, nimg), 256, 0, s>>>(disp, fit, W, H, f_min, margin, mask);
+    return hipGetLastError();
+}
+
 size_t road_workspace_bytes(int W, int H, int nimg)
 {
     (void)W;
@@ -368,7 +426,8 @@ size_t road_workspace_bytes(int W, int H, int nimg)
 }
 
 hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H, int nimg, float min_disp,
-                           double margin, sgm_road_fit *fit, void *ws, hipStream_t s)
+                           double margin, const sgm_road_fit *prior, double tol, sgm_road_fit *fit, void *ws,
+                           hipStream_t s)
 {
     const int rows = road_rows(H, nimg, kTargetBlocks);
     const int nblk = (H + rows - 1) / rows;
@@ -376,13 +435,13 @@ hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H,
     const dim3 grid(nblk, nimg);
     const bool vec = vec_ok(disp, mask, nullptr, W);
     if (vec && W <= 1024)
-        k_road_moments_vec<1><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, part);
+        k_road_moments_vec<1><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, prior, tol, part);
     else if (vec && W <= 2048)
-        k_road_moments_vec<2><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, part);
+        k_road_moments_vec<2><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, prior, tol, part);
     else if (vec && W <= 4096)
-        k_road_moments_vec<4><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, part);
+        k_road_moments_vec<4><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, prior, tol, part);
     else
-        k_road_moments<<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, part);
+        k_road_moments<<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, prior, tol, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_road_solve<<<nimg, 64, 0, s>>>(part, nblk, W, H, fit);

@@ -503,13 +503,15 @@ sgm_status sgm_road_workspace_size(int32_t W, int32_t H, int32_t nimg, size_t *b
 }
 
 sgm_status sgm_road_fit_batch(const float *disp, const uint8_t *mask, int32_t W, int32_t H, int32_t nimg,
-                              float min_disp, double margin, sgm_road_fit *fit, void *ws, size_t ws_bytes,
-                              void *stream)
+                              float min_disp, double margin, const sgm_road_fit *prior, double tol,
+                              sgm_road_fit *fit, void *ws, size_t ws_bytes, void *stream)
 {
     if (!disp || !fit) return fail(SGM_ERR_INVALID, "disp and fit must not be NULL");
     sgm_status st = check_maps(W, H, nimg);
     if (st != SGM_OK) return st;
     if (isnan(min_disp) || isnan(margin)) return fail(SGM_ERR_INVALID, "min_disp and margin must not be NaN");
+    if (!(tol >= 0.0)) return fail(SGM_ERR_INVALID, "tol must be >= 0 (or +INFINITY)");
+    if (prior && !is_aligned(prior, 8)) return fail(SGM_ERR_INVALID, "prior misaligned");
     if (!ws) return fail(SGM_ERR_INVALID, "workspace is NULL");
     if (!is_aligned(ws, 256)) return fail(SGM_ERR_INVALID, "workspace must be 256-byte aligned");
     if (!is_aligned(disp, 4) || !is_aligned(fit, 8)) return fail(SGM_ERR_INVALID, "disp or fit misaligned");
@@ -517,7 +519,8 @@ sgm_status sgm_road_fit_batch(const float *disp, const uint8_t *mask, int32_t W,
     if (ws_bytes < need)
         return fail(SGM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
     if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
-    hipError_t e = sgm::launch_road_fit(disp, mask, W, H, nimg, min_disp, margin, fit, ws, (hipStream_t)stream);
+    hipError_t e = sgm::launch_road_fit(disp, mask, W, H, nimg, min_disp, margin, prior, tol, fit, ws,
+                                           (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "road fit launch");
 }
 
@@ -598,6 +601,19 @@ sgm_status sgm_pothole_label_batch(const float *d2, const uint8_t *mask, int32_t
     if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = sgm::launch_pothole_label(d2, mask, W, H, nimg, result, labels, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "pothole label launch");
+}
+
+sgm_status sgm_road_mask_batch(const float *disp, const sgm_road_fit *fit, int32_t W, int32_t H, int32_t nimg,
+                               double f_min, double margin, uint8_t *mask, void *stream)
+{
+    if (!disp || !fit || !mask) return fail(SGM_ERR_INVALID, "disp, fit and mask must not be NULL");
+    sgm_status st = check_maps(W, H, nimg);
+    if (st != SGM_OK) return st;
+    if (isnan(f_min) || isnan(margin)) return fail(SGM_ERR_INVALID, "f_min and margin must not be NaN");
+    if (!is_aligned(disp, 4) || !is_aligned(fit, 8)) return fail(SGM_ERR_INVALID, "disp or fit misaligned");
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
+    hipError_t e = sgm::launch_road_mask(disp, fit, W, H, nimg, f_min, margin, mask, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "road mask launch");
 }
 
 static sgm_status check_slic(int32_t W, int32_t H, int32_t S, int32_t nimg)

@@ -123,7 +123,8 @@ hipError_t launch_batch(const BatchDev &b, const BatchGrids &g, int census_n, bo
 
 size_t road_workspace_bytes(int W, int H, int nimg);
 hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H, int nimg, float min_disp,
-                           double margin, sgm_road_fit *fit, void *ws, hipStream_t s);
+                           double margin, const sgm_road_fit *prior, double tol, sgm_road_fit *fit, void *ws,
+                           hipStream_t s);
 hipError_t launch_road_window(const sgm_road_fit *fit, int W, int H, int nimg, int w, int mode, double delta,
                               double scale, int32_t *d_lo, hipStream_t s);
 hipError_t launch_disp_transform(const float *disp, const sgm_road_fit *fit, int W, int H, int nimg,
@@ -132,6 +133,8 @@ hipError_t launch_disp_transform(const float *disp, const sgm_road_fit *fit, int
 // ---------------------------------------------------------------------------
 // pothole threshold and labelling
 
+hipError_t launch_road_mask(const float *disp, const sgm_road_fit *fit, int W, int H, int nimg, double f_min,
+                            double margin, uint8_t *mask, hipStream_t s);
 size_t pothole_workspace_bytes(int nbins, int nimg);
 size_t slic_workspace_bytes(int W, int H, int S, int nimg);
 hipError_t launch_slic(const float *d2, const uint8_t *mask, int W, int H, int nimg, int S, double m, int iters,

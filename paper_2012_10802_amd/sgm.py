@@ -107,7 +107,7 @@ def _load_library():
         "sgm_batch_launch": [P, P],
         "sgm_batch_autotune": [P, P, S, P, ctypes.c_char_p, ctypes.POINTER(sgm_tuning)],
         "sgm_road_workspace_size": [I, I, I, ctypes.POINTER(S)],
-        "sgm_road_fit_batch": [P, P, I, I, I, ctypes.c_float, D, P, P, S, P],
+        "sgm_road_fit_batch": [P, P, I, I, I, ctypes.c_float, D, P, D, P, P, S, P],
         "sgm_road_window_batch": [P, I, I, I, I, I, D, D, P, P],
         "sgm_disparity_transform_batch": [P, P, I, I, I, D, P, P],
         "sgm_pothole_workspace_size": [I, I, ctypes.POINTER(S)],
@@ -115,6 +115,7 @@ def _load_library():
         "sgm_pothole_label_batch": [P, P, I, I, I, P, P, P],
         "sgm_slic_workspace_size": [I, I, I, I, ctypes.POINTER(S)],
         "sgm_slic_batch": [P, P, I, I, I, I, D, I, P, P, P, P, S, P],
+        "sgm_road_mask_batch": [P, P, I, I, I, D, D, P, P],
         "sgm_status_str": [I],
         "sgm_last_error": [],
     }
@@ -248,11 +249,12 @@ def _maps(t, dtype, name):
     return t
 
 
-def road_fit(disp, mask=None, min_disp=float("-inf"), margin=float("-inf"), fit=None, workspace=None,
-             stream=None):
+def road_fit(disp, mask=None, min_disp=float("-inf"), margin=float("-inf"), prior=None, tol=float("inf"),
+             fit=None, workspace=None, stream=None):
     """Fit of the road model to float32 device disparity maps [H, W] or
     [n, H, W] (mask: uint8 of the same shape, or None; pixels with
-    d < min_disp or column - d < margin are skipped).  Returns the fits as a
+    d < min_disp or column - d < margin are skipped, and with a prior fit
+    those farther than tol from its road line).  Returns the fits as a
     float64 device tensor [n, 8] (sgm_road_fit records; see road_fit_dicts)."""
     d = _maps(disp, torch.float32, "disp")
     n, H, W = d.shape
@@ -267,7 +269,10 @@ def road_fit(disp, mask=None, min_disp=float("-inf"), margin=float("-inf"), fit=
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=d.device)
     _need(workspace, torch.uint8, None, "workspace")
-    _check(_lib.sgm_road_fit_batch(_ptr(d), _ptr(mask), W, H, n, float(min_disp), float(margin), _ptr(fit),
+    if prior is not None:
+        _need(prior, torch.float64, (n, ROAD_FIT_WORDS), "prior")
+    _check(_lib.sgm_road_fit_batch(_ptr(d), _ptr(mask), W, H, n, float(min_disp), float(margin), _ptr(prior),
+                                   float(tol), _ptr(fit),
                                    _ptr(workspace), workspace.numel(), _stream(stream)),
            "sgm_road_fit_batch")
     return fit
@@ -309,6 +314,20 @@ def disparity_transform(disp, fit, delta_dt, out=None, stream=None):
     _check(_lib.sgm_disparity_transform_batch(_ptr(d), _ptr(fit), W, H, n, float(delta_dt), _ptr(out),
                                               _stream(stream)), "sgm_disparity_transform_batch")
     return out
+
+
+def road_mask(disp, fit, f_min, margin=float("-inf"), mask=None, stream=None):
+    """Road region uint8 [n, H, W] from device fits: road line f >= f_min,
+    column - f >= margin, finite disparity."""
+    d = _maps(disp, torch.float32, "disp")
+    n, H, W = d.shape
+    _need(fit, torch.float64, (n, ROAD_FIT_WORDS), "fit")
+    if mask is None:
+        mask = torch.empty((n, H, W), dtype=torch.uint8, device=d.device)
+    _need(mask, torch.uint8, (n, H, W), "mask")
+    _check(_lib.sgm_road_mask_batch(_ptr(d), _ptr(fit), W, H, n, float(f_min), float(margin), _ptr(mask),
+                                    _stream(stream)), "sgm_road_mask_batch")
+    return mask
 
 
 # ---------------------------------------------------------------------------

@@ -250,14 +250,18 @@ def test_road_calls_validate_before_launch():
     assert lib.sgm_road_workspace_size(1 << 16, 1 << 15, 1, ctypes.byref(n)) == -2
     ws = sgm.road_workspace_size(64, 48, 2)
     ninf = float("-inf")
-    assert lib.sgm_road_fit_batch(None, None, 64, 48, 2, f(0.0), ninf, d, d, ws, None) == -1
-    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(float("nan")), ninf, d, d, ws, None) == -1
-    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), float("nan"), d, d, ws, None) == -1
-    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, d, None, ws, None) == -1
-    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, d, ctypes.c_void_p((1 << 20) + 16), ws,
+    assert lib.sgm_road_fit_batch(None, None, 64, 48, 2, f(0.0), ninf, None, float("inf"), d, d, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(float("nan")), ninf, None, float("inf"), d, d, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), float("nan"), None, float("inf"), d, d, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, None, float("inf"), d, None, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, None, float("inf"), d, ctypes.c_void_p((1 << 20) + 16), ws,
                                   None) == -1
-    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, d, d, ws - 1, None) == -4
-    assert lib.sgm_road_fit_batch(ctypes.c_void_p((1 << 20) + 2), None, 64, 48, 2, f(0.0), ninf, d, d, ws,
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, None, float("inf"), d, d, ws - 1, None) == -4
+    assert lib.sgm_road_fit_batch(ctypes.c_void_p((1 << 20) + 2), None, 64, 48, 2, f(0.0), ninf, None, float("inf"), d, d, ws,
+                                  None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, d, -1.0, d, d, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, d, float("nan"), d, d, ws, None) == -1
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, ctypes.c_void_p((1 << 20) + 4), 1.0, d, d, ws,
                                   None) == -1
     assert lib.sgm_road_window_batch(d, 64, 48, 2, 0, 0, 0.0, 1.0, d, None) == -1
     assert lib.sgm_road_window_batch(d, 64, 48, 2, 24, 2, 0.0, 1.0, d, None) == -1
@@ -268,9 +272,12 @@ def test_road_calls_validate_before_launch():
     assert lib.sgm_disparity_transform_batch(d, d, 64, 48, 2, float("nan"), d, None) == -1
     assert lib.sgm_disparity_transform_batch(d, d, 64, -48, 2, 0.0, d, None) == -1
     assert lib.sgm_disparity_transform_batch(d, d, 64, 48, 2, 0.0, None, None) == -1
+    assert lib.sgm_road_mask_batch(d, d, 64, 48, 2, float("nan"), 0.0, d, None) == -1
+    assert lib.sgm_road_mask_batch(d, None, 64, 48, 2, 1.0, 0.0, d, None) == -1
+    assert lib.sgm_road_mask_batch(d, d, 64, 48, 0, 1.0, 0.0, d, None) == -1
     # an armed launch fault fails the fit with nothing enqueued
     assert lib.sgm_debug_inject_fault(1) == 0
-    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, d, d, ws, None) == -3
+    assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, None, float("inf"), d, d, ws, None) == -3
     assert lib.sgm_debug_inject_fault(0) == 0
 
 

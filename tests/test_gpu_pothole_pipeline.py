@@ -1,0 +1,79 @@
+"""The end-to-end detector (pairs -> D1 -> fit -> road region -> D2 ->
+threshold -> SLIC / D3 -> labelled potholes): every stage equals the CPU
+oracle applied to the previous stage's GPU output, and the detections land
+on the generator's potholes."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pothole as opd
+from oracle import road as oroad
+from oracle import slic as oslic
+from paper_2012_10802_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _pairs(cfg, seeds):
+    import torch
+    ps = [synth.make_pair(synth.scene_for_config(cfg, s), s) for s in seeds]
+    L = torch.from_numpy(np.stack([p.left for p in ps])).cuda()
+    R = torch.from_numpy(np.stack([p.right for p in ps])).cuda()
+    return ps, L, R
+
+
+def test_plain_detector_stage_by_stage():
+    import torch
+    from paper_2012_10802_amd import sgm
+    from paper_2012_10802_amd.pothole_pipeline import PotholeDetector
+    c = synth.CONFIGS["road640"]
+    ps, L, R = _pairs("road640", [31, 32])
+    det = PotholeDetector(640, 480, 2, ndisp=c["ndisp"], matcher="plain", delta_pd=0.5, slic_iters=6)
+    labels = det.detect(L, R).cpu().numpy()
+    torch.cuda.synchronize()
+    i = 1
+    p = ps[i]
+    oi, osub = oracle.sgm(p.left, p.right, c["census"], c["ndisp"], c["npaths"], c["p1"], c["p2"])
+    D1 = det.disp[i].cpu().numpy()
+    np.testing.assert_allclose(D1, osub, rtol=0, atol=1e-4)
+    prior = None
+    for k, tol in enumerate((math.inf,) + det.refit_tols):  # each fit against the oracle on the GPU's prior
+        f = sgm.road_fit_dicts(det.fits[k])[i]
+        want = oroad.fit_road(D1, None, 0.5, 4.0, prior, tol)
+        assert f["status"] == want["status"] == 0 and f["count"] == want["count"]
+        assert f["phi"] == pytest.approx(want["phi"], abs=1e-7) and f["a1"] == pytest.approx(want["a1"], rel=1e-7)
+        prior = (f["a0"], f["a1"], f["phi"])
+    road = det.road[i].cpu().numpy()
+    wroad = oroad.road_mask(D1, f["a0"], f["a1"], f["phi"], 2.0, 4.0)
+    edge = np.abs(oroad.road_disparity(f["a0"], f["a1"], f["phi"], 640, 480) - 2.0) < 1e-9
+    np.testing.assert_array_equal(road[~edge], wroad[~edge])
+    d2 = det.d2[i].cpu().numpy()
+    np.testing.assert_allclose(d2, oroad.transform(D1, f["a0"], f["a1"], f["phi"], 10.0), rtol=2.5e-7, atol=1e-9)
+    t = sgm.pothole_threshold_dicts(det.threshold)[i]
+    wt = opd.threshold(d2, 2.0, 18.0, 128, 0.5, road)
+    assert (t["status"], t["k"], t["n1"], t["n2"], t["t_s"]) == (wt["status"], wt["k"], wt["n1"], wt["n2"], wt["t_s"])
+    sp, d3, _ = oslic.slic(d2, 16, 4.0, 6, road)
+    np.testing.assert_array_equal(det.superpixels[i].cpu().numpy(), sp)
+    np.testing.assert_array_equal(det.d3[i].cpu().numpy(), d3)
+    np.testing.assert_array_equal(labels[i], opd.label(d3, t["t_s"], road))
+
+
+def test_learned_detector_finds_the_potholes():
+    """Full-size pairs through the learned-window matcher: the road region
+    covers the generator's road, and the pixels marked as potholes are
+    nearly all inside its depressions."""
+    import torch
+    from paper_2012_10802_amd.pothole_pipeline import PotholeDetector
+    ps, L, R = _pairs("road1920", [10_000_101, 10_000_102])
+    det = PotholeDetector(1920, 1080, 2, delta_pd=0.5)
+    labels = det.detect(L, R).cpu().numpy()
+    road = det.road.cpu().numpy().astype(bool)
+    torch.cuda.synchronize()
+    for i, p in enumerate(ps):
+        found = labels[i] > 0
+        assert found.sum() > 100
+        assert (found & p.pothole).sum() / found.sum() > 0.9
+        assert (road & p.road).sum() / road.sum() > 0.99
+        assert math.isfinite(det.d3[i][road[i]].float().mean().item())

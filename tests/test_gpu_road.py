@@ -307,3 +307,46 @@ def test_perspective_pipeline_from_images_alone(lib):
     _close_fit(f, oroad.fit_road(D1, None, 2.0, 16.0), D1)
     np.testing.assert_allclose(d2.cpu().numpy(), oroad.transform(D1, f["a0"], f["a1"], f["phi"], 20.0),
                                rtol=2.5e-7, atol=1e-9)
+
+
+def test_road_mask_matches_oracle(lib):
+    """The road region from device fits equals the oracle's from the same
+    (a0, a1, phi), except on pixels whose road disparity lies within 1e-9 of
+    f_min (the two evaluate the line in another order); failed fits give an
+    empty mask."""
+    rng = np.random.default_rng(12)
+    W, H = 321, 200
+    Ds = []
+    for a0, a1, roll in ((14.0, 0.1, 2.0), (20.0, 0.12, -3.0)):
+        D = oroad.road_disparity(a0, a1, math.radians(roll), W, H) + rng.normal(0, 0.3, (H, W))
+        D[D < 0.5] = 0.0
+        Ds.append(D.astype(np.float32))
+    Ds = np.stack(Ds + [np.zeros((H, W), np.float32)])
+    Ds[1, 5, 7] = np.nan
+    fit = lib.road_fit(_dev(Ds), None, 0.5, 4.0)
+    fs = lib.road_fit_dicts(fit)
+    assert [f["status"] for f in fs] == [0, 0, 1]
+    got = lib.road_mask(_dev(Ds), fit, 2.0, 4.0).cpu().numpy()
+    for i in range(2):
+        f = fs[i]
+        want = oroad.road_mask(Ds[i], f["a0"], f["a1"], f["phi"], 2.0, 4.0)
+        edge = np.abs(oroad.road_disparity(f["a0"], f["a1"], f["phi"], W, H) - 2.0) < 1e-9
+        np.testing.assert_array_equal(got[i][~edge], want[~edge])
+        assert 0.2 < want.mean() < 0.95
+    assert not got[2].any()
+
+
+def test_refit_over_the_first_fits_road(lib):
+    """Refits with a prior fit (in place, prior = fit) select exactly the
+    oracle's pixels within tol of the prior road line."""
+    ps, D = _sgm_disp(lib, "road640", 9)
+    fit = lib.road_fit(_dev(D), None, 0.5, 4.0)
+    prior = lib.road_fit_dicts(fit)[0]
+    for tol in (2.0, 1.0, 0.5):
+        lib.road_fit(_dev(D), None, 0.5, 4.0, prior=fit, tol=tol, fit=fit)
+        got = lib.road_fit_dicts(fit)[0]
+        want = oroad.fit_road(D, None, 0.5, 4.0, (prior["a0"], prior["a1"], prior["phi"]), tol)
+        _close_fit(got, want, D)
+        prior = got
+    a0, a1, phi = ps.road_params
+    assert abs(prior["a1"] - a1) < 2e-3 and abs(prior["phi"] - phi) < 2e-3

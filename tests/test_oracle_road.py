@@ -178,3 +178,53 @@ def test_generator_road_is_recovered_and_transformed():
     flat = ps.road & ~ps.pothole
     np.testing.assert_allclose(D2[flat], 5.0, atol=2e-5)
     assert np.all(D2[ps.pothole] < 5.0)
+
+
+def test_road_mask_is_the_region_below_the_horizon_line():
+    """With phi = 0 the road line reaches f_min on the row
+    v = cy + (f_min - a0) / a1: the mask is every row below it (closed
+    form); a roll tilts that line (a column test), and the margin drops the
+    band on the left where the road's match leaves the right image."""
+    W, H = 200, 150
+    a0, a1 = 10.0, 0.2
+    D = _plane(a0, a1, 0.0, W, H).astype(np.float32)
+    m = road.road_mask(D, a0, a1, 0.0, 2.0, -np.inf)
+    v_h = (H - 1) / 2 + (2.0 - a0) / a1
+    rows = np.arange(H) >= v_h
+    np.testing.assert_array_equal(m, np.repeat(rows[:, None], W, 1).astype(np.uint8))
+    phi = math.radians(5.0)
+    m = road.road_mask(D, a0, a1, phi, 2.0, -np.inf)
+    assert m[:, 0].sum() > m[:, -1].sum()  # positive roll lifts the road on the left
+    m = road.road_mask(D, a0, a1, 0.0, 2.0, 3.0)
+    cols = np.arange(W)[None, :]
+    f = _plane(a0, a1, 0.0, W, H)
+    np.testing.assert_array_equal(m, ((f >= 2.0) & (cols - f >= 3.0)).astype(np.uint8))
+    assert m[-1, :28].sum() == 0 and m[-1, 28:].all()  # the bottom row's road disparity is 24.9
+    Dn = D.copy()
+    Dn[-1, 50] = np.nan
+    assert road.road_mask(Dn, a0, a1, 0.0, 2.0, -np.inf)[-1, 50] == 0
+
+
+def test_refit_on_the_first_fits_road_drops_outliers():
+    """A road plane plus an obstacle above the line where the road reaches
+    3 px (an eighth of the pixels), at a constant disparity of 5 px that the
+    road line never takes there: the plain fit is pulled off the plane; the
+    refit over the pixels within 1 px of that first fit equals the fit over
+    those pixels chosen directly, and refits converge to the plane.  (With
+    a first fit far off the plane, refits can lock onto a wrong band: the
+    outliers must be a minority.)"""
+    W, H = 240, 160
+    a0, a1, phi = 12.0, 0.15, math.radians(2.0)
+    plane = _plane(a0, a1, phi, W, H)
+    D = np.where(plane >= 3.0, plane, 5.0).astype(np.float32)  # 12.5 % of the pixels
+    first = road.fit_road(D, None, 0.5)
+    assert abs(first["a1"] - a1) > 0.01
+    prior = (first["a0"], first["a1"], first["phi"])
+    ref = road.fit_road(D, None, 0.5, prior=prior, tol=1.0)
+    near = np.abs(D - road.road_disparity(*prior, W, H)) <= 1.0
+    direct = road.fit_road(D, near.astype(np.uint8), 0.5)
+    for key in ("a0", "a1", "phi", "e0min", "count"):
+        assert ref[key] == pytest.approx(direct[key], rel=1e-12, abs=1e-9)
+    for _ in range(3):
+        ref = road.fit_road(D, None, 0.5, prior=(ref["a0"], ref["a1"], ref["phi"]), tol=0.25)
+    assert ref["phi"] == pytest.approx(phi, abs=1e-6) and ref["a1"] == pytest.approx(a1, rel=1e-6)
