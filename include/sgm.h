@@ -431,6 +431,15 @@ sgm_status sgm_road_fit_batch(const float *disp, const uint8_t *mask, int32_t wi
 sgm_status sgm_road_window_batch(const sgm_road_fit *fit, int32_t width, int32_t height, int32_t nimg,
                                  int32_t w, int32_t mode, double delta, double scale, int32_t *d_lo,
                                  void *stream);
+/* Per-pixel windows centred on the fitted road plane, for the windowed
+ * calls (sgm_match_win_batch): lo(u, v) = max(0, floor(f(u, v) + 1/2) -
+ * floor(w/2)) with f = scale a0 + g_u (u - cx) + g_v (v - cy) on W x H
+ * frames (scale as in sgm_road_window_batch).  The plane carries the roll
+ * of eq. (3), so a window follows the road across a row as well as down
+ * the image; clamped to 32767; 0 on maps whose fit failed.  lo: int32
+ * [nimg][H][W], device. */
+sgm_status sgm_road_window_map_batch(const sgm_road_fit *fit, int32_t width, int32_t height, int32_t nimg,
+                                     int32_t w, double scale, int32_t *lo, void *stream);
 /* Disparity transformation of eq. (13): out = disp - f(u, v) + delta_dt per
  * pixel, in float64 rounded once to float32; NaN on maps whose fit failed.
  * out may equal disp (in place).  8 bytes of traffic per pixel. */

@@ -176,3 +176,12 @@ def road_mask(disp, a0, a1, phi, f_min, margin):
     f = road_disparity(a0, a1, phi, W, H)
     cols = np.arange(W, dtype=np.float64)[None, :]
     return ((f >= f_min) & (cols - f >= margin) & np.isfinite(D)).astype(np.uint8)
+
+
+def window_map(a0, a1, phi, W, H, w, scale=1.0):
+    """Per-pixel windows centred on the road plane of eq. (3) (a0 of a fit
+    at 1/scale resolution scaled by `scale`): lo = max(0, floor(f + 1/2) -
+    floor(w/2)), int32 [H][W]."""
+    f = road_disparity(scale * a0, a1, phi, W, H)
+    lo = np.floor(f + 0.5) - (w // 2)
+    return np.where(lo > 0, lo, 0).astype(np.int32)

@@ -373,6 +373,27 @@ __global__ __launch_bounds__(kRoadThreads) void k_disp_transform(const float *__
     }
 }
 
+// Per-pixel windows centred on the road line: lo(u, v) = max(0,
+// floor(f(u, v) + 1/2) - floor(w/2)), f of a fit at 1/scale resolution
+// (a0 scaled), clamped to 32767; 0 for a failed fit.
+__global__ __launch_bounds__(256) void k_road_window_map(const sgm_road_fit *__restrict__ fit, int W, int H, int w,
+                                                         double scale, int32_t *__restrict__ lo)
+{
+    const int img = blockIdx.y;
+    const int n = W * H;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const sgm_road_fit f = fit[img];
+    const int v = p / W, u = p - v * W;
+    int32_t out = 0;
+    if (f.status == 0) {
+        const double road = scale * f.a0 + f.g_v * ((double)v - 0.5 * (H - 1)) + f.g_u * ((double)u - 0.5 * (W - 1));
+        const double l = floor(road + 0.5) - (double)(w / 2);
+        if (l > 0.0) out = l < 32767.0 ? (int32_t)l : 32767;  // NaN stays 0
+    }
+    lo[(size_t)img * n + p] = out;
+}
+
 // Road region: f(u, v) >= f_min (below the horizon line of the fit),
 // u - f >= margin (the road's match inside the right image) and the
 // disparity finite (float64); 0 for a failed fit.
@@ -408,6 +429,14 @@ bool vec_ok(const void *a, const void *b, const void *c, int W)
 }
 
 }  // namespace
+
+hipError_t launch_road_window_map(const sgm_road_fit *fit, int W, int H, int nimg, int w, double scale, int32_t *lo,
+                                  hipStream_t s)
+{
+    const int n = W * H;
+    k_road_window_map<<<dim3((n + 255) / 256, nimg), 256, 0, s>>>(fit, W, H, w, scale, lo);
+    return hipGetLastError();
+}
 
 hipError_t launch_road_mask(const float *disp, const sgm_road_fit *fit, int W, int H, int nimg, double f_min,
                             double margin, uint8_t *mask, hipStream_t s)

@@ -603,6 +603,20 @@ sgm_status sgm_pothole_label_batch(const float *d2, const uint8_t *mask, int32_t
     return e == hipSuccess ? SGM_OK : hip_fail(e, "pothole label launch");
 }
 
+sgm_status sgm_road_window_map_batch(const sgm_road_fit *fit, int32_t W, int32_t H, int32_t nimg, int32_t w,
+                                     double scale, int32_t *lo, void *stream)
+{
+    if (!fit || !lo) return fail(SGM_ERR_INVALID, "fit and lo must not be NULL");
+    sgm_status st = check_maps(W, H, nimg);
+    if (st != SGM_OK) return st;
+    if (w < 1) return fail(SGM_ERR_INVALID, "w must be >= 1");
+    if (!(scale > 0.0) || !isfinite(scale)) return fail(SGM_ERR_INVALID, "scale must be finite and > 0");
+    if (!is_aligned(fit, 8) || !is_aligned(lo, 4)) return fail(SGM_ERR_INVALID, "fit or lo misaligned");
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
+    hipError_t e = sgm::launch_road_window_map(fit, W, H, nimg, w, scale, lo, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "road window map launch");
+}
+
 sgm_status sgm_road_mask_batch(const float *disp, const sgm_road_fit *fit, int32_t W, int32_t H, int32_t nimg,
                                double f_min, double margin, uint8_t *mask, void *stream)
 {

@@ -133,6 +133,8 @@ hipError_t launch_disp_transform(const float *disp, const sgm_road_fit *fit, int
 // ---------------------------------------------------------------------------
 // pothole threshold and labelling
 
+hipError_t launch_road_window_map(const sgm_road_fit *fit, int W, int H, int nimg, int w, double scale, int32_t *lo,
+                                  hipStream_t s);
 hipError_t launch_road_mask(const float *disp, const sgm_road_fit *fit, int W, int H, int nimg, double f_min,
                             double margin, uint8_t *mask, hipStream_t s);
 size_t pothole_workspace_bytes(int nbins, int nimg);

@@ -116,6 +116,7 @@ def _load_library():
         "sgm_slic_workspace_size": [I, I, I, I, ctypes.POINTER(S)],
         "sgm_slic_batch": [P, P, I, I, I, I, D, I, P, P, P, P, S, P],
         "sgm_road_mask_batch": [P, P, I, I, I, D, D, P, P],
+        "sgm_road_window_map_batch": [P, I, I, I, I, D, P, P],
         "sgm_status_str": [I],
         "sgm_last_error": [],
     }
@@ -314,6 +315,19 @@ def disparity_transform(disp, fit, delta_dt, out=None, stream=None):
     _check(_lib.sgm_disparity_transform_batch(_ptr(d), _ptr(fit), W, H, n, float(delta_dt), _ptr(out),
                                               _stream(stream)), "sgm_disparity_transform_batch")
     return out
+
+
+def road_window_map(fit, width, height, w, scale=1.0, lo=None, stream=None):
+    """Per-pixel window starts int32 [n, H, W] centred on the fitted road
+    plane (fits of maps at 1/scale resolution)."""
+    _need(fit, torch.float64, None, "fit")
+    n = fit.shape[0]
+    if lo is None:
+        lo = torch.empty((n, height, width), dtype=torch.int32, device=fit.device)
+    _need(lo, torch.int32, (n, height, width), "lo")
+    _check(_lib.sgm_road_window_map_batch(_ptr(fit), int(width), int(height), n, int(w), float(scale), _ptr(lo),
+                                          _stream(stream)), "sgm_road_window_map_batch")
+    return lo
 
 
 def road_mask(disp, fit, f_min, margin=float("-inf"), mask=None, stream=None):

@@ -272,6 +272,9 @@ def test_road_calls_validate_before_launch():
     assert lib.sgm_disparity_transform_batch(d, d, 64, 48, 2, float("nan"), d, None) == -1
     assert lib.sgm_disparity_transform_batch(d, d, 64, -48, 2, 0.0, d, None) == -1
     assert lib.sgm_disparity_transform_batch(d, d, 64, 48, 2, 0.0, None, None) == -1
+    assert lib.sgm_road_window_map_batch(d, 64, 48, 2, 0, 1.0, d, None) == -1
+    assert lib.sgm_road_window_map_batch(d, 64, 48, 2, 16, -1.0, d, None) == -1
+    assert lib.sgm_road_window_map_batch(None, 64, 48, 2, 16, 1.0, d, None) == -1
     assert lib.sgm_road_mask_batch(d, d, 64, 48, 2, float("nan"), 0.0, d, None) == -1
     assert lib.sgm_road_mask_batch(d, None, 64, 48, 2, 1.0, 0.0, d, None) == -1
     assert lib.sgm_road_mask_batch(d, d, 64, 48, 0, 1.0, 0.0, d, None) == -1

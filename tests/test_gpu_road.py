@@ -269,42 +269,66 @@ def test_full_size_batch_of_16(lib):
     np.testing.assert_allclose(D2[9].cpu().numpy(), want, rtol=2.5e-7, atol=1e-9)
 
 
-def test_perspective_pipeline_from_images_alone(lib):
+def _check_fits(lib, fits, tols, D, min_disp, margin):
+    """Each fit of a fit-then-refit sequence against the oracle, the oracle
+    given the GPU's previous fit as its prior."""
+    prior = None
+    for k, tol in enumerate((math.inf,) + tuple(tols)):
+        f = lib.road_fit_dicts(fits[k])[0]
+        _close_fit(f, oroad.fit_road(D, None, min_disp, margin, prior, tol), D)
+        prior = (f["a0"], f["a1"], f["phi"])
+    return lib.road_fit_dicts(fits[-1])[0]
+
+
+@pytest.mark.parametrize("windows", ["row", "pixel"])
+def test_perspective_pipeline_from_images_alone(lib, windows):
     """The self-contained perspective-transformed path on a 1280x720 road
     pair: every stage equals the oracle on the previous stage's GPU output
-    (4x4 reduction and quarter-scale SGM bit-exact, coarse fit, windows at
-    scale 4, windowed SGM bit-exact, refit on D1, eq. (13)), and the coarse
-    fit finds the scene's own road line."""
+    (4x4 reduction and quarter-scale SGM bit-exact, coarse fit and refit,
+    row windows or per-pixel windows from the plane at scale 4, windowed
+    SGM bit-exact, fit and refits on D1, eq. (13)), and the coarse fit finds
+    the scene's own road line."""
     import torch
     from paper_2012_10802_amd.road_pipeline import PerspectiveMatcher
     seed = 5
     sc = synth.scene_for_config("road1280", seed)
     ps = synth.make_pair(sc, seed)
-    pm = PerspectiveMatcher(1280, 720, ndisp=128, w=24, census=7, npaths=8, p1=10, p2=120, delta_dt=20.0)
-    dint, dsub, d2 = pm.match(_dev(ps.left), _dev(ps.right))
+    pm = PerspectiveMatcher(1280, 720, ndisp=128, w=24, census=7, npaths=8, p1=10, p2=120, windows=windows,
+                            delta_dt=20.0)
+    dint, dsub, d2 = (t[0] for t in pm.match(_dev(ps.left), _dev(ps.right)))
     torch.cuda.synchronize()
     lc, rc = oracle.downsample4(ps.left), oracle.downsample4(ps.right)
-    np.testing.assert_array_equal(pm.left_c.cpu().numpy(), lc)
-    np.testing.assert_array_equal(pm.right_c.cpu().numpy(), rc)
+    np.testing.assert_array_equal(pm.left_c[0].cpu().numpy(), lc)
+    np.testing.assert_array_equal(pm.right_c[0].cpu().numpy(), rc)
     ci, cs = oracle.sgm(lc, rc, 7, 32, 8, 10, 120)
-    np.testing.assert_array_equal(pm.coarse_int.cpu().numpy().view(np.uint16), ci)
-    np.testing.assert_allclose(pm.coarse_sub.cpu().numpy(), cs, rtol=0, atol=1e-4)
-    cmap = pm.coarse_sub.cpu().numpy()
-    cf = lib.road_fit_dicts(pm.coarse_fit)[0]
-    _close_fit(cf, oroad.fit_road(cmap, None, 0.5, 4.0), cmap)
+    np.testing.assert_array_equal(pm.coarse_int[0].cpu().numpy().view(np.uint16), ci)
+    np.testing.assert_allclose(pm.coarse_sub[0].cpu().numpy(), cs, rtol=0, atol=1e-4)
+    cmap = pm.coarse_sub[0].cpu().numpy()
+    cf = _check_fits(lib, pm.coarse_fits, pm.coarse_tols, cmap, 0.5, 4.0)
     a0, a1, phi = ps.road_params
     assert abs(cf["phi"] - phi) < math.radians(0.2) and abs(4 * cf["a0"] - a0) < 1.0
-    want = oracle.window_from_road(4 * cf["a0"], cf["a1"], cf["phi"], 1280, 720, 24, 0)
-    arg = _floor_arg(4 * cf["a0"], cf["a1"], cf["phi"], 1280, 720, 24, 0, 0.0)
-    edge = np.abs(arg - np.rint(arg)) < 1e-6
-    d_lo = pm.d_lo.cpu().numpy()
-    np.testing.assert_array_equal(d_lo[~edge], want[~edge])
-    oi, osub = oracle.sgm(ps.left, ps.right, 7, 24, 8, 10, 120, d_lo)
+    if windows == "row":
+        want = oracle.window_from_road(4 * cf["a0"], cf["a1"], cf["phi"], 1280, 720, 24, 0)
+        arg = _floor_arg(4 * cf["a0"], cf["a1"], cf["phi"], 1280, 720, 24, 0, 0.0)
+        edge = np.abs(arg - np.rint(arg)) < 1e-6
+        d_lo = pm.d_lo[0].cpu().numpy()
+        np.testing.assert_array_equal(d_lo[~edge], want[~edge])
+        oi, osub = oracle.sgm(ps.left, ps.right, 7, 24, 8, 10, 120, d_lo)
+    else:
+        lo = pm.lo[0].cpu().numpy()
+        want = oroad.window_map(cf["a0"], cf["a1"], cf["phi"], 1280, 720, 16, 4.0)
+        f = oroad.road_disparity(4 * cf["a0"], cf["a1"], cf["phi"], 1280, 720) + 0.5
+        edge = np.abs(f - np.rint(f)) < 1e-6
+        np.testing.assert_array_equal(lo[~edge], want[~edge])
+        oi, osub = oracle.sgm_win(ps.left, ps.right, 7, 16, 8, 10, 120, lo)
+        # the windows hold the scene's road: ground truth inside them on the road
+        road = ps.road & ~ps.pothole
+        inside = (ps.gt >= lo) & (ps.gt <= lo + 15)
+        assert inside[road].mean() > 0.999
     np.testing.assert_array_equal(dint.cpu().numpy().view(np.uint16), oi)
     np.testing.assert_allclose(dsub.cpu().numpy(), osub, rtol=0, atol=1e-4)
     D1 = dsub.cpu().numpy()
-    f = lib.road_fit_dicts(pm.fit)[0]
-    _close_fit(f, oroad.fit_road(D1, None, 2.0, 16.0), D1)
+    f = _check_fits(lib, pm.fits, pm.fine_tols, D1, 2.0, 16.0)
     np.testing.assert_allclose(d2.cpu().numpy(), oroad.transform(D1, f["a0"], f["a1"], f["phi"], 20.0),
                                rtol=2.5e-7, atol=1e-9)
 
@@ -350,3 +374,44 @@ def test_refit_over_the_first_fits_road(lib):
         prior = got
     a0, a1, phi = ps.road_params
     assert abs(prior["a1"] - a1) < 2e-3 and abs(prior["phi"] - phi) < 2e-3
+
+
+def test_window_map_matches_oracle(lib):
+    """Per-pixel windows from device fits (scale 1 and 4) equal the oracle's
+    from the same parameters, except where f + 1/2 lies within 1e-6 of an
+    integer; a failed fit gives zeros."""
+    rng = np.random.default_rng(21)
+    W, H = 160, 120
+    Ds = [(oroad.road_disparity(a0, a1, math.radians(r), W, H) + rng.normal(0, 0.2, (H, W))).astype(np.float32)
+          for a0, a1, r in ((10.0, 0.1, 2.5), (20.0, 0.15, -1.0))]
+    Ds = np.stack(Ds + [np.zeros((H, W), np.float32)])
+    fit = lib.road_fit(_dev(Ds), None, 0.5)
+    fs = lib.road_fit_dicts(fit)
+    for s_ in (1.0, 4.0):
+        Wf, Hf = int(W * s_), int(H * s_)
+        lo = lib.road_window_map(fit, Wf, Hf, 16, scale=s_).cpu().numpy()
+        for i in range(2):
+            f = fs[i]
+            want = oroad.window_map(f["a0"], f["a1"], f["phi"], Wf, Hf, 16, s_)
+            x = oroad.road_disparity(s_ * f["a0"], f["a1"], f["phi"], Wf, Hf) + 0.5
+            edge = np.abs(x - np.rint(x)) < 1e-6
+            np.testing.assert_array_equal(lo[i][~edge], want[~edge])
+        assert not lo[2].any()
+
+
+def test_perspective_pipeline_batch_equals_single_frames(lib):
+    """A batch of three frames gives, frame by frame, what batches of one
+    give (per-pixel windows)."""
+    import torch
+    from paper_2012_10802_amd.road_pipeline import PerspectiveMatcher
+    ps = [synth.make_pair(synth.scene_for_config("road640", s), s) for s in (41, 42, 43)]
+    L = _dev(np.stack([p.left for p in ps]))
+    R = _dev(np.stack([p.right for p in ps]))
+    pm3 = PerspectiveMatcher(640, 480, batch=3, ndisp=64)
+    out3 = [t.clone() for t in pm3.match(L, R)]
+    pm1 = PerspectiveMatcher(640, 480, batch=1, ndisp=64)
+    for i in range(3):
+        out1 = pm1.match(L[i], R[i])
+        for a, b in zip(out3, out1):
+            assert torch.equal(a[i], b[0])
+        assert torch.equal(pm3.lo[i], pm1.lo[0])

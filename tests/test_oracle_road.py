@@ -228,3 +228,24 @@ def test_refit_on_the_first_fits_road_drops_outliers():
     for _ in range(3):
         ref = road.fit_road(D, None, 0.5, prior=(ref["a0"], ref["a1"], ref["phi"]), tol=0.25)
     assert ref["phi"] == pytest.approx(phi, abs=1e-6) and ref["a1"] == pytest.approx(a1, rel=1e-6)
+
+
+def test_window_map_is_the_row_window_at_the_row_centre():
+    """The per-pixel windows of the road plane: at the row centre (odd width,
+    so cx is a pixel) they equal the C oracle's centred row windows (other
+    code, eq. (3) at u = cx); with no roll every column is that row window;
+    a roll shifts them by a1 sin(phi) per column."""
+    import oracle
+    W, H = 161, 120
+    for a0, a1, deg in ((14.0, 0.1, 0.0), (20.0, 0.12, 2.5), (30.0, 0.1, -3.0)):
+        phi = math.radians(deg)
+        lo = road.window_map(a0, a1, phi, W, H, 16)
+        rows = oracle.window_from_road(a0, a1, phi, W, H, 16, 0)
+        np.testing.assert_array_equal(lo[:, (W - 1) // 2], rows)
+        if deg == 0.0:
+            np.testing.assert_array_equal(lo, np.repeat(rows[:, None], W, 1))
+        else:
+            step = np.diff(lo[-1].astype(int))
+            assert set(np.unique(step)) <= {0, 1, -1} and abs(step.sum() + a1 * math.sin(phi) * (W - 1)) <= 1
+    lo4 = road.window_map(3.0, 0.1, 0.0, 4 * W, 4 * H, 16, scale=4.0)
+    np.testing.assert_array_equal(lo4, road.window_map(12.0, 0.1, 0.0, 4 * W, 4 * H, 16))
