@@ -537,12 +537,24 @@ def perspective_leg(args, log=None):
 
 def detector_leg(args, log=None):
     """The whole method end to end (PotholeDetector): batches of 16 held-out
-    1920x1080 road pairs -> learned-window SGM -> road fit and refits ->
+    1920x1080 road pairs -> perspective-transformed SGM (the paper's) or
+    learned-window SGM -> road fit and refits ->
     road region -> D2 -> threshold -> SLIC / D3 -> labelled potholes, with
     no ground truth used.  Wall time per batch (host clock around
     detect(), synchronised; the learned matcher reads its fallback rows on
     the host once per batch), and the detections against the generator's
     depressions: pixel precision / recall and the share of potholes hit."""
+    import torch
+
+    from paper_2012_10802_amd.pothole_pipeline import PotholeDetector
+
+    dev = torch.device("cuda:0")
+    n, W, H = 16, 1920, 1080
+    return {m: _detector_run(PotholeDetector(W, H, n, matcher=m, delta_pd=0.5, device=dev), n, W, H, m, log)
+            for m in ("perspective", "learned")}
+
+
+def _detector_run(det, n, W, H, matcher, log):
     import math
 
     import numpy as np
@@ -550,11 +562,8 @@ def detector_leg(args, log=None):
     from scipy import ndimage
 
     from paper_2012_10802_amd import synth
-    from paper_2012_10802_amd.pothole_pipeline import PotholeDetector
 
-    dev = torch.device("cuda:0")
-    n, W, H = 16, 1920, 1080
-    det = PotholeDetector(W, H, n, delta_pd=0.5, device=dev)
+    dev = det.device
     times, tp, fp, fn, hit, holes_total = [], 0, 0, 0, 0, 0
     for b in range(2):
         seeds = [20_000_000 + 100 * b + i for i in range(n)]
@@ -593,15 +602,18 @@ def detector_leg(args, log=None):
     ms = 1e3 * float(np.mean(times))
     prec, rec = tp / max(1, tp + fp), tp / max(1, tp + fn)
     if log:
-        log("pothole detector: %.3f ms per batch of %d (%.0f frames/s)" % (ms, n, n / (ms * 1e-3)))
+        log("pothole detector (%s): %.3f ms per batch of %d (%.0f frames/s)" % (matcher, ms, n, n / (ms * 1e-3)))
     return {
+        "matcher": matcher,
         "pairs": 2 * n, "batch": n, "width": W, "height": H,
         "ms_per_batch": round(ms, 3), "frames_per_s": round(n / (ms * 1e-3), 1),
         "pixel_precision": round(prec, 4), "pixel_recall": round(rec, 4),
         "pixel_f1": round(2 * prec * rec / max(1e-12, prec + rec), 4),
         "potholes_hit": hit, "potholes_total": holes_total,
-        "settings": "learned-window SGM (0-191), fit + refits (2, 1 px), road region f >= 2 px, "
-                    "delta_DT 10, 128 bins over 2..18, delta_PD 0.5, SLIC S 16 m 4 x 10",
+        "settings": "%s SGM (0-191), fit + refits (2, 1 px), road region f >= 2 px, "
+                    "delta_DT 10, 128 bins over 2..18, delta_PD 0.5, SLIC S 16 m 4 x 10"
+                    % ("perspective-transformed (windows of 16 on the fitted plane)" if matcher == "perspective"
+                       else "learned-window"),
         "timing": "host wall clock around detect() (synchronised), median of 3 after 2 warm-ups, "
                   "mean over 2 batches",
     }

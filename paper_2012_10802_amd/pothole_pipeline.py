@@ -2,8 +2,10 @@
 batch of pairs of one size, every step a HIP kernel behind the C ABI,
 enqueued on one stream (the learned-window matcher adds its side streams).
 
-  1. disparity D1 (Sec. II-A, II-B): learned-window SGM (the default) or
-     plain full-range batched SGM;
+  1. disparity D1 (Sec. II-A, II-B): the perspective-transformed path (the
+     default: quarter-scale SGM, road fit, per-pixel windows on the fitted
+     road plane, windowed SGM; road_pipeline.PerspectiveMatcher), the
+     learned-window SGM, or plain full-range batched SGM;
   2. road model (Sec. II-C, eq. (11), (12)) fitted to D1 over the pixels
      with d >= min_disp whose match lies `margin` pixels inside the right
      image, then refitted over the pixels within each of `refit_tols` of the
@@ -33,7 +35,7 @@ class PotholeDetector:
     pothole labels int32 [batch, H, W].  Intermediate maps stay available
     as attributes: disp (D1), fit, road, d2, threshold, superpixels, d3."""
 
-    def __init__(self, width, height, batch, ndisp=192, census=7, npaths=8, p1=10, p2=120, matcher="learned",
+    def __init__(self, width, height, batch, ndisp=192, census=7, npaths=8, p1=10, p2=120, matcher="perspective",
                  net=None, delta_dt=10.0, delta_pd=0.5, nbins=128, span=8.0, slic_step=16, slic_m=4.0,
                  slic_iters=10, min_disp=0.5, margin=4.0, f_min=2.0, refit_tols=(2.0, 1.0), device="cuda"):
         self.W, self.H, self.n = int(width), int(height), int(batch)
@@ -43,7 +45,12 @@ class PotholeDetector:
         self.refit_tols = tuple(float(t) for t in refit_tols)
         dev = self.device = torch.device(device)
         n, H, W = self.n, self.H, self.W
-        if matcher == "learned":
+        if matcher == "perspective":
+            from .road_pipeline import PerspectiveMatcher
+            self.matcher = PerspectiveMatcher(W, H, batch=n, ndisp=ndisp, census=census, npaths=npaths, p1=p1,
+                                              p2=p2, windows="pixel", delta_dt=delta_dt, device=device)
+            self._match = self._match_perspective
+        elif matcher == "learned":
             from .learned_window import LearnedWindowMatcher
             self.matcher = LearnedWindowMatcher(W, H, batch=n, ndisp=ndisp, census=census, npaths=npaths, p1=p1,
                                                 p2=p2, net=net, device=device)
@@ -58,7 +65,7 @@ class PotholeDetector:
                                    census=census, npaths=npaths, p1=p1, p2=p2, device=dev)
             self._match = self._match_plain
         else:
-            raise ValueError("matcher must be 'learned' or 'plain'")
+            raise ValueError("matcher must be 'perspective', 'learned' or 'plain'")
         # fits[0] the first fit, fits[i] the refit with refit_tols[i - 1]; fit the last
         self.fits = [torch.empty((n, S.ROAD_FIT_WORDS), dtype=torch.float64, device=dev)
                      for _ in range(1 + len(self.refit_tols))]
@@ -75,6 +82,10 @@ class PotholeDetector:
         self.slic_ws = torch.empty(S.slic_workspace_size(W, H, self.slic_step, n), dtype=torch.uint8, device=dev)
         self.labels = torch.empty((n, H, W), dtype=torch.int32, device=dev)
         self.disp = None
+
+    def _match_perspective(self, left, right, stream=None):
+        dint, dsub, _ = self.matcher.match(left, right, stream=stream)
+        return dint, dsub
 
     def _match_plain(self, left, right, stream=None):
         self._left.copy_(left)

@@ -60,14 +60,15 @@ def test_plain_detector_stage_by_stage():
     np.testing.assert_array_equal(labels[i], opd.label(d3, t["t_s"], road))
 
 
-def test_learned_detector_finds_the_potholes():
-    """Full-size pairs through the learned-window matcher: the road region
-    covers the generator's road, and the pixels marked as potholes are
-    nearly all inside its depressions."""
+@pytest.mark.parametrize("matcher", ["perspective", "learned"])
+def test_detector_finds_the_potholes(matcher):
+    """Full-size pairs through the perspective-transformed or the
+    learned-window matcher: the road region covers the generator's road, and
+    the pixels marked as potholes are nearly all inside its depressions."""
     import torch
     from paper_2012_10802_amd.pothole_pipeline import PotholeDetector
     ps, L, R = _pairs("road1920", [10_000_101, 10_000_102])
-    det = PotholeDetector(1920, 1080, 2, delta_pd=0.5)
+    det = PotholeDetector(1920, 1080, 2, matcher=matcher, delta_pd=0.5)
     labels = det.detect(L, R).cpu().numpy()
     road = det.road.cpu().numpy().astype(bool)
     torch.cuda.synchronize()
