@@ -135,13 +135,6 @@ def run_batch(args):
         stream.synchronize()
         t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
-    road = persp = detector = None
-    if not args.no_road:
-        road = road_model_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
-        persp = perspective_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
-        if os.path.exists(args.weights):
-            detector = detector_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
-
     out = {
         "metric": METRIC,
         "value": round(evals / (ms * 1e-3) / 1e6, 1),
@@ -783,10 +776,12 @@ def main():
     if not args.no_learned and os.path.exists(args.weights):
         learned = learned_vs_plain(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
 
-    road = persp = None
+    road = persp = detector = None
     if not args.no_road:
         road = road_model_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
         persp = perspective_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
+        if os.path.exists(args.weights):
+            detector = detector_leg(args, log=lambda msg: print(msg, file=sys.stderr, flush=True))
 
     out = {
         "metric": METRIC,
