@@ -88,8 +88,9 @@ class PotholeDetector:
         return dint, dsub
 
     def _match_plain(self, left, right, stream=None):
-        self._left.copy_(left)
-        self._right.copy_(right)
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+            self._left.copy_(left)  # the batch reads its own input buffers
+            self._right.copy_(right)
         self.matcher.run(stream=stream)
         return self._dint, self._dsub
 

@@ -113,8 +113,9 @@ class PerspectiveMatcher:
         else:
             S.road_window(self.coarse_fit, self.W, self.H, self.w, self.mode, self.delta_pt, scale=4.0,
                           d_lo=self.d_lo, stream=stream)
-            self.left_f.copy_(left)
-            self.right_f.copy_(right)
+            with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+                self.left_f.copy_(left)  # the batch reads its own input buffers
+                self.right_f.copy_(right)
             self.fine.run(stream=stream)
         self._fit(self.disp_sub, self.fits, self.fine_tols, 4 * self.min_disp, 4 * self.margin, stream)
         S.disparity_transform(self.disp_sub, self.fit, self.delta_dt, out=self.d2, stream=stream)
