@@ -337,7 +337,9 @@ def road_model_leg(args, log=None):
     pd_res = torch.empty((n, sgm.POTHOLE_WORDS), dtype=torch.float64, device=dev)
     pd_ws = torch.empty(sgm.pothole_workspace_size(nbins, n), dtype=torch.uint8, device=dev)
     labels = torch.empty((n, H, W), dtype=torch.int32, device=dev)
+    from paper_2012_10802_amd.pothole_pipeline import SLIC_TOL
     S_slic, m_slic, it_slic = 16, 4.0, 10
+    sp_rounds = torch.empty((n,), dtype=torch.int32, device=dev)
     sp_labels = torch.empty((n, H, W), dtype=torch.int32, device=dev)
     d3 = torch.empty((n, H, W), dtype=torch.float32, device=dev)
     centres = torch.empty((n, sgm.slic_num_centres(W, H, S_slic), 3), dtype=torch.float64, device=dev)
@@ -362,9 +364,10 @@ def road_model_leg(args, log=None):
         sgm.pothole_labels(d2, pd_res, mask=mask, labels=labels)
         if ev:
             ev[5].record()
-        # superpixels on D2 and the superpixel means D3 (SLIC, 10 rounds)
-        sgm.slic(d2, S_slic, m_slic, it_slic, mask=mask, labels=sp_labels, d3=d3, centres=centres,
-                 workspace=sp_ws)
+        # superpixels on D2 and the superpixel means D3 (SLIC, at most 10
+        # rounds, each map stopping once its centres move by <= SLIC_TOL)
+        sgm.slic(d2, S_slic, m_slic, it_slic, mask=mask, tol=SLIC_TOL, labels=sp_labels, d3=d3, centres=centres,
+                 workspace=sp_ws, rounds=sp_rounds)
         if ev:
             ev[6].record()
 
@@ -419,7 +422,8 @@ def road_model_leg(args, log=None):
                       "a1_max_rel": round(max(da1), 6), "a0_max_px": round(max(da0), 4)},
         "pothole": {"threshold_ms": round(thr_ms, 4), "label_ms": round(lab_ms, 4),
                     "slic_ms": round(slic_ms, 4),
-                    "slic": {"S": S_slic, "m": m_slic, "iters": it_slic,
+                    "slic": {"S": S_slic, "m": m_slic, "iters": it_slic, "tol": SLIC_TOL,
+                             "rounds_mean": round(float(sp_rounds.double().mean()), 2),
                              "superpixels_per_map": sgm.slic_num_centres(W, H, S_slic)},
                     "threshold_hbm": {"bytes_per_pixel": 5,
                                       "achieved": round(px * 5 / (thr_ms * 1e-3) / 1e9, 1), "unit": "GB/s"},
@@ -557,7 +561,7 @@ def _detector_run(det, n, W, H, matcher, log):
     from paper_2012_10802_amd import synth
 
     dev = det.device
-    times, tp, fp, fn, hit, holes_total = [], 0, 0, 0, 0, 0
+    times, tp, fp, fn, hit, holes_total, rounds = [], 0, 0, 0, 0, 0, []
     for b in range(2):
         seeds = [20_000_000 + 100 * b + i for i in range(n)]
         L = torch.empty((n, H, W), dtype=torch.uint8, device=dev)
@@ -583,6 +587,7 @@ def _detector_run(det, n, W, H, matcher, log):
             torch.cuda.synchronize()
             reps.append(time.perf_counter() - t0)
         times.append(sorted(reps)[1])
+        rounds += det.slic_rounds.tolist()
         lab = det.labels.cpu().numpy()
         for i, hole in enumerate(truth):
             found = lab[i] > 0
@@ -603,10 +608,11 @@ def _detector_run(det, n, W, H, matcher, log):
         "pixel_precision": round(prec, 4), "pixel_recall": round(rec, 4),
         "pixel_f1": round(2 * prec * rec / max(1e-12, prec + rec), 4),
         "potholes_hit": hit, "potholes_total": holes_total,
+        "slic_rounds_mean": round(float(np.mean(rounds)), 2),
         "settings": "%s SGM (0-191), fit + refits (2, 1 px), road region f >= 2 px, "
-                    "delta_DT 10, 128 bins over 2..18, delta_PD 0.5, SLIC S 16 m 4 x 10"
+                    "delta_DT 10, 128 bins over 2..18, delta_PD 0.5, SLIC S 16 m 4, at most %d rounds, tol %g"
                     % ("perspective-transformed (windows of 16 on the fitted plane)" if matcher == "perspective"
-                       else "learned-window"),
+                       else "learned-window", det.slic_iters, det.slic_tol),
         "timing": "host wall clock around detect() (synchronised), median of 3 after 2 warm-ups, "
                   "mean over 2 batches",
     }

@@ -517,28 +517,36 @@ sgm_status sgm_pothole_label_batch(const float *d2, const uint8_t *mask, int32_t
  * (v(x,y+1) - v(x,y-1))^2 (float64, coordinates clamped; +inf unless the
  * four pixels are used) is strictly below G at the start.  A pixel is used
  * when its mask entry is non-zero (mask NULL: all), its value is finite
- * and |v| < 2048; unused pixels get label -1 and D3 NaN.  Each of `iters`
- * rounds assigns every used pixel of grid cell (i, j) to the nearest of
+ * and |v| < 2048; unused pixels get label -1 and D3 NaN.  Each of up to
+ * `iters` rounds assigns every used pixel of grid cell (i, j) to the nearest of
  * the centres of cells (i+di, j+dj), |di|, |dj| <= 1, in index order, by
  * d = (v - v_c)^2 + ((x - x_c)^2 + (y - y_c)^2) w, w = (m / S)^2, float64
  * without fused multiply-add, first smallest wins; then every centre with
  * pixels moves to their mean position and mean value, the value mean taken
- * over v rounded to multiples of 2^-20 and summed exactly.  Labels are the
- * last assignment's centre indices; D3(p) = value of p's centre after the
- * last update (float32).  The result does not depend on the order of any
- * sum, so it is the same on every run.
+ * over v rounded to multiples of 2^-20 and summed exactly.  The rounds stop
+ * when the residual between the previous and the updated centres has
+ * converged (Sec. II-D): the residual of a round is the largest change
+ * dv^2 + (dx^2 + dy^2) w of a centre with pixels (float64, no fused
+ * multiply-add), and a map's rounds stop after the first whose residual is
+ * <= tol^2.  tol = 0 stops only once no centre moves, which leaves every
+ * result as if all `iters` rounds had run.  Labels are the last
+ * assignment's centre indices; D3(p) = value of p's centre after the last
+ * update (float32).  The result does not depend on the order of any sum,
+ * so it is the same on every run.
  *
  * Buffers: maps float32 [nimg][H][W], mask uint8 [nimg][H][W] or NULL,
  * labels int32 [nimg][H][W], d3 float32 [nimg][H][W], centres float64
- * [nimg][K][3] (x, y, v after the last update); all device.
+ * [nimg][K][3] (x, y, v after the last update), rounds int32 [nimg] (the
+ * rounds each map ran) or NULL; all device.
  */
 sgm_status sgm_slic_workspace_size(int32_t width, int32_t height, int32_t S, int32_t nimg, size_t *bytes);
-/* 2 <= S <= 256, ceil(H/S) <= 65535, m finite and >= 0, 1 <= iters <= 100.
- * workspace: device, 256-byte aligned, at least sgm_slic_workspace_size
- * bytes. */
+/* 2 <= S <= 256, ceil(H/S) <= 65535, m finite and >= 0, 1 <= iters <= 100,
+ * tol finite and >= 0.  workspace: device, 256-byte aligned, at least
+ * sgm_slic_workspace_size bytes.  Every round's kernels are enqueued; those
+ * of a map whose rounds have stopped return at once. */
 sgm_status sgm_slic_batch(const float *d2, const uint8_t *mask, int32_t width, int32_t height, int32_t nimg,
-                          int32_t S, double m, int32_t iters, int32_t *labels, float *d3, double *centres,
-                          void *workspace, size_t workspace_bytes, void *stream);
+                          int32_t S, double m, int32_t iters, double tol, int32_t *rounds, int32_t *labels,
+                          float *d3, double *centres, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Per-row window starts from the road model of eq. (3),
  *   f(u,v) = a0 + a1 (cos(phi) (v - cy) - sin(phi) (u - cx)),

@@ -31,9 +31,16 @@ Readings (the paper gives no constants):
   the value mean is taken from v rounded to multiples of 2^-20 and summed
   exactly (integers), so it does not depend on the summation order; a
   centre without pixels stays;
-* `iters` rounds of assignment then update; labels are those of the last
-  assignment and D3(p) = v_c of p's centre after the last update, rounded
-  to float32.
+* rounds of assignment then update, at most `iters` of them; the paper
+  iterates until the residual between the previous and the updated centres
+  converges: here the residual of a round is the largest over the centres
+  with pixels of dv^2 + (dx^2 + dy^2) w (the change of the centre in the
+  metric of the assignment, float64, no fused multiply-add), and the
+  rounds stop after the first whose residual is <= tol^2.  tol = 0 stops
+  only when no centre moved, which changes no result (the next round would
+  repeat the last one);
+* labels are those of the last assignment and D3(p) = v_c of p's centre
+  after the last update, rounded to float32.
 """
 from __future__ import annotations
 
@@ -138,13 +145,36 @@ def update(D, u, lab, cx, cy, cv):
     return cx, cy, cv, cnt
 
 
-def slic(d2, S, m, iters, mask=None):
-    """(labels int64 [H][W], D3 float32 [H][W], centres (x, y, v) float64)."""
+def residual(S, m, old, new, cnt):
+    """Largest change of a centre with pixels, dv^2 + (dx^2 + dy^2) w."""
+    t = m / S
+    w = t * t
+    has = cnt > 0
+    if not has.any():
+        return 0.0
+    dx = new[0][has] - old[0][has]
+    dy = new[1][has] - old[1][has]
+    dv = new[2][has] - old[2][has]
+    return float(np.max(dv * dv + (dx * dx + dy * dy) * w))
+
+
+def slic(d2, S, m, iters, mask=None, tol=0.0, info=None):
+    """(labels int64 [H][W], D3 float32 [H][W], centres (x, y, v) float64).
+    `info`, a dict, receives "rounds" (the rounds run) and "residuals"."""
     D, u = used(d2, mask)
     cx, cy, cv = init_centres(D, u, S)
     lab = None
+    tol2 = tol * tol
+    res = []
     for _ in range(iters):
         lab = assign(D, u, S, m, cx, cy, cv)
-        cx, cy, cv, _ = update(D, u, lab, cx, cy, cv)
+        nx, ny, nv, cnt = update(D, u, lab, cx, cy, cv)
+        res.append(residual(S, m, (cx, cy, cv), (nx, ny, nv), cnt))
+        cx, cy, cv = nx, ny, nv
+        if res[-1] <= tol2:
+            break
+    if info is not None:
+        info["rounds"] = len(res)
+        info["residuals"] = res
     d3 = np.where(lab >= 0, cv[np.maximum(lab, 0)], np.nan).astype(np.float32)
     return lab, d3, (cx, cy, cv)

@@ -649,14 +649,17 @@ sgm_status sgm_slic_workspace_size(int32_t W, int32_t H, int32_t S, int32_t nimg
 }
 
 sgm_status sgm_slic_batch(const float *d2, const uint8_t *mask, int32_t W, int32_t H, int32_t nimg, int32_t S,
-                          double m, int32_t iters, int32_t *labels, float *d3, double *centres, void *ws,
-                          size_t ws_bytes, void *stream)
+                          double m, int32_t iters, double tol, int32_t *rounds, int32_t *labels, float *d3,
+                          double *centres, void *ws, size_t ws_bytes, void *stream)
 {
     if (!d2 || !labels || !d3 || !centres) return fail(SGM_ERR_INVALID, "d2, labels, d3 and centres must not be NULL");
     sgm_status st = check_slic(W, H, S, nimg);
     if (st != SGM_OK) return st;
     if (!isfinite(m) || m < 0.0) return fail(SGM_ERR_INVALID, "m must be finite and >= 0");
-    if (iters < 1 || iters > 100) return fail(SGM_ERR_INVALID, "iters %d not in [1, 100]", iters);
+    if (iters < 1 || iters > sgm::kSlicMaxRounds)
+        return fail(SGM_ERR_INVALID, "iters %d not in [1, %d]", iters, sgm::kSlicMaxRounds);
+    if (!(tol >= 0.0) || !isfinite(tol)) return fail(SGM_ERR_INVALID, "tol must be finite and >= 0");
+    if (rounds && !is_aligned(rounds, 4)) return fail(SGM_ERR_INVALID, "rounds misaligned");
     if (!ws) return fail(SGM_ERR_INVALID, "workspace is NULL");
     if (!is_aligned(ws, 256)) return fail(SGM_ERR_INVALID, "workspace must be 256-byte aligned");
     if (!is_aligned(d2, 4) || !is_aligned(labels, 4) || !is_aligned(d3, 4) || !is_aligned(centres, 8))
@@ -665,7 +668,8 @@ sgm_status sgm_slic_batch(const float *d2, const uint8_t *mask, int32_t W, int32
     if (ws_bytes < need)
         return fail(SGM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
     if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
-    hipError_t e = sgm::launch_slic(d2, mask, W, H, nimg, S, m, iters, labels, d3, centres, ws, (hipStream_t)stream);
+    hipError_t e = sgm::launch_slic(d2, mask, W, H, nimg, S, m, iters, tol, rounds, labels, d3, centres, ws,
+                                    (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "slic launch");
 }
 

@@ -138,9 +138,11 @@ hipError_t launch_road_window_map(const sgm_road_fit *fit, int W, int H, int nim
 hipError_t launch_road_mask(const float *disp, const sgm_road_fit *fit, int W, int H, int nimg, double f_min,
                             double margin, uint8_t *mask, hipStream_t s);
 size_t pothole_workspace_bytes(int nbins, int nimg);
+constexpr int kSlicMaxRounds = 100;  // the most SLIC rounds one call runs
 size_t slic_workspace_bytes(int W, int H, int S, int nimg);
 hipError_t launch_slic(const float *d2, const uint8_t *mask, int W, int H, int nimg, int S, double m, int iters,
-                       int32_t *labels, float *d3, double *centres, void *ws, hipStream_t s);
+                       double tol, int32_t *rounds, int32_t *labels, float *d3, double *centres, void *ws,
+                       hipStream_t s);
 hipError_t launch_pothole_threshold(const float *d2, const uint8_t *mask, int W, int H, int nimg, double lo,
                                     double b, int nbins, double delta_pd, sgm_pothole_threshold *out,
                                     double *curve, void *ws, hipStream_t s);

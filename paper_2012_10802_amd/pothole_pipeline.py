@@ -18,8 +18,10 @@ enqueued on one stream (the learned-window matcher adds its side streams).
   4. the threshold t_r of eq. (14), (15) from D2's vectors over the road
      region, on `nbins` bins spanning delta_DT +- span, and
      t_s = t_r - delta_PD;
-  5. SLIC superpixels on D2 over the road region (Sec. II-D) and their
-     means D3 (Sec. II-E);
+  5. SLIC superpixels on D2 over the road region (Sec. II-D), at most
+     `slic_iters` rounds, each map stopping once its largest centre change
+     is within `slic_tol` (the residual of Sec. II-D), and their means D3
+     (Sec. II-E);
   6. potholes: the 8-connected components of D3 below t_s, labelled
      1 + the smallest row-major index of the component.
 """
@@ -29,18 +31,24 @@ import torch
 
 from . import sgm as S
 
+# SLIC stops once no centre moves by more than this (in disparities, with
+# the spatial part weighted by (m / S)^2) in one round
+SLIC_TOL = 0.25
+
 
 class PotholeDetector:
     """detect(left, right) on uint8 device stacks [batch, H, W]; returns the
     pothole labels int32 [batch, H, W].  Intermediate maps stay available
-    as attributes: disp (D1), fit, road, d2, threshold, superpixels, d3."""
+    as attributes: disp (D1), fit, road, d2, threshold, superpixels, d3,
+    slic_rounds (the SLIC rounds each map ran)."""
 
     def __init__(self, width, height, batch, ndisp=192, census=7, npaths=8, p1=10, p2=120, matcher="perspective",
                  net=None, delta_dt=10.0, delta_pd=0.5, nbins=128, span=8.0, slic_step=16, slic_m=4.0,
-                 slic_iters=10, min_disp=0.5, margin=4.0, f_min=2.0, refit_tols=(2.0, 1.0), device="cuda"):
+                 slic_iters=10, slic_tol=SLIC_TOL, min_disp=0.5, margin=4.0, f_min=2.0, refit_tols=(2.0, 1.0), device="cuda"):
         self.W, self.H, self.n = int(width), int(height), int(batch)
         self.delta_dt, self.delta_pd, self.nbins, self.span = float(delta_dt), float(delta_pd), int(nbins), span
         self.slic_step, self.slic_m, self.slic_iters = int(slic_step), float(slic_m), int(slic_iters)
+        self.slic_tol = float(slic_tol)
         self.min_disp, self.margin, self.f_min = float(min_disp), float(margin), float(f_min)
         self.refit_tols = tuple(float(t) for t in refit_tols)
         dev = self.device = torch.device(device)
@@ -80,6 +88,7 @@ class PotholeDetector:
         self.centres = torch.empty((n, S.slic_num_centres(W, H, self.slic_step), 3), dtype=torch.float64,
                                    device=dev)
         self.slic_ws = torch.empty(S.slic_workspace_size(W, H, self.slic_step, n), dtype=torch.uint8, device=dev)
+        self.slic_rounds = torch.empty((n,), dtype=torch.int32, device=dev)
         self.labels = torch.empty((n, H, W), dtype=torch.int32, device=dev)
         self.disp = None
 
@@ -106,7 +115,8 @@ class PotholeDetector:
         S.pothole_threshold(self.d2, self.delta_dt - self.span, self.delta_dt + self.span, self.nbins,
                             self.delta_pd, mask=self.road, result=self.threshold, workspace=self.thr_ws,
                             stream=stream)
-        S.slic(self.d2, self.slic_step, self.slic_m, self.slic_iters, mask=self.road, labels=self.superpixels,
-               d3=self.d3, centres=self.centres, workspace=self.slic_ws, stream=stream)
+        S.slic(self.d2, self.slic_step, self.slic_m, self.slic_iters, mask=self.road, tol=self.slic_tol,
+               labels=self.superpixels, d3=self.d3, centres=self.centres, workspace=self.slic_ws,
+               rounds=self.slic_rounds, stream=stream)
         S.pothole_labels(self.d3, self.threshold, mask=self.road, labels=self.labels, stream=stream)
         return self.labels

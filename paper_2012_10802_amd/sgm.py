@@ -114,7 +114,7 @@ def _load_library():
         "sgm_pothole_threshold_batch": [P, P, I, I, I, D, D, I, D, P, P, P, S, P],
         "sgm_pothole_label_batch": [P, P, I, I, I, P, P, P],
         "sgm_slic_workspace_size": [I, I, I, I, ctypes.POINTER(S)],
-        "sgm_slic_batch": [P, P, I, I, I, I, D, I, P, P, P, P, S, P],
+        "sgm_slic_batch": [P, P, I, I, I, I, D, I, D, P, P, P, P, P, S, P],
         "sgm_road_mask_batch": [P, P, I, I, I, D, D, P, P],
         "sgm_road_window_map_batch": [P, I, I, I, I, D, P, P],
         "sgm_status_str": [I],
@@ -422,9 +422,13 @@ def slic_num_centres(width, height, S) -> int:
     return ((int(width) + S - 1) // S) * ((int(height) + S - 1) // S)
 
 
-def slic(d2, S, m, iters, mask=None, labels=None, d3=None, centres=None, workspace=None, stream=None):
-    """SLIC on float32 device maps [H, W] or [n, H, W].  Returns (labels
-    int32 [n, H, W], d3 float32 [n, H, W], centres float64 [n, K, 3])."""
+def slic(d2, S, m, iters, mask=None, tol=0.0, labels=None, d3=None, centres=None, workspace=None, rounds=None,
+         stream=None):
+    """SLIC on float32 device maps [H, W] or [n, H, W], at most `iters`
+    rounds, stopping per map after the first round whose largest centre
+    change is <= tol^2.  Returns (labels int32 [n, H, W], d3 float32
+    [n, H, W], centres float64 [n, K, 3]); `rounds`, an int32 [n] device
+    tensor, receives the rounds each map ran."""
     d = _maps(d2, torch.float32, "d2")
     n, H, W = d.shape
     if mask is not None:
@@ -441,11 +445,14 @@ def slic(d2, S, m, iters, mask=None, labels=None, d3=None, centres=None, workspa
     _need(labels, torch.int32, (n, H, W), "labels")
     _need(d3, torch.float32, (n, H, W), "d3")
     _need(centres, torch.float64, (n, K, 3), "centres")
+    if rounds is not None:
+        _need(rounds, torch.int32, (n,), "rounds")
     if workspace is None:
         workspace = torch.empty(slic_workspace_size(W, H, S, n), dtype=torch.uint8, device=d.device)
     _need(workspace, torch.uint8, None, "workspace")
-    _check(_lib.sgm_slic_batch(_ptr(d), _ptr(mask), W, H, n, int(S), float(m), int(iters), _ptr(labels), _ptr(d3),
-                               _ptr(centres), _ptr(workspace), workspace.numel(), _stream(stream)),
+    _check(_lib.sgm_slic_batch(_ptr(d), _ptr(mask), W, H, n, int(S), float(m), int(iters), float(tol),
+                               _ptr(rounds), _ptr(labels), _ptr(d3), _ptr(centres), _ptr(workspace),
+                               workspace.numel(), _stream(stream)),
            "sgm_slic_batch")
     return labels, d3, centres
 

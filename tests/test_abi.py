@@ -322,17 +322,20 @@ def test_slic_calls_validate_before_launch():
     d = ctypes.c_void_p(1 << 20)
     n = ctypes.c_size_t()
     assert lib.sgm_slic_workspace_size(1920, 1080, 16, 16, ctypes.byref(n)) == 0
-    assert n.value == 120 * 68 * 16 * 4 * 8
+    assert n.value == 120 * 68 * 16 * 4 * 8 + 16 * 100 * 8  # accumulators, then residuals of 100 rounds
     assert lib.sgm_slic_workspace_size(64, 48, 1, 1, ctypes.byref(n)) == -1
     assert lib.sgm_slic_workspace_size(64, 48, 257, 1, ctypes.byref(n)) == -1
     ws = sgm.slic_workspace_size(64, 48, 8, 2)
     B = lib.sgm_slic_batch
-    assert B(d, None, 64, 48, 2, 8, 10.0, 5, d, d, None, d, ws, None) == -1
-    assert B(d, None, 64, 48, 2, 8, -1.0, 5, d, d, d, d, ws, None) == -1
-    assert B(d, None, 64, 48, 2, 8, float("nan"), 5, d, d, d, d, ws, None) == -1
-    assert B(d, None, 64, 48, 2, 8, 10.0, 0, d, d, d, d, ws, None) == -1
-    assert B(d, None, 64, 48, 2, 8, 10.0, 101, d, d, d, d, ws, None) == -1
-    assert B(d, None, 64, 48, 2, 8, 10.0, 5, d, d, d, d, ws - 8, None) == -4
-    assert B(d, None, 64, 48, 2, 8, 10.0, 5, d, d, ctypes.c_void_p((1 << 20) + 4), d, ws, None) == -1
-    assert B(d, None, 64, 48, 2, 8, 10.0, 5, d, d, d, None, ws, None) == -1
-    assert B(d, None, 4, 300000, 1, 2, 10.0, 5, d, d, d, d, ws, None) == -2
+    assert B(d, None, 64, 48, 2, 8, 10.0, 5, 0.0, None, d, d, None, d, ws, None) == -1
+    assert B(d, None, 64, 48, 2, 8, -1.0, 5, 0.0, None, d, d, d, d, ws, None) == -1
+    assert B(d, None, 64, 48, 2, 8, float("nan"), 5, 0.0, None, d, d, d, d, ws, None) == -1
+    assert B(d, None, 64, 48, 2, 8, 10.0, 0, 0.0, None, d, d, d, d, ws, None) == -1
+    assert B(d, None, 64, 48, 2, 8, 10.0, 101, 0.0, None, d, d, d, d, ws, None) == -1
+    for tol in (-0.5, float("nan"), float("inf")):
+        assert B(d, None, 64, 48, 2, 8, 10.0, 5, tol, None, d, d, d, d, ws, None) == -1
+    assert B(d, None, 64, 48, 2, 8, 10.0, 5, 0.0, ctypes.c_void_p((1 << 20) + 2), d, d, d, d, ws, None) == -1
+    assert B(d, None, 64, 48, 2, 8, 10.0, 5, 0.0, None, d, d, d, d, ws - 8, None) == -4
+    assert B(d, None, 64, 48, 2, 8, 10.0, 5, 0.0, None, d, d, ctypes.c_void_p((1 << 20) + 4), d, ws, None) == -1
+    assert B(d, None, 64, 48, 2, 8, 10.0, 5, 0.0, None, d, d, d, None, ws, None) == -1
+    assert B(d, None, 4, 300000, 1, 2, 10.0, 5, 0.0, None, d, d, d, d, ws, None) == -2

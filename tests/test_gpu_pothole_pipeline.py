@@ -54,7 +54,9 @@ def test_plain_detector_stage_by_stage():
     t = sgm.pothole_threshold_dicts(det.threshold)[i]
     wt = opd.threshold(d2, 2.0, 18.0, 128, 0.5, road)
     assert (t["status"], t["k"], t["n1"], t["n2"], t["t_s"]) == (wt["status"], wt["k"], wt["n1"], wt["n2"], wt["t_s"])
-    sp, d3, _ = oslic.slic(d2, 16, 4.0, 6, road)
+    info = {}
+    sp, d3, _ = oslic.slic(d2, 16, 4.0, 6, road, tol=det.slic_tol, info=info)
+    assert int(det.slic_rounds[i]) == info["rounds"]
     np.testing.assert_array_equal(det.superpixels[i].cpu().numpy(), sp)
     np.testing.assert_array_equal(det.d3[i].cpu().numpy(), d3)
     np.testing.assert_array_equal(labels[i], opd.label(d3, t["t_s"], road))

@@ -98,3 +98,69 @@ def test_mask_nan_and_shift():
     np.testing.assert_array_equal(lab2, lab)
     ok = lab >= 0
     np.testing.assert_allclose(d32[ok], d3[ok] + 4.0, rtol=0, atol=1e-5)
+
+
+def test_hand_worked_convergence():
+    """The stopping rule on the hand-worked maps: the residuals of each
+    round and the rounds run at several tolerances, worked by hand; stopping
+    at tol = 0 leaves the hand-worked result unchanged."""
+    with open(os.path.join(GOLD, "hand_slic.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        D = np.array(c["disp"], np.float32)
+        for tol, rounds in c["rounds_at_tol"]:
+            info = {}
+            lab, d3, (cx, cy, cv) = slic.slic(D, c["S"], c["m"], 10, tol=tol, info=info)
+            assert info["rounds"] == rounds, (c["note"][:30], tol)
+            np.testing.assert_array_equal(info["residuals"], c["residuals"][:rounds])
+            np.testing.assert_array_equal(lab, c["labels"])
+            np.testing.assert_array_equal(np.stack([cx, cy, cv], 1), c["centres"])
+        info = {}
+        slic.slic(D, c["S"], c["m"], 1, tol=0.0, info=info)
+        assert info["rounds"] == 1  # never more than `iters`
+
+
+def test_exact_stop_changes_nothing():
+    """Rounds run from the bare steps for a fixed count agree with the
+    early-stopped result at tol = 0 whenever the count reaches the stop; a
+    positive tol stops no later; residuals are the largest centre moves."""
+    D, _ = _two_level(seed=8, H=48, W=64)
+    S, m = 8, 2.0
+    Dd, u = slic.used(D)
+    cx, cy, cv = slic.init_centres(Dd, u, S)
+    w = (m / S) ** 2
+    moves = []
+    for _ in range(40):
+        lab = slic.assign(Dd, u, S, m, cx, cy, cv)
+        nx, ny, nv, cnt = slic.update(Dd, u, lab, cx, cy, cv)
+        e = 0.0
+        for k in np.flatnonzero(cnt):
+            e = max(e, (nv[k] - cv[k]) ** 2 + ((nx[k] - cx[k]) ** 2 + (ny[k] - cy[k]) ** 2) * w)
+        moves.append(e)
+        cx, cy, cv = nx, ny, nv
+        if e == 0.0:
+            break
+    assert moves[-1] == 0.0, "this map settles within 40 rounds"
+    info = {}
+    lab0, d30, (ax, ay, av) = slic.slic(D, S, m, 40, tol=0.0, info=info)
+    assert info["rounds"] == len(moves)
+    np.testing.assert_array_equal(info["residuals"], moves)
+    np.testing.assert_array_equal(np.stack([ax, ay, av]), np.stack([cx, cy, cv]))
+    np.testing.assert_array_equal(lab0, lab)
+    for tol in (0.05, 0.3, 1.0):
+        info = {}
+        slic.slic(D, S, m, 40, tol=tol, info=info)
+        r = info["rounds"]
+        assert all(e > tol * tol for e in moves[:r - 1]) and moves[r - 1] <= tol * tol
+
+
+def test_centre_without_pixels_does_not_block_the_stop():
+    """A centre on a masked-out corner keeps a NaN value and takes no pixels;
+    it takes no part in the residual, so the rounds still stop."""
+    D = np.array([[1, 1, 5, 5]] * 4, np.float32)
+    mask = np.ones((4, 4), np.uint8)
+    mask[2:, 2:] = 0
+    info = {}
+    lab, _, (cx, cy, cv) = slic.slic(D, 2, 0.0, 10, mask, tol=0.0, info=info)
+    assert np.isnan(cv).any() and (lab[2:, 2:] == -1).all()
+    assert info["rounds"] < 10
