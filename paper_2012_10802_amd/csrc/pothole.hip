@@ -1,6 +1,7 @@
 // Pothole threshold and labelling on the transformed disparity map D2
-// (Sec. II-E, eq. (14), (15)), applied to D2 pixel by pixel (the paper
-// applies it to SLIC superpixels, which are not built here).
+// (Sec. II-E, eq. (14), (15)): the threshold from D2's vectors, the
+// labelling of any map below it (D2 pixel by pixel, or the superpixel
+// means D3).
 //
 // Vectors g = [D2(p), sum of D2 over the 8-neighbourhood] of pixels whose
 // 3x3 neighbourhood is inside the image, selected and finite.  For a
@@ -25,8 +26,17 @@
 //   k_pd_label_*  8-connected components of D2 < t_s by union-find with
 //                 atomicMin on parent links (parents always point to a
 //                 smaller index, so every find ends and the root of a
-//                 component is its smallest index): init, union with the
-//                 four preceding neighbours, flatten to the root, name.
+//                 component is its smallest index):
+//                   local    per 32 x 32 tile, union-find in LDS over the
+//                            edges inside the tile; every pixel points at
+//                            its tile component's smallest pixel;
+//                   union    the edges between tiles (only tile-border
+//                            pixels have any), on the global forest;
+//                   flatten  every pixel to its root;
+//                   name     root + 1.
+//                 Row-major order inside a tile agrees with the image's,
+//                 so a tile component's root is its smallest image index
+//                 and the global roots come out as in a pixel-level pass.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -244,7 +254,8 @@ __global__ __launch_bounds__(64) void k_pd_select(const double *__restrict__ his
     out[img] = r;
 }
 
-__device__ inline int pd_find(const int32_t *lab, int x)
+template <typename T>
+__device__ inline int pd_find(const T *lab, int x)
 {
     int p = lab[x];
     while (p != x) {
@@ -254,50 +265,124 @@ __device__ inline int pd_find(const int32_t *lab, int x)
     return x;
 }
 
-__global__ void k_pd_label_init(const float *__restrict__ d2, const uint8_t *__restrict__ mask, int W, int H,
-                                const sgm_pothole_threshold *__restrict__ thr, int32_t *__restrict__ lab)
+// link the roots of a and c, the larger under the smaller; a failed link
+// (the root gained a parent meanwhile) retries from the new, smaller value
+template <typename T>
+__device__ inline void pd_link(T *lab, int a, int c)
 {
-    const int img = blockIdx.y;
-    const int n = W * H;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const size_t at = (size_t)img * n + p;
-    const sgm_pothole_threshold r = thr[img];
-    const float d = d2[at];
-    const bool fg = r.status == 0 && (!mask || mask[at] != 0) && finite_f(d) && (double)d < r.t_s;
-    lab[at] = fg ? p : -1;
+    a = pd_find(lab, a);
+    c = pd_find(lab, c);
+    while (a != c) {
+        if (a < c) {
+            const int old = atomicMin(&lab[c], a);
+            if (old == c) break;
+            c = pd_find(lab, old);
+        } else {
+            const int old = atomicMin(&lab[a], c);
+            if (old == a) break;
+            a = pd_find(lab, old);
+        }
+    }
 }
 
-__global__ void k_pd_label_union(int W, int H, int32_t *__restrict__ lab_all)
+constexpr int kLabTile = 32;                                        // tile side, a power of two
+constexpr int kLabThreads = 256;
+constexpr int kLabRowsPerPass = kLabThreads / kLabTile;             // 8
+constexpr int kLabPasses = kLabTile * kLabTile / kLabThreads;       // 4
+
+// Edges linked: a pixel's left and upper neighbours always, its upper-left
+// one only when neither the upper nor the left neighbour is foreground, its
+// upper-right one only when the upper one is not: a skipped diagonal joins
+// pixels already joined through the upper (or left) neighbour, whose own
+// left (or upper) edge is always linked, so the components are those of
+// all 8-neighbour edges.
+//
+// One 32 x 32 tile per workgroup (tiles in row-major order along x, maps
+// along y): foreground test, union-find in LDS over the tile's own edges,
+// then every pixel's entry = the image index of its tile component's root
+// (-1 off the foreground).
+__global__ __launch_bounds__(kLabThreads) void k_pd_label_local(const float *__restrict__ d2,
+                                                                const uint8_t *__restrict__ mask, int W, int H,
+                                                                const sgm_pothole_threshold *__restrict__ thr,
+                                                                int32_t *__restrict__ lab)
 {
+    __shared__ int t[kLabTile * kLabTile];
     const int img = blockIdx.y;
-    const int n = W * H;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    int32_t *lab = lab_all + (size_t)img * n;
-    if (lab[p] < 0) return;
-    const int y = p / W, x = p - y * W;
-    // the four neighbours that precede p in row-major order
-    const int dx[4] = {-1, -1, 0, 1}, dy[4] = {0, -1, -1, -1};
-    for (int e = 0; e < 4; ++e) {
-        const int xx = x + dx[e], yy = y + dy[e];
-        if (xx < 0 || xx >= W || yy < 0) continue;
-        const int q = yy * W + xx;
-        if (lab[q] < 0) continue;
-        int a = pd_find(lab, p), c = pd_find(lab, q);
-        // link the larger root under the smaller; a failed link (the root
-        // gained a parent meanwhile) retries from the new, smaller value
-        while (a != c) {
-            if (a < c) {
-                const int old = atomicMin(&lab[c], a);
-                if (old == c) break;
-                c = pd_find(lab, old);
-            } else {
-                const int old = atomicMin(&lab[a], c);
-                if (old == a) break;
-                a = pd_find(lab, old);
-            }
+    const int ntx = (W + kLabTile - 1) / kLabTile;
+    const int x0 = (int)(blockIdx.x % ntx) * kLabTile, y0 = (int)(blockIdx.x / ntx) * kLabTile;
+    const size_t base = (size_t)img * W * H;
+    const sgm_pothole_threshold r = thr[img];
+    const int lx = threadIdx.x % kLabTile, ly0 = threadIdx.x / kLabTile;
+#pragma unroll
+    for (int k = 0; k < kLabPasses; ++k) {
+        const int ly = ly0 + kLabRowsPerPass * k, l = ly * kLabTile + lx;
+        const int x = x0 + lx, y = y0 + ly;
+        bool fg = false;
+        if (x < W && y < H) {
+            const size_t at = base + (size_t)y * W + x;
+            const float d = d2[at];
+            fg = r.status == 0 && (!mask || mask[at] != 0) && finite_f(d) && (double)d < r.t_s;
         }
+        t[l] = fg ? l : -1;
+    }
+    __syncthreads();
+    // an entry's sign never changes after the barrier (links only lower
+    // non-negative entries), so the foreground tests below are stable
+#pragma unroll
+    for (int k = 0; k < kLabPasses; ++k) {
+        const int ly = ly0 + kLabRowsPerPass * k, l = ly * kLabTile + lx;
+        if (t[l] < 0) continue;
+        const bool left = lx > 0 && t[l - 1] >= 0;
+        const bool up = ly > 0 && t[l - kLabTile] >= 0;
+        if (left) pd_link(t, l, l - 1);
+        if (up) {
+            pd_link(t, l, l - kLabTile);
+        } else if (ly > 0) {  // the diagonals matter only when the pixel above is background
+            if (!left && lx > 0 && t[l - kLabTile - 1] >= 0) pd_link(t, l, l - kLabTile - 1);
+            if (lx + 1 < kLabTile && t[l - kLabTile + 1] >= 0) pd_link(t, l, l - kLabTile + 1);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kLabPasses; ++k) {
+        const int ly = ly0 + kLabRowsPerPass * k, l = ly * kLabTile + lx;
+        const int x = x0 + lx, y = y0 + ly;
+        if (x >= W || y >= H) continue;
+        int v = -1;
+        if (t[l] >= 0) {
+            const int root = pd_find(t, l);
+            v = (y0 + root / kLabTile) * W + x0 + root % kLabTile;
+        }
+        lab[base + (size_t)y * W + x] = v;
+    }
+}
+
+constexpr int kLabBorder = 3 * kLabTile - 2;  // a tile's top row, left and right columns
+
+// The edges between tiles, the same subset as inside them.  Only the pixels
+// of a tile's top row and left and right columns have a preceding neighbour
+// in another tile: one workgroup per tile, one thread per such pixel.
+__global__ __launch_bounds__(128) void k_pd_label_union(int W, int H, int32_t *__restrict__ lab_all)
+{
+    const int i = threadIdx.x;
+    if (i >= kLabBorder) return;
+    const int img = blockIdx.y;
+    const int ntx = (W + kLabTile - 1) / kLabTile;
+    const int tx = i < kLabTile ? i : (i < 2 * kLabTile - 1 ? 0 : kLabTile - 1);
+    const int ty = i < kLabTile ? 0 : (i < 2 * kLabTile - 1 ? i - (kLabTile - 1) : i - (2 * kLabTile - 2));
+    const int x = (int)(blockIdx.x % ntx) * kLabTile + tx, y = (int)(blockIdx.x / ntx) * kLabTile + ty;
+    if (x >= W || y >= H) return;
+    int32_t *lab = lab_all + (size_t)img * W * H;
+    const int p = y * W + x;
+    if (lab[p] < 0) return;
+    const bool left = x > 0 && lab[p - 1] >= 0;
+    const bool up = y > 0 && lab[p - W] >= 0;
+    if (left && tx == 0) pd_link(lab, p, p - 1);
+    if (up) {
+        if (ty == 0) pd_link(lab, p, p - W);
+    } else if (y > 0) {
+        if (!left && x > 0 && (tx == 0 || ty == 0) && lab[p - W - 1] >= 0) pd_link(lab, p, p - W - 1);
+        if (x + 1 < W && (tx == kLabTile - 1 || ty == 0) && lab[p - W + 1] >= 0) pd_link(lab, p, p - W + 1);
     }
 }
 
@@ -356,10 +441,11 @@ hipError_t launch_pothole_label(const float *d2, const uint8_t *mask, int W, int
 {
     const int n = W * H;
     const dim3 grid((n + 255) / 256, nimg);
-    k_pd_label_init<<<grid, 256, 0, s>>>(d2, mask, W, H, thr, labels);
+    const dim3 tiles((unsigned)(((W + kLabTile - 1) / kLabTile) * ((H + kLabTile - 1) / kLabTile)), nimg);
+    k_pd_label_local<<<tiles, kLabThreads, 0, s>>>(d2, mask, W, H, thr, labels);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_pd_label_union<<<grid, 256, 0, s>>>(W, H, labels);
+    k_pd_label_union<<<tiles, 128, 0, s>>>(W, H, labels);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_pd_label_flatten<<<grid, 256, 0, s>>>(W, H, labels);

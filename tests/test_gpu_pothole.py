@@ -116,6 +116,39 @@ def test_labels_on_dense_random_masks(lib):
         np.testing.assert_array_equal(lab, opd.label(D, 5.0))
 
 
+@pytest.mark.parametrize("shape", ["full", "checker", "serpentine", "stripes", "antistripes"])
+def test_labels_on_shapes_that_cross_many_tiles(lib, shape):
+    """Components that span many 32 x 32 tiles and join only through tile
+    borders: a full map, a checkerboard (one component through diagonal
+    steps alone), a one-pixel serpentine and diagonal stripes, on a ragged
+    map size, two maps per launch."""
+    import torch
+    H, W = 97, 161
+    yy, xx = np.mgrid[0:H, 0:W]
+    if shape == "full":
+        fg = np.ones((H, W), bool)
+    elif shape == "checker":
+        fg = (xx + yy) % 2 == 0
+    elif shape == "serpentine":
+        fg = np.zeros((H, W), bool)
+        fg[::4, :] = True
+        for r in range(0, H - 4, 4):
+            fg[r:r + 5, W - 1 if (r // 4) % 2 == 0 else 0] = True
+    elif shape == "stripes":
+        fg = (xx - yy) % 7 == 0
+    else:
+        fg = (xx + yy) % 5 == 0
+    D = np.stack([np.where(fg, 1.0, 9.0), np.where(fg[::-1, ::-1], 1.0, 9.0)]).astype(np.float32)
+    res = torch.zeros((2, lib.POTHOLE_WORDS), dtype=torch.float64, device="cuda")
+    res[:, 1] = 5.0  # t_s; status 0
+    lab = lib.pothole_labels(_dev(D), res).cpu().numpy()
+    for i in range(2):
+        want = opd.label(D[i], 5.0)
+        np.testing.assert_array_equal(lab[i], want)
+    if shape in ("full", "checker", "serpentine"):
+        assert len(np.unique(lab[0][lab[0] > 0])) == 1
+
+
 def test_degenerate_maps(lib):
     D = np.full((20, 30), 7.0, np.float32)
     res, _ = lib.pothole_threshold(_dev(D), 0.0, 16.0, 32, 1.0)
