@@ -284,6 +284,28 @@ def copy_calibration(args, dev):
         del src, dst
 
 
+def copy_reference(dev, mib=1024, reps=10):
+    """Rate of a plain device-to-device copy of `mib` MiB (torch copy_,
+    HIP events, median of `reps`): the bandwidth a streaming kernel can
+    reach in practice, beside the 8 TB/s peak."""
+    import numpy as np
+    import torch
+    src = torch.ones(mib << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        dst.copy_(src)
+        b.record()
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    del src, dst
+    return {"bytes": 2 * (mib << 20), "ms": round(ms, 4), "achieved": round(2 * (mib << 20) / (ms * 1e-3) / 1e9, 1),
+            "unit": "GB/s", "kernel": "torch copy_ of %d MiB, device to device (read + write)" % mib}
+
+
 def road_model_leg(args, log=None):
     """The road-model stages around the matcher on a batch of 16 full-range
     1920x1080 SGM disparity maps of generated road pairs: the fit of
@@ -753,6 +775,8 @@ def main():
            "unit": "TOP/s (u16)", "frac": round(agg_tops / VALU_PEAK_TOPS_U16, 4), "traffic": traffic}
     roofline = hbm if hbm["frac"] >= alu["frac"] else alu
     roofline["kernel"] = "k_aggregate"
+    copy_ref = copy_reference(torch.device("cuda:0"))
+    copy_ref["aggregate_over_copy"] = round(agg_gbs / copy_ref["achieved"], 4)
     # the whole step: cost written once, read once per direction, R volumes
     # written and read back by the selection
     step_bytes_per_eval = 1 + R * (1 + 2 * elem_bytes)
@@ -812,6 +836,7 @@ def main():
         "roofline_other_bound": alu if roofline is hbm else hbm,
         "step_hbm": {"bytes_per_eval": step_bytes_per_eval, "achieved": round(step_gbs, 1), "unit": "GB/s",
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
+        "hbm_copy_reference": copy_ref,
         "kernels_ms": {"cost": round(cost_ms, 4), "aggregate": round(agg_ms, 4),
                        "wta": round(wta_ms, 4)},
         "accuracy": accuracy,
