@@ -673,9 +673,9 @@ def main():
                          "(reference kernel for scaling memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the SGM path shards by independent stereo pairs and "
-              "this build runs and reports a single MI355X (got --gpus %d)" % args.gpus,
-              file=sys.stderr)
+        print("bench.py measures one GPU only (got --gpus %d): batches shard by independent stereo "
+              "pairs, one GPU's share being exactly the single-GPU run, and no multi-GPU path is "
+              "implemented here" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.mode == "batch" or args.workload == "road_batch64":
         return run_batch(args)
