@@ -403,6 +403,23 @@ def road_model_leg(args, log=None):
     torch.cuda.synchronize()
     per = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(6)] for e in events])
     fit_ms, win_ms, tr_ms, thr_ms, lab_ms, slic_ms = (float(x) for x in per.mean(axis=0))
+    # the curve E0min(phi) of eq. (12) (Fig. 3) on a 0.1 degree grid over
+    # the same maps and pixels as the fit; its minimum against the fit's phi
+    nphi = 1800
+    phis = torch.linspace(-math.pi / 2, math.pi / 2, nphi + 1, dtype=torch.float64, device=dev)[1:].contiguous()
+    energy = torch.empty((n, nphi), dtype=torch.float64, device=dev)
+    curve_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    sgm.road_energy(disp, phis, mask, 0.5, energy=energy, workspace=ws)
+    for a, b in curve_ev:
+        a.record()
+        sgm.road_energy(disp, phis, mask, 0.5, energy=energy, workspace=ws)
+        b.record()
+    sgm.road_fit(disp, mask, 0.5, fit=fit, workspace=ws)
+    torch.cuda.synchronize()
+    curve_ms = float(np.median([a.elapsed_time(b) for a, b in curve_ev]))
+    fit_phi = fit[:, 2].cpu().numpy()
+    arg_phi = phis.cpu().numpy()[energy.argmin(dim=1).cpu().numpy()]
+    curve_dev = float(np.max(np.abs(arg_phi - fit_phi)))
     pd_stat = sgm.pothole_threshold_dicts(pd_res)
     detection = []
     for dpd in (delta_pd, 1.0, 0.5):  # the paper's tolerance, then smaller ones for shallower potholes
@@ -440,6 +457,9 @@ def road_model_leg(args, log=None):
                     "frac": round(fit_gbs / HBM_PEAK_GBS, 4)},
         "transform_hbm": {"bytes_per_pixel": 8, "achieved": round(tr_gbs, 1), "unit": "GB/s",
                           "frac": round(tr_gbs / HBM_PEAK_GBS, 4)},
+        "e0min_curve": {"nphi": nphi, "grid_deg": 0.1, "ms_per_batch": round(curve_ms, 4),
+                        "argmin_vs_fit_max_deg": round(math.degrees(curve_dev), 4),
+                        "note": "eq. (12) at every grid angle from the fit's moments (one pass over the maps)"},
         "fit_error": {"phi_max_deg": round(math.degrees(max(dphi)), 5),
                       "a1_max_rel": round(max(da1), 6), "a0_max_px": round(max(da0), 4)},
         "pothole": {"threshold_ms": round(thr_ms, 4), "label_ms": round(lab_ms, 4),

@@ -419,6 +419,19 @@ sgm_status sgm_road_fit_batch(const float *disp, const uint8_t *mask, int32_t wi
                               int32_t nimg, float min_disp, double margin, const sgm_road_fit *prior,
                               double tol, sgm_road_fit *fit, void *workspace, size_t workspace_bytes,
                               void *stream);
+/* The curve E0min(phi) of eq. (12) (Fig. 3) over the pixels that
+ * sgm_road_fit_batch would select with the same arguments: for each map and
+ * each roll angle phi[j] (radians), the residual sum of squares of the
+ * least-squares fit d ~ a0 + a1 y, y = cos(phi) v - sin(phi) u, computed
+ * from the same float64 moments as S_dd - S_yd^2 / S_yy (centred sums).
+ * NaN for a map with fewer than 2 selected pixels or where y is constant
+ * over them (S_yy <= 1e-12 (S_uu + S_vv)).  phi: float64 [nphi], energy:
+ * float64 [nimg][nphi], both device; 1 <= nphi <= 65536; workspace as for
+ * sgm_road_fit_batch.  The minimum over phi is the fit's e0min at its phi. */
+sgm_status sgm_road_energy_batch(const float *disp, const uint8_t *mask, int32_t width, int32_t height,
+                                 int32_t nimg, float min_disp, double margin, const sgm_road_fit *prior,
+                                 double tol, const double *phi, int32_t nphi, double *energy, void *workspace,
+                                 size_t workspace_bytes, void *stream);
 /* Per-row window starts for W x H frames from device-resident fits (the
  * device form of sgm_window_from_road below, with the plane's slopes in
  * place of a1 cos(phi) and -a1 sin(phi)).  With scale s the fits are of

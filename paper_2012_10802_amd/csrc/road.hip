@@ -17,6 +17,8 @@
 //                    (k_road_moments_vec: float4 loads, two rows in flight);
 //   k_road_solve     one wave per map: ordered reduction of the partials and
 //                    the closed form;
+//   k_road_energy    one wave per map: the same reduction, then eq. (12) at
+//                    each of a list of roll angles (the curve of Fig. 3);
 //   k_road_window    one thread per row: window starts from the fit;
 //   k_disp_transform eq. (13), float4 in and out, HBM-bound.
 #include <hip/hip_runtime.h>
@@ -216,13 +218,11 @@ __global__ __launch_bounds__(kRoadThreads) void k_road_moments(const float *__re
     store_partial(acc, part + ((size_t)img * nblk + b) * kMoments);
 }
 
-// One wave per map: lane l sums partials l, l + 64, ... in order, then a
-// fixed butterfly; lane 0 solves.
-__global__ __launch_bounds__(64) void k_road_solve(const double *__restrict__ part, int nblk, int W, int H,
-                                                   sgm_road_fit *__restrict__ fit)
+// The ten sums of map img: lane l adds partials l, l + 64, ... in order,
+// then a fixed butterfly leaves the totals in every lane.
+__device__ inline void reduce_moments(const double *__restrict__ part, int nblk, int img, int lane,
+                                      double (&m)[kMoments])
 {
-    const int img = blockIdx.x, lane = threadIdx.x;
-    double m[kMoments];
 #pragma unroll
     for (int i = 0; i < kMoments; ++i) m[i] = 0.0;
     for (int j = lane; j < nblk; j += 64) {
@@ -232,6 +232,15 @@ __global__ __launch_bounds__(64) void k_road_solve(const double *__restrict__ pa
     }
 #pragma unroll
     for (int i = 0; i < kMoments; ++i) m[i] = wave_sum(m[i]);
+}
+
+// One wave per map: the sums, then lane 0 solves.
+__global__ __launch_bounds__(64) void k_road_solve(const double *__restrict__ part, int nblk, int W, int H,
+                                                   sgm_road_fit *__restrict__ fit)
+{
+    const int img = blockIdx.x, lane = threadIdx.x;
+    double m[kMoments];
+    reduce_moments(part, nblk, img, lane, m);
     if (lane != 0) return;
 
     sgm_road_fit f;
@@ -274,6 +283,43 @@ __global__ __launch_bounds__(64) void k_road_solve(const double *__restrict__ pa
         }
     }
     fit[img] = f;
+}
+
+// eq. (12) at roll angle phi[j] for every j: with y = cos(phi) v -
+// sin(phi) u, E0min = S_dd - S_yd^2 / S_yy, where S are sums of centred
+// products over the selected pixels (T = [1, y] projects d onto the
+// constant and y).  NaN with fewer than 2 pixels or when y takes a single
+// value over them (S_yy <= 1e-12 (S_uu + S_vv): T has rank 1).
+__global__ __launch_bounds__(64) void k_road_energy(const double *__restrict__ part, int nblk,
+                                                    const double *__restrict__ phi, int nphi,
+                                                    double *__restrict__ energy)
+{
+    const int img = blockIdx.x, lane = threadIdx.x;
+    double m[kMoments];
+    reduce_moments(part, nblk, img, lane, m);
+    const double n = m[0];
+    const double nan = __builtin_nan("");
+    double cuu = 0.0, cuv = 0.0, cvv = 0.0, cud = 0.0, cvd = 0.0, cdd = 0.0;
+    if (n >= 2.0) {
+        const double mu = m[1] / n, mv = m[2] / n, md = m[6] / n;
+        cuu = m[3] - m[1] * mu;
+        cuv = m[4] - m[1] * mv;
+        cvv = m[5] - m[2] * mv;
+        cud = m[7] - m[1] * md;
+        cvd = m[8] - m[2] * md;
+        cdd = m[9] - m[6] * md;
+    }
+    for (int j = lane; j < nphi; j += 64) {
+        double e = nan;
+        if (n >= 2.0) {
+            double s, c;
+            sincos(phi[j], &s, &c);
+            const double syy = c * c * cvv - 2.0 * s * c * cuv + s * s * cuu;
+            const double syd = c * cvd - s * cud;
+            if (syy > 1e-12 * (cuu + cvv)) e = cdd - syd * syd / syy;
+        }
+        energy[(size_t)img * nphi + j] = e;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_road_window(const sgm_road_fit *__restrict__ fit, int W, int H, int w,
@@ -454,12 +500,15 @@ size_t road_workspace_bytes(int W, int H, int nimg)
     return nblk * (size_t)nimg * kMoments * sizeof(double);
 }
 
-hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H, int nimg, float min_disp,
-                           double margin, const sgm_road_fit *prior, double tol, sgm_road_fit *fit, void *ws,
-                           hipStream_t s)
+// The moments pass of the fit: per-block partial sums into ws; returns the
+// number of blocks per map through nblk_out.
+static hipError_t launch_moments(const float *disp, const uint8_t *mask, int W, int H, int nimg, float min_disp,
+                                 double margin, const sgm_road_fit *prior, double tol, void *ws, hipStream_t s,
+                                 int *nblk_out)
 {
     const int rows = road_rows(H, nimg, kTargetBlocks);
     const int nblk = (H + rows - 1) / rows;
+    *nblk_out = nblk;
     double *part = static_cast<double *>(ws);
     const dim3 grid(nblk, nimg);
     const bool vec = vec_ok(disp, mask, nullptr, W);
@@ -471,9 +520,28 @@ hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H,
         k_road_moments_vec<4><<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, prior, tol, part);
     else
         k_road_moments<<<grid, kRoadThreads, 0, s>>>(disp, mask, W, H, rows, nblk, min_disp, margin, prior, tol, part);
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H, int nimg, float min_disp,
+                           double margin, const sgm_road_fit *prior, double tol, sgm_road_fit *fit, void *ws,
+                           hipStream_t s)
+{
+    int nblk = 0;
+    hipError_t e = launch_moments(disp, mask, W, H, nimg, min_disp, margin, prior, tol, ws, s, &nblk);
     if (e != hipSuccess) return e;
-    k_road_solve<<<nimg, 64, 0, s>>>(part, nblk, W, H, fit);
+    k_road_solve<<<nimg, 64, 0, s>>>(static_cast<const double *>(ws), nblk, W, H, fit);
+    return hipGetLastError();
+}
+
+hipError_t launch_road_energy(const float *disp, const uint8_t *mask, int W, int H, int nimg, float min_disp,
+                              double margin, const sgm_road_fit *prior, double tol, const double *phi, int nphi,
+                              double *energy, void *ws, hipStream_t s)
+{
+    int nblk = 0;
+    hipError_t e = launch_moments(disp, mask, W, H, nimg, min_disp, margin, prior, tol, ws, s, &nblk);
+    if (e != hipSuccess) return e;
+    k_road_energy<<<nimg, 64, 0, s>>>(static_cast<const double *>(ws), nblk, phi, nphi, energy);
     return hipGetLastError();
 }
 

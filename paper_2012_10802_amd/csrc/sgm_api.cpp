@@ -524,6 +524,31 @@ sgm_status sgm_road_fit_batch(const float *disp, const uint8_t *mask, int32_t W,
     return e == hipSuccess ? SGM_OK : hip_fail(e, "road fit launch");
 }
 
+sgm_status sgm_road_energy_batch(const float *disp, const uint8_t *mask, int32_t W, int32_t H, int32_t nimg,
+                                 float min_disp, double margin, const sgm_road_fit *prior, double tol,
+                                 const double *phi, int32_t nphi, double *energy, void *ws, size_t ws_bytes,
+                                 void *stream)
+{
+    if (!disp || !phi || !energy) return fail(SGM_ERR_INVALID, "disp, phi and energy must not be NULL");
+    sgm_status st = check_maps(W, H, nimg);
+    if (st != SGM_OK) return st;
+    if (nphi < 1 || nphi > 65536) return fail(SGM_ERR_INVALID, "nphi %d not in [1, 65536]", nphi);
+    if (isnan(min_disp) || isnan(margin)) return fail(SGM_ERR_INVALID, "min_disp and margin must not be NaN");
+    if (!(tol >= 0.0)) return fail(SGM_ERR_INVALID, "tol must be >= 0 (or +INFINITY)");
+    if (prior && !is_aligned(prior, 8)) return fail(SGM_ERR_INVALID, "prior misaligned");
+    if (!ws) return fail(SGM_ERR_INVALID, "workspace is NULL");
+    if (!is_aligned(ws, 256)) return fail(SGM_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (!is_aligned(disp, 4) || !is_aligned(phi, 8) || !is_aligned(energy, 8))
+        return fail(SGM_ERR_INVALID, "disp, phi or energy misaligned");
+    const size_t need = sgm::road_workspace_bytes(W, H, nimg);
+    if (ws_bytes < need)
+        return fail(SGM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
+    hipError_t e = sgm::launch_road_energy(disp, mask, W, H, nimg, min_disp, margin, prior, tol, phi, nphi, energy,
+                                           ws, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "road energy launch");
+}
+
 sgm_status sgm_road_window_batch(const sgm_road_fit *fit, int32_t W, int32_t H, int32_t nimg, int32_t w,
                                  int32_t mode, double delta, double scale, int32_t *d_lo, void *stream)
 {

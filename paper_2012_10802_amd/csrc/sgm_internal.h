@@ -122,6 +122,9 @@ hipError_t launch_batch(const BatchDev &b, const BatchGrids &g, int census_n, bo
 // road model (fit, windows, disparity transformation)
 
 size_t road_workspace_bytes(int W, int H, int nimg);
+hipError_t launch_road_energy(const float *disp, const uint8_t *mask, int W, int H, int nimg, float min_disp,
+                              double margin, const sgm_road_fit *prior, double tol, const double *phi, int nphi,
+                              double *energy, void *ws, hipStream_t s);
 hipError_t launch_road_fit(const float *disp, const uint8_t *mask, int W, int H, int nimg, float min_disp,
                            double margin, const sgm_road_fit *prior, double tol, sgm_road_fit *fit, void *ws,
                            hipStream_t s);

@@ -109,6 +109,7 @@ def _load_library():
         "sgm_road_workspace_size": [I, I, I, ctypes.POINTER(S)],
         "sgm_road_fit_batch": [P, P, I, I, I, ctypes.c_float, D, P, D, P, P, S, P],
         "sgm_road_window_batch": [P, I, I, I, I, I, D, D, P, P],
+        "sgm_road_energy_batch": [P, P, I, I, I, ctypes.c_float, D, P, D, P, I, P, P, S, P],
         "sgm_disparity_transform_batch": [P, P, I, I, I, D, P, P],
         "sgm_pothole_workspace_size": [I, I, ctypes.POINTER(S)],
         "sgm_pothole_threshold_batch": [P, P, I, I, I, D, D, I, D, P, P, P, S, P],
@@ -277,6 +278,37 @@ def road_fit(disp, mask=None, min_disp=float("-inf"), margin=float("-inf"), prio
                                    _ptr(workspace), workspace.numel(), _stream(stream)),
            "sgm_road_fit_batch")
     return fit
+
+
+def road_energy(disp, phi, mask=None, min_disp=float("-inf"), margin=float("-inf"), prior=None, tol=float("inf"),
+                energy=None, workspace=None, stream=None):
+    """E0min(phi) of eq. (12) (the curve of Fig. 3) for float32 device maps
+    [H, W] or [n, H, W] at the roll angles of `phi` (float64 device [m]),
+    over the pixels road_fit selects with the same arguments.  Returns
+    float64 [n, m] (NaN where eq. (12) is undefined)."""
+    d = _maps(disp, torch.float32, "disp")
+    n, H, W = d.shape
+    if mask is not None:
+        mask = _maps(mask, torch.uint8, "mask")
+        if tuple(mask.shape) != (n, H, W):
+            raise ValueError("mask must have the shape of disp")
+    _need(phi, torch.float64, None, "phi")
+    if phi.dim() != 1:
+        raise ValueError("phi must be one-dimensional")
+    m = phi.numel()
+    if energy is None:
+        energy = torch.empty((n, m), dtype=torch.float64, device=d.device)
+    _need(energy, torch.float64, (n, m), "energy")
+    if workspace is None:
+        workspace = torch.empty(max(road_workspace_size(W, H, n), 1), dtype=torch.uint8, device=d.device)
+    _need(workspace, torch.uint8, None, "workspace")
+    if prior is not None:
+        _need(prior, torch.float64, (n, ROAD_FIT_WORDS), "prior")
+    _check(_lib.sgm_road_energy_batch(_ptr(d), _ptr(mask), W, H, n, float(min_disp), float(margin), _ptr(prior),
+                                      float(tol), _ptr(phi), m, _ptr(energy), _ptr(workspace), workspace.numel(),
+                                      _stream(stream)),
+           "sgm_road_energy_batch")
+    return energy
 
 
 def road_fit_dicts(fit):

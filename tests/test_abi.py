@@ -278,9 +278,23 @@ def test_road_calls_validate_before_launch():
     assert lib.sgm_road_mask_batch(d, d, 64, 48, 2, float("nan"), 0.0, d, None) == -1
     assert lib.sgm_road_mask_batch(d, None, 64, 48, 2, 1.0, 0.0, d, None) == -1
     assert lib.sgm_road_mask_batch(d, d, 64, 48, 0, 1.0, 0.0, d, None) == -1
-    # an armed launch fault fails the fit with nothing enqueued
+    E = lib.sgm_road_energy_batch
+    inf = float("inf")
+    assert E(d, None, 64, 48, 2, f(0.0), ninf, None, inf, None, 5, d, d, ws, None) == -1  # phi NULL
+    assert E(d, None, 64, 48, 2, f(0.0), ninf, None, inf, d, 5, None, d, ws, None) == -1  # energy NULL
+    assert E(d, None, 64, 48, 2, f(0.0), ninf, None, inf, d, 0, d, d, ws, None) == -1
+    assert E(d, None, 64, 48, 2, f(0.0), ninf, None, inf, d, 65537, d, d, ws, None) == -1
+    assert E(d, None, 64, 48, 2, f(float("nan")), ninf, None, inf, d, 5, d, d, ws, None) == -1
+    assert E(d, None, 64, 48, 2, f(0.0), ninf, d, -1.0, d, 5, d, d, ws, None) == -1
+    assert E(d, None, 64, 48, 2, f(0.0), ninf, None, inf, ctypes.c_void_p((1 << 20) + 4), 5, d, d, ws, None) == -1
+    assert E(d, None, 64, 48, 2, f(0.0), ninf, None, inf, d, 5, ctypes.c_void_p((1 << 20) + 4), d, ws, None) == -1
+    assert E(d, None, 64, 48, 2, f(0.0), ninf, None, inf, d, 5, d, d, ws - 1, None) == -4
+    assert E(d, None, 64, 48, 0, f(0.0), ninf, None, inf, d, 5, d, d, ws, None) == -1
+    # an armed launch fault fails the fit and the curve with nothing enqueued
     assert lib.sgm_debug_inject_fault(1) == 0
     assert lib.sgm_road_fit_batch(d, None, 64, 48, 2, f(0.0), ninf, None, float("inf"), d, d, ws, None) == -3
+    assert lib.sgm_debug_inject_fault(1) == 0
+    assert E(d, None, 64, 48, 2, f(0.0), ninf, None, inf, d, 5, d, d, ws, None) == -3
     assert lib.sgm_debug_inject_fault(0) == 0
 
 

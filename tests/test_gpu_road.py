@@ -415,3 +415,82 @@ def test_perspective_pipeline_batch_equals_single_frames(lib):
         for a, b in zip(out3, out1):
             assert torch.equal(a[i], b[0])
         assert torch.equal(pm3.lo[i], pm1.lo[0])
+
+
+def _oracle_curve(D, phis, mask=None, min_disp=-math.inf, margin=-math.inf, prior=None, tol=math.inf):
+    u, v, d = oroad.select(D, mask, min_disp, margin, prior, tol)
+    out = []
+    for p in phis:
+        if len(d) < 2 or np.linalg.matrix_rank(oroad.T_matrix(u, v, p)) < 2:
+            out.append(math.nan)
+        else:
+            out.append(oroad.e0min(u, v, d, p))
+    return np.array(out)
+
+
+def _close_curve(got, want, D):
+    sdd = float(np.nansum(np.where(np.isfinite(D), D.astype(np.float64), 0.0) ** 2))
+    np.testing.assert_array_equal(np.isnan(got), np.isnan(want))
+    ok = ~np.isnan(want)
+    np.testing.assert_allclose(got[ok], want[ok], rtol=1e-6, atol=1e-10 * sdd + 1e-12)
+
+
+def test_energy_curve_matches_oracle(lib):
+    """E0min(phi) of eq. (12) (Fig. 3) at 181 roll angles over a half turn:
+    the hand-worked map, and SGM output of a generated road pair with the
+    selections a pipeline uses (floor, margin, a refit's prior and tol)."""
+    import torch
+    phis = np.linspace(-math.pi / 2, math.pi / 2, 181)[1:]
+    ph = _dev(phis)
+    with open(os.path.join(GOLD, "hand_road3x3.json")) as f:
+        D = np.array(json.load(f)["disp"], np.float32)
+    got = lib.road_energy(_dev(D), ph).cpu().numpy()[0]
+    _close_curve(got, _oracle_curve(D, phis), D)
+    ps, D = _sgm_disp(lib, "road640", 7)
+    got = lib.road_energy(_dev(D), ph, _dev(ps.road.astype(np.uint8))).cpu().numpy()[0]
+    _close_curve(got, _oracle_curve(D, phis, ps.road), D)
+    got = lib.road_energy(_dev(D), ph, None, 0.5, 4.0).cpu().numpy()[0]
+    _close_curve(got, _oracle_curve(D, phis, None, 0.5, 4.0), D)
+    fit = lib.road_fit(_dev(D), None, 0.5, 4.0)
+    f = lib.road_fit_dicts(fit)[0]
+    got = lib.road_energy(_dev(D), ph, None, 0.5, 4.0, prior=fit, tol=2.0).cpu().numpy()[0]
+    _close_curve(got, _oracle_curve(D, phis, None, 0.5, 4.0, (f["a0"], f["a1"], f["phi"]), 2.0), D)
+    torch.cuda.synchronize()
+
+
+def test_energy_curve_minimum_is_the_fit(lib):
+    """The curve's value at the fitted roll equals the fit's E0min, and no
+    angle of a fine grid lies below it: the closed form finds the minimum
+    of the curve that Sec. II-C searches."""
+    ps, D = _sgm_disp(lib, "road320", 2)
+    d = _dev(D)
+    m = _dev(ps.road.astype(np.uint8))
+    f = lib.road_fit_dicts(lib.road_fit(d, m))[0]
+    assert f["status"] == 0
+    phis = np.concatenate([[f["phi"]], f["phi"] + np.linspace(-0.05, 0.05, 2001), np.linspace(-1.5, 1.5, 301)])
+    e = lib.road_energy(d, _dev(phis), m).cpu().numpy()[0]
+    sdd = float(np.sum(D[ps.road].astype(np.float64) ** 2))
+    assert e[0] == pytest.approx(f["e0min"], rel=1e-6, abs=1e-10 * sdd)
+    assert e.min() >= e[0] - 1e-10 * sdd
+    assert np.argmin(e[1:2002]) in range(995, 1006)  # the grid's minimum sits next to the fitted phi
+
+
+def test_energy_curve_degenerate_maps(lib):
+    """A one-row map: y = v is constant at phi = 0 (NaN) but not at other
+    angles; a one-pixel selection: NaN everywhere; both in one batch with a
+    regular map."""
+    import torch
+    rng = np.random.default_rng(5)
+    W = 40
+    D = np.stack([np.full((3, W), np.nan, np.float32) for _ in range(3)])
+    D[0, 1] = 5.0 + 0.1 * np.arange(W) + rng.normal(0, 0.05, W)  # one row
+    D[1, 2, 7] = 3.0  # one pixel
+    D[2] = 4.0 + 0.2 * np.arange(3)[:, None] + 0.05 * np.arange(W)[None, :]
+    phis = np.array([0.0, 0.3, -1.2])
+    e = lib.road_energy(_dev(D), _dev(phis)).cpu().numpy()
+    assert math.isnan(e[0, 0]) and np.isfinite(e[0, 1:]).all()
+    assert np.isnan(e[1]).all()
+    assert np.isfinite(e[2]).all()
+    for i in range(3):
+        _close_curve(e[i], _oracle_curve(D[i], phis), D[i])
+    torch.cuda.synchronize()
