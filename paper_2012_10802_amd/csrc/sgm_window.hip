@@ -51,6 +51,22 @@ __global__ __launch_bounds__(256) void k_downsample4(const uint8_t *__restrict__
 constexpr int kWinTile = 64;    // pixels of one row per workgroup
 constexpr int kWinReach = 256;  // right columns reachable left of the tile
 
+__device__ __forceinline__ int wave_min(int x)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) x = min(x, __shfl_xor(x, o, 64));
+    return x;
+}
+__device__ __forceinline__ int wave_max(int x)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) x = max(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// One row tile of 64 pixels per workgroup (one wave).  Only the right
+// columns that the tile's windows reach are staged: [u0 - max lo - 15,
+// u0 + 63 - min lo], clipped to the image and to the staging array.
 __global__ __launch_bounds__(64) void k_cost_win(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr,
                                                  const int32_t *__restrict__ lo, int W, int H, int w, int cmax,
                                                  uint8_t *__restrict__ cost, long long codes_pair,
@@ -64,16 +80,22 @@ __global__ __launch_bounds__(64) void k_cost_win(const uint64_t *__restrict__ cl
     cost += blockIdx.z * cost_pair;
     const int v = blockIdx.y, u0 = blockIdx.x * kWinTile;
     const int first = u0 - kWinReach;  // right column held in s_cr[0]
-    for (int t = threadIdx.x; t < kWinTile + kWinReach; t += blockDim.x) {
-        const int col = first + t;
-        s_cr[t] = (col >= 0 && col < W) ? cr[(size_t)v * W + col] : 0ull;
-    }
-    __syncthreads();
     const int u = u0 + threadIdx.x;
-    if (u >= W) return;
+    const bool act = u < W;
     const size_t pix = (size_t)v * W + u;
+    const int l = act ? lo[pix] : 0;
+    const int lmax = __builtin_amdgcn_readfirstlane(wave_max(act ? l : -0x7FFFFFFF - 1));
+    const int lmin = __builtin_amdgcn_readfirstlane(wave_min(act ? l : 0x7FFFFFFF));
+    // columns read below: u - l - j, j in [0, 16), of the active lanes, and
+    // only those >= 0 inside the staging array (the rest cost cmax); columns
+    // past the right edge hold 0
+    const long long c0 = max(max((long long)u0 - lmax - 15, (long long)first), 0ll);
+    const long long c1 = min((long long)u0 + kWinTile - 1 - lmin, (long long)u0 + kWinTile - 1);
+    for (long long col = c0 + threadIdx.x; col <= c1; col += blockDim.x)
+        s_cr[col - first] = col < W ? cr[(size_t)v * W + col] : 0ull;
+    __syncthreads();
+    if (!act) return;
     const uint64_t a = cl[pix];
-    const int l = lo[pix];
     uint32_t word[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -361,18 +383,6 @@ __device__ __forceinline__ uint32_t bytes_hi(uint32_t c) { return __builtin_amdg
 __device__ __forceinline__ uint32_t pack4(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x06040200u); }
 __device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) { return __builtin_amdgcn_alignbit(hi, lo, 16); }
 
-__device__ __forceinline__ int wave_min(int x)
-{
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) x = min(x, __shfl_xor(x, o, 64));
-    return x;
-}
-__device__ __forceinline__ int wave_max(int x)
-{
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) x = max(x, __shfl_xor(x, o, 64));
-    return x;
-}
 
 // One step of eq. (8) on per-pixel windows for one lane (one scanline):
 // L, m hold the predecessor's 16 values (packed u16 pairs) and their

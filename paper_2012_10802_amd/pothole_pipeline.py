@@ -93,7 +93,8 @@ class PotholeDetector:
         self.disp = None
 
     def _match_perspective(self, left, right, stream=None):
-        dint, dsub, _ = self.matcher.match(left, right, stream=stream)
+        # the detector fits D1 itself (step 2), so the matcher stops at D1
+        dint, dsub, _ = self.matcher.match(left, right, stream=stream, refit=False)
         return dint, dsub
 
     def _match_plain(self, left, right, stream=None):

@@ -97,7 +97,10 @@ class PerspectiveMatcher:
             S.road_fit(disp, None, min_disp, margin, prior=fits[i], tol=tol, fit=fits[i + 1], workspace=self.ws,
                        stream=stream)
 
-    def match(self, left, right, stream=None):
+    def match(self, left, right, stream=None, refit=True):
+        """Steps 1-6 (refit=False: steps 1-5 only, for a caller that fits
+        D1 itself; `fits` and `d2` are then left as they were and d2 is
+        returned as None)."""
         if left.dim() == 2:
             left, right = left.unsqueeze(0), right.unsqueeze(0)
         if tuple(left.shape) != (self.n, self.H, self.W) or left.shape != right.shape:
@@ -117,6 +120,8 @@ class PerspectiveMatcher:
                 self.left_f.copy_(left)  # the batch reads its own input buffers
                 self.right_f.copy_(right)
             self.fine.run(stream=stream)
+        if not refit:
+            return self.disp_int, self.disp_sub, None
         self._fit(self.disp_sub, self.fits, self.fine_tols, 4 * self.min_disp, 4 * self.margin, stream)
         S.disparity_transform(self.disp_sub, self.fit, self.delta_dt, out=self.d2, stream=stream)
         return self.disp_int, self.disp_sub, self.d2
