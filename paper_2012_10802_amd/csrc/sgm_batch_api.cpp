@@ -319,8 +319,8 @@ sgm_status sgm_batch_plan(const sgm_batch_params *prm, const sgm_pair *pairs, in
         d.pitch = p.pitch;
         d.vpl = lane_width(p.ndisp);
         d.pad = p.ndisp < 16 * d.vpl ? 1 : 0;
-        d.census_tx = (p.width + 63) / 64;
-        d.census_ty = (p.height + 3) / 4;
+        d.census_tx = (p.width + sgm::kCensusTW - 1) / sgm::kCensusTW;
+        d.census_ty = (p.height + sgm::kCensusTH - 1) / sgm::kCensusTH;
         d.cost_tx = (p.width + 63) / 64;
         d.census_start = census_blk;
         census_blk += 2 * d.census_tx * d.census_ty;

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sgm_internal.h"
+
 namespace sgm {
 namespace dev {
 
@@ -226,38 +228,96 @@ __device__ __forceinline__ void load_u16_pairs(uint32_t (&v)[VPL / 2], const uin
 
 // ---------------------------------------------------------------------------
 // census transform
+//
+// A workgroup covers a tile of kCensusTW x kCensusTH pixels (256 threads);
+// each thread takes four horizontally adjacent pixels of one row and
+// compares their neighbours four at a time inside 32-bit words (one byte
+// per pixel).  For
+// bytes a (neighbour) and c (centre), t = (a | 0x80) - (c & 0x7F) stays
+// inside its byte, and its bit 7 says whether the low seven bits of a are
+// >= those of c; a >= c is then the majority of (a, not c, t) at bit 7, and
+// a < c its complement.  Eight consecutive comparisons are gathered per byte by
+// shifting right (the first ends at bit 0), so each 32-bit word holds one
+// byte of the code of each of the four pixels; byte permutes then assemble
+// the four codes.  Bit b of a code is the b-th comparison in row-major order
+// over the window (centre skipped), as the definition orders them.
 
 template <int N>
 __device__ __forceinline__ void census_tile(const uint8_t *__restrict__ img, int pitch, int W, int H,
                                             uint64_t *__restrict__ out, int bx, int by)
 {
-    constexpr int R = N / 2, TW = 64, TH = 4, LW = TW + 2 * R, LH = TH + 2 * R;
-    __shared__ uint8_t tile[LH][LW];
+    static_assert(N == 3 || N == 5 || N == 7, "census window 3, 5 or 7");
+    constexpr int R = N / 2;
+    constexpr int NB = N * N - 1;                  // 8, 24 or 48 bits: whole bytes
+    constexpr int NPL = NB / 8;                    // bytes of a code
+    constexpr int TW = kCensusTW, TH = kCensusTH;
+    constexpr int LW = TW + 8;                     // 4 margin columns on each side (R <= 3)
+    constexpr int LH = TH + 2 * R;
+    constexpr int QPR = TW / 4;                    // threads (quads) per row
+    __shared__ uint32_t tile[LH][LW / 4];
     const int u0 = bx * TW, v0 = by * TH;
-    for (int t = threadIdx.x; t < LH * LW; t += blockDim.x) {
-        const int ty = t / LW, tx = t % LW;
-        const int v = min(max(v0 + ty - R, 0), H - 1);
-        const int u = min(max(u0 + tx - R, 0), W - 1);
-        tile[ty][tx] = img[(size_t)v * pitch + u];
+    // tile byte (ty, tx) = I(clamp(u0 + tx - 4), clamp(v0 + ty - R)), one
+    // dword (four columns) per thread and step
+    for (int t = threadIdx.x; t < LH * (LW / 4); t += blockDim.x) {
+        const int ty = t / (LW / 4), d = t % (LW / 4);
+        const uint8_t *row = img + (size_t)min(max(v0 + ty - R, 0), H - 1) * pitch;
+        const int x = u0 - 4 + 4 * d;
+        uint32_t wd = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) wd |= (uint32_t)row[min(max(x + e, 0), W - 1)] << (8 * e);
+        tile[ty][d] = wd;
     }
     __syncthreads();
-    const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
-    const int u = u0 + tx, v = v0 + ty;
-    if (u >= W || v >= H) return;
-    const int c = tile[ty + R][tx + R];
-    uint64_t bits = 0;
+    const int q = threadIdx.x % QPR, ty = threadIdx.x / QPR;
+    const int v = v0 + ty, ub = u0 + 4 * q;  // the quad's pixels: ub .. ub + 3 of row v
+    if (ty >= TH || v >= H || ub >= W) return;
+    constexpr uint32_t kTop = 0x80808080u;
+    const uint32_t c = tile[ty + R][q + 1];
+    const uint32_t c7 = c & ~kTop, nc = ~c;
+    uint32_t acc[NPL];
+#pragma unroll
+    for (int g = 0; g < NPL; ++g) acc[g] = 0u;
     int b = 0;
 #pragma unroll
-    for (int dy = -R; dy <= R; ++dy)
+    for (int dy = -R; dy <= R; ++dy) {
+        // tile columns 4q .. 4q + 11 = image columns ub - 4 .. ub + 7
+        const uint32_t w0 = tile[ty + R + dy][q], w1 = tile[ty + R + dy][q + 1], w2 = tile[ty + R + dy][q + 2];
 #pragma unroll
         for (int dx = -R; dx <= R; ++dx) {
             if (dx == 0 && dy == 0) continue;
-            bits |= (uint64_t)(tile[ty + R + dy][tx + R + dx] < c) << b;
+            const int k = 4 + dx;  // byte offset of the neighbours of the quad in w0 w1 w2
+            const uint32_t a = k < 4 ? __builtin_amdgcn_alignbyte(w1, w0, k)
+                                     : (k == 4 ? w1 : __builtin_amdgcn_alignbyte(w2, w1, k - 4));
+            const uint32_t t = (a | kTop) - c7;
+            // a >= c at bit 7: the majority of (a, not c, t); its complement,
+            // the borrow out of the byte, is taken once the word is full
+            const uint32_t ge = (a & nc) | (a & t) | (nc & t);
+            acc[b / 8] = (acc[b / 8] >> 1) | (ge & kTop);
             ++b;
         }
-    out[(size_t)v * W + u] = bits;
+    }
+#pragma unroll
+    for (int g = 0; g < NPL; ++g) acc[g] = ~acc[g];  // every bit was filled: a >= c becomes a < c
+    // pixel i's code: byte g = byte i of acc[g]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (ub + i >= W) break;
+        uint32_t lo = 0, hi = 0;
+#pragma unroll
+        for (int g = 0; g < NPL; g += 2) {
+            const uint32_t s0 = g + 1 < NPL ? acc[g + 1] : 0u;
+            // bytes (acc[g].b_i, acc[g+1].b_i) at positions (g % 4, g % 4 + 1)
+            const uint32_t sel = (g % 4 == 0) ? ((uint32_t)i | ((uint32_t)(4 + i) << 8) | 0x0C0C0000u)
+                                              : (0x00000C0Cu | ((uint32_t)i << 16) | ((uint32_t)(4 + i) << 24));
+            const uint32_t pv = __builtin_amdgcn_perm(s0, acc[g], sel);
+            if (g < 4)
+                lo |= pv;
+            else
+                hi |= pv;
+        }
+        out[(size_t)v * W + ub + i] = ((uint64_t)hi << 32) | lo;
+    }
 }
-
 
 // ---------------------------------------------------------------------------
 // matching cost: C(u,v,k) = popcount(cL(u,v) ^ cR(u - d_lo(v) - k, v))

@@ -12,6 +12,8 @@ namespace sgm {
 
 // thread-local text of the last failure (sgm_last_error)
 constexpr int kErrorBufferSize = 512;
+constexpr int kCensusTW = 64;  // census tile width in pixels (16 threads of 4 pixels)
+constexpr int kCensusTH = 16;  // census tile height in rows (16 threads per row)
 char *error_buffer();
 
 // Launch configuration chosen at plan time.

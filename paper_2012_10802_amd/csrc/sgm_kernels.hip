@@ -227,7 +227,7 @@ long long volume_stride(const Problem &pb, bool l8)
 
 hipError_t launch_census(const Problem &pb, const uint8_t *img, int pitch, uint64_t *codes, hipStream_t s)
 {
-    dim3 grid((pb.W + 63) / 64, (pb.H + 3) / 4), block(256);
+    dim3 grid((pb.W + kCensusTW - 1) / kCensusTW, (pb.H + kCensusTH - 1) / kCensusTH), block(256);
     switch (pb.n) {
     case 3: hipLaunchKernelGGL(k_census<3>, grid, block, 0, s, img, pitch, pb.W, pb.H, codes); break;
     case 5: hipLaunchKernelGGL(k_census<5>, grid, block, 0, s, img, pitch, pb.W, pb.H, codes); break;

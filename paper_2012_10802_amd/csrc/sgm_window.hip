@@ -777,7 +777,7 @@ hipError_t launch_match_win_pairs(const Problem &pb, const WinPairs &b, hipStrea
     const long long ws_words = (long long)(b.ws_pair / 8);
     // census of every left and right image
     {
-        dim3 grid((pb.W + 63) / 64, (pb.H + 3) / 4, 2 * b.npairs), block(256);
+        dim3 grid((pb.W + kCensusTW - 1) / kCensusTW, (pb.H + kCensusTH - 1) / kCensusTH, 2 * b.npairs), block(256);
         switch (pb.n) {
         case 3:
             hipLaunchKernelGGL(k_census_pairs<3>, grid, block, 0, s, b.left, b.right, b.pitch, b.img_pair, pb.W, pb.H,
