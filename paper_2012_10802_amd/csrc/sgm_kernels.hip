@@ -153,7 +153,11 @@ hipError_t by_vpl(int vpl, A &&...args)
     }
 }
 
-constexpr int kPrefetch = 8;
+// Steps of cost prefetched ahead by each scanline.  Measured on 1280x720,
+// w = 128 (four u16 pairs per lane): 24 steps stream the cost 11 % faster
+// than 8 (20 and 32 do not), so that width takes 24; the others keep 8,
+// where deeper rings only add registers.
+constexpr int prefetch_steps(int vpl) { return vpl == 8 ? 24 : 8; }
 
 template <int VPL>
 struct AggLaunch {
@@ -161,14 +165,14 @@ struct AggLaunch {
                           hipStream_t s)
     {
         if (!kc.aligned) {
-            if (l8) hipLaunchKernelGGL((k_aggregate<VPL, false, true, true, kPrefetch>), grid, block, 0, s, p);
-            else hipLaunchKernelGGL((k_aggregate<VPL, false, true, false, kPrefetch>), grid, block, 0, s, p);
+            if (l8) hipLaunchKernelGGL((k_aggregate<VPL, false, true, true, prefetch_steps(VPL)>), grid, block, 0, s, p);
+            else hipLaunchKernelGGL((k_aggregate<VPL, false, true, false, prefetch_steps(VPL)>), grid, block, 0, s, p);
         } else if (pad) {
-            if (l8) hipLaunchKernelGGL((k_aggregate<VPL, true, true, true, kPrefetch>), grid, block, 0, s, p);
-            else hipLaunchKernelGGL((k_aggregate<VPL, true, true, false, kPrefetch>), grid, block, 0, s, p);
+            if (l8) hipLaunchKernelGGL((k_aggregate<VPL, true, true, true, prefetch_steps(VPL)>), grid, block, 0, s, p);
+            else hipLaunchKernelGGL((k_aggregate<VPL, true, true, false, prefetch_steps(VPL)>), grid, block, 0, s, p);
         } else {
-            if (l8) hipLaunchKernelGGL((k_aggregate<VPL, true, false, true, kPrefetch>), grid, block, 0, s, p);
-            else hipLaunchKernelGGL((k_aggregate<VPL, true, false, false, kPrefetch>), grid, block, 0, s, p);
+            if (l8) hipLaunchKernelGGL((k_aggregate<VPL, true, false, true, prefetch_steps(VPL)>), grid, block, 0, s, p);
+            else hipLaunchKernelGGL((k_aggregate<VPL, true, false, false, prefetch_steps(VPL)>), grid, block, 0, s, p);
         }
         return hipGetLastError();
     }
