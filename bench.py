@@ -652,9 +652,10 @@ def _detector_run(det, n, W, H, matcher, log):
         "potholes_hit": hit, "potholes_total": holes_total,
         "slic_rounds_mean": round(float(np.mean(rounds)), 2),
         "settings": "%s SGM (0-191), fit + refits (2, 1 px), road region f >= 2 px, "
-                    "delta_DT 10, 128 bins over 2..18, delta_PD 0.5, SLIC S 16 m 4, at most %d rounds, tol %g"
+                    "delta_DT 10, 128 bins over 2..18, delta_PD 0.5, SLIC S 16 m 4, at most %d rounds, tol %g%s"
                     % ("perspective-transformed (windows of 16 on the fitted plane)" if matcher == "perspective"
-                       else "learned-window", det.slic_iters, det.slic_tol),
+                       else "learned-window", det.slic_iters, det.slic_tol,
+                       ", potholes in a single superpixel dropped" if det.prune_single else ""),
         "timing": "host wall clock around detect() (synchronised), median of 3 after 2 warm-ups, "
                   "mean over 2 batches",
     }

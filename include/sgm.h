@@ -518,6 +518,14 @@ sgm_status sgm_pothole_threshold_batch(const float *d2, const uint8_t *mask, int
 sgm_status sgm_pothole_label_batch(const float *d2, const uint8_t *mask, int32_t width, int32_t height,
                                    int32_t nimg, const sgm_pothole_threshold *result, int32_t *labels,
                                    void *stream);
+/* Removes the potholes that lie in a single superpixel, which Sec. III-B
+ * counts as false detections: every component of `labels` (as written by
+ * sgm_pothole_label_batch: 1 + root index, 0 elsewhere) whose pixels all
+ * have the same entry in `superpixels` (int32 [nimg][H][W], e.g. the SLIC
+ * labels of sgm_slic_batch) is set to 0, in place; the other components
+ * keep their labels.  Both arrays device, dense. */
+sgm_status sgm_pothole_prune_batch(const int32_t *superpixels, int32_t width, int32_t height, int32_t nimg,
+                                   int32_t *labels, void *stream);
 
 /* ------------------------------------------------------------------------
  * Superpixels on D2 (SLIC, Sec. II-D) and the superpixel-mean map D3

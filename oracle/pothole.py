@@ -130,3 +130,17 @@ def label(d2, t_s, mask=None):
                     seen[yy, xx] = True
                     queue.append((yy, xx))
     return lab
+
+
+def prune_single_superpixel(labels, superpixels):
+    """Sec. III-B counts a detected pothole made of a single superpixel as a
+    false one: every component of `labels` (0 = none) whose pixels all lie
+    in one superpixel of `superpixels` is removed (set to 0); the others
+    keep their labels."""
+    lab = np.array(labels, dtype=np.int32, copy=True)
+    sp = np.asarray(superpixels)
+    for name in np.unique(lab[lab > 0]):
+        if np.unique(sp[lab == name]).size == 1:
+            lab[lab == name] = 0
+    return lab
+

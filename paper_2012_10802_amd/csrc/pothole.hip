@@ -36,7 +36,12 @@
 //                   name     root + 1.
 //                 Row-major order inside a tile agrees with the image's,
 //                 so a tile component's root is its smallest image index
-//                 and the global roots come out as in a pixel-level pass.
+//                 and the global roots come out as in a pixel-level pass;
+//   k_pd_prune_*  components lying in a single superpixel removed (Sec.
+//                 III-B counts them as false detections): mark the roots of
+//                 components with a pixel in another superpixel than the
+//                 root's (sign bit of the root's label), drop the unmarked,
+//                 clear the marks.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -406,7 +411,55 @@ __global__ void k_pd_label_name(size_t n, int32_t *__restrict__ lab)
         lab[i] += 1;
 }
 
+// root label mark (the sign bit; labels are >= 0): the component spans
+// several superpixels
+constexpr int32_t kMulti = (int32_t)0x80000000u;
+constexpr int32_t kName = 0x7FFFFFFF;
+
+__global__ void k_pd_prune_mark(const int32_t *__restrict__ sp, size_t n, int npix, int32_t *__restrict__ lab)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int32_t l = lab[i] & kName;
+        if (l == 0) continue;
+        const size_t root = i - i % npix + (size_t)(l - 1);
+        if (sp[i] != sp[root] && !(lab[root] & kMulti)) atomicOr(&lab[root], kMulti);
+    }
+}
+
+// A root without the mark is dropped by its own thread; the others read its
+// label before or after that, and see no mark either way.
+__global__ void k_pd_prune_drop(size_t n, int npix, int32_t *__restrict__ lab)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int32_t l = lab[i] & kName;
+        if (l == 0) continue;
+        const size_t root = i - i % npix + (size_t)(l - 1);
+        if (!(lab[root] & kMulti)) lab[i] = 0;
+    }
+}
+
+__global__ void k_pd_prune_clear(size_t n, int32_t *__restrict__ lab)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        lab[i] &= kName;
+}
+
 }  // namespace
+
+hipError_t launch_pothole_prune(const int32_t *superpixels, int W, int H, int nimg, int32_t *labels, hipStream_t s)
+{
+    const int npix = W * H;
+    const size_t total = (size_t)npix * nimg;
+    const unsigned blocks = (unsigned)((total + 255) / 256 < 8192 ? (total + 255) / 256 : 8192);
+    k_pd_prune_mark<<<blocks, 256, 0, s>>>(superpixels, total, npix, labels);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_pd_prune_drop<<<blocks, 256, 0, s>>>(total, npix, labels);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_pd_prune_clear<<<blocks, 256, 0, s>>>(total, labels);
+    return hipGetLastError();
+}
 
 size_t pothole_workspace_bytes(int nbins, int nimg)
 {

@@ -628,6 +628,19 @@ sgm_status sgm_pothole_label_batch(const float *d2, const uint8_t *mask, int32_t
     return e == hipSuccess ? SGM_OK : hip_fail(e, "pothole label launch");
 }
 
+sgm_status sgm_pothole_prune_batch(const int32_t *superpixels, int32_t W, int32_t H, int32_t nimg, int32_t *labels,
+                                   void *stream)
+{
+    if (!superpixels || !labels) return fail(SGM_ERR_INVALID, "superpixels and labels must not be NULL");
+    sgm_status st = check_maps(W, H, nimg);
+    if (st != SGM_OK) return st;
+    if (!is_aligned(superpixels, 4) || !is_aligned(labels, 4))
+        return fail(SGM_ERR_INVALID, "superpixels or labels misaligned");
+    if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
+    hipError_t e = sgm::launch_pothole_prune(superpixels, W, H, nimg, labels, (hipStream_t)stream);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "pothole prune launch");
+}
+
 sgm_status sgm_road_window_map_batch(const sgm_road_fit *fit, int32_t W, int32_t H, int32_t nimg, int32_t w,
                                      double scale, int32_t *lo, void *stream)
 {

@@ -151,6 +151,7 @@ hipError_t launch_slic(const float *d2, const uint8_t *mask, int W, int H, int n
 hipError_t launch_pothole_threshold(const float *d2, const uint8_t *mask, int W, int H, int nimg, double lo,
                                     double b, int nbins, double delta_pd, sgm_pothole_threshold *out,
                                     double *curve, void *ws, hipStream_t s);
+hipError_t launch_pothole_prune(const int32_t *superpixels, int W, int H, int nimg, int32_t *labels, hipStream_t s);
 hipError_t launch_pothole_label(const float *d2, const uint8_t *mask, int W, int H, int nimg,
                                 const sgm_pothole_threshold *thr, int32_t *labels, hipStream_t s);
 

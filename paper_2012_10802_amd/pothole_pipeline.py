@@ -23,7 +23,9 @@ enqueued on one stream (the learned-window matcher adds its side streams).
      is within `slic_tol` (the residual of Sec. II-D), and their means D3
      (Sec. II-E);
   6. potholes: the 8-connected components of D3 below t_s, labelled
-     1 + the smallest row-major index of the component.
+     1 + the smallest row-major index of the component; with
+     `prune_single` (default) those lying in a single superpixel are
+     removed, as Sec. III-B counts them as false detections.
 """
 from __future__ import annotations
 
@@ -44,13 +46,15 @@ class PotholeDetector:
 
     def __init__(self, width, height, batch, ndisp=192, census=7, npaths=8, p1=10, p2=120, matcher="perspective",
                  net=None, delta_dt=10.0, delta_pd=0.5, nbins=128, span=8.0, slic_step=16, slic_m=4.0,
-                 slic_iters=10, slic_tol=SLIC_TOL, min_disp=0.5, margin=4.0, f_min=2.0, refit_tols=(2.0, 1.0), device="cuda"):
+                 slic_iters=10, slic_tol=SLIC_TOL, min_disp=0.5, margin=4.0, f_min=2.0, refit_tols=(2.0, 1.0),
+                 prune_single=True, device="cuda"):
         self.W, self.H, self.n = int(width), int(height), int(batch)
         self.delta_dt, self.delta_pd, self.nbins, self.span = float(delta_dt), float(delta_pd), int(nbins), span
         self.slic_step, self.slic_m, self.slic_iters = int(slic_step), float(slic_m), int(slic_iters)
         self.slic_tol = float(slic_tol)
         self.min_disp, self.margin, self.f_min = float(min_disp), float(margin), float(f_min)
         self.refit_tols = tuple(float(t) for t in refit_tols)
+        self.prune_single = bool(prune_single)
         dev = self.device = torch.device(device)
         n, H, W = self.n, self.H, self.W
         if matcher == "perspective":
@@ -120,4 +124,6 @@ class PotholeDetector:
                labels=self.superpixels, d3=self.d3, centres=self.centres, workspace=self.slic_ws,
                rounds=self.slic_rounds, stream=stream)
         S.pothole_labels(self.d3, self.threshold, mask=self.road, labels=self.labels, stream=stream)
+        if self.prune_single:
+            S.pothole_prune(self.labels, self.superpixels, stream=stream)
         return self.labels

@@ -114,6 +114,7 @@ def _load_library():
         "sgm_pothole_workspace_size": [I, I, ctypes.POINTER(S)],
         "sgm_pothole_threshold_batch": [P, P, I, I, I, D, D, I, D, P, P, P, S, P],
         "sgm_pothole_label_batch": [P, P, I, I, I, P, P, P],
+        "sgm_pothole_prune_batch": [P, I, I, I, P, P],
         "sgm_slic_workspace_size": [I, I, I, I, ctypes.POINTER(S)],
         "sgm_slic_batch": [P, P, I, I, I, I, D, I, D, P, P, P, P, P, S, P],
         "sgm_road_mask_batch": [P, P, I, I, I, D, D, P, P],
@@ -436,6 +437,19 @@ def pothole_labels(d2, result, mask=None, labels=None, stream=None):
     _need(labels, torch.int32, (n, H, W), "labels")
     _check(_lib.sgm_pothole_label_batch(_ptr(d), _ptr(mask), W, H, n, _ptr(result), _ptr(labels),
                                         _stream(stream)), "sgm_pothole_label_batch")
+    return labels
+
+
+def pothole_prune(labels, superpixels, stream=None):
+    """Removes, in place, the components of int32 device labels [H, W] or
+    [n, H, W] that lie in a single superpixel (int32 superpixel labels of
+    the same shape); returns `labels`."""
+    lab = _maps(labels, torch.int32, "labels")
+    sp = _maps(superpixels, torch.int32, "superpixels")
+    if tuple(sp.shape) != tuple(lab.shape):
+        raise ValueError("superpixels must have the shape of labels")
+    n, H, W = lab.shape
+    _check(_lib.sgm_pothole_prune_batch(_ptr(sp), W, H, n, _ptr(lab), _stream(stream)), "sgm_pothole_prune_batch")
     return labels
 
 

@@ -329,6 +329,23 @@ def test_pothole_calls_validate_before_launch():
     assert lib.sgm_debug_inject_fault(0) == 0
 
 
+def test_pothole_prune_validates_before_launch():
+    import ctypes
+    from paper_2012_10802_amd import sgm
+    lib = sgm.library()
+    d = ctypes.c_void_p(1 << 20)
+    P = lib.sgm_pothole_prune_batch
+    assert P(None, 64, 48, 2, d, None) == -1
+    assert P(d, 64, 48, 2, None, None) == -1
+    assert P(d, 0, 48, 2, d, None) == -1
+    assert P(d, 64, 48, 70000, d, None) == -2
+    assert P(ctypes.c_void_p((1 << 20) + 2), 64, 48, 2, d, None) == -1
+    assert P(d, 64, 48, 2, ctypes.c_void_p((1 << 20) + 2), None) == -1
+    assert lib.sgm_debug_inject_fault(1) == 0
+    assert P(d, 64, 48, 2, d, None) == -3
+    assert lib.sgm_debug_inject_fault(0) == 0
+
+
 def test_slic_calls_validate_before_launch():
     import ctypes
     from paper_2012_10802_amd import sgm

@@ -177,3 +177,29 @@ def test_full_size_batch_of_16(lib):
     for i in (0, 5, 15):
         np.testing.assert_array_equal(lab[i], opd.label(Ds[i], got[i]["t_s"]))
     assert all(g["status"] == 0 for g in got)
+
+
+def test_prune_single_superpixel_matches_oracle(lib):
+    """Components of thresholded maps pruned by superpixels: the hand-worked
+    case, and labels of two-level maps against SLIC superpixels (several
+    maps per launch, ragged sizes), bit for bit with the oracle."""
+    import torch
+    from oracle import slic as oslic
+    lab = np.array([[1, 1, 0, 4, 4], [1, 0, 0, 0, 4]], np.int32)
+    sp = np.array([[3, 3, 3, 4, 5], [3, 3, 4, 4, 5]], np.int32)
+    got = lib.pothole_prune(_dev(lab), _dev(sp)).cpu().numpy()
+    np.testing.assert_array_equal(got, [[0, 0, 0, 4, 4], [0, 0, 0, 0, 4]])
+    rng = np.random.default_rng(21)
+    for H, W in ((60, 90), (37, 53)):
+        Ds = np.stack([_two_level(rng, H, W) for _ in range(3)])
+        res = torch.zeros((3, lib.POTHOLE_WORDS), dtype=torch.float64, device="cuda")
+        res[:, 1] = 9.3  # t_s (status 0): the potholes and many small noise components
+        labels = lib.pothole_labels(_dev(Ds), res)
+        before = labels.cpu().numpy()
+        sp, _, _ = lib.slic(_dev(Ds), 6, 2.0, 4)
+        want = [opd.prune_single_superpixel(before[i], sp[i].cpu().numpy()) for i in range(3)]
+        got = lib.pothole_prune(labels, sp).cpu().numpy()  # in place
+        for i in range(3):
+            np.testing.assert_array_equal(got[i], want[i])
+            # some components kept, some removed
+            assert (want[i] > 0).any() and len(np.unique(before[i])) > len(np.unique(want[i]))

@@ -59,7 +59,7 @@ def test_plain_detector_stage_by_stage():
     assert int(det.slic_rounds[i]) == info["rounds"]
     np.testing.assert_array_equal(det.superpixels[i].cpu().numpy(), sp)
     np.testing.assert_array_equal(det.d3[i].cpu().numpy(), d3)
-    np.testing.assert_array_equal(labels[i], opd.label(d3, t["t_s"], road))
+    np.testing.assert_array_equal(labels[i], opd.prune_single_superpixel(opd.label(d3, t["t_s"], road), sp))
 
 
 @pytest.mark.parametrize("matcher", ["perspective", "learned"])

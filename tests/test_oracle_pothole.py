@@ -119,3 +119,19 @@ def test_masks_borders_and_degenerate_maps():
     # maps too small for any vector
     assert pothole.threshold(np.ones((2, 9), np.float32), 0.0, 16.0, 32, 1.0)["status"] == 1
     assert not pothole.label(D, -math.inf).any()
+
+
+def test_prune_single_superpixel_hand_worked():
+    """Sec. III-B: a pothole inside one superpixel counts as false.  Two
+    components: the left one lies in superpixel 3 only (removed), the right
+    one spans superpixels 4 and 5 (kept with its label)."""
+    lab = np.array([[1, 1, 0, 4, 4],
+                    [1, 0, 0, 0, 4]], np.int32)
+    sp = np.array([[3, 3, 3, 4, 5],
+                   [3, 3, 4, 4, 5]], np.int32)
+    got = pothole.prune_single_superpixel(lab, sp)
+    np.testing.assert_array_equal(got, [[0, 0, 0, 4, 4], [0, 0, 0, 0, 4]])
+    # nothing to prune when every component spans two superpixels
+    np.testing.assert_array_equal(pothole.prune_single_superpixel(lab, np.arange(10).reshape(2, 5)), lab)
+    # everything pruned when the map is one superpixel
+    assert not pothole.prune_single_superpixel(lab, np.zeros((2, 5), np.int32)).any()
