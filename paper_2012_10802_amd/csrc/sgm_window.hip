@@ -653,8 +653,8 @@ __global__ __launch_bounds__(64) void k_aggregate_win16_h(Win16Params a)
 // Vertical and diagonal scanlines: neighbouring lanes are neighbouring
 // pixels of one row at every step, so one scanline per lane keeps every
 // access contiguous.
-template <int PF>
-__global__ __launch_bounds__(256, 2) void k_aggregate_win16(Win16Params a)
+template <int PF, int MINWG>
+__global__ __launch_bounds__(256, MINWG) void k_aggregate_win16(Win16Params a)
 {
     __shared__ uint32_t rows[kW16Lines * kW16Row];
     uint32_t *row = rows + threadIdx.x * kW16Row;
@@ -678,9 +678,11 @@ __global__ __launch_bounds__(256, 2) void k_aggregate_win16(Win16Params a)
         win16_scan<PF, kDiagonal>(a, rc, rl, ro, du, dv, g, row);
 }
 
-// steps of cost prefetched by k_aggregate_win16: 12 (about 200 registers, two
-// waves per SIMD) beat 6 (four waves per SIMD) by 6 % on 16 x 1920x1080 pairs
-constexpr int kWin16Prefetch = 12;
+// Steps of cost prefetched by k_aggregate_win16, by frame size (measured on
+// batches of 16 pairs): on 1920x1080, 12 steps (about 200 registers, two
+// waves per SIMD) beat 6 (four waves per SIMD) by 6 %; on 1280x720, with
+// fewer scanlines to spread, 6 steps beat 12 by 13 %.
+constexpr long long kWin16DeepPixels = 1500000;  // pixels per pair from which 12 steps are used
 
 }  // namespace
 
@@ -849,8 +851,12 @@ hipError_t launch_match_win_pairs(const Problem &pb, const WinPairs &b, hipStrea
             }
         p.np = no;
         p.gstart[no] = acc;
-        if (no > 0)
-            hipLaunchKernelGGL(k_aggregate_win16<kWin16Prefetch>, dim3(acc, b.npairs), dim3(kW16Lines), 0, s, p);
+        if (no > 0) {
+            if ((long long)pb.W * pb.H >= kWin16DeepPixels)
+                hipLaunchKernelGGL((k_aggregate_win16<12, 2>), dim3(acc, b.npairs), dim3(kW16Lines), 0, s, p);
+            else
+                hipLaunchKernelGGL((k_aggregate_win16<6, 4>), dim3(acc, b.npairs), dim3(kW16Lines), 0, s, p);
+        }
         if (hs != s) {
             const hipError_t e1 = hipEventRecord(ss->join, hs);
             const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s, ss->join, 0) : e1;
