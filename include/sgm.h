@@ -62,7 +62,9 @@ typedef enum {
 
 /* Parameters of one matching problem (Sec. II-B, eq. (7)-(8)). */
 typedef struct {
-    int32_t width, height; /* W, H >= 1, W * H * ndisp < 2^31            */
+    int32_t width, height; /* W, H >= 1, W * H * ndisp < 2^31, and < 2^30
+                              when Cmax + P2 > 255 (uint16 per-path volumes;
+                              larger ones give SGM_ERR_UNSUPPORTED)        */
     int32_t census;        /* census window side n: 3, 5 or 7 (Cmax = n*n-1) */
     int32_t ndisp;         /* window width w, 1..256                       */
     int32_t npaths;        /* 4 or 8                                       */
@@ -104,7 +106,8 @@ sgm_status sgm_aggregate(sgm_plan_t plan, const uint8_t *cost, uint16_t *sum,
                          void *workspace, size_t workspace_bytes, void *stream);
 
 /* One direction's aggregated cost L_r (device, uint16 [H][W][w]), for
- * testing and inspection; path in 0..7 (see the direction table above). */
+ * testing and inspection; path in 0..7 (see the direction table above).
+ * Being uint16, it needs W * H * ndisp < 2^30 (else SGM_ERR_UNSUPPORTED). */
 sgm_status sgm_aggregate_path(sgm_plan_t plan, const uint8_t *cost, int32_t path,
                               uint16_t *L, void *stream);
 
@@ -316,7 +319,8 @@ typedef struct {
     int32_t width, height; /* W, H of this pair                               */
     int32_t ndisp;         /* window width w; must be a multiple of the lane
                               width (2, 4, 8, 12, 16 values for w up to 32,
-                              64, 128, 192, 256)                           */
+                              64, 128, 192, 256); W * H * ndisp < 2^31, and
+                              < 2^30 when Cmax + P2 > 255                  */
     int32_t pitch;         /* bytes between image rows, >= width             */
     const uint8_t *left, *right; /* device images [H][pitch]                 */
     const int32_t *d_lo;   /* device [H] window starts, or NULL for all 0    */

@@ -162,6 +162,12 @@ sgm_status sgm_plan(const sgm_params *pr, sgm_plan_t *out)
     p->kc.vpl = choose_vpl(q.ndisp);
     p->kc.aligned = (q.ndisp % p->kc.vpl) == 0;
     p->kc.l8 = cmax + q.p2 <= 255;
+    if (!p->kc.l8 && (long long)q.width * q.height * q.ndisp >= sgm::kMaxU16Volume) {
+        delete p;
+        return fail(SGM_ERR_UNSUPPORTED,
+                    "uint16 per-path volumes (Cmax + P2 > 255) need W*H*ndisp < 2^30 (got %lld)",
+                    (long long)q.width * q.height * q.ndisp);
+    }
     p->kc.agg_block = 256;
     for (int i = 0; i < 8; ++i) p->paths[i] = i;
     p->n_pix = (size_t)q.width * q.height;
@@ -240,6 +246,8 @@ sgm_status sgm_aggregate_path(sgm_plan_t plan, const uint8_t *cost, int32_t path
     if (sgm_status s = check_plan(plan)) return s;
     if (!cost || !L) return fail(SGM_ERR_INVALID, "cost and L must not be NULL");
     if (path < 0 || path > 7) return fail(SGM_ERR_INVALID, "path %d not in [0, 7]", path);
+    if ((long long)plan->n_vol >= sgm::kMaxU16Volume)
+        return fail(SGM_ERR_UNSUPPORTED, "sgm_aggregate_path writes uint16: W*H*ndisp must be < 2^30");
     const sgm::KernelConfig kc = config_for(plan, cost, L);
     const int paths[1] = {path};
     if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");

@@ -266,6 +266,8 @@ sgm_status sgm_batch_plan(const sgm_batch_params *prm, const sgm_pair *pairs, in
                          p.ndisp, lane_width(p.ndisp));
         if ((long long)p.width * p.height * p.ndisp >= (1ll << 31))
             return bfail(SGM_ERR_UNSUPPORTED, "pair %d: W*H*ndisp must be < 2^31", i);
+        if (cmax + q.p2 > 255 && (long long)p.width * p.height * p.ndisp >= sgm::kMaxU16Volume)
+            return bfail(SGM_ERR_UNSUPPORTED, "pair %d: uint16 per-path volumes need W*H*ndisp < 2^30", i);
         if (!p.left || !p.right || !p.disp_int) return bfail(SGM_ERR_INVALID, "pair %d: NULL buffer", i);
     }
     sgm_batch_s *b = new (std::nothrow) sgm_batch_s();

@@ -15,6 +15,10 @@ constexpr int kErrorBufferSize = 512;
 constexpr int kCensusTW = 64;  // census tile width in pixels (16 threads of 4 pixels)
 constexpr int kCensusTH = 16;  // census tile height in rows (16 threads per row)
 char *error_buffer();
+// The aggregation addresses a volume with 32-bit byte offsets and drops a
+// store by pointing it at byte 2^31, which must lie outside every volume:
+// a uint16 volume therefore holds fewer than 2^30 values.
+constexpr long long kMaxU16Volume = 1ll << 30;
 
 // Launch configuration chosen at plan time.
 struct KernelConfig {

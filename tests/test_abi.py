@@ -70,6 +70,53 @@ def test_plan_validation(sgm, kw, want):
     assert _plan_status(sgm, **kw) == want
 
 
+@pytest.mark.parametrize("kw,want", [
+    # uint8 volumes (Cmax + P2 = 168): any W*H*ndisp below 2^31
+    ({"width": 4096, "height": 2304, "ndisp": 128}, 0),
+    # uint16 volumes (Cmax + P2 = 268): 4096x2304x128 = 1.2e9 values is more
+    # than 2^30, so a dropped store (byte 2^31) would land inside the volume
+    ({"width": 4096, "height": 2304, "ndisp": 128, "p2": 220}, -2),
+    ({"width": 4096, "height": 2048, "ndisp": 128, "p2": 220}, -2),   # exactly 2^30
+    ({"width": 4096, "height": 2047, "ndisp": 128, "p2": 220}, 0),    # 2^30 - 4096*128
+])
+def test_plan_rejects_uint16_volumes_reaching_the_drop_offset(sgm, kw, want):
+    assert _plan_status(sgm, **kw) == want
+    if want:
+        assert b"2^30" in sgm.library().sgm_last_error()
+
+
+def test_aggregate_path_rejects_volumes_reaching_the_drop_offset(sgm):
+    """sgm_aggregate_path always writes uint16: a plan with 2^30 or more
+    values is refused there before anything is enqueued."""
+    lib = sgm.library()
+    dummy = ctypes.c_void_p(256)
+    plan = sgm.sgm_plan(4096, 2304, 7, 128, 8, 10, 120)
+    try:
+        assert lib.sgm_aggregate_path(plan, dummy, 0, dummy, None) == -2
+        assert b"2^30" in lib.sgm_last_error()
+    finally:
+        sgm.sgm_plan_free(plan)
+
+
+def test_batch_plan_rejects_uint16_volumes_reaching_the_drop_offset(sgm):
+    lib = sgm.library()
+
+    def status(W, H, w, p2):
+        prm = sgm.sgm_batch_params(7, 8, 10, p2, 0)
+        arr = (sgm.sgm_pair * 1)(sgm.sgm_pair(W, H, w, W, 256, 256, None, 256, None))
+        h = ctypes.c_void_p()
+        st = lib.sgm_batch_plan(ctypes.byref(prm), arr, 1, ctypes.byref(h))
+        if st == 0:
+            lib.sgm_batch_free(h)
+        return st
+
+    assert status(4096, 2304, 128, 220) == -2
+    # accepted by validation; without a GPU the plan's pinned queue cannot
+    # be allocated afterwards (SGM_ERR_HIP)
+    assert status(4096, 2047, 128, 220) in (0, -3)
+    assert status(4096, 2304, 128, 120) in (0, -3)
+
+
 def test_error_strings(sgm):
     lib = sgm.library()
     assert lib.sgm_status_str(-4) == b"SGM_ERR_WORKSPACE"
