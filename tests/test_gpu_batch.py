@@ -137,10 +137,10 @@ def _road_workload(counts, seed0=4000, unique=2):
     return out
 
 
-def test_mixed_64_pair_workload_matches_single_pair_path(sgm):
-    """24 x 640x480 (w 64) + 24 x 1280x720 (w 128) + 16 x 1920x1080 (w 192)
-    in one batch: every pair equals sgm_match on that pair, and one pair
-    of each size also equals the oracle on sampled rows."""
+@pytest.fixture(scope="module")
+def mixed64(sgm):
+    """The 64-pair mixed workload (24 x 640x480 w 64, 24 x 1280x720 w 128,
+    16 x 1920x1080 w 192) run once as one batch."""
     import torch
     work = _road_workload([("road640", 24), ("road1280", 24), ("road1920", 16)])
     dev_imgs = {}
@@ -154,6 +154,16 @@ def test_mixed_64_pair_workload_matches_single_pair_path(sgm):
     b = sgm.Batch(pairs, census=N, npaths=R, p1=P1, p2=P2)
     b.run()
     torch.cuda.synchronize()
+    out = [(b.disp_int[i].cpu().numpy(), b.disp_sub[i].cpu().numpy()) for i in range(len(work))]
+    del b, pairs
+    torch.cuda.empty_cache()
+    return work, dev_imgs, out
+
+
+def test_mixed_64_pair_workload_matches_single_pair_path(sgm, mixed64):
+    """Every pair of the 64-pair batch equals sgm_match on that pair."""
+    import torch
+    work, dev_imgs, out = mixed64
     singles = {}
     for i, (name, w, p) in enumerate(work):
         key = id(p)
@@ -164,10 +174,20 @@ def test_mixed_64_pair_workload_matches_single_pair_path(sgm):
             torch.cuda.synchronize()
             singles[key] = (di.cpu().numpy(), ds.cpu().numpy())
             del m
-        np.testing.assert_array_equal(b.disp_int[i].cpu().numpy(), singles[key][0], err_msg="pair %d" % i)
-        np.testing.assert_array_equal(b.disp_sub[i].cpu().numpy(), singles[key][1], err_msg="pair %d" % i)
-    # the oracle on the smallest size, whole frame
-    name, w, p = work[0]
+        np.testing.assert_array_equal(out[i][0], singles[key][0], err_msg="pair %d" % i)
+        np.testing.assert_array_equal(out[i][1], singles[key][1], err_msg="pair %d" % i)
+
+
+@pytest.mark.parametrize("size", ["road640", "road1280", "road1920"])
+def test_mixed_64_pair_workload_matches_oracle(mixed64, size):
+    """One pair of each size of the 64-pair batch equals the oracle over the
+    whole frame: integer disparity bit for bit, sub-pixel disparity within
+    1e-4 px (and in fact bit for bit)."""
+    work, _, out = mixed64
+    i = next(k for k, (name, _, _) in enumerate(work) if name == size)
+    name, w, p = work[i]
     want_i, want_s = oracle.sgm(p.left, p.right, N, w, R, P1, P2)
-    np.testing.assert_array_equal(b.disp_int[0].cpu().numpy().view(np.uint16), want_i)
-    np.testing.assert_array_equal(b.disp_sub[0].cpu().numpy(), want_s)
+    got_i = out[i][0].view(np.uint16)
+    np.testing.assert_array_equal(got_i, want_i, err_msg="pair %d (%s)" % (i, name))
+    assert np.abs(out[i][1] - want_s).max() <= 1e-4
+    np.testing.assert_array_equal(out[i][1], want_s, err_msg="pair %d (%s)" % (i, name))

@@ -198,6 +198,13 @@ def test_road1280_census7_8paths_full(lib):
     _full_parity(lib, "road1280", 2000)
 
 
+def test_road1920_census7_8paths_full(lib):
+    """1920x1080, census 7x7, 8 paths, disparities 0..191 (twelve values per
+    lane, the widest frame of the batched and learned-window workloads):
+    every output of the plain full-range path."""
+    _full_parity(lib, "road1920", 2001)
+
+
 def test_road1280_row_windows_full(lib):
     """1280x720 with per-row windows of width 24 centred on the road model."""
     p, c = _road("road1280_pt", 3000)

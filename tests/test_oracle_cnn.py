@@ -138,3 +138,57 @@ def test_merge_fallback_takes_rect_results_on_masked_pixels():
     assert (di[m] >= 100).all() and (di[~m] < 50).all()
     np.testing.assert_array_equal(di[2:, 1:5][m[2:, 1:5]], bi[m[2:, 1:5]])
     np.testing.assert_array_equal(ds[~m], ws[~m])
+
+
+def _golden():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "hand_cnn_loss_adam.json")) as f:
+        return json.load(f)
+
+
+def test_loss_value_and_gradient_on_hand_worked_pixels():
+    """The loss value itself (not only its gradient): Huber delta 1, the
+    strict |e| < 1 confidence target (pixel C sits exactly at |e| = 1) and
+    the mean over pixels, worked by hand."""
+    g = _golden()["loss"]
+    out = np.zeros((1, 1, 3, cnn.CH))
+    out[0, 0, :, 0] = g["offset"]
+    out[0, 0, :, 1] = g["logit"]
+    coarse = np.array(g["coarse"]).reshape(1, 1, 3)
+    label = np.array(g["label"]).reshape(1, 1, 3)
+    loss, grad = cnn.loss_and_grad(out, coarse, label)
+    assert abs(loss - g["loss"]) <= 1e-14
+    np.testing.assert_allclose(grad[0, 0, :, 0], g["d_offset"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(grad[0, 0, :, 1], g["d_logit"], rtol=0, atol=1e-15)
+    assert not grad[..., 2:].any()
+
+
+def test_adam_second_step_hand_worked():
+    """Two bias-corrected steps with different gradients, worked by hand."""
+    g = _golden()["adam"]
+    p = np.array(g["p0"])
+    m = np.zeros(2)
+    v = np.zeros(2)
+    p, m, v = cnn.adam(p, m, v, np.array(g["g"][0]), 1, lr=g["lr"], eps=0.0)
+    np.testing.assert_allclose(p, g["p1"], rtol=0, atol=1e-15)
+    p, m, v = cnn.adam(p, m, v, np.array(g["g"][1]), 2, lr=g["lr"], eps=0.0)
+    np.testing.assert_allclose(m, g["m2"], rtol=1e-14)
+    np.testing.assert_allclose(v, g["v2"], rtol=1e-13)
+    assert abs(p[1] - g["p2_component2"]) <= 1e-14
+    assert abs(p[0] - g["p2_component1_approx"]) <= g["p2_component1_tol"]
+
+
+def test_adam_constant_gradient_moves_by_the_learning_rate_every_step():
+    """With a constant gradient the bias-corrected moments equal g and g^2 at
+    every step t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so each step moves
+    by exactly lr * sign(g) when eps = 0 -- a property of the published
+    update that fails for a bias correction taken at the wrong step."""
+    g = np.array([0.7, -0.03, 5.0])
+    p = np.array([0.0, 1.0, -2.0])
+    m = np.zeros(3)
+    v = np.zeros(3)
+    for step in range(1, 8):
+        before = p.copy()
+        p, m, v = cnn.adam(p, m, v, g, step, lr=0.01, eps=0.0)
+        np.testing.assert_allclose(before - p, 0.01 * np.sign(g), rtol=1e-9, err_msg="step %d" % step)
