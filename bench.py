@@ -86,6 +86,71 @@ def eval_mask(p, w, r, d_lo=None):
     return m
 
 
+def host_cpu():
+    """The host the CPU oracle runs on: CPU model, logical CPUs, CPUs this
+    process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def _median_time(fn, runs):
+    import numpy as np
+    ts = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t)
+    return float(np.median(ts)), [round(x, 3) for x in ts]
+
+
+def cpu_baseline_frame(pair, n, w, R, p1, p2, d_lo, runs=3, log=None):
+    """The C oracle as it stands on the same frame: its own threading (one
+    thread per path direction, so at most R), median of `runs` whole-frame
+    runs; and single-threaded on the middle quarter of the rows (same width
+    and window), median of `runs`.  Rates in Mdisp-evals/s over the evals
+    each run covers."""
+    import oracle
+    H, W = pair.left.shape
+    dl = None if d_lo is None else d_lo
+    threads = min(R, oracle.num_threads())
+    med, ts = _median_time(lambda: oracle.sgm(pair.left, pair.right, n, w, R, p1, p2, dl), runs)
+    if log:
+        log("cpu oracle, %d threads: %s s" % (threads, ts))
+    v0, v1 = 3 * H // 8, 5 * H // 8
+    band_dl = None if dl is None else dl[v0:v1]
+    saved = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        med1, ts1 = _median_time(lambda: oracle.sgm(pair.left[v0:v1], pair.right[v0:v1], n, w, R, p1, p2, band_dl),
+                                 runs)
+    finally:
+        oracle.set_num_threads(saved)
+    if log:
+        log("cpu oracle, 1 thread, rows %d..%d: %s s" % (v0, v1 - 1, ts1))
+    evals = W * H * w
+    return {"value": round(evals / med / 1e6, 3), "unit": "Mdisp-evals/s", "cores": threads, "kind": "oracle",
+            "sample": "the whole %dx%dx%d frame through the C oracle (census, cost, %d paths, selection), "
+                      "median of %d runs: %s s; the oracle's threads are its path directions"
+                      % (W, H, w, R, runs, ts),
+            "single_thread": {"value": round(W * (v1 - v0) * w / med1 / 1e6, 3), "unit": "Mdisp-evals/s",
+                              "cores": 1,
+                              "sample": "rows %d..%d (the middle quarter, %dx%dx%d), median of %d runs: %s s"
+                                        % (v0, v1 - 1, W, v1 - v0, w, runs, ts1)},
+            "host": host_cpu()}
+
+
 def emit(record, args):
     """Print the one JSON line (and append it to --jsonl when given)."""
     line = json.dumps(record)
@@ -96,15 +161,19 @@ def emit(record, args):
 
 
 def run_batch(args):
-    """Batch mode: the whole batch as one captured graph per step."""
+    """Batch mode: the whole batch as one captured graph per step; per-stage
+    kernel times from eagerly enqueued runs timed with HIP events on the
+    same stream; the CPU oracle on a few pairs of each size class,
+    extrapolated in evals."""
     import numpy as np
     import torch
 
     from paper_2012_10802_amd import sgm, synth
 
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)  # noqa: E731
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
-    pairs, evals, renders = [], 0, {}
+    pairs, evals, renders, hosts = [], 0, {}, {}
     for name, count in BATCHES[args.workload]:
         c = synth.CONFIGS[name]
         for j in range(count):
@@ -112,12 +181,14 @@ def run_batch(args):
             if k not in renders:
                 seed = args.seed + 97 * j
                 p = synth.make_pair(synth.scene_for_config(name, seed), seed)
+                hosts[k] = p
                 renders[k] = (torch.from_numpy(p.left).to(dev), torch.from_numpy(p.right).to(dev))
             L, R = renders[k]
             pairs.append({"left": L, "right": R, "ndisp": c["ndisp"]})
             evals += c["width"] * c["height"] * c["ndisp"]
     c0 = synth.CONFIGS[BATCHES[args.workload][0][0]]
-    b = sgm.Batch(pairs, census=c0["census"], npaths=c0["npaths"], p1=c0["p1"], p2=c0["p2"], device=dev)
+    n_cen, R_paths, p1, p2 = c0["census"], c0["npaths"], c0["p1"], c0["p2"]
+    b = sgm.Batch(pairs, census=n_cen, npaths=R_paths, p1=p1, p2=p2, device=dev)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         tuning = b.autotune(args.tune_cache)
@@ -134,7 +205,26 @@ def run_batch(args):
         e1.record(stream)
         stream.synchronize()
         t1 = time.perf_counter()
+        # the same kernels enqueued eagerly, stages bracketed by HIP events
+        stage = np.array([b.run_timed(stream) for _ in range(args.steps)])
     ms = (t1 - t0) * 1e3 / args.steps
+    census_ms, cost_ms, agg_ms, wta_ms = (float(x) for x in stage.mean(axis=0))
+    log("batch stages (ms, mean of %d): census %.3f cost %.3f aggregate %.3f select %.3f"
+        % (args.steps, census_ms, cost_ms, agg_ms, wta_ms))
+    # algorithmic bytes of the persistent aggregation: every direction reads
+    # the cost volume once and writes its uint8 volume (R (1 + 1) B/eval);
+    # the selection reads the R volumes back (R B/eval)
+    agg_bpe, wta_bpe = R_paths * 2, R_paths
+    agg_gbs = evals * agg_bpe / (agg_ms * 1e-3) / 1e9
+    wta_gbs = evals * wta_bpe / (wta_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(agg_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(agg_gbs / HBM_PEAK_GBS, 4), "traffic": counter_traffic(args.workload),
+                "bytes_per_eval": agg_bpe, "bytes_per_launch": evals * agg_bpe, "kernel": "k_aggregate_batch",
+                "launch_ms": round(agg_ms, 4),
+                "note": "every volume of the batch (29 GB) exceeds the 256 MB MALL: HBM-clean"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_batch(args, hosts, n_cen, R_paths, p1, p2, log)
     out = {
         "metric": METRIC,
         "value": round(evals / (ms * 1e-3) / 1e6, 1),
@@ -148,19 +238,65 @@ def run_batch(args):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u16",
+        "storage": "uint8 cost and per-direction volumes, packed u16 arithmetic",
         "data": "synthetic",
         "mode": "batch (one persistent aggregation launch, graph replay)",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "pairs": len(pairs), "evals_per_step": evals, "unique_renders": len(renders)},
         "tuning": {"waves_per_cu": tuning[0], "order": ["longest-first", "pair-major",
                                                         "direction-major"][tuning[1]]},
+        "roofline": roofline,
+        "kernels_ms": {"census": round(census_ms, 4), "cost": round(cost_ms, 4), "aggregate": round(agg_ms, 4),
+                       "wta": round(wta_ms, 4),
+                       "timing": "eager runs of the same kernels, HIP events between stages on the run's "
+                                 "stream, mean of %d" % args.steps},
+        "wta_hbm": {"bytes_per_eval": wta_bpe, "achieved": round(wta_gbs, 1), "unit": "GB/s",
+                    "frac": round(wta_gbs / HBM_PEAK_GBS, 4)},
         # whole step: cost written once and read by each of the 8 directions,
         # 8 uint8 volumes written and read back by the selection
         "step_hbm": {"bytes_per_eval": 25, "achieved": round(evals * 25 / (ms * 1e-3) / 1e9, 1), "unit": "GB/s",
                      "frac": round(evals * 25 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "cpu_baseline": cpu,
         "kernel_source_sha256": kernel_source_digest(),
     }
     emit(out, args)
+
+
+def cpu_baseline_batch(args, hosts, n, R, p1, p2, log):
+    """The C oracle on `--cpu-pairs-per-size` pairs of each size class of the
+    batch (cycling over the renders the batch uses), at the oracle's own
+    threads; the batch's CPU time is extrapolated linearly in evals from the
+    median rate of each class."""
+    import numpy as np
+
+    import oracle
+    from paper_2012_10802_amd import synth
+    threads = min(R, oracle.num_threads())
+    classes, total_s, total_evals = [], 0.0, 0
+    for name, count in BATCHES[args.workload]:
+        c = synth.CONFIGS[name]
+        rend = [hosts[k] for k in sorted(hosts) if k[0] == name]
+        ts = []
+        for j in range(args.cpu_pairs_per_size):
+            p = rend[j % len(rend)]
+            t = time.perf_counter()
+            oracle.sgm(p.left, p.right, n, c["ndisp"], R, p1, p2)
+            ts.append(time.perf_counter() - t)
+        pe = c["width"] * c["height"] * c["ndisp"]
+        med = float(np.median(ts))
+        log("cpu oracle %s: %s s per pair" % (name, [round(x, 2) for x in ts]))
+        classes.append({"class": "%dx%dx%d" % (c["width"], c["height"], c["ndisp"]), "pairs_in_batch": count,
+                        "timed_pairs": len(ts), "s_per_pair": [round(x, 3) for x in ts],
+                        "value": round(pe / med / 1e6, 3)})
+        total_s += count * med
+        total_evals += count * pe
+    return {"value": round(total_evals / total_s / 1e6, 3), "unit": "Mdisp-evals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d pairs of each size class through the C oracle (the oracle's threads are its path "
+                      "directions); the %d-pair batch's time extrapolated linearly in evals from each class's "
+                      "median: %.1f s per batch" % (args.cpu_pairs_per_size, sum(k for _, k in BATCHES[args.workload]),
+                                                     total_s),
+            "per_class": classes, "host": host_cpu()}
 
 
 def learned_vs_plain(args, log=None):
@@ -689,6 +825,9 @@ def main():
     ap.add_argument("--detector-only", action="store_true",
                     help="print only the end-to-end pothole detector")
     ap.add_argument("--jsonl", default=None, help="also append the JSON record to this file")
+    ap.add_argument("--cpu-runs", type=int, default=3, help="timed runs of the CPU oracle (median)")
+    ap.add_argument("--cpu-pairs-per-size", type=int, default=4,
+                    help="batch mode: pairs of each size class the CPU oracle times (extrapolated in evals)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one device-to-device copy of this many MiB "
                          "(reference kernel for scaling memory counters)")
@@ -796,6 +935,10 @@ def main():
            "unit": "TOP/s (u16)", "frac": round(agg_tops / VALU_PEAK_TOPS_U16, 4), "traffic": traffic}
     roofline = hbm if hbm["frac"] >= alu["frac"] else alu
     roofline["kernel"] = "k_aggregate"
+    if cost.numel() <= (256 << 20):
+        roofline["note"] = ("effective rate (algorithmic bytes / kernel time): the %d MB cost volume fits the "
+                            "256 MB MALL, which serves most of its 8 reads; the batched workload, whose volumes "
+                            "exceed it, gives the HBM-clean figure" % (cost.numel() >> 20))
     copy_ref = copy_reference(torch.device("cuda:0"))
     copy_ref["aggregate_over_copy"] = round(agg_gbs / copy_ref["achieved"], 4)
     # the whole step: cost written once, read once per direction, R volumes
@@ -814,14 +957,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        t = time.perf_counter()
-        oracle.sgm(pair.left, pair.right, n, w, R, p1, p2, None if d_lo is None else d_lo.cpu().numpy())
-        dt = time.perf_counter() - t
-        cpu = {"value": round(evals / dt / 1e6, 3), "unit": "Mdisp-evals/s",
-               "cores": min(R, oracle.num_threads()), "kind": "oracle",
-               "sample": "one full %dx%dx%d frame through the C oracle (census, cost, %d paths, "
-                         "selection), %.1f s wall" % (W, H, w, R, dt)}
+        cpu = cpu_baseline_frame(pair, n, w, R, p1, p2, None if d_lo is None else d_lo.cpu().numpy(),
+                                 runs=args.cpu_runs, log=lambda msg: print(msg, file=sys.stderr, flush=True))
 
     learned = None
     if not args.no_learned and os.path.exists(args.weights):
@@ -846,6 +983,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u16",
+        "storage": "uint8 cost and per-direction volumes, packed u16 arithmetic",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "width": W, "height": H, "ndisp": w, "census": n, "npaths": R,

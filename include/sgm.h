@@ -195,7 +195,15 @@ sgm_status sgm_match_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *ri
  *   disp_int      device uint16 [nimg][H][W]; disp_sub float32 [nimg][H][W]
  *                 or NULL
  *   workspace     device, 256-byte aligned, sgm_workspace_size_win_batch()
- *                 bytes (pair i uses the i-th sgm_workspace_size() slice). */
+ *                 bytes (pair i uses the i-th sgm_workspace_size() slice).
+ * Library-owned state: the horizontal directions are aggregated on a second
+ * stream per device, created (non-blocking, default priority) on the first
+ * call on that device and kept until the process ends; `stream` forks to it
+ * and joins back through two library-owned events, so the call stays
+ * ordered on `stream` like every other call.  The fork and join are
+ * serialised by a process-wide mutex: concurrent callers (any thread, any
+ * stream) run this call's enqueue one at a time, and their horizontal
+ * passes queue on the one side stream. */
 sgm_status sgm_workspace_size_win_batch(sgm_plan_t plan, int32_t nimg, size_t *bytes);
 sgm_status sgm_match_win_batch(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
                                int32_t pitch, int64_t image_stride, const int32_t *lo,
@@ -345,7 +353,11 @@ typedef struct sgm_batch_s *sgm_batch_t;
 
 /* Validate and lay out a batch (host; allocates pinned host memory for the
  * descriptor tables).  The pairs' buffers must stay valid while the batch
- * is used. */
+ * is used.  Every run and graph replay uploads the tables from that pinned
+ * memory; sgm_batch_set_tuning (and the autotuner), sgm_batch_capture and
+ * sgm_batch_free rewrite or release it, and the graph, only after the
+ * device has finished every run and replay already enqueued (the host
+ * blocks on the batch's last enqueued work). */
 sgm_status sgm_batch_plan(const sgm_batch_params *params, const sgm_pair *pairs,
                           int32_t npairs, sgm_batch_t *out);
 void sgm_batch_free(sgm_batch_t batch);
@@ -356,6 +368,13 @@ sgm_status sgm_batch_get_tuning(sgm_batch_t batch, sgm_tuning *tuning);
 /* Enqueue one run of the whole batch on `stream`. */
 sgm_status sgm_batch_run(sgm_batch_t batch, void *workspace, size_t workspace_bytes,
                          void *stream);
+
+/* One run like sgm_batch_run that also times its stages with HIP events
+ * on `stream` and waits for them (host blocks): ms[0..3] receive the census,
+ * cost, aggregation and selection times in milliseconds.  For measurement;
+ * results are those of sgm_batch_run. */
+sgm_status sgm_batch_run_timed(sgm_batch_t batch, void *workspace, size_t workspace_bytes,
+                               void *stream, float *ms);
 
 /* Record one run into a HIP graph owned by the batch (stream capture on
  * `stream`, which must not be the null stream), and replay it.  Changing

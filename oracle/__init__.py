@@ -53,6 +53,8 @@ def _load():
         lib.oracle_sgm.argtypes = [P, P, I, I, I, I, I, I, I, I, P, P, P]
         lib.oracle_window_from_road.argtypes = [D, D, D, I, I, I, I, D, P]
         lib.oracle_num_threads.argtypes = []
+        lib.oracle_set_num_threads.argtypes = [I]
+        lib.oracle_set_num_threads.restype = None
         lib.oracle_cost_win.argtypes = [P, P, I, I, I, I, P, P]
         lib.oracle_path_win.argtypes = [P, P, I, I, I, I, I, I, I, P]
         lib.oracle_sgm_win.argtypes = [P, P, I, I, I, I, I, I, I, I, P, P, P]
@@ -81,6 +83,11 @@ def _dlo(d_lo, H):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's loop over path directions (timing only)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def census(img: np.ndarray, n: int) -> np.ndarray:

@@ -437,3 +437,14 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the direction loop in oracle_sum (timing only; results do not
+ * depend on it). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -120,20 +120,29 @@ __global__ __launch_bounds__(256) void k_wta_batch(BatchDev b)
 
 }  // namespace
 
-hipError_t launch_batch(const BatchDev &b, const BatchGrids &g, int census_n, bool l8, int agg_waves, hipStream_t s)
+hipError_t launch_batch(const BatchDev &b, const BatchGrids &g, int census_n, bool l8, int agg_waves, hipStream_t s,
+                        const hipEvent_t *ev)
 {
+    if (census_n != 3 && census_n != 5 && census_n != 7) return hipErrorInvalidValue;
+    auto mark = [&](int i) {
+        if (ev && ev[i]) hipEventRecord(ev[i], s);
+    };
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, b.counter);
+    mark(0);
     switch (census_n) {
     case 3: hipLaunchKernelGGL(k_census_batch<3>, dim3(g.census), dim3(256), 0, s, b); break;
     case 5: hipLaunchKernelGGL(k_census_batch<5>, dim3(g.census), dim3(256), 0, s, b); break;
-    case 7: hipLaunchKernelGGL(k_census_batch<7>, dim3(g.census), dim3(256), 0, s, b); break;
-    default: return hipErrorInvalidValue;
+    default: hipLaunchKernelGGL(k_census_batch<7>, dim3(g.census), dim3(256), 0, s, b); break;
     }
+    mark(1);
     hipLaunchKernelGGL(k_cost_batch, dim3(g.cost), dim3(256), 0, s, b);
+    mark(2);
     if (l8) hipLaunchKernelGGL(k_aggregate_batch<true>, dim3(agg_waves), dim3(64), 0, s, b);
     else hipLaunchKernelGGL(k_aggregate_batch<false>, dim3(agg_waves), dim3(64), 0, s, b);
+    mark(3);
     if (l8) hipLaunchKernelGGL(k_wta_batch<true>, dim3(g.wta), dim3(256), 0, s, b);
     else hipLaunchKernelGGL(k_wta_batch<false>, dim3(g.wta), dim3(256), 0, s, b);
+    mark(4);
     return hipGetLastError();
 }
 

@@ -96,9 +96,17 @@ struct sgm_batch_s {
     uint32_t *pin_items = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // recorded after every enqueued run or graph replay: the pinned tables
+    // and the graph stay untouched until the device has passed it
+    hipEvent_t inflight = nullptr;
+    bool capturing = false;
     int num_cu = 0;
     ~sgm_batch_s()
     {
+        if (inflight) {
+            hipEventSynchronize(inflight);
+            hipEventDestroy(inflight);
+        }
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
         if (pin_pairs) hipHostFree(pin_pairs);
@@ -108,8 +116,32 @@ struct sgm_batch_s {
 
 namespace {
 
+// Block until the device has finished every run and replay enqueued so far
+// (they read the pinned tables through their uploads, and replays run the
+// graph).
+void wait_inflight(sgm_batch_s *b)
+{
+    if (b->inflight) hipEventSynchronize(b->inflight);
+}
+
+// Mark the end of the work just enqueued on `st` (not while capturing: the
+// graph's own replays are marked when launched).
+hipError_t mark_inflight(sgm_batch_s *b, hipStream_t st)
+{
+    if (b->capturing) return hipSuccess;
+    if (!b->inflight) {
+        hipError_t e = hipEventCreateWithFlags(&b->inflight, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            b->inflight = nullptr;
+            return e;
+        }
+    }
+    return hipEventRecord(b->inflight, st);
+}
+
 void drop_graph(sgm_batch_s *b)
 {
+    wait_inflight(b);
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
     b->exec = nullptr;
@@ -119,6 +151,7 @@ void drop_graph(sgm_batch_s *b)
 // Queue order of the aggregation items for the current tuning.
 void order_items(sgm_batch_s *b)
 {
+    wait_inflight(b);  // a pending upload may still read the pinned queue
     std::vector<Item> &it = b->items;
     switch (b->tuning.order) {
     case 1:  // pair by pair, horizontal then diagonal then vertical inside a pair
@@ -164,7 +197,7 @@ int agg_waves(sgm_batch_s *b)
     return (int)std::max(1ll, std::min(want, (long long)b->items.size()));
 }
 
-sgm_status enqueue_run(sgm_batch_s *b, void *ws, hipStream_t st)
+sgm_status enqueue_run(sgm_batch_s *b, void *ws, hipStream_t st, const hipEvent_t *ev = nullptr)
 {
     if (sgm::fault_take(sgm::kFaultLaunch)) return bfail(SGM_ERR_HIP, "injected launch failure");
     uint8_t *base = static_cast<uint8_t *>(ws);
@@ -186,7 +219,8 @@ sgm_status enqueue_run(sgm_batch_s *b, void *ws, hipStream_t st)
     d.p2x2 = (uint32_t)b->prm.p2 * 0x10001u;
     d.cmax = b->cmax;
     d.npaths = b->prm.npaths;
-    e = sgm::launch_batch(d, b->grids, b->prm.census, b->l8, agg_waves(b), st);
+    e = sgm::launch_batch(d, b->grids, b->prm.census, b->l8, agg_waves(b), st, ev);
+    if (e == hipSuccess) e = mark_inflight(b, st);
     return e == hipSuccess ? SGM_OK : bfail(SGM_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
 }
 
@@ -402,7 +436,9 @@ sgm_status sgm_batch_capture(sgm_batch_t b, void *ws, size_t bytes, void *stream
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bfail(SGM_ERR_HIP, "begin capture: %s", hipGetErrorString(e));
+    b->capturing = true;
     sgm_status rs = enqueue_run(b, ws, st);
+    b->capturing = false;
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(st, &g);
     if (rs != SGM_OK) {
@@ -427,7 +463,30 @@ sgm_status sgm_batch_launch(sgm_batch_t b, void *stream)
     if (!b->exec) return bfail(SGM_ERR_INVALID, "no captured graph (call sgm_batch_capture first)");
     if (sgm::fault_take(sgm::kFaultLaunch)) return bfail(SGM_ERR_HIP, "injected launch failure");
     hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    if (e == hipSuccess) e = mark_inflight(b, (hipStream_t)stream);
     return e == hipSuccess ? SGM_OK : bfail(SGM_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+}
+
+sgm_status sgm_batch_run_timed(sgm_batch_t b, void *ws, size_t bytes, void *stream, float *ms)
+{
+    if (!b || !ms) return bfail(SGM_ERR_INVALID, "batch and ms must not be NULL");
+    if (sgm_status s = check_batch_ws(b, ws, bytes)) return s;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    sgm_status rs = SGM_OK;
+    for (int i = 0; i < 5 && rs == SGM_OK; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) {
+            ev[i] = nullptr;
+            rs = bfail(SGM_ERR_HIP, "event creation failed");
+        }
+    if (rs == SGM_OK) rs = enqueue_run(b, ws, (hipStream_t)stream, ev);
+    if (rs == SGM_OK) {
+        hipError_t e = hipEventSynchronize(ev[4]);
+        for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]);
+        if (e != hipSuccess) rs = bfail(SGM_ERR_HIP, "stage timing: %s", hipGetErrorString(e));
+    }
+    for (hipEvent_t x : ev)
+        if (x) hipEventDestroy(x);
+    return rs;
 }
 
 sgm_status sgm_batch_autotune(sgm_batch_t b, void *ws, size_t bytes, void *stream, const char *cache_path,

@@ -121,8 +121,10 @@ struct BatchGrids {
     int census, cost, wta;
 };
 
+// ev (may be NULL, as may each entry): events recorded before the census,
+// cost, aggregation and selection launches and after the selection.
 hipError_t launch_batch(const BatchDev &b, const BatchGrids &g, int census_n, bool l8, int agg_waves,
-                        hipStream_t s);
+                        hipStream_t s, const hipEvent_t *ev = nullptr);
 
 // ---------------------------------------------------------------------------
 // road model (fit, windows, disparity transformation)

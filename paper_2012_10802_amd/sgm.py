@@ -105,6 +105,7 @@ def _load_library():
         "sgm_batch_run": [P, P, S, P],
         "sgm_batch_capture": [P, P, S, P],
         "sgm_batch_launch": [P, P],
+        "sgm_batch_run_timed": [P, P, S, P, ctypes.POINTER(ctypes.c_float)],
         "sgm_batch_autotune": [P, P, S, P, ctypes.c_char_p, ctypes.POINTER(sgm_tuning)],
         "sgm_road_workspace_size": [I, I, I, ctypes.POINTER(S)],
         "sgm_road_fit_batch": [P, P, I, I, I, ctypes.c_float, D, P, D, P, P, S, P],
@@ -836,6 +837,14 @@ class Batch:
     def run(self, stream=None):
         _check(_lib.sgm_batch_run(self.handle, _ptr(self.workspace), self.ws_bytes, _stream(stream)),
                "sgm_batch_run")
+
+    def run_timed(self, stream=None):
+        """One run with its stages timed by HIP events on `stream`; waits for
+        it and returns the census, cost, aggregation and selection times (ms)."""
+        ms = (ctypes.c_float * 4)()
+        _check(_lib.sgm_batch_run_timed(self.handle, _ptr(self.workspace), self.ws_bytes, _stream(stream), ms),
+               "sgm_batch_run_timed")
+        return [float(x) for x in ms]
 
     def capture(self, stream):
         """Record one run into a graph on `stream` (a non-default torch stream)."""
