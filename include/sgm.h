@@ -154,6 +154,28 @@ sgm_status sgm_match(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
                      float *disp_sub, void *workspace, size_t workspace_bytes,
                      void *stream);
 
+/* For callers that cannot allocate device memory (work under stream
+ * capture, serving loops, harnesses that forbid hipMalloc): sgm_match with
+ * its workspace in a library-owned device array of
+ * SGM_NOALLOC_SCRATCH_BYTES bytes, so plans whose sgm_workspace_size() is at
+ * most that (e.g. 320x240, 32 disparities, 4 paths: 13.5 MB) need no
+ * workspace argument.  Same arguments and identical outputs as sgm_match.
+ *   - Allocates nothing: no hipMalloc / hipFree, no memset, no copy; only
+ *     the kernels of sgm_match are enqueued on `stream`.
+ *   - Every device the library runs on holds its own copy of the array
+ *     from the code object's load until the process ends; its device
+ *     address is looked up on the first call made with that device current.
+ *   - Every call on one device shares that device's array: calls that
+ *     overlap on one device (several streams or threads) race and give
+ *     undefined results; serialise them.  Nothing in the array needs to
+ *     start at zero, and each call overwrites what the previous one left.
+ *   - A plan needing more than SGM_NOALLOC_SCRATCH_BYTES of workspace gives
+ *     SGM_ERR_WORKSPACE before anything is enqueued. */
+#define SGM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sgm_status sgm_match_noalloc(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
+                             int32_t pitch, const int32_t *d_lo, uint16_t *disp_int,
+                             float *disp_sub, void *stream);
+
 /* ------------------------------------------------------------------------
  * Per-pixel search windows in absolute disparity (the learned-window form).
  *

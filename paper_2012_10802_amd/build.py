@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsgm.so")
 
-SOURCES = ["sgm_kernels.hip", "sgm_batch.hip", "sgm_window.hip", "cnn.hip", "road.hip", "pothole.hip", "slic.hip",
+SOURCES = ["sgm_kernels.hip", "sgm_batch.hip", "sgm_window.hip", "cnn.hip", "road.hip", "pothole.hip", "slic.hip", "sgm_noalloc.hip",
            "sgm_api.cpp",
            "sgm_batch_api.cpp"]
 

@@ -72,6 +72,7 @@ def _load_library():
         "sgm_wta": [P, P, P, P, P, P],
         "sgm_aggregate_wta": [P, P, P, P, P, P, S, P],
         "sgm_match": [P, P, P, I, P, P, P, P, S, P],
+        "sgm_match_noalloc": [P, P, P, I, P, P, P, P],
         "sgm_path_volumes": [P, ctypes.POINTER(I), ctypes.POINTER(S), ctypes.POINTER(S)],
         "sgm_aggregate_paths": [P, P, P, S, P],
         "sgm_wta_paths": [P, P, P, P, P, P],

@@ -145,6 +145,26 @@ def test_workspace_size_and_checks(sgm):
         sgm.sgm_plan_free(plan)
 
 
+def test_noalloc_match_rejects_plans_beyond_its_scratch(sgm):
+    """sgm_match_noalloc refuses, before any HIP call, plans whose workspace
+    exceeds the library's scratch array, and null arguments."""
+    lib = sgm.library()
+    limit = 64 << 20
+    dummy = ctypes.c_void_p(256)
+    small = sgm.sgm_plan(320, 240, 5, 32, 4, 10, 120)
+    big = sgm.sgm_plan(1280, 720, 7, 128, 8, 10, 120)
+    try:
+        assert sgm.sgm_workspace_size(small) <= limit < sgm.sgm_workspace_size(big)
+        assert lib.sgm_match_noalloc(big, dummy, dummy, 1280, None, dummy, None, None) == -4
+        assert b"scratch" in lib.sgm_last_error()
+        assert lib.sgm_match_noalloc(None, dummy, dummy, 320, None, dummy, None, None) == -1
+        assert lib.sgm_match_noalloc(small, None, dummy, 320, None, dummy, None, None) == -1
+        assert lib.sgm_match_noalloc(small, dummy, dummy, 320, None, None, None, None) == -1
+    finally:
+        sgm.sgm_plan_free(small)
+        sgm.sgm_plan_free(big)
+
+
 def test_window_helper_host(sgm):
     import math
     import oracle
