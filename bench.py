@@ -208,6 +208,7 @@ def run_batch(args):
         # the same kernels enqueued eagerly, stages bracketed by HIP events
         stage = np.array([b.run_timed(stream) for _ in range(args.steps)])
     ms = (t1 - t0) * 1e3 / args.steps
+    copy_calibration(args, dev)
     census_ms, cost_ms, agg_ms, wta_ms = (float(x) for x in stage.mean(axis=0))
     log("batch stages (ms, mean of %d): census %.3f cost %.3f aggregate %.3f select %.3f"
         % (args.steps, census_ms, cost_ms, agg_ms, wta_ms))
