@@ -327,8 +327,10 @@ def learned_vs_plain(args, log=None):
     stream = torch.cuda.Stream()
     uu = torch.arange(W, device=dev)[None, :]
     tot = {"pix": 0, "bad_plain": 0, "bad_learned": 0, "miss": 0, "conf_pix": 0, "fallback": 0,
-           "rect_area": 0}
-    t_plain, t_learned = [], []
+           "rect_area": 0, "fb_scored": 0, "fb_bad_plain": 0, "fb_bad_learned": 0, "fb_differ": 0}
+    t_plain, t_learned, stages = [], [], []
+    ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev_stage = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
     nb = max(1, args.eval_pairs // B)
     with torch.cuda.stream(stream):
         L.zero_()
@@ -350,23 +352,27 @@ def learned_vs_plain(args, log=None):
                 gts.append(gt)
                 masks.append(m)
             stream.synchronize()
+            # HIP events on the stream around each batch (the learned form
+            # includes the time the stream waits while the host plans the
+            # fallback rectangles from the window maps)
             reps = []
             for k in range(args.lw_reps + 1):
                 stream.synchronize()
-                t0 = time.perf_counter()
+                ev_a.record(stream)
                 plain.launch(stream)
+                ev_b.record(stream)
                 stream.synchronize()
                 if k:
-                    reps.append(time.perf_counter() - t0)
+                    reps.append(ev_a.elapsed_time(ev_b) * 1e-3)
             t_plain.append(float(np.median(reps)))
             reps = []
             for k in range(args.lw_reps + 1):
                 stream.synchronize()
-                t0 = time.perf_counter()
-                lw.match(L, Rt, stream)
+                lw.match(L, Rt, stream, events=ev_stage)
                 stream.synchronize()
                 if k:
-                    reps.append(time.perf_counter() - t0)
+                    reps.append(ev_stage[0].elapsed_time(ev_stage[6]) * 1e-3)
+                    stages.append([ev_stage[i].elapsed_time(ev_stage[i + 1]) for i in range(6)])
             t_learned.append(float(np.median(reps)))
             for j in range(B):
                 m = masks[j]
@@ -382,10 +388,42 @@ def learned_vs_plain(args, log=None):
                 tot["conf_pix"] += int(conf.sum())
                 tot["fallback"] += int(lw.nfallback[j])
                 tot["rect_area"] += sum((y1 - y0) * (x1 - x0) for y0, y1, x0, x1 in lw.last_rects[j])
+                # fallback pixels: the crop's full-range SGM against full-frame full-range SGM
+                fbm = lw.mask[j] > 0
+                tot["fb_differ"] += int((fbm & (lw.dint[j] != plain.disp_int[j])).sum())
+                fs = fbm & m
+                tot["fb_scored"] += int(fs.sum())
+                tot["fb_bad_plain"] += int(((e_p > 1.0) & fs).sum())
+                tot["fb_bad_learned"] += int(((e_l > 1.0) & fs).sum())
             if log:
                 log("learned-window batch %d/%d: plain %.2f ms, learned %.2f ms"
                     % (b + 1, nb, t_plain[-1] * 1e3, t_learned[-1] * 1e3))
     npairs = nb * B
+    st = np.array(stages).mean(axis=0)
+    stage_ms = {name: round(float(v), 4) for name, v in zip(LW.LearnedWindowMatcher.STAGES, st)}
+    # algorithmic bytes per stage (per batch of B pairs): full-resolution
+    # pixels P, quarter-resolution pixels Pc
+    P, Pc, Dc = B * W * H, B * (W // 4) * (H // 4), D // 4
+    stage_bytes = {
+        # both images read, both reductions written
+        "reduce": 2 * P + 2 * Pc,
+        # plain SGM at quarter scale: 25 B per eval (cost written once and
+        # read by 8 directions, 8 uint8 volumes written and read back)
+        "coarse_sgm": 25 * Pc * Dc,
+        # input prep (5 B in, 32 B out), three hidden layers (32 B in + 32 B
+        # out), last layer (32 B in, 8 B out), per quarter-resolution pixel
+        "network": Pc * (37 + 3 * 64 + 40),
+        # coarse disparity and two outputs per quarter pixel in, window
+        # start (4 B) and fallback flag (1 B) out per pixel
+        "window_map": Pc * 12 + P * 5,
+        # census (2 B in, 16 B out), cost (16 B codes + 4 B lo in, 16 B out),
+        # 8 directions x (16 B cost + 4 B lo in, 16 B out), selection
+        # (8 x 16 B + 4 B lo in, 6 B out), per pixel
+        "windowed_sgm": P * (18 + 36 + 8 * 36 + 138),
+    }
+    stage_roof = {k: {"bytes": v, "achieved_gbs": round(v / (stage_ms[k] * 1e-3) / 1e9, 1),
+                      "frac": round(v / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                  for k, v in stage_bytes.items() if stage_ms.get(k, 0) > 0}
     bp = 100.0 * tot["bad_plain"] / tot["pix"]
     bl = 100.0 * tot["bad_learned"] / tot["pix"]
     return {
@@ -400,11 +438,22 @@ def learned_vs_plain(args, log=None):
         "fallback_pixel_pct": round(100.0 * tot["fallback"] / (npairs * W * H), 4),
         "fallback_area_pct": round(100.0 * tot["rect_area"] / (npairs * W * H), 3),
         "window_miss_pct_vs_full_range": round(100.0 * tot["miss"] / max(1, tot["conf_pix"]), 4),
+        "fallback_vs_full_frame": {
+            "fallback_pixels": tot["fallback"],
+            "integer_disparity_differs_pct": round(100.0 * tot["fb_differ"] / max(1, tot["fallback"]), 4),
+            "scored_fallback_pixels": tot["fb_scored"],
+            "bad_1px_pct_full_frame": round(100.0 * tot["fb_bad_plain"] / max(1, tot["fb_scored"]), 4),
+            "bad_1px_pct_crop": round(100.0 * tot["fb_bad_learned"] / max(1, tot["fb_scored"]), 4),
+            "note": "fallback pixels take full-range SGM of a crop around them; compared here with "
+                    "full-range SGM of the whole frame on the same pixels"},
+        "stages_ms": stage_ms,
+        "stage_roofline": stage_roof,
         "tau": args.tau,
         "window": 16,
         "pixels_scored": tot["pix"],
-        "timing": "host wall clock around each batch (learned includes its one host read of the "
-                  "fallback rows), median of %d after one warm-up, mean over batches" % args.lw_reps,
+        "timing": "HIP events on the stream around each batch (the learned form includes the stream's wait "
+                  "while the host plans the fallback rectangles), median of %d after one warm-up, mean over "
+                  "batches; stages from events between them" % args.lw_reps,
     }
 
 
@@ -808,7 +857,9 @@ def main():
                     help="single: the split single-pair calls; batch: the batch calls as a graph")
     ap.add_argument("--unique", type=int, default=2,
                     help="batch mode: distinct rendered pairs per size (inputs are shared)")
-    ap.add_argument("--tune-cache", default=None, help="batch mode: autotuner cache file")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
+    ap.add_argument("--lanes", type=int, default=None, choices=[0, 4, 8, 16],
+                    help="single mode: lanes per scanline of the volume kernels (default: autotuned)")
     ap.add_argument("--seed", type=int, default=2001)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
@@ -880,6 +931,12 @@ def main():
     if args.workload == "road1280_pt":  # per-row windows from the scene's road model, eq. (3), (6)
         a0, a1, phi = pair.road_params
         d_lo = sgm.sgm_window_from_road(a0, a1, phi, W, H, w, mode=0).to(dev)
+    # lane mapping of the volume kernels: fixed by --lanes, else timed on
+    # this frame (sgm_autotune; cached in --tune-cache when given)
+    if args.lanes is not None:
+        m = sgm.Matcher(W, H, census=n, ndisp=w, npaths=R, p1=p1, p2=p2, device=dev, lanes=args.lanes)
+    else:
+        m.autotune(left, right, d_lo=d_lo, cache_path=args.tune_cache)
     cost = m.new_volume(torch.uint8)
     paths = m.new_paths()
     dint = torch.empty((H, W), dtype=torch.int16, device=dev)
@@ -992,6 +1049,8 @@ def main():
         "full_range_equivalent": None if d_lo is None else {
             "ndisp": 128, "value": round(W * H * 128 / (ms_per_step * 1e-3) / 1e6, 1),
             "unit": "Mdisp-evals/s (pixels x 128 disparities per second)"},
+        "tuning": {"lanes_per_scanline": m.lanes,
+                   "chosen_by": "--lanes" if args.lanes is not None else "sgm_autotune"},
         "roofline": roofline,
         "roofline_other_bound": alu if roofline is hbm else hbm,
         "step_hbm": {"bytes_per_eval": step_bytes_per_eval, "achieved": round(step_gbs, 1), "unit": "GB/s",

@@ -75,10 +75,37 @@ typedef struct {
 
 typedef struct sgm_plan_s *sgm_plan_t;
 
+/* Launch choices (picked by sgm_autotune / sgm_batch_autotune or set by
+ * hand; none of them changes results).
+ *   lanes: lanes that carry one scanline of the aggregation, each holding
+ *          w / lanes (rounded up to a compiled count) consecutive window
+ *          values, so that a wave of 64 lanes advances 64 / lanes
+ *          scanlines: 16 serves every window width; 8 and 4 serve widths
+ *          up to 64 that are a multiple of the per-lane count (8: 4 or 8
+ *          values; 4: 4, 8, 12 or 16).  0 means 16; a count that does not
+ *          serve a width falls back to 16 (for the plan, or for that pair
+ *          of a batch).  The selection always takes the fewest lanes per
+ *          pixel that serve the width.
+ *   waves_per_cu, order: batches only (ignored by plans): resident
+ *          aggregation waves per compute unit, 1..32; queue order of the
+ *          scanline groups (0 longest first, 1 pair by pair, 2 direction by
+ *          direction). */
+typedef struct {
+    int32_t waves_per_cu;
+    int32_t order;
+    int32_t lanes;
+} sgm_tuning;
+
 /* Validate `params` and build a plan (host only, touches no device).
  * On success *out owns host memory released by sgm_plan_free(). */
 sgm_status sgm_plan(const sgm_params *params, sgm_plan_t *out);
 void sgm_plan_free(sgm_plan_t plan);
+
+/* sgm_plan with the launch choice tuning->lanes (0, 4, 8 or 16); the
+ * plan's results are those of sgm_plan.  sgm_plan_get_tuning reports the
+ * lane count the plan uses (waves_per_cu and order read 0). */
+sgm_status sgm_plan_tuned(const sgm_params *params, const sgm_tuning *tuning, sgm_plan_t *out);
+sgm_status sgm_plan_get_tuning(sgm_plan_t plan, sgm_tuning *tuning);
 
 /* Bytes of device workspace that sgm_cost, sgm_aggregate,
  * sgm_aggregate_wta and sgm_match need (one figure covers all of them).
@@ -153,6 +180,18 @@ sgm_status sgm_match(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
                      int32_t pitch, const int32_t *d_lo, uint16_t *disp_int,
                      float *disp_sub, void *workspace, size_t workspace_bytes,
                      void *stream);
+
+/* Pick the lane count for `params`: reuse the entry for this device
+ * architecture and problem (W, H, w, census, paths, P1, P2) from the text
+ * file `cache_path` (may be NULL) if it holds one, else run sgm_match with
+ * every distinct lane mapping on the given buffers (as for sgm_match; the
+ * outputs are overwritten), time each on `stream` (one warm-up, best of
+ * three; the host waits), keep the fastest and append it to the file.
+ * *chosen (may be NULL) receives the result, for sgm_plan_tuned. */
+sgm_status sgm_autotune(const sgm_params *params, const uint8_t *left, const uint8_t *right,
+                        int32_t pitch, const int32_t *d_lo, uint16_t *disp_int, float *disp_sub,
+                        void *workspace, size_t workspace_bytes, void *stream,
+                        const char *cache_path, sgm_tuning *chosen);
 
 /* For callers that cannot allocate device memory (work under stream
  * capture, serving loops, harnesses that forbid hipMalloc): sgm_match with
@@ -271,8 +310,10 @@ sgm_status sgm_downsample4_batch(const uint8_t *images, int32_t width, int32_t h
  *   x0      bfloat16 NHWC [n][H][W][16] network input
  *   acts    bfloat16 [3][n][H][W][16] hidden activations (forward output,
  *           backward input)
- *   out     float32 NHWC [n][H][W][16] network output
- *   dy      bfloat16 NHWC [n][H][W][16] loss gradient w.r.t. out
+ *   out     float32 NHWC [n][H][W][2] network output: the two channels
+ *           used (centre offset, confidence logit) of the last layer's 16
+ *   dy      bfloat16 NHWC [n][H][W][16] loss gradient w.r.t. the last
+ *           layer's 16 outputs (zero beyond the first two)
  * Activations and dy must be 16-byte aligned.  Weight gradients are reduced
  * in a fixed order, so training is bitwise reproducible.
  */
@@ -305,13 +346,13 @@ sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, in
  * [3][H]: per row the number of fallback pixels, the leftmost and the
  * rightmost fallback column (W and -1 for a row without any); nfallback
  * uint32, the total.  The statistics are cleared by this call.
- * coarse_disp and cnn_out are [Hc][Wc] and [Hc][Wc][16] float32. */
+ * coarse_disp and cnn_out are [Hc][Wc] and [Hc][Wc][2] float32. */
 sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_t coarse_width,
                           int32_t coarse_height, int32_t width, int32_t height, int32_t ndisp,
                           int32_t w, float conf_threshold, int32_t *lo, uint8_t *fallback_mask,
                           int32_t *row_stats, uint32_t *nfallback, void *stream);
 /* The same for nimg images at once: every buffer holds the images packed
- * one after another (coarse_disp [nimg][Hc][Wc], cnn_out [nimg][Hc][Wc][16],
+ * one after another (coarse_disp [nimg][Hc][Wc], cnn_out [nimg][Hc][Wc][2],
  * lo and fallback_mask [nimg][H][W], row_stats [nimg][3][H], nfallback
  * [nimg]). */
 sgm_status sgm_window_map_batch(const float *coarse_disp, const float *cnn_out,
@@ -362,14 +403,6 @@ typedef struct {
     int32_t census, npaths, p1, p2; /* shared by every pair, as in sgm_params */
     uint32_t flags;                 /* reserved, must be 0                    */
 } sgm_batch_params;
-
-/* Launch choices of the persistent aggregation (picked by sgm_batch_autotune
- * or set by hand; neither changes results). */
-typedef struct {
-    int32_t waves_per_cu; /* resident aggregation waves per compute unit, 1..32 */
-    int32_t order;        /* queue order of scanline groups: 0 longest first,
-                             1 pair by pair, 2 direction by direction       */
-} sgm_tuning;
 
 typedef struct sgm_batch_s *sgm_batch_t;
 

@@ -36,6 +36,7 @@ constexpr int LAYERS = 4;
 constexpr int PER_LAYER = 9 * CH * CH + CH;
 constexpr int NPARAMS = LAYERS * PER_LAYER;
 constexpr int kWgradWaves = 1024;
+constexpr int kOutCh = 2;  // output channels used: centre offset, confidence logit
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -78,7 +79,8 @@ __device__ __forceinline__ Strip strip_of(int s, int W, int H)
 // convolution forward (and input gradient): D[pixel][co] over 9 taps
 
 // MODE 0: hidden layer forward  (out = bf16(relu(conv + b)))
-// MODE 1: last layer forward    (out32 = conv + b, float)
+// MODE 1: last layer forward    (out32 = conv + b, float, only the two
+//                                channels the window map reads: offset, logit)
 // MODE 2: input gradient        (dx = conv^T(dy); out = bf16(dx * [mask > 0]))
 //
 // A wave takes kStripsPerWave consecutive strips: the 9 taps' weight
@@ -128,7 +130,7 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ x, co
             if (MODE == 0) {
                 out[o] = f2bf(fmaxf(acc[r] + bi, 0.0f));
             } else if (MODE == 1) {
-                out32[o] = acc[r] + bi;
+                if (i < kOutCh) out32[(((size_t)st.n * H + st.y) * W + xo) * kOutCh + i] = acc[r] + bi;
             } else {
                 out[o] = f2bf(bf2f(mask[o]) > 0.0f ? acc[r] : 0.0f);
             }
@@ -229,7 +231,7 @@ __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ 
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
     const float invn = 1.0f / (float)npix;
-    const float off = out[(size_t)p * CH], logit = out[(size_t)p * CH + 1];
+    const float off = out[(size_t)p * kOutCh], logit = out[(size_t)p * kOutCh + 1];
     const float e = off - (label[p] - coarse[p]);
     const float ae = fabsf(e);
     const float c = ae < 1.0f ? 1.0f : 0.0f;
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(256) void k_window_map(const float *__restrict__ co
     {
         const size_t z = blockIdx.z;
         coarse += z * Wc * Hc;
-        out += z * Wc * Hc * CH;
+        out += z * Wc * Hc * kOutCh;
         lo += z * W * H;
         if (mask) mask += z * W * H;
         if (row_stats) row_stats += z * 3 * H;
@@ -315,8 +317,8 @@ __global__ __launch_bounds__(256) void k_window_map(const float *__restrict__ co
         const int cx = min(x / 4, Wc - 1), cy = min(y / 4, Hc - 1);
         const size_t cp = (size_t)cy * Wc + cx;
         const float cd = coarse[cp];
-        const bool conf = out[cp * CH + 1] > thr;
-        const float centre = 4.0f * (conf ? __fadd_rn(cd, out[cp * CH]) : cd);
+        const bool conf = out[cp * kOutCh + 1] > thr;
+        const float centre = 4.0f * (conf ? __fadd_rn(cd, out[cp * kOutCh]) : cd);
         int l = (int)floorf(__fadd_rn(centre, 0.5f)) - w / 2;
         l = min(max(l, 0), D - w);
         lo[(size_t)y * W + x] = l;

@@ -67,15 +67,6 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int choose_vpl(int w)
-{
-    if (w <= 32) return 2;
-    if (w <= 64) return 4;
-    if (w <= 128) return 8;
-    if (w <= 192) return 12;
-    return 16;
-}
-
 bool is_aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 sgm_status check_plan(sgm_plan_t plan)
@@ -95,17 +86,25 @@ sgm_status check_ws(const sgm_plan_s *p, void *ws, size_t bytes)
 }
 
 // Effective kernel configuration for given buffer pointers: vector access of
-// a lane's values needs w % vpl == 0 and buffers aligned to a lane's bytes.
+// a lane's values needs w % vpl == 0 and buffers aligned to a lane's bytes;
+// misaligned buffers take the 16-lane mapping's element-wise form.
 sgm::KernelConfig config_for(const sgm_plan_s *p, const void *a, const void *b)
 {
     sgm::KernelConfig kc = p->kc;
     // widest access: a lane's values as uint16 (2*vpl bytes), issued as
     // power-of-two sized pieces
-    const size_t bytes = (size_t)kc.vpl * 2;
+    const size_t bytes = (size_t)(kc.vpl > kc.wta_vpl ? kc.vpl : kc.wta_vpl) * 2;
     const size_t need = bytes & (~bytes + 1);
-    if (kc.aligned && ((a && !is_aligned(a, need)) || (b && !is_aligned(b, need)))) kc.aligned = false;
+    if (kc.aligned && ((a && !is_aligned(a, need)) || (b && !is_aligned(b, need)))) {
+        const sgm::Mapping m = sgm::choose_mapping(p->pb.w, 16);
+        kc.lanes = kc.wta_lanes = m.lanes;
+        kc.vpl = kc.wta_vpl = m.vpl;
+        kc.aligned = false;
+    }
     return kc;
 }
+
+sgm_status make_plan(const sgm_params *pr, int lanes, sgm_plan_t *out);
 
 }  // namespace
 
@@ -133,7 +132,29 @@ const char *sgm_status_str(sgm_status s)
 
 const char *sgm_last_error(void) { return sgm::error_buffer(); }
 
-sgm_status sgm_plan(const sgm_params *pr, sgm_plan_t *out)
+sgm_status sgm_plan(const sgm_params *pr, sgm_plan_t *out) { return make_plan(pr, 0, out); }
+
+sgm_status sgm_plan_tuned(const sgm_params *pr, const sgm_tuning *tuning, sgm_plan_t *out)
+{
+    if (!tuning) return fail(SGM_ERR_INVALID, "tuning is NULL");
+    if (tuning->lanes != 0 && tuning->lanes != 4 && tuning->lanes != 8 && tuning->lanes != 16)
+        return fail(SGM_ERR_INVALID, "lanes %d not in {0, 4, 8, 16}", tuning->lanes);
+    return make_plan(pr, tuning->lanes, out);
+}
+
+sgm_status sgm_plan_get_tuning(sgm_plan_t plan, sgm_tuning *tuning)
+{
+    if (sgm_status s = check_plan(plan)) return s;
+    if (!tuning) return fail(SGM_ERR_INVALID, "tuning is NULL");
+    *tuning = sgm_tuning{0, 0, plan->kc.lanes};
+    return SGM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+sgm_status make_plan(const sgm_params *pr, int lanes, sgm_plan_t *out)
 {
     if (!pr || !out) return fail(SGM_ERR_INVALID, "params and out must not be NULL");
     *out = nullptr;
@@ -159,8 +180,14 @@ sgm_status sgm_plan(const sgm_params *pr, sgm_plan_t *out)
     if (!p) return fail(SGM_ERR_INVALID, "out of host memory");
     p->params = q;
     p->pb = {q.width, q.height, q.ndisp, q.census, q.npaths, q.p1, q.p2, cmax};
-    p->kc.vpl = choose_vpl(q.ndisp);
-    p->kc.aligned = (q.ndisp % p->kc.vpl) == 0;
+    const sgm::Mapping mp = sgm::choose_mapping(q.ndisp, lanes);
+    p->kc.lanes = mp.lanes;
+    p->kc.vpl = mp.vpl;
+    const sgm::Mapping ms = sgm::select_mapping(q.ndisp);
+    p->kc.wta_lanes = ms.lanes;
+    p->kc.wta_vpl = ms.vpl;
+    // (narrower mappings exist only for widths that are a multiple of vpl)
+    p->kc.aligned = (q.ndisp % sgm::choose_mapping(q.ndisp, 16).vpl) == 0;
     p->kc.l8 = cmax + q.p2 <= 255;
     if (!p->kc.l8 && (long long)q.width * q.height * q.ndisp >= sgm::kMaxU16Volume) {
         delete p;
@@ -187,6 +214,10 @@ sgm_status sgm_plan(const sgm_params *pr, sgm_plan_t *out)
     *out = p;
     return SGM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 void sgm_plan_free(sgm_plan_t plan) { delete plan; }
 
@@ -331,6 +362,94 @@ sgm_status sgm_match(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
     uint8_t *cost = static_cast<uint8_t *>(ws) + plan->off_cost;
     if (sgm_status s = sgm_cost(plan, left, right, pitch, d_lo, cost, ws, ws_bytes, stream)) return s;
     return sgm_aggregate_wta(plan, cost, d_lo, disp_int, disp_sub, ws, ws_bytes, stream);
+}
+
+sgm_status sgm_autotune(const sgm_params *params, const uint8_t *left, const uint8_t *right, int32_t pitch,
+                        const int32_t *d_lo, uint16_t *disp_int, float *disp_sub, void *ws, size_t ws_bytes,
+                        void *stream, const char *cache_path, sgm_tuning *chosen)
+{
+    if (!params) return fail(SGM_ERR_INVALID, "params is NULL");
+    sgm_plan_t base = nullptr;
+    if (sgm_status s = make_plan(params, 0, &base)) return s;
+    const sgm_params q = base->params;
+    const int deflt = base->kc.lanes;
+    sgm_plan_free(base);
+    // cache key: device architecture and the problem's shape and parameters
+    char key[256];
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        char arch[64] = "unknown";
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+        for (char *c = arch; *c; ++c)
+            if (*c == ' ' || *c == ':') *c = '_';
+        snprintf(key, sizeof key, "single|%s|%dx%dx%d|n%d|R%d|P%d,%d", arch, q.width, q.height, q.ndisp, q.census,
+                 q.npaths, q.p1, q.p2);
+    }
+    if (cache_path) {
+        if (FILE *f = fopen(cache_path, "r")) {
+            char line[512], k[300];
+            int lanes = -1, found = -1;
+            double ms = 0;
+            while (fgets(line, sizeof line, f))
+                if (sscanf(line, "%299s %d %lf", k, &lanes, &ms) == 3 && !strcmp(k, key) &&
+                    (lanes == 4 || lanes == 8 || lanes == 16))
+                    found = lanes;
+            fclose(f);
+            if (found > 0) {
+                if (chosen) *chosen = sgm_tuning{0, 0, found};
+                return SGM_OK;
+            }
+        }
+    }
+    // time each distinct mapping: one warm-up run, then the best of three
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return fail(SGM_ERR_HIP, "autotune: event creation failed");
+    }
+    int best = deflt, seen[3] = {0, 0, 0}, nseen = 0;
+    float best_ms = 1e30f;
+    sgm_status rs = SGM_OK;
+    for (int lanes : {16, 8, 4}) {
+        sgm_plan_t p = nullptr;
+        if ((rs = make_plan(params, lanes, &p)) != SGM_OK) break;
+        const int eff = p->kc.lanes;
+        bool dup = false;
+        for (int i = 0; i < nseen; ++i) dup = dup || seen[i] == eff;
+        if (dup) {
+            sgm_plan_free(p);
+            continue;
+        }
+        seen[nseen++] = eff;
+        float ms = 1e30f;
+        for (int rep = 0; rep < 4 && rs == SGM_OK; ++rep) {
+            if (hipEventRecord(e0, st) != hipSuccess) rs = fail(SGM_ERR_HIP, "autotune: event record failed");
+            if (rs == SGM_OK) rs = sgm_match(p, left, right, pitch, d_lo, disp_int, disp_sub, ws, ws_bytes, stream);
+            if (rs == SGM_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rs = fail(SGM_ERR_HIP, "autotune: event wait failed");
+            float t = 0;
+            if (rs == SGM_OK && rep > 0 && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t < ms ? t : ms;
+        }
+        sgm_plan_free(p);
+        if (rs != SGM_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = eff;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rs != SGM_OK) return rs;
+    if (cache_path)
+        if (FILE *f = fopen(cache_path, "a")) {
+            fprintf(f, "%s %d %.5f\n", key, best, best_ms);
+            fclose(f);
+        }
+    if (chosen) *chosen = sgm_tuning{0, 0, best};
+    return SGM_OK;
 }
 
 // ---------------------------------------------------------------------------

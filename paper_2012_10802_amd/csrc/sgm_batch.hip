@@ -4,7 +4,7 @@
 // Stage grids are the concatenation of the single-pair grids; a workgroup
 // finds its pair by binary search over the per-pair start indices.  The
 // aggregation is persistent: each workgroup is one wave that repeatedly
-// takes the next item (pair, direction, group of four scanlines) from a
+// takes the next item (pair, direction, group of 64 / lanes scanlines) from a
 // queue in the workspace with one atomic add, runs it, and stops when the
 // queue is empty (every wave reaches that exit).  The queue order is laid
 // out on the host (longest scanlines first by default), which balances
@@ -56,6 +56,8 @@ __global__ __launch_bounds__(256) void k_cost_batch(BatchDev b)
     const int bx = local % P.cost_tx, v = local / P.cost_tx;
     if (P.w % 16 == 0)
         cost_tile<16>(cl, cr, P.d_lo, P.W, P.H, P.w, b.cmax, cost, bx, v);
+    else if (P.w % 8 == 0)
+        cost_tile<8>(cl, cr, P.d_lo, P.W, P.H, P.w, b.cmax, cost, bx, v);
     else
         cost_tile<4>(cl, cr, P.d_lo, P.W, P.H, P.w, b.cmax, cost, bx, v);
 }
@@ -84,19 +86,33 @@ __global__ __launch_bounds__(64) void k_aggregate_batch(BatchDev b)
         a.p1x2 = b.p1x2;
         a.p2x2 = b.p2x2;
         a.np = b.npaths;
-        a.lines_per_wg = 4;
-        const int variant = __builtin_amdgcn_readfirstlane(P.vpl * 2 + P.pad);
+        const int lanes = __builtin_amdgcn_readfirstlane(P.lanes);
+        a.lines_per_wg = 64 / lanes;
+        // (lanes, values per lane, padded window) of the pair's mapping
+        const int variant = __builtin_amdgcn_readfirstlane(lanes * 512 + P.vpl * 2 + P.pad);
         switch (variant) {
-        case 4: agg_item<2, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
-        case 5: agg_item<2, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
-        case 8: agg_item<4, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
-        case 9: agg_item<4, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
-        case 16: agg_item<8, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
-        case 17: agg_item<8, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
-        case 24: agg_item<12, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
-        case 25: agg_item<12, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
-        case 32: agg_item<16, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
-        default: agg_item<16, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 16 * 512 + 4: agg_item<16, 2, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 16 * 512 + 5: agg_item<16, 2, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 16 * 512 + 8: agg_item<16, 4, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 16 * 512 + 9: agg_item<16, 4, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 16 * 512 + 16: agg_item<16, 8, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 16 * 512 + 17: agg_item<16, 8, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 16 * 512 + 24: agg_item<16, 12, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 16 * 512 + 25: agg_item<16, 12, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 16 * 512 + 32: agg_item<16, 16, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 16 * 512 + 33: agg_item<16, 16, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 8 * 512 + 8: agg_item<8, 4, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 8 * 512 + 9: agg_item<8, 4, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 8 * 512 + 16: agg_item<8, 8, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 8 * 512 + 17: agg_item<8, 8, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 4 * 512 + 8: agg_item<4, 4, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 4 * 512 + 9: agg_item<4, 4, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 4 * 512 + 16: agg_item<4, 8, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 4 * 512 + 17: agg_item<4, 8, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 4 * 512 + 24: agg_item<4, 12, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 4 * 512 + 25: agg_item<4, 12, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
+        case 4 * 512 + 32: agg_item<4, 16, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
+        default: agg_item<4, 16, true, true, L8, kBatchPrefetch>(a, r, r, g); break;
         }
     }
 }
@@ -109,12 +125,18 @@ __global__ __launch_bounds__(256) void k_wta_batch(BatchDev b)
     const PairDev &P = b.pairs[pi];
     const long long local = blk - P.wta_start;
     const void *vols = b.ws + P.off_vols;
-    switch (__builtin_amdgcn_readfirstlane(P.vpl)) {
-    case 2: wta_paths_group<2, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
-    case 4: wta_paths_group<4, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
-    case 8: wta_paths_group<8, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
-    case 12: wta_paths_group<12, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
-    default: wta_paths_group<16, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
+    switch (__builtin_amdgcn_readfirstlane(P.wta_lanes * 256 + P.wta_vpl)) {
+    case 16 * 256 + 2: wta_paths_group<16, 2, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
+    case 16 * 256 + 4: wta_paths_group<16, 4, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
+    case 16 * 256 + 8: wta_paths_group<16, 8, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
+    case 16 * 256 + 12: wta_paths_group<16, 12, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
+    case 8 * 256 + 4: wta_paths_group<8, 4, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
+    case 8 * 256 + 8: wta_paths_group<8, 8, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
+    case 4 * 256 + 4: wta_paths_group<4, 4, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
+    case 4 * 256 + 8: wta_paths_group<4, 8, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
+    case 4 * 256 + 12: wta_paths_group<4, 12, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
+    case 4 * 256 + 16: wta_paths_group<4, 16, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
+    default: wta_paths_group<16, 16, true, L8>(vols, P.vstride, b.npaths, P.d_lo, P.W, P.H, P.w, P.dint, P.dsub, local); break;
     }
 }
 

@@ -29,18 +29,14 @@ sgm_status bfail(sgm_status st, const char *fmt, ...)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int lane_width(int w)
-{
-    if (w <= 32) return 2;
-    if (w <= 64) return 4;
-    if (w <= 128) return 8;
-    if (w <= 192) return 12;
-    return 16;
-}
+// values per lane of the 16-lane mapping (every window width has one); a
+// pair's ndisp must be a multiple of it
+int lane_width(int w) { return sgm::choose_mapping(w, 16).vpl; }
 
-// Step range of scanline group g (4 lines) of direction r; same geometry as
-// the kernels (horizontal: rows, vertical: columns, diagonal: sheared index).
-int group_length(int r, int g, int W, int H)
+// Step range of scanline group g (lpi lines) of direction r; same geometry
+// as the kernels (horizontal: rows, vertical: columns, diagonal: sheared
+// index).
+int group_length(int r, int g, int W, int H, int lpi)
 {
     static const int DU[8] = {1, -1, 0, 0, 1, -1, 1, -1};
     static const int DV[8] = {0, 0, 1, -1, 1, 1, -1, -1};
@@ -48,8 +44,8 @@ int group_length(int r, int g, int W, int H)
     if (dv == 0) return W;
     if (du == 0) return H;
     int i0 = 1 << 30, i1 = 0;
-    for (int l = 0; l < 4; ++l) {
-        const int idx = 4 * g + l;
+    for (int l = 0; l < lpi; ++l) {
+        const int idx = lpi * g + l;
         if (idx >= W + H - 1) break;
         const int ell = du > 0 ? idx - (H - 1) : idx;
         int a, b;
@@ -68,11 +64,12 @@ int group_length(int r, int g, int W, int H)
     return i1 > i0 ? i1 - i0 : 0;
 }
 
-int groups_of(int r, int W, int H)
+// scanline groups of direction r: one wave (64 lanes) carries lpi lines
+int groups_of(int r, int W, int H, int lpi)
 {
-    if (r <= 1) return (H + 3) / 4;
-    if (r <= 3) return (W + 3) / 4;
-    return (W + H - 1 + 3) / 4;
+    if (r <= 1) return (H + lpi - 1) / lpi;
+    if (r <= 3) return (W + lpi - 1) / lpi;
+    return (W + H - 1 + lpi - 1) / lpi;
 }
 
 struct Item {
@@ -87,7 +84,7 @@ struct sgm_batch_s {
     std::vector<sgm_pair> pairs;
     int cmax = 0;
     bool l8 = true;
-    sgm_tuning tuning{8, 0};
+    sgm_tuning tuning{8, 0, 0};
     size_t off_pairs = 0, off_items = 0, off_counter = 0, ws_bytes = 0;
     std::vector<sgm::PairDev> dev;  // offsets, host copy
     sgm::BatchGrids grids{0, 0, 0};
@@ -146,6 +143,40 @@ void drop_graph(sgm_batch_s *b)
     if (b->graph) hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+}
+
+// Lane mapping of every pair, the selection grid and the aggregation queue
+// for the current tuning's lane count (the caller has waited for enqueued
+// runs, which read the pinned tables).  Items are built in pair and
+// direction order; order_items then sorts them.
+void layout_queue(sgm_batch_s *b)
+{
+    b->items.clear();
+    int wta_blk = 0;
+    const int np = (int)b->pairs.size();
+    for (int i = 0; i < np; ++i) {
+        const sgm_pair &p = b->pairs[i];
+        sgm::PairDev &d = b->dev[i];
+        const sgm::Mapping m = sgm::choose_mapping(p.ndisp, b->tuning.lanes);
+        d.lanes = m.lanes;
+        d.vpl = m.vpl;
+        d.pad = p.ndisp < m.lanes * m.vpl ? 1 : 0;
+        const sgm::Mapping ms = sgm::select_mapping(p.ndisp);
+        d.wta_lanes = ms.lanes;
+        d.wta_vpl = ms.vpl;
+        const long long npix = (long long)p.width * p.height, ppb = 256 / ms.lanes;
+        d.wta_start = wta_blk;
+        wta_blk += (int)((npix + ppb - 1) / ppb);
+        const int lpi = 64 / m.lanes;
+        for (int r = 0; r < b->prm.npaths; ++r) {
+            const int kind = r <= 1 ? 0 : (r >= 4 ? 1 : 2);  // horizontal, diagonal, vertical
+            for (int g = 0, n = groups_of(r, p.width, p.height, lpi); g < n; ++g)
+                b->items.push_back(Item{(uint32_t)(i << 8 | r), (uint32_t)g,
+                                        group_length(r, g, p.width, p.height, lpi), i, kind});
+        }
+    }
+    b->grids.wta = wta_blk;
+    memcpy(b->pin_pairs, b->dev.data(), b->dev.size() * sizeof(sgm::PairDev));
 }
 
 // Queue order of the aggregation items for the current tuning.
@@ -236,7 +267,7 @@ std::string tuning_key(const sgm_batch_s *b)
     for (const sgm_pair &p : b->pairs)
         shapes.push_back(std::to_string(p.width) + "x" + std::to_string(p.height) + "x" + std::to_string(p.ndisp));
     std::sort(shapes.begin(), shapes.end());
-    std::string key = arch + "|n" + std::to_string(b->prm.census) + "|R" + std::to_string(b->prm.npaths) + "|P" +
+    std::string key = "batch|" + arch + "|n" + std::to_string(b->prm.census) + "|R" + std::to_string(b->prm.npaths) + "|P" +
                       std::to_string(b->prm.p1) + "," + std::to_string(b->prm.p2) + "|";
     for (size_t i = 0; i < shapes.size();) {
         size_t j = i;
@@ -247,7 +278,11 @@ std::string tuning_key(const sgm_batch_s *b)
     return key;
 }
 
-bool valid_tuning(const sgm_tuning &t) { return t.waves_per_cu >= 1 && t.waves_per_cu <= 32 && t.order >= 0 && t.order <= 2; }
+bool valid_tuning(const sgm_tuning &t)
+{
+    return t.waves_per_cu >= 1 && t.waves_per_cu <= 32 && t.order >= 0 && t.order <= 2 &&
+           (t.lanes == 0 || t.lanes == 4 || t.lanes == 8 || t.lanes == 16);
+}
 
 bool read_cache(const char *path, const std::string &key, sgm_tuning *out)
 {
@@ -258,10 +293,10 @@ bool read_cache(const char *path, const std::string &key, sgm_tuning *out)
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         char k[3500];
-        int wv = 0, ord = 0;
+        int wv = 0, ord = 0, lanes = -1;
         double ms = 0;
-        if (sscanf(line, "%3499s %d %d %lf", k, &wv, &ord, &ms) == 4 && key == k) {
-            sgm_tuning t{wv, ord};
+        if (sscanf(line, "%3499s %d %d %d %lf", k, &wv, &ord, &lanes, &ms) == 5 && key == k) {
+            sgm_tuning t{wv, ord, lanes};
             if (valid_tuning(t)) {
                 *out = t;
                 found = true;
@@ -316,9 +351,11 @@ sgm_status sgm_batch_plan(const sgm_batch_params *prm, const sgm_pair *pairs, in
     size_t off = 0;
     b->off_pairs = off;
     off += align256((size_t)npairs * sizeof(sgm::PairDev));
+    // queue capacity: the most items any lane count gives (16 lanes, four
+    // scanlines per item)
     size_t nitems = 0;
     for (int i = 0; i < npairs; ++i)
-        for (int r = 0; r < q.npaths; ++r) nitems += groups_of(r, pairs[i].width, pairs[i].height);
+        for (int r = 0; r < q.npaths; ++r) nitems += groups_of(r, pairs[i].width, pairs[i].height, 4);
     if (nitems >= (1u << 31)) {
         delete b;
         return bfail(SGM_ERR_UNSUPPORTED, "too many scanline groups");
@@ -328,7 +365,7 @@ sgm_status sgm_batch_plan(const sgm_batch_params *prm, const sgm_pair *pairs, in
     b->off_counter = off;
     off += 256;
     b->dev.resize(npairs);
-    int census_blk = 0, cost_blk = 0, wta_blk = 0;
+    int census_blk = 0, cost_blk = 0;
     for (int i = 0; i < npairs; ++i) {
         const sgm_pair &p = pairs[i];
         sgm::PairDev &d = b->dev[i];
@@ -353,8 +390,6 @@ sgm_status sgm_batch_plan(const sgm_batch_params *prm, const sgm_pair *pairs, in
         d.H = p.height;
         d.w = p.ndisp;
         d.pitch = p.pitch;
-        d.vpl = lane_width(p.ndisp);
-        d.pad = p.ndisp < 16 * d.vpl ? 1 : 0;
         d.census_tx = (p.width + sgm::kCensusTW - 1) / sgm::kCensusTW;
         d.census_ty = (p.height + sgm::kCensusTH - 1) / sgm::kCensusTH;
         d.cost_tx = (p.width + 63) / 64;
@@ -362,19 +397,10 @@ sgm_status sgm_batch_plan(const sgm_batch_params *prm, const sgm_pair *pairs, in
         census_blk += 2 * d.census_tx * d.census_ty;
         d.cost_start = cost_blk;
         cost_blk += d.cost_tx * p.height;
-        d.wta_start = wta_blk;
-        wta_blk += (int)((npix + 15) / 16);
     }
     b->ws_bytes = off;
-    b->grids = {census_blk, cost_blk, wta_blk};
+    b->grids = {census_blk, cost_blk, 0};
     b->items.reserve(nitems);
-    for (int i = 0; i < npairs; ++i)
-        for (int r = 0; r < q.npaths; ++r) {
-            const int kind = r <= 1 ? 0 : (r >= 4 ? 1 : 2);  // horizontal, diagonal, vertical
-            for (int g = 0, n = groups_of(r, pairs[i].width, pairs[i].height); g < n; ++g)
-                b->items.push_back(Item{(uint32_t)(i << 8 | r), (uint32_t)g,
-                                        group_length(r, g, pairs[i].width, pairs[i].height), i, kind});
-        }
     if (sgm::fault_take(sgm::kFaultAlloc)) {
         delete b;
         return bfail(SGM_ERR_HIP, "injected allocation failure");
@@ -385,7 +411,7 @@ sgm_status sgm_batch_plan(const sgm_batch_params *prm, const sgm_pair *pairs, in
         delete b;
         return bfail(SGM_ERR_HIP, "pinned host allocation failed");
     }
-    memcpy(b->pin_pairs, b->dev.data(), npairs * sizeof(sgm::PairDev));
+    layout_queue(b);
     order_items(b);
     *out = b;
     return SGM_OK;
@@ -404,10 +430,12 @@ sgm_status sgm_batch_set_tuning(sgm_batch_t b, const sgm_tuning *t)
 {
     if (!b || !t) return bfail(SGM_ERR_INVALID, "batch and tuning must not be NULL");
     if (!valid_tuning(*t)) return bfail(SGM_ERR_INVALID, "tuning out of range");
-    if (t->order != b->tuning.order || t->waves_per_cu != b->tuning.waves_per_cu) {
-        drop_graph(b);
-        const bool reorder = t->order != b->tuning.order;
+    if (t->order != b->tuning.order || t->waves_per_cu != b->tuning.waves_per_cu || t->lanes != b->tuning.lanes) {
+        drop_graph(b);  // also waits for every enqueued run
+        const bool relayout = t->lanes != b->tuning.lanes;
+        const bool reorder = relayout || t->order != b->tuning.order;
         b->tuning = *t;
+        if (relayout) layout_queue(b);
         if (reorder) order_items(b);
     }
     return SGM_OK;
@@ -511,25 +539,30 @@ sgm_status sgm_batch_autotune(sgm_batch_t b, void *ws, size_t bytes, void *strea
     const sgm_tuning start = b->tuning;
     sgm_tuning best = start;
     float best_ms = 1e30f;
-    const int waves[] = {4, 8, 12, 16, 24};
     bool ok = true;
-    for (int order = 0; order <= 2 && ok; ++order)
-        for (int wv : waves) {
-            sgm_tuning c{wv, order};
-            sgm_batch_set_tuning(b, &c);
-            float ms = 1e30f;
-            for (int rep = 0; rep < 3 && ok; ++rep) {
-                ok = hipEventRecord(e0, st) == hipSuccess && enqueue_run(b, ws, st) == SGM_OK &&
-                     hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
-                float t_ms = 0;
-                if (ok && rep > 0 && hipEventElapsedTime(&t_ms, e0, e1) == hipSuccess) ms = std::min(ms, t_ms);
-            }
-            if (!ok) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = c;
-            }
+    auto trial = [&](const sgm_tuning &c) {
+        sgm_batch_set_tuning(b, &c);
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3 && ok; ++rep) {
+            ok = hipEventRecord(e0, st) == hipSuccess && enqueue_run(b, ws, st) == SGM_OK &&
+                 hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float t_ms = 0;
+            if (ok && rep > 0 && hipEventElapsedTime(&t_ms, e0, e1) == hipSuccess) ms = std::min(ms, t_ms);
         }
+        if (ok && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    };
+    // the lane mapping first (at 8 waves per CU, longest first), then
+    // waves per CU x queue order at the best mapping
+    for (int lanes : {0, 16, 8})
+        if (ok) trial(sgm_tuning{8, 0, lanes});
+    const int lanes = best.lanes;
+    const int waves[] = {4, 8, 12, 16, 24};
+    for (int order = 0; order <= 2 && ok; ++order)
+        for (int wv : waves)
+            if (ok && !(wv == 8 && order == 0)) trial(sgm_tuning{wv, order, lanes});
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (!ok) {
@@ -541,7 +574,7 @@ sgm_status sgm_batch_autotune(sgm_batch_t b, void *ws, size_t bytes, void *strea
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "%s %d %d %.4f\n", key.c_str(), best.waves_per_cu, best.order, best_ms);
+            fprintf(f, "%s %d %d %d %.4f\n", key.c_str(), best.waves_per_cu, best.order, best.lanes, best_ms);
             fclose(f);
         }
     }

@@ -30,6 +30,22 @@ __device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b)
 {
     return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - __builtin_bit_cast(u16x2, b));
 }
+// the minimum of the two halves, in both halves
+__device__ __forceinline__ uint32_t pk_min_halves(uint32_t a)
+{
+    const u16x2 v = __builtin_bit_cast(u16x2, a);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(v, __builtin_shufflevector(v, v, 1, 0)));
+}
+// packed minimum of n pairs as a balanced tree (a short dependency chain)
+template <int N>
+__device__ __forceinline__ uint32_t pk_min_tree(const uint32_t *v)
+{
+    if constexpr (N == 1) {
+        return v[0];
+    } else {
+        return pk_min(pk_min_tree<N / 2>(v), pk_min_tree<N - N / 2>(v + N / 2));
+    }
+}
 
 // DPP move: lanes whose source lies outside their 16-lane row keep `old`.
 template <int CTRL>
@@ -66,6 +82,38 @@ __device__ __forceinline__ uint32_t row_max16(uint32_t x)
     x = max(x, rot<kRowRor4>(x));
     x = max(x, rot<kRowRor8>(x));
     return x;
+}
+
+// the same over aligned groups of G = 4, 8 or 16 lanes (a quad, a half row,
+// a row): after the two quad swaps every lane holds its quad's extremum, and
+// the half-row mirror (lane i reads lane 7 - i of its half row) brings in
+// the other quad of the half row
+constexpr int kRowHalfMirror = 0x141;
+template <int G>
+__device__ __forceinline__ uint32_t group_min(uint32_t x)
+{
+    static_assert(G == 4 || G == 8 || G == 16, "groups of 4, 8 or 16 lanes");
+    if constexpr (G == 16) {
+        return row_min16(x);
+    } else {
+        x = min(x, rot<kQuadSwap1>(x));
+        x = min(x, rot<kQuadSwap2>(x));
+        if constexpr (G == 8) x = min(x, rot<kRowHalfMirror>(x));
+        return x;
+    }
+}
+template <int G>
+__device__ __forceinline__ uint32_t group_max(uint32_t x)
+{
+    static_assert(G == 4 || G == 8 || G == 16, "groups of 4, 8 or 16 lanes");
+    if constexpr (G == 16) {
+        return row_max16(x);
+    } else {
+        x = max(x, rot<kQuadSwap1>(x));
+        x = max(x, rot<kQuadSwap2>(x));
+        if constexpr (G == 8) x = max(x, rot<kRowHalfMirror>(x));
+        return x;
+    }
 }
 
 // direction table: path r -> r = (du, dv); predecessor of p is p - r
@@ -367,8 +415,8 @@ __device__ __forceinline__ void cost_tile(const uint64_t *__restrict__ cl, const
             for (int h = 0; h < 4; ++h) {
                 const int kk = 4 * q + h;
                 uint32_t c;
-                if constexpr (CH == 16) {
-                    // w % 16 == 0: every kk is inside the window and base - kk
+                if constexpr (CH >= 8) {
+                    // w % CH == 0: every kk is inside the window and base - kk
                     // inside s_cr, so the read is unconditional and only the
                     // off-image columns are replaced (branch-free)
                     const uint32_t pc = (uint32_t)__popcll(a ^ s_cr[base - kk]);
@@ -384,6 +432,8 @@ __device__ __forceinline__ void cost_tile(const uint64_t *__restrict__ cl, const
         uint8_t *dst = out + (size_t)px * w + k0;
         if constexpr (CH == 16) {
             *reinterpret_cast<uint4 *>(dst) = make_uint4(word[0], word[1], word[2], word[3]);
+        } else if constexpr (CH == 8) {
+            *reinterpret_cast<uint2 *>(dst) = make_uint2(word[0], word[1]);
         } else {
             for (int h = 0; h < CH && k0 + h < w; ++h) dst[h] = (uint8_t)(word[h / 4] >> (8 * (h % 4)));
         }
@@ -665,14 +715,15 @@ enum { kHorizontal = 0, kVertical = 1, kDiagonal = 2 };
 // only their loads and stores are masked.  Before a scanline enters the
 // image its loads return 0, which keeps L' at 0, so the first in-image
 // step computes L = C without any reset.
-template <int VPL, bool ALIGNED, bool PAD, bool L8, int PF, int KIND>
+template <int G, int VPL, bool ALIGNED, bool PAD, bool L8, int PF, int KIND>
 __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsrc_t rc, __amdgpu_buffer_rsrc_t ro,
                                          int du, int dv, int g)
 {
     constexpr int NP = VPL / 2;
     constexpr int UNROLL = 2 * PF;  // steps per loop iteration
-    const int lane = threadIdx.x & 15;
-    const int lw = threadIdx.x >> 4;
+    constexpr int LPWAVE = 64 / G;  // scanlines per wave
+    const int lane = threadIdx.x & (G - 1);
+    const int lw = threadIdx.x / G;
     const int W = a.W, H = a.H, w = a.w;
     const int lpw = a.lines_per_wg;
 
@@ -685,10 +736,12 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
         idx = min(idx, W - 1);
         I1 = H;
     } else {
+        // the wave's step range: the union over its own scanlines
         I0 = 1 << 30;
         I1 = 0;
-        for (int l = 0; l < lpw; ++l) {
-            const Line t = line_geom(g * lpw + l, du, dv, W, H);
+        const int first = g * lpw + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * LPWAVE;
+        for (int l = 0; l < LPWAVE; ++l) {
+            const Line t = line_geom(first + l, du, dv, W, H);
             if (t.i1 > t.i0) {
                 I0 = min(I0, t.i0);
                 I1 = max(I1, t.i1);
@@ -757,27 +810,33 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
                 const uint32_t o = (ip < I1) ? offset(ip) : kOff;
                 buf_load_u8<VPL, ALIGNED>(ring[s % PF], rc, o, nvalid);
             }
-            // m_q = min_k L(q,k): lane-local pair minimum (computed at the end
-            // of the previous step) reduced over the 16 lanes.  This chain is
-            // independent of the neighbour terms below, which overlap it.
-            const uint32_t m = row_min16(min(mnq & 0xFFFFu, mnq >> 16));
-            const uint32_t mm = m | (m << 16);
-            const uint32_t mp2 = pk_add(mm, a.p2x2);
+            // m_q = min_k L(q,k) in both u16 halves: the lane's pair minimum
+            // (from the end of the previous step) folded over its halves,
+            // then reduced over the group as 32-bit values (such doubled
+            // values order as m_q does).  This chain is independent of the
+            // neighbour terms below, which overlap it.
+            const uint32_t mm = group_min<G>(pk_min_halves(mnq));
             // end neighbours across the lane edges (outside the window: 0x3FFF)
-            const uint32_t e = dpp<kRowShr1>(kInf2, Lq[NP - 1]);
-            const uint32_t f = dpp<kRowShl1>(kInf2, Lq[0]);
+            uint32_t e = dpp<kRowShr1>(kInf2, Lq[NP - 1]);
+            uint32_t f = dpp<kRowShl1>(kInf2, Lq[0]);
+            if constexpr (G < 16) {
+                // groups inside a DPP row: their end lanes read another scanline
+                e = lane == 0 ? kInf2 : e;
+                f = lane == G - 1 ? kInf2 : f;
+            }
+            // L(p,k) = C(p,k) + min(L(q,k), L(q,k+-1) + P1, m_q + P2) - m_q
+            //        = C(p,k) + min(t - m_q, P2),  t = min(L(q,k), L(q,k+-1) + P1) >= m_q,
+            // so m_q enters only after t (no u16 value goes below 0 or past
+            // 0x3FFF + P1 + P2)
             uint32_t Ln[NP];
-            uint32_t mn = 0xFFFFFFFFu;
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
                 const uint32_t lft = j ? Lq[j - 1] : __builtin_amdgcn_alignbit(Lq[NP - 1], e, 16);
                 const uint32_t rgt = j + 1 < NP ? Lq[j + 1] : __builtin_amdgcn_alignbit(f, Lq[0], 16);
-                // L(p,k) = C(p,k) + min(L(q,k), L(q,k+-1) + P1, m_q + P2) - m_q
-                uint32_t t = pk_add(pk_min(lft, rgt), a.p1x2);
-                t = pk_min(pk_min(t, Lq[j]), mp2);
-                Ln[j] = pk_sub(pk_add(t, c2[j]), mm);
-                mn = pk_min(mn, Ln[j]);
+                const uint32_t t = pk_min(Lq[j], pk_add(pk_min(lft, rgt), a.p1x2));
+                Ln[j] = pk_add(pk_min(pk_sub(t, mm), a.p2x2), c2[j]);
             }
+            const uint32_t mn = pk_min_tree<NP>(Ln);
             store_strided<VPL, ALIGNED, L8>(Ln, ro, (i < I1) ? offset(i) : kOff, nvalid);
 #pragma unroll
             for (int j = 0; j < NP; ++j) Lq[j] = Ln[j];
@@ -789,7 +848,7 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
 
 // One workgroup-sized piece of the aggregation: direction r, scanline group g
 // of the volume described by `a`, written to output volume `vol`.
-template <int VPL, bool ALIGNED, bool PAD, bool L8, int PF>
+template <int G, int VPL, bool ALIGNED, bool PAD, bool L8, int PF>
 __device__ __forceinline__ void agg_item(const AggParams &a, int r, int vol, int g)
 {
     const int du = __builtin_amdgcn_readfirstlane(dir_du(r)), dv = __builtin_amdgcn_readfirstlane(dir_dv(r));
@@ -803,19 +862,19 @@ __device__ __forceinline__ void agg_item(const AggParams &a, int r, int vol, int
     if (dv == 0) {
         // the longest dependency chains: issue them first on a shared SIMD
         __builtin_amdgcn_s_setprio(2);
-        agg_scan<VPL, ALIGNED, PAD, L8, PF, kHorizontal>(a, rc, ro, du, dv, g);
+        agg_scan<G, VPL, ALIGNED, PAD, L8, PF, kHorizontal>(a, rc, ro, du, dv, g);
         __builtin_amdgcn_s_setprio(0);
     } else if (du == 0) {
-        agg_scan<VPL, ALIGNED, PAD, L8, PF, kVertical>(a, rc, ro, du, dv, g);
+        agg_scan<G, VPL, ALIGNED, PAD, L8, PF, kVertical>(a, rc, ro, du, dv, g);
     } else {
-        agg_scan<VPL, ALIGNED, PAD, L8, PF, kDiagonal>(a, rc, ro, du, dv, g);
+        agg_scan<G, VPL, ALIGNED, PAD, L8, PF, kDiagonal>(a, rc, ro, du, dv, g);
     }
 }
 
 // ---------------------------------------------------------------------------
 // winner-take-all, sub-pixel parabola, eq. (10) offset
 
-template <int VPL>
+template <int G, int VPL>
 __device__ __forceinline__ void select_and_write(const uint32_t (&S)[VPL / 2], int kbase, int w, int lane,
                                                  int lo, long long pix, uint16_t *dint, float *dsub)
 {
@@ -828,7 +887,7 @@ __device__ __forceinline__ void select_and_write(const uint32_t (&S)[VPL / 2], i
         if (k < w) best = min(best, (s0 << 8) | (uint32_t)k);
         if (k + 1 < w) best = min(best, (s1 << 8) | (uint32_t)(k + 1));
     }
-    best = row_min16(best);
+    best = group_min<G>(best);
     const int ks = (int)(best & 0xFFu);
     const int s0 = (int)(best >> 8);
     uint32_t sm = 0, sp = 0;
@@ -841,8 +900,8 @@ __device__ __forceinline__ void select_and_write(const uint32_t (&S)[VPL / 2], i
         if (k == ks + 1) sp = a;
         if (k + 1 == ks + 1) sp = b;
     }
-    sm = row_max16(sm);
-    sp = row_max16(sp);
+    sm = group_max<G>(sm);
+    sp = group_max<G>(sp);
     if (lane == 0) {
         dint[pix] = (uint16_t)(lo + ks);
         if (dsub) {
@@ -863,7 +922,7 @@ __device__ __forceinline__ void select_and_write(const uint32_t (&S)[VPL / 2], i
 // halves of separate registers (sums <= npaths * (Cmax + P2) <= 65535, so
 // halves never carry).  ev[q] then holds S at window indices (4q, 4q+2) and
 // od[q] at (4q+1, 4q+3) of the lane's range.
-template <int VPL>
+template <int G, int VPL>
 __device__ __forceinline__ void select_swar(const uint32_t (&ev)[Raw<VPL>::NW], const uint32_t (&od)[Raw<VPL>::NW],
                                             int kbase, int w, int lane, int lo, long long pix, uint16_t *dint,
                                             float *dsub)
@@ -879,7 +938,7 @@ __device__ __forceinline__ void select_swar(const uint32_t (&ev)[Raw<VPL>::NW], 
             if (4 * q + h < VPL && k < w) best = min(best, (sv << 8) | (uint32_t)k);
         }
     }
-    best = row_min16(best);
+    best = group_min<G>(best);
     const int ks = (int)(best & 0xFFu);
     const int s0 = (int)(best >> 8);
     uint32_t sm = 0, sp = 0;
@@ -895,8 +954,8 @@ __device__ __forceinline__ void select_swar(const uint32_t (&ev)[Raw<VPL>::NW], 
             }
         }
     }
-    sm = row_max16(sm);
-    sp = row_max16(sp);
+    sm = group_max<G>(sm);
+    sp = group_max<G>(sp);
     if (lane == 0) {
         dint[pix] = (uint16_t)(lo + ks);
         if (dsub) {
@@ -912,16 +971,17 @@ __device__ __forceinline__ void select_swar(const uint32_t (&ev)[Raw<VPL>::NW], 
 }
 
 
-// selection for pixel group `pblock` (16 pixels per 256 threads) of one volume set
-template <int VPL, bool ALIGNED, bool L8>
+// selection for pixel group `pblock` (blockDim / G pixels, G lanes each) of
+// one volume set
+template <int G, int VPL, bool ALIGNED, bool L8>
 __device__ __forceinline__ void wta_paths_group(const void *__restrict__ vols, long long vstride, int np,
                                                 const int32_t *__restrict__ d_lo, int W, int H, int w,
                                                 uint16_t *__restrict__ dint, float *__restrict__ dsub,
                                                 long long pblock)
 {
     constexpr int NP = VPL / 2;
-    const int lane = threadIdx.x & 15;
-    const long long pix = pblock * (blockDim.x >> 4) + (threadIdx.x >> 4);
+    const int lane = threadIdx.x & (G - 1);
+    const long long pix = pblock * (blockDim.x / G) + (threadIdx.x / G);
     if (pix >= (long long)W * H) return;
     const int kbase = lane * VPL;
     const int nvalid = min(max(w - kbase, 0), VPL);
@@ -967,7 +1027,7 @@ __device__ __forceinline__ void wta_paths_group(const void *__restrict__ vols, l
                 }
             }
         }
-        select_swar<VPL>(ev, od, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
+        select_swar<G, VPL>(ev, od, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
     } else {
         uint32_t S[NP];
 #pragma unroll
@@ -989,7 +1049,7 @@ __device__ __forceinline__ void wta_paths_group(const void *__restrict__ vols, l
                 }
             }
         }
-        select_and_write<VPL>(S, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
+        select_and_write<G, VPL>(S, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
     }
 }
 

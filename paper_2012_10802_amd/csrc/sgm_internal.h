@@ -20,10 +20,47 @@ char *error_buffer();
 // a uint16 volume therefore holds fewer than 2^30 values.
 constexpr long long kMaxU16Volume = 1ll << 30;
 
+// Lane mapping of the volume kernels: `lanes` lanes carry one scanline of
+// the aggregation (one pixel of the selection), each holding `vpl`
+// consecutive window values.  Compiled mappings: 16 lanes with vpl 2, 4, 8,
+// 12 or 16 (any window width); 8 lanes with vpl 4 or 8 and 4 lanes with vpl
+// 4, 8, 12 or 16, only for widths that are a multiple of vpl.
+struct Mapping {
+    int lanes, vpl;
+};
+
+// The mapping for window width w (1..256) and a requested lane count (4, 8
+// or 16; 0 = 16).  A request that no compiled mapping serves at this width
+// falls back to 16 lanes.
+inline Mapping choose_mapping(int w, int lanes)
+{
+    if (lanes == 4 || lanes == 8) {
+        static const int v8[] = {4, 8}, v4[] = {4, 8, 12, 16};
+        const int *v = lanes == 8 ? v8 : v4;
+        const int n = lanes == 8 ? 2 : 4;
+        for (int i = 0; i < n; ++i)
+            if (lanes * v[i] >= w && w % v[i] == 0) return Mapping{lanes, v[i]};
+    }
+    return Mapping{16, w <= 32 ? 2 : (w <= 64 ? 4 : (w <= 128 ? 8 : (w <= 192 ? 12 : 16)))};
+}
+
+// The selection's mapping: the fewest lanes per pixel that serve w (more
+// pixels per wave, fewer idle lanes and cross-lane steps).
+inline Mapping select_mapping(int w)
+{
+    Mapping m = choose_mapping(w, 4);
+    if (m.lanes == 16) m = choose_mapping(w, 8);
+    return m;
+}
+
 // Launch configuration chosen at plan time.
 struct KernelConfig {
-    int vpl;        // disparities per lane; 16 lanes carry one scanline
-    bool aligned;   // w % vpl == 0: vector loads/stores of a lane's values
+    int lanes;      // aggregation: lanes per scanline (4, 8 or 16)
+    int vpl;        // aggregation: disparities per lane
+    int wta_lanes;  // selection: lanes per pixel
+    int wta_vpl;    // selection: disparities per lane
+    bool aligned;   // vector loads/stores of a lane's values (w % vpl == 0
+                    // and buffers aligned); false only with 16-lane mappings
     bool l8;        // per-path aggregated costs fit in uint8 (Cmax + P2 <= 255)
     int agg_block;  // threads per aggregation workgroup (multiple of 64)
 };
@@ -101,7 +138,7 @@ struct PairDev {
     float *dsub;
     long long off_codes_l, off_codes_r, off_cost, off_vols;
     long long vstride;  // elements between per-direction volumes
-    int32_t W, H, w, pitch, vpl, pad;
+    int32_t W, H, w, pitch, lanes, vpl, pad, wta_lanes, wta_vpl;
     int32_t census_start, cost_start, wta_start;  // first block of the pair in each batched grid
     int32_t census_tx, census_ty, cost_tx;
 };

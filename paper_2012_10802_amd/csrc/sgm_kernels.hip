@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_cost(const uint64_t *__restrict__ cl, c
     cost_tile<CH>(cl, cr, d_lo, W, H, w, cmax, cost, blockIdx.x, blockIdx.y);
 }
 
-template <int VPL, bool ALIGNED, bool PAD, bool L8, int PF>
+template <int G, int VPL, bool ALIGNED, bool PAD, bool L8, int PF>
 __global__ __launch_bounds__(256) void k_aggregate(AggParams a)
 {
     int slot = 0;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_aggregate(AggParams a)
     const int r = __builtin_amdgcn_readfirstlane(a.paths[slot] & 0xFF);
     const int vol = __builtin_amdgcn_readfirstlane(a.paths[slot] >> 8);
     const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x - a.gstart[slot]);
-    agg_item<VPL, ALIGNED, PAD, L8, PF>(a, r, vol, g);
+    agg_item<G, VPL, ALIGNED, PAD, L8, PF>(a, r, vol, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -126,19 +126,42 @@ __global__ __launch_bounds__(256) void k_wta_sum(const uint16_t *__restrict__ su
 #pragma unroll
         for (int j = 0; j < VPL / 2; ++j) S[j] = 0;
     const int v = (int)(pix / W);
-    select_and_write<VPL>(S, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
+    select_and_write<16, VPL>(S, kbase, w, lane, d_lo ? d_lo[v] : 0, pix, dint, dsub);
 }
 
-template <int VPL, bool ALIGNED, bool L8>
+template <int G, int VPL, bool ALIGNED, bool L8>
 __global__ __launch_bounds__(256) void k_wta_paths(const void *__restrict__ vols, long long vstride, int np,
                                                    const int32_t *__restrict__ d_lo, int W, int H, int w,
                                                    uint16_t *__restrict__ dint, float *__restrict__ dsub)
 {
-    wta_paths_group<VPL, ALIGNED, L8>(vols, vstride, np, d_lo, W, H, w, dint, dsub, blockIdx.x);
+    wta_paths_group<G, VPL, ALIGNED, L8>(vols, vstride, np, d_lo, W, H, w, dint, dsub, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // dispatch helpers
+
+// Lane mappings compiled for the volume kernels: G lanes carry one scanline
+// (aggregation) or one pixel (selection), each holding VPL window values.
+// G = 16 serves every window width (with any w % VPL); the narrower groups
+// serve w <= 64 when w is a multiple of VPL.
+template <template <int, int> class F, typename... A>
+hipError_t by_mapping(int g, int vpl, A &&...args)
+{
+    switch (g * 256 + vpl) {
+    case 16 * 256 + 2: return F<16, 2>::run(args...);
+    case 16 * 256 + 4: return F<16, 4>::run(args...);
+    case 16 * 256 + 8: return F<16, 8>::run(args...);
+    case 16 * 256 + 12: return F<16, 12>::run(args...);
+    case 16 * 256 + 16: return F<16, 16>::run(args...);
+    case 8 * 256 + 4: return F<8, 4>::run(args...);
+    case 8 * 256 + 8: return F<8, 8>::run(args...);
+    case 4 * 256 + 4: return F<4, 4>::run(args...);
+    case 4 * 256 + 8: return F<4, 8>::run(args...);
+    case 4 * 256 + 12: return F<4, 12>::run(args...);
+    case 4 * 256 + 16: return F<4, 16>::run(args...);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 template <template <int> class F, typename... A>
 hipError_t by_vpl(int vpl, A &&...args)
@@ -157,22 +180,29 @@ hipError_t by_vpl(int vpl, A &&...args)
 // w = 128 (four u16 pairs per lane): 24 steps stream the cost 11 % faster
 // than 8 (20 and 32 do not), so that width takes 24; the others keep 8,
 // where deeper rings only add registers.
-constexpr int prefetch_steps(int vpl) { return vpl == 8 ? 24 : 8; }
+constexpr int prefetch_steps(int g, int vpl) { return (g == 16 && vpl == 8) ? 24 : 8; }
 
-template <int VPL>
+template <int G, int VPL>
 struct AggLaunch {
+    static constexpr int PF = prefetch_steps(G, VPL);
     static hipError_t run(const KernelConfig &kc, bool l8, bool pad, const AggParams &p, dim3 grid, dim3 block,
                           hipStream_t s)
     {
-        if (!kc.aligned) {
-            if (l8) hipLaunchKernelGGL((k_aggregate<VPL, false, true, true, prefetch_steps(VPL)>), grid, block, 0, s, p);
-            else hipLaunchKernelGGL((k_aggregate<VPL, false, true, false, prefetch_steps(VPL)>), grid, block, 0, s, p);
-        } else if (pad) {
-            if (l8) hipLaunchKernelGGL((k_aggregate<VPL, true, true, true, prefetch_steps(VPL)>), grid, block, 0, s, p);
-            else hipLaunchKernelGGL((k_aggregate<VPL, true, true, false, prefetch_steps(VPL)>), grid, block, 0, s, p);
+        if constexpr (G == 16) {
+            if (!kc.aligned) {
+                if (l8) hipLaunchKernelGGL((k_aggregate<G, VPL, false, true, true, PF>), grid, block, 0, s, p);
+                else hipLaunchKernelGGL((k_aggregate<G, VPL, false, true, false, PF>), grid, block, 0, s, p);
+                return hipGetLastError();
+            }
         } else {
-            if (l8) hipLaunchKernelGGL((k_aggregate<VPL, true, false, true, prefetch_steps(VPL)>), grid, block, 0, s, p);
-            else hipLaunchKernelGGL((k_aggregate<VPL, true, false, false, prefetch_steps(VPL)>), grid, block, 0, s, p);
+            if (!kc.aligned) return hipErrorInvalidValue;
+        }
+        if (pad) {
+            if (l8) hipLaunchKernelGGL((k_aggregate<G, VPL, true, true, true, PF>), grid, block, 0, s, p);
+            else hipLaunchKernelGGL((k_aggregate<G, VPL, true, true, false, PF>), grid, block, 0, s, p);
+        } else {
+            if (l8) hipLaunchKernelGGL((k_aggregate<G, VPL, true, false, true, PF>), grid, block, 0, s, p);
+            else hipLaunchKernelGGL((k_aggregate<G, VPL, true, false, false, PF>), grid, block, 0, s, p);
         }
         return hipGetLastError();
     }
@@ -193,28 +223,33 @@ struct WtaSumLaunch {
     }
 };
 
-template <int VPL>
+template <int G, int VPL>
 struct WtaPathsLaunch {
     static hipError_t run(const KernelConfig &kc, const Problem &pb, const void *vols, long long vstride, int np,
                           bool l8, const int32_t *d_lo, uint16_t *dint, float *dsub, hipStream_t s)
     {
         const long long npix = (long long)pb.W * pb.H;
-        dim3 grid((unsigned)((npix + 15) / 16)), block(256);
-        if (kc.aligned) {
-            if (l8)
-                hipLaunchKernelGGL((k_wta_paths<VPL, true, true>), grid, block, 0, s, vols, vstride, np, d_lo, pb.W,
-                                   pb.H, pb.w, dint, dsub);
-            else
-                hipLaunchKernelGGL((k_wta_paths<VPL, true, false>), grid, block, 0, s, vols, vstride, np, d_lo, pb.W,
-                                   pb.H, pb.w, dint, dsub);
+        constexpr int PPB = 256 / G;  // pixels per workgroup
+        dim3 grid((unsigned)((npix + PPB - 1) / PPB)), block(256);
+        if constexpr (G == 16) {
+            if (!kc.aligned) {
+                if (l8)
+                    hipLaunchKernelGGL((k_wta_paths<G, VPL, false, true>), grid, block, 0, s, vols, vstride, np,
+                                       d_lo, pb.W, pb.H, pb.w, dint, dsub);
+                else
+                    hipLaunchKernelGGL((k_wta_paths<G, VPL, false, false>), grid, block, 0, s, vols, vstride, np,
+                                       d_lo, pb.W, pb.H, pb.w, dint, dsub);
+                return hipGetLastError();
+            }
         } else {
-            if (l8)
-                hipLaunchKernelGGL((k_wta_paths<VPL, false, true>), grid, block, 0, s, vols, vstride, np, d_lo, pb.W,
-                                   pb.H, pb.w, dint, dsub);
-            else
-                hipLaunchKernelGGL((k_wta_paths<VPL, false, false>), grid, block, 0, s, vols, vstride, np, d_lo,
-                                   pb.W, pb.H, pb.w, dint, dsub);
+            if (!kc.aligned) return hipErrorInvalidValue;
         }
+        if (l8)
+            hipLaunchKernelGGL((k_wta_paths<G, VPL, true, true>), grid, block, 0, s, vols, vstride, np, d_lo, pb.W,
+                               pb.H, pb.w, dint, dsub);
+        else
+            hipLaunchKernelGGL((k_wta_paths<G, VPL, true, false>), grid, block, 0, s, vols, vstride, np, d_lo, pb.W,
+                               pb.H, pb.w, dint, dsub);
         return hipGetLastError();
     }
 };
@@ -246,9 +281,13 @@ hipError_t launch_cost(const Problem &pb, const KernelConfig &kc, const uint64_t
 {
     (void)kc;
     dim3 grid((pb.W + kCostTile - 1) / kCostTile, pb.H), block(256);
-    // 16-byte stores need w % 16 == 0 and a 16-byte aligned volume
-    if ((pb.w % 16) == 0 && (reinterpret_cast<uintptr_t>(cost) % 16) == 0)
+    // 16-byte (8-byte) stores need w % 16 == 0 (w % 8 == 0) and a volume
+    // aligned to them
+    const uintptr_t a = reinterpret_cast<uintptr_t>(cost);
+    if ((pb.w % 16) == 0 && (a % 16) == 0)
         hipLaunchKernelGGL(k_cost<16>, grid, block, 0, s, cl, cr, d_lo, pb.W, pb.H, pb.w, pb.cmax, cost);
+    else if ((pb.w % 8) == 0 && (a % 8) == 0)
+        hipLaunchKernelGGL(k_cost<8>, grid, block, 0, s, cl, cr, d_lo, pb.W, pb.H, pb.w, pb.cmax, cost);
     else
         hipLaunchKernelGGL(k_cost<4>, grid, block, 0, s, cl, cr, d_lo, pb.W, pb.H, pb.w, pb.cmax, cost);
     return hipGetLastError();
@@ -267,7 +306,7 @@ hipError_t launch_aggregate(const Problem &pb, const KernelConfig &kc, const uin
     p.p1x2 = (uint32_t)pb.p1 * 0x10001u;
     p.p2x2 = (uint32_t)pb.p2 * 0x10001u;
     p.np = np;
-    p.lines_per_wg = kc.agg_block / 16;
+    p.lines_per_wg = kc.agg_block / kc.lanes;
     // Dispatch slots in order of scanline length (horizontal, diagonal,
     // vertical) so the longest dependency chains start first.  Slot o
     // aggregates direction paths[i] into output volume i: code = r | i << 8.
@@ -285,7 +324,7 @@ hipError_t launch_aggregate(const Problem &pb, const KernelConfig &kc, const uin
         }
     p.gstart[np] = acc;
     dim3 grid(acc), block(kc.agg_block);
-    return by_vpl<AggLaunch>(kc.vpl, kc, l8, pb.w < 16 * kc.vpl, p, grid, block, s);
+    return by_mapping<AggLaunch>(kc.lanes, kc.vpl, kc, l8, pb.w < kc.lanes * kc.vpl, p, grid, block, s);
 }
 
 hipError_t launch_sum(const Problem &pb, const KernelConfig &kc, const void *vols, int np, bool l8, uint16_t *sum,
@@ -304,13 +343,16 @@ hipError_t launch_sum(const Problem &pb, const KernelConfig &kc, const void *vol
 hipError_t launch_wta_sum(const Problem &pb, const KernelConfig &kc, const uint16_t *sum, const int32_t *d_lo,
                           uint16_t *dint, float *dsub, hipStream_t s)
 {
-    return by_vpl<WtaSumLaunch>(kc.vpl, kc, pb, sum, d_lo, dint, dsub, s);
+    // the materialised sum is read by 16 lanes per pixel
+    const Mapping m = choose_mapping(pb.w, 16);
+    return by_vpl<WtaSumLaunch>(m.vpl, kc, pb, sum, d_lo, dint, dsub, s);
 }
 
 hipError_t launch_wta_paths(const Problem &pb, const KernelConfig &kc, const void *vols, int np, bool l8,
                             const int32_t *d_lo, uint16_t *dint, float *dsub, hipStream_t s)
 {
-    return by_vpl<WtaPathsLaunch>(kc.vpl, kc, pb, vols, volume_stride(pb, l8), np, l8, d_lo, dint, dsub, s);
+    return by_mapping<WtaPathsLaunch>(kc.wta_lanes, kc.wta_vpl, kc, pb, vols, volume_stride(pb, l8), np, l8, d_lo,
+                                      dint, dsub, s);
 }
 
 }  // namespace sgm

@@ -386,9 +386,10 @@ __device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) { return 
 
 // One step of eq. (8) on per-pixel windows for one lane (one scanline):
 // L, m hold the predecessor's 16 values (packed u16 pairs) and their
-// minimum and are replaced by the new ones; c4 holds the 16 cost bytes; sh
-// = lo(p) - lo(q) (0 where q has no window).  Returns the new values as
-// bytes.  Every lane of the wave must call it (wave-uniform branches).
+// minimum (in both u16 halves) and are replaced by the new ones; c4 holds
+// the 16 cost bytes; sh = lo(p) - lo(q) (0 where q has no window).  Returns
+// the new values as bytes.  Every lane of the wave must call it
+// (wave-uniform branches).
 __device__ __forceinline__ v4u win16_update(uint32_t (&L)[8], uint32_t &m, const v4u c4, const int sh,
                                             const uint32_t P1, const uint32_t P2, uint32_t *row)
 {
@@ -425,22 +426,20 @@ __device__ __forceinline__ v4u win16_update(uint32_t (&L)[8], uint32_t &m, const
         P0[k] = funnel16(V[k + 1], V[k]);
         Pp[k] = V[k + 1];
     }
-    const uint32_t m2 = m | (m << 16);
-    const uint32_t mp2 = pk_add(m2, P2);
+    // C + min(V(j), V(j+-1) + P1, m_q + P2) - m_q = C + min(t - m_q, P2) with
+    // t = min(V(j), V(j+-1) + P1) >= m_q (sentinels included), so m_q enters
+    // last and the step's dependency chain stays short
     const uint32_t cw[4] = {c4.x, c4.y, c4.z, c4.w};
     uint32_t Ln[8];
-    uint32_t mn = 0xFFFFFFFFu;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        uint32_t t = pk_add(pk_min(Pm[k], Pp[k]), P1);
-        t = pk_min(pk_min(t, P0[k]), mp2);
+        const uint32_t t = pk_min(P0[k], pk_add(pk_min(Pm[k], Pp[k]), P1));
         const uint32_t c = (k & 1) ? bytes_hi(cw[k >> 1]) : bytes_lo(cw[k >> 1]);
-        Ln[k] = pk_sub(pk_add(c, t), m2);
-        mn = pk_min(mn, Ln[k]);
+        Ln[k] = pk_add(pk_min(pk_sub(t, m), P2), c);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) L[k] = Ln[k];
-    m = min(mn & 0xFFFFu, mn >> 16);
+    m = pk_min_halves(pk_min_tree<8>(Ln));
     return (v4u){pack4(Ln[0], Ln[1]), pack4(Ln[2], Ln[3]), pack4(Ln[4], Ln[5]), pack4(Ln[6], Ln[7])};
 }
 
@@ -482,7 +481,7 @@ __device__ __forceinline__ void win16_scan(const Win16Params &a, __amdgpu_buffer
     uint32_t L[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) L[k] = 0u;
-    uint32_t m = 0u;  // min of L
+    uint32_t m = 0u;  // min of L (in both halves)
     int loq = kNoLo;
 
     // one step: consume ring slot S (loaded PF steps ago), refill it for

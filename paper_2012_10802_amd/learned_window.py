@@ -46,6 +46,7 @@ import torch
 from . import sgm as S
 
 CH = 16
+OUT_CH = 2  # network outputs kept: centre offset, confidence logit
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "window_cnn.npz")
 _lib = S.library()
@@ -103,7 +104,7 @@ class WindowNet:
     # --- buffers for n images of W x H
     def buffers(self, W, H, n):
         act = torch.empty((3, n, H, W, CH), dtype=torch.int16, device=self.device)
-        out = torch.empty((n, H, W, CH), dtype=torch.float32, device=self.device)
+        out = torch.empty((n, H, W, OUT_CH), dtype=torch.float32, device=self.device)
         return act, out
 
     def forward(self, x0, acts, out, W, H, n, stream=None):
@@ -316,20 +317,34 @@ class LearnedWindowMatcher:
         cache[key] = m
         return m
 
-    def windows(self, left, right, stream=None):
+    STAGES = ("reduce", "coarse_sgm", "network", "window_map", "windowed_sgm", "fallback_merge")
+
+    def windows(self, left, right, stream=None, events=None):
         """Steps 1-5 for left, right uint8 [n, H, W]: fills lo, mask, stats,
-        nfallback, dint and dsub (records ev_maps once the maps are done)."""
+        nfallback, dint and dsub (records ev_maps once the maps are done).
+        `events` (optional, 7 timing events) are recorded on the stream
+        before the first stage and after each of STAGES."""
         n = self.n
         if tuple(left.shape) != (n, self.H, self.W) or tuple(right.shape) != (n, self.H, self.W):
             raise ValueError("left and right must be uint8 [%d, %d, %d]" % (n, self.H, self.W))
         main = stream if stream is not None else torch.cuda.current_stream(self.device)
+
+        def mark(k):
+            if events is not None:
+                events[k].record(main)
+
+        mark(0)
         S.sgm_downsample4_batch(left, self.cl, main)
         S.sgm_downsample4_batch(right, self.cr, main)
+        mark(1)
         self.coarse.run(main)
+        mark(2)
         prepare_input(self.cds, self.cl, self.Wc, self.Hc, n, self.x0, main)
         self.net.forward(self.x0, self.acts, self.out, self.Wc, self.Hc, n, main)
+        mark(3)
         window_map_batch(self.cds, self.out, self.W, self.H, self.D, self.w, self.tau, self.lo, self.mask,
                          self.stats, self.nfallback, main)
+        mark(4)
         self.ev_maps.record(main)
         if self.w == 16:
             self.fine.match_win_batch(left, right, self.lo, disp_int=self.dint, disp_sub=self.dsub,
@@ -338,8 +353,9 @@ class LearnedWindowMatcher:
             for i in range(n):
                 self.fine.match_win(left[i], right[i], self.lo[i], disp_int=self.dint[i], disp_sub=self.dsub[i],
                                     stream=main)
+        mark(5)
 
-    def fallback(self, left, right, stream=None):
+    def fallback(self, left, right, stream=None, events=None):
         """Step 6: waits on the host for the window maps only; the
         rectangles' plain SGM runs on the side stream beside the windowed
         SGM, and the merge follows both on the main stream."""
@@ -366,16 +382,18 @@ class LearnedWindowMatcher:
                 self._full_matcher(j, h, w).match_at(left[i], right[i], y0, x0, disp_int=bi, disp_sub=bs,
                                                      stream=self.fb_streams[j])
                 merges.append((i, y0, x0, bi, bs))
-        if not merges:
-            return
-        for st, ev in zip(self.fb_streams, self.ev_fb):
-            ev.record(st)
-            main.wait_event(ev)
-        for i, y0, x0, bi, bs in merges:
-            fallback_merge(self.mask[i], bi, bs, y0, x0, self.dint[i], self.dsub[i], main)
+        if merges:
+            for st, ev in zip(self.fb_streams, self.ev_fb):
+                ev.record(st)
+                main.wait_event(ev)
+            for i, y0, x0, bi, bs in merges:
+                fallback_merge(self.mask[i], bi, bs, y0, x0, self.dint[i], self.dsub[i], main)
+        if events is not None:
+            events[6].record(main)
 
-    def match(self, left, right, stream=None):
-        """Returns (disp_int int16 [n,H,W], disp_sub float32 [n,H,W]) device tensors."""
-        self.windows(left, right, stream)
-        self.fallback(left, right, stream)
+    def match(self, left, right, stream=None, events=None):
+        """Returns (disp_int int16 [n,H,W], disp_sub float32 [n,H,W]) device
+        tensors.  `events`: optional 7 timing events for the stages (STAGES)."""
+        self.windows(left, right, stream, events)
+        self.fallback(left, right, stream, events)
         return self.dint, self.dsub

@@ -51,7 +51,7 @@ class sgm_batch_params(ctypes.Structure):
 
 
 class sgm_tuning(ctypes.Structure):
-    _fields_ = [("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32)]
+    _fields_ = [("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32), ("lanes", ctypes.c_int32)]
 
 
 def _load_library():
@@ -64,6 +64,10 @@ def _load_library():
     sig = {
         "sgm_plan": [ctypes.POINTER(sgm_params), ctypes.POINTER(P)],
         "sgm_plan_free": [P],
+        "sgm_plan_tuned": [ctypes.POINTER(sgm_params), ctypes.POINTER(sgm_tuning), ctypes.POINTER(P)],
+        "sgm_plan_get_tuning": [P, ctypes.POINTER(sgm_tuning)],
+        "sgm_autotune": [ctypes.POINTER(sgm_params), P, P, I, P, P, P, P, S, P, ctypes.c_char_p,
+                         ctypes.POINTER(sgm_tuning)],
         "sgm_workspace_size": [P, ctypes.POINTER(S)],
         "sgm_census": [P, P, I, P, P],
         "sgm_cost": [P, P, P, I, P, P, P, S, P],
@@ -180,11 +184,23 @@ def _need(t, dtype, shape, name, device=True):
 # the C calls, one for one
 
 
-def sgm_plan(width, height, census, ndisp, npaths, p1, p2, flags=0):
+def sgm_plan(width, height, census, ndisp, npaths, p1, p2, flags=0, lanes=None):
+    """A plan (sgm_plan, or sgm_plan_tuned when `lanes` is given: 0, 4, 8, 16)."""
     prm = sgm_params(width, height, census, ndisp, npaths, p1, p2, flags)
     h = ctypes.c_void_p()
-    _check(_lib.sgm_plan(ctypes.byref(prm), ctypes.byref(h)), "sgm_plan")
+    if lanes is None:
+        _check(_lib.sgm_plan(ctypes.byref(prm), ctypes.byref(h)), "sgm_plan")
+    else:
+        t = sgm_tuning(0, 0, int(lanes))
+        _check(_lib.sgm_plan_tuned(ctypes.byref(prm), ctypes.byref(t), ctypes.byref(h)), "sgm_plan_tuned")
     return h
+
+
+def sgm_plan_lanes(plan) -> int:
+    """Lanes per scanline / pixel the plan's volume kernels use."""
+    t = sgm_tuning()
+    _check(_lib.sgm_plan_get_tuning(plan, ctypes.byref(t)), "sgm_plan_get_tuning")
+    return int(t.lanes)
 
 
 def sgm_plan_free(plan):
@@ -514,10 +530,10 @@ class Matcher:
     """
 
     def __init__(self, width, height, census=7, ndisp=128, npaths=8, p1=10, p2=120,
-                 device=None, workspace=None):
+                 device=None, workspace=None, lanes=None):
         self.W, self.H, self.n, self.w = int(width), int(height), int(census), int(ndisp)
         self.npaths, self.p1, self.p2 = int(npaths), int(p1), int(p2)
-        self.plan = sgm_plan(self.W, self.H, self.n, self.w, self.npaths, self.p1, self.p2)
+        self.plan = sgm_plan(self.W, self.H, self.n, self.w, self.npaths, self.p1, self.p2, lanes=lanes)
         self.device = torch.device(device or "cuda")
         need = sgm_workspace_size(self.plan)
         if workspace is None:
@@ -757,6 +773,28 @@ class Matcher:
                               _ptr(self.workspace), self.ws_bytes, _stream(stream)), "sgm_match")
         return disp_int, disp_sub
 
+    @property
+    def lanes(self):
+        return sgm_plan_lanes(self.plan)
+
+    def autotune(self, left, right, d_lo=None, cache_path=None, stream=None):
+        """Time every lane mapping on these inputs (sgm_autotune; the host
+        waits), then rebuild the plan with the fastest.  Returns the lane
+        count chosen."""
+        self._img(left, "left")
+        self._img(right, "right")
+        di, ds = self._outs(None, None, True)
+        prm = sgm_params(self.W, self.H, self.n, self.w, self.npaths, self.p1, self.p2, 0)
+        t = sgm_tuning()
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(_lib.sgm_autotune(ctypes.byref(prm), _ptr(left), _ptr(right), left.shape[1], _ptr(self._dlo(d_lo)),
+                                 _ptr(di), _ptr(ds), _ptr(self.workspace), self.ws_bytes, _stream(stream), path,
+                                 ctypes.byref(t)), "sgm_autotune")
+        old = self.plan
+        self.plan = sgm_plan(self.W, self.H, self.n, self.w, self.npaths, self.p1, self.p2, lanes=int(t.lanes))
+        _lib.sgm_plan_free(old)
+        return int(t.lanes)
+
 
 class Batch:
     """Many pairs (of several sizes) matched together by the batch calls.
@@ -826,13 +864,15 @@ class Batch:
 
     @property
     def tuning(self):
+        """(waves per CU, queue order, lanes per scanline: 0 = default)"""
         t = sgm_tuning()
         _check(_lib.sgm_batch_get_tuning(self.handle, ctypes.byref(t)), "sgm_batch_get_tuning")
-        return int(t.waves_per_cu), int(t.order)
+        return int(t.waves_per_cu), int(t.order), int(t.lanes)
 
     @tuning.setter
     def tuning(self, value):
-        t = sgm_tuning(int(value[0]), int(value[1]))
+        lanes = int(value[2]) if len(value) > 2 else 0
+        t = sgm_tuning(int(value[0]), int(value[1]), lanes)
         _check(_lib.sgm_batch_set_tuning(self.handle, ctypes.byref(t)), "sgm_batch_set_tuning")
 
     def run(self, stream=None):
@@ -860,7 +900,7 @@ class Batch:
         path = None if cache_path is None else str(cache_path).encode()
         _check(_lib.sgm_batch_autotune(self.handle, _ptr(self.workspace), self.ws_bytes,
                                        _stream(stream), path, ctypes.byref(t)), "sgm_batch_autotune")
-        return int(t.waves_per_cu), int(t.order)
+        return int(t.waves_per_cu), int(t.order), int(t.lanes)
 
 
 def u16(t: torch.Tensor) -> torch.Tensor:

@@ -35,7 +35,7 @@ def _rand_pair(W, H, seed, shift=4):
 # (W, H, w, pitch, with row windows): every lane width, ragged sizes
 SMALL = [(97, 61, 24, 97, True), (160, 120, 64, 160, False), (200, 150, 128, 256, False),
          (45, 33, 16, 45, True), (64, 40, 192, 64, False), (70, 9, 256, 80, False),
-         (33, 70, 32, 33, False)]
+         (33, 70, 32, 33, False), (51, 47, 48, 64, True)]
 
 
 def _small_batch(sgm, seed=0):
@@ -66,8 +66,11 @@ def test_small_mixed_batch_matches_oracle(sgm):
     _check_against_oracle(b, host)
 
 
-@pytest.mark.parametrize("tuning", [(1, 0), (4, 1), (32, 2), (8, 0)])
+@pytest.mark.parametrize("tuning", [(1, 0, 0), (4, 1, 16), (32, 2, 8), (8, 0, 4), (8, 0, 16), (12, 2, 0)])
 def test_every_tuning_gives_identical_results(sgm, tuning):
+    """Waves per CU, queue order and lanes per scanline (0: the default
+    mapping of each width; 4 and 8 apply to the widths they serve, the
+    others keep 16) change nothing in the results."""
     import torch
     pairs, host = _small_batch(sgm, seed=1)
     b = sgm.Batch(pairs, census=N, npaths=R, p1=P1, p2=P2)

@@ -262,6 +262,70 @@ def test_split_aggregate_paths_and_selection(lib, shape):
     np.testing.assert_array_equal(dsub.cpu().numpy(), ws)
 
 
+@pytest.mark.parametrize("lanes", [4, 8, 16])
+@pytest.mark.parametrize("w", [16, 24, 32, 40, 48, 64])
+def test_lane_mappings_match_oracle(lib, w, lanes):
+    """Every lane mapping of the volume kernels (a scanline / a pixel carried
+    by 4, 8 or 16 lanes; idle lanes where the window does not fill the
+    group) on a ragged frame with row windows: each direction's L_r, the
+    selection on the per-direction volumes, the fused and the whole-path
+    calls; uint8 volumes, and uint16 ones (P2 = 220) at two widths."""
+    import torch
+    W, H, n = 77, 29, 7
+    p2 = 220 if w in (24, 48) else 120
+    L, Rimg = _rand_pair(W, H, 31 * w + lanes)
+    d_lo = np.random.default_rng(w + lanes).integers(0, 5, size=H).astype(np.int32)
+    m = lib.Matcher(W, H, census=n, ndisp=w, npaths=8, p1=10, p2=p2, lanes=lanes)
+    want_lanes = lanes if (lanes == 16 or any(lanes * v >= w and w % v == 0
+                                              for v in ((4, 8) if lanes == 8 else (4, 8, 12, 16)))) else 16
+    assert m.lanes == want_lanes
+    dl = _dev(d_lo)
+    cost = m.cost(_dev(L), _dev(Rimg), d_lo=dl)
+    paths = m.aggregate_paths(cost)
+    bi, bs = m.wta_paths(paths, d_lo=dl)
+    fi, fs = m.aggregate_wta(cost, d_lo=dl)
+    mi, ms = m.match(_dev(L), _dev(Rimg), d_lo=dl)
+    torch.cuda.synchronize()
+    c = cost.cpu().numpy()
+    np.testing.assert_array_equal(c, oracle.cost(oracle.census(L, n), oracle.census(Rimg, n), n, w, d_lo))
+    esz = m.path_volumes()[0]
+    for r in range(8):
+        got = m.path_volume(paths, r).cpu().numpy()
+        got = got.view(np.uint16) if esz == 2 else got
+        np.testing.assert_array_equal(got, oracle.path(c, r, 10, p2), err_msg="path %d" % r)
+    wi, ws = oracle.wta(oracle.sum_paths(c, 8, 10, p2), d_lo)
+    for a, b in ((bi, bs), (fi, fs), (mi, ms)):
+        np.testing.assert_array_equal(_np_u16(a), wi)
+        assert np.abs(b.cpu().numpy() - ws).max() <= SUB_TOL
+        np.testing.assert_array_equal(b.cpu().numpy(), ws)
+
+
+def test_single_pair_autotune_keeps_results(lib, tmp_path):
+    """sgm_autotune times the lane mappings, caches the choice, and the
+    tuned plan gives the oracle's disparities."""
+    import torch
+    p, c = _road("road1280_pt", 3001)
+    H, W = p.left.shape
+    a0, a1, phi = p.road_params
+    d_lo = oracle.window_from_road(a0, a1, phi, W, H, 24, mode=0)
+    m = lib.Matcher(W, H, census=7, ndisp=24, npaths=8)
+    cache = tmp_path / "tune.txt"
+    L, Rt, dl = _dev(p.left), _dev(p.right), _dev(d_lo)
+    lanes = m.autotune(L, Rt, d_lo=dl, cache_path=cache)
+    assert lanes in (4, 8, 16) and m.lanes == lanes
+    assert len(cache.read_text().splitlines()) == 1
+    m2 = lib.Matcher(W, H, census=7, ndisp=24, npaths=8)
+    assert m2.autotune(L, Rt, d_lo=dl, cache_path=cache) == lanes  # read back
+    assert len(cache.read_text().splitlines()) == 1
+    dint, dsub = m.match(L, Rt, d_lo=dl)
+    torch.cuda.synchronize()
+    n = 7
+    want_c = oracle.cost(oracle.census(p.left, n), oracle.census(p.right, n), n, 24, d_lo)
+    wi, ws = oracle.wta(oracle.sum_paths(want_c, 8, 10, 120), d_lo)
+    np.testing.assert_array_equal(_np_u16(dint), wi)
+    np.testing.assert_array_equal(dsub.cpu().numpy(), ws)
+
+
 def test_injected_launch_fault_then_recovery(lib):
     """An armed launch fault fails exactly one call (nothing enqueued); the
     next call runs normally and matches the oracle."""
