@@ -328,7 +328,7 @@ def learned_vs_plain(args, log=None):
     uu = torch.arange(W, device=dev)[None, :]
     tot = {"pix": 0, "bad_plain": 0, "bad_learned": 0, "miss": 0, "conf_pix": 0, "fallback": 0,
            "rect_area": 0, "fb_scored": 0, "fb_bad_plain": 0, "fb_bad_learned": 0, "fb_differ": 0}
-    t_plain, t_learned, stages = [], [], []
+    t_plain, t_learned, stages, rect_shapes = [], [], [], []
     ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev_stage = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
     nb = max(1, args.eval_pairs // B)
@@ -388,6 +388,8 @@ def learned_vs_plain(args, log=None):
                 tot["conf_pix"] += int(conf.sum())
                 tot["fallback"] += int(lw.nfallback[j])
                 tot["rect_area"] += sum((y1 - y0) * (x1 - x0) for y0, y1, x0, x1 in lw.last_rects[j])
+                for y0, y1, x0, x1 in lw.last_rects[j]:
+                    rect_shapes.append((y1 - y0, x1 - x0, x0 == 0))
                 # fallback pixels: the crop's full-range SGM against full-frame full-range SGM
                 fbm = lw.mask[j] > 0
                 tot["fb_differ"] += int((fbm & (lw.dint[j] != plain.disp_int[j])).sum())
@@ -446,6 +448,11 @@ def learned_vs_plain(args, log=None):
             "bad_1px_pct_crop": round(100.0 * tot["fb_bad_learned"] / max(1, tot["fb_scored"]), 4),
             "note": "fallback pixels take full-range SGM of a crop around them; compared here with "
                     "full-range SGM of the whole frame on the same pixels"},
+        "fallback_rectangles": {
+            "per_pair": round(len(rect_shapes) / max(1, nb * B), 2),
+            "mean_rows": round(float(np.mean([r[0] for r in rect_shapes])), 1) if rect_shapes else 0,
+            "mean_cols": round(float(np.mean([r[1] for r in rect_shapes])), 1) if rect_shapes else 0,
+            "at_left_edge_pct": round(100.0 * float(np.mean([r[2] for r in rect_shapes])), 1) if rect_shapes else 0},
         "stages_ms": stage_ms,
         "stage_roofline": stage_roof,
         "tau": args.tau,

@@ -256,7 +256,9 @@ sgm_status sgm_match_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *ri
  *   disp_int      device uint16 [nimg][H][W]; disp_sub float32 [nimg][H][W]
  *                 or NULL
  *   workspace     device, 256-byte aligned, sgm_workspace_size_win_batch()
- *                 bytes (pair i uses the i-th sgm_workspace_size() slice).
+ *                 bytes (pair i uses the i-th of nimg equal slices: the
+ *                 plan's workspace, then its window starts as bytes, which
+ *                 the aggregation reads instead of the int32 map).
  * Library-owned state: the horizontal directions are aggregated on a second
  * stream per device, created (non-blocking, default priority) on the first
  * call on that device and kept until the process ends; `stream` forks to it
@@ -341,7 +343,11 @@ sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, in
  * search of ndisp disparities: lo = clamp(floor(centre + 1/2) - w/2, 0,
  * ndisp - w), full pixel (x, y) reading coarse pixel (min(x/4, Wc-1),
  * min(y/4, Hc-1)).  A pixel is confident when logit > log(tau / (1 - tau))
- * (tau <= 0: every pixel, tau >= 1: none).  Optional outputs (NULL to
+ * (tau <= 0: every pixel, tau >= 1: none).  A pixel that is not confident
+ * falls back to the full range when its coarse match lies inside the right
+ * image, x - 4 coarse >= fallback_margin (float32; INT32_MIN: always);
+ * further left it sees a point outside the right camera's view, which no
+ * disparity range can match, and it keeps its window.  Optional outputs (NULL to
  * skip): fallback_mask uint8 [H][W] (1 = falls back); row_stats int32
  * [3][H]: per row the number of fallback pixels, the leftmost and the
  * rightmost fallback column (W and -1 for a row without any); nfallback
@@ -349,8 +355,8 @@ sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, in
  * coarse_disp and cnn_out are [Hc][Wc] and [Hc][Wc][2] float32. */
 sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_t coarse_width,
                           int32_t coarse_height, int32_t width, int32_t height, int32_t ndisp,
-                          int32_t w, float conf_threshold, int32_t *lo, uint8_t *fallback_mask,
-                          int32_t *row_stats, uint32_t *nfallback, void *stream);
+                          int32_t w, float conf_threshold, int32_t fallback_margin, int32_t *lo,
+                          uint8_t *fallback_mask, int32_t *row_stats, uint32_t *nfallback, void *stream);
 /* The same for nimg images at once: every buffer holds the images packed
  * one after another (coarse_disp [nimg][Hc][Wc], cnn_out [nimg][Hc][Wc][2],
  * lo and fallback_mask [nimg][H][W], row_stats [nimg][3][H], nfallback
@@ -358,8 +364,9 @@ sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_
 sgm_status sgm_window_map_batch(const float *coarse_disp, const float *cnn_out,
                                 int32_t coarse_width, int32_t coarse_height, int32_t width,
                                 int32_t height, int32_t ndisp, int32_t w, float conf_threshold,
-                                int32_t nimg, int32_t *lo, uint8_t *fallback_mask, int32_t *row_stats,
-                                uint32_t *nfallback, void *stream);
+                                int32_t fallback_margin, int32_t nimg, int32_t *lo,
+                                uint8_t *fallback_mask, int32_t *row_stats, uint32_t *nfallback,
+                                void *stream);
 /* The full-range fallback: the full-range SGM result of the rectangle rows
  * y0 .. y0+rows-1, columns x0 .. x0+cols-1 (band_int int16 / band_sub
  * float32, [rows][cols], band_sub may be NULL) replaces the windowed result
@@ -369,6 +376,19 @@ sgm_status sgm_fallback_merge(const uint8_t *fallback_mask, const int16_t *band_
                               const float *band_sub, int32_t width, int32_t height, int32_t y0,
                               int32_t rows, int32_t x0, int32_t cols, int16_t *disp_int,
                               float *disp_sub, void *stream);
+/* The same for every rectangle of a batch of nframes frames in one launch.
+ * rects: device int32 [nrects][6] = (frame, y0, rows, x0, cols, offset of
+ * the rectangle's first element in band_int / band_sub), each band
+ * [rows][cols] row-major; max_rows / max_cols bound every rectangle's rows
+ * and columns (the launch covers them; larger ones are clipped to them).
+ * fallback_mask, disp_int, disp_sub: [nframes][height][width]; band_len:
+ * elements of the band arrays.  Rectangles of one frame must not overlap
+ * (on shared pixels either result may land).  Entries outside the frames
+ * or the band arrays are skipped. */
+sgm_status sgm_fallback_merge_rects(const uint8_t *fallback_mask, const int32_t *rects, int32_t nrects,
+                                    int32_t max_rows, int32_t max_cols, int32_t width, int32_t height,
+                                    int32_t nframes, const int16_t *band_int, const float *band_sub,
+                                    int64_t band_len, int16_t *disp_int, float *disp_sub, void *stream);
 /* Training target at the coarse level: mean of each 4 x 4 block of a full-
  * resolution disparity map, divided by 4 (coarse pixels). */
 sgm_status sgm_label_downsample4(const float *label, int32_t width, int32_t height, float *coarse,

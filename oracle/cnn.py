@@ -153,12 +153,14 @@ def confidence_threshold(tau):
     return np.float32(np.log(tau / (1.0 - tau)))
 
 
-def window_map(coarse_disp, out, W, H, D, w, tau):
+def window_map(coarse_disp, out, W, H, D, w, tau, fallback_margin=None):
     """Per-pixel window start and fallback mask.  Each full-resolution pixel
     takes its coarse pixel (x // 4, y // 4, clamped to the coarse grid).
     Confident pixels centre the window on 4 * (coarse + offset), the others
-    on 4 * coarse and are marked for the full-range fallback;
-    lo = clamp(floor(centre + 1/2) - w/2, 0, D - w).
+    on 4 * coarse; lo = clamp(floor(centre + 1/2) - w/2, 0, D - w).  A
+    pixel that is not confident is marked for the full-range fallback when
+    fallback_margin is None, or else when its coarse match x - 4 * coarse
+    (float32) is at least fallback_margin.
     Returns (lo int32 [H, W], number of fallback pixels, mask uint8 [H, W])."""
     Hc, Wc = coarse_disp.shape
     ys = np.minimum(np.arange(H) // 4, Hc - 1)
@@ -170,7 +172,11 @@ def window_map(coarse_disp, out, W, H, D, w, tau):
     centre_c = np.where(conf, cd + off, cd).astype(np.float32)
     centre = np.float32(4.0) * centre_c
     lo = np.floor(centre + np.float32(0.5)).astype(np.int64) - w // 2
-    mask = (~conf).astype(np.uint8)
+    fb = ~conf
+    if fallback_margin is not None:
+        match = np.arange(W, dtype=np.float32)[None, :] - centre  # x - 4 coarse where not confident
+        fb &= match >= np.float32(fallback_margin)
+    mask = fb.astype(np.uint8)
     return np.clip(lo, 0, D - w).astype(np.int32), int(mask.sum()), mask
 
 

@@ -293,15 +293,20 @@ __global__ void k_clear_stats(int32_t *__restrict__ row_stats, int H, int W, uin
     if (nfallback && i == 0) *nfallback = 0u;
 }
 
-// One row of full-resolution pixels per grid row; block of 256 along x.
-// Fallback counts and column extents are reduced per wave (the lanes of a
-// wave hold 64 consecutive columns) before one atomic per wave.
+// One row of full-resolution pixels per grid row, four consecutive pixels
+// per thread (one 16-byte store of window starts and one 4-byte store of
+// fallback flags where the row offset allows).  The fallback count and
+// column extent of the row segment are reduced over the workgroup (wave
+// shuffles, then LDS) before one atomic per statistic.
+constexpr int kMapPix = 4;
+
 __global__ __launch_bounds__(256) void k_window_map(const float *__restrict__ coarse, const float *__restrict__ out,
                                                     int Wc, int Hc, int W, int H, int D, int w, float thr,
-                                                    int32_t *__restrict__ lo, uint8_t *__restrict__ mask,
+                                                    float fb_margin, int32_t *__restrict__ lo,
+                                                    uint8_t *__restrict__ mask,
                                                     int32_t *__restrict__ row_stats, uint32_t *__restrict__ nfallback)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * kMapPix, y = blockIdx.y;
     // image blockIdx.z of a stack: every buffer is packed per image
     {
         const size_t z = blockIdx.z;
@@ -312,28 +317,74 @@ __global__ __launch_bounds__(256) void k_window_map(const float *__restrict__ co
         if (row_stats) row_stats += z * 3 * H;
         if (nfallback) nfallback += z;
     }
-    bool fb = false;
-    if (x < W) {
-        const int cx = min(x / 4, Wc - 1), cy = min(y / 4, Hc - 1);
-        const size_t cp = (size_t)cy * Wc + cx;
-        const float cd = coarse[cp];
-        const bool conf = out[cp * kOutCh + 1] > thr;
-        const float centre = 4.0f * (conf ? __fadd_rn(cd, out[cp * kOutCh]) : cd);
-        int l = (int)floorf(__fadd_rn(centre, 0.5f)) - w / 2;
-        l = min(max(l, 0), D - w);
-        lo[(size_t)y * W + x] = l;
-        if (mask) mask[(size_t)y * W + x] = conf ? 0 : 1;
-        fb = !conf;
-    }
-    const unsigned long long bal = __ballot(fb);
-    if ((threadIdx.x & 63) == 0 && bal) {
-        const int xw = x;  // column of lane 0 of this wave
-        if (row_stats) {
-            atomicAdd(row_stats + y, (int)__popcll(bal));
-            atomicMin(row_stats + H + y, xw + (int)__ffsll((long long)bal) - 1);
-            atomicMax(row_stats + 2 * H + y, xw + 63 - (int)__clzll((long long)bal));
+    int cnt = 0, xmin = W, xmax = -1;
+    int32_t lv[kMapPix];
+    uint32_t mv = 0;
+    const int cy = min(y / 4, Hc - 1);
+#pragma unroll
+    for (int e = 0; e < kMapPix; ++e) {
+        const int x = x0 + e;
+        lv[e] = 0;
+        if (x < W) {
+            const int cx = min(x / 4, Wc - 1);
+            const size_t cp = (size_t)cy * Wc + cx;
+            const float cd = coarse[cp];
+            const bool conf = out[cp * kOutCh + 1] > thr;
+            const float centre = 4.0f * (conf ? __fadd_rn(cd, out[cp * kOutCh]) : cd);
+            int l = (int)floorf(__fadd_rn(centre, 0.5f)) - w / 2;
+            lv[e] = min(max(l, 0), D - w);
+            // a low-confidence pixel falls back to full range only while its
+            // coarse match lies inside the right image (x - 4 coarse >=
+            // margin); further left it sees a point outside the right
+            // camera's view, which no disparity range can match
+            if (!conf && __fsub_rn((float)x, 4.0f * cd) >= fb_margin) {
+                mv |= 1u << (8 * e);
+                ++cnt;
+                xmin = min(xmin, x);
+                xmax = max(xmax, x);
+            }
         }
-        if (nfallback) atomicAdd(nfallback, (uint32_t)__popcll(bal));
+    }
+    const size_t o = (size_t)y * W + x0;
+    if (x0 + kMapPix <= W && (o % kMapPix) == 0) {
+        *reinterpret_cast<int4 *>(lo + o) = make_int4(lv[0], lv[1], lv[2], lv[3]);
+        if (mask) *reinterpret_cast<uint32_t *>(mask + o) = mv;
+    } else {
+        for (int e = 0; e < kMapPix && x0 + e < W; ++e) {
+            lo[o + e] = lv[e];
+            if (mask) mask[o + e] = (uint8_t)((mv >> (8 * e)) & 1u);
+        }
+    }
+    if (!row_stats && !nfallback) return;
+    // the workgroup's fallback count and column extent
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        cnt += __shfl_xor(cnt, d);
+        xmin = min(xmin, __shfl_xor(xmin, d));
+        xmax = max(xmax, __shfl_xor(xmax, d));
+    }
+    __shared__ int s_st[3][4];
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_st[0][wv] = cnt;
+        s_st[1][wv] = xmin;
+        s_st[2][wv] = xmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            cnt += s_st[0][k];
+            xmin = min(xmin, s_st[1][k]);
+            xmax = max(xmax, s_st[2][k]);
+        }
+        if (cnt > 0) {
+            if (row_stats) {
+                atomicAdd(row_stats + y, cnt);
+                atomicMin(row_stats + H + y, xmin);
+                atomicMax(row_stats + 2 * H + y, xmax);
+            }
+            if (nfallback) atomicAdd(nfallback, (uint32_t)cnt);
+        }
     }
 }
 
@@ -346,6 +397,28 @@ __global__ void k_merge_fallback(const uint8_t *__restrict__ mask, const int16_t
     const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
     if (c >= cols || r >= rows) return;
     const size_t o = (size_t)(y0 + r) * W + x0 + c, b = (size_t)r * cols + c;
+    if (!mask[o]) return;
+    dint[o] = band_int[b];
+    if (dsub && band_sub) dsub[o] = band_sub[b];
+}
+
+// Every fallback rectangle of a batch in one launch: rectangle z (grid z)
+// = rects[6z .. 6z+5] = frame, y0, rows, x0, cols, offset of its first
+// element in the band arrays.  Rectangles, or pixels of them, outside the
+// frames or the band arrays are skipped (memory-safe for any table).
+__global__ void k_merge_fallback_rects(const uint8_t *__restrict__ mask, const int32_t *__restrict__ rects, int W,
+                                       int H, int nframes, const int16_t *__restrict__ band_int,
+                                       const float *__restrict__ band_sub, long long band_len,
+                                       int16_t *__restrict__ dint, float *__restrict__ dsub)
+{
+    const int32_t *R = rects + 6 * (size_t)blockIdx.z;
+    const int f = R[0], y0 = R[1], rows = R[2], x0 = R[3], cols = R[4];
+    const long long boff = R[5];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (c >= cols || r >= rows || f < 0 || f >= nframes || y0 < 0 || x0 < 0 || y0 + r >= H || x0 + c >= W) return;
+    const long long b = boff + (long long)r * cols + c;
+    if (boff < 0 || b >= band_len) return;
+    const size_t o = ((size_t)f * H + (size_t)(y0 + r)) * W + x0 + c;
     if (!mask[o]) return;
     dint[o] = band_int[b];
     if (dsub && band_sub) dsub[o] = band_sub[b];
@@ -520,8 +593,8 @@ sgm_status sgm_cnn_adam(float *params, float *m, float *v, const float *grad, in
 
 static sgm_status window_map_n(const float *coarse_disp, const float *cnn_out, int32_t coarse_width,
                                int32_t coarse_height, int32_t width, int32_t height, int32_t ndisp, int32_t w,
-                               float conf_threshold, int32_t nimg, int32_t *lo, uint8_t *fallback_mask,
-                               int32_t *row_stats, uint32_t *nfallback, void *stream)
+                               float conf_threshold, int32_t fallback_margin, int32_t nimg, int32_t *lo,
+                               uint8_t *fallback_mask, int32_t *row_stats, uint32_t *nfallback, void *stream)
 {
     if (!coarse_disp || !cnn_out || !lo) return cfail(SGM_ERR_INVALID, "NULL buffer");
     if (coarse_width < 1 || coarse_height < 1 || width < 1 || height < 1 || w < 1 || w > ndisp || ndisp > 256)
@@ -544,27 +617,28 @@ static sgm_status window_map_n(const float *coarse_disp, const float *cnn_out, i
     if (row_stats || nfallback)
         hipLaunchKernelGGL(k_clear_stats, dim3((height + 255) / 256, 1, nimg), dim3(256), 0, s, row_stats,
                            (int)height, (int)width, nfallback);
-    dim3 grid((width + 255) / 256, height, nimg), block(256);
+    dim3 grid((width + 256 * kMapPix - 1) / (256 * kMapPix), height, nimg), block(256);
     hipLaunchKernelGGL(k_window_map, grid, block, 0, s, coarse_disp, cnn_out, coarse_width, coarse_height, width,
-                       height, ndisp, w, thr, lo, fallback_mask, row_stats, nfallback);
+                       height, ndisp, w, thr, (float)fallback_margin, lo, fallback_mask, row_stats, nfallback);
     return launched("window map");
 }
 
 sgm_status sgm_window_map(const float *coarse_disp, const float *cnn_out, int32_t coarse_width, int32_t coarse_height,
-                          int32_t width, int32_t height, int32_t ndisp, int32_t w, float conf_threshold, int32_t *lo,
-                          uint8_t *fallback_mask, int32_t *row_stats, uint32_t *nfallback, void *stream)
+                          int32_t width, int32_t height, int32_t ndisp, int32_t w, float conf_threshold,
+                          int32_t fallback_margin, int32_t *lo, uint8_t *fallback_mask, int32_t *row_stats,
+                          uint32_t *nfallback, void *stream)
 {
-    return window_map_n(coarse_disp, cnn_out, coarse_width, coarse_height, width, height, ndisp, w, conf_threshold, 1,
-                        lo, fallback_mask, row_stats, nfallback, stream);
+    return window_map_n(coarse_disp, cnn_out, coarse_width, coarse_height, width, height, ndisp, w, conf_threshold,
+                        fallback_margin, 1, lo, fallback_mask, row_stats, nfallback, stream);
 }
 
 sgm_status sgm_window_map_batch(const float *coarse_disp, const float *cnn_out, int32_t coarse_width,
                                 int32_t coarse_height, int32_t width, int32_t height, int32_t ndisp, int32_t w,
-                                float conf_threshold, int32_t nimg, int32_t *lo, uint8_t *fallback_mask,
-                                int32_t *row_stats, uint32_t *nfallback, void *stream)
+                                float conf_threshold, int32_t fallback_margin, int32_t nimg, int32_t *lo,
+                                uint8_t *fallback_mask, int32_t *row_stats, uint32_t *nfallback, void *stream)
 {
     return window_map_n(coarse_disp, cnn_out, coarse_width, coarse_height, width, height, ndisp, w, conf_threshold,
-                        nimg, lo, fallback_mask, row_stats, nfallback, stream);
+                        fallback_margin, nimg, lo, fallback_mask, row_stats, nfallback, stream);
 }
 
 sgm_status sgm_fallback_merge(const uint8_t *fallback_mask, const int16_t *band_int, const float *band_sub,
@@ -582,6 +656,24 @@ sgm_status sgm_fallback_merge(const uint8_t *fallback_mask, const int16_t *band_
     hipLaunchKernelGGL(k_merge_fallback, grid, block, 0, (hipStream_t)stream, fallback_mask, band_int, band_sub,
                        width, y0, rows, x0, cols, disp_int, disp_sub);
     return launched("fallback merge");
+}
+
+sgm_status sgm_fallback_merge_rects(const uint8_t *fallback_mask, const int32_t *rects, int32_t nrects,
+                                    int32_t max_rows, int32_t max_cols, int32_t width, int32_t height,
+                                    int32_t nframes, const int16_t *band_int, const float *band_sub,
+                                    int64_t band_len, int16_t *disp_int, float *disp_sub, void *stream)
+{
+    if (!fallback_mask || !rects || !band_int || !disp_int) return cfail(SGM_ERR_INVALID, "NULL buffer");
+    if (width < 1 || height < 1 || nframes < 1 || nrects < 0 || max_rows < 0 || max_cols < 0 || band_len < 0)
+        return cfail(SGM_ERR_INVALID, "sizes must be >= 0 (frames >= 1)");
+    if (nrects == 0 || max_rows == 0 || max_cols == 0) return SGM_OK;
+    if (nrects > 65535 || max_rows > 65535) return cfail(SGM_ERR_UNSUPPORTED, "more than 65535 rectangles or rows");
+    if ((long long)width * height * nframes >= (1ll << 40)) return cfail(SGM_ERR_UNSUPPORTED, "frames too large");
+    dim3 grid((max_cols + 255) / 256, max_rows, nrects), block(256);
+    if (fault_take(kFaultLaunch)) return cfail(SGM_ERR_HIP, "injected launch failure");
+    hipLaunchKernelGGL(k_merge_fallback_rects, grid, block, 0, (hipStream_t)stream, fallback_mask, rects, width,
+                       height, nframes, band_int, band_sub, (long long)band_len, disp_int, disp_sub);
+    return launched("fallback merge of rectangles");
 }
 
 sgm_status sgm_label_downsample4(const float *label, int32_t width, int32_t height, float *coarse, void *stream)

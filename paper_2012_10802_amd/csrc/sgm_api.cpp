@@ -556,12 +556,22 @@ sgm_status sgm_match_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *ri
     return sgm_wta_win_paths(plan, base + plan->off_paths, lo, disp_int, disp_sub, stream);
 }
 
+}  // extern "C"
+
+namespace {
+// workspace slice of one pair in a windowed batch: the plan's workspace,
+// then the window starts as bytes
+size_t win_pair_bytes(const sgm_plan_s *p) { return p->ws_bytes + align256(p->n_pix); }
+}  // namespace
+
+extern "C" {
+
 sgm_status sgm_workspace_size_win_batch(sgm_plan_t plan, int32_t nimg, size_t *bytes)
 {
     if (sgm_status s = check_plan(plan)) return s;
     if (!bytes) return fail(SGM_ERR_INVALID, "bytes is NULL");
     if (nimg < 1) return fail(SGM_ERR_INVALID, "nimg must be >= 1 (got %d)", nimg);
-    *bytes = plan->ws_bytes * (size_t)nimg;
+    *bytes = win_pair_bytes(plan) * (size_t)nimg;
     return SGM_OK;
 }
 
@@ -579,9 +589,10 @@ sgm_status sgm_match_win_batch(sgm_plan_t plan, const uint8_t *left, const uint8
     if (image_stride < (int64_t)pitch * plan->pb.H)
         return fail(SGM_ERR_INVALID, "image_stride %lld < pitch * height", (long long)image_stride);
     if (!is_aligned(ws, 256)) return fail(SGM_ERR_INVALID, "workspace must be 256-byte aligned");
-    if (ws_bytes / (size_t)nimg < plan->ws_bytes)
+    const size_t pair_bytes = win_pair_bytes(plan);
+    if (ws_bytes / (size_t)nimg < pair_bytes)
         return fail(SGM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
-                    plan->ws_bytes * (size_t)nimg);
+                    pair_bytes * (size_t)nimg);
     uint8_t *base = static_cast<uint8_t *>(ws);
     size_t vs = 0;
     sgm_path_volumes(plan, nullptr, &vs, nullptr);
@@ -592,7 +603,8 @@ sgm_status sgm_match_win_batch(sgm_plan_t plan, const uint8_t *left, const uint8
     b.img_pair = (long long)image_stride;
     b.lo = lo;
     b.npairs = nimg;
-    b.ws_pair = plan->ws_bytes;
+    b.ws_pair = pair_bytes;
+    b.lo8 = base + plan->ws_bytes;
     b.codes_l = reinterpret_cast<uint64_t *>(base + plan->off_codes_l);
     b.codes_r = reinterpret_cast<uint64_t *>(base + plan->off_codes_r);
     b.cost = base + plan->off_cost;

@@ -116,7 +116,8 @@ struct WinPairs {
     long long img_pair;  // bytes between the images of consecutive pairs
     const int32_t *lo;   // [npairs][H][W]
     int npairs;
-    size_t ws_pair;
+    size_t ws_pair;      // bytes of workspace per pair
+    uint8_t *lo8;        // the pair's window starts as bytes (in its workspace slice)
     uint64_t *codes_l, *codes_r;
     uint8_t *cost, *paths;
     long long vstride;   // bytes between direction volumes

@@ -70,7 +70,8 @@ __device__ __forceinline__ int wave_max(int x)
 __global__ __launch_bounds__(64) void k_cost_win(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr,
                                                  const int32_t *__restrict__ lo, int W, int H, int w, int cmax,
                                                  uint8_t *__restrict__ cost, long long codes_pair,
-                                                 long long pix_pair, long long cost_pair)
+                                                 long long pix_pair, long long cost_pair,
+                                                 uint8_t *__restrict__ lo8)
 {
     __shared__ uint64_t s_cr[kWinTile + kWinReach];
     // pair blockIdx.z of a batch (strides 0 for one pair)
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(64) void k_cost_win(const uint64_t *__restrict__ cl
     cr += blockIdx.z * codes_pair;
     lo += blockIdx.z * pix_pair;
     cost += blockIdx.z * cost_pair;
+    if (lo8) lo8 += blockIdx.z * cost_pair;  // (in the pair's workspace slice)
     const int v = blockIdx.y, u0 = blockIdx.x * kWinTile;
     const int first = u0 - kWinReach;  // right column held in s_cr[0]
     const int u = u0 + threadIdx.x;
@@ -95,6 +97,9 @@ __global__ __launch_bounds__(64) void k_cost_win(const uint64_t *__restrict__ cl
         s_cr[col - first] = col < W ? cr[(size_t)v * W + col] : 0ull;
     __syncthreads();
     if (!act) return;
+    // byte copy of the window start for the batched aggregation (window
+    // starts are at most 256 - w)
+    if (lo8) lo8[pix] = (uint8_t)l;
     const uint64_t a = cl[pix];
     uint32_t word[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -367,9 +372,9 @@ constexpr int kW16Pad = 18;          // u16 index of value 0 in the lane's row
 
 struct Win16Params {
     const uint8_t *cost;
-    const int32_t *lo;
+    const uint8_t *lo;  // window starts, one byte per pixel
     uint8_t *out;
-    long long cost_pair, lo_pair, out_pair, vstride;  // bytes, elements, bytes, bytes
+    long long cost_pair, lo_pair, out_pair, vstride;  // bytes
     int W, H;
     uint32_t p1, p2;
     int np;
@@ -475,7 +480,7 @@ __device__ __forceinline__ void win16_scan(const Win16Params &a, __amdgpu_buffer
         const uint32_t px = pix0 + (uint32_t)i * pstep;
         const bool in = inside(i);
         ring_c[s] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rc, in ? px * 16u : kOff, 0, 0));
-        ring_l[s] = __builtin_amdgcn_raw_buffer_load_b32(rl, in ? px * 4u : kOff, 0, 0);
+        ring_l[s] = __builtin_amdgcn_raw_buffer_load_b8(rl, in ? px : kOff, 0, 0);
     }
     const uint32_t P1 = a.p1 | (a.p1 << 16), P2 = a.p2 | (a.p2 << 16);
     uint32_t L[8];
@@ -499,7 +504,7 @@ __device__ __forceinline__ void win16_scan(const Win16Params &a, __amdgpu_buffer
             const uint32_t px = pix0 + (uint32_t)ip * pstep;
             const bool in = inside(ip);
             ring_c[S] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rc, in ? px * 16u : kOff, 0, 0));
-            ring_l[S] = __builtin_amdgcn_raw_buffer_load_b32(rl, in ? px * 4u : kOff, 0, 0);
+            ring_l[S] = __builtin_amdgcn_raw_buffer_load_b8(rl, in ? px : kOff, 0, 0);
         }
         const int sh = (act && loq != kNoLo) ? lop - loq : 0;
         const v4u o4 = win16_update(L, m, c4, sh, P1, P2, row);
@@ -561,7 +566,7 @@ __global__ __launch_bounds__(64) void k_aggregate_win16_h(Win16Params a)
     const int W = a.W, H = a.H;
     const uint32_t npix = (uint32_t)W * (uint32_t)H;
     const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost + pr * a.cost_pair, npix * 16u);
-    const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.lo + pr * a.lo_pair, npix * 4u);
+    const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.lo + pr * a.lo_pair, npix);
     const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out + pr * a.out_pair + (size_t)vol * a.vstride, npix * 16u);
     const int R0 = g * 64;            // first row of this wave
     const int K = (W + kHT - 1) / kHT;  // tiles per row
@@ -577,7 +582,7 @@ __global__ __launch_bounds__(64) void k_aggregate_win16_h(Win16Params a)
     auto lo_off = [&](int k, int q) -> uint32_t {
         const int rr = 8 * q + crow, x = kHT * k + cu, y = R0 + rr;
         const bool in = ((uint32_t)y < (uint32_t)H) & ((uint32_t)x < (uint32_t)W);
-        return in ? ((uint32_t)y * (uint32_t)W + (uint32_t)x) * 4u : kOff;
+        return in ? (uint32_t)y * (uint32_t)W + (uint32_t)x : kOff;
     };
     v4u ring_c[kHRing][8];
     uint32_t ring_l[kHRing][8];
@@ -588,7 +593,7 @@ __global__ __launch_bounds__(64) void k_aggregate_win16_h(Win16Params a)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             ring_c[slot_][q] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rc, cost_off(k, q), 0, 0));
-            ring_l[slot_][q] = __builtin_amdgcn_raw_buffer_load_b32(rl, lo_off(k, q), 0, 0);
+            ring_l[slot_][q] = __builtin_amdgcn_raw_buffer_load_b8(rl, lo_off(k, q), 0, 0);
         }
     };
 #pragma unroll
@@ -667,7 +672,7 @@ __global__ __launch_bounds__(256, MINWG) void k_aggregate_win16(Win16Params a)
     const int pr = blockIdx.y;
     const uint32_t npix = (uint32_t)a.W * (uint32_t)a.H;
     const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cost + pr * a.cost_pair, npix * 16u);
-    const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.lo + pr * a.lo_pair, npix * 4u);
+    const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.lo + pr * a.lo_pair, npix);
     const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out + pr * a.out_pair + (size_t)vol * a.vstride, npix * 16u);
 #pragma unroll
     for (int q = 0; q < kW16Row; ++q) row[q] = kInf2;  // sentinel padding; values are written per use
@@ -697,7 +702,8 @@ hipError_t launch_cost_win(const Problem &pb, const uint64_t *cl, const uint64_t
                            uint8_t *cost, hipStream_t s)
 {
     dim3 grid((pb.W + kWinTile - 1) / kWinTile, pb.H), block(kWinTile);
-    hipLaunchKernelGGL(k_cost_win, grid, block, 0, s, cl, cr, lo, pb.W, pb.H, pb.w, pb.cmax, cost, 0ll, 0ll, 0ll);
+    hipLaunchKernelGGL(k_cost_win, grid, block, 0, s, cl, cr, lo, pb.W, pb.H, pb.w, pb.cmax, cost, 0ll, 0ll, 0ll,
+                       nullptr);
     return hipGetLastError();
 }
 
@@ -801,16 +807,16 @@ hipError_t launch_match_win_pairs(const Problem &pb, const WinPairs &b, hipStrea
     {
         dim3 grid((pb.W + kWinTile - 1) / kWinTile, pb.H, b.npairs), block(kWinTile);
         hipLaunchKernelGGL(k_cost_win, grid, block, 0, s, b.codes_l, b.codes_r, b.lo, pb.W, pb.H, pb.w, pb.cmax, b.cost,
-                           ws_words, npix, (long long)b.ws_pair);
+                           ws_words, npix, (long long)b.ws_pair, b.lo8);
     }
     // aggregation of every pair and direction in one launch
     {
         Win16Params p{};
         p.cost = b.cost;
-        p.lo = b.lo;
+        p.lo = b.lo8;
         p.out = b.paths;
         p.cost_pair = (long long)b.ws_pair;
-        p.lo_pair = npix;
+        p.lo_pair = (long long)b.ws_pair;
         p.out_pair = (long long)b.ws_pair;
         p.vstride = b.vstride;
         p.W = pb.W;

@@ -177,23 +177,27 @@ def label_downsample4(label, out=None, stream=None):
     return out
 
 
+ALWAYS_FALL_BACK = -2 ** 31  # fallback margin: every low-confidence pixel falls back
+
+
 def window_map(coarse_disp, out, W, H, ndisp, w, tau, lo=None, mask=None, row_stats=None,
-               nfallback=None, stream=None):
+               nfallback=None, fallback_margin=0, stream=None):
     Hc, Wc = coarse_disp.shape[-2:]
     if lo is None:
         lo = torch.empty((H, W), dtype=torch.int32, device=coarse_disp.device)
-    S._check(_lib.sgm_window_map(_c(coarse_disp), _c(out), Wc, Hc, W, H, ndisp, w, float(tau), _c(lo),
-                                 _c(mask), _c(row_stats), _c(nfallback), S._stream(stream)),
+    S._check(_lib.sgm_window_map(_c(coarse_disp), _c(out), Wc, Hc, W, H, ndisp, w, float(tau), int(fallback_margin),
+                                 _c(lo), _c(mask), _c(row_stats), _c(nfallback), S._stream(stream)),
              "sgm_window_map")
     return lo
 
 
-def window_map_batch(coarse_disp, out, W, H, ndisp, w, tau, lo, mask, row_stats, nfallback, stream=None):
+def window_map_batch(coarse_disp, out, W, H, ndisp, w, tau, lo, mask, row_stats, nfallback, fallback_margin=0,
+                     stream=None):
     """window_map for a stack of n images (every buffer packed per image)."""
     n, Hc, Wc = coarse_disp.shape
-    S._check(_lib.sgm_window_map_batch(_c(coarse_disp), _c(out), Wc, Hc, W, H, ndisp, w, float(tau), n, _c(lo),
-                                       _c(mask), _c(row_stats), _c(nfallback), S._stream(stream)),
-             "sgm_window_map_batch")
+    S._check(_lib.sgm_window_map_batch(_c(coarse_disp), _c(out), Wc, Hc, W, H, ndisp, w, float(tau),
+                                       int(fallback_margin), n, _c(lo), _c(mask), _c(row_stats), _c(nfallback),
+                                       S._stream(stream)), "sgm_window_map_batch")
     return lo
 
 
@@ -203,6 +207,17 @@ def fallback_merge(mask, band_int, band_sub, y0, x0, disp_int, disp_sub, stream=
     S._check(_lib.sgm_fallback_merge(_c(mask), _c(band_int), _c(band_sub), W, H, int(y0), int(rows), int(x0),
                                      int(cols), _c(disp_int), _c(disp_sub), S._stream(stream)),
              "sgm_fallback_merge")
+
+
+def fallback_merge_rects(mask, table, nrects, max_rows, max_cols, band_int, band_sub, disp_int, disp_sub,
+                         stream=None):
+    """Every rectangle of a batch in one launch: `table` int32 device
+    [>= nrects, 6] rows (frame, y0, rows, x0, cols, band offset); mask,
+    disp_int, disp_sub [n, H, W]; band_int / band_sub flat."""
+    n, H, W = disp_int.shape
+    S._check(_lib.sgm_fallback_merge_rects(_c(mask), _c(table), int(nrects), int(max_rows), int(max_cols), W, H, n,
+                                           _c(band_int), _c(band_sub), int(band_int.numel()), _c(disp_int),
+                                           _c(disp_sub), S._stream(stream)), "sgm_fallback_merge_rects")
 
 
 def fallback_rects(row_stats, W, ndisp, r, margin=32, full_fraction=0.5):
@@ -245,13 +260,16 @@ class LearnedWindowMatcher:
 
     def __init__(self, width, height, batch=1, ndisp=192, window=16, census=7, npaths=8, p1=10,
                  p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, fallback_streams=4, autotune=True,
-                 device="cuda"):
+                 fallback_margin=0, device="cuda"):
         if width % 4 or height % 4 or ndisp % 4:
             raise ValueError("width, height and ndisp must be multiples of 4")
         self.W, self.H, self.D, self.w, self.n = width, height, ndisp, window, batch
         self.Wc, self.Hc = width // 4, height // 4
         self.census, self.npaths, self.p1, self.p2 = census, npaths, p1, p2
         self.tau, self.margin, self.full_fraction = tau, margin, full_fraction
+        # low-confidence pixels fall back only while x - 4 coarse >= this
+        # (ALWAYS_FALL_BACK: all of them)
+        self.fallback_margin = int(fallback_margin)
         self.device = dev = torch.device(device)
         self.net = net if net is not None else WindowNet.load(DEFAULT_WEIGHTS, device=device)
         n, Hc, Wc = batch, self.Hc, self.Wc
@@ -271,7 +289,9 @@ class LearnedWindowMatcher:
         self.acts, self.out = self.net.buffers(Wc, Hc, n)
         fine_plan = S.sgm_plan(width, height, census, window, npaths, p1, p2)
         try:
-            fine_ws = int(S.sgm_workspace_size(fine_plan)) * n
+            nb = ctypes.c_size_t()
+            S._check(_lib.sgm_workspace_size_win_batch(fine_plan, n, ctypes.byref(nb)), "sgm_workspace_size_win_batch")
+            fine_ws = int(nb.value)
         finally:
             S.sgm_plan_free(fine_plan)
         self.fine_ws = torch.empty(fine_ws, dtype=torch.uint8, device=dev)  # every pair's slice
@@ -302,6 +322,11 @@ class LearnedWindowMatcher:
         self.fb_sub = torch.empty(n * height * width, dtype=torch.float32, device=dev)
         self.ev_maps = torch.cuda.Event()
         self.ev_fb = [torch.cuda.Event() for _ in range(nst)]
+        # the batch's rectangle table for the one-launch merge (pinned host
+        # copy uploaded on the main stream)
+        self.max_rects = 4096
+        self.rect_host = torch.zeros((self.max_rects, 6), dtype=torch.int32, pin_memory=True)
+        self.rect_dev = torch.zeros((self.max_rects, 6), dtype=torch.int32, device=dev)
         self._full = [{} for _ in range(nst)]
         self.last_rects = []
 
@@ -343,7 +368,7 @@ class LearnedWindowMatcher:
         self.net.forward(self.x0, self.acts, self.out, self.Wc, self.Hc, n, main)
         mark(3)
         window_map_batch(self.cds, self.out, self.W, self.H, self.D, self.w, self.tau, self.lo, self.mask,
-                         self.stats, self.nfallback, main)
+                         self.stats, self.nfallback, self.fallback_margin, main)
         mark(4)
         self.ev_maps.record(main)
         if self.w == 16:
@@ -386,8 +411,22 @@ class LearnedWindowMatcher:
             for st, ev in zip(self.fb_streams, self.ev_fb):
                 ev.record(st)
                 main.wait_event(ev)
-            for i, y0, x0, bi, bs in merges:
-                fallback_merge(self.mask[i], bi, bs, y0, x0, self.dint[i], self.dsub[i], main)
+            if len(merges) <= self.max_rects:
+                # one launch for every rectangle (bands of a frame never overlap)
+                tab = self.rect_host.numpy()
+                off = 0
+                for k, (i, y0, x0, bi, bs) in enumerate(merges):
+                    h, w = bi.shape
+                    tab[k] = (i, y0, h, x0, w, off)
+                    off += h * w
+                with torch.cuda.stream(main):
+                    self.rect_dev[:len(merges)].copy_(self.rect_host[:len(merges)], non_blocking=True)
+                fallback_merge_rects(self.mask, self.rect_dev, len(merges), max(b.shape[0] for _, _, _, b, _ in merges),
+                                     max(b.shape[1] for _, _, _, b, _ in merges), self.fb_int[:off],
+                                     self.fb_sub[:off], self.dint, self.dsub, main)
+            else:
+                for i, y0, x0, bi, bs in merges:
+                    fallback_merge(self.mask[i], bi, bs, y0, x0, self.dint[i], self.dsub[i], main)
         if events is not None:
             events[6].record(main)
 

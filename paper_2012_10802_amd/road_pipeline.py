@@ -48,7 +48,7 @@ class PerspectiveMatcher:
 
     def __init__(self, width, height, batch=1, ndisp=128, w=24, census=7, npaths=8, p1=10, p2=120,
                  windows="pixel", mode=0, delta_pt=0.0, delta_dt=0.0, min_disp=0.5, margin=4.0,
-                 coarse_tols=(1.0,), fine_tols=(2.0, 1.0), device=None):
+                 coarse_tols=(1.0,), fine_tols=(2.0, 1.0), autotune=True, device=None):
         if width % 4 or height % 4:
             raise ValueError("width and height must be multiples of 4")
         if windows not in ("pixel", "row"):
@@ -90,6 +90,17 @@ class PerspectiveMatcher:
             self.fine = S.Batch([dict(left=self.left_f[i], right=self.right_f[i], ndisp=self.w, d_lo=self.d_lo[i],
                                       disp_int=self.disp_int[i], disp_sub=self.disp_sub[i]) for i in range(n)],
                                 census=census, npaths=npaths, p1=p1, p2=p2, device=dev)
+        if autotune:
+            # launch shapes of the batched stages (lane mapping, waves per CU,
+            # queue order), timed once on these buffers
+            self.left_c.zero_()
+            self.right_c.zero_()
+            self.coarse.autotune()
+            if windows == "row":
+                self.left_f.zero_()
+                self.right_f.zero_()
+                self.d_lo.zero_()
+                self.fine.autotune()
 
     def _fit(self, disp, fits, tols, min_disp, margin, stream):
         S.road_fit(disp, None, min_disp, margin, fit=fits[0], workspace=self.ws, stream=stream)

@@ -96,9 +96,10 @@ def _load_library():
         "sgm_cnn_backward": [P, P, P, P, I, I, I, P, P, S, P],
         "sgm_cnn_adam": [P, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                          ctypes.c_float, P, P, P],
-        "sgm_window_map": [P, P, I, I, I, I, I, I, ctypes.c_float, P, P, P, P, P],
+        "sgm_window_map": [P, P, I, I, I, I, I, I, ctypes.c_float, I, P, P, P, P, P],
         "sgm_fallback_merge": [P, P, P, I, I, I, I, I, I, P, P, P],
-        "sgm_window_map_batch": [P, P, I, I, I, I, I, I, ctypes.c_float, I, P, P, P, P, P],
+        "sgm_fallback_merge_rects": [P, P, I, I, I, I, I, I, P, P, ctypes.c_int64, P, P, P],
+        "sgm_window_map_batch": [P, P, I, I, I, I, I, I, ctypes.c_float, I, I, P, P, P, P, P],
         "sgm_downsample4_batch": [P, I, I, I, ctypes.c_int64, I, P, P],
         "sgm_label_downsample4": [P, I, I, P, P],
         "sgm_batch_plan": [ctypes.POINTER(sgm_batch_params), ctypes.POINTER(sgm_pair), I,

@@ -306,6 +306,7 @@ hipError_t launch_match_win_pairs(const Problem &pb, const WinPairs &b, hipStrea
     touch_w(b.codes_l, last * b.ws_pair + npix(pb) * 8);
     touch_w(b.codes_r, last * b.ws_pair + npix(pb) * 8);
     touch_w(b.cost, last * b.ws_pair + vol(pb));
+    if (b.lo8) touch_w(b.lo8, last * b.ws_pair + npix(pb));
     touch_w(b.paths, last * b.ws_pair + (size_t)(pb.npaths - 1) * b.vstride + vol(pb));
     touch_w(b.dint, (size_t)b.npairs * npix(pb) * 2);
     if (b.dsub) touch_w(b.dsub, (size_t)b.npairs * npix(pb) * 4);

@@ -241,7 +241,8 @@ def test_window_batch_needs_width_16():
         assert rc == -2
         b = ctypes.c_size_t()
         assert lib.sgm_workspace_size_win_batch(plan, 3, ctypes.byref(b)) == 0
-        assert b.value == 3 * sgm.sgm_workspace_size(plan)
+        # each pair's slice: the plan's workspace, then its window starts as bytes
+        assert b.value == 3 * (sgm.sgm_workspace_size(plan) + (64 * 32 + 255) // 256 * 256)
         assert lib.sgm_workspace_size_win_batch(plan, 0, ctypes.byref(b)) == -1
     finally:
         sgm.sgm_plan_free(plan)
@@ -264,8 +265,8 @@ def test_cnn_and_window_calls_validate_before_launch():
     assert lib.sgm_cnn_backward(d, d, d, d, 8, 8, 1, d, d, 0, None) == -4  # scratch too small
     assert lib.sgm_cnn_adam(d, d, d, d, 0, f(1e-3), f(0.9), f(0.999), f(1e-8), d, d, None) == -1
     # window map: NaN threshold, window wider than the range
-    assert lib.sgm_window_map(d, d, 4, 4, 16, 16, 192, 16, f(float("nan")), d, None, None, None, None) == -1
-    assert lib.sgm_window_map(d, d, 4, 4, 16, 16, 8, 16, f(0.5), d, None, None, None, None) == -1
+    assert lib.sgm_window_map(d, d, 4, 4, 16, 16, 192, 16, f(float("nan")), 0, d, None, None, None, None) == -1
+    assert lib.sgm_window_map(d, d, 4, 4, 16, 16, 8, 16, f(0.5), 0, d, None, None, None, None) == -1
     # fallback merge: rectangle outside the frame, too many rows
     assert lib.sgm_fallback_merge(d, d, None, 100, 50, 40, 20, 0, 10, d, None, None) == -1
     assert lib.sgm_fallback_merge(d, d, None, 100, 50, 0, 10, 95, 10, d, None, None) == -1

@@ -253,23 +253,30 @@ def test_window_map_exact(lw):
     cd[0, :4] = [0.0, 47.9, 1.9, 2.125]  # clamps at both ends, a .5 tie
     out = rng.normal(0, 1.5, (1, Hc, Wc, CH)).astype(np.float32)
     out[0, 1, :3, 1] = 0.0  # logit exactly at the tau = 1/2 threshold: not confident
-    for tau in (0.0, 0.5, 0.8, 1.0):
-        nfb = torch.zeros(1, dtype=torch.int32, device="cuda")
-        stats = torch.full((3, H), 7, dtype=torch.int32, device="cuda")  # cleared by the call
-        mask = torch.empty((H, W), dtype=torch.uint8, device="cuda")
-        lo = lw.window_map(_dev(cd), _dev(np.ascontiguousarray(out[..., :2])), W, H, D, w, tau, mask=mask,
-                           row_stats=stats, nfallback=nfb)
-        torch.cuda.synchronize()
-        want, want_n, want_mask = ocnn.window_map(cd, out, W, H, D, w, tau)
-        np.testing.assert_array_equal(lo.cpu().numpy(), want, err_msg=str(tau))
-        np.testing.assert_array_equal(mask.cpu().numpy(), want_mask, err_msg=str(tau))
-        st = stats.cpu().numpy()
-        cols = np.arange(W)
-        np.testing.assert_array_equal(st[0], want_mask.sum(axis=1), err_msg=str(tau))
-        np.testing.assert_array_equal(st[1], np.where(want_mask > 0, cols, W).min(axis=1), err_msg=str(tau))
-        np.testing.assert_array_equal(st[2], np.where(want_mask > 0, cols, -1).max(axis=1), err_msg=str(tau))
-        assert int(nfb.item()) == want_n
-    assert want_n == H * W  # tau = 1: every pixel falls back
+    cd[2, 5] = 5.0  # coarse match exactly at x = 20 - 4 * 5 = 0 for the pixel (8, 20): on the margin-0 edge
+    for margin in (lw.ALWAYS_FALL_BACK, 0, 37):
+        for tau in (0.0, 0.5, 0.8, 1.0):
+            msg = f"tau {tau} margin {margin}"
+            nfb = torch.zeros(1, dtype=torch.int32, device="cuda")
+            stats = torch.full((3, H), 7, dtype=torch.int32, device="cuda")  # cleared by the call
+            mask = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+            lo = lw.window_map(_dev(cd), _dev(np.ascontiguousarray(out[..., :2])), W, H, D, w, tau, mask=mask,
+                               row_stats=stats, nfallback=nfb, fallback_margin=margin)
+            torch.cuda.synchronize()
+            want, want_n, want_mask = ocnn.window_map(cd, out, W, H, D, w, tau,
+                                                      None if margin == lw.ALWAYS_FALL_BACK else margin)
+            np.testing.assert_array_equal(lo.cpu().numpy(), want, err_msg=msg)
+            np.testing.assert_array_equal(mask.cpu().numpy(), want_mask, err_msg=msg)
+            st = stats.cpu().numpy()
+            cols = np.arange(W)
+            np.testing.assert_array_equal(st[0], want_mask.sum(axis=1), err_msg=msg)
+            np.testing.assert_array_equal(st[1], np.where(want_mask > 0, cols, W).min(axis=1), err_msg=msg)
+            np.testing.assert_array_equal(st[2], np.where(want_mask > 0, cols, -1).max(axis=1), err_msg=msg)
+            assert int(nfb.item()) == want_n
+            if tau == 1.0 and margin == lw.ALWAYS_FALL_BACK:
+                assert want_n == H * W  # every pixel falls back
+            if tau == 1.0 and margin == 0:
+                assert want_mask[8, 20] == 1 and 0 < want_n < H * W
 
 
 def test_fallback_merge(lw):
@@ -293,6 +300,38 @@ def test_fallback_merge(lw):
     want_i, want_s = ocnn.merge_fallback(wi, ws, mask, rects, res)
     np.testing.assert_array_equal(di.cpu().numpy(), want_i)
     np.testing.assert_array_equal(ds.cpu().numpy(), want_s)
+
+
+def test_fallback_merge_rects_one_launch(lw):
+    """Every rectangle of a two-frame batch merged by one launch equals the
+    rectangle-by-rectangle merge of the oracle (rectangles of one frame do
+    not overlap; a table row outside the frames is skipped)."""
+    import torch
+    rng = np.random.default_rng(13)
+    n, H, W = 2, 37, 300
+    wi = rng.integers(0, 50, (n, H, W)).astype(np.int16)
+    ws = rng.uniform(0, 50, (n, H, W)).astype(np.float32)
+    mask = (rng.random((n, H, W)) < 0.4).astype(np.uint8)
+    rects = [(0, (0, 9, 0, 300)), (0, (20, 37, 41, 250)), (1, (9, 20, 299, 300)), (1, (0, 5, 7, 19))]
+    res = [(rng.integers(100, 190, (b - a, x1 - x0)).astype(np.int16),
+            rng.uniform(100, 190, (b - a, x1 - x0)).astype(np.float32)) for _, (a, b, x0, x1) in rects]
+    table, off = [], 0
+    for (f, (a, b, x0, x1)), (bi, _) in zip(rects, res):
+        table.append((f, a, b - a, x0, x1 - x0, off))
+        off += bi.size
+    table.append((5, 0, 4, 0, 4, 0))  # frame outside the batch: skipped
+    band_i = np.concatenate([bi.ravel() for bi, _ in res])
+    band_s = np.concatenate([bs.ravel() for _, bs in res])
+    di, ds = _dev(wi), _dev(ws)
+    tab = _dev(np.array(table, np.int32))
+    bid, bsd, md = _dev(band_i), _dev(band_s), _dev(mask)
+    lw.fallback_merge_rects(md, tab, len(table), 17, 300, bid, bsd, di, ds)
+    torch.cuda.synchronize()
+    for f in range(n):
+        sel = [k for k, (g, _) in enumerate(rects) if g == f]
+        want_i, want_s = ocnn.merge_fallback(wi[f], ws[f], mask[f], [rects[k][1] for k in sel], [res[k] for k in sel])
+        np.testing.assert_array_equal(di[f].cpu().numpy(), want_i)
+        np.testing.assert_array_equal(ds[f].cpu().numpy(), want_s)
 
 
 def test_training_resume_is_bitwise(lw, tmp_path):
@@ -375,7 +414,7 @@ def test_learned_window_pipeline_stepwise(lw, fallback):
         want_out = want_out[..., :2]
         gout = m.out[i:i + 1].cpu().numpy()
         assert np.abs(gout - want_out).max() <= 0.02 * np.abs(want_out).max() + 1e-6
-        want_lo, want_n, want_mask = ocnn.window_map(gcs, gout, W, H, D, w, tau)
+        want_lo, want_n, want_mask = ocnn.window_map(gcs, gout, W, H, D, w, tau, m.fallback_margin)
         np.testing.assert_array_equal(m.lo[i].cpu().numpy(), want_lo)
         np.testing.assert_array_equal(m.mask[i].cpu().numpy(), want_mask)
         nfb_total += want_n
@@ -456,7 +495,7 @@ def test_learned_window_full_size_batch16(lw):
         want_out = want_out[..., :2]
         gout = m.out[i:i + 1].cpu().numpy()
         assert np.abs(gout - want_out).max() <= 0.02 * np.abs(want_out).max()
-        want_lo, _, want_mask = ocnn.window_map(gcs, gout, W, H, D, w, m.tau)
+        want_lo, _, want_mask = ocnn.window_map(gcs, gout, W, H, D, w, m.tau, m.fallback_margin)
         np.testing.assert_array_equal(m.lo[i].cpu().numpy(), want_lo)
         rects = ocnn.fallback_rects(want_mask, m.margin, m.full_fraction, D, 3)
         assert m.last_rects[i] == rects

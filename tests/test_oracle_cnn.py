@@ -83,6 +83,27 @@ def test_window_map_fallback_and_clamps():
     assert cnn.window_map(coarse, out, 8, 8, 192, 16, 0.0)[1] == 0
 
 
+def test_window_map_fallback_margin_by_hand():
+    # one coarse pixel, not confident, 4 x 4 full pixels at x = 0..3
+    # (and a copy at x = 4..7 through the clamp to the last coarse column)
+    out = np.zeros((1, 1, 1, cnn.CH), np.float32)
+    out[0, 0, 0, 1] = -1.0
+    coarse = np.array([[0.5]], np.float32)  # match x - 2: left of the image for x < 2
+    _, n_all, _ = cnn.window_map(coarse, out, 8, 4, 64, 16, 0.5)
+    assert n_all == 32
+    _, n0, m0 = cnn.window_map(coarse, out, 8, 4, 64, 16, 0.5, 0)
+    assert n0 == 4 * 6 and not m0[:, :2].any() and m0[:, 2:].all()  # x - 2 >= 0 from x = 2 on
+    _, n5, m5 = cnn.window_map(coarse, out, 8, 4, 64, 16, 0.5, 5)
+    assert n5 == 4 * 1 and m5[:, 7].all()                             # only x = 7 has x - 2 >= 5
+    _, nneg, _ = cnn.window_map(coarse, out, 8, 4, 64, 16, 0.5, -2)
+    assert nneg == 32                                                  # x - 2 >= -2 everywhere
+    # the margin never touches confident pixels or the window starts
+    out[0, 0, 0, 1] = 1.0
+    lo_a, n_a, _ = cnn.window_map(coarse, out, 8, 4, 64, 16, 0.5)
+    lo_b, n_b, _ = cnn.window_map(coarse, out, 8, 4, 64, 16, 0.5, 0)
+    assert n_a == n_b == 0 and (lo_a == lo_b).all()
+
+
 def test_confidence_threshold_is_the_logit():
     for tau in (0.1, 0.5, 0.73, 0.99):
         t = float(cnn.confidence_threshold(tau))
