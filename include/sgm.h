@@ -326,6 +326,11 @@ sgm_status sgm_cnn_prepare_input(const float *coarse_disp, const uint8_t *coarse
                                  int32_t height, int32_t nimg, uint16_t *x0, void *stream);
 sgm_status sgm_cnn_forward(const uint16_t *wf, const float *params, const uint16_t *x0, int32_t width,
                            int32_t height, int32_t nimg, uint16_t *acts, float *out, void *stream);
+/* Inference form of sgm_cnn_forward: the same out, bit for bit, from one
+ * launch that keeps the hidden activations on chip (no acts buffer; x0
+ * and wf 8-byte aligned; at most 65535 images). */
+sgm_status sgm_cnn_infer(const uint16_t *wf, const float *params, const uint16_t *x0, int32_t width,
+                         int32_t height, int32_t nimg, float *out, void *stream);
 /* Loss = mean over pixels of Huber(offset - (label - coarse)) + logistic
  * loss of the logit against [|offset - (label - coarse)| < 1]; writes dy
  * and adds the two loss terms to loss_sum[0..1] (may be NULL). */

@@ -139,6 +139,145 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ x, co
 }
 
 // ---------------------------------------------------------------------------
+// inference: all four layers for one output tile in one workgroup
+//
+// The tile's input with a halo of 4 pixels (one per layer) sits in LDS as
+// bfloat16 [row][column][16]; each layer reads one LDS buffer and writes the
+// other, shrinking the computed region by one pixel per side, so hidden
+// activations never reach HBM.  A layer's output outside the image is
+// written as 0 (the next layer's zero padding).  Positions beyond a
+// layer's computed region are never read by a position inside the next
+// layer's region, so their contents do not matter.
+//
+// The MFMA runs transposed with respect to k_conv (weights as the A
+// operand, pixels as B): D[co][pixel], so each lane ends with 4 channels of
+// one pixel, which is one 8-byte LDS write in the layout the next layer
+// reads.  The products and their order over the 16 input channels of each
+// tap are those of k_conv, and the taps accumulate in the same order, so the
+// result equals the layer-by-layer forward bit for bit.  A wave runs two
+// items' MFMA chains interleaved and loads the next two items' operands from
+// LDS before them.
+
+constexpr int kFTW = 24;           // output tile columns
+constexpr int kFTH = 16;           // output tile rows
+constexpr int kFR = kFTH + 8;      // tile rows with the halo
+constexpr int kFCP = 40;           // tile columns with the halo (32) and slack for the last strip's reads
+constexpr int kFPix = kFR * kFCP;  // pixels per LDS buffer
+
+// LDS entry of channels 4q .. 4q+3 of tile pixel p: the four 8-byte groups
+// of pixels with bit 3 set are stored in the order 2, 3, 0, 1, so that the
+// 16 consecutive pixels x 2 groups of a half-wave's access fall on 32
+// distinct bank pairs
+__device__ __forceinline__ int fslot(int p, int q) { return p * 4 + (q ^ ((p >> 2) & 2)); }
+
+__global__ __launch_bounds__(256) void k_cnn_infer(const uint16_t *__restrict__ x0, const uint16_t *__restrict__ wf,
+                                                   const float *__restrict__ params, int W, int H,
+                                                   float *__restrict__ out)
+{
+    __shared__ uint2 buf[2][kFPix * 4];  // 4 channels (8 bytes) per entry
+    const int X0 = (int)blockIdx.x * kFTW - 4, Y0 = (int)blockIdx.y * kFTH - 4;
+    const size_t img = (size_t)blockIdx.z * H;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform: item loops without exec masks
+    const int i = lane & 15, g = lane >> 4;
+    // every global load of the launch is issued before the first wait: the
+    // input tile, then all four layers' weight operands and biases
+    constexpr int kLoads = kFPix * 4 / 256;
+    static_assert(kFPix * 4 % 256 == 0, "tile loads must split evenly over 256 threads");
+    uint2 tile[kLoads];
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+        const int q = (int)threadIdx.x + 256 * k;
+        const int px = q >> 2, part = q & 3;
+        const int r = px / kFCP, c = px - r * kFCP;
+        const int yy = Y0 + r, xx = X0 + c;
+        tile[k] = make_uint2(0u, 0u);
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+            tile[k] = *reinterpret_cast<const uint2 *>(x0 + ((img + yy) * W + xx) * CH + 4 * part);
+    }
+    v4s wt[LAYERS][9];
+    float bias[LAYERS][4];
+#pragma unroll
+    for (int l = 0; l < LAYERS; ++l) {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) wt[l][t] = load4(wf + ((size_t)l * 9 + t) * CH * CH + (size_t)i * CH + 4 * g);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bias[l][e] = params[(size_t)l * PER_LAYER + 9 * CH * CH + 4 * g + e];
+    }
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+        const int q = (int)threadIdx.x + 256 * k;
+        buf[0][fslot(q >> 2, q & 3)] = tile[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < LAYERS; ++l) {
+        const uint2 *in = buf[l & 1];
+        uint2 *ob = buf[(l + 1) & 1];
+        // layer l computes rows [l + 1, kFR - l - 1) and columns
+        // [l + 1, l + 33) of the tile: two strips of 16 pixels per row
+        const int h = l + 1;
+        const int nitems = 2 * (kFR - 2 * h);
+        auto load_item = [&](int it, v4s(&a)[9]) __attribute__((always_inline)) {
+            const int r = h + (it >> 1), c0 = h + 16 * (it & 1);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const uint2 v = in[fslot((r + t / 3 - 1) * kFCP + c0 + i + t % 3 - 1, g)];
+                a[t] = __builtin_bit_cast(v4s, v);
+            }
+        };
+        // items it and it + 4 together: two independent MFMA chains
+        auto compute = [&](int it, const v4s(&a)[9], const v4s(&b)[9]) __attribute__((always_inline)) {
+            v4f acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[l][t], a[t], acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[l][t], b[t], acc[1], 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int iu = it + 4 * u;
+                if (iu >= nitems) break;
+                const int r = h + (iu >> 1), c = h + 16 * (iu & 1) + i;
+                const int yy = Y0 + r, xx = X0 + c;
+                // acc[u][e]: channel 4g + e of pixel (r, c)
+                if (l < LAYERS - 1) {
+                    const uint32_t inside = ((unsigned)yy < (unsigned)H) & ((unsigned)xx < (unsigned)W);
+                    const uint32_t keep = 0u - inside;
+                    uint32_t v[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = f2bf(fmaxf(acc[u][e] + bias[l][e], 0.0f));
+                    ob[fslot(r * kFCP + c, g)] =
+                        make_uint2((v[0] | (v[1] << 16)) & keep, (v[2] | (v[3] << 16)) & keep);
+                } else if (g == 0 && c < 4 + kFTW && yy < H && xx < W) {
+                    *reinterpret_cast<float2 *>(out + ((img + yy) * W + xx) * kOutCh) =
+                        make_float2(acc[u][0] + bias[l][0], acc[u][1] + bias[l][1]);
+                }
+            }
+        };
+        // a wave's items: wave, wave + 4, ...; pairs of them, the next pair's
+        // operands loaded from LDS before the current pair's MFMAs
+        v4s p0[2][9], p1[2][9];
+        auto load_pair = [&](int it, v4s(&p)[2][9]) __attribute__((always_inline)) {
+            if (it < nitems) load_item(it, p[0]);
+            if (it + 4 < nitems) load_item(it + 4, p[1]);
+        };
+        int it = wave;
+        load_pair(it, p0);
+        while (it < nitems) {
+            load_pair(it + 8, p1);
+            compute(it, p0[0], p0[1]);
+            it += 8;
+            if (it >= nitems) break;
+            load_pair(it + 8, p0);
+            compute(it, p1[0], p1[1]);
+            it += 8;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // weight gradient: per tap D[co][ci] = sum_p dy[p][co] x[p + offset][ci]
 
 __global__ __launch_bounds__(64) void k_wgrad(const uint16_t *__restrict__ x, const uint16_t *__restrict__ dy, int W,
@@ -526,6 +665,19 @@ sgm_status sgm_cnn_forward(const uint16_t *wf, const float *params, const uint16
         }
     }
     return launched("cnn forward");
+}
+
+sgm_status sgm_cnn_infer(const uint16_t *wf, const float *params, const uint16_t *x0, int32_t width, int32_t height,
+                         int32_t nimg, float *out, void *stream)
+{
+    if (!wf || !params || !x0 || !out) return cfail(SGM_ERR_INVALID, "NULL buffer");
+    if (sgm_status st = check_images(width, height, nimg)) return st;
+    if (!aligned(x0, 8) || !aligned(wf, 8)) return cfail(SGM_ERR_INVALID, "misaligned buffer");
+    if (nimg > 65535) return cfail(SGM_ERR_UNSUPPORTED, "more than 65535 images");
+    if (fault_take(kFaultLaunch)) return cfail(SGM_ERR_HIP, "injected launch failure");
+    dim3 grid((width + kFTW - 1) / kFTW, (height + kFTH - 1) / kFTH, nimg), block(256);
+    hipLaunchKernelGGL(k_cnn_infer, grid, block, 0, (hipStream_t)stream, x0, wf, params, width, height, out);
+    return launched("cnn inference");
 }
 
 sgm_status sgm_cnn_loss(const float *out, const float *coarse_disp, const float *label, int32_t width, int32_t height,

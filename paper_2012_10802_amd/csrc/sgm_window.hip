@@ -398,38 +398,46 @@ __device__ __forceinline__ uint32_t funnel16(uint32_t hi, uint32_t lo) { return 
 __device__ __forceinline__ v4u win16_update(uint32_t (&L)[8], uint32_t &m, const v4u c4, const int sh,
                                             const uint32_t P1, const uint32_t P2, uint32_t *row)
 {
-    // predecessor values at window indices j - 1, j, j + 1 of p's window:
-    // V[j] = L[j + sh - 1] for j = 0..17 (sentinel outside q's window),
-    // held as 9 packed pairs; Pm = V[0..15], P0 = V[1..16], Pp = V[2..17]
+    // predecessor values at window indices j - 1, j, j + 1 of p's window,
+    // V(j) = Lq(j + sh) (sentinel outside q's window), as packed pairs:
+    // Pm[k] = (V(2k-1), V(2k)), P0[k] = (V(2k), V(2k+1)), Pp[k] = (V(2k+1), V(2k+2))
     auto Ld = [&](int q) -> uint32_t { return (q >= 0 && q < 8) ? L[q] : kInf2; };
-    uint32_t V[9];
+    uint32_t Pm[8], P0[8], Pp[8];
+    {
+        // sh = 0: P0 is L itself, Pm and Pp are L moved by half a pair
+        uint32_t F[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) V[q] = funnel16(Ld(q), Ld(q - 1));  // sh = 0
-    if (__ballot(sh != 0) != 0) {
-        if (__ballot(sh < -1 || sh > 1) != 0) {
-            // any shift: through the lane's LDS row
+        for (int q = 0; q < 9; ++q) F[q] = funnel16(Ld(q), Ld(q - 1));
 #pragma unroll
-            for (int k = 0; k < 8; ++k) row[kW16Pad / 2 + k] = L[k];
-            const int e = min(max(sh - 1, -kW16Pad), 16);
-            const int b = e & 1;
-            const int base = (kW16Pad + e - b) >> 1;  // dword of V[0] (or of V[-1] when e is odd)
-            uint32_t D[10];
-#pragma unroll
-            for (int q = 0; q < 10; ++q) D[q] = row[base + q];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) V[q] = b ? funnel16(D[q + 1], D[q]) : D[q];
-        } else {
-            // shifts of one: whole registers move
-#pragma unroll
-            for (int q = 0; q < 9; ++q) V[q] = sh == 1 ? Ld(q) : (sh == -1 ? Ld(q - 1) : V[q]);
+        for (int k = 0; k < 8; ++k) {
+            Pm[k] = F[k];
+            P0[k] = L[k];
+            Pp[k] = F[k + 1];
         }
     }
-    uint32_t Pm[8], P0[8], Pp[8];
+    if (__ballot(sh != 0) != 0) {
+        // any lane re-indexes: every lane goes through its LDS row, where
+        // q's 16 values sit between sentinels (lanes with sh = 0 read them
+        // back unmoved).  Value V(j - 1) = Lq(j + e), e = sh - 1, starts
+        // at u16 index kW16Pad + e of the row: dword `base`, half e & 1,
+        // taken with a per-lane funnel shift of 0 or 16 bits.
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        Pm[k] = V[k];
-        P0[k] = funnel16(V[k + 1], V[k]);
-        Pp[k] = V[k + 1];
+        for (int k = 0; k < 8; ++k) row[kW16Pad / 2 + k] = L[k];
+        const int e = min(max(sh - 1, -kW16Pad), 16);
+        const int base = (kW16Pad + e) >> 1;
+        const uint32_t half = (uint32_t)(e & 1) << 4;
+        uint32_t D[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) D[q] = row[base + q];
+        uint32_t V[9];  // V[q] = (V(2q-1), V(2q))
+#pragma unroll
+        for (int q = 0; q < 9; ++q) V[q] = __builtin_amdgcn_alignbit(D[q + 1], D[q], half);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            Pm[k] = V[k];
+            P0[k] = funnel16(V[k + 1], V[k]);
+            Pp[k] = V[k + 1];
+        }
     }
     // C + min(V(j), V(j+-1) + P1, m_q + P2) - m_q = C + min(t - m_q, P2) with
     // t = min(V(j), V(j+-1) + P1) >= m_q (sentinels included), so m_q enters

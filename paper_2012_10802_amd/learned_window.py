@@ -112,6 +112,12 @@ class WindowNet:
                                       S._stream(stream)), "sgm_cnn_forward")
         return out
 
+    def infer(self, x0, out, W, H, n, stream=None):
+        """forward without hidden activations (one launch; same out)"""
+        S._check(_lib.sgm_cnn_infer(_c(self.wf), _c(self.params), _c(x0), W, H, n, _c(out), S._stream(stream)),
+                 "sgm_cnn_infer")
+        return out
+
     def train_buffers(self, W, H, n):
         acts, out = self.buffers(W, H, n)
         dy = torch.empty((n, H, W, CH), dtype=torch.int16, device=self.device)
@@ -286,7 +292,7 @@ class LearnedWindowMatcher:
             self.cr.zero_()
             self.coarse.autotune()
         self.x0 = torch.empty((n, Hc, Wc, CH), dtype=torch.int16, device=dev)
-        self.acts, self.out = self.net.buffers(Wc, Hc, n)
+        self.out = torch.empty((n, Hc, Wc, OUT_CH), dtype=torch.float32, device=dev)
         fine_plan = S.sgm_plan(width, height, census, window, npaths, p1, p2)
         try:
             nb = ctypes.c_size_t()
@@ -365,7 +371,7 @@ class LearnedWindowMatcher:
         self.coarse.run(main)
         mark(2)
         prepare_input(self.cds, self.cl, self.Wc, self.Hc, n, self.x0, main)
-        self.net.forward(self.x0, self.acts, self.out, self.Wc, self.Hc, n, main)
+        self.net.infer(self.x0, self.out, self.Wc, self.Hc, n, main)
         mark(3)
         window_map_batch(self.cds, self.out, self.W, self.H, self.D, self.w, self.tau, self.lo, self.mask,
                          self.stats, self.nfallback, self.fallback_margin, main)

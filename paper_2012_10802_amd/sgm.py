@@ -92,6 +92,7 @@ def _load_library():
         "sgm_cnn_pack_weights": [P, P, P, P],
         "sgm_cnn_prepare_input": [P, P, I, I, I, P, P],
         "sgm_cnn_forward": [P, P, P, I, I, I, P, P, P],
+        "sgm_cnn_infer": [P, P, P, I, I, I, P, P],
         "sgm_cnn_loss": [P, P, P, I, I, I, P, P, P],
         "sgm_cnn_backward": [P, P, P, P, I, I, I, P, P, S, P],
         "sgm_cnn_adam": [P, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,

@@ -260,6 +260,9 @@ def test_cnn_and_window_calls_validate_before_launch():
     # sizes
     assert lib.sgm_cnn_forward(d, d, d, 0, 8, 1, d, d, None) == -1
     assert lib.sgm_cnn_forward(d, d, d, 1 << 16, 1 << 12, 1, d, d, None) == -2
+    assert lib.sgm_cnn_infer(d, d, d, 0, 8, 1, d, None) == -1
+    assert lib.sgm_cnn_infer(d, d, d, 8, 8, 1 << 16, d, None) == -2
+    assert lib.sgm_cnn_infer(d, d, ctypes.c_void_p(258), 8, 8, 1, d, None) == -1  # x0 misaligned
     assert lib.sgm_cnn_prepare_input(d, d, 8, 8, 0, d, None) == -1
     assert lib.sgm_cnn_loss(d, d, d, 8, -1, 1, d, None, None) == -1
     assert lib.sgm_cnn_backward(d, d, d, d, 8, 8, 1, d, d, 0, None) == -4  # scratch too small

@@ -109,6 +109,26 @@ def test_forward_layerwise(lw, shape):
             assert np.all(err <= tol[..., :2]), "output max err %g" % err.max()
 
 
+@pytest.mark.parametrize("shape", SHAPES + [(3, 40, 61), (16, 270, 480)], ids=lambda s: "x".join(map(str, s)))
+def test_infer_equals_layer_by_layer_forward(lw, shape):
+    """The one-launch inference (activations kept in LDS, tiles of 24 x 16
+    with a 4-pixel halo) gives the layer-by-layer forward's output bit for
+    bit: tiles in both directions, ragged right and bottom tiles, image
+    borders inside tiles, several images."""
+    import torch
+    n, H, W = shape
+    params = _params(n + H + W)
+    x0 = _input(n, H, W, H)
+    net = lw.WindowNet(params)
+    acts, out = net.buffers(W, H, n)
+    xd = _to_bf16_dev(x0)
+    net.forward(xd, acts, out, W, H, n)
+    out2 = torch.full_like(out, float("nan"))
+    net.infer(xd, out2, W, H, n)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+
+
 def test_forward_end_to_end_matches_oracle(lw):
     import torch
     n, H, W = 2, 11, 45
