@@ -323,7 +323,7 @@ def learned_vs_plain(args, log=None):
     plain = sgm.Batch([dict(left=L[i], right=Rt[i], ndisp=D) for i in range(B)], census=n_cen, npaths=R,
                       p1=p1, p2=p2, device=dev)
     lw = LW.LearnedWindowMatcher(W, H, batch=B, ndisp=D, window=16, census=n_cen, npaths=R, p1=p1, p2=p2,
-                                 net=net, tau=args.tau, device=dev)
+                                 net=net, tau=args.tau, fallback_margin=args.fallback_margin, device=dev)
     stream = torch.cuda.Stream()
     uu = torch.arange(W, device=dev)[None, :]
     tot = {"pix": 0, "bad_plain": 0, "bad_learned": 0, "miss": 0, "conf_pix": 0, "fallback": 0,
@@ -456,6 +456,7 @@ def learned_vs_plain(args, log=None):
         "stages_ms": stage_ms,
         "stage_roofline": stage_roof,
         "tau": args.tau,
+        "fallback_margin": args.fallback_margin,
         "window": 16,
         "pixels_scored": tot["pix"],
         "timing": "HIP events on the stream around each batch (the learned form includes the stream's wait "
@@ -873,6 +874,9 @@ def main():
                     help="skip the learned-window vs plain comparison")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2012_10802_amd", "window_cnn.npz"))
     ap.add_argument("--tau", type=float, default=0.5, help="confidence threshold of the learned windows")
+    ap.add_argument("--fallback-margin", type=int, default=8,
+                    help="low-confidence pixels fall back to full range only where x - 4 * coarse disparity is at "
+                         "least this (-2147483648: all of them)")
     ap.add_argument("--eval-pairs", type=int, default=64)
     ap.add_argument("--lw-reps", type=int, default=3)
     ap.add_argument("--learned-only", action="store_true", help="print only the learned-window comparison")

@@ -266,15 +266,17 @@ class LearnedWindowMatcher:
 
     def __init__(self, width, height, batch=1, ndisp=192, window=16, census=7, npaths=8, p1=10,
                  p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, fallback_streams=4, autotune=True,
-                 fallback_margin=0, device="cuda"):
+                 fallback_margin=8, device="cuda"):
         if width % 4 or height % 4 or ndisp % 4:
             raise ValueError("width, height and ndisp must be multiples of 4")
         self.W, self.H, self.D, self.w, self.n = width, height, ndisp, window, batch
         self.Wc, self.Hc = width // 4, height // 4
         self.census, self.npaths, self.p1, self.p2 = census, npaths, p1, p2
         self.tau, self.margin, self.full_fraction = tau, margin, full_fraction
-        # low-confidence pixels fall back only while x - 4 coarse >= this
-        # (ALWAYS_FALL_BACK: all of them)
+        # low-confidence pixels fall back only while x - 4 coarse >= this:
+        # by default, unless the coarse match lies within two coarse pixels
+        # of the left image edge, where the scene point is taken as outside
+        # the right camera's view (ALWAYS_FALL_BACK: every one of them)
         self.fallback_margin = int(fallback_margin)
         self.device = dev = torch.device(device)
         self.net = net if net is not None else WindowNet.load(DEFAULT_WEIGHTS, device=device)

@@ -449,14 +449,15 @@ def test_learned_window_pipeline_stepwise(lw, fallback):
 
 
 def test_full_fallback_is_plain_sgm(lw):
-    """tau = 1: no pixel is confident, and the learned-window form returns
-    plain full-range SGM of each frame, exactly."""
+    """tau = 1 with every low-confidence pixel sent to the fallback: the
+    learned-window form returns plain full-range SGM of each frame, exactly."""
     import torch
     from paper_2012_10802_amd import sgm as S
     ps, L, R = _road_pairs("road320", [5, 6])
     n, H, W = L.shape
     D = 64
-    m = lw.LearnedWindowMatcher(W, H, batch=n, ndisp=D, window=16, net=lw.WindowNet(_params(2)), tau=1.0)
+    m = lw.LearnedWindowMatcher(W, H, batch=n, ndisp=D, window=16, net=lw.WindowNet(_params(2)), tau=1.0,
+                                fallback_margin=lw.ALWAYS_FALL_BACK)
     Ld, Rd = _dev(L), _dev(R)
     dint, dsub = m.match(Ld, Rd)
     plain = S.Matcher(W, H, census=7, ndisp=D, npaths=8, p1=10, p2=120)
