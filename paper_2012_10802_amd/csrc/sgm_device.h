@@ -379,6 +379,55 @@ __device__ __forceinline__ void census_tile(const uint8_t *__restrict__ img, int
 
 constexpr int kCostTile = 64;
 
+// the items (pixel, group of CH window values) of one cost tile.  FULL: the
+// tile has kCostTile pixels (item -> pixel by shifts).  INIMG (CH >= 8
+// only): every right column the tile reads lies inside the image, so no
+// value is replaced by Cmax.
+template <int CH, bool FULL, bool INIMG>
+__device__ __forceinline__ void cost_items(const uint64_t *s_cl, const uint64_t *s_cr, int u0, int lo, int w,
+                                           int cmax, int npix, int nch, uint8_t *__restrict__ out)
+{
+    const int np = FULL ? kCostTile : npix;
+    for (int it = threadIdx.x; it < np * nch; it += blockDim.x) {
+        const int ch = it / np, px = it - ch * np;
+        const int k0 = CH * ch;
+        const uint64_t a = s_cl[px];
+        // right column of window index k: u0 + px - lo - k = first + (px + w - 1 - k)
+        const int base = px + w - 1 - k0;
+        const int col0 = u0 + px - lo - k0;
+        uint32_t word[CH / 4];
+#pragma unroll
+        for (int q = 0; q < CH / 4; ++q) {
+            uint32_t wd = 0;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int kk = 4 * q + h;
+                uint32_t c;
+                if constexpr (CH >= 8) {
+                    // w % CH == 0: every kk is inside the window and base - kk
+                    // inside s_cr, so the read is unconditional and only the
+                    // off-image columns are replaced (branch-free)
+                    const uint32_t pc = (uint32_t)__popcll(a ^ s_cr[base - kk]);
+                    c = (INIMG || col0 - kk >= 0) ? pc : (uint32_t)cmax;
+                } else {
+                    c = (uint32_t)cmax;
+                    if (col0 - kk >= 0 && k0 + kk < w) c = (uint32_t)__popcll(a ^ s_cr[base - kk]);
+                }
+                wd |= c << (8 * h);
+            }
+            word[q] = wd;
+        }
+        uint8_t *dst = out + (size_t)px * w + k0;
+        if constexpr (CH == 16) {
+            *reinterpret_cast<uint4 *>(dst) = make_uint4(word[0], word[1], word[2], word[3]);
+        } else if constexpr (CH == 8) {
+            *reinterpret_cast<uint2 *>(dst) = make_uint2(word[0], word[1]);
+        } else {
+            for (int h = 0; h < CH && k0 + h < w; ++h) dst[h] = (uint8_t)(word[h / 4] >> (8 * (h % 4)));
+        }
+    }
+}
+
 template <int CH>
 __device__ __forceinline__ void cost_tile(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr,
                                           const int32_t *__restrict__ d_lo, int W, int H, int w, int cmax,
@@ -400,44 +449,14 @@ __device__ __forceinline__ void cost_tile(const uint64_t *__restrict__ cl, const
     const int npix = min(kCostTile, W - u0);
     const int nch = (w + CH - 1) / CH;
     uint8_t *out = cost + ((size_t)v * W + u0) * w;
-    for (int it = threadIdx.x; it < npix * nch; it += blockDim.x) {
-        const int ch = it / npix, px = it - ch * npix;
-        const int k0 = CH * ch;
-        const uint64_t a = s_cl[px];
-        // right column of window index k: u0 + px - lo - k = first + (px + w - 1 - k)
-        const int base = px + w - 1 - k0;
-        const int col0 = u0 + px - lo - k0;
-        uint32_t word[CH / 4];
-#pragma unroll
-        for (int q = 0; q < CH / 4; ++q) {
-            uint32_t wd = 0;
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int kk = 4 * q + h;
-                uint32_t c;
-                if constexpr (CH >= 8) {
-                    // w % CH == 0: every kk is inside the window and base - kk
-                    // inside s_cr, so the read is unconditional and only the
-                    // off-image columns are replaced (branch-free)
-                    const uint32_t pc = (uint32_t)__popcll(a ^ s_cr[base - kk]);
-                    c = col0 - kk >= 0 ? pc : (uint32_t)cmax;
-                } else {
-                    c = (uint32_t)cmax;
-                    if (col0 - kk >= 0 && k0 + kk < w) c = (uint32_t)__popcll(a ^ s_cr[base - kk]);
-                }
-                wd |= c << (8 * h);
-            }
-            word[q] = wd;
-        }
-        uint8_t *dst = out + (size_t)px * w + k0;
-        if constexpr (CH == 16) {
-            *reinterpret_cast<uint4 *>(dst) = make_uint4(word[0], word[1], word[2], word[3]);
-        } else if constexpr (CH == 8) {
-            *reinterpret_cast<uint2 *>(dst) = make_uint2(word[0], word[1]);
-        } else {
-            for (int h = 0; h < CH && k0 + h < w; ++h) dst[h] = (uint8_t)(word[h / 4] >> (8 * (h % 4)));
-        }
-    }
+    // (uniform over the workgroup)
+    const bool full = npix == kCostTile, inimg = CH >= 8 && first >= 0;
+    if (full && inimg)
+        cost_items<CH, true, true>(s_cl, s_cr, u0, lo, w, cmax, npix, nch, out);
+    else if (full)
+        cost_items<CH, true, false>(s_cl, s_cr, u0, lo, w, cmax, npix, nch, out);
+    else
+        cost_items<CH, false, false>(s_cl, s_cr, u0, lo, w, cmax, npix, nch, out);
 }
 
 
