@@ -258,9 +258,24 @@ def run_batch(args):
         "step_hbm": {"bytes_per_eval": 25, "achieved": round(evals * 25 / (ms * 1e-3) / 1e9, 1), "unit": "GB/s",
                      "frac": round(evals * 25 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
         "kernel_source_sha256": kernel_source_digest(),
     }
     emit(out, args)
+
+
+# The paper's own timings, quoted as context only: they were taken on
+# another GPU, and its frame size and disparity range are not stated, so
+# they convert to no Mdisp-evals/s figure and set no target.
+PAPER_CONTEXT = {
+    "hardware": "NVIDIA RTX 2080 Ti (CUDA)",
+    "gpt_sgm_ms_per_frame": 10.1,
+    "gpt_sgm_source": "Sec. III-A (disparity estimation: perspective-transformed SGM on KITTI road pairs)",
+    "whole_detector_ms_per_frame": 47.48,
+    "whole_detector_source": "Table II (all three datasets; SLIC the largest share)",
+    "comparable": False,
+    "note": "frame size and disparity range not stated: context only, not a baseline",
+}
 
 
 def cpu_baseline_batch(args, hosts, n, R, p1, p2, log):
@@ -1075,6 +1090,7 @@ def main():
         "perspective_from_images": persp,
         "pothole_detector": detector,
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
         "kernel_source_sha256": kernel_source_digest(),
     }
     emit(out, args)
