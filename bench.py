@@ -245,7 +245,8 @@ def run_batch(args):
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "pairs": len(pairs), "evals_per_step": evals, "unique_renders": len(renders)},
         "tuning": {"waves_per_cu": tuning[0], "order": ["longest-first", "pair-major",
-                                                        "direction-major"][tuning[1]]},
+                                                        "direction-major"][tuning[1]],
+                   "lanes_per_scanline": (tuning[2] or 16) if len(tuning) > 2 else 16},
         "roofline": roofline,
         "kernels_ms": {"census": round(census_ms, 4), "cost": round(cost_ms, 4), "aggregate": round(agg_ms, 4),
                        "wta": round(wta_ms, 4),
