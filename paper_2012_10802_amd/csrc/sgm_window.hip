@@ -51,17 +51,21 @@ __global__ __launch_bounds__(256) void k_downsample4(const uint8_t *__restrict__
 constexpr int kWinTile = 64;    // pixels of one row per workgroup
 constexpr int kWinReach = 256;  // right columns reachable left of the tile
 
+// minimum / maximum over the 64 lanes of a wave (every lane active): the
+// DPP reduction of each 16-lane row, then the four rows' results as scalars
 __device__ __forceinline__ int wave_min(int x)
 {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) x = min(x, __shfl_xor(x, o, 64));
-    return x;
+    const int u = (int)group_min<16>((uint32_t)x ^ 0x80000000u);  // signed order as unsigned
+    const uint32_t m = min(min((uint32_t)__builtin_amdgcn_readlane(u, 0), (uint32_t)__builtin_amdgcn_readlane(u, 16)),
+                           min((uint32_t)__builtin_amdgcn_readlane(u, 32), (uint32_t)__builtin_amdgcn_readlane(u, 48)));
+    return (int)(m ^ 0x80000000u);
 }
 __device__ __forceinline__ int wave_max(int x)
 {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) x = max(x, __shfl_xor(x, o, 64));
-    return x;
+    const int u = (int)group_max<16>((uint32_t)x ^ 0x80000000u);
+    const uint32_t m = max(max((uint32_t)__builtin_amdgcn_readlane(u, 0), (uint32_t)__builtin_amdgcn_readlane(u, 16)),
+                           max((uint32_t)__builtin_amdgcn_readlane(u, 32), (uint32_t)__builtin_amdgcn_readlane(u, 48)));
+    return (int)(m ^ 0x80000000u);
 }
 
 // One row tile of 64 pixels per workgroup (one wave).  Only the right
@@ -102,13 +106,21 @@ __global__ __launch_bounds__(64) void k_cost_win(const uint64_t *__restrict__ cl
     if (lo8) lo8[pix] = (uint8_t)l;
     const uint64_t a = cl[pix];
     uint32_t word[4] = {0, 0, 0, 0};
+    if (w == 16 && lmin >= 0 && lmax <= kWinReach - 16 && u0 - lmax - 15 >= 0) {
+        // (uniform) every window value of the tile reads a staged column
+        // inside the image: no checks
+        const uint64_t *src = s_cr + (u - l - first);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int col = u - l - j;
-        const int idx = col - first;
-        uint32_t c = (uint32_t)cmax;
-        if (j < w && col >= 0 && idx >= 0 && idx < kWinTile + kWinReach) c = (uint32_t)__popcll(a ^ s_cr[idx]);
-        word[j / 4] |= c << (8 * (j % 4));
+        for (int j = 0; j < 16; ++j) word[j / 4] |= (uint32_t)__popcll(a ^ src[-j]) << (8 * (j % 4));
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int col = u - l - j;
+            const int idx = col - first;
+            uint32_t c = (uint32_t)cmax;
+            if (j < w && col >= 0 && idx >= 0 && idx < kWinTile + kWinReach) c = (uint32_t)__popcll(a ^ s_cr[idx]);
+            word[j / 4] |= c << (8 * (j % 4));
+        }
     }
     uint8_t *dst = cost + pix * w;
     if (w == 16) {

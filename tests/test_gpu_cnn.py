@@ -109,7 +109,8 @@ def test_forward_layerwise(lw, shape):
             assert np.all(err <= tol[..., :2]), "output max err %g" % err.max()
 
 
-@pytest.mark.parametrize("shape", SHAPES + [(3, 40, 61), (16, 270, 480)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("shape", SHAPES + [(2, 1, 1), (1, 3, 2), (3, 40, 61), (16, 270, 480)],
+                         ids=lambda s: "x".join(map(str, s)))
 def test_infer_equals_layer_by_layer_forward(lw, shape):
     """The one-launch inference (activations kept in LDS, tiles of 24 x 16
     with a 4-pixel halo) gives the layer-by-layer forward's output bit for
