@@ -897,6 +897,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-window vs plain comparison")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2012_10802_amd", "window_cnn.npz"))
+    ap.add_argument("--no-graph", action="store_true",
+                    help="single mode: time eager steps instead of replays of the step captured in a HIP graph")
     ap.add_argument("--tau", type=float, default=0.5, help="confidence threshold of the learned windows")
     ap.add_argument("--fallback-margin", type=int, default=8,
                     help="low-confidence pixels fall back to full range only where x - 4 * coarse disparity is at "
@@ -993,6 +995,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # eager steps with HIP events between the stages (per-kernel times)
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -1000,9 +1003,36 @@ def main():
         step(events[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ms_eager = (t1 - t0) * 1e3 / args.steps
     per = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(3)] for e in events])
     cost_ms, agg_ms, wta_ms = (float(x) for x in per.mean(axis=0))
+    ms_per_step, graph_info = ms_eager, None
+    if not args.no_graph:
+        # the same step captured once in a HIP graph and replayed (the calls
+        # allocate nothing and issue no memsets); its result must equal the
+        # eager one bit for bit before it is timed
+        want_i, want_s = dint.clone(), dsub.clone()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        dint.fill_(-1)
+        dsub.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        if not (torch.equal(dint, want_i) and torch.equal(dsub, want_s)):
+            raise RuntimeError("graph replay of the step differs from the eager step")
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms_per_step = (t1 - t0) * 1e3 / args.steps
+        graph_info = {"ms_per_step_eager": round(ms_eager, 4),
+                      "note": "value from replays of the step captured in a HIP graph (checked bit-equal to the "
+                              "eager step); kernels_ms from the eager steps' HIP events"}
 
     evals = W * H * w
     value = evals / (ms_per_step * 1e-3) / 1e6
@@ -1084,6 +1114,7 @@ def main():
         "full_range_equivalent": None if d_lo is None else {
             "ndisp": 128, "value": round(W * H * 128 / (ms_per_step * 1e-3) / 1e6, 1),
             "unit": "Mdisp-evals/s (pixels x 128 disparities per second)"},
+        "graph": graph_info,
         "tuning": {"lanes_per_scanline": m.lanes,
                    "chosen_by": "--lanes" if args.lanes is not None else "sgm_autotune"},
         "roofline": roofline,

@@ -326,6 +326,51 @@ def test_single_pair_autotune_keeps_results(lib, tmp_path):
     np.testing.assert_array_equal(dsub.cpu().numpy(), ws)
 
 
+def test_single_pair_step_replays_in_a_graph(lib):
+    """The split single-pair step (sgm_cost, sgm_aggregate_paths,
+    sgm_wta_paths, as the benchmark times it) captured once in a HIP graph:
+    every replay on new images copied into the captured buffers, with eager
+    work and synchronisations in between, equals the oracle and the eager
+    step bit for bit."""
+    import torch
+    W, H, D = 150, 70, 48
+    m = lib.Matcher(W, H, census=7, ndisp=D, npaths=8, p1=10, p2=120)
+    left = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    right = torch.empty_like(left)
+    cost = m.new_volume(torch.uint8)
+    paths = m.new_paths()
+    dint = torch.empty((H, W), dtype=torch.int16, device="cuda")
+    dsub = torch.empty((H, W), dtype=torch.float32, device="cuda")
+
+    def step():
+        m.cost(left, right, cost=cost)
+        m.aggregate_paths(cost, paths)
+        m.wta_paths(paths, disp_int=dint, disp_sub=dsub)
+
+    L0, R0 = _rand_pair(W, H, 5)
+    left.copy_(torch.from_numpy(L0))
+    right.copy_(torch.from_numpy(R0))
+    step()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for seed in (11, 12, 13):
+        L, R = _rand_pair(W, H, seed)
+        left.copy_(torch.from_numpy(L))
+        right.copy_(torch.from_numpy(R))
+        dint.fill_(-1)
+        graph.replay()
+        torch.cuda.synchronize()
+        gi, gs = dint.clone(), dsub.clone()
+        step()  # eager, same buffers
+        torch.cuda.synchronize()
+        assert torch.equal(gi, dint) and torch.equal(gs, dsub), seed
+        wi, ws = oracle.sgm(L, R, 7, D, 8, 10, 120)
+        np.testing.assert_array_equal(_np_u16(gi), wi)
+        np.testing.assert_array_equal(gs.cpu().numpy(), ws)
+
+
 def test_injected_launch_fault_then_recovery(lib):
     """An armed launch fault fails exactly one call (nothing enqueued); the
     next call runs normally and matches the oracle."""
