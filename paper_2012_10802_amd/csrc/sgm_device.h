@@ -129,10 +129,23 @@ __device__ __forceinline__ int dir_dv(int r)
 // ---------------------------------------------------------------------------
 // lane value I/O: VPL bytes (or u16) per lane
 
+template <bool B, class T, class F>
+struct pick_type {
+    using type = T;
+};
+template <class T, class F>
+struct pick_type<false, T, F> {
+    using type = F;
+};
+
+// The bytes of two values are held as a 16-bit word: a 32-bit word holding
+// a zero-extended 16-bit load is narrowed by the compiler, which then
+// re-extends the loop-carried ring registers at the loop head and so waits
+// there for every load in flight.
 template <int VPL>
 struct Raw {
     static constexpr int NW = (VPL + 3) / 4;
-    uint32_t d[NW];
+    typename pick_type<VPL == 2, uint16_t, uint32_t>::type d[NW];
 };
 
 // (used for the per-direction volumes, which are read once: non-temporal)
