@@ -1013,26 +1013,31 @@ def main():
         # eager one bit for bit before it is timed
         want_i, want_s = dint.clone(), dsub.clone()
         graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            step()
-        dint.fill_(-1)
-        dsub.fill_(float("nan"))
-        graph.replay()
-        torch.cuda.synchronize()
-        if not (torch.equal(dint, want_i) and torch.equal(dsub, want_s)):
-            raise RuntimeError("graph replay of the step differs from the eager step")
-        for _ in range(args.warmup):
+        try:
+            with torch.cuda.graph(graph):
+                step()
+        except RuntimeError as exc:  # capture unavailable: the eager time stands
+            graph = None
+            graph_info = {"error": "capture failed (%s); value from the eager steps" % exc}
+        if graph is not None:
+            dint.fill_(-1)
+            dsub.fill_(float("nan"))
             graph.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            graph.replay()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ms_per_step = (t1 - t0) * 1e3 / args.steps
-        graph_info = {"ms_per_step_eager": round(ms_eager, 4),
-                      "note": "value from replays of the step captured in a HIP graph (checked bit-equal to the "
-                              "eager step); kernels_ms from the eager steps' HIP events"}
+            torch.cuda.synchronize()
+            if not (torch.equal(dint, want_i) and torch.equal(dsub, want_s)):
+                raise RuntimeError("graph replay of the step differs from the eager step")
+            for _ in range(args.warmup):
+                graph.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                graph.replay()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ms_per_step = (t1 - t0) * 1e3 / args.steps
+            graph_info = {"ms_per_step_eager": round(ms_eager, 4),
+                          "note": "value from replays of the step captured in a HIP graph (checked bit-equal to "
+                                  "the eager step); kernels_ms from the eager steps' HIP events"}
 
     evals = W * H * w
     value = evals / (ms_per_step * 1e-3) / 1e6
