@@ -554,15 +554,14 @@ sgm_status sgm_batch_autotune(sgm_batch_t b, void *ws, size_t bytes, void *strea
             best = c;
         }
     };
-    // the lane mapping first (at 8 waves per CU, longest first), then
-    // waves per CU x queue order at the best mapping
-    for (int lanes : {0, 16, 8})
-        if (ok) trial(sgm_tuning{8, 0, lanes});
-    const int lanes = best.lanes;
+    // every lane mapping x waves per CU x queue order (the best lane count
+    // moves with the waves per CU: on 16 quarter-scale 480x270x48 pairs 4
+    // lanes at 4 waves beat the best 8-lane choice by 10 %)
     const int waves[] = {4, 8, 12, 16, 24};
-    for (int order = 0; order <= 2 && ok; ++order)
-        for (int wv : waves)
-            if (ok && !(wv == 8 && order == 0)) trial(sgm_tuning{wv, order, lanes});
+    for (int lanes : {16, 8, 4})
+        for (int order = 0; order <= 2 && ok; ++order)
+            for (int wv : waves)
+                if (ok) trial(sgm_tuning{wv, order, lanes});
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (!ok) {
