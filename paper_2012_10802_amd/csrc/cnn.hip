@@ -1,20 +1,24 @@
 // The search-window network of the learned-window form: four 3x3
 // convolutions, 16 channels, zero padding, ReLU after the first three,
 // bfloat16 weights and activations with float32 accumulation on the matrix
-// cores (v_mfma_f32_16x16x16bf16_1k), plus its hand-written training
-// kernels (loss, input and weight gradients, Adam) and the window map that
-// turns its output into per-pixel search windows.
+// cores, plus its hand-written training kernels (loss, input and weight
+// gradients, Adam) and the window map that turns its output into per-pixel
+// search windows.
 //
 // Implicit GEMM: a wave owns 16 consecutive pixels of one row (the M
 // dimension) and all 16 output channels (N); the reduction runs over the 9
-// taps x 16 input channels as 9 MFMA steps of K = 16.  Activations are
-// NHWC [n][H][W][16] bfloat16, so a lane's 4 input channels of one pixel
-// are one 8-byte load.
+// taps x 16 input channels.  The forward passes (training forward and the
+// one-launch inference) take two taps per v_mfma_f32_16x16x32_bf16 step
+// (5 steps, the last one tap and zeros); the input gradient takes one tap
+// per v_mfma_f32_16x16x16bf16_1k step.  Activations are NHWC [n][H][W][16]
+// bfloat16, so a lane's 8 (4) input channels of one pixel are one 16-byte
+// (8-byte) load.
 //
-// Operand layout of v_mfma_f32_16x16x16bf16_1k used here (lane l, g = l/16):
-//   A[i][k]: i = l % 16, k = 4g .. 4g+3      (4 bf16 in one 64-bit register)
-//   B[k][j]: j = l % 16, k = 4g .. 4g+3
-//   D[i][j]: j = l % 16, i = 4g + r for accumulator element r = 0..3.
+// Operand layouts (lane l, g = l/16; checked on the device):
+//   16x16x32: A[i][k]: i = l % 16, k = 8g .. 8g+7; B[k][j]: j = l % 16,
+//             k = 8g .. 8g+7 (8 bf16 in four registers)
+//   16x16x16: the same with k = 4g .. 4g+3 (4 bf16 in two registers)
+//   D[i][j]:  j = l % 16, i = 4g + r for accumulator element r = 0..3.
 //
 // Weight-gradient sums run over pixels; each wave writes its partial sums
 // and a second kernel adds the partials in wave order, so the gradient is
@@ -40,6 +44,7 @@ constexpr int kOutCh = 2;  // output channels used: centre offset, confidence lo
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // float -> bfloat16, round to nearest even
 __device__ __forceinline__ uint16_t f2bf(float f)
@@ -48,6 +53,13 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// 8 consecutive bfloat16 (16 bytes, 4-byte aligned at least)
+__device__ __forceinline__ v8bf load8(const uint16_t *p)
+{
+    return __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(p));
+}
+__device__ __forceinline__ v8bf zero8() { return __builtin_bit_cast(v8bf, make_uint4(0u, 0u, 0u, 0u)); }
 
 __device__ __forceinline__ v4s load4(const uint16_t *p)
 {
@@ -99,29 +111,52 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ x, co
     const int s_first = wave * kStripsPerWave;
     if (s_first >= nstrips) return;
     const int i = lane & 15, g = lane >> 4;
-    v4s b[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) b[t] = load4(wt + (size_t)t * CH * CH + (size_t)i * CH + 4 * g);
     const float bi = MODE == 2 ? 0.0f : bias[i];
     const int s_end = min(s_first + kStripsPerWave, nstrips);
+    // forward (MODE 0, 1): K = 32 per MFMA, two taps at a time — lane group
+    // g holds tap 2m + g/2, channels 8 (g % 2) .. +7 of step m (the fifth
+    // step carries tap 8 and zeros).  Input gradient (MODE 2): K = 16, one
+    // tap per step, lane group g holds channels 4g .. 4g+3.
+    v8bf b8[5];
+    v4s b[9];
+    if constexpr (MODE != 2) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            const int t = 2 * m + (g >> 1);
+            b8[m] = t < 9 ? load8(wt + (size_t)t * CH * CH + (size_t)i * CH + 8 * (g & 1)) : zero8();
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) b[t] = load4(wt + (size_t)t * CH * CH + (size_t)i * CH + 4 * g);
+    }
     for (int s = s_first; s < s_end; ++s) {
         const Strip st = strip_of(s, W, H);
-        v4s a[9];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            int dy = t / 3 - 1, dx = t % 3 - 1;
-            if (MODE == 2) {  // transpose: the gradient flows back from p - offset
-                dy = -dy;
-                dx = -dx;
-            }
-            const int yy = st.y + dy, xx = st.x0 + i + dx;
-            a[t] = (v4s){0, 0, 0, 0};
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                a[t] = load4(x + (((size_t)st.n * H + yy) * W + xx) * CH + 4 * g);
-        }
         v4f acc = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (MODE != 2) {
+            v8bf a8[5];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], b[t], acc, 0, 0, 0);
+            for (int m = 0; m < 5; ++m) {
+                const int t = 2 * m + (g >> 1);
+                const int yy = st.y + t / 3 - 1, xx = st.x0 + i + t % 3 - 1;
+                a8[m] = zero8();
+                if (t < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    a8[m] = load8(x + (((size_t)st.n * H + yy) * W + xx) * CH + 8 * (g & 1));
+            }
+#pragma unroll
+            for (int m = 0; m < 5; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8[m], b8[m], acc, 0, 0, 0);
+        } else {
+            v4s a[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                // transpose: the gradient flows back from p - offset
+                const int yy = st.y - (t / 3 - 1), xx = st.x0 + i - (t % 3 - 1);
+                a[t] = (v4s){0, 0, 0, 0};
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    a[t] = load4(x + (((size_t)st.n * H + yy) * W + xx) * CH + 4 * g);
+            }
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], b[t], acc, 0, 0, 0);
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int xo = st.x0 + 4 * g + r;
@@ -152,9 +187,10 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ x, co
 // The MFMA runs transposed with respect to k_conv (weights as the A
 // operand, pixels as B): D[co][pixel], so each lane ends with 4 channels of
 // one pixel, which is one 8-byte LDS write in the layout the next layer
-// reads.  The products and their order over the 16 input channels of each
-// tap are those of k_conv, and the taps accumulate in the same order, so the
-// result equals the layer-by-layer forward bit for bit.  A wave runs two
+// reads.  The products and their positions in each K = 32 step (two taps x
+// 16 input channels) are those of k_conv's forward, and the steps
+// accumulate in the same order, so the result equals the layer-by-layer
+// forward bit for bit.  A wave runs two
 // items' MFMA chains interleaved and loads the next two items' operands from
 // LDS before them.
 
@@ -195,12 +231,15 @@ __global__ __launch_bounds__(256) void k_cnn_infer(const uint16_t *__restrict__ 
         if (yy >= 0 && yy < H && xx >= 0 && xx < W)
             tile[k] = *reinterpret_cast<const uint2 *>(x0 + ((img + yy) * W + xx) * CH + 4 * part);
     }
-    v4s wt[LAYERS][9];
+    v8bf wt[LAYERS][5];
     float bias[LAYERS][4];
 #pragma unroll
     for (int l = 0; l < LAYERS; ++l) {
 #pragma unroll
-        for (int t = 0; t < 9; ++t) wt[l][t] = load4(wf + ((size_t)l * 9 + t) * CH * CH + (size_t)i * CH + 4 * g);
+        for (int m = 0; m < 5; ++m) {
+            const int t = 2 * m + (g >> 1);
+            wt[l][m] = t < 9 ? load8(wf + ((size_t)l * 9 + t) * CH * CH + (size_t)i * CH + 8 * (g & 1)) : zero8();
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) bias[l][e] = params[(size_t)l * PER_LAYER + 9 * CH * CH + 4 * g + e];
     }
@@ -218,21 +257,26 @@ __global__ __launch_bounds__(256) void k_cnn_infer(const uint16_t *__restrict__ 
         // [l + 1, l + 33) of the tile: two strips of 16 pixels per row
         const int h = l + 1;
         const int nitems = 2 * (kFR - 2 * h);
-        auto load_item = [&](int it, v4s(&a)[9]) __attribute__((always_inline)) {
+        auto load_item = [&](int it, v8bf(&a)[5]) __attribute__((always_inline)) {
             const int r = h + (it >> 1), c0 = h + 16 * (it & 1);
 #pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const uint2 v = in[fslot((r + t / 3 - 1) * kFCP + c0 + i + t % 3 - 1, g)];
-                a[t] = __builtin_bit_cast(v4s, v);
+            for (int m = 0; m < 5; ++m) {
+                // tap 2m + g/2, channels 8 (g % 2) .. +7: two adjacent 8-byte groups
+                const int t = 2 * m + (g >> 1);
+                a[m] = zero8();
+                if (t < 9) {
+                    const uint2 *q = &in[fslot((r + t / 3 - 1) * kFCP + c0 + i + t % 3 - 1, 2 * (g & 1))];
+                    a[m] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(q));
+                }
             }
         };
         // items it and it + 4 together: two independent MFMA chains
-        auto compute = [&](int it, const v4s(&a)[9], const v4s(&b)[9]) __attribute__((always_inline)) {
+        auto compute = [&](int it, const v8bf(&a)[5], const v8bf(&b)[5]) __attribute__((always_inline)) {
             v4f acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[l][t], a[t], acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[l][t], b[t], acc[1], 0, 0, 0);
+            for (int m = 0; m < 5; ++m) {
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt[l][m], a[m], acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt[l][m], b[m], acc[1], 0, 0, 0);
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -257,8 +301,8 @@ __global__ __launch_bounds__(256) void k_cnn_infer(const uint16_t *__restrict__ 
         };
         // a wave's items: wave, wave + 4, ...; pairs of them, the next pair's
         // operands loaded from LDS before the current pair's MFMAs
-        v4s p0[2][9], p1[2][9];
-        auto load_pair = [&](int it, v4s(&p)[2][9]) __attribute__((always_inline)) {
+        v8bf p0[2][5], p1[2][5];
+        auto load_pair = [&](int it, v8bf(&p)[2][5]) __attribute__((always_inline)) {
             if (it < nitems) load_item(it, p[0]);
             if (it + 4 < nitems) load_item(it + 4, p[1]);
         };
