@@ -821,59 +821,68 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
     for (int j = 0; j < NP; ++j) Lq[j] = 0;
     uint32_t mnq = 0;
 
-    // the step count is padded to a multiple of UNROLL; padded steps load
-    // nothing and store nothing
-    const int nblk = (I1 - I0 + UNROLL - 1) / UNROLL;
+    // one step: consume ring slot S (loaded PF steps ago), refill it for
+    // step i + PF, aggregate, store
+    auto step = [&](const int i, const int S) __attribute__((always_inline)) {
+        // ring[S] was loaded PF steps ago; everything issued since may stay
+        // in flight.  The scheduling fence keeps later steps' reads of the
+        // ring below this wait.
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(VmemPerStep<VPL, ALIGNED, L8>::stores +
+                                             (PF - 1) * VmemPerStep<VPL, ALIGNED, L8>::total));
+        uint32_t c2[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) c2[j] = unpack_strided(ring[S], j) | padp[j];
+        {
+            const int ip = i + PF;
+            const uint32_t o = (ip < I1) ? offset(ip) : kOff;
+            buf_load_u8<VPL, ALIGNED>(ring[S], rc, o, nvalid);
+        }
+        // m_q = min_k L(q,k) in both u16 halves: the lane's pair minimum
+        // (from the end of the previous step) folded over its halves, then
+        // reduced over the group as 32-bit values (such doubled values order
+        // as m_q does).  This chain is independent of the neighbour terms
+        // below, which overlap it.
+        const uint32_t mm = group_min<G>(pk_min_halves(mnq));
+        // end neighbours across the lane edges (outside the window: 0x3FFF)
+        uint32_t e = dpp<kRowShr1>(kInf2, Lq[NP - 1]);
+        uint32_t f = dpp<kRowShl1>(kInf2, Lq[0]);
+        if constexpr (G < 16) {
+            // groups inside a DPP row: their end lanes read another scanline
+            e = lane == 0 ? kInf2 : e;
+            f = lane == G - 1 ? kInf2 : f;
+        }
+        // L(p,k) = C(p,k) + min(L(q,k), L(q,k+-1) + P1, m_q + P2) - m_q
+        //        = C(p,k) + min(t - m_q, P2),  t = min(L(q,k), L(q,k+-1) + P1) >= m_q,
+        // so m_q enters only after t (no u16 value goes below 0 or past
+        // 0x3FFF + P1 + P2)
+        uint32_t Ln[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const uint32_t lft = j ? Lq[j - 1] : __builtin_amdgcn_alignbit(Lq[NP - 1], e, 16);
+            const uint32_t rgt = j + 1 < NP ? Lq[j + 1] : __builtin_amdgcn_alignbit(f, Lq[0], 16);
+            const uint32_t t = pk_min(Lq[j], pk_add(pk_min(lft, rgt), a.p1x2));
+            Ln[j] = pk_add(pk_min(pk_sub(t, mm), a.p2x2), c2[j]);
+        }
+        const uint32_t mn = pk_min_tree<NP>(Ln);
+        store_strided<VPL, ALIGNED, L8>(Ln, ro, (i < I1) ? offset(i) : kOff, nvalid);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) Lq[j] = Ln[j];
+        mnq = mn;
+    };
+
+    // The first turn of the ring runs outside the loop: at the loop head
+    // every slot was then refilled by a step, exactly as on the back edge,
+    // so the compiler sees the same loads in flight from both sides and
+    // needs no deeper wait there than inside the loop.  The step count is
+    // padded to PF + a multiple of UNROLL; padded steps load nothing and
+    // store nothing.
+#pragma unroll
+    for (int S = 0; S < PF; ++S) step(I0 + S, S);
+    const int nblk = (I1 - I0 - PF + UNROLL - 1) / UNROLL;
     for (int blk = 0; blk < nblk; ++blk) {
 #pragma unroll
-        for (int s = 0; s < UNROLL; ++s) {
-            const int i = I0 + blk * UNROLL + s;
-            // ring[s % PF] was loaded PF steps ago; everything issued since
-            // may stay in flight.  The scheduling fence keeps later steps'
-            // reads of the ring below this wait.
-            __builtin_amdgcn_sched_barrier(0);
-            __builtin_amdgcn_s_waitcnt(vmcnt_imm(VmemPerStep<VPL, ALIGNED, L8>::stores +
-                                                 (PF - 1) * VmemPerStep<VPL, ALIGNED, L8>::total));
-            uint32_t c2[NP];
-#pragma unroll
-            for (int j = 0; j < NP; ++j) c2[j] = unpack_strided(ring[s % PF], j) | padp[j];
-            {
-                const int ip = i + PF;
-                const uint32_t o = (ip < I1) ? offset(ip) : kOff;
-                buf_load_u8<VPL, ALIGNED>(ring[s % PF], rc, o, nvalid);
-            }
-            // m_q = min_k L(q,k) in both u16 halves: the lane's pair minimum
-            // (from the end of the previous step) folded over its halves,
-            // then reduced over the group as 32-bit values (such doubled
-            // values order as m_q does).  This chain is independent of the
-            // neighbour terms below, which overlap it.
-            const uint32_t mm = group_min<G>(pk_min_halves(mnq));
-            // end neighbours across the lane edges (outside the window: 0x3FFF)
-            uint32_t e = dpp<kRowShr1>(kInf2, Lq[NP - 1]);
-            uint32_t f = dpp<kRowShl1>(kInf2, Lq[0]);
-            if constexpr (G < 16) {
-                // groups inside a DPP row: their end lanes read another scanline
-                e = lane == 0 ? kInf2 : e;
-                f = lane == G - 1 ? kInf2 : f;
-            }
-            // L(p,k) = C(p,k) + min(L(q,k), L(q,k+-1) + P1, m_q + P2) - m_q
-            //        = C(p,k) + min(t - m_q, P2),  t = min(L(q,k), L(q,k+-1) + P1) >= m_q,
-            // so m_q enters only after t (no u16 value goes below 0 or past
-            // 0x3FFF + P1 + P2)
-            uint32_t Ln[NP];
-#pragma unroll
-            for (int j = 0; j < NP; ++j) {
-                const uint32_t lft = j ? Lq[j - 1] : __builtin_amdgcn_alignbit(Lq[NP - 1], e, 16);
-                const uint32_t rgt = j + 1 < NP ? Lq[j + 1] : __builtin_amdgcn_alignbit(f, Lq[0], 16);
-                const uint32_t t = pk_min(Lq[j], pk_add(pk_min(lft, rgt), a.p1x2));
-                Ln[j] = pk_add(pk_min(pk_sub(t, mm), a.p2x2), c2[j]);
-            }
-            const uint32_t mn = pk_min_tree<NP>(Ln);
-            store_strided<VPL, ALIGNED, L8>(Ln, ro, (i < I1) ? offset(i) : kOff, nvalid);
-#pragma unroll
-            for (int j = 0; j < NP; ++j) Lq[j] = Ln[j];
-            mnq = mn;
-        }
+        for (int s = 0; s < UNROLL; ++s) step(I0 + PF + blk * UNROLL + s, s % PF);
     }
 }
 
