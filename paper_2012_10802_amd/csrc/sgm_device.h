@@ -17,9 +17,20 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 constexpr uint32_t kInf2 = 0x3FFF3FFFu;  // pair of "outside the window" values
 constexpr uint32_t kPad = 0x3FFFu;
 
+// a compile-time flag passed to generic lambdas
+template <bool B>
+struct Flag {
+    static constexpr bool value = B;
+};
+
 __device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b)
 {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
                                                                   __builtin_bit_cast(u16x2, b)));
 }
 __device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b)
@@ -47,11 +58,11 @@ __device__ __forceinline__ uint32_t pk_min_tree(const uint32_t *v)
     }
 }
 
-// DPP move: lanes whose source lies outside their 16-lane row keep `old`.
+// DPP move with zero fill: lanes whose source lies outside their row read 0
 template <int CTRL>
-__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t src)
+__device__ __forceinline__ uint32_t dpp0(uint32_t src)
 {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)src, CTRL, 0xF, 0xF, true);
 }
 constexpr int kQuadSwap1 = 0xB1;  // quad_perm [1,0,3,2]
 constexpr int kQuadSwap2 = 0x4E;  // quad_perm [2,3,0,1]
@@ -799,6 +810,21 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
             return o;
     };
 
+    // The end lanes of a group have no neighbour across the group edge:
+    // the half they use of their DPP neighbour (0 at a row edge, another
+    // scanline's value inside a row, at most kInf2 + P2) is raised to at
+    // least kInf2, which acts as outside the window (kInf2 + P1 - m_q > P2).
+    const uint32_t edge_l = lane == 0 ? kInf2 : 0u;
+    const uint32_t edge_r = lane == G - 1 ? kInf2 : 0u;
+    // narrow lanes (one dword of cost bytes): the pair unpacking and the
+    // padding in one byte permutation, padded halves taking kInf2's bytes
+    uint32_t psel[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const uint32_t lo = j >= nvalid ? 0x0504u : ((uint32_t)j | 0x0C00u);
+        const uint32_t hi = j + NP >= nvalid ? 0x0706u : ((uint32_t)(j + NP) | 0x0C00u);
+        psel[j] = lo | (hi << 16);
+    }
     uint32_t padp[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
@@ -822,8 +848,10 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
     uint32_t mnq = 0;
 
     // one step: consume ring slot S (loaded PF steps ago), refill it for
-    // step i + PF, aggregate, store
-    auto step = [&](const int i, const int S) __attribute__((always_inline)) {
+    // step i + PF, aggregate, store.  A checked step may lie past the
+    // scanline's last step or prefetch past it: those accesses are dropped.
+    auto step = [&](const int i, const int S, auto checked) __attribute__((always_inline)) {
+        constexpr bool CHECKED = decltype(checked)::value;
         // ring[S] was loaded PF steps ago; everything issued since may stay
         // in flight.  The scheduling fence keeps later steps' reads of the
         // ring below this wait.
@@ -832,10 +860,15 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
                                              (PF - 1) * VmemPerStep<VPL, ALIGNED, L8>::total));
         uint32_t c2[NP];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) c2[j] = unpack_strided(ring[S], j) | padp[j];
+        for (int j = 0; j < NP; ++j) {
+            if constexpr (PAD && NP <= 2)
+                c2[j] = __builtin_amdgcn_perm(kInf2, (uint32_t)ring[S].d[0], psel[j]);
+            else
+                c2[j] = unpack_strided(ring[S], j) | padp[j];
+        }
         {
             const int ip = i + PF;
-            const uint32_t o = (ip < I1) ? offset(ip) : kOff;
+            const uint32_t o = (!CHECKED || ip < I1) ? offset(ip) : kOff;
             buf_load_u8<VPL, ALIGNED>(ring[S], rc, o, nvalid);
         }
         // m_q = min_k L(q,k) in both u16 halves: the lane's pair minimum
@@ -845,13 +878,10 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
         // below, which overlap it.
         const uint32_t mm = group_min<G>(pk_min_halves(mnq));
         // end neighbours across the lane edges (outside the window: 0x3FFF)
-        uint32_t e = dpp<kRowShr1>(kInf2, Lq[NP - 1]);
-        uint32_t f = dpp<kRowShl1>(kInf2, Lq[0]);
-        if constexpr (G < 16) {
-            // groups inside a DPP row: their end lanes read another scanline
-            e = lane == 0 ? kInf2 : e;
-            f = lane == G - 1 ? kInf2 : f;
-        }
+        // (e: only its high half is used, so a 32-bit maximum, which the
+        // compiler folds into the DPP move; f: its low half, a packed one)
+        const uint32_t e = max(dpp0<kRowShr1>(Lq[NP - 1]), edge_l);
+        const uint32_t f = pk_max(dpp0<kRowShl1>(Lq[0]), edge_r);
         // L(p,k) = C(p,k) + min(L(q,k), L(q,k+-1) + P1, m_q + P2) - m_q
         //        = C(p,k) + min(t - m_q, P2),  t = min(L(q,k), L(q,k+-1) + P1) >= m_q,
         // so m_q enters only after t (no u16 value goes below 0 or past
@@ -865,24 +895,31 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
             Ln[j] = pk_add(pk_min(pk_sub(t, mm), a.p2x2), c2[j]);
         }
         const uint32_t mn = pk_min_tree<NP>(Ln);
-        store_strided<VPL, ALIGNED, L8>(Ln, ro, (i < I1) ? offset(i) : kOff, nvalid);
+        store_strided<VPL, ALIGNED, L8>(Ln, ro, (!CHECKED || i < I1) ? offset(i) : kOff, nvalid);
 #pragma unroll
         for (int j = 0; j < NP; ++j) Lq[j] = Ln[j];
         mnq = mn;
     };
 
-    // The first turn of the ring runs outside the loop: at the loop head
+    // The first turn of the ring runs outside the loops: at a loop head
     // every slot was then refilled by a step, exactly as on the back edge,
     // so the compiler sees the same loads in flight from both sides and
     // needs no deeper wait there than inside the loop.  The step count is
     // padded to PF + a multiple of UNROLL; padded steps load nothing and
-    // store nothing.
+    // store nothing.  Blocks whose steps and prefetches all lie before I1
+    // (the last prefetch of block blk is step I0 + 2 PF + (blk + 1) UNROLL
+    // - 1) run without the per-step range checks.
 #pragma unroll
-    for (int S = 0; S < PF; ++S) step(I0 + S, S);
+    for (int S = 0; S < PF; ++S) step(I0 + S, S, Flag<true>{});
     const int nblk = (I1 - I0 - PF + UNROLL - 1) / UNROLL;
-    for (int blk = 0; blk < nblk; ++blk) {
+    const int nfull = min(nblk, max(0, (I1 - I0 - 2 * PF) / UNROLL));
+    for (int blk = 0; blk < nfull; ++blk) {
 #pragma unroll
-        for (int s = 0; s < UNROLL; ++s) step(I0 + PF + blk * UNROLL + s, s % PF);
+        for (int s = 0; s < UNROLL; ++s) step(I0 + PF + blk * UNROLL + s, s % PF, Flag<false>{});
+    }
+    for (int blk = nfull; blk < nblk; ++blk) {
+#pragma unroll
+        for (int s = 0; s < UNROLL; ++s) step(I0 + PF + blk * UNROLL + s, s % PF, Flag<true>{});
     }
 }
 
