@@ -4,7 +4,8 @@
 // Stage grids are the concatenation of the single-pair grids; a workgroup
 // finds its pair by binary search over the per-pair start indices.  The
 // aggregation is persistent: each workgroup is one wave that repeatedly
-// takes the next item (pair, direction, group of 64 / lanes scanlines) from a
+// takes the next item (pair, direction, group of 64 / lanes scanlines, 4 for
+// the horizontal directions, which always run on 16 lanes) from a
 // queue in the workspace with one atomic add, runs it, and stops when the
 // queue is empty (every wave reaches that exit).  The queue order is laid
 // out on the host (longest scanlines first by default), which balances
@@ -86,10 +87,11 @@ __global__ __launch_bounds__(64) void k_aggregate_batch(BatchDev b)
         a.p1x2 = b.p1x2;
         a.p2x2 = b.p2x2;
         a.np = b.npaths;
-        const int lanes = __builtin_amdgcn_readfirstlane(P.lanes);
-        a.lines_per_wg = 64 / lanes;
-        // (lanes, values per lane, padded window) of the pair's mapping
-        const int variant = __builtin_amdgcn_readfirstlane(lanes * 512 + P.vpl * 2 + P.pad);
+        // (lanes, values per lane, padded window) of the pair's mapping; the
+        // horizontal directions take the pair's 16-lane one
+        const bool horiz = r <= 1;
+        const int variant = __builtin_amdgcn_readfirstlane(horiz ? 16 * 512 + P.h_vpl * 2 + P.h_pad
+                                                                 : P.lanes * 512 + P.vpl * 2 + P.pad);
         switch (variant) {
         case 16 * 512 + 4: agg_item<16, 2, true, false, L8, kBatchPrefetch>(a, r, r, g); break;
         case 16 * 512 + 5: agg_item<16, 2, true, true, L8, kBatchPrefetch>(a, r, r, g); break;

@@ -161,15 +161,19 @@ void layout_queue(sgm_batch_s *b)
         d.lanes = m.lanes;
         d.vpl = m.vpl;
         d.pad = p.ndisp < m.lanes * m.vpl ? 1 : 0;
+        // the horizontal directions always take 16 lanes per scanline
+        const sgm::Mapping mh = sgm::choose_mapping(p.ndisp, 16);
+        d.h_vpl = mh.vpl;
+        d.h_pad = p.ndisp < 16 * mh.vpl ? 1 : 0;
         const sgm::Mapping ms = sgm::select_mapping(p.ndisp);
         d.wta_lanes = ms.lanes;
         d.wta_vpl = ms.vpl;
         const long long npix = (long long)p.width * p.height, ppb = 256 / ms.lanes;
         d.wta_start = wta_blk;
         wta_blk += (int)((npix + ppb - 1) / ppb);
-        const int lpi = 64 / m.lanes;
         for (int r = 0; r < b->prm.npaths; ++r) {
             const int kind = r <= 1 ? 0 : (r >= 4 ? 1 : 2);  // horizontal, diagonal, vertical
+            const int lpi = 64 / (kind == 0 ? 16 : m.lanes);  // scanlines per item
             for (int g = 0, n = groups_of(r, p.width, p.height, lpi); g < n; ++g)
                 b->items.push_back(Item{(uint32_t)(i << 8 | r), (uint32_t)g,
                                         group_length(r, g, p.width, p.height, lpi), i, kind});

@@ -494,7 +494,6 @@ struct AggParams {
     int W, H, w;
     uint32_t p1x2, p2x2;  // P1, P2 replicated in both u16 halves
     int np;
-    int lines_per_wg;
     int paths[8];   // per dispatch slot: direction | output volume << 8
     int gstart[9];  // first workgroup of each slot, ascending
 };
@@ -768,7 +767,7 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
     const int lane = threadIdx.x & (G - 1);
     const int lw = threadIdx.x / G;
     const int W = a.W, H = a.H, w = a.w;
-    const int lpw = a.lines_per_wg;
+    const int lpw = (int)blockDim.x / G;  // scanlines per workgroup
 
     int I0 = 0, I1;
     int idx = g * lpw + lw;
@@ -925,8 +924,12 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
 
 
 // One workgroup-sized piece of the aggregation: direction r, scanline group g
-// of the volume described by `a`, written to output volume `vol`.
-template <int G, int VPL, bool ALIGNED, bool PAD, bool L8, int PF>
+// of the volume described by `a`, written to output volume `vol`.  The
+// horizontal directions may take a lane mapping of their own (GH, VPLH,
+// PADH, PFH): their scanlines are the longest dependency chains, which the
+// widest groups run with the fewest dependent instructions per step.
+template <int G, int VPL, bool ALIGNED, bool PAD, bool L8, int PF, int GH = G, int VPLH = VPL, bool PADH = PAD,
+          int PFH = PF>
 __device__ __forceinline__ void agg_item(const AggParams &a, int r, int vol, int g)
 {
     const int du = __builtin_amdgcn_readfirstlane(dir_du(r)), dv = __builtin_amdgcn_readfirstlane(dir_dv(r));
@@ -940,7 +943,7 @@ __device__ __forceinline__ void agg_item(const AggParams &a, int r, int vol, int
     if (dv == 0) {
         // the longest dependency chains: issue them first on a shared SIMD
         __builtin_amdgcn_s_setprio(2);
-        agg_scan<G, VPL, ALIGNED, PAD, L8, PF, kHorizontal>(a, rc, ro, du, dv, g);
+        agg_scan<GH, VPLH, ALIGNED, PADH, L8, PFH, kHorizontal>(a, rc, ro, du, dv, g);
         __builtin_amdgcn_s_setprio(0);
     } else if (du == 0) {
         agg_scan<G, VPL, ALIGNED, PAD, L8, PF, kVertical>(a, rc, ro, du, dv, g);

@@ -140,6 +140,7 @@ struct PairDev {
     long long off_codes_l, off_codes_r, off_cost, off_vols;
     long long vstride;  // elements between per-direction volumes
     int32_t W, H, w, pitch, lanes, vpl, pad, wta_lanes, wta_vpl;
+    int32_t h_vpl, h_pad;  // the horizontal directions' 16-lane mapping
     int32_t census_start, cost_start, wta_start;  // first block of the pair in each batched grid
     int32_t census_tx, census_ty, cost_tx;
 };

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_cost(const uint64_t *__restrict__ cl, c
     cost_tile<CH>(cl, cr, d_lo, W, H, w, cmax, cost, blockIdx.x, blockIdx.y);
 }
 
-template <int G, int VPL, bool ALIGNED, bool PAD, bool L8, int PF>
+template <int G, int VPL, bool ALIGNED, bool PAD, bool L8, int PF, int GH, int VPLH, bool PADH, int PFH>
 __global__ __launch_bounds__(256) void k_aggregate(AggParams a)
 {
     int slot = 0;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_aggregate(AggParams a)
     const int r = __builtin_amdgcn_readfirstlane(a.paths[slot] & 0xFF);
     const int vol = __builtin_amdgcn_readfirstlane(a.paths[slot] >> 8);
     const int g = __builtin_amdgcn_readfirstlane((int)blockIdx.x - a.gstart[slot]);
-    agg_item<G, VPL, ALIGNED, PAD, L8, PF>(a, r, vol, g);
+    agg_item<G, VPL, ALIGNED, PAD, L8, PF, GH, VPLH, PADH, PFH>(a, r, vol, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,27 +182,47 @@ hipError_t by_vpl(int vpl, A &&...args)
 // where deeper rings only add registers.
 constexpr int prefetch_steps(int g, int vpl) { return (g == 16 && vpl == 8) ? 24 : 8; }
 
+// The horizontal directions always run on 16 lanes per scanline (see
+// agg_item): a narrower mapping (w <= 64) pairs with the 16-lane one of the
+// same widths, whose lanes hold 2 values up to w = 32 and 4 up to 64, padded
+// whenever its 16 * VPLH slots exceed the narrow mapping's G * VPL.
+template <int G, int VPL>
+struct HorizontalMapping {
+    static constexpr int VPLH = G == 16 ? VPL : (G * VPL <= 32 ? 2 : 4);
+    static constexpr int PFH = prefetch_steps(16, VPLH);
+    template <bool PAD>
+    static constexpr bool padh() { return PAD || 16 * VPLH != G * VPL; }
+};
+
 template <int G, int VPL>
 struct AggLaunch {
     static constexpr int PF = prefetch_steps(G, VPL);
+    static constexpr int VPLH = HorizontalMapping<G, VPL>::VPLH;
+    static constexpr int PFH = HorizontalMapping<G, VPL>::PFH;
+    template <bool ALIGNED, bool PAD, bool L8>
+    static void launch(const AggParams &p, dim3 grid, dim3 block, hipStream_t s)
+    {
+        constexpr bool PADH = HorizontalMapping<G, VPL>::template padh<PAD>();
+        hipLaunchKernelGGL((k_aggregate<G, VPL, ALIGNED, PAD, L8, PF, 16, VPLH, PADH, PFH>), grid, block, 0, s, p);
+    }
     static hipError_t run(const KernelConfig &kc, bool l8, bool pad, const AggParams &p, dim3 grid, dim3 block,
                           hipStream_t s)
     {
         if constexpr (G == 16) {
             if (!kc.aligned) {
-                if (l8) hipLaunchKernelGGL((k_aggregate<G, VPL, false, true, true, PF>), grid, block, 0, s, p);
-                else hipLaunchKernelGGL((k_aggregate<G, VPL, false, true, false, PF>), grid, block, 0, s, p);
+                if (l8) launch<false, true, true>(p, grid, block, s);
+                else launch<false, true, false>(p, grid, block, s);
                 return hipGetLastError();
             }
         } else {
             if (!kc.aligned) return hipErrorInvalidValue;
         }
         if (pad) {
-            if (l8) hipLaunchKernelGGL((k_aggregate<G, VPL, true, true, true, PF>), grid, block, 0, s, p);
-            else hipLaunchKernelGGL((k_aggregate<G, VPL, true, true, false, PF>), grid, block, 0, s, p);
+            if (l8) launch<true, true, true>(p, grid, block, s);
+            else launch<true, true, false>(p, grid, block, s);
         } else {
-            if (l8) hipLaunchKernelGGL((k_aggregate<G, VPL, true, false, true, PF>), grid, block, 0, s, p);
-            else hipLaunchKernelGGL((k_aggregate<G, VPL, true, false, false, PF>), grid, block, 0, s, p);
+            if (l8) launch<true, false, true>(p, grid, block, s);
+            else launch<true, false, false>(p, grid, block, s);
         }
         return hipGetLastError();
     }
@@ -306,10 +326,11 @@ hipError_t launch_aggregate(const Problem &pb, const KernelConfig &kc, const uin
     p.p1x2 = (uint32_t)pb.p1 * 0x10001u;
     p.p2x2 = (uint32_t)pb.p2 * 0x10001u;
     p.np = np;
-    p.lines_per_wg = kc.agg_block / kc.lanes;
     // Dispatch slots in order of scanline length (horizontal, diagonal,
     // vertical) so the longest dependency chains start first.  Slot o
     // aggregates direction paths[i] into output volume i: code = r | i << 8.
+    // A workgroup carries agg_block / lanes scanlines, the horizontal ones
+    // on 16 lanes each.
     int no = 0, acc = 0;
     for (int kind = 0; kind < 3; ++kind)
         for (int i = 0; i < np; ++i) {
@@ -317,9 +338,10 @@ hipError_t launch_aggregate(const Problem &pb, const KernelConfig &kc, const uin
             const int k = (r <= 1) ? 0 : (r >= 4 ? 1 : 2);
             if (k != kind) continue;
             const int nl = (r <= 1) ? pb.H : (r <= 3 ? pb.W : pb.W + pb.H - 1);
+            const int lpw = kc.agg_block / (k == 0 ? 16 : kc.lanes);
             p.paths[no] = r | (i << 8);
             p.gstart[no] = acc;
-            acc += (nl + p.lines_per_wg - 1) / p.lines_per_wg;
+            acc += (nl + lpw - 1) / lpw;
             ++no;
         }
     p.gstart[np] = acc;

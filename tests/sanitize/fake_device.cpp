@@ -347,9 +347,13 @@ hipError_t launch_batch(const BatchDev &b, const BatchGrids &g, int census_n, bo
         cost_next += P.cost_tx * P.H;
         const long long ppb = 256 / P.wta_lanes;
         wta_next += (int)(((long long)np + ppb - 1) / ppb);
-        const int lpi = 64 / P.lanes;
-        for (int r = 0; r < b.npaths; ++r)
+        // horizontal directions: the 16-lane mapping, four scanlines per item
+        check_mapping(P.w, 16, P.h_vpl, true);
+        CHECK(P.h_pad == (P.w < 16 * P.h_vpl ? 1 : 0));
+        for (int r = 0; r < b.npaths; ++r) {
+            const int lpi = 64 / (r <= 1 ? 16 : P.lanes);
             for (int q = 0, n = groups(r, P.W, P.H, lpi); q < n; ++q) want.insert(std::make_tuple(i, r, q));
+        }
     }
     CHECK(g.census == census_next && g.cost == cost_next && g.wta == wta_next);
     CHECK((size_t)b.nitems == want.size());
