@@ -246,7 +246,8 @@ def run_batch(args):
                    "pairs": len(pairs), "evals_per_step": evals, "unique_renders": len(renders)},
         "tuning": {"waves_per_cu": tuning[0], "order": ["longest-first", "pair-major",
                                                         "direction-major"][tuning[1]],
-                   "lanes_per_scanline": (tuning[2] or 16) if len(tuning) > 2 else 16},
+                   "lanes_per_scanline": (tuning[2] or 16) if len(tuning) > 2 else 16,
+                   "horizontal_lanes_per_scanline": 16},
         "roofline": roofline,
         "kernels_ms": {"census": round(census_ms, 4), "cost": round(cost_ms, 4), "aggregate": round(agg_ms, 4),
                        "wta": round(wta_ms, 4),
@@ -1120,7 +1121,7 @@ def main():
             "ndisp": 128, "value": round(W * H * 128 / (ms_per_step * 1e-3) / 1e6, 1),
             "unit": "Mdisp-evals/s (pixels x 128 disparities per second)"},
         "graph": graph_info,
-        "tuning": {"lanes_per_scanline": m.lanes,
+        "tuning": {"lanes_per_scanline": m.lanes, "horizontal_lanes_per_scanline": 16,
                    "chosen_by": "--lanes" if args.lanes is not None else "sgm_autotune"},
         "roofline": roofline,
         "roofline_other_bound": alu if roofline is hbm else hbm,

@@ -77,15 +77,16 @@ typedef struct sgm_plan_s *sgm_plan_t;
 
 /* Launch choices (picked by sgm_autotune / sgm_batch_autotune or set by
  * hand; none of them changes results).
- *   lanes: lanes that carry one scanline of the aggregation, each holding
- *          w / lanes (rounded up to a compiled count) consecutive window
- *          values, so that a wave of 64 lanes advances 64 / lanes
- *          scanlines: 16 serves every window width; 8 and 4 serve widths
- *          up to 64 that are a multiple of the per-lane count (8: 4 or 8
- *          values; 4: 4, 8, 12 or 16).  0 means 16; a count that does not
- *          serve a width falls back to 16 (for the plan, or for that pair
- *          of a batch).  The selection always takes the fewest lanes per
- *          pixel that serve the width.
+ *   lanes: lanes that carry one scanline of the aggregation's vertical
+ *          and diagonal directions, each holding w / lanes (rounded up to a
+ *          compiled count) consecutive window values, so that a wave of 64
+ *          lanes advances 64 / lanes scanlines: 16 serves every window
+ *          width; 8 and 4 serve widths up to 64 that are a multiple of the
+ *          per-lane count (8: 4 or 8 values; 4: 4, 8, 12 or 16).  0 means
+ *          16; a count that does not serve a width falls back to 16 (for
+ *          the plan, or for that pair of a batch).  The horizontal
+ *          directions always take 16 lanes per scanline, and the selection
+ *          the fewest lanes per pixel that serve the width.
  *   waves_per_cu, order: batches only (ignored by plans): resident
  *          aggregation waves per compute unit, 1..32; queue order of the
  *          scanline groups (0 longest first, 1 pair by pair, 2 direction by

@@ -375,6 +375,8 @@ sgm_status sgm_autotune(const sgm_params *params, const uint8_t *left, const uin
     const int deflt = base->kc.lanes;
     sgm_plan_free(base);
     // cache key: device architecture and the problem's shape and parameters
+    // (h16: horizontal directions on 16 lanes, so entries timed with another
+    // schedule are not reused)
     char key[256];
     {
         int dev = 0;
@@ -384,7 +386,7 @@ sgm_status sgm_autotune(const sgm_params *params, const uint8_t *left, const uin
             snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
         for (char *c = arch; *c; ++c)
             if (*c == ' ' || *c == ':') *c = '_';
-        snprintf(key, sizeof key, "single|%s|%dx%dx%d|n%d|R%d|P%d,%d", arch, q.width, q.height, q.ndisp, q.census,
+        snprintf(key, sizeof key, "single|h16|%s|%dx%dx%d|n%d|R%d|P%d,%d", arch, q.width, q.height, q.ndisp, q.census,
                  q.npaths, q.p1, q.p2);
     }
     if (cache_path) {

@@ -271,7 +271,9 @@ std::string tuning_key(const sgm_batch_s *b)
     for (const sgm_pair &p : b->pairs)
         shapes.push_back(std::to_string(p.width) + "x" + std::to_string(p.height) + "x" + std::to_string(p.ndisp));
     std::sort(shapes.begin(), shapes.end());
-    std::string key = "batch|" + arch + "|n" + std::to_string(b->prm.census) + "|R" + std::to_string(b->prm.npaths) + "|P" +
+    // (h16: horizontal directions on 16 lanes, so entries timed with another
+    // schedule are not reused)
+    std::string key = "batch|h16|" + arch + "|n" + std::to_string(b->prm.census) + "|R" + std::to_string(b->prm.npaths) + "|P" +
                       std::to_string(b->prm.p1) + "," + std::to_string(b->prm.p2) + "|";
     for (size_t i = 0; i < shapes.size();) {
         size_t j = i;
