@@ -251,8 +251,7 @@ sgm_status sgm_cost(sgm_plan_t plan, const uint8_t *left, const uint8_t *right, 
     uint64_t *cr = reinterpret_cast<uint64_t *>(base + plan->off_codes_r);
     hipStream_t st = (hipStream_t)stream;
     if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
-    hipError_t e = sgm::launch_census(plan->pb, left, pitch, cl, st);
-    if (e == hipSuccess) e = sgm::launch_census(plan->pb, right, pitch, cr, st);
+    hipError_t e = sgm::launch_census_lr(plan->pb, left, right, pitch, cl, cr, st);
     if (e == hipSuccess) e = sgm::launch_cost(plan->pb, config_for(plan, cost, nullptr), cl, cr, d_lo, cost, st);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "cost launch");
 }
@@ -504,8 +503,7 @@ sgm_status sgm_cost_win(sgm_plan_t plan, const uint8_t *left, const uint8_t *rig
     uint64_t *cr = reinterpret_cast<uint64_t *>(base + plan->off_codes_r);
     hipStream_t st = (hipStream_t)stream;
     if (sgm::fault_take(sgm::kFaultLaunch)) return fail(SGM_ERR_HIP, "injected launch failure");
-    hipError_t e = sgm::launch_census(plan->pb, left, pitch, cl, st);
-    if (e == hipSuccess) e = sgm::launch_census(plan->pb, right, pitch, cr, st);
+    hipError_t e = sgm::launch_census_lr(plan->pb, left, right, pitch, cl, cr, st);
     if (e == hipSuccess) e = sgm::launch_cost_win(plan->pb, cl, cr, lo, cost, st);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "cost_win launch");
 }

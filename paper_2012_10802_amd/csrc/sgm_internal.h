@@ -77,6 +77,9 @@ bool fault_take(int kind);
 // All launchers return hipSuccess or the launch error.
 hipError_t launch_census(const Problem &pb, const uint8_t *img, int pitch, uint64_t *codes,
                          hipStream_t s);
+// both images of a pair in one launch
+hipError_t launch_census_lr(const Problem &pb, const uint8_t *left, const uint8_t *right, int pitch, uint64_t *cl,
+                            uint64_t *cr, hipStream_t s);
 hipError_t launch_cost(const Problem &pb, const KernelConfig &kc, const uint64_t *cl,
                        const uint64_t *cr, const int32_t *d_lo, uint8_t *cost, hipStream_t s);
 // Aggregates the directions listed in paths[0..np) into np volumes at

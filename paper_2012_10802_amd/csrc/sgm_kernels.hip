@@ -46,6 +46,16 @@ __global__ __launch_bounds__(256) void k_census(const uint8_t *__restrict__ img,
     census_tile<N>(img, pitch, W, H, out, blockIdx.x, blockIdx.y);
 }
 
+// both images of a pair in one launch (blockIdx.z: 0 left, 1 right)
+template <int N>
+__global__ __launch_bounds__(256) void k_census_lr(const uint8_t *__restrict__ left,
+                                                   const uint8_t *__restrict__ right, int pitch, int W, int H,
+                                                   uint64_t *__restrict__ out_l, uint64_t *__restrict__ out_r)
+{
+    const bool r = blockIdx.z != 0;
+    census_tile<N>(r ? right : left, pitch, W, H, r ? out_r : out_l, blockIdx.x, blockIdx.y);
+}
+
 template <int CH>
 __global__ __launch_bounds__(256) void k_cost(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr,
                                               const int32_t *__restrict__ d_lo, int W, int H, int w, int cmax,
@@ -291,6 +301,19 @@ hipError_t launch_census(const Problem &pb, const uint8_t *img, int pitch, uint6
     case 3: hipLaunchKernelGGL(k_census<3>, grid, block, 0, s, img, pitch, pb.W, pb.H, codes); break;
     case 5: hipLaunchKernelGGL(k_census<5>, grid, block, 0, s, img, pitch, pb.W, pb.H, codes); break;
     case 7: hipLaunchKernelGGL(k_census<7>, grid, block, 0, s, img, pitch, pb.W, pb.H, codes); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_census_lr(const Problem &pb, const uint8_t *left, const uint8_t *right, int pitch, uint64_t *cl,
+                            uint64_t *cr, hipStream_t s)
+{
+    dim3 grid((pb.W + kCensusTW - 1) / kCensusTW, (pb.H + kCensusTH - 1) / kCensusTH, 2), block(256);
+    switch (pb.n) {
+    case 3: hipLaunchKernelGGL(k_census_lr<3>, grid, block, 0, s, left, right, pitch, pb.W, pb.H, cl, cr); break;
+    case 5: hipLaunchKernelGGL(k_census_lr<5>, grid, block, 0, s, left, right, pitch, pb.W, pb.H, cl, cr); break;
+    case 7: hipLaunchKernelGGL(k_census_lr<7>, grid, block, 0, s, left, right, pitch, pb.W, pb.H, cl, cr); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

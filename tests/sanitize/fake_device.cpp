@@ -194,6 +194,13 @@ hipError_t launch_census(const Problem &pb, const uint8_t *img, int pitch, uint6
     return hipSuccess;
 }
 
+hipError_t launch_census_lr(const Problem &pb, const uint8_t *left, const uint8_t *right, int pitch, uint64_t *cl,
+                            uint64_t *cr, hipStream_t s)
+{
+    launch_census(pb, left, pitch, cl, s);
+    return launch_census(pb, right, pitch, cr, s);
+}
+
 hipError_t launch_cost(const Problem &pb, const KernelConfig &, const uint64_t *cl, const uint64_t *cr,
                        const int32_t *d_lo, uint8_t *cost, hipStream_t)
 {
