@@ -17,12 +17,6 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 constexpr uint32_t kInf2 = 0x3FFF3FFFu;  // pair of "outside the window" values
 constexpr uint32_t kPad = 0x3FFFu;
 
-// a compile-time flag passed to generic lambdas
-template <bool B>
-struct Flag {
-    static constexpr bool value = B;
-};
-
 __device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b)
 {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
@@ -140,23 +134,12 @@ __device__ __forceinline__ int dir_dv(int r)
 // ---------------------------------------------------------------------------
 // lane value I/O: VPL bytes (or u16) per lane
 
-template <bool B, class T, class F>
-struct pick_type {
-    using type = T;
-};
-template <class T, class F>
-struct pick_type<false, T, F> {
-    using type = F;
-};
-
-// The bytes of two values are held as a 16-bit word: a 32-bit word holding
-// a zero-extended 16-bit load is narrowed by the compiler, which then
-// re-extends the loop-carried ring registers at the loop head and so waits
-// there for every load in flight.
+// a lane's VPL cost bytes as loaded, in dwords (the two bytes of a 2-value
+// lane zero-extended)
 template <int VPL>
 struct Raw {
     static constexpr int NW = (VPL + 3) / 4;
-    typename pick_type<VPL == 2, uint16_t, uint32_t>::type d[NW];
+    uint32_t d[NW];
 };
 
 // (used for the per-direction volumes, which are read once: non-temporal)
@@ -559,26 +542,29 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kRsrcWord3);
 }
 
-// VPL cost bytes of one lane at byte offset `off` (kOff: none)
+// VPL cost bytes of one lane at byte offset `off` (kOff: none) plus the
+// wave-uniform `soff`, which the range check may leave out: callers keep
+// off + soff inside the buffer whenever off is
 template <int VPL, bool ALIGNED>
-__device__ __forceinline__ void buf_load_u8(Raw<VPL> &r, __amdgpu_buffer_rsrc_t rs, uint32_t off, int nvalid)
+__device__ __forceinline__ void buf_load_u8(Raw<VPL> &r, __amdgpu_buffer_rsrc_t rs, uint32_t off, int nvalid,
+                                            uint32_t soff = 0)
 {
     if constexpr (ALIGNED) {
         if constexpr (VPL == 2) {
-            r.d[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+            r.d[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, off, soff, 0);
         } else if constexpr (VPL == 4) {
-            r.d[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+            r.d[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, soff, 0);
         } else if constexpr (VPL == 8) {
-            const v2u t = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+            const v2u t = __builtin_amdgcn_raw_buffer_load_b64(rs, off, soff, 0);
             r.d[0] = t.x;
             r.d[1] = t.y;
         } else if constexpr (VPL == 12) {
-            const v3u t = __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0);
+            const v3u t = __builtin_amdgcn_raw_buffer_load_b96(rs, off, soff, 0);
             r.d[0] = t.x;
             r.d[1] = t.y;
             r.d[2] = t.z;
         } else {
-            const v4u t = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+            const v4u t = __builtin_amdgcn_raw_buffer_load_b128(rs, off, soff, 0);
             r.d[0] = t.x;
             r.d[1] = t.y;
             r.d[2] = t.z;
@@ -590,63 +576,7 @@ __device__ __forceinline__ void buf_load_u8(Raw<VPL> &r, __amdgpu_buffer_rsrc_t 
 #pragma unroll
         for (int i = 0; i < VPL; ++i) {
             const uint32_t o = (i < nvalid && off != kOff) ? off + i : kOff;
-            r.d[i / 4] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, o, 0, 0) << (8 * (i % 4));
-        }
-    }
-}
-
-// packed u16 pairs of one lane -> uint8 (L8) or uint16 values at element
-// offset `off` of the buffer (kOff: none)
-template <int VPL, bool ALIGNED, bool L8>
-__device__ __forceinline__ void buf_store_pairs(const uint32_t (&v)[VPL / 2], __amdgpu_buffer_rsrc_t rs, uint32_t off,
-                                                int nvalid)
-{
-    constexpr int NP = VPL / 2;
-    if constexpr (ALIGNED && L8) {
-        if constexpr (VPL == 2) {
-            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)__builtin_amdgcn_perm(v[0], v[0], 0x0C0C0200u), rs,
-                                                  off, 0, 0);
-        } else if constexpr (VPL == 4) {
-            __builtin_amdgcn_raw_buffer_store_b32(pack_bytes(v[0], v[1]), rs, off, 0, 0);
-        } else if constexpr (VPL == 8) {
-            const v2u t = {pack_bytes(v[0], v[1]), pack_bytes(v[2], v[3])};
-            __builtin_amdgcn_raw_buffer_store_b64(t, rs, off, 0, 0);
-        } else if constexpr (VPL == 12) {
-            const v3u t = {pack_bytes(v[0], v[1]), pack_bytes(v[2], v[3]), pack_bytes(v[4], v[5])};
-            __builtin_amdgcn_raw_buffer_store_b96(t, rs, off, 0, 0);
-        } else {
-            const v4u t = {pack_bytes(v[0], v[1]), pack_bytes(v[2], v[3]), pack_bytes(v[4], v[5]),
-                           pack_bytes(v[6], v[7])};
-            __builtin_amdgcn_raw_buffer_store_b128(t, rs, off, 0, 0);
-        }
-    } else if constexpr (ALIGNED) {
-        const uint32_t bo = off == kOff ? kOff : off * 2;
-        if constexpr (NP == 1) {
-            __builtin_amdgcn_raw_buffer_store_b32(v[0], rs, bo, 0, 0);
-        } else if constexpr (NP == 2) {
-            const v2u t = {v[0], v[1]};
-            __builtin_amdgcn_raw_buffer_store_b64(t, rs, bo, 0, 0);
-        } else {
-#pragma unroll
-            for (int j = 0; j < NP; j += 2) {
-                const v2u t = {v[j], v[j + 1]};
-                __builtin_amdgcn_raw_buffer_store_b64(t, rs, bo == kOff ? kOff : bo + 4 * j, 0, 0);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int i = 2 * j + h;
-                const uint32_t val = h ? (v[j] >> 16) : (v[j] & 0xFFFFu);
-                const bool ok = i < nvalid && off != kOff;
-                if (L8)
-                    __builtin_amdgcn_raw_buffer_store_b8((unsigned char)val, rs, ok ? off + i : kOff, 0, 0);
-                else
-                    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)val, rs, ok ? 2 * (off + i) : kOff, 0,
-                                                          0);
-            }
+            r.d[i / 4] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, o, soff, 0) << (8 * (i % 4));
         }
     }
 }
@@ -694,28 +624,29 @@ __device__ __forceinline__ void pack_strided(const uint32_t (&p)[VPL / 2], uint3
 }
 
 // stores of one lane's aggregated values (strided pairs) at element offset
-// `off` of the output volume (kOff: dropped by the range check)
+// `off` of the output volume (kOff: dropped by the range check) plus the
+// wave-uniform `soff` elements (as for buf_load_u8)
 template <int VPL, bool ALIGNED, bool L8>
 __device__ __forceinline__ void store_strided(const uint32_t (&v)[VPL / 2], __amdgpu_buffer_rsrc_t rs, uint32_t off,
-                                              int nvalid)
+                                              int nvalid, uint32_t soff = 0)
 {
     constexpr int NP = VPL / 2;
     if constexpr (ALIGNED && L8) {
         uint32_t d[(VPL + 3) / 4];
         pack_strided<VPL>(v, d);
         if constexpr (VPL == 2) {
-            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)d[0], rs, off, 0, kStreamPolicy);
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)d[0], rs, off, soff, kStreamPolicy);
         } else if constexpr (VPL == 4) {
-            __builtin_amdgcn_raw_buffer_store_b32(d[0], rs, off, 0, kStreamPolicy);
+            __builtin_amdgcn_raw_buffer_store_b32(d[0], rs, off, soff, kStreamPolicy);
         } else if constexpr (VPL == 8) {
             const v2u t = {d[0], d[1]};
-            __builtin_amdgcn_raw_buffer_store_b64(t, rs, off, 0, kStreamPolicy);
+            __builtin_amdgcn_raw_buffer_store_b64(t, rs, off, soff, kStreamPolicy);
         } else if constexpr (VPL == 12) {
             const v3u t = {d[0], d[1], d[2]};
-            __builtin_amdgcn_raw_buffer_store_b96(t, rs, off, 0, kStreamPolicy);
+            __builtin_amdgcn_raw_buffer_store_b96(t, rs, off, soff, kStreamPolicy);
         } else {
             const v4u t = {d[0], d[1], d[2], d[3]};
-            __builtin_amdgcn_raw_buffer_store_b128(t, rs, off, 0, kStreamPolicy);
+            __builtin_amdgcn_raw_buffer_store_b128(t, rs, off, soff, kStreamPolicy);
         }
     } else {
         // value i of the lane: pair i % NP, half i / NP
@@ -724,9 +655,9 @@ __device__ __forceinline__ void store_strided(const uint32_t (&v)[VPL / 2], __am
             const uint32_t val = (i < NP) ? (v[i] & 0xFFFFu) : (v[i - NP] >> 16);
             const bool ok = i < nvalid && off != kOff;
             if (L8)
-                __builtin_amdgcn_raw_buffer_store_b8((unsigned char)val, rs, ok ? off + i : kOff, 0, kStreamPolicy);
+                __builtin_amdgcn_raw_buffer_store_b8((unsigned char)val, rs, ok ? off + i : kOff, soff, kStreamPolicy);
             else
-                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)val, rs, ok ? 2 * (off + i) : kOff, 0,
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)val, rs, ok ? 2 * (off + i) : kOff, 2 * soff,
                                                       kStreamPolicy);
         }
     }
@@ -847,10 +778,10 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
     uint32_t mnq = 0;
 
     // one step: consume ring slot S (loaded PF steps ago), refill it for
-    // step i + PF, aggregate, store.  A checked step may lie past the
-    // scanline's last step or prefetch past it: those accesses are dropped.
-    auto step = [&](const int i, const int S, auto checked) __attribute__((always_inline)) {
-        constexpr bool CHECKED = decltype(checked)::value;
+    // step i + PF from offset lo (+ scalar lso), aggregate, store at so
+    // (+ sso)
+    auto step = [&](const int S, const uint32_t lo, const uint32_t lso, const uint32_t so,
+                    const uint32_t sso) __attribute__((always_inline)) {
         // ring[S] was loaded PF steps ago; everything issued since may stay
         // in flight.  The scheduling fence keeps later steps' reads of the
         // ring below this wait.
@@ -865,11 +796,7 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
             else
                 c2[j] = unpack_strided(ring[S], j) | padp[j];
         }
-        {
-            const int ip = i + PF;
-            const uint32_t o = (!CHECKED || ip < I1) ? offset(ip) : kOff;
-            buf_load_u8<VPL, ALIGNED>(ring[S], rc, o, nvalid);
-        }
+        buf_load_u8<VPL, ALIGNED>(ring[S], rc, lo, nvalid, lso);
         // m_q = min_k L(q,k) in both u16 halves: the lane's pair minimum
         // (from the end of the previous step) folded over its halves, then
         // reduced over the group as 32-bit values (such doubled values order
@@ -878,9 +805,14 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
         const uint32_t mm = group_min<G>(pk_min_halves(mnq));
         // end neighbours across the lane edges (outside the window: 0x3FFF)
         // (e: only its high half is used, so a 32-bit maximum, which the
-        // compiler folds into the DPP move; f: its low half, a packed one)
+        // compiler folds into the DPP move; f: its low half, a packed one
+        // unless the group is a whole row)
         const uint32_t e = max(dpp0<kRowShr1>(Lq[NP - 1]), edge_l);
-        const uint32_t f = pk_max(dpp0<kRowShl1>(Lq[0]), edge_r);
+        uint32_t f;
+        if constexpr (G == 16)  // (edge lanes read the zero fill: a 32-bit maximum is exact)
+            f = max(dpp0<kRowShl1>(Lq[0]), edge_r);
+        else
+            f = pk_max(dpp0<kRowShl1>(Lq[0]), edge_r);
         // L(p,k) = C(p,k) + min(L(q,k), L(q,k+-1) + P1, m_q + P2) - m_q
         //        = C(p,k) + min(t - m_q, P2),  t = min(L(q,k), L(q,k+-1) + P1) >= m_q,
         // so m_q enters only after t (no u16 value goes below 0 or past
@@ -894,10 +826,16 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
             Ln[j] = pk_add(pk_min(pk_sub(t, mm), a.p2x2), c2[j]);
         }
         const uint32_t mn = pk_min_tree<NP>(Ln);
-        store_strided<VPL, ALIGNED, L8>(Ln, ro, (!CHECKED || i < I1) ? offset(i) : kOff, nvalid);
+        store_strided<VPL, ALIGNED, L8>(Ln, ro, so, nvalid, sso);
 #pragma unroll
         for (int j = 0; j < NP; ++j) Lq[j] = Ln[j];
         mnq = mn;
+    };
+
+    // step i with its accesses checked against the scanline's end: a step
+    // past it, or a prefetch past it, is dropped
+    auto checked_step = [&](const int i, const int S) __attribute__((always_inline)) {
+        step(S, i + PF < I1 ? offset(i + PF) : kOff, 0u, i < I1 ? offset(i) : kOff, 0u);
     };
 
     // The first turn of the ring runs outside the loops: at a loop head
@@ -905,20 +843,38 @@ __device__ __forceinline__ void agg_scan(const AggParams &a, __amdgpu_buffer_rsr
     // so the compiler sees the same loads in flight from both sides and
     // needs no deeper wait there than inside the loop.  The step count is
     // padded to PF + a multiple of UNROLL; padded steps load nothing and
-    // store nothing.  Blocks whose steps and prefetches all lie before I1
-    // (the last prefetch of block blk is step I0 + 2 PF + (blk + 1) UNROLL
-    // - 1) run without the per-step range checks.
+    // store nothing.
 #pragma unroll
-    for (int S = 0; S < PF; ++S) step(I0 + S, S, Flag<true>{});
+    for (int S = 0; S < PF; ++S) checked_step(I0 + S, S);
     const int nblk = (I1 - I0 - PF + UNROLL - 1) / UNROLL;
+    // Blocks whose steps and prefetches all lie before I1 (the last prefetch
+    // of block blk is step I0 + 2 PF + (blk + 1) UNROLL - 1) need no range
+    // checks.  Horizontal and vertical scanlines also share one stride
+    // (every lane with values advances by it): such a block takes one
+    // vector offset per access kind and puts the step's place in the block
+    // into the scalar offset, never negative (a block walking down the
+    // addresses is based at its last step), every access staying inside the
+    // volume.
     const int nfull = min(nblk, max(0, (I1 - I0 - 2 * PF) / UNROLL));
+    const int ustride = __builtin_amdgcn_readfirstlane((dv * W + du) * w);
+    const int sb = ustride < 0 ? UNROLL - 1 : 0;
     for (int blk = 0; blk < nfull; ++blk) {
+        const int ib = I0 + PF + blk * UNROLL;
+        if constexpr (KIND == kDiagonal) {
 #pragma unroll
-        for (int s = 0; s < UNROLL; ++s) step(I0 + PF + blk * UNROLL + s, s % PF, Flag<false>{});
+            for (int s = 0; s < UNROLL; ++s) step(s % PF, offset(ib + s + PF), 0u, offset(ib + s), 0u);
+        } else {
+            const uint32_t vl = offset(ib + PF + sb), vs = offset(ib + sb);
+#pragma unroll
+            for (int s = 0; s < UNROLL; ++s) {
+                const uint32_t so = (uint32_t)__builtin_amdgcn_readfirstlane((s - sb) * ustride);
+                step(s % PF, vl, so, vs, so);
+            }
+        }
     }
     for (int blk = nfull; blk < nblk; ++blk) {
 #pragma unroll
-        for (int s = 0; s < UNROLL; ++s) step(I0 + PF + blk * UNROLL + s, s % PF, Flag<true>{});
+        for (int s = 0; s < UNROLL; ++s) checked_step(I0 + PF + blk * UNROLL + s, s % PF);
     }
 }
 
