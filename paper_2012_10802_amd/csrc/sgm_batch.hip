@@ -55,12 +55,13 @@ __global__ __launch_bounds__(256) void k_cost_batch(BatchDev b)
     const uint64_t *cr = reinterpret_cast<const uint64_t *>(b.ws + P.off_codes_r);
     uint8_t *cost = b.ws + P.off_cost;
     const int bx = local % P.cost_tx, v = local / P.cost_tx;
+    __shared__ CostLds lds;  // one for every piece width
     if (P.w % 16 == 0)
-        cost_tile<16>(cl, cr, P.d_lo, P.W, P.H, P.w, b.cmax, cost, bx, v);
+        cost_tile<16>(cl, cr, P.d_lo, P.W, P.H, P.w, b.cmax, cost, bx, v, lds);
     else if (P.w % 8 == 0)
-        cost_tile<8>(cl, cr, P.d_lo, P.W, P.H, P.w, b.cmax, cost, bx, v);
+        cost_tile<8>(cl, cr, P.d_lo, P.W, P.H, P.w, b.cmax, cost, bx, v, lds);
     else
-        cost_tile<4>(cl, cr, P.d_lo, P.W, P.H, P.w, b.cmax, cost, bx, v);
+        cost_tile<4>(cl, cr, P.d_lo, P.W, P.H, P.w, b.cmax, cost, bx, v, lds);
 }
 
 constexpr int kBatchPrefetch = 8;

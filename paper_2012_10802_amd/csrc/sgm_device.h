@@ -382,9 +382,22 @@ __device__ __forceinline__ void census_tile(const uint8_t *__restrict__ img, int
 // staged in LDS.  Each thread then produces CH consecutive window values of
 // one pixel per item; neighbouring lanes take neighbouring pixels, so the
 // LDS reads of a wave are conflict-free (8-byte stride), and a pixel's
-// window is written in CH-byte pieces.
+// window is written in CH-byte pieces (through an LDS tile, see CostLds).
 
 constexpr int kCostTile = 64;
+
+// LDS of one cost workgroup: the tile's left codes, the right codes its
+// windows reach, and (CH >= 8, w >= 64) the tile's output, whose pixel rows are
+// padded to an odd number of CH-byte pieces so that the items' piece stores
+// (one pixel per lane) fall on distinct banks; the tile then leaves in
+// contiguous CH-byte pieces per lane, whole lines per wave.  Stores of one
+// piece per lane at the pixel stride reach only about half the HBM write
+// rate of contiguous ones.
+struct CostLds {
+    uint64_t cl[kCostTile];
+    uint64_t cr[kCostTile + 256];
+    alignas(16) uint8_t out[kCostTile * (256 + 16)];
+};
 
 // the items (pixel, group of CH window values) of one cost tile.  FULL: the
 // tile has kCostTile pixels (item -> pixel by shifts).  INIMG (CH >= 8
@@ -392,7 +405,7 @@ constexpr int kCostTile = 64;
 // value is replaced by Cmax.
 template <int CH, bool FULL, bool INIMG>
 __device__ __forceinline__ void cost_items(const uint64_t *s_cl, const uint64_t *s_cr, int u0, int lo, int w,
-                                           int cmax, int npix, int nch, uint8_t *__restrict__ out)
+                                           int cmax, int npix, int nch, uint8_t *__restrict__ out, int ostride)
 {
     const int np = FULL ? kCostTile : npix;
     for (int it = threadIdx.x; it < np * nch; it += blockDim.x) {
@@ -424,7 +437,7 @@ __device__ __forceinline__ void cost_items(const uint64_t *s_cl, const uint64_t 
             }
             word[q] = wd;
         }
-        uint8_t *dst = out + (size_t)px * w + k0;
+        uint8_t *dst = out + (size_t)px * ostride + k0;
         if constexpr (CH == 16) {
             *reinterpret_cast<uint4 *>(dst) = make_uint4(word[0], word[1], word[2], word[3]);
         } else if constexpr (CH == 8) {
@@ -438,10 +451,9 @@ __device__ __forceinline__ void cost_items(const uint64_t *s_cl, const uint64_t 
 template <int CH>
 __device__ __forceinline__ void cost_tile(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr,
                                           const int32_t *__restrict__ d_lo, int W, int H, int w, int cmax,
-                                          uint8_t *__restrict__ cost, int bx, int v)
+                                          uint8_t *__restrict__ cost, int bx, int v, CostLds &lds)
 {
-    __shared__ uint64_t s_cl[kCostTile];
-    __shared__ uint64_t s_cr[kCostTile + 256];
+    uint64_t *s_cl = lds.cl, *s_cr = lds.cr;
     const int u0 = bx * kCostTile;
     const int lo = d_lo ? d_lo[v] : 0;
     const int first = u0 - lo - (w - 1);  // right column held in s_cr[0]
@@ -456,14 +468,34 @@ __device__ __forceinline__ void cost_tile(const uint64_t *__restrict__ cl, const
     const int npix = min(kCostTile, W - u0);
     const int nch = (w + CH - 1) / CH;
     uint8_t *out = cost + ((size_t)v * W + u0) * w;
+    // items into the LDS tile (CH >= 8 and w >= 64: a wave's pieces lie a
+    // cache line or more apart) or straight to the volume (narrower windows
+    // keep a wave's pieces within a few lines; staging them measured slower)
+    const bool staged = CH >= 8 && w >= 64;
+    uint8_t *dst = staged ? lds.out : out;
+    const int dstride = staged ? (nch | 1) * CH : w;
     // (uniform over the workgroup)
     const bool full = npix == kCostTile, inimg = CH >= 8 && first >= 0;
     if (full && inimg)
-        cost_items<CH, true, true>(s_cl, s_cr, u0, lo, w, cmax, npix, nch, out);
+        cost_items<CH, true, true>(s_cl, s_cr, u0, lo, w, cmax, npix, nch, dst, dstride);
     else if (full)
-        cost_items<CH, true, false>(s_cl, s_cr, u0, lo, w, cmax, npix, nch, out);
+        cost_items<CH, true, false>(s_cl, s_cr, u0, lo, w, cmax, npix, nch, dst, dstride);
     else
-        cost_items<CH, false, false>(s_cl, s_cr, u0, lo, w, cmax, npix, nch, out);
+        cost_items<CH, false, false>(s_cl, s_cr, u0, lo, w, cmax, npix, nch, dst, dstride);
+    if (CH >= 8 && staged) {
+        // the tile's npix * w bytes are contiguous in the volume: piece t is
+        // piece t % nch of pixel t / nch (exact in float: t < 64 * 32)
+        __syncthreads();
+        const float rn = __fdiv_rn(1.0f, (float)nch);
+        for (int t = threadIdx.x; t < npix * nch; t += blockDim.x) {
+            const int px = (int)(((float)t + 0.5f) * rn), c = t - px * nch;
+            const uint8_t *src = lds.out + px * dstride + c * CH;
+            if constexpr (CH == 16)
+                *reinterpret_cast<uint4 *>(out + (size_t)t * 16) = *reinterpret_cast<const uint4 *>(src);
+            else
+                *reinterpret_cast<uint2 *>(out + (size_t)t * 8) = *reinterpret_cast<const uint2 *>(src);
+        }
+    }
 }
 
 

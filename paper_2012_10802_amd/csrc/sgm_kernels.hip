@@ -61,7 +61,8 @@ __global__ __launch_bounds__(256) void k_cost(const uint64_t *__restrict__ cl, c
                                               const int32_t *__restrict__ d_lo, int W, int H, int w, int cmax,
                                               uint8_t *__restrict__ cost)
 {
-    cost_tile<CH>(cl, cr, d_lo, W, H, w, cmax, cost, blockIdx.x, blockIdx.y);
+    __shared__ CostLds lds;
+    cost_tile<CH>(cl, cr, d_lo, W, H, w, cmax, cost, blockIdx.x, blockIdx.y, lds);
 }
 
 template <int G, int VPL, bool ALIGNED, bool PAD, bool L8, int PF, int GH, int VPLH, bool PADH, int PFH>
