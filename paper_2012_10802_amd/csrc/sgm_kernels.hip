@@ -7,15 +7,17 @@
 //   summed S       uint16 [H][W][w]       (eq. (9))
 //
 // Lane mapping of the aggregation (eq. (8)): a scanline of the path is
-// carried by one 16-lane DPP row; lane j holds the VPL consecutive window
-// indices [j*VPL, (j+1)*VPL) as VPL/2 packed u16 pairs.  One wave64 thus
-// advances four scanlines, one workgroup of 256 threads sixteen.  Per step
-// a lane
+// carried by a group of G lanes (a 16-lane DPP row, or for the vertical and
+// diagonal directions of windows up to 64 a half row or a quad); lane j
+// holds the VPL consecutive window indices [j*VPL, (j+1)*VPL) as VPL/2
+// packed u16 pairs.  With G = 16 one wave64 advances four scanlines, one
+// workgroup of 256 threads sixteen.  Per step a lane
 //   * loads its VPL cost bytes (prefetched PF steps ahead into registers),
 //   * forms the k-1 / k+1 neighbour pairs with v_alignbit inside the lane
 //     and one row_shr / row_shl DPP move across lanes,
-//   * reduces the predecessor's minimum m_q over the window with four DPP
-//     steps (independent of, and overlapped with, the neighbour terms),
+//   * reduces the predecessor's minimum m_q over the window with DPP
+//     steps (four for a row; independent of, and overlapped with, the
+//     neighbour terms),
 //   * evaluates C + min(L(k), min(L(k-1), L(k+1)) + P1, m_q + P2) - m_q with
 //     packed u16 min/add/sub.
 // Window indices k >= w (when 16*VPL > w) carry the cost 0x3FFF; their
@@ -28,8 +30,6 @@
 // 16 neighbouring pixels of the same image row at every step (a sheared
 // index for the diagonals), which keeps every wave's loads and stores on
 // contiguous 512-byte runs.
-
-#include "sgm_internal.h"
 
 #include "sgm_device.h"
 #include "sgm_internal.h"
