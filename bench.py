@@ -1122,6 +1122,7 @@ def main():
             "unit": "Mdisp-evals/s (pixels x 128 disparities per second)"},
         "graph": graph_info,
         "tuning": {"lanes_per_scanline": m.lanes, "horizontal_lanes_per_scanline": 16,
+                   "slot_order": ["horizontal, diagonal, vertical", "horizontal, vertical, diagonal"][m.order],
                    "chosen_by": "--lanes" if args.lanes is not None else "sgm_autotune"},
         "roofline": roofline,
         "roofline_other_bound": alu if roofline is hbm else hbm,

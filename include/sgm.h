@@ -87,10 +87,12 @@ typedef struct sgm_plan_s *sgm_plan_t;
  *          the plan, or for that pair of a batch).  The horizontal
  *          directions always take 16 lanes per scanline, and the selection
  *          the fewest lanes per pixel that serve the width.
- *   waves_per_cu, order: batches only (ignored by plans): resident
- *          aggregation waves per compute unit, 1..32; queue order of the
- *          scanline groups (0 longest first, 1 pair by pair, 2 direction by
- *          direction). */
+ *   order: plans: dispatch order of the aggregation's direction slots
+ *          after the horizontal ones (0 diagonal then vertical, 1 vertical
+ *          then diagonal); batches: queue order of the scanline groups (0
+ *          longest first, 1 pair by pair, 2 direction by direction).
+ *   waves_per_cu: batches only (ignored by plans): resident aggregation
+ *          waves per compute unit, 1..32. */
 typedef struct {
     int32_t waves_per_cu;
     int32_t order;
@@ -102,9 +104,10 @@ typedef struct {
 sgm_status sgm_plan(const sgm_params *params, sgm_plan_t *out);
 void sgm_plan_free(sgm_plan_t plan);
 
-/* sgm_plan with the launch choice tuning->lanes (0, 4, 8 or 16); the
- * plan's results are those of sgm_plan.  sgm_plan_get_tuning reports the
- * lane count the plan uses (waves_per_cu and order read 0). */
+/* sgm_plan with the launch choices tuning->lanes (0, 4, 8 or 16) and
+ * tuning->order (0 or 1; other values: SGM_ERR_INVALID); the plan's results
+ * are those of sgm_plan.  sgm_plan_get_tuning reports the lane count and
+ * slot order the plan uses (waves_per_cu reads 0). */
 sgm_status sgm_plan_tuned(const sgm_params *params, const sgm_tuning *tuning, sgm_plan_t *out);
 sgm_status sgm_plan_get_tuning(sgm_plan_t plan, sgm_tuning *tuning);
 
@@ -182,13 +185,14 @@ sgm_status sgm_match(sgm_plan_t plan, const uint8_t *left, const uint8_t *right,
                      float *disp_sub, void *workspace, size_t workspace_bytes,
                      void *stream);
 
-/* Pick the lane count for `params`: reuse the entry for this device
- * architecture and problem (W, H, w, census, paths, P1, P2) from the text
- * file `cache_path` (may be NULL) if it holds one, else run sgm_match with
- * every distinct lane mapping on the given buffers (as for sgm_match; the
- * outputs are overwritten), time each on `stream` (one warm-up, best of
- * three; the host waits), keep the fastest and append it to the file.
- * *chosen (may be NULL) receives the result, for sgm_plan_tuned. */
+/* Pick the lane count and slot order for `params`: reuse the entry for
+ * this device architecture and problem (W, H, w, census, paths, P1, P2)
+ * from the text file `cache_path` (may be NULL) if it holds one, else run
+ * sgm_match with every distinct (lane mapping, order) on the given buffers
+ * (as for sgm_match; the outputs are overwritten), time each on `stream`
+ * (one warm-up, best of three; the host waits), keep the fastest and
+ * append it to the file.  *chosen (may be NULL) receives the result, for
+ * sgm_plan_tuned. */
 sgm_status sgm_autotune(const sgm_params *params, const uint8_t *left, const uint8_t *right,
                         int32_t pitch, const int32_t *d_lo, uint16_t *disp_int, float *disp_sub,
                         void *workspace, size_t workspace_bytes, void *stream,

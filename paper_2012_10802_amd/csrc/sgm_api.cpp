@@ -104,7 +104,7 @@ sgm::KernelConfig config_for(const sgm_plan_s *p, const void *a, const void *b)
     return kc;
 }
 
-sgm_status make_plan(const sgm_params *pr, int lanes, sgm_plan_t *out);
+sgm_status make_plan(const sgm_params *pr, int lanes, int order, sgm_plan_t *out);
 
 }  // namespace
 
@@ -132,21 +132,23 @@ const char *sgm_status_str(sgm_status s)
 
 const char *sgm_last_error(void) { return sgm::error_buffer(); }
 
-sgm_status sgm_plan(const sgm_params *pr, sgm_plan_t *out) { return make_plan(pr, 0, out); }
+sgm_status sgm_plan(const sgm_params *pr, sgm_plan_t *out) { return make_plan(pr, 0, 0, out); }
 
 sgm_status sgm_plan_tuned(const sgm_params *pr, const sgm_tuning *tuning, sgm_plan_t *out)
 {
     if (!tuning) return fail(SGM_ERR_INVALID, "tuning is NULL");
     if (tuning->lanes != 0 && tuning->lanes != 4 && tuning->lanes != 8 && tuning->lanes != 16)
         return fail(SGM_ERR_INVALID, "lanes %d not in {0, 4, 8, 16}", tuning->lanes);
-    return make_plan(pr, tuning->lanes, out);
+    if (tuning->order != 0 && tuning->order != 1)
+        return fail(SGM_ERR_INVALID, "order %d not in {0, 1} for a plan", tuning->order);
+    return make_plan(pr, tuning->lanes, tuning->order, out);
 }
 
 sgm_status sgm_plan_get_tuning(sgm_plan_t plan, sgm_tuning *tuning)
 {
     if (sgm_status s = check_plan(plan)) return s;
     if (!tuning) return fail(SGM_ERR_INVALID, "tuning is NULL");
-    *tuning = sgm_tuning{0, 0, plan->kc.lanes};
+    *tuning = sgm_tuning{0, plan->kc.agg_order, plan->kc.lanes};
     return SGM_OK;
 }
 
@@ -154,7 +156,7 @@ sgm_status sgm_plan_get_tuning(sgm_plan_t plan, sgm_tuning *tuning)
 
 namespace {
 
-sgm_status make_plan(const sgm_params *pr, int lanes, sgm_plan_t *out)
+sgm_status make_plan(const sgm_params *pr, int lanes, int order, sgm_plan_t *out)
 {
     if (!pr || !out) return fail(SGM_ERR_INVALID, "params and out must not be NULL");
     *out = nullptr;
@@ -196,6 +198,7 @@ sgm_status make_plan(const sgm_params *pr, int lanes, sgm_plan_t *out)
                     (long long)q.width * q.height * q.ndisp);
     }
     p->kc.agg_block = 256;
+    p->kc.agg_order = order;
     for (int i = 0; i < 8; ++i) p->paths[i] = i;
     p->n_pix = (size_t)q.width * q.height;
     p->n_vol = p->n_pix * (size_t)q.ndisp;
@@ -369,7 +372,7 @@ sgm_status sgm_autotune(const sgm_params *params, const uint8_t *left, const uin
 {
     if (!params) return fail(SGM_ERR_INVALID, "params is NULL");
     sgm_plan_t base = nullptr;
-    if (sgm_status s = make_plan(params, 0, &base)) return s;
+    if (sgm_status s = make_plan(params, 0, 0, &base)) return s;
     const sgm_params q = base->params;
     const int deflt = base->kc.lanes;
     sgm_plan_free(base);
@@ -391,40 +394,44 @@ sgm_status sgm_autotune(const sgm_params *params, const uint8_t *left, const uin
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "r")) {
             char line[512], k[300];
-            int lanes = -1, found = -1;
+            int lanes = -1, order = -1, found = -1, found_order = 0;
             double ms = 0;
             while (fgets(line, sizeof line, f))
-                if (sscanf(line, "%299s %d %lf", k, &lanes, &ms) == 3 && !strcmp(k, key) &&
-                    (lanes == 4 || lanes == 8 || lanes == 16))
+                if (sscanf(line, "%299s %d %d %lf", k, &lanes, &order, &ms) == 4 && !strcmp(k, key) &&
+                    (lanes == 4 || lanes == 8 || lanes == 16) && (order == 0 || order == 1)) {
                     found = lanes;
+                    found_order = order;
+                }
             fclose(f);
             if (found > 0) {
-                if (chosen) *chosen = sgm_tuning{0, 0, found};
+                if (chosen) *chosen = sgm_tuning{0, found_order, found};
                 return SGM_OK;
             }
         }
     }
-    // time each distinct mapping: one warm-up run, then the best of three
+    // time each distinct (lane mapping, slot order): one warm-up run, then
+    // the best of three
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0) hipEventDestroy(e0);
         return fail(SGM_ERR_HIP, "autotune: event creation failed");
     }
-    int best = deflt, seen[3] = {0, 0, 0}, nseen = 0;
+    int best = deflt, best_order = 0, seen[6] = {0, 0, 0, 0, 0, 0}, nseen = 0;
     float best_ms = 1e30f;
     sgm_status rs = SGM_OK;
-    for (int lanes : {16, 8, 4}) {
+    static const int kTrials[6][2] = {{16, 0}, {16, 1}, {8, 0}, {8, 1}, {4, 0}, {4, 1}};  // (lanes, order)
+    for (const auto &trial : kTrials) {
         sgm_plan_t p = nullptr;
-        if ((rs = make_plan(params, lanes, &p)) != SGM_OK) break;
-        const int eff = p->kc.lanes;
+        if ((rs = make_plan(params, trial[0], trial[1], &p)) != SGM_OK) break;
+        const int eff = p->kc.lanes, key2 = eff * 2 + trial[1];
         bool dup = false;
-        for (int i = 0; i < nseen; ++i) dup = dup || seen[i] == eff;
+        for (int i = 0; i < nseen; ++i) dup = dup || seen[i] == key2;
         if (dup) {
             sgm_plan_free(p);
             continue;
         }
-        seen[nseen++] = eff;
+        seen[nseen++] = key2;
         float ms = 1e30f;
         for (int rep = 0; rep < 4 && rs == SGM_OK; ++rep) {
             if (hipEventRecord(e0, st) != hipSuccess) rs = fail(SGM_ERR_HIP, "autotune: event record failed");
@@ -439,6 +446,7 @@ sgm_status sgm_autotune(const sgm_params *params, const uint8_t *left, const uin
         if (ms < best_ms) {
             best_ms = ms;
             best = eff;
+            best_order = trial[1];
         }
     }
     hipEventDestroy(e0);
@@ -446,10 +454,10 @@ sgm_status sgm_autotune(const sgm_params *params, const uint8_t *left, const uin
     if (rs != SGM_OK) return rs;
     if (cache_path)
         if (FILE *f = fopen(cache_path, "a")) {
-            fprintf(f, "%s %d %.5f\n", key, best, best_ms);
+            fprintf(f, "%s %d %d %.5f\n", key, best, best_order, best_ms);
             fclose(f);
         }
-    if (chosen) *chosen = sgm_tuning{0, 0, best};
+    if (chosen) *chosen = sgm_tuning{0, best_order, best};
     return SGM_OK;
 }
 

@@ -63,6 +63,9 @@ struct KernelConfig {
                     // and buffers aligned); false only with 16-lane mappings
     bool l8;        // per-path aggregated costs fit in uint8 (Cmax + P2 <= 255)
     int agg_block;  // threads per aggregation workgroup (multiple of 64)
+    int agg_order;  // dispatch order of the aggregation's direction slots
+                    // after the horizontal ones: 0 diagonal then vertical,
+                    // 1 vertical then diagonal
 };
 
 struct Problem {

@@ -350,8 +350,10 @@ hipError_t launch_aggregate(const Problem &pb, const KernelConfig &kc, const uin
     p.p1x2 = (uint32_t)pb.p1 * 0x10001u;
     p.p2x2 = (uint32_t)pb.p2 * 0x10001u;
     p.np = np;
-    // Dispatch slots in order of scanline length (horizontal, diagonal,
-    // vertical) so the longest dependency chains start first.  Slot o
+    // Dispatch slots: the horizontal directions first (the longest
+    // dependency chains), then diagonal and vertical (agg_order 0) or
+    // vertical and diagonal (1), the better one depending on the frame and
+    // lane count (a tuned launch choice).  Slot o
     // aggregates direction paths[i] into output volume i: code = r | i << 8.
     // A workgroup carries agg_block / lanes scanlines, the horizontal ones
     // on 16 lanes each.
@@ -359,7 +361,7 @@ hipError_t launch_aggregate(const Problem &pb, const KernelConfig &kc, const uin
     for (int kind = 0; kind < 3; ++kind)
         for (int i = 0; i < np; ++i) {
             const int r = paths[i];
-            const int k = (r <= 1) ? 0 : (r >= 4 ? 1 : 2);
+            const int k = (r <= 1) ? 0 : ((r >= 4) == (kc.agg_order == 0) ? 1 : 2);
             if (k != kind) continue;
             const int nl = (r <= 1) ? pb.H : (r <= 3 ? pb.W : pb.W + pb.H - 1);
             const int lpw = kc.agg_block / (k == 0 ? 16 : kc.lanes);

@@ -186,14 +186,15 @@ def _need(t, dtype, shape, name, device=True):
 # the C calls, one for one
 
 
-def sgm_plan(width, height, census, ndisp, npaths, p1, p2, flags=0, lanes=None):
-    """A plan (sgm_plan, or sgm_plan_tuned when `lanes` is given: 0, 4, 8, 16)."""
+def sgm_plan(width, height, census, ndisp, npaths, p1, p2, flags=0, lanes=None, order=None):
+    """A plan (sgm_plan, or sgm_plan_tuned when `lanes` (0, 4, 8, 16) or the
+    slot `order` (0, 1) is given)."""
     prm = sgm_params(width, height, census, ndisp, npaths, p1, p2, flags)
     h = ctypes.c_void_p()
-    if lanes is None:
+    if lanes is None and order is None:
         _check(_lib.sgm_plan(ctypes.byref(prm), ctypes.byref(h)), "sgm_plan")
     else:
-        t = sgm_tuning(0, 0, int(lanes))
+        t = sgm_tuning(0, int(order or 0), int(lanes or 0))
         _check(_lib.sgm_plan_tuned(ctypes.byref(prm), ctypes.byref(t), ctypes.byref(h)), "sgm_plan_tuned")
     return h
 
@@ -203,6 +204,13 @@ def sgm_plan_lanes(plan) -> int:
     t = sgm_tuning()
     _check(_lib.sgm_plan_get_tuning(plan, ctypes.byref(t)), "sgm_plan_get_tuning")
     return int(t.lanes)
+
+
+def sgm_plan_order(plan) -> int:
+    """The plan's dispatch order of the aggregation's direction slots."""
+    t = sgm_tuning()
+    _check(_lib.sgm_plan_get_tuning(plan, ctypes.byref(t)), "sgm_plan_get_tuning")
+    return int(t.order)
 
 
 def sgm_plan_free(plan):
@@ -532,10 +540,11 @@ class Matcher:
     """
 
     def __init__(self, width, height, census=7, ndisp=128, npaths=8, p1=10, p2=120,
-                 device=None, workspace=None, lanes=None):
+                 device=None, workspace=None, lanes=None, order=None):
         self.W, self.H, self.n, self.w = int(width), int(height), int(census), int(ndisp)
         self.npaths, self.p1, self.p2 = int(npaths), int(p1), int(p2)
-        self.plan = sgm_plan(self.W, self.H, self.n, self.w, self.npaths, self.p1, self.p2, lanes=lanes)
+        self.plan = sgm_plan(self.W, self.H, self.n, self.w, self.npaths, self.p1, self.p2, lanes=lanes,
+                             order=order)
         self.device = torch.device(device or "cuda")
         need = sgm_workspace_size(self.plan)
         if workspace is None:
@@ -779,10 +788,14 @@ class Matcher:
     def lanes(self):
         return sgm_plan_lanes(self.plan)
 
+    @property
+    def order(self):
+        return sgm_plan_order(self.plan)
+
     def autotune(self, left, right, d_lo=None, cache_path=None, stream=None):
-        """Time every lane mapping on these inputs (sgm_autotune; the host
-        waits), then rebuild the plan with the fastest.  Returns the lane
-        count chosen."""
+        """Time every lane mapping and slot order on these inputs
+        (sgm_autotune; the host waits), then rebuild the plan with the
+        fastest.  Returns the lane count chosen (the order: `order`)."""
         self._img(left, "left")
         self._img(right, "right")
         di, ds = self._outs(None, None, True)
@@ -793,7 +806,8 @@ class Matcher:
                                  _ptr(di), _ptr(ds), _ptr(self.workspace), self.ws_bytes, _stream(stream), path,
                                  ctypes.byref(t)), "sgm_autotune")
         old = self.plan
-        self.plan = sgm_plan(self.W, self.H, self.n, self.w, self.npaths, self.p1, self.p2, lanes=int(t.lanes))
+        self.plan = sgm_plan(self.W, self.H, self.n, self.w, self.npaths, self.p1, self.p2, lanes=int(t.lanes),
+                             order=int(t.order))
         _lib.sgm_plan_free(old)
         return int(t.lanes)
 

@@ -117,6 +117,34 @@ def test_batch_plan_rejects_uint16_volumes_reaching_the_drop_offset(sgm):
     assert status(4096, 2304, 128, 120) in (0, -3)
 
 
+@pytest.mark.parametrize("lanes,order,want_status,want", [
+    (0, 0, 0, (16, 0)),
+    (8, 1, 0, (8, 1)),
+    (4, 1, 0, (4, 1)),
+    (4, 0, 0, (4, 0)),
+    (8, 2, -1, None),
+    (8, -1, -1, None),
+    (5, 0, -1, None),
+])
+def test_plan_tuning_round_trip(sgm, lanes, order, want_status, want):
+    """sgm_plan_tuned keeps the lane count (w = 64 serves 4, 8 and 16) and
+    the slot order, rejects orders outside {0, 1} and unknown lane counts,
+    and sgm_plan_get_tuning reports both."""
+    lib = sgm.library()
+    h = ctypes.c_void_p()
+    t = sgm.sgm_tuning(0, order, lanes)
+    st = lib.sgm_plan_tuned(ctypes.byref(_params()), ctypes.byref(t), ctypes.byref(h))
+    assert st == want_status
+    if st != 0:
+        return
+    try:
+        got = sgm.sgm_tuning()
+        assert lib.sgm_plan_get_tuning(h, ctypes.byref(got)) == 0
+        assert (got.lanes, got.order, got.waves_per_cu) == (want[0], want[1], 0)
+    finally:
+        lib.sgm_plan_free(h)
+
+
 def test_error_strings(sgm):
     lib = sgm.library()
     assert lib.sgm_status_str(-4) == b"SGM_ERR_WORKSPACE"

@@ -300,6 +300,32 @@ def test_lane_mappings_match_oracle(lib, w, lanes):
         np.testing.assert_array_equal(b.cpu().numpy(), ws)
 
 
+@pytest.mark.parametrize("lanes", [4, 8, 16])
+def test_slot_orders_match_oracle(lib, lanes):
+    """Both dispatch orders of the aggregation's direction slots, with each
+    lane count, on a ragged row-window frame: every direction's L_r and the
+    disparities equal the oracle's."""
+    import torch
+    W, H, n, w = 93, 41, 7, 24
+    L, Rimg = _rand_pair(W, H, 577 + lanes)
+    d_lo = np.random.default_rng(lanes).integers(0, 7, size=H).astype(np.int32)
+    c = oracle.cost(oracle.census(L, n), oracle.census(Rimg, n), n, w, d_lo)
+    wi, ws = oracle.wta(oracle.sum_paths(c, 8, 10, 120), d_lo)
+    dl = _dev(d_lo)
+    for order in (0, 1):
+        m = lib.Matcher(W, H, census=n, ndisp=w, npaths=8, p1=10, p2=120, lanes=lanes, order=order)
+        assert (m.lanes, m.order) == (lanes, order)
+        cost = m.cost(_dev(L), _dev(Rimg), d_lo=dl)
+        paths = m.aggregate_paths(cost)
+        mi, ms = m.match(_dev(L), _dev(Rimg), d_lo=dl)
+        torch.cuda.synchronize()
+        for r in range(8):
+            np.testing.assert_array_equal(m.path_volume(paths, r).cpu().numpy(), oracle.path(c, r, 10, 120),
+                                          err_msg="order %d path %d" % (order, r))
+        np.testing.assert_array_equal(_np_u16(mi), wi)
+        np.testing.assert_array_equal(ms.cpu().numpy(), ws)
+
+
 def test_single_pair_autotune_keeps_results(lib, tmp_path):
     """sgm_autotune times the lane mappings, caches the choice, and the
     tuned plan gives the oracle's disparities."""
@@ -312,10 +338,11 @@ def test_single_pair_autotune_keeps_results(lib, tmp_path):
     cache = tmp_path / "tune.txt"
     L, Rt, dl = _dev(p.left), _dev(p.right), _dev(d_lo)
     lanes = m.autotune(L, Rt, d_lo=dl, cache_path=cache)
-    assert lanes in (4, 8, 16) and m.lanes == lanes
+    assert lanes in (4, 8, 16) and m.lanes == lanes and m.order in (0, 1)
     assert len(cache.read_text().splitlines()) == 1
     m2 = lib.Matcher(W, H, census=7, ndisp=24, npaths=8)
     assert m2.autotune(L, Rt, d_lo=dl, cache_path=cache) == lanes  # read back
+    assert m2.order == m.order
     assert len(cache.read_text().splitlines()) == 1
     dint, dsub = m.match(L, Rt, d_lo=dl)
     torch.cuda.synchronize()
