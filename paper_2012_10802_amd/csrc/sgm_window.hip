@@ -551,7 +551,7 @@ __device__ __forceinline__ void win16_scan(const Win16Params &a, __amdgpu_buffer
 // a wave hold 64 rows, so a direct access per step would touch 64 cache
 // lines.  Instead the wave moves tiles of 8 pixels x 64 rows: the cost tile
 // (8 KB) and the window starts (2 KB) are fetched with 8 rows x 128 bytes
-// per load instruction into a register ring two tiles ahead, written to LDS,
+// per load instruction into a register ring one tile ahead, written to LDS,
 // read back one pixel per lane and step, and the results go out the same
 // way.  The cost and output tiles are XOR-swizzled (unit (r, p) at
 // r * 8 + (p ^ (r & 7))) so that both the row-wise copies and the per-lane
@@ -560,7 +560,7 @@ __device__ __forceinline__ void win16_scan(const Win16Params &a, __amdgpu_buffer
 // barrier.
 
 constexpr int kHT = 8;      // pixels per tile
-constexpr int kHRing = 2;   // tiles in flight ahead of the one processed
+constexpr int kHRing = 1;   // tiles in flight ahead of the one processed
 
 __global__ __launch_bounds__(64) void k_aggregate_win16_h(Win16Params a)
 {
@@ -626,9 +626,10 @@ __global__ __launch_bounds__(64) void k_aggregate_win16_h(Win16Params a)
     uint32_t m = 0u;
     int loq = kNoLo;
     const int y = R0 + lane;
-    // 16 loads and 8 stores per tile; the tile's loads were issued two tiles
-    // ago, followed by the previous tiles' stores and the next tile's loads
-    constexpr int kAfter = 8 + 16 + 8;
+    // 16 loads and 8 stores per tile; the tile's loads were issued kHRing
+    // tiles ago, followed by that tile's stores and, for each tile since,
+    // its loads and stores
+    constexpr int kAfter = 8 + (kHRing - 1) * (16 + 8);
     auto tile = [&](const int t, const int sl) __attribute__((always_inline)) {
         const int k = du > 0 ? t : K - 1 - t;
         __builtin_amdgcn_sched_barrier(0);
