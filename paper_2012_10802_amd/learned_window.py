@@ -265,7 +265,7 @@ class LearnedWindowMatcher:
     full-range fallback, for batches of `batch` pairs of one size."""
 
     def __init__(self, width, height, batch=1, ndisp=192, window=16, census=7, npaths=8, p1=10,
-                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, fallback_streams=4, autotune=True,
+                 p2=120, net=None, tau=0.5, margin=32, full_fraction=0.5, fallback_streams=3, autotune=True,
                  fallback_margin=8, device="cuda"):
         if width % 4 or height % 4 or ndisp % 4:
             raise ValueError("width, height and ndisp must be multiples of 4")
@@ -322,7 +322,14 @@ class LearnedWindowMatcher:
         finally:
             S.sgm_plan_free(full)
         # pair i's rectangles go to side stream i % len(streams), each stream
-        # with its own workspace, so the small launches also overlap each other
+        # with its own workspace, so the small launches also overlap each other.
+        # Streams share the process's hardware queues (four by default, given
+        # out in turn as streams are made): a fallback stream that lands on
+        # the queue of the stream running the windowed SGM waits behind it.
+        # Measured on a batch of 16 x 1920x1080 (stream made after this
+        # object): 3 side streams 4.22 ms per batch with the fallback done
+        # 0.03 ms after the windowed SGM, 4 streams 4.51 ms (0.41 ms after),
+        # 2 streams 4.39 ms, 1 stream 4.57 ms.
         nst = max(1, min(fallback_streams, n))
         self.fb_streams = [torch.cuda.Stream(device=dev) for _ in range(nst)]
         self.fb_ws = [torch.empty(need, dtype=torch.uint8, device=dev) for _ in range(nst)]
