@@ -58,6 +58,11 @@ SHAPES = [
     (23, 7, 5, 1, 4),
     (1, 30, 5, 16, 8),
     (45, 1, 7, 20, 8),
+    # cost tiles staged through LDS (w >= 64): a one-pixel column, a full
+    # tile, a tile plus one pixel
+    (1, 9, 7, 64, 8),
+    (64, 5, 5, 128, 4),
+    (65, 3, 7, 192, 4),
 ]
 
 
